@@ -1,0 +1,877 @@
+/*
+ * oracle.c -- CPU oracle (TEST INFRASTRUCTURE ONLY; see oracle.h).
+ *
+ * What it computes, and where each definition comes from:
+ *
+ *  - CSR and COO storage and the sparse matrix-vector product y = A x are
+ *    the ones the paper uses in its section "Central Sparse Linear Algebra
+ *    Functionality": COO keeps (row, column, value) for every stored entry,
+ *    CSR replaces the row indices of a row-sorted COO matrix by pointers to
+ *    the first entry of each row.  The product and its scaled form
+ *    y = alpha*A*x + beta*y follow the BLAS convention that beta == 0 does
+ *    not read y.
+ *  - ELL is only named by the paper (its preamble defines the macro); the
+ *    padded column-major layout used here is the standard one of Williams et
+ *    al., the SpMV survey the paper cites.  Hybrid ELL+COO is not in the paper
+ *    at all; its split width follows the byte-count model of the paper's
+ *    "SpMV Performance Analysis" subsection (value + index bytes per ELL slot
+ *    against value + two index bytes per COO entry).
+ *  - CG, BiCGSTAB and GMRES are the Krylov solvers of the same section; the
+ *    paper gives no algorithm text and refers to Saad's book (2nd ed., 2003)
+ *    and to Saad & Schultz (1986) for GMRES.  The textbook forms are written
+ *    out below in that notation.
+ *  - Row sums are accumulated with the compensated dot product of Ogita,
+ *    Rump & Oishi ("Accurate sum and dot product", 2005) and rounded once,
+ *    so the oracle's own error is about one unit in the last place and the
+ *    per-entry tolerance of a GPU comparison measures the GPU alone.
+ *  - Mixed-precision iterative refinement is not in the paper; it is the
+ *    classical scheme (residual and update in FP64, correction solved in
+ *    FP32) with the inner solver being the CG below run in float.
+ */
+#include "oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* compensated accumulation (Ogita-Rump-Oishi Dot2)                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double s;     /* running sum                              */
+  double c;     /* accumulated rounding errors              */
+  double naive; /* plain sum, used when a term is not finite */
+} acc_t;
+
+static void acc_init(acc_t* a, double start) {
+  a->s = start;
+  a->c = 0.0;
+  a->naive = start;
+}
+
+static void acc_add(acc_t* a, double u, double v) {
+  double h = u * v;
+  double r = fma(u, v, -h); /* exact error of the product */
+  double s = a->s + h;
+  double z = s - a->s;
+  double q = (a->s - (s - z)) + (h - z); /* exact error of the sum */
+  a->s = s;
+  a->c = a->c + (q + r);
+  a->naive = a->naive + h;
+}
+
+static double acc_result(const acc_t* a) {
+  double res = a->s + a->c;
+  if (!isfinite(a->naive) || !isfinite(res)) return a->naive;
+  return res;
+}
+
+static double scale_out(double alpha, double s, double beta, double yold) {
+  if (beta == 0.0) return alpha * s;
+  return alpha * s + beta * yold;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ingest                                                                   */
+/* ------------------------------------------------------------------------ */
+int orc_csr_validate(int64_t n, int64_t ncols, int64_t nnz,
+                     const int32_t* rowptr, const int32_t* col) {
+  if (n < 0 || ncols < 0 || nnz < 0) return ORC_INVALID_ARG;
+  if (n > INT32_MAX || ncols > INT32_MAX || nnz > INT32_MAX)
+    return ORC_UNSUPPORTED;
+  if (rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) return ORC_INVALID_MATRIX;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return ORC_INVALID_MATRIX;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      if (col[k] < 0 || (int64_t)col[k] >= ncols) return ORC_INVALID_MATRIX;
+      if (k > rowptr[i] && col[k] <= col[k - 1]) return ORC_INVALID_MATRIX;
+    }
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* conversions                                                              */
+/* ------------------------------------------------------------------------ */
+void orc_csr_to_coo(int64_t n, const int32_t* rowptr, int32_t* row_out) {
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) row_out[k] = (int32_t)i;
+}
+
+void orc_coo_to_csr(int64_t n, int64_t nnz, const int32_t* row,
+                    int32_t* rowptr_out) {
+  for (int64_t i = 0; i <= n; ++i) rowptr_out[i] = 0;
+  for (int64_t k = 0; k < nnz; ++k) rowptr_out[row[k] + 1] += 1;
+  for (int64_t i = 0; i < n; ++i) rowptr_out[i + 1] += rowptr_out[i];
+}
+
+int64_t orc_ell_width(int64_t n, const int32_t* rowptr) {
+  int64_t K = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t L = rowptr[i + 1] - rowptr[i];
+    if (L > K) K = L;
+  }
+  return K;
+}
+
+int64_t orc_ell_stride(int64_t n) { return (n + 63) / 64 * 64; }
+
+void orc_csr_to_ell(int64_t n, const int32_t* rowptr, const int32_t* col,
+                    const double* val, int64_t K, int64_t stride,
+                    int32_t* ecol, double* eval) {
+  for (int64_t j = 0; j < K; ++j)
+    for (int64_t i = 0; i < stride; ++i) {
+      int64_t slot = j * stride + i;
+      int64_t L = (i < n) ? (int64_t)(rowptr[i + 1] - rowptr[i]) : 0;
+      if (j < L) {
+        ecol[slot] = col[rowptr[i] + j];
+        eval[slot] = val[rowptr[i] + j];
+      } else {
+        ecol[slot] = -1;
+        eval[slot] = 0.0;
+      }
+    }
+}
+
+/* Width of the ELL part of a hybrid matrix.  One more ELL column costs
+ * stride slots of (value + 4) bytes; it removes #{rows with length >= K}
+ * entries of (value + 8) bytes from the COO part.  K_h is the largest K for
+ * which every column up to K pays for itself.                              */
+int64_t orc_hyb_width(int64_t n, const int32_t* rowptr, int value_bytes) {
+  int64_t stride = orc_ell_stride(n);
+  int64_t Kmax = orc_ell_width(n, rowptr);
+  int64_t* count = (int64_t*)calloc((size_t)Kmax + 2, sizeof(int64_t));
+  for (int64_t i = 0; i < n; ++i) count[rowptr[i + 1] - rowptr[i]] += 1;
+  /* count_ge[K] = #{L_i >= K}, computed from the top down in place */
+  for (int64_t K = Kmax - 1; K >= 0; --K) count[K] += count[K + 1];
+  int64_t Kh = 0;
+  for (int64_t K = 1; K <= Kmax; ++K) {
+    double coo_bytes_saved = (double)count[K] * (double)(value_bytes + 8);
+    double ell_bytes_added = (double)stride * (double)(value_bytes + 4);
+    if (coo_bytes_saved > ell_bytes_added)
+      Kh = K;
+    else
+      break;
+  }
+  free(count);
+  return Kh;
+}
+
+int64_t orc_csr_to_hyb(int64_t n, const int32_t* rowptr, const int32_t* col,
+                       const double* val, int64_t K, int64_t stride,
+                       int32_t* ecol, double* eval, int32_t* crow,
+                       int32_t* ccol, double* cval) {
+  int64_t c = 0;
+  for (int64_t j = 0; j < K; ++j)
+    for (int64_t i = 0; i < stride; ++i) {
+      int64_t slot = j * stride + i;
+      int64_t L = (i < n) ? (int64_t)(rowptr[i + 1] - rowptr[i]) : 0;
+      if (j < L) {
+        ecol[slot] = col[rowptr[i] + j];
+        eval[slot] = val[rowptr[i] + j];
+      } else {
+        ecol[slot] = -1;
+        eval[slot] = 0.0;
+      }
+    }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rowptr[i] + K; k < rowptr[i + 1]; ++k) {
+      crow[c] = (int32_t)i;
+      ccol[c] = col[k];
+      cval[c] = val[k];
+      ++c;
+    }
+  return c;
+}
+
+int orc_cast_f32(int64_t count, const double* in, float* out) {
+  for (int64_t k = 0; k < count; ++k) {
+    float f = (float)in[k]; /* IEEE round to nearest, ties to even */
+    if (isfinite(in[k]) && !isfinite(f)) return ORC_UNSUPPORTED;
+    out[k] = f;
+  }
+  return ORC_OK;
+}
+
+/* IEEE 754 binary16 from its definition: 1 sign bit, 5 exponent bits with
+ * bias 15, 10 fraction bits; normal numbers (1024+f)*2^(e-25), subnormals
+ * f*2^-24.  Rounding is to nearest, ties to even.                          */
+uint16_t orc_f64_to_f16(double v) {
+  uint16_t sign = signbit(v) ? 0x8000u : 0u;
+  if (isnan(v)) return (uint16_t)(sign | 0x7e00u);
+  double a = fabs(v);
+  if (isinf(a)) return (uint16_t)(sign | 0x7c00u);
+  if (a == 0.0) return sign;
+  int e2;
+  frexp(a, &e2); /* a = f * 2^e2 with f in [0.5, 1) */
+  int E = e2 - 1;  /* floor(log2 a) */
+  if (E < -14) E = -14; /* subnormal range: spacing 2^-24 */
+  double q = ldexp(a, 10 - E); /* a / spacing, exact */
+  double fl = floor(q);
+  double frac = q - fl;
+  uint64_t m = (uint64_t)fl;
+  if (frac > 0.5 || (frac == 0.5 && (m & 1u))) m += 1;
+  if (m >= 2048) {
+    m >>= 1;
+    E += 1;
+  }
+  if (E > 15) return (uint16_t)(sign | 0x7c00u);
+  if (m < 1024) return (uint16_t)(sign | (uint16_t)m);
+  return (uint16_t)(sign | (uint16_t)(((E + 15) << 10) | (int)(m - 1024)));
+}
+
+double orc_f16_to_f64(uint16_t h) {
+  int s = h >> 15;
+  int e = (h >> 10) & 31;
+  int f = h & 1023;
+  double v;
+  if (e == 0)
+    v = ldexp((double)f, -24);
+  else if (e == 31)
+    v = f ? NAN : INFINITY;
+  else
+    v = ldexp((double)(1024 + f), e - 25);
+  return s ? -v : v;
+}
+
+/* Per-row power-of-two scale s_i = 2^ceil(log2 max|a_ij|) (1 for an empty or
+ * all-zero row), stored as FP32; h = binary16(a / s_i).                     */
+int orc_rowscale_f16(int64_t n, const int32_t* rowptr, const double* val,
+                     uint16_t* h, float* scale) {
+  for (int64_t i = 0; i < n; ++i) {
+    double m = 0.0;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      if (!isfinite(val[k])) return ORC_UNSUPPORTED;
+      if (fabs(val[k]) > m) m = fabs(val[k]);
+    }
+    double s = 1.0;
+    if (m > 0.0) {
+      int e2;
+      double f = frexp(m, &e2); /* m = f * 2^e2 */
+      int E = (f == 0.5) ? e2 - 1 : e2;
+      if (E > 127 || E < -126) return ORC_UNSUPPORTED;
+      s = ldexp(1.0, E);
+    }
+    scale[i] = (float)s;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+      h[k] = orc_f64_to_f16(val[k] / s);
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SpMV                                                                     */
+/* ------------------------------------------------------------------------ */
+void orc_spmv_csr(int64_t n, const int32_t* rowptr, const int32_t* col,
+                  const double* val, const double* x, double alpha,
+                  double beta, double* y, int mode) {
+  for (int64_t i = 0; i < n; ++i) {
+    double s;
+    if (mode == 1) {
+      s = 0.0;
+      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+        s = s + val[k] * x[col[k]];
+    } else {
+      acc_t a;
+      acc_init(&a, 0.0);
+      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+        acc_add(&a, val[k], x[col[k]]);
+      s = acc_result(&a);
+    }
+    y[i] = scale_out(alpha, s, beta, beta == 0.0 ? 0.0 : y[i]);
+  }
+}
+
+void orc_spmv_coo(int64_t n, int64_t nnz, const int32_t* row,
+                  const int32_t* col, const double* val, const double* x,
+                  double alpha, double beta, double* y) {
+  acc_t* a = (acc_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(acc_t));
+  for (int64_t i = 0; i < n; ++i) acc_init(&a[i], 0.0);
+  for (int64_t k = 0; k < nnz; ++k) acc_add(&a[row[k]], val[k], x[col[k]]);
+  for (int64_t i = 0; i < n; ++i)
+    y[i] = scale_out(alpha, acc_result(&a[i]), beta, beta == 0.0 ? 0.0 : y[i]);
+  free(a);
+}
+
+void orc_spmv_ell(int64_t n, int64_t K, int64_t stride, const int32_t* ecol,
+                  const double* eval, const double* x, double alpha,
+                  double beta, double* y) {
+  for (int64_t i = 0; i < n; ++i) {
+    acc_t a;
+    acc_init(&a, 0.0);
+    for (int64_t j = 0; j < K; ++j) {
+      int32_t c = ecol[j * stride + i];
+      if (c < 0) continue; /* padding slot */
+      acc_add(&a, eval[j * stride + i], x[c]);
+    }
+    y[i] = scale_out(alpha, acc_result(&a), beta, beta == 0.0 ? 0.0 : y[i]);
+  }
+}
+
+void orc_spmv_hyb(int64_t n, int64_t K, int64_t stride, const int32_t* ecol,
+                  const double* eval, int64_t cnnz, const int32_t* crow,
+                  const int32_t* ccol, const double* cval, const double* x,
+                  double alpha, double beta, double* y) {
+  acc_t* a = (acc_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(acc_t));
+  for (int64_t i = 0; i < n; ++i) {
+    acc_init(&a[i], 0.0);
+    for (int64_t j = 0; j < K; ++j) {
+      int32_t c = ecol[j * stride + i];
+      if (c < 0) continue;
+      acc_add(&a[i], eval[j * stride + i], x[c]);
+    }
+  }
+  for (int64_t k = 0; k < cnnz; ++k) acc_add(&a[crow[k]], cval[k], x[ccol[k]]);
+  for (int64_t i = 0; i < n; ++i)
+    y[i] = scale_out(alpha, acc_result(&a[i]), beta, beta == 0.0 ? 0.0 : y[i]);
+  free(a);
+}
+
+void orc_spmv_csr_f16(int64_t n, const int32_t* rowptr, const int32_t* col,
+                      const uint16_t* h, const float* scale, const double* x,
+                      double alpha, double beta, double* y) {
+  for (int64_t i = 0; i < n; ++i) {
+    acc_t a;
+    acc_init(&a, 0.0);
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+      acc_add(&a, orc_f16_to_f64(h[k]), x[col[k]]);
+    double s = (double)scale[i] * acc_result(&a);
+    y[i] = scale_out(alpha, s, beta, beta == 0.0 ? 0.0 : y[i]);
+  }
+}
+
+void orc_absrow(int64_t n, const int32_t* rowptr, const int32_t* col,
+                const double* val, const double* x, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+      s = s + fabs(val[k]) * fabs(x[col[k]]);
+    out[i] = s;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* dense reference routines                                                 */
+/* ------------------------------------------------------------------------ */
+void orc_dense_matvec(int64_t n, int64_t m, const double* A, const double* x,
+                      double* y) {
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t j = 0; j < m; ++j) s = s + A[i * m + j] * x[j];
+    y[i] = s;
+  }
+}
+
+/* Gaussian elimination with partial pivoting on a copy of row-major A. */
+int orc_dense_lu_solve(int64_t n, const double* A, const double* b,
+                       double* x) {
+  double* M = (double*)malloc((size_t)(n * n > 0 ? n * n : 1) * sizeof(double));
+  double* r = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  memcpy(M, A, (size_t)(n * n) * sizeof(double));
+  memcpy(r, b, (size_t)n * sizeof(double));
+  int status = ORC_OK;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t p = k;
+    for (int64_t i = k + 1; i < n; ++i)
+      if (fabs(M[i * n + k]) > fabs(M[p * n + k])) p = i;
+    if (M[p * n + k] == 0.0) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    if (p != k) {
+      for (int64_t j = 0; j < n; ++j) {
+        double t = M[k * n + j];
+        M[k * n + j] = M[p * n + j];
+        M[p * n + j] = t;
+      }
+      double t = r[k];
+      r[k] = r[p];
+      r[p] = t;
+    }
+    for (int64_t i = k + 1; i < n; ++i) {
+      double l = M[i * n + k] / M[k * n + k];
+      M[i * n + k] = 0.0;
+      for (int64_t j = k + 1; j < n; ++j) M[i * n + j] -= l * M[k * n + j];
+      r[i] -= l * r[k];
+    }
+  }
+  if (status == ORC_OK)
+    for (int64_t i = n - 1; i >= 0; --i) {
+      double s = r[i];
+      for (int64_t j = i + 1; j < n; ++j) s -= M[i * n + j] * x[j];
+      x[i] = s / M[i * n + i];
+    }
+  free(M);
+  free(r);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* vector helpers for the solvers (plain ascending loops)                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t n;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+} csr_t;
+
+static void matvec(const csr_t* A, const double* x, double* y) {
+  orc_spmv_csr(A->n, A->rowptr, A->col, A->val, x, 1.0, 0.0, y, 0);
+}
+
+/* r = b - A x, each entry accumulated accurately and rounded once */
+static void residual(const csr_t* A, const double* b, const double* x,
+                     double* r) {
+  for (int64_t i = 0; i < A->n; ++i) {
+    acc_t a;
+    acc_init(&a, b[i]);
+    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+      acc_add(&a, -A->val[k], x[A->col[k]]);
+    r[i] = acc_result(&a);
+  }
+}
+
+static double dot(int64_t n, const double* a, const double* b) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s = s + a[i] * b[i];
+  return s;
+}
+
+static double nrm2(int64_t n, const double* a) { return sqrt(dot(n, a, a)); }
+
+static double* vec(int64_t n) {
+  return (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+}
+
+static double threshold(const orc_stop* st, double nb, double nr0) {
+  double base = st->baseline == 1 ? nr0 : nb;
+  double t = st->rel_tol * base;
+  return t > st->abs_tol ? t : st->abs_tol;
+}
+
+static double baseline_norm(const orc_stop* st, double nb, double nr0) {
+  double base = st->baseline == 1 ? nr0 : nb;
+  return base > 0.0 ? base : 1.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* CG (Hestenes-Stiefel, unpreconditioned; Saad 2003, ch. 6)                */
+/* ------------------------------------------------------------------------ */
+int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
+           const double* val, const double* b, double* x,
+           const orc_stop* stop, orc_info* info, double* hist,
+           int64_t hist_cap) {
+  csr_t A = {n, rowptr, col, val};
+  memset(info, 0, sizeof(*info));
+  double nb = nrm2(n, b);
+  if (!isfinite(nb)) return ORC_NONFINITE;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    return ORC_OK;
+  }
+  double *r = vec(n), *p = vec(n), *q = vec(n);
+  residual(&A, b, x, r);
+  double rho = dot(n, r, r);
+  double nr0 = sqrt(rho);
+  double thr = threshold(stop, nb, nr0);
+  double base = baseline_norm(stop, nb, nr0);
+  int status = ORC_OK;
+  memcpy(p, r, (size_t)n * sizeof(double));
+  int64_t it = 0, repl = 0;
+  int check = sqrt(rho) <= thr;
+  for (;;) {
+    if (check) {
+      /* stopping test on the recurrence residual passed: verify the true
+       * residual b - A x, replacing r and restarting p if it disagrees */
+      residual(&A, b, x, r);
+      double nt = nrm2(n, r);
+      info->relres_true = nt / base;
+      if (nt <= thr) break;
+      if (repl >= stop->max_replacements) {
+        status = ORC_NOT_CONVERGED;
+        break;
+      }
+      repl++;
+      rho = nt * nt;
+      memcpy(p, r, (size_t)n * sizeof(double));
+      check = 0;
+    }
+    if (it >= stop->max_iters) {
+      residual(&A, b, x, q);
+      info->relres_true = nrm2(n, q) / base;
+      status = ORC_NOT_CONVERGED;
+      break;
+    }
+    matvec(&A, p, q);
+    double pq = dot(n, p, q);
+    if (!isfinite(pq)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (pq <= 0.0) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    double alpha = rho / pq;
+    for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+    double rho_new = dot(n, r, r);
+    ++it;
+    info->relres_recurrence = sqrt(rho_new) / base;
+    double beta = rho_new / rho;
+    if (hist && 2 * it <= hist_cap) {
+      hist[2 * (it - 1)] = alpha;
+      hist[2 * (it - 1) + 1] = beta;
+    }
+    if (sqrt(rho_new) <= thr) {
+      check = 1;
+      continue;
+    }
+    for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+    rho = rho_new;
+  }
+  info->iters = it;
+  info->replacements = repl;
+  free(r);
+  free(p);
+  free(q);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* BiCGSTAB (van der Vorst 1992; Saad 2003, ch. 7), r_hat = r_0             */
+/* ------------------------------------------------------------------------ */
+int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
+                 const double* val, const double* b, double* x,
+                 const orc_stop* stop, orc_info* info) {
+  csr_t A = {n, rowptr, col, val};
+  memset(info, 0, sizeof(*info));
+  double nb = nrm2(n, b);
+  if (!isfinite(nb)) return ORC_NONFINITE;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    return ORC_OK;
+  }
+  double *r = vec(n), *rh = vec(n), *p = vec(n), *v = vec(n), *s = vec(n),
+         *t = vec(n);
+  residual(&A, b, x, r);
+  double nr0 = nrm2(n, r);
+  double thr = threshold(stop, nb, nr0);
+  double base = baseline_norm(stop, nb, nr0);
+  int status = ORC_OK;
+  int64_t it = 0, repl = 0;
+  int restart = 1;
+  int check = nr0 <= thr;
+  double rho = 1.0, alpha = 1.0, omega = 1.0;
+  for (;;) {
+    if (check) {
+      residual(&A, b, x, r);
+      double nt = nrm2(n, r);
+      info->relres_true = nt / base;
+      if (nt <= thr) break;
+      if (repl >= stop->max_replacements) {
+        status = ORC_NOT_CONVERGED;
+        break;
+      }
+      repl++;
+      restart = 1;
+      check = 0;
+    }
+    if (restart) {
+      memcpy(rh, r, (size_t)n * sizeof(double));
+      for (int64_t i = 0; i < n; ++i) p[i] = v[i] = 0.0;
+      rho = alpha = omega = 1.0;
+      restart = 0;
+    }
+    if (it >= stop->max_iters) {
+      residual(&A, b, x, t);
+      info->relres_true = nrm2(n, t) / base;
+      status = ORC_NOT_CONVERGED;
+      break;
+    }
+    double rho1 = dot(n, rh, r);
+    if (!isfinite(rho1)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (rho1 == 0.0 || omega == 0.0) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    double beta = (rho1 / rho) * (alpha / omega);
+    for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+    matvec(&A, p, v);
+    double rv = dot(n, rh, v);
+    if (!isfinite(rv)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (rv == 0.0) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    alpha = rho1 / rv;
+    for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+    ++it;
+    double ns = nrm2(n, s);
+    info->relres_recurrence = ns / base;
+    if (ns <= thr) {
+      /* half step: the first update already meets the tolerance */
+      for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+      check = 1;
+      continue;
+    }
+    matvec(&A, s, t);
+    double tt = dot(n, t, t);
+    if (!isfinite(tt)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (tt == 0.0) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    omega = dot(n, t, s) / tt;
+    for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i] + omega * s[i];
+    for (int64_t i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
+    double nr = nrm2(n, r);
+    info->relres_recurrence = nr / base;
+    rho = rho1;
+    if (nr <= thr) check = 1;
+  }
+  info->iters = it;
+  info->replacements = repl;
+  free(r);
+  free(rh);
+  free(p);
+  free(v);
+  free(s);
+  free(t);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* GMRES(m) (Saad & Schultz 1986), modified Gram-Schmidt Arnoldi, Givens    */
+/* rotations on the Hessenberg matrix, restart after m steps                */
+/* ------------------------------------------------------------------------ */
+int orc_gmres(int64_t n, const int32_t* rowptr, const int32_t* col,
+              const double* val, const double* b, double* x, int64_t m,
+              const orc_stop* stop, orc_info* info, double* hist,
+              int64_t hist_cap) {
+  csr_t A = {n, rowptr, col, val};
+  memset(info, 0, sizeof(*info));
+  if (m < 1) return ORC_INVALID_ARG;
+  double nb = nrm2(n, b);
+  if (!isfinite(nb)) return ORC_NONFINITE;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    return ORC_OK;
+  }
+  double* V = vec((m + 1) * n);
+  double* H = vec((m + 1) * m); /* H[i*m + j] = h_{i,j}, 0-based */
+  double *cs = vec(m), *sn = vec(m), *g = vec(m + 1), *y = vec(m);
+  double *w = vec(n), *r = vec(n);
+  residual(&A, b, x, r);
+  double beta = nrm2(n, r);
+  double thr = threshold(stop, nb, beta);
+  double base = baseline_norm(stop, nb, beta);
+  info->relres_true = beta / base;
+  int status = ORC_OK;
+  int64_t it = 0, nhist = 0;
+  while (beta > thr) {
+    if (it >= stop->max_iters) {
+      status = ORC_NOT_CONVERGED;
+      break;
+    }
+    for (int64_t i = 0; i < n; ++i) V[i] = r[i] / beta;
+    for (int64_t i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = beta;
+    int64_t k = 0;
+    for (int64_t j = 0; j < m && it < stop->max_iters; ++j) {
+      double* vj = V + j * n;
+      matvec(&A, vj, w);
+      ++it;
+      for (int64_t i = 0; i <= j; ++i) {
+        double* vi = V + i * n;
+        double h = dot(n, w, vi);
+        H[i * m + j] = h;
+        for (int64_t l = 0; l < n; ++l) w[l] = w[l] - h * vi[l];
+      }
+      double hnext = nrm2(n, w);
+      if (!isfinite(hnext)) {
+        status = ORC_NONFINITE;
+        break;
+      }
+      H[(j + 1) * m + j] = hnext;
+      for (int64_t i = 0; i < j; ++i) {
+        double a = H[i * m + j], c = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * c;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      double a = H[j * m + j], c = H[(j + 1) * m + j];
+      double d = sqrt(a * a + c * c);
+      if (d == 0.0) {
+        status = ORC_BREAKDOWN;
+        break;
+      }
+      cs[j] = a / d;
+      sn[j] = c / d;
+      H[j * m + j] = d;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      double est = fabs(g[j + 1]);
+      info->relres_recurrence = est / base;
+      if (hist && nhist < hist_cap) hist[nhist++] = est;
+      if (est <= thr || hnext == 0.0) break; /* converged or happy breakdown */
+      double* vn = V + (j + 1) * n;
+      for (int64_t l = 0; l < n; ++l) vn[l] = w[l] / hnext;
+    }
+    if (status != ORC_OK) break;
+    /* back substitution R y = g, then x += V_k y */
+    for (int64_t i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int64_t l = i + 1; l < k; ++l) s = s - H[i * m + l] * y[l];
+      y[i] = s / H[i * m + i];
+    }
+    for (int64_t i = 0; i < k; ++i) {
+      double* vi = V + i * n;
+      for (int64_t l = 0; l < n; ++l) x[l] = x[l] + y[i] * vi[l];
+    }
+    residual(&A, b, x, r);
+    beta = nrm2(n, r);
+    info->relres_true = beta / base;
+    if (beta <= thr) break;
+    info->restarts++;
+  }
+  info->iters = it;
+  free(V);
+  free(H);
+  free(cs);
+  free(sn);
+  free(g);
+  free(y);
+  free(w);
+  free(r);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* mixed-precision iterative refinement                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t n;
+  const int32_t* rowptr;
+  const int32_t* col;
+  int kind;
+  const float* v32;
+  const uint16_t* h16;
+  const float* scale;
+} lowmat_t;
+
+/* FP32 operator: y_i = sum_j a_ij x_j in float, ascending order; for the
+ * FP16 storage y_i = s_i * sum_j float(h_ij) x_j.                         */
+static void low_matvec(const lowmat_t* L, const float* x, float* y) {
+  for (int64_t i = 0; i < L->n; ++i) {
+    float s = 0.0f;
+    for (int64_t k = L->rowptr[i]; k < L->rowptr[i + 1]; ++k) {
+      float a = L->kind == 0 ? L->v32[k] : (float)orc_f16_to_f64(L->h16[k]);
+      s = s + a * x[L->col[k]];
+    }
+    y[i] = L->kind == 0 ? s : L->scale[i] * s;
+  }
+}
+
+/* reductions accumulate in double and round once to float */
+static float fdot(int64_t n, const float* a, const float* b) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s = s + (double)a[i] * (double)b[i];
+  return (float)s;
+}
+
+/* inner FP32 CG from d = 0 on A_low d = f, to ||r|| <= tol * ||f|| */
+static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
+                      int64_t maxit) {
+  int64_t n = L->n;
+  float* r = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+  float* p = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+  float* q = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+  for (int64_t i = 0; i < n; ++i) {
+    d[i] = 0.0f;
+    r[i] = f[i];
+    p[i] = f[i];
+  }
+  float rho = fdot(n, r, r);
+  float thr = tol * sqrtf(rho);
+  int64_t it = 0;
+  while (sqrtf(rho) > thr && it < maxit) {
+    low_matvec(L, p, q);
+    float pq = fdot(n, p, q);
+    if (!(pq > 0.0f)) break;
+    float alpha = rho / pq;
+    for (int64_t i = 0; i < n; ++i) d[i] = d[i] + alpha * p[i];
+    for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+    float rho_new = fdot(n, r, r);
+    ++it;
+    if (sqrtf(rho_new) <= thr) break;
+    float beta = rho_new / rho;
+    for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+    rho = rho_new;
+  }
+  free(r);
+  free(p);
+  free(q);
+  return it;
+}
+
+int orc_ir(int64_t n, const int32_t* rowptr, const int32_t* col,
+           const double* val64, int low_kind, const float* val32,
+           const uint16_t* h16, const float* scale, const double* b,
+           double* x, double outer_tol, int64_t outer_max, double inner_tol,
+           int64_t inner_max, int last_step_variant, orc_ir_info* info) {
+  csr_t A = {n, rowptr, col, val64};
+  lowmat_t L = {n, rowptr, col, low_kind, val32, h16, scale};
+  memset(info, 0, sizeof(*info));
+  double nb = nrm2(n, b);
+  if (!isfinite(nb)) return ORC_NONFINITE;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    return ORC_OK;
+  }
+  double* r = vec(n);
+  float* f = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+  float* d = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+  int status = ORC_OK;
+  for (;;) {
+    residual(&A, b, x, r); /* FP64 residual with the FP64 matrix */
+    double nr = nrm2(n, r);
+    double relres = nr / nb;
+    info->relres_true = relres;
+    if (!isfinite(nr)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (relres <= outer_tol) break;
+    if (info->outer_iters >= outer_max) {
+      status = ORC_NOT_CONVERGED;
+      break;
+    }
+    double sigma = nr;
+    for (int64_t i = 0; i < n; ++i) f[i] = (float)(r[i] / sigma);
+    double tol = inner_tol;
+    if (last_step_variant && relres * inner_tol <= outer_tol) {
+      double t2 = 0.1 * outer_tol / relres;
+      if (t2 > tol) tol = t2;
+    }
+    info->inner_iters_total += low_cg(&L, f, d, (float)tol, inner_max);
+    for (int64_t i = 0; i < n; ++i) x[i] = x[i] + sigma * (double)d[i];
+    info->outer_iters++;
+  }
+  free(r);
+  free(f);
+  free(d);
+  return status;
+}

@@ -1,0 +1,136 @@
+/*
+ * oracle.h -- CPU oracle for the sparse matrix-vector product and the Krylov
+ * solvers of Tsai, Cojean & Anzt, "Porting a sparse linear algebra math
+ * library to Intel GPUs" (arXiv 2103.10116).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct FP64 definition that the GPU library is checked against.  Only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no source, header or helper with the GPU library and the
+ * GPU library never calls it.
+ *
+ * Conventions: n = rows, ncols = columns, int32 CSR indices, int64 sizes.
+ * Every routine is single-threaded and built with -ffp-contract=off, so the
+ * only fused multiply-adds are the explicit fma() calls of the exact
+ * two-product in the accurate dot product.
+ */
+#ifndef MXS_ORACLE_H
+#define MXS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORC_OK = 0,
+  ORC_INVALID_ARG = 1,
+  ORC_INVALID_MATRIX = 2,
+  ORC_UNSUPPORTED = 3,
+  ORC_NOT_CONVERGED = 6,
+  ORC_BREAKDOWN = 7,
+  ORC_NONFINITE = 8
+};
+
+/* ---- CSR ingest ------------------------------------------------------- */
+int orc_csr_validate(int64_t n, int64_t ncols, int64_t nnz,
+                     const int32_t* rowptr, const int32_t* col);
+
+/* ---- format conversions ----------------------------------------------- */
+void orc_csr_to_coo(int64_t n, const int32_t* rowptr, int32_t* row_out);
+void orc_coo_to_csr(int64_t n, int64_t nnz, const int32_t* row,
+                    int32_t* rowptr_out);
+int64_t orc_ell_width(int64_t n, const int32_t* rowptr);
+int64_t orc_ell_stride(int64_t n);
+void orc_csr_to_ell(int64_t n, const int32_t* rowptr, const int32_t* col,
+                    const double* val, int64_t K, int64_t stride,
+                    int32_t* ecol, double* eval);
+int64_t orc_hyb_width(int64_t n, const int32_t* rowptr, int value_bytes);
+int64_t orc_csr_to_hyb(int64_t n, const int32_t* rowptr, const int32_t* col,
+                       const double* val, int64_t K, int64_t stride,
+                       int32_t* ecol, double* eval, int32_t* crow,
+                       int32_t* ccol, double* cval);
+int orc_cast_f32(int64_t count, const double* in, float* out);
+uint16_t orc_f64_to_f16(double v);
+double orc_f16_to_f64(uint16_t h);
+int orc_rowscale_f16(int64_t n, const int32_t* rowptr, const double* val,
+                     uint16_t* h, float* scale);
+
+/* ---- SpMV: y = alpha*A*x + beta*y; beta == 0 never reads y -------------
+ * mode 0: accurate row sums (compensated dot product, rounded once)
+ * mode 1: naive ascending-order sums (for the dense cross-check)          */
+void orc_spmv_csr(int64_t n, const int32_t* rowptr, const int32_t* col,
+                  const double* val, const double* x, double alpha,
+                  double beta, double* y, int mode);
+void orc_spmv_coo(int64_t n, int64_t nnz, const int32_t* row,
+                  const int32_t* col, const double* val, const double* x,
+                  double alpha, double beta, double* y);
+void orc_spmv_ell(int64_t n, int64_t K, int64_t stride, const int32_t* ecol,
+                  const double* eval, const double* x, double alpha,
+                  double beta, double* y);
+void orc_spmv_hyb(int64_t n, int64_t K, int64_t stride, const int32_t* ecol,
+                  const double* eval, int64_t cnnz, const int32_t* crow,
+                  const int32_t* ccol, const double* cval, const double* x,
+                  double alpha, double beta, double* y);
+void orc_spmv_csr_f16(int64_t n, const int32_t* rowptr, const int32_t* col,
+                      const uint16_t* h, const float* scale, const double* x,
+                      double alpha, double beta, double* y);
+/* sum_j |a_ij| |x_j| per row (the scale of the per-entry error bound) */
+void orc_absrow(int64_t n, const int32_t* rowptr, const int32_t* col,
+                const double* val, const double* x, double* out);
+
+/* ---- dense reference routines ---------------------------------------- */
+void orc_dense_matvec(int64_t n, int64_t m, const double* A, const double* x,
+                      double* y);
+int orc_dense_lu_solve(int64_t n, const double* A, const double* b,
+                       double* x);
+
+/* ---- Krylov solvers --------------------------------------------------- */
+typedef struct {
+  int64_t max_iters;
+  double rel_tol;
+  double abs_tol;
+  int32_t baseline;     /* 0: relative to ||b||, 1: relative to ||r0|| */
+  int32_t max_replacements;
+} orc_stop;
+
+typedef struct {
+  int64_t iters;
+  double relres_recurrence;
+  double relres_true;
+  int64_t replacements;
+  int64_t restarts;
+} orc_info;
+
+/* hist (nullable, capacity hist_cap doubles): CG writes (alpha_k, beta_k)
+ * pairs, GMRES writes the residual estimate |g_{j+1}| after every step.  */
+int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
+           const double* val, const double* b, double* x,
+           const orc_stop* stop, orc_info* info, double* hist,
+           int64_t hist_cap);
+int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
+                 const double* val, const double* b, double* x,
+                 const orc_stop* stop, orc_info* info);
+int orc_gmres(int64_t n, const int32_t* rowptr, const int32_t* col,
+              const double* val, const double* b, double* x, int64_t m,
+              const orc_stop* stop, orc_info* info, double* hist,
+              int64_t hist_cap);
+
+/* Mixed-precision iterative refinement: FP64 residual and update, inner CG
+ * in FP32 on a low-precision copy of A.  low_kind 0: FP32 values (val32);
+ * low_kind 1: FP16 values with a per-row power-of-two scale (h16, scale). */
+typedef struct {
+  int64_t outer_iters;
+  int64_t inner_iters_total;
+  double relres_true;
+} orc_ir_info;
+int orc_ir(int64_t n, const int32_t* rowptr, const int32_t* col,
+           const double* val64, int low_kind, const float* val32,
+           const uint16_t* h16, const float* scale, const double* b,
+           double* x, double outer_tol, int64_t outer_max, double inner_tol,
+           int64_t inner_max, int last_step_variant, orc_ir_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

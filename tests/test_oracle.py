@@ -1,0 +1,289 @@
+"""Pins for the CPU oracle (no GPU): every oracle routine is checked against
+something other than itself -- hand-computed layouts, numpy's dense routines,
+closed-form stencil eigenpairs, CG/GMRES finite termination, IEEE conversions
+done by numpy -- chosen so that a dropped term, a wrong sign or index, or a
+transposed operand fails at least one test."""
+import numpy as np
+import pytest
+
+from conftest import load_golden
+from paper_2103_10116_amd import inputs as I
+
+U = 2.0 ** -53
+
+
+def small_from_golden():
+    g = load_golden("formats_small.txt")
+    A = I.CSRMatrix(g["n"][0], g["ncols"][0], np.array(g["rowptr"], np.int32),
+                    np.array(g["col"], np.int32), np.array(g["val"], float))
+    return g, A
+
+
+def random_pattern(n, m, density, seed, empty_rows=(), full_row=None):
+    g = I.rng(seed)
+    M = np.where(g.random((n, m)) < density, g.uniform(-1, 1, (n, m)), 0.0)
+    for r in empty_rows:
+        M[r, :] = 0.0
+    if full_row is not None:
+        M[full_row, :] = g.uniform(-1, 1, m)
+    return M
+
+
+# ---------------------------------------------------------------------------
+# ingest
+# ---------------------------------------------------------------------------
+def test_validate_accepts_and_rejects(orc):
+    g, A = small_from_golden()
+    assert orc.validate(A.n, A.ncols, A.rowptr, A.col) == orc.OK
+    bad = [
+        (np.array([1, 2, 2, 5, 6, 10]), A.col),          # rowptr[0] != 0
+        (np.array([0, 2, 1, 5, 6, 10]), A.col),          # not monotone
+        (A.rowptr, np.array([0, 3, 1, 2, 5, 4, 0, 1, 2, 6])),   # col >= ncols
+        (A.rowptr, np.array([3, 0, 1, 2, 5, 4, 0, 1, 2, 5])),   # unsorted row
+        (A.rowptr, np.array([0, 0, 1, 2, 5, 4, 0, 1, 2, 5])),   # duplicate
+        (A.rowptr, np.array([0, 3, -1, 2, 5, 4, 0, 1, 2, 5])),  # negative col
+    ]
+    for rp, ci in bad:
+        assert orc.validate(A.n, A.ncols, rp, ci) == orc.INVALID_MATRIX
+
+
+# ---------------------------------------------------------------------------
+# conversions: hand-computed layouts and round trips
+# ---------------------------------------------------------------------------
+def test_formats_match_hand_layout(orc):
+    g, A = small_from_golden()
+    assert np.array_equal(orc.csr_to_coo(A.n, A.rowptr), g["coo_row"])
+    E = orc.csr_to_ell(A)
+    assert (E.K, E.stride) == (g["ell_K"][0], g["ell_stride"][0])
+    exp_col = np.full(E.K * E.stride, -1, np.int32)
+    exp_val = np.zeros(E.K * E.stride)
+    for slot, c, v in g["ell_slot"]:
+        exp_col[slot] = c
+        exp_val[slot] = v
+    assert np.array_equal(E.col, exp_col)
+    assert np.array_equal(E.val, exp_val)
+    assert not np.signbit(E.val[exp_col < 0]).any()  # padding is +0.0
+    H = orc.csr_to_hyb(A, 8, K=1)
+    assert np.array_equal(H.ecol, exp_col[:64]) and np.array_equal(H.eval, exp_val[:64])
+    assert np.array_equal(H.crow, g["hyb1_coo_row"])
+    assert np.array_equal(H.ccol, g["hyb1_coo_col"])
+    assert np.array_equal(H.cval, g["hyb1_coo_val"])
+    st, h, s = orc.rowscale_f16(A)
+    assert st == orc.OK
+    assert np.array_equal(s, np.array(g["f16_scale"], np.float32))
+    assert np.array_equal(h, np.array(g["f16_bits"], np.uint16))
+
+
+def test_spmv_all_formats_hand_example(orc):
+    g, A = small_from_golden()
+    x = np.array(g["x"], float)
+    y = np.array(g["y"], float)
+    assert np.array_equal(orc.spmv_csr(A, x), y)
+    assert np.array_equal(orc.spmv_coo(A.n, orc.csr_to_coo(A.n, A.rowptr), A.col, A.val, x), y)
+    assert np.array_equal(orc.spmv_ell(orc.csr_to_ell(A), x), y)
+    for K in range(0, 5):
+        assert np.array_equal(orc.spmv_hyb(orc.csr_to_hyb(A, 8, K=K), x), y)
+    st, h, s = orc.rowscale_f16(A)
+    assert np.array_equal(orc.spmv_csr_f16(A, h, s, x), y)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_round_trips(orc, seed):
+    A = I.zipf_random(3000, 2.0, 200, seed=seed)
+    row = orc.csr_to_coo(A.n, A.rowptr)
+    assert np.array_equal(orc.coo_to_csr(A.n, row), A.rowptr)
+    E = orc.csr_to_ell(A)
+    # decode ELL column by column back to CSR arrays
+    cols = E.col.reshape(E.K, E.stride)[:, :A.n].T
+    vals = E.val.reshape(E.K, E.stride)[:, :A.n].T
+    mask = cols >= 0
+    assert np.array_equal(mask.sum(1), A.row_lengths())
+    assert np.array_equal(cols[mask], A.col) and np.array_equal(vals[mask], A.val)
+    assert (E.col.reshape(E.K, E.stride)[:, A.n:] == -1).all()
+    for vb in (8, 4):
+        H = orc.csr_to_hyb(A, vb)
+        hc = H.ecol.reshape(H.K, H.stride)[:, :A.n].T
+        lens = np.minimum(A.row_lengths(), H.K)
+        assert np.array_equal((hc >= 0).sum(1), lens)
+        assert len(H.crow) == int(np.maximum(A.row_lengths() - H.K, 0).sum())
+
+
+def test_hyb_width_byte_rule(orc):
+    # 64 rows (stride 64): an ELL column costs 64*(V+4) bytes and saves
+    # count*(V+8) COO bytes; the column is kept only if it saves strictly more
+    def width(nlong, vb):
+        lens = np.zeros(64, np.int64)
+        lens[:nlong] = 1
+        rp = np.zeros(65, np.int32)
+        rp[1:] = np.cumsum(lens)
+        return orc.hyb_width(64, rp, vb)
+    assert width(48, 8) == 0 and width(49, 8) == 1      # 48*16 == 64*12
+    assert width(42, 4) == 0 and width(43, 4) == 1      # 43*12 > 64*8
+    # a second column is kept only if it pays for itself too
+    lens = np.array([3] * 60 + [1] * 4)
+    rp = np.zeros(65, np.int32)
+    rp[1:] = np.cumsum(lens)
+    assert orc.hyb_width(64, rp, 8) == 3
+
+
+def test_cast_f32_matches_ieee(orc):
+    g = I.rng(5)
+    v = np.concatenate([g.standard_normal(10000) * 10.0 ** g.integers(-45, 38, 10000) * 0.3,
+                        [0.0, -0.0, np.inf, -np.inf, 3.4028234663852886e38, 1e-46, -1e-40]])
+    st, out = orc.cast_f32(v)
+    assert st == orc.OK
+    with np.errstate(over="ignore"):
+        ref = v.astype(np.float32)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    st, _ = orc.cast_f32(np.array([1.0, 3.5e38]))
+    assert st == orc.UNSUPPORTED
+    st, out = orc.cast_f32(np.array([np.nan]))
+    assert st == orc.OK and np.isnan(out[0])
+
+
+def test_f16_conversion_matches_ieee(orc):
+    g = I.rng(6)
+    v = np.concatenate([
+        g.standard_normal(4000) * 2.0 ** g.integers(-30, 18, 4000),
+        np.arange(-2048, 2049) * 2.0 ** -25,          # subnormal grid and its ties
+        np.arange(0, 1025) * 2.0 ** -24 + 2.0 ** -25,  # exact ties between subnormals
+        [65504.0, 65519.99, 65520.0, 1e6, -1e6, 2.0 ** -14, 2.0 ** -24, 2.0 ** -25,
+         2.0 ** -25 * 1.0000001, 0.0, -0.0, np.inf, -np.inf],
+        1.0 + np.arange(0, 64) * 2.0 ** -11,          # ties at 1.0 spacing
+    ])
+    bits = orc.f64_to_f16_bits(v)
+    with np.errstate(over="ignore"):
+        ref = v.astype(np.float16).view(np.uint16)
+    assert np.array_equal(bits, ref)
+    back = orc.f16_bits_to_f64(ref)
+    with np.errstate(over="ignore"):
+        assert np.array_equal(back, v.astype(np.float16).astype(np.float64))
+
+
+# ---------------------------------------------------------------------------
+# SpMV against dense products
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,density,empty,full", [
+    ((1, 1), 1.0, (), None), ((7, 7), 0.0, (), None), ((33, 40), 0.2, (0, 5, 32), 7),
+    ((64, 64), 0.5, (3,), 63), ((50, 17), 0.3, (), 0)])
+def test_spmv_vs_dense(orc, shape, density, empty, full):
+    M = random_pattern(*shape, density, seed=sum(shape), empty_rows=empty, full_row=full)
+    A = I.dense_to_csr(M)
+    x = I.rng(9).uniform(-1, 1, shape[1])
+    # naive sparse sum equals the naive dense loop exactly (same order,
+    # zeros of the dense matrix add nothing)
+    assert np.array_equal(orc.spmv_csr(A, x, mode="naive"), orc.dense_matvec(M, x))
+    # accurate sums agree with numpy's dense product within its error bound
+    bound = (shape[1] + 2) * U * (np.abs(M) @ np.abs(x)) + 1e-300
+    y = orc.spmv_csr(A, x)
+    assert (np.abs(y - M @ x) <= bound).all()
+    # integer data and dyadic x: every product and partial sum is exact
+    Mi = np.round(M * 8)
+    Ai = I.dense_to_csr(Mi)
+    xi = np.round(x * 1024) / 1024
+    assert np.array_equal(orc.spmv_csr(Ai, xi), Mi @ xi)
+    assert np.array_equal(orc.spmv_coo(Ai.n, orc.csr_to_coo(Ai.n, Ai.rowptr), Ai.col, Ai.val, xi), Mi @ xi)
+    assert np.array_equal(orc.spmv_ell(orc.csr_to_ell(Ai), xi), Mi @ xi)
+    assert np.array_equal(orc.spmv_hyb(orc.csr_to_hyb(Ai, 8), xi), Mi @ xi)
+
+
+def test_spmv_accurate_beats_naive(orc):
+    # catastrophic cancellation: 1e16 + 1 - 1e16 is 1 exactly
+    A = I.dense_to_csr(np.array([[1e16, 1.0, -1e16]]))
+    x = np.ones(3)
+    assert orc.spmv_csr(A, x)[0] == 1.0
+    assert orc.spmv_csr(A, x, mode="naive")[0] == 0.0
+
+
+def test_spmv_alpha_beta(orc):
+    g, A = small_from_golden()
+    x = np.array(g["x"], float)
+    y = np.array(g["y"], float)
+    y0 = np.array([1.0, -2.0, 0.5, 4.0, 8.0])
+    assert np.array_equal(orc.spmv_csr(A, x, alpha=2.0, beta=-1.0, y=y0), 2.0 * y - y0)
+    nan_y = np.full(5, np.nan)
+    for f in (lambda yy: orc.spmv_csr(A, x, 1.5, 0.0, yy),
+              lambda yy: orc.spmv_ell(orc.csr_to_ell(A), x, 1.5, 0.0, yy),
+              lambda yy: orc.spmv_hyb(orc.csr_to_hyb(A, 8, K=1), x, 1.5, 0.0, yy),
+              lambda yy: orc.spmv_coo(A.n, orc.csr_to_coo(A.n, A.rowptr), A.col, A.val, x, 1.5, 0.0, yy)):
+        assert np.array_equal(f(nan_y), 1.5 * y)   # beta == 0 never reads y
+
+
+def test_spmv_formats_agree_on_power_law(orc):
+    A = I.zipf_random(5000, 2.0, 1000, seed=11)
+    x = I.uniform_vector(A.n, 12)
+    y = orc.spmv_csr(A, x)
+    assert np.array_equal(orc.spmv_coo(A.n, orc.csr_to_coo(A.n, A.rowptr), A.col, A.val, x), y)
+    assert np.array_equal(orc.spmv_ell(orc.csr_to_ell(A), x), y)
+    assert np.array_equal(orc.spmv_hyb(orc.csr_to_hyb(A, 8), x), y)
+
+
+# ---------------------------------------------------------------------------
+# closed-form eigenpairs of the stencil matrices
+# ---------------------------------------------------------------------------
+def _modes(N, k, w=None):
+    j = np.arange(1, N + 1)
+    s = np.sin(j * k * np.pi / (N + 1))
+    return s if w is None else s * w ** (j / 2.0)
+
+
+def _check_eig(orc, A, v, lam):
+    r = orc.spmv_csr(A, v) - lam * v
+    scale = orc.absrow(A, v).max()
+    assert np.abs(r).max() <= 1e-13 * scale, np.abs(r).max() / scale
+
+
+@pytest.mark.parametrize("m,j,k", [(64, 1, 1), (64, 64, 64), (64, 3, 50), (9, 2, 7)])
+def test_poisson2d_eigenpairs(orc, m, j, k):
+    A = I.poisson2d(m)
+    vx, vy = _modes(m, j), _modes(m, k)
+    v = np.outer(vy, vx).ravel()  # index = x + m*y
+    lam = 4 - 2 * np.cos(j * np.pi / (m + 1)) - 2 * np.cos(k * np.pi / (m + 1))
+    _check_eig(orc, A, v, lam)
+
+
+@pytest.mark.parametrize("N,ks", [(16, (1, 1, 1)), (16, (16, 2, 9)), (128, (1, 1, 1)), (128, (128, 64, 3))])
+def test_poisson3d_eigenpairs(orc, N, ks):
+    A = I.poisson3d(N)
+    m = [_modes(N, k) for k in ks]
+    v = np.einsum("z,y,x->zyx", m[2], m[1], m[0]).ravel()
+    lam = 6 - sum(2 * np.cos(k * np.pi / (N + 1)) for k in ks)
+    _check_eig(orc, A, v, lam)
+
+
+@pytest.mark.parametrize("N,ks", [(12, (1, 1, 1)), (12, (12, 5, 2)), (40, (1, 40, 7))])
+def test_stencil27_eigenpairs(orc, N, ks):
+    A = I.stencil27(N)
+    assert A.nnz == (3 * N - 2) ** 3
+    m = [_modes(N, k) for k in ks]
+    v = np.einsum("z,y,x->zyx", m[2], m[1], m[0]).ravel()
+    lam = 27 - np.prod([1 + 2 * np.cos(k * np.pi / (N + 1)) for k in ks])
+    _check_eig(orc, A, v, lam)
+
+
+@pytest.mark.parametrize("N,ks", [(16, (1, 1, 1)), (16, (16, 3, 8)), (64, (2, 64, 31))])
+def test_convdiff_eigenpairs(orc, N, ks):
+    c = 10.0
+    h = 1.0 / (N + 1)
+    A = I.convdiff3d(N, c)
+    w = 1 + c * h  # sub-diagonal (upwind) coefficient magnitude
+    m = [_modes(N, k, w) for k in ks]
+    v = np.einsum("z,y,x->zyx", m[2], m[1], m[0]).ravel()
+    lam = sum((2 + c * h) - 2 * np.sqrt(w) * np.cos(k * np.pi / (N + 1)) for k in ks)
+    _check_eig(orc, A, v, lam)
+
+
+# ---------------------------------------------------------------------------
+# dense LU
+# ---------------------------------------------------------------------------
+def test_lu_vs_numpy(orc):
+    g = I.rng(21)
+    for n in (1, 2, 5, 30):
+        M = g.standard_normal((n, n)) + n * np.eye(n) * (g.random() > 0.5)
+        b = g.standard_normal(n)
+        st, x = orc.lu_solve(M, b)
+        assert st == orc.OK
+        xr = np.linalg.solve(M, b)
+        assert np.linalg.norm(x - xr) <= 1e-12 * np.linalg.cond(M) * np.linalg.norm(xr)
+    st, _ = orc.lu_solve(np.zeros((3, 3)), np.ones(3))
+    assert st == orc.BREAKDOWN

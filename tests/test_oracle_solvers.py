@@ -1,0 +1,214 @@
+"""Pins for the oracle's Krylov solvers and iterative refinement (no GPU):
+finite termination, eigenvector right-hand sides, Lanczos/Ritz values against
+closed-form spectra, dense solves by numpy and by the oracle's LU, breakdown
+and failure cases."""
+import numpy as np
+import pytest
+
+from paper_2103_10116_amd import inputs as I
+
+
+def _relerr(x, xr):
+    return np.linalg.norm(x - xr) / np.linalg.norm(xr)
+
+
+# ---------------------------------------------------------------------------
+# CG
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,seed", [(4, 1), (10, 2), (16, 3)])
+def test_cg_finite_termination(orc, n, seed):
+    # exact arithmetic ends in <= n steps; with kappa = 10 rounding does not
+    # delay it (larger kappa loses orthogonality and needs extra steps)
+    M = I.random_spd_small(n, 10.0, seed)
+    A = I.dense_to_csr(M)
+    b = I.rng(seed + 50).standard_normal(n)
+    r = orc.cg(A, b, tol=1e-12, maxit=n)
+    assert r.status == orc.OK and r.iters <= n
+    assert r.relres_true <= 1e-12
+    xr = np.linalg.solve(M, b)
+    assert _relerr(r.x, xr) <= 10.0 * 1e-10
+    st, xl = orc.lu_solve(M, b)
+    assert _relerr(r.x, xl) <= 10.0 * 1e-10
+
+
+def test_cg_eigenvector_rhs_one_step(orc):
+    m = 12
+    A = I.poisson2d(m)
+    j, k = 3, 5
+    s = lambda kk: np.sin(np.arange(1, m + 1) * kk * np.pi / (m + 1))
+    v = np.outer(s(k), s(j)).ravel()
+    lam = 4 - 2 * np.cos(j * np.pi / (m + 1)) - 2 * np.cos(k * np.pi / (m + 1))
+    r = orc.cg(A, v, tol=1e-12)
+    assert r.status == orc.OK and r.iters == 1
+    assert _relerr(r.x, v / lam) <= 1e-13
+
+
+def test_cg_k_eigenvectors_k_steps(orc):
+    m = 12
+    A = I.poisson2d(m)
+    s = lambda kk: np.sin(np.arange(1, m + 1) * kk * np.pi / (m + 1))
+    pairs = [(1, 1), (2, 5), (7, 3), (12, 12)]  # four distinct eigenvalues
+    b = sum(np.outer(s(k), s(j)).ravel() * (i + 1) for i, (j, k) in enumerate(pairs))
+    r = orc.cg(A, b, tol=1e-11)
+    assert r.status == orc.OK and r.iters <= len(pairs)
+
+
+def test_cg_ritz_values_match_closed_form(orc):
+    # the Lanczos tridiagonal built from CG's (alpha, beta) has extreme
+    # eigenvalues converging to those of A (2D 5-point, 64 x 64)
+    m = 64
+    A = I.poisson2d(m)
+    b = I.uniform_vector(A.n, 3)
+    r = orc.cg(A, b, tol=1e-10, hist=True)
+    assert r.status == orc.OK
+    al, be = r.hist[:, 0], r.hist[:, 1]
+    k = len(al)
+    T = np.zeros((k, k))
+    for i in range(k):
+        T[i, i] = 1.0 / al[i] + (be[i - 1] / al[i - 1] if i > 0 else 0.0)
+        if i + 1 < k:
+            T[i, i + 1] = T[i + 1, i] = np.sqrt(be[i]) / al[i]
+    ev = np.linalg.eigvalsh(T)
+    lmin = 4 - 4 * np.cos(np.pi / (m + 1))
+    lmax = 4 + 4 * np.cos(np.pi / (m + 1))
+    assert abs(ev[0] - lmin) <= 1e-8 * lmin
+    assert abs(ev[-1] - lmax) <= 1e-8 * lmax
+
+
+def test_cg_poisson_64(orc):
+    A = I.poisson2d(64)
+    b = orc.spmv_csr(A, np.ones(A.n))
+    r = orc.cg(A, b, tol=1e-10)
+    assert r.status == orc.OK and r.relres_true <= 1e-10
+    assert 100 <= r.iters <= 200
+    assert _relerr(r.x, np.ones(A.n)) <= 1711.7 * 1e-10
+
+
+def test_cg_special_cases(orc):
+    A = I.poisson2d(8)
+    r = orc.cg(A, np.zeros(A.n))
+    assert r.status == orc.OK and r.iters == 0 and not r.x.any()
+    b = np.ones(A.n)
+    b[3] = np.nan
+    assert orc.cg(A, b).status == orc.NONFINITE
+    r = orc.cg(A, np.ones(A.n), maxit=3)
+    assert r.status == orc.NOT_CONVERGED and r.iters == 3
+    # indefinite matrix: p.Ap <= 0 somewhere
+    M = np.diag([1.0, -1.0, 2.0, -3.0])
+    r = orc.cg(I.dense_to_csr(M), np.ones(4))
+    assert r.status == orc.BREAKDOWN
+    # already converged initial guess: 0 iterations
+    x0 = r_ = orc.cg(A, np.ones(A.n)).x
+    r = orc.cg(A, np.ones(A.n), x0=x0)
+    assert r.status == orc.OK and r.iters == 0
+
+
+# ---------------------------------------------------------------------------
+# BiCGSTAB
+# ---------------------------------------------------------------------------
+def test_bicgstab_scaled_identity(orc):
+    n = 20
+    A = I.dense_to_csr(3.0 * np.eye(n))
+    b = I.uniform_vector(n, 4)
+    r = orc.bicgstab(A, b, tol=1e-14)
+    assert r.status == orc.OK and r.iters == 1
+    assert np.allclose(r.x, b / 3.0, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (25, 2)])
+def test_bicgstab_nonsymmetric_vs_numpy(orc, n, seed):
+    g = I.rng(seed)
+    M = g.standard_normal((n, n)) * 0.3 + np.diag(np.full(n, 3.0))
+    b = g.standard_normal(n)
+    r = orc.bicgstab(I.dense_to_csr(M), b, tol=1e-12)
+    assert r.status == orc.OK and r.relres_true <= 1e-12
+    kappa = np.linalg.cond(M)
+    assert _relerr(r.x, np.linalg.solve(M, b)) <= kappa * 1e-10
+
+
+def test_bicgstab_breakdown(orc):
+    M = np.array([[0.0, 1.0], [-1.0, 0.0]])  # skew-symmetric: r0 . A r0 = 0
+    r = orc.bicgstab(I.dense_to_csr(M), np.array([1.0, 2.0]))
+    assert r.status == orc.BREAKDOWN
+
+
+def test_bicgstab_convdiff(orc):
+    A = I.convdiff3d(12)
+    xs = I.uniform_vector(A.n, 5)
+    b = orc.spmv_csr(A, xs)
+    r = orc.bicgstab(A, b, tol=1e-10)
+    assert r.status == orc.OK and r.relres_true <= 1e-10
+    assert orc.true_relres(A, b, r.x) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# GMRES(m)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,seed", [(5, 1), (18, 2)])
+def test_gmres_full_space_is_exact(orc, n, seed):
+    g = I.rng(seed)
+    M = g.standard_normal((n, n)) + np.diag(np.full(n, 2.0))
+    b = g.standard_normal(n)
+    r = orc.gmres(I.dense_to_csr(M), b, m=n, tol=1e-12, hist=True)
+    assert r.status == orc.OK and r.iters <= n and r.restarts == 0
+    assert _relerr(r.x, np.linalg.solve(M, b)) <= np.linalg.cond(M) * 1e-11
+    # the residual estimate |g_{j+1}| never increases within a cycle
+    assert (np.diff(r.hist) <= 1e-15 * r.hist[0]).all()
+
+
+def test_gmres_eigenvector_happy_breakdown(orc):
+    A = I.convdiff3d(6)
+    N, c = 6, 10.0
+    w = 1 + c / (N + 1)
+    s = lambda k: np.sin(np.arange(1, N + 1) * k * np.pi / (N + 1)) * w ** (np.arange(1, N + 1) / 2)
+    v = np.einsum("z,y,x->zyx", s(2), s(1), s(3)).ravel()
+    r = orc.gmres(A, v, m=30, tol=1e-12)
+    assert r.status == orc.OK and r.iters == 1
+
+
+def test_gmres_restarted_convdiff(orc):
+    A = I.convdiff3d(14)
+    xs = I.uniform_vector(A.n, 6)
+    b = orc.spmv_csr(A, xs)
+    r = orc.gmres(A, b, m=30, tol=1e-10, hist=True)
+    assert r.status == orc.OK and r.relres_true <= 1e-10
+    assert r.restarts >= 1  # 2744 unknowns need more than one cycle of 30
+    assert orc.true_relres(A, b, r.x) <= 1e-10
+
+
+def test_gmres_not_converged(orc):
+    A = I.convdiff3d(10)
+    r = orc.gmres(A, np.ones(A.n), m=5, tol=1e-10, maxit=7)
+    assert r.status == orc.NOT_CONVERGED and r.iters == 7
+
+
+# ---------------------------------------------------------------------------
+# iterative refinement
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("low", ["f32", "f16"])
+def test_ir_poisson(orc, low):
+    A = I.poisson3d(16)
+    xs = I.uniform_vector(A.n, 7)
+    b = orc.spmv_csr(A, xs)
+    r = orc.ir(A, b, low=low, tol=1e-10)
+    assert r.status == orc.OK and r.relres_true <= 1e-10
+    assert orc.true_relres(A, b, r.x) <= 1e-10
+    assert 2 <= r.outer_iters <= 5
+    ref = orc.cg(A, b, tol=1e-12)
+    assert _relerr(r.x, ref.x) <= 1e-8
+
+
+def test_ir_f16_storage_exact_for_poisson(orc):
+    A = I.poisson3d(8)
+    st, h, s = orc.rowscale_f16(A)
+    dec = orc.f16_bits_to_f64(h) * np.repeat(s.astype(float), A.row_lengths())
+    assert np.array_equal(dec, A.val)
+
+
+def test_ir_random_spd_small(orc):
+    A = I.random_spd(4000, seed=8)
+    xs = I.uniform_vector(A.n, 9)
+    b = orc.spmv_csr(A, xs)
+    for low in ("f32", "f16"):
+        r = orc.ir(A, b, low=low, tol=1e-10, last_step_variant=True)
+        assert r.status == orc.OK and r.relres_true <= 1e-10
