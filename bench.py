@@ -1,0 +1,362 @@
+"""Benchmark of the SpMV + Krylov hot path on one MI355X.
+
+One timed step = one SpMV y = A x in each of the four formats (CSR, COO,
+ELL, hybrid) and both value types (FP64, FP32) on the 27-point stencil
+matrix of a 128^3 grid (n = 2,097,152, nnz = 55,742,968), inputs resident
+in HBM.  `value` is the step's algorithmic bytes divided by its time.
+Alongside, the run measures the attainable HBM bandwidth, every format on
+the power-law matrices (n = 2^20, MALL flushed between repetitions), the
+Krylov solvers on the 128^3 Poisson and convection-diffusion matrices,
+iterative refinement against plain FP64 CG, and the CPU oracle on a
+bounded sample.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections ...]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SpMV GB/s & % HBM roofline; CG solves/s + p99 latency, batched vs plain"
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic bytes per product (each array counted once)
+# ---------------------------------------------------------------------------
+def spmv_bytes(fmt, desc, vb, xb, beta_nonzero=False):
+    n, nnz = desc["nrows"], desc["nnz"]
+    vec = n * xb * (3 if beta_nonzero else 2)  # x read, y write (+ y read)
+    if fmt == "csr":
+        return nnz * (vb + 4) + 4 * (n + 1) + vec
+    if fmt == "coo":
+        return nnz * (vb + 8) + vec
+    # ELL and HYB: useful bytes, i.e. the entries they hold, plus vectors
+    if fmt == "ell":
+        return nnz * (vb + 4) + vec
+    K, stride, cn = desc["ell_width"], desc["ell_stride"], desc["coo_nnz"]
+    return (nnz - cn) * (vb + 4) + cn * (vb + 8) + vec
+
+
+def ell_streamed_bytes(desc, vb, xb):
+    return desc["ell_width"] * desc["ell_stride"] * (vb + 4) + 2 * desc["nrows"] * xb
+
+
+class Timer:
+    """HIP events on the ctx stream (torch's current stream)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def time(self, fn, reps, flush=None):
+        torch = self.torch
+        times = []
+        if flush is None:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps * 1e-3, None
+        for _ in range(reps):
+            flush()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.mean(times)), float(np.median(times))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sections", default="probe,spmv,zipf,krylov,ir,cpu")
+    ap.add_argument("--grid", type=int, default=128, help="stencil grid side (128 = full size)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "design is described in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+    sections = set(args.sections.split(","))
+
+    import torch
+    from paper_2103_10116_amd import inputs as I
+    from paper_2103_10116_amd import mxs
+
+    dev = torch.device("cuda:0")
+    ctx = mxs.Context(0)
+    timer = Timer(torch)
+    out = {"metric": METRIC, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic"}
+    extra = {}
+
+    # ---------------- HBM probe ----------------
+    peak_meas = None
+    if "probe" in sections:
+        bw = mxs.hbm_probe(ctx, 1 << 30, 5)
+        peak_meas = bw["best_gbs"]
+        extra["hbm_probe_gbs"] = {k: round(v, 1) for k, v in bw.items()}
+        log("hbm probe", extra["hbm_probe_gbs"])
+
+    # ---------------- SpMV step on the 27-point stencil ----------------
+    N = args.grid
+    log(f"generating 27-point stencil {N}^3")
+    A = I.stencil27(N)
+    x64 = I.uniform_vector(A.n, I.VECTOR_SEED)
+    M = mxs.Matrix.from_host(ctx, A)
+    xd = {"f64": torch.from_numpy(x64).to(dev), "f32": torch.from_numpy(x64.astype(np.float32)).to(dev)}
+    yd = {"f64": torch.zeros(A.n, dtype=torch.float64, device=dev),
+          "f32": torch.zeros(A.n, dtype=torch.float32, device=dev)}
+    mats = {}
+    for fmt in ("csr", "coo", "ell", "hyb"):
+        for dt in ("f64", "f32"):
+            mats[(fmt, dt)] = M if (fmt, dt) == ("csr", "f64") else M.convert(fmt, dt)
+    per = {}
+    step_bytes = 0
+    for (fmt, dt), B in mats.items():
+        vb = 8 if dt == "f64" else 4
+        nbytes = spmv_bytes(fmt, B.info(), vb, vb)
+        step_bytes += nbytes
+        fn = lambda B=B, dt=dt: mxs.spmv(ctx, B, xd[dt], yd[dt])
+        for _ in range(args.warmup):
+            fn()
+        t, _ = timer.time(fn, max(args.steps, 10))
+        per[f"{fmt}_{dt}"] = {"us": round(t * 1e6, 2), "GBs": round(nbytes / t / 1e9, 1),
+                              "bytes": nbytes,
+                              "frac_spec": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 4)}
+        if peak_meas:
+            per[f"{fmt}_{dt}"]["frac_measured"] = round(nbytes / t / 1e9 / peak_meas, 4)
+        log(f"stencil27 {fmt} {dt}: {t*1e6:.1f} us  {nbytes/t/1e9:.0f} GB/s")
+
+    def step():
+        for (fmt, dt), B in mats.items():
+            mxs.spmv(ctx, B, xd[dt], yd[dt])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = step_bytes / (ms_step * 1e-3) / 1e9
+    out.update({"value": round(value, 1), "ms_per_step": round(ms_step, 4)})
+    out["config"] = {"workload": f"SpMV y=Ax, 27-point stencil {N}^3 (n={A.n}, nnz={A.nnz}), "
+                                 "CSR+COO+ELL+HYB x FP64+FP32 per step",
+                     "n": A.n, "nnz": A.nnz, "step_bytes": step_bytes,
+                     "wall_s_timed": round(wall, 4)}
+    # dominant kernel: the slowest of the step
+    dom = max(per, key=lambda k: per[k]["us"])
+    d = per[dom]
+    out["roofline"] = {"bound": "hbm", "kernel": f"spmv_{dom}", "achieved": d["GBs"],
+                       "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": round(d["GBs"] / PEAK_HBM_GBS, 4),
+                       "bytes_per_launch": d["bytes"], "us_per_launch": d["us"],
+                       "traffic": None}
+    if peak_meas:
+        out["roofline"]["measured_peak"] = round(peak_meas, 1)
+        out["roofline"]["frac_measured"] = round(d["GBs"] / peak_meas, 4)
+    extra["stencil27_per_kernel"] = per
+    for k in list(mats):
+        if k != ("csr", "f64"):
+            mats[k].close()
+    del mats
+
+    # ---------------- power-law matrices, cold (MALL flushed) ----------------
+    if "zipf" in sections:
+        zres = {}
+        for label, s in (("zipf_s2.0", 2.0), ("zipf_s1.79_mean16", 1.79)):
+            log(f"generating {label}")
+            Z = I.zipf_random(2 ** 20, s, 4096)
+            Zm = mxs.Matrix.from_host(ctx, Z)
+            zx = {"f64": torch.from_numpy(I.uniform_vector(Z.n, I.VECTOR_SEED)).to(dev)}
+            zx["f32"] = zx["f64"].float()
+            zy = {"f64": torch.zeros(Z.n, dtype=torch.float64, device=dev),
+                  "f32": torch.zeros(Z.n, dtype=torch.float32, device=dev)}
+            r = {"nnz": Z.nnz, "max_row": int(Z.row_lengths().max())}
+            for fmt in ("csr", "coo", "hyb", "ell"):
+                for dt in ("f64", "f32"):
+                    B = Zm if (fmt, dt) == ("csr", "f64") else Zm.convert(fmt, dt)
+                    vb = 8 if dt == "f64" else 4
+                    info = B.info()
+                    nbytes = spmv_bytes(fmt, info, vb, vb)
+                    fn = lambda B=B, dt=dt: mxs.spmv(ctx, B, zx[dt], zy[dt])
+                    fn()
+                    t_cold, med = timer.time(fn, 10, flush=lambda: mxs.flush_cache(ctx, 1 << 30))
+                    t_warm, _ = timer.time(fn, 10)
+                    e = {"cold_us": round(t_cold * 1e6, 2), "cold_GBs": round(nbytes / t_cold / 1e9, 1),
+                         "warm_us": round(t_warm * 1e6, 2), "warm_GBs_cache_assisted": round(nbytes / t_warm / 1e9, 1),
+                         "bytes": nbytes}
+                    if fmt == "ell":
+                        e["ell_width"] = info["ell_width"]
+                        e["streamed_bytes_if_fully_read"] = ell_streamed_bytes(info, vb, vb)
+                    if fmt == "hyb":
+                        e["ell_width"] = info["ell_width"]
+                        e["coo_nnz"] = info["coo_nnz"]
+                    r[f"{fmt}_{dt}"] = e
+                    log(f"{label} {fmt} {dt}: cold {t_cold*1e6:.1f} us {nbytes/t_cold/1e9:.0f} GB/s, "
+                        f"warm {t_warm*1e6:.1f} us")
+                    if B is not Zm:
+                        B.close()
+            Zm.close()
+            zres[label] = r
+        extra["powerlaw_2p20"] = zres
+
+    # ---------------- Krylov solvers ----------------
+    if "krylov" in sections:
+        kr = {}
+        # 2D Poisson 64x64, b = A * ones (small: launch/latency bound)
+        P = I.poisson2d(64)
+        Pm = mxs.Matrix.from_host(ctx, P)
+        ones = torch.ones(P.n, dtype=torch.float64, device=dev)
+        b = torch.zeros(P.n, dtype=torch.float64, device=dev)
+        mxs.spmv(ctx, Pm, ones, b)
+        xs = torch.zeros_like(b)
+        lat = []
+        for i in range(25):
+            xs.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = mxs.solve(ctx, "cg", Pm, b, xs, tol=1e-10)
+            lat.append(time.perf_counter() - t0)
+        lat = np.array(lat[3:])
+        kr["cg_poisson2d_64"] = {"iters": r.iters, "relres_true": r.relres_true,
+                                 "solves_per_s": round(1.0 / lat.mean(), 1),
+                                 "p50_ms": round(np.percentile(lat, 50) * 1e3, 3),
+                                 "p99_ms": round(np.percentile(lat, 99) * 1e3, 3)}
+        log("cg poisson2d 64", kr["cg_poisson2d_64"])
+        # 3D problems at 128^3
+        for name, gen, solver in (("cg_poisson3d", I.poisson3d, "cg"),
+                                  ("bicgstab_convdiff3d", I.convdiff3d, "bicgstab"),
+                                  ("gmres30_convdiff3d", I.convdiff3d, "gmres")):
+            Q = gen(N)
+            Qm = mxs.Matrix.from_host(ctx, Q)
+            xstar = torch.from_numpy(I.uniform_vector(Q.n, I.VECTOR_SEED)).to(dev)
+            bq = torch.zeros(Q.n, dtype=torch.float64, device=dev)
+            mxs.spmv(ctx, Qm, xstar, bq)
+            xq = torch.zeros_like(bq)
+            ts = []
+            for rep in range(3):
+                xq.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = mxs.solve(ctx, solver, Qm, bq, xq, tol=1e-10, restart=30)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
+            err = float(torch.linalg.norm(xq - xstar) / torch.linalg.norm(xstar))
+            csr_b = Q.nnz * 12 + 4 * (Q.n + 1) + 16 * Q.n
+            kr[name] = {"n": Q.n, "nnz": Q.nnz, "iters": r.iters, "restarts": r.restarts,
+                        "relres_true": r.relres_true, "err_vs_xstar": err,
+                        "time_s": round(t, 4), "solves_per_s": round(1 / t, 2),
+                        "ms_per_iter": round(t / max(r.iters, 1) * 1e3, 4),
+                        "spmv_bytes": csr_b}
+            log(name, kr[name])
+            Qm.close()
+        extra["krylov"] = kr
+
+    # ---------------- iterative refinement vs plain FP64 CG ----------------
+    if "ir" in sections:
+        irr = {}
+        for name, gen in (("poisson3d_128", lambda: I.poisson3d(N)),
+                          ("random_spd_2p20", lambda: I.random_spd(2 ** 20))):
+            log("IR", name)
+            Q = gen()
+            Qm = mxs.Matrix.from_host(ctx, Q)
+            xstar = torch.from_numpy(I.uniform_vector(Q.n, I.VECTOR_SEED)).to(dev)
+            bq = torch.zeros(Q.n, dtype=torch.float64, device=dev)
+            mxs.spmv(ctx, Qm, xstar, bq)
+            xq = torch.zeros_like(bq)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = mxs.solve(ctx, "cg", Qm, bq, xq, tol=1e-10, raise_on_error=False)
+            torch.cuda.synchronize()
+            t_plain = time.perf_counter() - t0
+            x_plain = xq.clone()
+            e = {"plain_f64_cg": {"iters": r.iters, "status": r.status, "time_s": round(t_plain, 4),
+                                  "relres_true": r.relres_true}}
+            for low in ("f32", "f16"):
+                for variant in (False, True):
+                    L = Qm.convert("csr", low)
+                    xq.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ri = mxs.solve_ir(ctx, Qm, L, bq, xq, tol=1e-10, last_step_variant=variant,
+                                      raise_on_error=False)
+                    torch.cuda.synchronize()
+                    t_ir = time.perf_counter() - t0
+                    err = float(torch.linalg.norm(xq - x_plain) / torch.linalg.norm(x_plain))
+                    e[f"ir_{low}{'_laststep' if variant else ''}"] = {
+                        "outer": ri.outer_iters, "inner_total": ri.inner_iters_total,
+                        "status": ri.status, "relres_true": ri.relres_true,
+                        "time_s": round(t_ir, 4), "speedup_vs_plain": round(t_plain / t_ir, 3),
+                        "err_vs_fp64_cg": err}
+                    L.close()
+            irr[name] = e
+            log(name, json.dumps(e))
+            Qm.close()
+        extra["iterative_refinement"] = irr
+
+    # ---------------- CPU oracle baseline ----------------
+    if "cpu" in sections:
+        import oracle
+        xs64 = I.uniform_vector(A.n, I.VECTOR_SEED)
+        oracle.lib()
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            oracle.spmv_csr(A, xs64)
+            reps += 1
+            if time.perf_counter() - t0 > 10.0:
+                break
+        tcpu = (time.perf_counter() - t0) / reps
+        b_csr = spmv_bytes("csr", {"nrows": A.n, "nnz": A.nnz}, 8, 8)
+        out["cpu_baseline"] = {"value": round(b_csr / tcpu / 1e9, 3), "unit": "GB/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{reps} FP64 CSR products of the 27-point {N}^3 matrix "
+                                         f"(accurate row sums, 1 thread), {tcpu:.3f} s each",
+                               "cpu": _cpu_model()}
+    out["extra"] = extra
+    print(json.dumps(out), flush=True)
+    M.close()
+    ctx.close()
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,270 @@
+/*
+ * mxs.h -- C ABI of libmxs, an MI355X (gfx950) implementation of the sparse
+ * matrix-vector product and the Krylov solvers studied in Tsai, Cojean &
+ * Anzt, "Porting a sparse linear algebra math library to Intel GPUs"
+ * (arXiv 2103.10116), section "Central Sparse Linear Algebra Functionality".
+ *
+ * General rules
+ * -------------
+ *  - Every function returns an mxs_status; MXS_OK (0) is success.  Output
+ *    parameters are written only on success (solver info blocks are also
+ *    written when the status is MXS_NOT_CONVERGED or MXS_BREAKDOWN).
+ *  - No C++ exception crosses this boundary.  mxs_last_error(ctx) returns a
+ *    human-readable detail string for the last failing call on that ctx.
+ *  - Indices are int32 (n, ncols and nnz must be <= INT32_MAX, otherwise
+ *    MXS_UNSUPPORTED); sizes in the signatures are int64.
+ *  - "Device pointer" means memory on the ctx's GPU (e.g. a torch tensor's
+ *    data_ptr()).  The library never frees memory it did not allocate.
+ *  - All GPU work is enqueued on the ctx's HIP stream.  mxs_spmv returns
+ *    without synchronising; calls that must report a result to the host
+ *    (matrix creation/conversion, solvers, probes) synchronise that stream.
+ *  - A ctx must not be used by two host threads at the same time.  Two
+ *    SpMVs with the same COO or hybrid matrix must not run concurrently on
+ *    different streams (the matrix owns a small scratch array per chunk).
+ */
+#ifndef MXS_H
+#define MXS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mxs_status;
+#define MXS_OK 0
+#define MXS_INVALID_ARG 1      /* bad argument (NULL handle, size < 0, ...)   */
+#define MXS_INVALID_MATRIX 2   /* CSR failed validation (see mxs_matrix_create_csr) */
+#define MXS_UNSUPPORTED 3      /* size beyond int32, value outside FP32 range, format/dtype combination not offered */
+#define MXS_OOM 4              /* device allocation failed                     */
+#define MXS_HIP 5              /* a HIP runtime call failed                    */
+#define MXS_NOT_CONVERGED 6    /* max_iters reached; x holds the last iterate  */
+#define MXS_BREAKDOWN 7        /* solver breakdown (e.g. p.Ap <= 0 in CG)      */
+#define MXS_NONFINITE 8        /* NaN/Inf met in the right-hand side or a reduction */
+#define MXS_BUDGET 9           /* request exceeds the batch memory budget     */
+#define MXS_PENDING 10         /* batch poll: not finished yet (not an error) */
+
+typedef enum { MXS_CSR = 0, MXS_COO = 1, MXS_ELL = 2, MXS_HYB = 3 } mxs_format;
+
+/* Value storage: FP64; FP32 (round to nearest even from FP64); FP16 with a
+ * per-row power-of-two scale s_i = 2^ceil(log2 max_j |a_ij|) held in FP32
+ * and binary16 codes of a_ij / s_i (CSR only). */
+typedef enum { MXS_F64 = 0, MXS_F32 = 1, MXS_F16_ROWSCALED = 2 } mxs_dtype;
+
+typedef struct mxs_ctx mxs_ctx;
+typedef struct mxs_matrix mxs_matrix;
+
+/* Optional device allocator.  alloc returns device memory of at least
+ * `bytes` bytes usable on `stream` (NULL on failure); free releases it. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* user;
+} mxs_allocator;
+
+/* ---------------------------------------------------------------------- */
+/* context                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` that enqueues its work on
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream).  `alloc`
+ * may be NULL, in which case hipMalloc/hipFree are used.  The stream is
+ * borrowed and must outlive the context. */
+mxs_status mxs_ctx_create(int device, void* hip_stream, const mxs_allocator* alloc,
+                          mxs_ctx** out);
+/* Releases the context's workspaces.  NULL is a no-op. */
+mxs_status mxs_ctx_destroy(mxs_ctx* ctx);
+/* Switches the stream later calls enqueue on. */
+mxs_status mxs_ctx_set_stream(mxs_ctx* ctx, void* hip_stream);
+/* Waits for all work enqueued on the ctx stream. */
+mxs_status mxs_ctx_synchronize(mxs_ctx* ctx);
+
+/* ---------------------------------------------------------------------- */
+/* matrices                                                                */
+/* ---------------------------------------------------------------------- */
+#define MXS_HOST_PTRS 0   /* rowptr/col/val are host memory (copied in)   */
+#define MXS_DEVICE_PTRS 1 /* rowptr/col/val are device memory (copied)    */
+
+/* Ingest a CSR matrix (paper, section "Central Sparse Linear Algebra
+ * Functionality": row pointers to the first entry of each row of a
+ * row-sorted coordinate list).  Layout: rowptr[nrows+1] int32,
+ * col[nnz] int32, val[nnz] FP64.  The arrays are validated on the GPU:
+ * rowptr[0] == 0, rowptr non-decreasing, rowptr[nrows] == nnz,
+ * 0 <= col < ncols, columns strictly ascending within each row (sorted, no
+ * duplicates); any violation returns MXS_INVALID_MATRIX.  The matrix owns
+ * device copies of the arrays (format MXS_CSR, dtype MXS_F64) and the
+ * row-block partition its SpMV kernel uses.  Synchronises the ctx stream. */
+mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
+                                 const int32_t* rowptr, const int32_t* col,
+                                 const double* val, int flags, mxs_matrix** out);
+
+typedef struct {
+  int64_t ell_width;      /* ELL: 0 = max row length; HYB: 0 = byte-model width, else forced K */
+  int64_t max_ell_bytes;  /* 0 = no limit; ELL/HYB larger than this -> MXS_UNSUPPORTED */
+  int32_t block_nnz;      /* CSR/COO: entries per work unit (256, 512 or 1024; others are rounded up); 0 = 512 */
+} mxs_convert_opts;
+
+/* Converts `src` (an FP64 CSR matrix from mxs_matrix_create_csr) to another
+ * format and value type, on the GPU.  Layouts (all int32 indices):
+ *  - CSR: as ingested.
+ *  - COO: row[k], col[k], val[k] in exactly the CSR order (row-major,
+ *    columns ascending).
+ *  - ELL: width K (max row length unless forced), stride = nrows rounded up
+ *    to a multiple of 64; slot (i, j) at j*stride + i (int64 offset) holds
+ *    the j-th entry of row i; padding slots hold column -1 and value +0.
+ *  - HYB: ELL part of width K_h holding the first min(L_i, K_h) entries of
+ *    each row, the remaining entries in a COO part in CSR order.  The
+ *    default K_h is the largest K for which each ELL column saves more COO
+ *    bytes than it costs: #{rows with L_i >= K} * (V+8) > stride * (V+4),
+ *    V = value bytes (the byte-per-entry model of the paper's "SpMV
+ *    Performance Analysis" subsection).
+ *  - F32 values are round-to-nearest-even casts; a finite FP64 value beyond
+ *    the FP32 range returns MXS_UNSUPPORTED.  F16_ROWSCALED is CSR only.
+ * The new matrix is independent of `src`.  Synchronises the ctx stream. */
+mxs_status mxs_matrix_convert(mxs_ctx* ctx, const mxs_matrix* src, mxs_format fmt,
+                              mxs_dtype dt, const mxs_convert_opts* opts, mxs_matrix** out);
+
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  int32_t format, dtype;
+  int64_t ell_width, ell_stride; /* ELL / ELL part of HYB */
+  int64_t coo_nnz;               /* COO entries (HYB: overflow part) */
+  int64_t blocks;                /* work units of the SpMV kernel */
+  int64_t bytes;                 /* device bytes owned by the matrix */
+  int32_t block_nnz;
+} mxs_matrix_desc;
+
+mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out);
+
+/* Arrays a matrix exposes to mxs_matrix_export. */
+typedef enum {
+  MXS_ARR_ROWPTR = 0,  /* CSR: int32[nrows+1]                        */
+  MXS_ARR_COL = 1,     /* CSR/COO: int32[nnz]                        */
+  MXS_ARR_VAL = 2,     /* CSR/COO: value type [nnz] (F16: uint16)   */
+  MXS_ARR_ROW = 3,     /* COO: int32[nnz]                            */
+  MXS_ARR_ELL_COL = 4, /* ELL/HYB: int32[K*stride]                   */
+  MXS_ARR_ELL_VAL = 5, /* ELL/HYB: value type [K*stride]            */
+  MXS_ARR_COO_ROW = 6, /* HYB overflow: int32[coo_nnz]               */
+  MXS_ARR_COO_COL = 7,
+  MXS_ARR_COO_VAL = 8,
+  MXS_ARR_SCALE = 9    /* F16_ROWSCALED: float[nrows]                */
+} mxs_array;
+
+/* Copies one array of `A` to host memory `dst` of `bytes` bytes (must equal
+ * the array's size, else MXS_INVALID_ARG).  Synchronises the ctx stream. */
+mxs_status mxs_matrix_export(mxs_ctx* ctx, const mxs_matrix* A, mxs_array which, void* dst,
+                             size_t bytes);
+
+/* Frees the matrix's device memory.  NULL is a no-op. */
+mxs_status mxs_matrix_destroy(mxs_matrix* A);
+
+/* ---------------------------------------------------------------------- */
+/* sparse matrix-vector product                                            */
+/* ---------------------------------------------------------------------- */
+
+/* y = alpha * A * x + beta * y (paper, section "Central Sparse Linear
+ * Algebra Functionality"), any format.  alpha and beta point to host
+ * scalars of the compute type: double for F64 matrices, float for F32 and
+ * F16_ROWSCALED.  x (ncols entries) and y (nrows entries) are device
+ * vectors of the compute type; they must not overlap.  beta == 0 never
+ * reads y (NaN/Inf in the old y do not propagate).  Asynchronous. */
+mxs_status mxs_spmv(mxs_ctx* ctx, const void* alpha, const mxs_matrix* A, const void* x,
+                    const void* beta, void* y);
+
+/* ---------------------------------------------------------------------- */
+/* Krylov solvers                                                          */
+/* ---------------------------------------------------------------------- */
+typedef enum { MXS_CG = 0, MXS_BICGSTAB = 1, MXS_GMRES = 2 } mxs_solver;
+
+#define MXS_BASELINE_RHS 0      /* tolerance relative to ||b||_2          */
+#define MXS_BASELINE_INITIAL 1  /* tolerance relative to ||b - A x0||_2   */
+
+typedef struct {
+  int64_t max_iters;        /* CG/BiCGSTAB iterations, GMRES inner steps */
+  double rel_tol;           /* stop when ||r|| <= max(rel_tol*baseline, abs_tol) */
+  double abs_tol;
+  int32_t baseline;         /* MXS_BASELINE_* */
+  int32_t check_every;      /* iterations between host reads of the device convergence flag (0 = default) */
+  int32_t max_replacements; /* true-residual replacements before NOT_CONVERGED (default 3 if < 0) */
+} mxs_stop;
+
+typedef struct {
+  int32_t restart; /* GMRES restart length m (0 = 30) */
+} mxs_solver_opts;
+
+typedef struct {
+  int64_t iters;             /* SpMV-based iterations (BiCGSTAB: full or half steps; GMRES: inner steps) */
+  double relres_recurrence;  /* last recurrence residual / baseline */
+  double relres_true;        /* ||b - A x|| / baseline, recomputed in FP64 at the end */
+  int64_t replacements;
+  int64_t restarts;
+  int32_t status;
+} mxs_solve_info;
+
+/* Solves A x = b (paper, section "Central Sparse Linear Algebra
+ * Functionality"; textbook forms from Saad 2003 and, for GMRES, Saad &
+ * Schultz 1986).  A: an F64 matrix in any format (else MXS_UNSUPPORTED);
+ * b, x: FP64 device vectors of nrows entries, x holds x0 on entry and the
+ * iterate on exit.  CG: Hestenes-Stiefel.  BiCGSTAB: r_hat = r0.  GMRES(m):
+ * classical Gram-Schmidt with reorthogonalisation, Givens rotations and
+ * the triangular solve on the GPU.  The solver stops when the recurrence
+ * residual meets the tolerance and then checks the true residual b - A x in
+ * FP64; if that fails it replaces r by it (CG/BiCGSTAB restart from the
+ * current x) up to max_replacements times.  b == 0 returns x = 0 after 0
+ * iterations.  Returns MXS_OK, MXS_NOT_CONVERGED, MXS_BREAKDOWN or
+ * MXS_NONFINITE; `info` (nullable) is filled in all four cases.
+ * Synchronises the ctx stream. */
+mxs_status mxs_solve(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, const double* b,
+                     double* x, const mxs_stop* stop, const mxs_solver_opts* opts,
+                     mxs_solve_info* info);
+
+typedef struct {
+  int64_t outer_iters;
+  int64_t inner_iters_total;
+  double relres_true;   /* final ||b - A64 x|| / ||b|| in FP64 */
+  int32_t status;
+} mxs_ir_info;
+
+/* Mixed-precision iterative refinement (not in the paper; the classical
+ * scheme): r = b - A64 x in FP64 with the FP64 matrix, stop when
+ * ||r||/||b|| <= outer->rel_tol, else solve A_low d = r/||r|| by CG in FP32
+ * (FP32 vectors and accumulation) to inner_rel_tol and update
+ * x += ||r|| d in FP64.  A64: F64 CSR; A_low: F32 or F16_ROWSCALED CSR with
+ * the same pattern.  last_step_variant != 0 loosens the inner tolerance to
+ * max(inner_rel_tol, 0.1*tol/relres) once relres*inner_rel_tol <= tol.
+ * Synchronises the ctx stream. */
+mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A_low,
+                        const double* b, double* x, const mxs_stop* outer,
+                        double inner_rel_tol, int64_t inner_max, int32_t last_step_variant,
+                        mxs_ir_info* info);
+
+/* ---------------------------------------------------------------------- */
+/* measurement                                                             */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  double read_gbs;   /* sum-reduction over one array          */
+  double copy_gbs;   /* b = a                                  */
+  double triad_gbs;  /* a = b + s*c                            */
+  double best_gbs;   /* max of the three                       */
+} mxs_bw_result;
+
+/* Attainable HBM bandwidth, in the spirit of the BabelStream runs of the
+ * paper's "Bandwidth Tests and Roofline Performance Model" subsection:
+ * `bytes` per array (>= 1 GiB recommended, well beyond the 256 MB
+ * Infinity Cache), `reps` timed repetitions per kernel (best kept).
+ * Counts bytes read + written.  Synchronises the ctx stream. */
+mxs_status mxs_hbm_probe(mxs_ctx* ctx, size_t bytes, int reps, mxs_bw_result* out);
+
+/* Writes `bytes` bytes of a ctx-owned scratch buffer so that later reads
+ * come from HBM rather than from the last-level cache.  Asynchronous. */
+mxs_status mxs_flush_cache(mxs_ctx* ctx, size_t bytes);
+
+const char* mxs_status_string(mxs_status s);
+const char* mxs_last_error(const mxs_ctx* ctx);
+const char* mxs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MXS_H */

@@ -1,0 +1,188 @@
+// common.h -- internal declarations of libmxs (not part of the C ABI).
+//
+// Device-side conventions for gfx950:
+//  * wave64 everywhere; reductions inside a wave use xor-butterflies, whose
+//    result is bitwise identical in every lane (each step adds the same two
+//    operands in both partner lanes), so every reduction is deterministic.
+//  * cross-block reductions never use floating-point atomics: blocks write
+//    partial sums to fixed slots and the last block to finish (ticket
+//    counter) adds them in slot order.  The ticket is reset by that block,
+//    so no memset is needed between launches.
+//  * work-groups are dispatched round-robin over the 8 XCDs; kernels that
+//    stream rows remap blockIdx so that each XCD (and its private L2) works
+//    on one contiguous eighth of the rows and of the x-vector window they
+//    gather from.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mxs.h"
+
+namespace mxs {
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;
+
+// ---------------------------------------------------------------------------
+// host-side objects
+// ---------------------------------------------------------------------------
+struct Allocator {
+  mxs_allocator cb{};
+  bool custom = false;
+  void* stream = nullptr;
+  void* alloc(size_t bytes) const;
+  void release(void* p) const;
+};
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace mxs
+
+struct mxs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  mxs::Allocator alloc;
+  std::string last_error;
+  int num_cus = 256;
+  // grow-only scratch for solvers and format conversion
+  mxs::Workspace ws;
+  // pinned host mirror of small device state blocks
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  // cache-flush buffer
+  void* flush = nullptr;
+  size_t flush_bytes = 0;
+};
+
+namespace mxs {
+
+// CSR: rows partitioned into blocks of at most block_nnz entries (a row
+// longer than that is a block on its own); one wave per block.
+struct CsrPart {
+  int32_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  void* val = nullptr;
+  float* scale = nullptr;  // F16_ROWSCALED only
+  int32_t* blocks = nullptr;
+  int64_t nblocks = 0;
+  int block_nnz = 512;
+};
+
+// COO: equal chunks of block_nnz entries, one wave per chunk.  Rows cut by
+// a chunk boundary are completed by a fix-up pass from per-chunk
+// continuation partials; rows with no entry are listed in empty_rows.
+struct CooPart {
+  int32_t* row = nullptr;
+  int32_t* col = nullptr;
+  void* val = nullptr;
+  int64_t nnz = 0;
+  int64_t nchunks = 0;
+  int block_nnz = 512;
+  int32_t* cont_row = nullptr;
+  void* cont_val = nullptr;
+  int32_t* empty_rows = nullptr;
+  int64_t nempty = 0;
+};
+
+// ELL: column-major padded slots; `waves` waves per 64 rows split the
+// columns round-robin.
+struct EllPart {
+  int32_t* col = nullptr;
+  void* val = nullptr;
+  int64_t K = 0;
+  int64_t stride = 0;
+  int waves = 1;
+};
+
+}  // namespace mxs
+
+struct mxs_matrix {
+  int device = 0;
+  mxs::Allocator alloc;
+  int64_t n = 0, ncols = 0, nnz = 0;
+  mxs_format fmt = MXS_CSR;
+  mxs_dtype dt = MXS_F64;
+  mxs::CsrPart csr;
+  mxs::CooPart coo;
+  mxs::EllPart ell;
+  std::vector<void*> owned;
+  int64_t bytes = 0;
+  // host copy of the row pointers (analysis data kept for conversions)
+  std::vector<int32_t> h_rowptr;
+};
+
+namespace mxs {
+
+mxs_status fail(mxs_ctx* ctx, mxs_status s, const char* fmt, ...);
+void* mat_alloc(mxs_matrix* A, size_t bytes);
+bool ws_reserve(mxs_ctx* ctx, size_t bytes);
+bool pinned_reserve(mxs_ctx* ctx, size_t bytes);
+
+inline size_t value_bytes(mxs_dtype dt) {
+  return dt == MXS_F64 ? 8 : dt == MXS_F32 ? 4 : 2;
+}
+
+// launchers shared between translation units (all enqueue on ctx->stream)
+// skip (nullable, device): when *skip != 0 every kernel of the product
+// returns at once (solvers queue iterations past convergence this way)
+mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, const void* x,
+                       const void* beta, void* y, const int32_t* skip);
+int64_t csr_partition(const int32_t* rowptr, int64_t n, int block_nnz,
+                      std::vector<int32_t>& blocks);
+
+}  // namespace mxs
+
+#define MXS_HIP_TRY(ctx, expr)                                                      \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return mxs::fail((ctx), MXS_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+namespace mxs {
+
+// Logical block for hardware block `bid` of `nblk`: XCD k (= bid % 8) gets
+// the k-th contiguous eighth of the logical range.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblk) {
+  const int64_t per = nblk / kNumXcd, rem = nblk % kNumXcd;
+  const int64_t xcd = bid % kNumXcd, idx = bid / kNumXcd;
+  return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Sum over a work-group of BS threads; every thread gets the result.  Wave
+// partials are added in wave order by all lanes (deterministic).
+template <typename T, int BS>
+__device__ __forceinline__ T block_sum(T v, T* lds /* BS/64 entries */) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+  __syncthreads();
+  T s = lds[0];
+#pragma unroll
+  for (int i = 1; i < BS / kWave; ++i) s += lds[i];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double to_acc(double v) { return v; }
+__device__ __forceinline__ float to_acc(float v) { return v; }
+__device__ __forceinline__ float to_acc(_Float16 v) { return (float)v; }
+
+}  // namespace mxs

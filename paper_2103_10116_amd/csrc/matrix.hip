@@ -1,0 +1,660 @@
+// matrix.hip -- CSR ingest (validation on the GPU), format conversions and
+// value casts on the GPU, export and bookkeeping.
+//
+// The O(n) analysis of the row pointers (row-length maximum and histogram,
+// the SpMV work partition, empty-row lists, overflow offsets of the hybrid
+// format) runs on the host from one copy of rowptr, as an analysis phase;
+// every O(nnz) pass -- validation of the column indices, the layout
+// transforms and the value casts -- runs on the GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace mxs {
+
+void* mat_alloc(mxs_matrix* A, size_t bytes) {
+  void* p = A->alloc.alloc(bytes);
+  if (p) {
+    A->owned.push_back(p);
+    A->bytes += (int64_t)bytes;
+  }
+  return p;
+}
+
+// Greedy row-block partition: consecutive rows are packed while the block
+// holds at most `C` entries and `C` rows; a row longer than C is a block of
+// its own.  Returns the block count; blocks[b]..blocks[b+1] are the rows.
+int64_t csr_partition(const int32_t* rp, int64_t n, int C, std::vector<int32_t>& blocks) {
+  blocks.clear();
+  blocks.push_back(0);
+  int64_t cur_nnz = 0, cur_rows = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t L = (int64_t)rp[i + 1] - rp[i];
+    if (L > C) {
+      if (cur_rows) blocks.push_back((int32_t)i);
+      blocks.push_back((int32_t)(i + 1));
+      cur_nnz = cur_rows = 0;
+      continue;
+    }
+    if (cur_rows && (cur_nnz + L > C || cur_rows + 1 > C)) {
+      blocks.push_back((int32_t)i);
+      cur_nnz = cur_rows = 0;
+    }
+    cur_nnz += L;
+    cur_rows += 1;
+  }
+  if (cur_rows) blocks.push_back((int32_t)n);
+  return (int64_t)blocks.size() - 1;
+}
+
+namespace {
+
+constexpr int kErrRowptr = 1, kErrCol = 2, kErrRange = 4, kErrNonfinite = 8;
+
+int grid_for(mxs_ctx* ctx, int64_t work, int bs) {
+  int64_t g = (work + bs - 1) / bs;
+  const int64_t cap = (int64_t)ctx->num_cus * 32;
+  if (g > cap) g = cap;
+  return (int)(g < 1 ? 1 : g);
+}
+
+// ---- validation ------------------------------------------------------------
+__global__ void k_check_rowptr(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
+                               int* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+    const int32_t v = rp[i];
+    bool bad = v < 0 || (int64_t)v > nnz;
+    if (i == 0) bad |= v != 0;
+    if (i == n) bad |= (int64_t)v != nnz;
+    if (i < n) bad |= rp[i + 1] < v;
+    if (bad) atomicOr(err, kErrRowptr);
+  }
+}
+
+// one thread per row; only launched once the row pointers passed
+__global__ void k_check_cols(int64_t n, int64_t ncols, const int32_t* __restrict__ rp,
+                             const int32_t* __restrict__ col, int* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int64_t prev = -1;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int64_t c = col[k];
+      if (c < 0 || c >= ncols || c <= prev) {
+        atomicOr(err, kErrCol);
+        break;
+      }
+      prev = c;
+    }
+  }
+}
+
+// ---- value casts -----------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ V cast_val(double v, int* err);
+
+template <>
+__device__ __forceinline__ double cast_val<double>(double v, int*) {
+  return v;
+}
+
+template <>
+__device__ __forceinline__ float cast_val<float>(double v, int* err) {
+  const float f = (float)v;  // v_cvt_f32_f64: round to nearest even
+  if (isfinite(v) && !isfinite(f)) atomicOr(err, kErrRange);
+  return f;
+}
+
+template <typename V>
+__global__ void k_cast(int64_t count, const double* __restrict__ in, V* __restrict__ out,
+                       int* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride)
+    out[k] = cast_val<V>(in[k], err);
+}
+
+// binary16 code of a double, rounded to nearest even, by integer arithmetic
+// on the IEEE fields (1 sign, 5 exponent bits biased by 15, 10 fraction
+// bits; subnormals are multiples of 2^-24)
+__device__ __forceinline__ uint16_t f64_to_f16_bits(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint16_t sign = (uint16_t)((b >> 48) & 0x8000u);
+  const int ex = (int)((b >> 52) & 0x7ff);
+  const uint64_t frac = b & 0xFFFFFFFFFFFFFull;
+  if (ex == 0x7ff) return (uint16_t)(sign | (frac ? 0x7e00u : 0x7c00u));
+  if (ex == 0) return sign;  // double subnormal or zero: far below half's range
+  int e = ex - 1023;
+  const uint64_t m = frac | (1ull << 52);  // 53-bit significand
+  if (e > 15) return (uint16_t)(sign | 0x7c00u);
+  int shift = (e >= -14) ? 42 : 42 + (-14 - e);  // bits dropped below the half ulp
+  if (shift > 53) return sign;                   // below 2^-25: rounds to 0
+  uint64_t q = m >> shift;
+  const uint64_t rem = m & ((1ull << shift) - 1);
+  const uint64_t half = 1ull << (shift - 1);
+  if (rem > half || (rem == half && (q & 1))) q += 1;
+  if (e >= -14) {
+    if (q == 2048) {
+      q = 1024;
+      e += 1;
+      if (e > 15) return (uint16_t)(sign | 0x7c00u);
+    }
+    return (uint16_t)(sign | (uint16_t)(((e + 15) << 10) | (int)(q - 1024)));
+  }
+  return (uint16_t)(sign | (uint16_t)q);  // subnormal, or 1024 = smallest normal
+}
+
+// one thread per row: power-of-two scale 2^ceil(log2 max|a|) and codes
+__global__ void k_rowscale_f16(int64_t n, const int32_t* __restrict__ rp,
+                               const double* __restrict__ val, uint16_t* __restrict__ h,
+                               float* __restrict__ scale, int* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int32_t a = rp[i], e = rp[i + 1];
+    double m = 0.0;
+    for (int32_t k = a; k < e; ++k) {
+      const double v = val[k];
+      if (!isfinite(v)) atomicOr(err, kErrNonfinite);
+      m = fmax(m, fabs(v));
+    }
+    int E = 0;
+    if (m > 0.0) {
+      const uint64_t bits = (uint64_t)__double_as_longlong(m);
+      const int ex = (int)((bits >> 52) & 0x7ff);
+      const bool pow2 = (bits & 0xFFFFFFFFFFFFFull) == 0;
+      E = ex - 1023 + (pow2 ? 0 : 1);
+      if (ex == 0 || E > 127 || E < -126) {
+        atomicOr(err, kErrRange);
+        E = 0;
+      }
+    }
+    scale[i] = ldexpf(1.0f, E);
+    for (int32_t k = a; k < e; ++k) h[k] = f64_to_f16_bits(ldexp(val[k], -E));
+  }
+}
+
+// ---- layout transforms -----------------------------------------------------
+__global__ void k_coo_rows(int64_t n, const int32_t* __restrict__ rp, int32_t* __restrict__ row) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) row[k] = (int32_t)i;
+}
+
+template <typename V>
+__global__ void k_fill_ell(int64_t n, int64_t K, int64_t ldk, const int32_t* __restrict__ rp,
+                           const int32_t* __restrict__ col, const double* __restrict__ val,
+                           int32_t* __restrict__ ecol, V* __restrict__ eval,
+                           int* __restrict__ err) {
+  const int64_t total = K * ldk;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total; s += stride) {
+    const int64_t j = s / ldk, i = s - j * ldk;
+    int32_t c = -1;
+    V v = (V)0;  // padding: column -1, value +0
+    if (i < n) {
+      const int32_t a = rp[i];
+      if (j < (int64_t)(rp[i + 1] - a)) {
+        c = col[a + j];
+        v = cast_val<V>(val[a + j], err);
+      }
+    }
+    ecol[s] = c;
+    eval[s] = v;
+  }
+}
+
+// hybrid overflow: entries K.. of each row, to offsets off[i]
+template <typename V>
+__global__ void k_fill_hyb_coo(int64_t n, int64_t K, const int32_t* __restrict__ rp,
+                               const int32_t* __restrict__ col, const double* __restrict__ val,
+                               const int64_t* __restrict__ off, int32_t* __restrict__ crow,
+                               int32_t* __restrict__ ccol, V* __restrict__ cval,
+                               int* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int64_t d = off[i];
+    for (int64_t k = (int64_t)rp[i] + K; k < (int64_t)rp[i + 1]; ++k, ++d) {
+      crow[d] = (int32_t)i;
+      ccol[d] = col[k];
+      cval[d] = cast_val<V>(val[k], err);
+    }
+  }
+}
+
+// ---- helpers ---------------------------------------------------------------
+mxs_status read_err(mxs_ctx* ctx, int* d_err, int* out) {
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, d_err, sizeof(int), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *out = *(int*)ctx->pinned;
+  return MXS_OK;
+}
+
+mxs_matrix* new_matrix(mxs_ctx* ctx) {
+  mxs_matrix* A = new (std::nothrow) mxs_matrix();
+  if (A) {
+    A->device = ctx->device;
+    A->alloc = ctx->alloc;
+  }
+  return A;
+}
+
+void free_matrix(mxs_matrix* A) {
+  if (!A) return;
+  (void)hipSetDevice(A->device);
+  for (void* p : A->owned) A->alloc.release(p);
+  delete A;
+}
+
+// the SpMV kernels are instantiated for 256, 512 and 1024 entries per wave
+int clamp_block_nnz(int v) {
+  if (v <= 0) return 512;
+  if (v <= 256) return 256;
+  if (v <= 512) return 512;
+  return 1024;
+}
+
+// Uploads a host array into matrix-owned device memory.
+template <typename T>
+T* upload(mxs_ctx* ctx, mxs_matrix* A, const std::vector<T>& h) {
+  T* d = (T*)mat_alloc(A, h.size() * sizeof(T) + 16);
+  if (d && !h.empty())
+    if (hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream) !=
+        hipSuccess)
+      return nullptr;
+  return d;
+}
+
+mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz) {
+  std::vector<int32_t> blocks;
+  A->csr.block_nnz = block_nnz;
+  A->csr.nblocks = csr_partition(A->h_rowptr.data(), A->n, block_nnz, blocks);
+  A->csr.blocks = upload(ctx, A, blocks);
+  if (!A->csr.blocks) return fail(ctx, MXS_OOM, "cannot upload the row-block partition");
+  // the host vector is freed on return: the copy must finish first
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MXS_OK;
+}
+
+mxs_status setup_coo_part(mxs_ctx* ctx, mxs_matrix* A, mxs::CooPart& P, int64_t nnz,
+                          int block_nnz, const std::vector<int32_t>& empty) {
+  P.nnz = nnz;
+  P.block_nnz = block_nnz;
+  P.nchunks = (nnz + block_nnz - 1) / block_nnz;
+  P.cont_row = (int32_t*)mat_alloc(A, (size_t)(P.nchunks + 1) * sizeof(int32_t));
+  P.cont_val = mat_alloc(A, (size_t)(P.nchunks + 1) * sizeof(double));
+  P.nempty = (int64_t)empty.size();
+  P.empty_rows = upload(ctx, A, empty);
+  if (!P.cont_row || !P.cont_val || !P.empty_rows) return fail(ctx, MXS_OOM, "coo setup");
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MXS_OK;
+}
+
+template <typename V>
+mxs_status cast_into(mxs_ctx* ctx, int64_t count, const double* in, void* out, int* d_err) {
+  if (count == 0) return MXS_OK;
+  if (sizeof(V) == sizeof(double)) {
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(out, in, count * sizeof(double), hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    return MXS_OK;
+  }
+  k_cast<V><<<grid_for(ctx, count, 256), 256, 0, ctx->stream>>>(count, in, (V*)out, d_err);
+  MXS_HIP_TRY(ctx, hipGetLastError());
+  return MXS_OK;
+}
+
+template <typename V>
+mxs_status convert_typed(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, mxs_format fmt,
+                         const mxs_convert_opts* opts, int* d_err) {
+  const int64_t n = S->n, nnz = S->nnz;
+  const int bnnz = clamp_block_nnz(opts ? opts->block_nnz : 0);
+  const int32_t* rp = S->csr.rowptr;
+  const size_t vb = sizeof(V);
+  const std::vector<int32_t>& hrp = S->h_rowptr;
+  int64_t Kmax = 0;
+  for (int64_t i = 0; i < n; ++i) Kmax = std::max<int64_t>(Kmax, hrp[i + 1] - hrp[i]);
+  const int64_t stride = (n + 63) / 64 * 64;
+
+  if (fmt == MXS_CSR) {
+    A->csr.rowptr = (int32_t*)mat_alloc(A, (n + 1) * 4);
+    A->csr.col = (int32_t*)mat_alloc(A, nnz * 4 + 4);
+    A->csr.val = mat_alloc(A, nnz * vb + 8);
+    if (!A->csr.rowptr || !A->csr.col || !A->csr.val) return fail(ctx, MXS_OOM, "csr arrays");
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(A->csr.rowptr, rp, (n + 1) * 4, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    if (nnz)
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(A->csr.col, S->csr.col, nnz * 4, hipMemcpyDeviceToDevice,
+                                      ctx->stream));
+    mxs_status st = cast_into<V>(ctx, nnz, (const double*)S->csr.val, A->csr.val, d_err);
+    if (st) return st;
+    A->h_rowptr = hrp;
+    return build_csr_partition(ctx, A, bnnz);
+  }
+
+  if (fmt == MXS_COO) {
+    A->coo.row = (int32_t*)mat_alloc(A, nnz * 4 + 4);
+    A->coo.col = (int32_t*)mat_alloc(A, nnz * 4 + 4);
+    A->coo.val = mat_alloc(A, nnz * vb + 8);
+    if (!A->coo.row || !A->coo.col || !A->coo.val) return fail(ctx, MXS_OOM, "coo arrays");
+    k_coo_rows<<<grid_for(ctx, n, 256), 256, 0, ctx->stream>>>(n, rp, A->coo.row);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    if (nnz)
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(A->coo.col, S->csr.col, nnz * 4, hipMemcpyDeviceToDevice,
+                                      ctx->stream));
+    mxs_status st = cast_into<V>(ctx, nnz, (const double*)S->csr.val, A->coo.val, d_err);
+    if (st) return st;
+    std::vector<int32_t> empty;
+    for (int64_t i = 0; i < n; ++i)
+      if (hrp[i + 1] == hrp[i]) empty.push_back((int32_t)i);
+    return setup_coo_part(ctx, A, A->coo, nnz, bnnz, empty);
+  }
+
+  // ELL and HYB
+  int64_t K;
+  if (fmt == MXS_ELL) {
+    K = Kmax;
+    if (opts && opts->ell_width > 0) {
+      if (opts->ell_width < Kmax)
+        return fail(ctx, MXS_INVALID_ARG, "ell_width %lld < longest row %lld",
+                    (long long)opts->ell_width, (long long)Kmax);
+      K = opts->ell_width;
+    }
+  } else if (opts && opts->ell_width > 0) {
+    K = std::min<int64_t>(opts->ell_width, Kmax);
+  } else {
+    // byte model: one more column costs stride*(V+4) bytes and saves
+    // #{L_i >= K}*(V+8) COO bytes
+    std::vector<int64_t> ge((size_t)Kmax + 2, 0);
+    for (int64_t i = 0; i < n; ++i) ge[hrp[i + 1] - hrp[i]] += 1;
+    for (int64_t k = Kmax - 1; k >= 0; --k) ge[k] += ge[k + 1];
+    K = 0;
+    for (int64_t k = 1; k <= Kmax; ++k) {
+      if ((double)ge[k] * (double)(vb + 8) > (double)stride * (double)(vb + 4))
+        K = k;
+      else
+        break;
+    }
+  }
+  const double ell_bytes = (double)K * (double)stride * (double)(vb + 4);
+  if (opts && opts->max_ell_bytes > 0 && ell_bytes > (double)opts->max_ell_bytes)
+    return fail(ctx, MXS_UNSUPPORTED, "ELL part needs %.0f bytes > max_ell_bytes", ell_bytes);
+  A->ell.K = K;
+  A->ell.stride = stride;
+  int waves = 1;  // chains of at most ~256 slots per lane-accumulator group
+  while (waves < 16 && (K + waves - 1) / waves > 256) waves <<= 1;
+  A->ell.waves = waves;
+  if (K > 0) {
+    A->ell.col = (int32_t*)mat_alloc(A, (size_t)(K * stride) * 4);
+    A->ell.val = mat_alloc(A, (size_t)(K * stride) * vb);
+    if (!A->ell.col || !A->ell.val) return fail(ctx, MXS_OOM, "ELL arrays (%.0f bytes)", ell_bytes);
+    k_fill_ell<V><<<grid_for(ctx, K * stride, 256), 256, 0, ctx->stream>>>(
+        n, K, stride, rp, S->csr.col, (const double*)S->csr.val, A->ell.col, (V*)A->ell.val,
+        d_err);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+  }
+  if (fmt == MXS_ELL) return MXS_OK;
+
+  std::vector<int64_t> off((size_t)n + 1, 0);
+  std::vector<int32_t> empty;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t L = hrp[i + 1] - hrp[i];
+    off[i + 1] = off[i] + std::max<int64_t>(L - K, 0);
+    if (L == 0) empty.push_back((int32_t)i);
+  }
+  const int64_t cnnz = off[n];
+  A->coo.row = (int32_t*)mat_alloc(A, cnnz * 4 + 4);
+  A->coo.col = (int32_t*)mat_alloc(A, cnnz * 4 + 4);
+  A->coo.val = mat_alloc(A, cnnz * vb + 8);
+  int64_t* d_off = upload(ctx, A, off);
+  if (!A->coo.row || !A->coo.col || !A->coo.val || !d_off) return fail(ctx, MXS_OOM, "hyb coo");
+  if (cnnz) {
+    k_fill_hyb_coo<V><<<grid_for(ctx, n, 256), 256, 0, ctx->stream>>>(
+        n, K, rp, S->csr.col, (const double*)S->csr.val, d_off, A->coo.row, A->coo.col,
+        (V*)A->coo.val, d_err);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+  }
+  return setup_coo_part(ctx, A, A->coo, cnnz, bnnz, empty);
+}
+
+}  // namespace
+}  // namespace mxs
+
+using namespace mxs;
+
+extern "C" {
+
+mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
+                                 const int32_t* rowptr, const int32_t* col, const double* val,
+                                 int flags, mxs_matrix** out) {
+  if (!ctx || !out) return MXS_INVALID_ARG;
+  if (nrows < 0 || ncols < 0 || nnz < 0)
+    return fail(ctx, MXS_INVALID_ARG, "negative size");
+  if (nrows > INT32_MAX - 1 || ncols > INT32_MAX || nnz > INT32_MAX)
+    return fail(ctx, MXS_UNSUPPORTED, "sizes beyond int32 indices");
+  if (!rowptr || (nnz > 0 && (!col || !val)))
+    return fail(ctx, MXS_INVALID_ARG, "NULL array");
+  if (flags != MXS_HOST_PTRS && flags != MXS_DEVICE_PTRS)
+    return fail(ctx, MXS_INVALID_ARG, "unknown flags %d", flags);
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  mxs_matrix* A = new_matrix(ctx);
+  if (!A) return MXS_OOM;
+  A->n = nrows;
+  A->ncols = ncols;
+  A->nnz = nnz;
+  A->fmt = MXS_CSR;
+  A->dt = MXS_F64;
+  mxs_status st = MXS_OK;
+  do {
+    A->csr.rowptr = (int32_t*)mat_alloc(A, (nrows + 1) * 4);
+    A->csr.col = (int32_t*)mat_alloc(A, nnz * 4 + 4);
+    A->csr.val = mat_alloc(A, nnz * 8 + 8);
+    if (!A->csr.rowptr || !A->csr.col || !A->csr.val || !ws_reserve(ctx, 256)) {
+      st = fail(ctx, MXS_OOM, "cannot allocate CSR arrays (%lld entries)", (long long)nnz);
+      break;
+    }
+    const hipMemcpyKind kind =
+        flags == MXS_HOST_PTRS ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (hipMemcpyAsync(A->csr.rowptr, rowptr, (nrows + 1) * 4, kind, ctx->stream) ||
+        (nnz && hipMemcpyAsync(A->csr.col, col, nnz * 4, kind, ctx->stream)) ||
+        (nnz && hipMemcpyAsync(A->csr.val, val, nnz * 8, kind, ctx->stream))) {
+      st = fail(ctx, MXS_HIP, "copying the CSR arrays failed");
+      break;
+    }
+    int* d_err = (int*)ctx->ws.ptr;
+    if (hipMemsetAsync(d_err, 0, sizeof(int), ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "memset failed");
+      break;
+    }
+    k_check_rowptr<<<grid_for(ctx, nrows + 1, 256), 256, 0, ctx->stream>>>(nrows, nnz,
+                                                                           A->csr.rowptr, d_err);
+    int err = 0;
+    if ((st = read_err(ctx, d_err, &err))) break;
+    if (err) {
+      st = fail(ctx, MXS_INVALID_MATRIX,
+                "row pointers must start at 0, never decrease and end at nnz");
+      break;
+    }
+    if (nrows > 0) {
+      k_check_cols<<<grid_for(ctx, nrows, 256), 256, 0, ctx->stream>>>(nrows, ncols,
+                                                                       A->csr.rowptr,
+                                                                       A->csr.col, d_err);
+      if ((st = read_err(ctx, d_err, &err))) break;
+      if (err) {
+        st = fail(ctx, MXS_INVALID_MATRIX,
+                  "column indices must lie in [0, ncols) and ascend strictly in each row");
+        break;
+      }
+    }
+    A->h_rowptr.resize((size_t)nrows + 1);
+    if (hipMemcpyAsync(A->h_rowptr.data(), A->csr.rowptr, (nrows + 1) * 4,
+                       hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "reading back the row pointers failed");
+      break;
+    }
+    st = build_csr_partition(ctx, A, 512);
+  } while (0);
+  if (st) {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_matrix(A);
+    return st;
+  }
+  *out = A;
+  return MXS_OK;
+}
+
+mxs_status mxs_matrix_convert(mxs_ctx* ctx, const mxs_matrix* src, mxs_format fmt,
+                              mxs_dtype dt, const mxs_convert_opts* opts, mxs_matrix** out) {
+  if (!ctx || !src || !out) return MXS_INVALID_ARG;
+  if (src->fmt != MXS_CSR || src->dt != MXS_F64)
+    return fail(ctx, MXS_UNSUPPORTED, "conversion source must be an F64 CSR matrix");
+  if (fmt < MXS_CSR || fmt > MXS_HYB || dt < MXS_F64 || dt > MXS_F16_ROWSCALED)
+    return fail(ctx, MXS_INVALID_ARG, "unknown format or dtype");
+  if (dt == MXS_F16_ROWSCALED && fmt != MXS_CSR)
+    return fail(ctx, MXS_UNSUPPORTED, "F16_ROWSCALED is offered for CSR only");
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (!ws_reserve(ctx, 256)) return fail(ctx, MXS_OOM, "workspace");
+  mxs_matrix* A = new_matrix(ctx);
+  if (!A) return MXS_OOM;
+  A->n = src->n;
+  A->ncols = src->ncols;
+  A->nnz = src->nnz;
+  A->fmt = fmt;
+  A->dt = dt;
+  int* d_err = (int*)ctx->ws.ptr;
+  mxs_status st = MXS_OK;
+  do {
+    if (hipMemsetAsync(d_err, 0, sizeof(int), ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "memset failed");
+      break;
+    }
+    if (dt == MXS_F64) {
+      st = convert_typed<double>(ctx, src, A, fmt, opts, d_err);
+    } else if (dt == MXS_F32) {
+      st = convert_typed<float>(ctx, src, A, fmt, opts, d_err);
+    } else {
+      const int64_t n = src->n, nnz = src->nnz;
+      A->csr.rowptr = (int32_t*)mat_alloc(A, (n + 1) * 4);
+      A->csr.col = (int32_t*)mat_alloc(A, nnz * 4 + 4);
+      A->csr.val = mat_alloc(A, nnz * 2 + 8);
+      A->csr.scale = (float*)mat_alloc(A, n * 4 + 4);
+      if (!A->csr.rowptr || !A->csr.col || !A->csr.val || !A->csr.scale) {
+        st = fail(ctx, MXS_OOM, "f16 arrays");
+        break;
+      }
+      if (hipMemcpyAsync(A->csr.rowptr, src->csr.rowptr, (n + 1) * 4, hipMemcpyDeviceToDevice,
+                         ctx->stream) ||
+          (nnz && hipMemcpyAsync(A->csr.col, src->csr.col, nnz * 4, hipMemcpyDeviceToDevice,
+                                 ctx->stream))) {
+        st = fail(ctx, MXS_HIP, "copy failed");
+        break;
+      }
+      if (n > 0)
+        k_rowscale_f16<<<grid_for(ctx, n, 256), 256, 0, ctx->stream>>>(
+            n, src->csr.rowptr, (const double*)src->csr.val, (uint16_t*)A->csr.val, A->csr.scale,
+            d_err);
+      A->h_rowptr = src->h_rowptr;
+      st = build_csr_partition(ctx, A, clamp_block_nnz(opts ? opts->block_nnz : 0));
+    }
+    if (st) break;
+    int err = 0;
+    if ((st = read_err(ctx, d_err, &err))) break;
+    if (err & kErrNonfinite) {
+      st = fail(ctx, MXS_UNSUPPORTED, "non-finite value cannot be stored with a row scale");
+      break;
+    }
+    if (err & kErrRange) {
+      st = fail(ctx, MXS_UNSUPPORTED, "value outside the range of the target type");
+      break;
+    }
+  } while (0);
+  if (st) {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_matrix(A);
+    return st;
+  }
+  *out = A;
+  return MXS_OK;
+}
+
+mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
+  if (!A || !out) return MXS_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->nrows = A->n;
+  out->ncols = A->ncols;
+  out->nnz = A->nnz;
+  out->format = A->fmt;
+  out->dtype = A->dt;
+  out->ell_width = A->ell.K;
+  out->ell_stride = A->ell.stride;
+  out->coo_nnz = (A->fmt == MXS_COO || A->fmt == MXS_HYB) ? A->coo.nnz : 0;
+  out->blocks = A->fmt == MXS_CSR ? A->csr.nblocks
+                : (A->fmt == MXS_COO || A->fmt == MXS_HYB) ? A->coo.nchunks
+                                                           : (A->ell.stride / 64);
+  out->block_nnz = A->fmt == MXS_CSR ? A->csr.block_nnz : A->coo.block_nnz;
+  out->bytes = A->bytes;
+  return MXS_OK;
+}
+
+mxs_status mxs_matrix_export(mxs_ctx* ctx, const mxs_matrix* A, mxs_array which, void* dst,
+                             size_t bytes) {
+  if (!ctx || !A || !dst) return MXS_INVALID_ARG;
+  const size_t vb = value_bytes(A->dt);
+  const void* src = nullptr;
+  size_t size = 0;
+  const bool csr = A->fmt == MXS_CSR, coo = A->fmt == MXS_COO, hyb = A->fmt == MXS_HYB,
+             ell = A->fmt == MXS_ELL;
+  switch (which) {
+    case MXS_ARR_ROWPTR:
+      if (csr) src = A->csr.rowptr, size = (A->n + 1) * 4;
+      break;
+    case MXS_ARR_COL:
+      if (csr) src = A->csr.col, size = A->nnz * 4;
+      if (coo) src = A->coo.col, size = A->nnz * 4;
+      break;
+    case MXS_ARR_VAL:
+      if (csr) src = A->csr.val, size = A->nnz * vb;
+      if (coo) src = A->coo.val, size = A->nnz * vb;
+      break;
+    case MXS_ARR_ROW:
+      if (coo) src = A->coo.row, size = A->nnz * 4;
+      break;
+    case MXS_ARR_ELL_COL:
+      if (ell || hyb) src = A->ell.col, size = A->ell.K * A->ell.stride * 4;
+      break;
+    case MXS_ARR_ELL_VAL:
+      if (ell || hyb) src = A->ell.val, size = A->ell.K * A->ell.stride * vb;
+      break;
+    case MXS_ARR_COO_ROW:
+      if (hyb) src = A->coo.row, size = A->coo.nnz * 4;
+      break;
+    case MXS_ARR_COO_COL:
+      if (hyb) src = A->coo.col, size = A->coo.nnz * 4;
+      break;
+    case MXS_ARR_COO_VAL:
+      if (hyb) src = A->coo.val, size = A->coo.nnz * vb;
+      break;
+    case MXS_ARR_SCALE:
+      if (csr && A->dt == MXS_F16_ROWSCALED) src = A->csr.scale, size = A->n * 4;
+      break;
+  }
+  if (!src && size == 0 && which != MXS_ARR_ELL_COL && which != MXS_ARR_ELL_VAL &&
+      which != MXS_ARR_COO_ROW && which != MXS_ARR_COO_COL && which != MXS_ARR_COO_VAL)
+    return fail(ctx, MXS_INVALID_ARG, "matrix has no such array");
+  if (bytes != size)
+    return fail(ctx, MXS_INVALID_ARG, "export buffer is %zu bytes, array is %zu", bytes, size);
+  if (size) {
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(dst, src, size, hipMemcpyDeviceToHost, ctx->stream));
+    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return MXS_OK;
+}
+
+mxs_status mxs_matrix_destroy(mxs_matrix* A) {
+  free_matrix(A);
+  return MXS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1020 @@
+// solvers.hip -- fused BLAS-1 reduction kernels and the Krylov solver
+// drivers (CG, BiCGSTAB, restarted GMRES) plus mixed-precision iterative
+// refinement, all on the GPU.
+//
+// The paper names CG, BiCGSTAB and GMRES as the solvers built on SpMV (its
+// section "Central Sparse Linear Algebra Functionality"; textbook forms in
+// Saad 2003 and Saad & Schultz 1986) and runs them in its "Krylov Solver
+// Performance Analysis" subsection.  Design for one MI355X:
+//  * every scalar of the recurrences (rho, alpha, beta, omega, the Hessenberg
+//    column, Givens rotations) lives in device memory and is produced by the
+//    last block of the reduction kernel that computes it, so an iteration
+//    never waits for the host;
+//  * a device status word stops all queued work once the solver converged
+//    or broke down: the host enqueues `check_every` iterations, then reads
+//    the status once (pinned memory);
+//  * reductions accumulate in FP64 (also for the FP32 inner solver of
+//    iterative refinement) with a fixed order: per-thread grid-stride sums,
+//    wave butterflies, wave partials in order, block partials in order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace mxs {
+namespace {
+
+constexpr int RB = 256;      // threads per reduction block
+constexpr int MAXG = 1024;   // reduction grid cap
+constexpr int MAXM = 32;     // largest GMRES restart length
+
+enum : int32_t {
+  RUN = 0,
+  ST_CONVERGED = 1,
+  ST_BREAKDOWN = 2,
+  ST_NONFINITE = 3,
+  ST_HALF = 4,   // BiCGSTAB: ||s|| met the tolerance, x += alpha p pending
+  ST_MAXIT = 5
+};
+
+struct KState {
+  double rho, rho1, alpha, beta, omega, thr, res2, dot[2];
+  int64_t iters, max_iters;
+  int32_t done;     // one of the ST_* values; every kernel returns at once if set
+  int32_t cycle;    // GMRES: 1 once the current cycle must end
+  int32_t k;        // GMRES: Arnoldi steps taken in the current cycle
+  int32_t m;        // GMRES restart length
+  uint32_t ticket[4];
+  double est;       // GMRES residual estimate |g_{k}|
+  double H[(MAXM + 1) * MAXM];  // column-major, leading dimension MAXM+1
+  double cs[MAXM], sn[MAXM], g[MAXM + 1], y[MAXM], h2[MAXM + 1];
+};
+
+int red_grid(int64_t n) {
+  int64_t g = (n + RB * 4 - 1) / (RB * 4);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, MAXG));
+}
+
+// Sums NV per-thread values over the grid.  Every block writes its NV
+// partials; the last block to arrive adds all partials in block order and
+// returns true with the totals in out[] (all its threads).
+template <int NV>
+__device__ bool grid_reduce(const double (&acc)[NV], double* __restrict__ partials,
+                            uint32_t* ticket, double (&out)[NV]) {
+  __shared__ double lds[RB / 64];
+  __shared__ double res[NV];
+  __shared__ int is_last;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double s = block_sum<double, RB>(acc[v], lds);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * NV + v] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += RB)
+      s += __builtin_nontemporal_load(&partials[(int64_t)b * NV + v]);
+    s = block_sum<double, RB>(s, lds);
+    if (threadIdx.x == 0) res[v] = s;
+  }
+  if (threadIdx.x == 0) *ticket = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = res[v];
+  return true;
+}
+
+#define GRID_STRIDE(i, n)                                                        \
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < (n); \
+       i += (int64_t)gridDim.x * RB)
+
+// ---------------------------------------------------------------------------
+// generic kernels
+// ---------------------------------------------------------------------------
+// dot[0] = a.b, dot[1] = c.d (c may be NULL)
+template <typename T>
+__global__ __launch_bounds__(RB) void k_dots(int64_t n, const T* __restrict__ a,
+                                             const T* __restrict__ b, const T* __restrict__ c,
+                                             const T* __restrict__ d, double* partials,
+                                             KState* st) {
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    acc[0] += (double)a[i] * (double)b[i];
+    if (c) acc[1] += (double)c[i] * (double)d[i];
+  }
+  double out[2];
+  if (grid_reduce<2>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+    st->dot[0] = out[0];
+    st->dot[1] = out[1];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_copy(int64_t n, const T* __restrict__ a,
+                                             T* __restrict__ b) {
+  GRID_STRIDE(i, n) b[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------
+// CG (Hestenes-Stiefel)
+// ---------------------------------------------------------------------------
+// alpha = rho / (p.q)
+template <typename T>
+__global__ __launch_bounds__(RB) void k_cg_alpha(int64_t n, const T* __restrict__ p,
+                                                 const T* __restrict__ q, double* partials,
+                                                 KState* st) {
+  if (st->done) return;
+  double acc[1] = {0.0};
+  GRID_STRIDE(i, n) acc[0] += (double)p[i] * (double)q[i];
+  double out[1];
+  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+    const double pq = out[0];
+    if (!isfinite(pq))
+      st->done = ST_NONFINITE;
+    else if (pq <= 0.0)
+      st->done = ST_BREAKDOWN;
+    else
+      st->alpha = st->rho / pq;
+  }
+}
+
+// x += alpha p; r -= alpha q; rho' = r.r; beta = rho'/rho; stopping test
+template <typename T>
+__global__ __launch_bounds__(RB) void k_cg_update(int64_t n, T* __restrict__ x,
+                                                  const T* __restrict__ p, T* __restrict__ r,
+                                                  const T* __restrict__ q, double* partials,
+                                                  KState* st) {
+  if (st->done) return;
+  const T a = (T)st->alpha;
+  double acc[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    acc[0] += (double)ri * (double)ri;
+  }
+  double out[1];
+  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+    const double rn = out[0];
+    st->iters += 1;
+    st->res2 = rn;
+    if (!isfinite(rn)) {
+      st->done = ST_NONFINITE;
+    } else {
+      st->beta = rn / st->rho;
+      st->rho = rn;
+      if (sqrt(rn) <= st->thr)
+        st->done = ST_CONVERGED;
+      else if (st->iters >= st->max_iters)
+        st->done = ST_MAXIT;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_cg_direction(int64_t n, const T* __restrict__ r,
+                                                     T* __restrict__ p, const KState* st) {
+  if (st->done) return;
+  const T b = (T)st->beta;
+  GRID_STRIDE(i, n) p[i] = r[i] + b * p[i];
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB (r_hat = r0)
+// ---------------------------------------------------------------------------
+// p = r + beta (p - omega v)
+__global__ __launch_bounds__(RB) void k_bi_p(int64_t n, const double* __restrict__ r,
+                                             double* __restrict__ p,
+                                             const double* __restrict__ v, const KState* st) {
+  if (st->done) return;
+  const double b = st->beta, w = st->omega;
+  GRID_STRIDE(i, n) p[i] = r[i] + b * (p[i] - w * v[i]);
+}
+
+// alpha = rho1 / (r_hat . v)
+__global__ __launch_bounds__(RB) void k_bi_alpha(int64_t n, const double* __restrict__ rh,
+                                                 const double* __restrict__ v,
+                                                 double* partials, KState* st) {
+  if (st->done) return;
+  double acc[1] = {0.0};
+  GRID_STRIDE(i, n) acc[0] += rh[i] * v[i];
+  double out[1];
+  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+    if (!isfinite(out[0]))
+      st->done = ST_NONFINITE;
+    else if (out[0] == 0.0)
+      st->done = ST_BREAKDOWN;
+    else
+      st->alpha = st->rho1 / out[0];
+  }
+}
+
+// s = r - alpha v; ||s|| test (a met tolerance leaves x += alpha p pending)
+__global__ __launch_bounds__(RB) void k_bi_s(int64_t n, const double* __restrict__ r,
+                                             const double* __restrict__ v,
+                                             double* __restrict__ s, double* partials,
+                                             KState* st) {
+  if (st->done) return;
+  const double a = st->alpha;
+  double acc[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    const double si = r[i] - a * v[i];
+    s[i] = si;
+    acc[0] += si * si;
+  }
+  double out[1];
+  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+    st->iters += 1;
+    st->res2 = out[0];
+    if (!isfinite(out[0]))
+      st->done = ST_NONFINITE;
+    else if (sqrt(out[0]) <= st->thr)
+      st->done = ST_HALF;
+  }
+}
+
+// the half step x += alpha p, launched once by the host after it read
+// ST_HALF (every queued kernel of later iterations returned early, so p and
+// alpha are those of the converging iteration)
+__global__ __launch_bounds__(RB) void k_bi_half(int64_t n, double* __restrict__ x,
+                                                const double* __restrict__ p,
+                                                const KState* st) {
+  const double a = st->alpha;
+  GRID_STRIDE(i, n) x[i] += a * p[i];
+}
+
+// omega = (t.s)/(t.t)
+__global__ __launch_bounds__(RB) void k_bi_omega(int64_t n, const double* __restrict__ t,
+                                                 const double* __restrict__ s,
+                                                 double* partials, KState* st) {
+  if (st->done) return;
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    acc[0] += t[i] * s[i];
+    acc[1] += t[i] * t[i];
+  }
+  double out[2];
+  if (grid_reduce<2>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+    if (!isfinite(out[0]) || !isfinite(out[1]))
+      st->done = ST_NONFINITE;
+    else if (out[1] == 0.0)
+      st->done = ST_BREAKDOWN;
+    else
+      st->omega = out[0] / out[1];
+  }
+}
+
+// x += alpha p + omega s; r = s - omega t; ||r|| test; rho1' = r_hat.r and
+// beta for the next iteration
+__global__ __launch_bounds__(RB) void k_bi_update(int64_t n, double* __restrict__ x,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ s,
+                                                  const double* __restrict__ t,
+                                                  double* __restrict__ r,
+                                                  const double* __restrict__ rh,
+                                                  double* partials, KState* st) {
+  if (st->done) return;
+  const double a = st->alpha, w = st->omega;
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    x[i] = x[i] + a * p[i] + w * s[i];
+    const double ri = s[i] - w * t[i];
+    r[i] = ri;
+    acc[0] += ri * ri;
+    acc[1] += rh[i] * ri;
+  }
+  double out[2];
+  if (grid_reduce<2>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+    st->res2 = out[0];
+    if (!isfinite(out[0]) || !isfinite(out[1])) {
+      st->done = ST_NONFINITE;
+    } else if (sqrt(out[0]) <= st->thr) {
+      st->done = ST_CONVERGED;
+    } else if (st->iters >= st->max_iters) {
+      st->done = ST_MAXIT;
+    } else if (out[1] == 0.0 || w == 0.0) {
+      st->done = ST_BREAKDOWN;
+    } else {
+      st->beta = (out[1] / st->rho1) * (a / w);
+      st->rho1 = out[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m): classical Gram-Schmidt with one reorthogonalisation pass
+// ---------------------------------------------------------------------------
+// h(0..j) = V(:,0..j)^T w  (first pass)
+__global__ __launch_bounds__(RB) void k_gm_dots(int64_t n, int64_t ldv, int j,
+                                                const double* __restrict__ V,
+                                                const double* __restrict__ w,
+                                                double* partials, KState* st) {
+  if (st->done || st->cycle) return;
+  double acc[MAXM];
+#pragma unroll
+  for (int i = 0; i < MAXM; ++i) acc[i] = 0.0;
+  GRID_STRIDE(r, n) {
+    const double wr = w[r];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i)
+      if (i <= j) acc[i] += V[i * ldv + r] * wr;
+  }
+  double out[MAXM];
+  if (grid_reduce<MAXM>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0)
+    for (int i = 0; i <= j; ++i) st->H[j * (MAXM + 1) + i] = out[i];
+}
+
+// w -= V h (h from the first pass); then h2 = V^T w on the updated rows
+__global__ __launch_bounds__(RB) void k_gm_orth(int64_t n, int64_t ldv, int j,
+                                                const double* __restrict__ V,
+                                                double* __restrict__ w, double* partials,
+                                                KState* st) {
+  if (st->done || st->cycle) return;
+  __shared__ double h[MAXM];
+  if (threadIdx.x < MAXM) h[threadIdx.x] = threadIdx.x <= j ? st->H[j * (MAXM + 1) + threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[MAXM];
+#pragma unroll
+  for (int i = 0; i < MAXM; ++i) acc[i] = 0.0;
+  GRID_STRIDE(r, n) {
+    double vr[MAXM];
+    double wr = w[r];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      vr[i] = i <= j ? V[i * ldv + r] : 0.0;
+      wr -= h[i] * vr[i];
+    }
+    w[r] = wr;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) acc[i] += vr[i] * wr;
+  }
+  double out[MAXM];
+  if (grid_reduce<MAXM>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0)
+    for (int i = 0; i <= j; ++i) {
+      st->h2[i] = out[i];
+      st->H[j * (MAXM + 1) + i] += out[i];
+    }
+}
+
+// w -= V h2; h_{j+1,j} = ||w||; Givens rotations; residual estimate
+__global__ __launch_bounds__(RB) void k_gm_norm(int64_t n, int64_t ldv, int j,
+                                                const double* __restrict__ V,
+                                                double* __restrict__ w, double* partials,
+                                                KState* st) {
+  if (st->done || st->cycle) return;
+  __shared__ double h[MAXM];
+  if (threadIdx.x < MAXM) h[threadIdx.x] = threadIdx.x <= j ? st->h2[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[1] = {0.0};
+  GRID_STRIDE(r, n) {
+    double wr = w[r];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i)
+      if (i <= j) wr -= h[i] * V[i * ldv + r];
+    w[r] = wr;
+    acc[0] += wr * wr;
+  }
+  double out[1];
+  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+    const int L = MAXM + 1;
+    double* Hj = st->H + j * L;
+    const double hn = sqrt(out[0]);
+    st->iters += 1;
+    if (!isfinite(hn)) {
+      st->done = ST_NONFINITE;
+      return;
+    }
+    Hj[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = Hj[i], c = Hj[i + 1];
+      Hj[i] = st->cs[i] * a + st->sn[i] * c;
+      Hj[i + 1] = -st->sn[i] * a + st->cs[i] * c;
+    }
+    const double a = Hj[j], c = Hj[j + 1];
+    const double d = sqrt(a * a + c * c);
+    if (d == 0.0) {
+      st->done = ST_BREAKDOWN;
+      return;
+    }
+    st->cs[j] = a / d;
+    st->sn[j] = c / d;
+    Hj[j] = d;
+    Hj[j + 1] = 0.0;
+    st->g[j + 1] = -st->sn[j] * st->g[j];
+    st->g[j] = st->cs[j] * st->g[j];
+    st->k = j + 1;
+    st->est = fabs(st->g[j + 1]);
+    st->res2 = hn;  // h_{j+1,j} for the scaling kernel
+    if (st->est <= st->thr || hn == 0.0 || st->iters >= st->max_iters || j + 1 >= st->m)
+      st->cycle = 1;
+  }
+}
+
+// v_{j+1} = w / h_{j+1,j}
+__global__ __launch_bounds__(RB) void k_gm_scale(int64_t n, const double* __restrict__ w,
+                                                 double* __restrict__ vn, const KState* st) {
+  if (st->done || st->cycle) return;
+  const double inv = 1.0 / st->res2;
+  GRID_STRIDE(r, n) vn[r] = w[r] * inv;
+}
+
+// back substitution R y = g on one thread (k <= 32)
+__global__ void k_gm_backsolve(KState* st) {
+  if (st->done) return;
+  const int L = MAXM + 1, k = st->k;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = st->g[i];
+    for (int l = i + 1; l < k; ++l) s -= st->H[l * L + i] * st->y[l];
+    st->y[i] = s / st->H[i * L + i];
+  }
+}
+
+// x += V(:, 0..k-1) y
+__global__ __launch_bounds__(RB) void k_gm_xupdate(int64_t n, int64_t ldv,
+                                                   const double* __restrict__ V,
+                                                   double* __restrict__ x, const KState* st) {
+  if (st->done) return;
+  __shared__ double y[MAXM];
+  const int k = st->k;
+  if (threadIdx.x < MAXM) y[threadIdx.x] = threadIdx.x < k ? st->y[threadIdx.x] : 0.0;
+  __syncthreads();
+  GRID_STRIDE(r, n) {
+    double xr = x[r];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i)
+      if (i < k) xr += y[i] * V[i * ldv + r];
+    x[r] = xr;
+  }
+}
+
+// v_0 = r / beta; g = beta e_1; new cycle (beta = sqrt(dot[0]))
+__global__ __launch_bounds__(RB) void k_gm_start(int64_t n, const double* __restrict__ r,
+                                                 double* __restrict__ v0, KState* st) {
+  const double beta = sqrt(st->dot[0]);
+  const double inv = 1.0 / beta;
+  GRID_STRIDE(i, n) v0[i] = r[i] * inv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int i = 0; i <= MAXM; ++i) st->g[i] = 0.0;
+    st->g[0] = beta;
+    st->k = 0;
+    st->cycle = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// iterative refinement helpers
+// ---------------------------------------------------------------------------
+// f = float(r / sigma)
+__global__ __launch_bounds__(RB) void k_ir_scale(int64_t n, const double* __restrict__ r,
+                                                 double sigma, float* __restrict__ f) {
+  GRID_STRIDE(i, n) f[i] = (float)(r[i] / sigma);
+}
+
+// x += sigma * double(d)
+__global__ __launch_bounds__(RB) void k_ir_update(int64_t n, double* __restrict__ x,
+                                                  const float* __restrict__ d, double sigma) {
+  GRID_STRIDE(i, n) x[i] += sigma * (double)d[i];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct Work {
+  KState* st;        // device
+  KState* hst;       // pinned mirror
+  double* partials;  // MAXG * MAXM doubles
+  char* vec;         // vectors
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+mxs_status get_work(mxs_ctx* ctx, size_t vec_bytes, Work* w) {
+  const size_t st_bytes = align_up(sizeof(KState), 256);
+  const size_t part_bytes = (size_t)MAXG * MAXM * sizeof(double);
+  if (!ws_reserve(ctx, st_bytes + part_bytes + vec_bytes + 256))
+    return fail(ctx, MXS_OOM, "solver workspace of %zu bytes", st_bytes + part_bytes + vec_bytes);
+  if (!pinned_reserve(ctx, st_bytes)) return fail(ctx, MXS_OOM, "pinned state mirror");
+  char* base = (char*)ctx->ws.ptr;
+  w->st = (KState*)base;
+  w->partials = (double*)(base + st_bytes);
+  w->vec = base + st_bytes + part_bytes;
+  w->hst = (KState*)ctx->pinned;
+  // zero the device state: its reduction tickets must start at 0
+  MXS_HIP_TRY(ctx, hipMemsetAsync(w->st, 0, sizeof(KState), ctx->stream));
+  return MXS_OK;
+}
+
+mxs_status push_state(mxs_ctx* ctx, Work& w) {
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(w.st, w.hst, sizeof(KState), hipMemcpyHostToDevice,
+                                  ctx->stream));
+  // the pinned buffer is reused by pull_state: the upload must finish first
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MXS_OK;
+}
+
+mxs_status pull_state(mxs_ctx* ctx, Work& w) {
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(w.hst, w.st, sizeof(KState), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MXS_OK;
+}
+
+// dot products of device vectors into the host mirror (synchronising)
+template <typename T>
+mxs_status dots(mxs_ctx* ctx, Work& w, int64_t n, const T* a, const T* b, const T* c,
+                const T* d, double* out0, double* out1) {
+  k_dots<T><<<red_grid(n), RB, 0, ctx->stream>>>(n, a, b, c, d, w.partials, w.st);
+  MXS_HIP_TRY(ctx, hipGetLastError());
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(w.hst->dot, w.st->dot, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, ctx->stream));
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *out0 = w.hst->dot[0];
+  if (out1) *out1 = w.hst->dot[1];
+  return MXS_OK;
+}
+
+// r = b - A x in FP64
+mxs_status residual(mxs_ctx* ctx, const mxs_matrix* A, const double* b, const double* x,
+                    double* r) {
+  const int64_t n = A->n;
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+  const double m1 = -1.0, one = 1.0;
+  return launch_spmv(ctx, A, &m1, x, &one, r, nullptr);
+}
+
+mxs_status map_done(int32_t done) {
+  switch (done) {
+    case ST_BREAKDOWN: return MXS_BREAKDOWN;
+    case ST_NONFINITE: return MXS_NONFINITE;
+    case ST_MAXIT: return MXS_NOT_CONVERGED;
+    default: return MXS_OK;
+  }
+}
+
+struct Stop {
+  int64_t max_iters;
+  double rel_tol, abs_tol;
+  int baseline, check_every, max_repl;
+};
+
+Stop read_stop(const mxs_stop* s, int64_t default_max) {
+  Stop o{default_max, 1e-10, 0.0, MXS_BASELINE_RHS, 16, 3};
+  if (s) {
+    if (s->max_iters > 0) o.max_iters = s->max_iters;
+    o.rel_tol = s->rel_tol;
+    o.abs_tol = s->abs_tol;
+    o.baseline = s->baseline;
+    if (s->check_every > 0) o.check_every = s->check_every;
+    if (s->max_replacements >= 0) o.max_repl = s->max_replacements;
+  }
+  return o;
+}
+
+// Runs CG iterations from the state already on the device until the
+// device status is set.  Vectors of type T; the operator is A.
+template <typename T>
+mxs_status cg_loop(mxs_ctx* ctx, const mxs_matrix* A, Work& w, T* x, T* r, T* p, T* q,
+                   int check_every) {
+  const int64_t n = A->n;
+  const int g = red_grid(n);
+  const T one = 1, zero = 0;
+  int64_t before = -1;
+  for (;;) {
+    for (int it = 0; it < check_every; ++it) {
+      mxs_status s = launch_spmv(ctx, A, &one, p, &zero, q, &w.st->done);
+      if (s) return s;
+      k_cg_alpha<T><<<g, RB, 0, ctx->stream>>>(n, p, q, w.partials, w.st);
+      k_cg_update<T><<<g, RB, 0, ctx->stream>>>(n, x, p, r, q, w.partials, w.st);
+      k_cg_direction<T><<<g, RB, 0, ctx->stream>>>(n, r, p, w.st);
+    }
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    mxs_status s = pull_state(ctx, w);
+    if (s) return s;
+    if (w.hst->done) return MXS_OK;
+    if (w.hst->iters == before)
+      return fail(ctx, MXS_HIP, "CG made no progress (device state not updated)");
+    before = w.hst->iters;
+  }
+}
+
+void fill_info(mxs_solve_info* info, const KState& h, double base, double relres_true,
+               int64_t repl, int64_t restarts, mxs_status st) {
+  if (!info) return;
+  info->iters = h.iters;
+  info->relres_recurrence = sqrt(h.res2 > 0 ? h.res2 : 0.0) / base;
+  info->relres_true = relres_true;
+  info->replacements = repl;
+  info->restarts = restarts;
+  info->status = st;
+}
+
+mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
+                    const Stop& stop, mxs_solve_info* info) {
+  const int64_t n = A->n;
+  const size_t ld = align_up((size_t)n, 64);
+  Work w;
+  mxs_status s = get_work(ctx, 3 * ld * sizeof(double), &w);
+  if (s) return s;
+  double* r = (double*)w.vec;
+  double* p = r + ld;
+  double* q = p + ld;
+  double nb2, nr2;
+  if ((s = residual(ctx, A, b, x, r))) return s;
+  if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
+  const double nb = sqrt(nb2), nr0 = sqrt(nr2);
+  if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
+  if (nb == 0.0) {
+    MXS_HIP_TRY(ctx, hipMemsetAsync(x, 0, n * sizeof(double), ctx->stream));
+    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    KState z{};
+    fill_info(info, z, 1.0, 0.0, 0, 0, MXS_OK);
+    return MXS_OK;
+  }
+  if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
+  const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
+  const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
+  KState& h = *w.hst;
+  std::memset(&h, 0, sizeof(KState));
+  h.rho = nr2;
+  h.res2 = nr2;
+  h.thr = thr;
+  h.max_iters = stop.max_iters;
+  h.done = nr0 <= thr ? ST_CONVERGED : RUN;
+  if ((s = push_state(ctx, w))) return s;
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(p, r, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+  int64_t repl = 0;
+  double relres_true = nr0 / base;
+  for (;;) {
+    if (h.done == RUN) {
+      if ((s = cg_loop<double>(ctx, A, w, x, r, p, q, stop.check_every))) return s;
+    }
+    if (h.done == ST_BREAKDOWN || h.done == ST_NONFINITE) {
+      s = map_done(h.done);
+      fill_info(info, h, base, relres_true, repl, 0, s);
+      return fail(ctx, s, h.done == ST_BREAKDOWN ? "CG breakdown: p.Ap <= 0 (matrix not SPD)"
+                                                 : "non-finite value in CG");
+    }
+    // true residual check (also after max_iters)
+    double rt2;
+    if ((s = residual(ctx, A, b, x, r))) return s;
+    if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr,
+                          &rt2, nullptr)))
+      return s;
+    relres_true = sqrt(rt2) / base;
+    const int32_t why = h.done;
+    if (why == ST_CONVERGED && sqrt(rt2) <= thr) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_OK);
+      return MXS_OK;
+    }
+    if (why == ST_MAXIT || repl >= stop.max_repl || h.iters >= stop.max_iters) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_NOT_CONVERGED);
+      return fail(ctx, MXS_NOT_CONVERGED, "CG stopped after %lld iterations, relres %.3e",
+                  (long long)h.iters, relres_true);
+    }
+    // residual replacement: r = b - A x (already in r), restart p = r
+    repl++;
+    h.rho = rt2;
+    h.res2 = rt2;
+    h.done = RUN;
+    if ((s = push_state(ctx, w))) return s;
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(p, r, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+  }
+}
+
+mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
+                          const Stop& stop, mxs_solve_info* info) {
+  const int64_t n = A->n;
+  const size_t ld = align_up((size_t)n, 64);
+  Work w;
+  mxs_status s = get_work(ctx, 6 * ld * sizeof(double), &w);
+  if (s) return s;
+  double* r = (double*)w.vec;
+  double* rh = r + ld;
+  double* p = rh + ld;
+  double* v = p + ld;
+  double* sv = v + ld;
+  double* t = sv + ld;
+  double nb2, nr2;
+  if ((s = residual(ctx, A, b, x, r))) return s;
+  if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
+  const double nb = sqrt(nb2), nr0 = sqrt(nr2);
+  if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
+  if (nb == 0.0) {
+    MXS_HIP_TRY(ctx, hipMemsetAsync(x, 0, n * sizeof(double), ctx->stream));
+    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    KState z{};
+    fill_info(info, z, 1.0, 0.0, 0, 0, MXS_OK);
+    return MXS_OK;
+  }
+  if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
+  const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
+  const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
+  const int g = red_grid(n);
+  const double one = 1.0, zero = 0.0;
+  KState& h = *w.hst;
+  std::memset(&h, 0, sizeof(KState));
+  int64_t repl = 0;
+  double relres_true = nr0 / base;
+  bool restart = true;
+  int32_t done = nr0 <= thr ? ST_CONVERGED : RUN;
+  int64_t iters = 0;
+  double rr = nr2;
+  for (;;) {
+    if (done == RUN && restart) {
+      // r_hat = r, p = v = 0, rho = alpha = omega = 1; first beta = rho1
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(rh, r, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                      ctx->stream));
+      MXS_HIP_TRY(ctx, hipMemsetAsync(p, 0, n * sizeof(double), ctx->stream));
+      MXS_HIP_TRY(ctx, hipMemsetAsync(v, 0, n * sizeof(double), ctx->stream));
+      std::memset(&h, 0, sizeof(KState));
+      h.rho1 = rr;
+      h.alpha = 1.0;
+      h.omega = 1.0;
+      h.beta = rr;  // (rho1 / 1) * (1 / 1)
+      h.res2 = rr;
+      h.thr = thr;
+      h.iters = iters;
+      h.max_iters = stop.max_iters;
+      h.done = rr == 0.0 ? ST_BREAKDOWN : RUN;
+      if ((s = push_state(ctx, w))) return s;
+      restart = false;
+    }
+    while (done == RUN) {
+      for (int it = 0; it < stop.check_every; ++it) {
+        k_bi_p<<<g, RB, 0, ctx->stream>>>(n, r, p, v, w.st);
+        if ((s = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return s;
+        k_bi_alpha<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.partials, w.st);
+        k_bi_s<<<g, RB, 0, ctx->stream>>>(n, r, v, sv, w.partials, w.st);
+        if ((s = launch_spmv(ctx, A, &one, sv, &zero, t, &w.st->done))) return s;
+        k_bi_omega<<<g, RB, 0, ctx->stream>>>(n, t, sv, w.partials, w.st);
+        k_bi_update<<<g, RB, 0, ctx->stream>>>(n, x, p, sv, t, r, rh, w.partials, w.st);
+      }
+      MXS_HIP_TRY(ctx, hipGetLastError());
+      const int64_t before = iters;
+      if ((s = pull_state(ctx, w))) return s;
+      done = h.done;
+      iters = h.iters;
+      if (done == RUN && iters == before)
+        return fail(ctx, MXS_HIP, "BiCGSTAB made no progress (device state not updated)");
+      if (done == ST_HALF) {
+        k_bi_half<<<g, RB, 0, ctx->stream>>>(n, x, p, w.st);
+        MXS_HIP_TRY(ctx, hipGetLastError());
+        done = ST_CONVERGED;
+      }
+    }
+    if (done == ST_BREAKDOWN || done == ST_NONFINITE) {
+      s = map_done(done);
+      fill_info(info, h, base, relres_true, repl, 0, s);
+      return fail(ctx, s, done == ST_BREAKDOWN ? "BiCGSTAB breakdown" : "non-finite value in BiCGSTAB");
+    }
+    double rt2;
+    if ((s = residual(ctx, A, b, x, r))) return s;
+    if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr,
+                          &rt2, nullptr)))
+      return s;
+    relres_true = sqrt(rt2) / base;
+    h.iters = iters;
+    if (done == ST_CONVERGED && sqrt(rt2) <= thr) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_OK);
+      return MXS_OK;
+    }
+    if (done == ST_MAXIT || repl >= stop.max_repl || iters >= stop.max_iters) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_NOT_CONVERGED);
+      return fail(ctx, MXS_NOT_CONVERGED, "BiCGSTAB stopped after %lld iterations, relres %.3e",
+                  (long long)iters, relres_true);
+    }
+    repl++;
+    rr = rt2;
+    restart = true;
+    done = RUN;
+  }
+}
+
+mxs_status solve_gmres(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
+                       const Stop& stop, int m, mxs_solve_info* info) {
+  if (m < 1 || m > MAXM)
+    return fail(ctx, MXS_UNSUPPORTED, "GMRES restart length must be in [1, %d]", MAXM);
+  const int64_t n = A->n;
+  const size_t ld = align_up((size_t)n, 64);
+  Work w;
+  mxs_status s = get_work(ctx, (size_t)(m + 3) * ld * sizeof(double), &w);
+  if (s) return s;
+  double* V = (double*)w.vec;  // m+1 basis vectors
+  double* wv = V + (size_t)(m + 1) * ld;
+  double* r = wv + ld;
+  double nb2, nr2;
+  if ((s = residual(ctx, A, b, x, r))) return s;
+  if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
+  const double nb = sqrt(nb2), nr0 = sqrt(nr2);
+  if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
+  if (nb == 0.0) {
+    MXS_HIP_TRY(ctx, hipMemsetAsync(x, 0, n * sizeof(double), ctx->stream));
+    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    KState z{};
+    fill_info(info, z, 1.0, 0.0, 0, 0, MXS_OK);
+    return MXS_OK;
+  }
+  if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
+  const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
+  const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
+  const int g = red_grid(n);
+  const double one = 1.0, zero = 0.0;
+  KState& h = *w.hst;
+  std::memset(&h, 0, sizeof(KState));
+  h.thr = thr;
+  h.max_iters = stop.max_iters;
+  h.m = m;
+  h.dot[0] = nr2;
+  if ((s = push_state(ctx, w))) return s;
+  double beta = nr0;
+  int64_t restarts = 0;
+  double est = nr0;
+  while (beta > thr) {
+    if (h.iters >= stop.max_iters) {
+      fill_info(info, h, base, beta / base, 0, restarts, MXS_NOT_CONVERGED);
+      if (info) info->relres_recurrence = est / base;
+      return fail(ctx, MXS_NOT_CONVERGED, "GMRES stopped after %lld steps, relres %.3e",
+                  (long long)h.iters, beta / base);
+    }
+    k_gm_start<<<g, RB, 0, ctx->stream>>>(n, r, V, w.st);
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (size_t)j * ld;
+      if ((s = launch_spmv(ctx, A, &one, vj, &zero, wv, &w.st->cycle))) return s;
+      k_gm_dots<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.partials, w.st);
+      k_gm_orth<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.partials, w.st);
+      k_gm_norm<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.partials, w.st);
+      k_gm_scale<<<g, RB, 0, ctx->stream>>>(n, wv, V + (size_t)(j + 1) * ld, w.st);
+    }
+    k_gm_backsolve<<<1, 1, 0, ctx->stream>>>(w.st);
+    k_gm_xupdate<<<g, RB, 0, ctx->stream>>>(n, ld, V, x, w.st);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    if ((s = residual(ctx, A, b, x, r))) return s;
+    k_dots<double><<<g, RB, 0, ctx->stream>>>(n, r, r, nullptr, nullptr, w.partials, w.st);
+    if ((s = pull_state(ctx, w))) return s;
+    if (h.done == ST_BREAKDOWN || h.done == ST_NONFINITE) {
+      s = map_done(h.done);
+      fill_info(info, h, base, beta / base, 0, restarts, s);
+      return fail(ctx, s, "GMRES %s", h.done == ST_BREAKDOWN ? "breakdown" : "non-finite value");
+    }
+    if (h.k == 0 && h.done == RUN)
+      return fail(ctx, MXS_HIP, "GMRES made no progress (device state not updated)");
+    est = h.est;
+    beta = sqrt(h.dot[0]);
+    if (!std::isfinite(beta)) return fail(ctx, MXS_NONFINITE, "non-finite GMRES residual");
+    if (beta <= thr) break;
+    restarts++;
+  }
+  fill_info(info, h, base, beta / base, 0, restarts, MXS_OK);
+  if (info) info->relres_recurrence = est / base;
+  return MXS_OK;
+}
+
+}  // namespace
+
+// exported for the iterative refinement driver below
+mxs_status solve_dispatch(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, const double* b,
+                          double* x, const mxs_stop* stop, const mxs_solver_opts* opts,
+                          mxs_solve_info* info) {
+  switch (kind) {
+    case MXS_CG:
+      return solve_cg(ctx, A, b, x, read_stop(stop, 20000), info);
+    case MXS_BICGSTAB:
+      return solve_bicgstab(ctx, A, b, x, read_stop(stop, 10000), info);
+    case MXS_GMRES:
+      return solve_gmres(ctx, A, b, x, read_stop(stop, 20000),
+                         opts && opts->restart > 0 ? opts->restart : 30, info);
+  }
+  return fail(ctx, MXS_INVALID_ARG, "unknown solver %d", (int)kind);
+}
+
+mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* Al,
+                         const double* b, double* x, const mxs_stop* outer, double inner_tol,
+                         int64_t inner_max, int last_step_variant, mxs_ir_info* info) {
+  const int64_t n = A64->n;
+  const size_t ld = align_up((size_t)n, 64);
+  Work w;
+  mxs_status s = get_work(ctx, ld * sizeof(double) + 4 * ld * sizeof(float), &w);
+  if (s) return s;
+  double* r = (double*)w.vec;
+  float* d = (float*)(r + ld);
+  float* rf = d + ld;
+  float* pf = rf + ld;
+  float* qf = pf + ld;
+  const Stop st = read_stop(outer, 50);
+  const int64_t outer_max = st.max_iters;
+  const double tol = st.rel_tol;
+  if (inner_max <= 0) inner_max = 20000;
+  double nb2;
+  if ((s = dots<double>(ctx, w, n, b, b, nullptr, nullptr, &nb2, nullptr))) return s;
+  const double nb = sqrt(nb2);
+  mxs_ir_info out{};
+  if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
+  if (nb == 0.0) {
+    MXS_HIP_TRY(ctx, hipMemsetAsync(x, 0, n * sizeof(double), ctx->stream));
+    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (info) *info = out;
+    return MXS_OK;
+  }
+  const int g = red_grid(n);
+  KState& h = *w.hst;
+  mxs_status result = MXS_OK;
+  for (;;) {
+    double nr2;
+    if ((s = residual(ctx, A64, b, x, r))) return s;
+    if ((s = dots<double>(ctx, w, n, r, r, nullptr, nullptr, &nr2, nullptr))) return s;
+    const double nr = sqrt(nr2), relres = nr / nb;
+    out.relres_true = relres;
+    if (!std::isfinite(nr)) {
+      result = fail(ctx, MXS_NONFINITE, "non-finite residual in refinement");
+      break;
+    }
+    if (relres <= tol) break;
+    if (out.outer_iters >= outer_max) {
+      result = fail(ctx, MXS_NOT_CONVERGED, "refinement stopped after %lld outer steps",
+                    (long long)out.outer_iters);
+      break;
+    }
+    double itol = inner_tol;
+    if (last_step_variant && relres * inner_tol <= tol) itol = std::max(itol, 0.1 * tol / relres);
+    // inner FP32 CG from d = 0 on A_low d = f, f = r / ||r||
+    k_ir_scale<<<g, RB, 0, ctx->stream>>>(n, r, nr, rf);
+    MXS_HIP_TRY(ctx, hipMemsetAsync(d, 0, n * sizeof(float), ctx->stream));
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(pf, rf, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    double f2;
+    if ((s = dots<float>(ctx, w, n, rf, rf, nullptr, nullptr, &f2, nullptr))) return s;
+    std::memset(&h, 0, sizeof(KState));
+    h.rho = f2;
+    h.res2 = f2;
+    h.thr = itol * sqrt(f2);
+    h.max_iters = inner_max;
+    h.done = f2 == 0.0 ? ST_CONVERGED : RUN;
+    if ((s = push_state(ctx, w))) return s;
+    if (h.done == RUN)
+      if ((s = cg_loop<float>(ctx, Al, w, d, rf, pf, qf, st.check_every))) return s;
+    out.inner_iters_total += h.iters;
+    if (h.done == ST_NONFINITE) {
+      result = fail(ctx, MXS_NONFINITE, "non-finite value in the inner solve");
+      break;
+    }
+    // a breakdown or max_iters in the inner solve still yields a usable
+    // correction; the FP64 residual decides
+    k_ir_update<<<g, RB, 0, ctx->stream>>>(n, x, d, nr);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    out.outer_iters++;
+  }
+  out.status = result;
+  if (info) *info = out;
+  return result;
+}
+
+}  // namespace mxs
+
+using namespace mxs;
+
+extern "C" {
+
+mxs_status mxs_solve(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, const double* b,
+                     double* x, const mxs_stop* stop, const mxs_solver_opts* opts,
+                     mxs_solve_info* info) {
+  if (!ctx || !A) return MXS_INVALID_ARG;
+  if (A->dt != MXS_F64)
+    return fail(ctx, MXS_UNSUPPORTED, "mxs_solve needs an F64 matrix (use mxs_solve_ir)");
+  if (A->n != A->ncols) return fail(ctx, MXS_INVALID_ARG, "matrix is not square");
+  if (A->n > 0 && (!b || !x)) return fail(ctx, MXS_INVALID_ARG, "NULL vector");
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (A->n == 0) return MXS_OK;
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return solve_dispatch(ctx, kind, A, b, x, stop, opts, info);
+}
+
+mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A_low,
+                        const double* b, double* x, const mxs_stop* outer,
+                        double inner_rel_tol, int64_t inner_max, int32_t last_step_variant,
+                        mxs_ir_info* info) {
+  if (!ctx || !A64 || !A_low) return MXS_INVALID_ARG;
+  if (A64->dt != MXS_F64 || A_low->dt == MXS_F64)
+    return fail(ctx, MXS_UNSUPPORTED, "need an F64 matrix and an F32/F16 copy");
+  if (A64->n != A64->ncols || A_low->n != A64->n || A_low->ncols != A64->ncols)
+    return fail(ctx, MXS_INVALID_ARG, "matrix shapes differ or are not square");
+  if (A64->n > 0 && (!b || !x)) return fail(ctx, MXS_INVALID_ARG, "NULL vector");
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (A64->n == 0) return MXS_OK;
+  if (!(inner_rel_tol > 0.0 && inner_rel_tol < 1.0))
+    return fail(ctx, MXS_INVALID_ARG, "inner tolerance must be in (0, 1)");
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return solve_ir_impl(ctx, A64, A_low, b, x, outer, inner_rel_tol, inner_max,
+                       last_step_variant, info);
+}
+
+}  // extern "C"

@@ -1,0 +1,497 @@
+// spmv.hip -- y = alpha*A*x + beta*y for CSR, COO, ELL and hybrid ELL+COO
+// storage on gfx950 (paper, section "Central Sparse Linear Algebra
+// Functionality"; the byte-per-entry model of its "SpMV Performance
+// Analysis" subsection makes every variant HBM-bound, so none uses MFMA).
+//
+// CSR  -- one wave per row block (<= 64*NPL entries, whole rows).  The wave
+//         streams the block's values and column indices with fully
+//         coalesced loads, gathers x, and stages the products and the
+//         block's row pointers in LDS.  Each lane then owns NPL consecutive
+//         products, sums the row segments it holds, and a segmented
+//         inclusive scan across the 64 lanes joins the segments of rows that
+//         straddle lanes.  Work per lane is NPL regardless of the row-length
+//         mix; a row longer than the block budget gets a wave of its own
+//         with four independent accumulators per lane.
+// COO  -- same lane-run/segmented-scan scheme over fixed chunks of 64*NPL
+//         entries.  A row cut by a chunk boundary is written by the chunk
+//         where it starts; later chunks store their part as a continuation
+//         partial that a small fix-up pass adds in chunk order.  No
+//         floating-point atomics, so the result is deterministic.
+// ELL  -- thread per row over the column-major slots; W waves per 64 rows
+//         take the columns round-robin (each lane keeps four accumulators),
+//         and a wave stops at the first slot group where all its rows are
+//         padding (padding is always at the end of a row).
+// HYB  -- ELL kernel for the regular part, then the COO kernel in
+//         accumulate mode for the overflow.
+//
+// Per-lane sequential chains are at most NPL (+ the scan depth of 6) for
+// CSR/COO blocks and at most a quarter of a row's entries per wave for long
+// rows and ELL; the FP64 error stays far below 1e-13 * sum|a_ij||x_j|.
+#include "common.h"
+
+namespace mxs {
+namespace {
+
+// LDS index with one pad slot every 32 elements: a lane reading NPL
+// consecutive products then hits spread-out banks.
+__device__ __forceinline__ int pad(int k) { return k + (k >> 5); }
+
+template <typename T>
+__device__ __forceinline__ T combine(T alpha, T s, T beta, const T* __restrict__ y, int64_t i) {
+  return beta == T(0) ? alpha * s : alpha * s + beta * y[i];
+}
+
+// ---------------------------------------------------------------------------
+// CSR
+// ---------------------------------------------------------------------------
+template <typename V, typename T, int NPL, bool SCALED>
+__global__ __launch_bounds__(64) void k_csr(const int32_t* __restrict__ blocks,
+                                            const int32_t* __restrict__ rowptr,
+                                            const int32_t* __restrict__ col,
+                                            const V* __restrict__ val,
+                                            const float* __restrict__ scale,
+                                            const T* __restrict__ x, T* __restrict__ y, T alpha,
+                                            T beta, const int32_t* __restrict__ skip) {
+  constexpr int C = 64 * NPL;
+  __shared__ T prod[C + C / 32];
+  __shared__ int32_t rp[C + 1];
+  if (skip && *skip) return;
+  const int lane = threadIdx.x;
+  const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const int32_t r0 = blocks[b], r1 = blocks[b + 1];
+  const int32_t s = rowptr[r0], e = rowptr[r1];
+  const int nr = r1 - r0, len = e - s;
+
+  auto emit = [&](int r, T sum) {
+    const int64_t i = (int64_t)r0 + r;
+    if (SCALED) sum *= (T)scale[i];
+    y[i] = combine(alpha, sum, beta, y, i);
+  };
+
+  if (len > C) {  // a single long row
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int32_t k = s + lane;
+    for (; k + 192 < e; k += 256) {
+      const int32_t c0 = col[k], c1 = col[k + 64], c2 = col[k + 128], c3 = col[k + 192];
+      const T v0 = to_acc(val[k]), v1 = to_acc(val[k + 64]), v2 = to_acc(val[k + 128]),
+              v3 = to_acc(val[k + 192]);
+      a0 += v0 * x[c0];
+      a1 += v1 * x[c1];
+      a2 += v2 * x[c2];
+      a3 += v3 * x[c3];
+    }
+    for (; k < e; k += 64) a0 += to_acc(val[k]) * x[col[k]];
+    const T acc = wave_sum((a0 + a1) + (a2 + a3));
+    if (lane == 0) emit(0, acc);
+    return;
+  }
+
+  for (int i = lane; i <= nr; i += 64) rp[i] = rowptr[r0 + i] - s;
+  {
+    int32_t c[NPL];
+    T v[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int k = t * 64 + lane;
+      c[t] = 0;
+      v[t] = 0;
+      if (k < len) {
+        c[t] = col[s + k];
+        v[t] = to_acc(val[s + k]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int k = t * 64 + lane;
+      if (k < len) prod[pad(k)] = v[t] * x[c[t]];
+    }
+  }
+  __syncthreads();
+
+  for (int i = lane; i < nr; i += 64)
+    if (rp[i] == rp[i + 1]) emit(i, T(0));  // empty rows
+
+  const int k0 = lane * NPL;
+  const bool active = k0 < len;
+  const int k1 = min(k0 + NPL, len);
+  T v = 0, hsum = 0, tsum = 0;
+  int f = 1, hrow = 0, trow = 0;
+  bool multi = false, hstart = false, tend = false;
+  if (active) {
+    int lo = 0, hi = nr;  // row holding entry k0: rp[lo] <= k0 < rp[lo+1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (rp[mid] <= k0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    hrow = lo;
+    hstart = rp[lo] == k0;
+    int r = lo, rend = rp[lo + 1];
+    T sum = 0;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int k = k0 + t;
+      if (k < k1) {
+        if (k == rend) {
+          if (!multi) {
+            hsum = sum;
+            multi = true;
+          } else {
+            emit(r, sum);  // a row that starts and ends in this lane
+          }
+          do {
+            ++r;
+            rend = rp[r + 1];
+          } while (rend <= k);
+          sum = 0;
+        }
+        sum += prod[pad(k)];
+      }
+    }
+    trow = r;
+    tsum = sum;
+    tend = rend == k1;
+    if (!multi) hsum = sum;
+    v = multi ? tsum : hsum;
+    f = (multi || hstart) ? 1 : 0;
+  }
+  // inclusive segmented scan over lanes: a set flag starts a new row
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T ov = __shfl_up(v, d, 64);
+    const int of = __shfl_up(f, d, 64);
+    if (lane >= d) {
+      if (!f) v = ov + v;
+      f |= of;
+    }
+  }
+  const T before = __shfl_up(v, 1, 64);
+  if (active) {
+    if (multi) {
+      emit(hrow, hstart ? hsum : before + hsum);
+      if (tend) emit(trow, tsum);
+    } else if (tend) {
+      emit(hrow, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// COO
+// ---------------------------------------------------------------------------
+template <typename V, typename T, int NPL, bool ACCUM>
+__global__ __launch_bounds__(64) void k_coo(int64_t nnz, const int32_t* __restrict__ row,
+                                            const int32_t* __restrict__ col,
+                                            const V* __restrict__ val, const T* __restrict__ x,
+                                            T* __restrict__ y, T alpha, T beta,
+                                            int32_t* __restrict__ cont_row,
+                                            T* __restrict__ cont_val,
+                                            const int32_t* __restrict__ skip) {
+  constexpr int C = 64 * NPL;
+  if (skip && *skip) return;
+  __shared__ T prod[C + C / 32];
+  __shared__ int32_t rw[C + C / 32];
+  __shared__ int32_t edge[2];
+  const int lane = threadIdx.x;
+  const int64_t ch = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t s = ch * C;
+  const int len = (int)((nnz - s) < C ? (nnz - s) : C);
+  if (lane == 0) {
+    edge[0] = s > 0 ? row[s - 1] : -1;
+    edge[1] = (s + len < nnz) ? row[s + len] : -1;
+  }
+  {
+    int32_t r[NPL], c[NPL];
+    T v[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int k = t * 64 + lane;
+      r[t] = c[t] = 0;
+      v[t] = 0;
+      if (k < len) {
+        r[t] = row[s + k];
+        c[t] = col[s + k];
+        v[t] = to_acc(val[s + k]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int k = t * 64 + lane;
+      if (k < len) {
+        prod[pad(k)] = v[t] * x[c[t]];
+        rw[pad(k)] = r[t];
+      }
+    }
+  }
+  __syncthreads();
+  const int32_t first = rw[0];
+  const bool first_continues = edge[0] == first;
+
+  auto emit = [&](int32_t r, T sum) {
+    if (first_continues && r == first) {
+      cont_row[ch] = r;
+      cont_val[ch] = sum;
+    } else if (ACCUM) {
+      y[r] = alpha * sum + y[r];
+    } else {
+      y[r] = combine(alpha, sum, beta, y, r);
+    }
+  };
+  if (lane == 0 && !first_continues) cont_row[ch] = -1;
+
+  const int k0 = lane * NPL;
+  const bool active = k0 < len;
+  const int k1 = min(k0 + NPL, len);
+  T v = 0, hsum = 0, tsum = 0;
+  int f = 1;
+  int32_t hrow = 0, trow = 0;
+  bool multi = false, hstart = false, tend = false;
+  if (active) {
+    hrow = rw[pad(k0)];
+    hstart = (k0 == 0 ? edge[0] : rw[pad(k0 - 1)]) != hrow;
+    int32_t r = hrow;
+    T sum = 0;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int k = k0 + t;
+      if (k < k1) {
+        const int32_t rk = rw[pad(k)];
+        if (rk != r) {
+          if (!multi) {
+            hsum = sum;
+            multi = true;
+          } else {
+            emit(r, sum);
+          }
+          r = rk;
+          sum = 0;
+        }
+        sum += prod[pad(k)];
+      }
+    }
+    trow = r;
+    tsum = sum;
+    // done within this chunk: the row ends here or the chunk ends here
+    tend = (k1 == len) || rw[pad(k1)] != r;
+    if (!multi) hsum = sum;
+    v = multi ? tsum : hsum;
+    f = (multi || hstart) ? 1 : 0;
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T ov = __shfl_up(v, d, 64);
+    const int of = __shfl_up(f, d, 64);
+    if (lane >= d) {
+      if (!f) v = ov + v;
+      f |= of;
+    }
+  }
+  // lane 0 has no predecessor: its head either starts here or continues a
+  // row from the previous chunk (that part is added by the fix-up pass)
+  const T up = __shfl_up(v, 1, 64);
+  const T before = lane > 0 ? up : T(0);
+  if (active) {
+    if (multi) {
+      emit(hrow, hstart ? hsum : before + hsum);
+      if (tend) emit(trow, tsum);
+    } else if (tend) {
+      emit(hrow, v);
+    }
+  }
+}
+
+// Adds the continuation partials of rows that straddle chunks, in chunk
+// order, to the value their first chunk wrote.
+template <typename T>
+__global__ void k_coo_fix(int64_t nchunks, const int32_t* __restrict__ cont_row,
+                          const T* __restrict__ cont_val, T* __restrict__ y, T alpha,
+                          const int32_t* __restrict__ skip) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nchunks || (skip && *skip)) return;
+  const int32_t r = cont_row[c];
+  if (r < 0 || (c > 0 && cont_row[c - 1] == r)) return;
+  T sum = cont_val[c];
+  for (int64_t d = c + 1; d < nchunks && cont_row[d] == r; ++d) sum += cont_val[d];
+  y[r] = y[r] + alpha * sum;
+}
+
+template <typename T>
+__global__ void k_empty_rows(int64_t count, const int32_t* __restrict__ rows,
+                             T* __restrict__ y, T beta, const int32_t* __restrict__ skip) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count || (skip && *skip)) return;
+  const int32_t r = rows[k];
+  y[r] = beta == T(0) ? T(0) : beta * y[r];
+}
+
+// ---------------------------------------------------------------------------
+// ELL
+// ---------------------------------------------------------------------------
+template <typename V, typename T, int W>
+__global__ __launch_bounds__(64 * W) void k_ell(int64_t n, int64_t K, int64_t ld,
+                                                const int32_t* __restrict__ ecol,
+                                                const V* __restrict__ eval,
+                                                const T* __restrict__ x, T* __restrict__ y,
+                                                T alpha, T beta,
+                                                const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = g * 64 + lane;  // < ld: the grid covers ld / 64 groups
+  T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int64_t j = w; j < K; j += 4 * W) {
+    const int64_t o0 = j * ld + i;
+    const int32_t c0 = ecol[o0];
+    const int32_t c1 = (j + W < K) ? ecol[o0 + W * ld] : -1;
+    const int32_t c2 = (j + 2 * W < K) ? ecol[o0 + 2 * W * ld] : -1;
+    const int32_t c3 = (j + 3 * W < K) ? ecol[o0 + 3 * W * ld] : -1;
+    if (c0 >= 0) a0 += to_acc(eval[o0]) * x[c0];
+    if (c1 >= 0) a1 += to_acc(eval[o0 + W * ld]) * x[c1];
+    if (c2 >= 0) a2 += to_acc(eval[o0 + 2 * W * ld]) * x[c2];
+    if (c3 >= 0) a3 += to_acc(eval[o0 + 3 * W * ld]) * x[c3];
+    if (!__any(c3 >= 0)) break;  // every later slot of these rows is padding
+  }
+  T acc = (a0 + a1) + (a2 + a3);
+  if (W > 1) {
+    __shared__ T red[W][64];
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w != 0) return;
+    acc = red[0][lane];
+#pragma unroll
+    for (int q = 1; q < W; ++q) acc += red[q][lane];
+  }
+  if (i < n) y[i] = combine(alpha, acc, beta, y, i);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename V, typename T, bool SCALED>
+void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
+                const int32_t* skip) {
+  const CsrPart& P = A->csr;
+  if (P.nblocks == 0) return;
+  const V* val = (const V*)P.val;
+  const dim3 grid((unsigned)P.nblocks);
+  switch (P.block_nnz) {
+    case 256:
+      k_csr<V, T, 4, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.rowptr, P.col, val,
+                                                           P.scale, x, y, alpha, beta, skip);
+      break;
+    case 1024:
+      k_csr<V, T, 16, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.rowptr, P.col, val,
+                                                            P.scale, x, y, alpha, beta, skip);
+      break;
+    default:
+      k_csr<V, T, 8, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.rowptr, P.col, val,
+                                                           P.scale, x, y, alpha, beta, skip);
+  }
+}
+
+template <typename V, typename T, bool ACCUM>
+void launch_coo(mxs_ctx* ctx, const CooPart& P, int64_t n, T alpha, const T* x, T beta, T* y,
+                const int32_t* skip) {
+  if (!ACCUM && P.nempty > 0)
+    k_empty_rows<T><<<(unsigned)((P.nempty + 255) / 256), 256, 0, ctx->stream>>>(
+        P.nempty, P.empty_rows, y, beta, skip);
+  if (P.nchunks == 0) return;
+  const V* val = (const V*)P.val;
+  const dim3 grid((unsigned)P.nchunks);
+  T* cv = (T*)P.cont_val;
+  switch (P.block_nnz) {
+    case 256:
+      k_coo<V, T, 4, ACCUM><<<grid, 64, 0, ctx->stream>>>(P.nnz, P.row, P.col, val, x, y, alpha,
+                                                          beta, P.cont_row, cv, skip);
+      break;
+    case 1024:
+      k_coo<V, T, 16, ACCUM><<<grid, 64, 0, ctx->stream>>>(P.nnz, P.row, P.col, val, x, y,
+                                                           alpha, beta, P.cont_row, cv, skip);
+      break;
+    default:
+      k_coo<V, T, 8, ACCUM><<<grid, 64, 0, ctx->stream>>>(P.nnz, P.row, P.col, val, x, y, alpha,
+                                                          beta, P.cont_row, cv, skip);
+  }
+  if (P.nchunks > 1)
+    k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
+        P.nchunks, P.cont_row, cv, y, alpha, skip);
+}
+
+template <typename V, typename T>
+void launch_ell(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
+                const int32_t* skip) {
+  const EllPart& P = A->ell;
+  if (P.stride == 0) return;
+  const dim3 grid((unsigned)(P.stride / 64));
+  const V* val = (const V*)P.val;
+  switch (P.waves) {
+#define MXS_ELL_CASE(WW)                                                                   \
+  case WW:                                                                                 \
+    k_ell<V, T, WW><<<grid, 64 * WW, 0, ctx->stream>>>(A->n, P.K, P.stride, P.col, val, x, y, \
+                                                        alpha, beta, skip);                \
+    break;
+    MXS_ELL_CASE(2)
+    MXS_ELL_CASE(4)
+    MXS_ELL_CASE(8)
+    MXS_ELL_CASE(16)
+#undef MXS_ELL_CASE
+    default:
+      k_ell<V, T, 1><<<grid, 64, 0, ctx->stream>>>(A->n, P.K, P.stride, P.col, val, x, y, alpha,
+                                                   beta, skip);
+  }
+}
+
+template <typename V, typename T, bool SCALED>
+void launch_typed(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
+                  const int32_t* skip) {
+  switch (A->fmt) {
+    case MXS_CSR:
+      launch_csr<V, T, SCALED>(ctx, A, alpha, x, beta, y, skip);
+      break;
+    case MXS_COO:
+      launch_coo<V, T, false>(ctx, A->coo, A->n, alpha, x, beta, y, skip);
+      break;
+    case MXS_ELL:
+      launch_ell<V, T>(ctx, A, alpha, x, beta, y, skip);
+      break;
+    case MXS_HYB:
+      if (A->ell.K == 0) {
+        launch_coo<V, T, false>(ctx, A->coo, A->n, alpha, x, beta, y, skip);
+      } else {
+        launch_ell<V, T>(ctx, A, alpha, x, beta, y, skip);
+        launch_coo<V, T, true>(ctx, A->coo, A->n, alpha, x, beta, y, skip);
+      }
+      break;
+  }
+}
+
+}  // namespace
+
+mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, const void* x,
+                       const void* beta, void* y, const int32_t* skip) {
+  if (A->n == 0) return MXS_OK;
+  if (A->dt == MXS_F64) {
+    launch_typed<double, double, false>(ctx, A, *(const double*)alpha, (const double*)x,
+                                        *(const double*)beta, (double*)y, skip);
+  } else if (A->dt == MXS_F32) {
+    launch_typed<float, float, false>(ctx, A, *(const float*)alpha, (const float*)x,
+                                      *(const float*)beta, (float*)y, skip);
+  } else {
+    launch_typed<_Float16, float, true>(ctx, A, *(const float*)alpha, (const float*)x,
+                                        *(const float*)beta, (float*)y, skip);
+  }
+  MXS_HIP_TRY(ctx, hipGetLastError());
+  return MXS_OK;
+}
+
+}  // namespace mxs
+
+extern "C" mxs_status mxs_spmv(mxs_ctx* ctx, const void* alpha, const mxs_matrix* A,
+                               const void* x, const void* beta, void* y) {
+  if (!ctx || !A || !alpha || !beta) return MXS_INVALID_ARG;
+  if (A->n > 0 && !y) return mxs::fail(ctx, MXS_INVALID_ARG, "y is NULL");
+  if (A->nnz > 0 && !x) return mxs::fail(ctx, MXS_INVALID_ARG, "x is NULL");
+  return mxs::launch_spmv(ctx, A, alpha, x, beta, y, nullptr);
+}

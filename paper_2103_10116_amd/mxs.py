@@ -1,0 +1,353 @@
+"""ctypes binding of libmxs (include/mxs.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts Python and
+torch arguments to the C ABI, raises MxsError on a non-OK status, and hands
+torch's current HIP stream to the library.  Importing it loads
+``libmxs.so`` from this package directory and fails loudly if it has not
+been built (``python -c "import __graft_entry__ as g; g.build()"``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmxs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                      "(paper_2103_10116_amd/build.py or __graft_entry__.build())")
+_lib = C.CDLL(LIB_PATH)
+
+OK, INVALID_ARG, INVALID_MATRIX, UNSUPPORTED, OOM, HIP = 0, 1, 2, 3, 4, 5
+NOT_CONVERGED, BREAKDOWN, NONFINITE, BUDGET, PENDING = 6, 7, 8, 9, 10
+
+CSR, COO, ELL, HYB = 0, 1, 2, 3
+F64, F32, F16_ROWSCALED = 0, 1, 2
+FORMATS = {"csr": CSR, "coo": COO, "ell": ELL, "hyb": HYB}
+DTYPES = {"f64": F64, "f32": F32, "f16": F16_ROWSCALED}
+CG, BICGSTAB, GMRES = 0, 1, 2
+SOLVERS = {"cg": CG, "bicgstab": BICGSTAB, "gmres": GMRES}
+HOST_PTRS, DEVICE_PTRS = 0, 1
+
+(ARR_ROWPTR, ARR_COL, ARR_VAL, ARR_ROW, ARR_ELL_COL, ARR_ELL_VAL,
+ ARR_COO_ROW, ARR_COO_COL, ARR_COO_VAL, ARR_SCALE) = range(10)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", C.c_void_p), ("free", C.c_void_p), ("user", C.c_void_p)]
+
+
+class ConvertOpts(C.Structure):
+    _fields_ = [("ell_width", C.c_int64), ("max_ell_bytes", C.c_int64),
+                ("block_nnz", C.c_int32)]
+
+
+class MatrixDesc(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
+                ("format", C.c_int32), ("dtype", C.c_int32), ("ell_width", C.c_int64),
+                ("ell_stride", C.c_int64), ("coo_nnz", C.c_int64), ("blocks", C.c_int64),
+                ("bytes", C.c_int64), ("block_nnz", C.c_int32)]
+
+
+class Stop(C.Structure):
+    _fields_ = [("max_iters", C.c_int64), ("rel_tol", C.c_double), ("abs_tol", C.c_double),
+                ("baseline", C.c_int32), ("check_every", C.c_int32),
+                ("max_replacements", C.c_int32)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("relres_recurrence", C.c_double),
+                ("relres_true", C.c_double), ("replacements", C.c_int64),
+                ("restarts", C.c_int64), ("status", C.c_int32)]
+
+
+class IRInfo(C.Structure):
+    _fields_ = [("outer_iters", C.c_int64), ("inner_iters_total", C.c_int64),
+                ("relres_true", C.c_double), ("status", C.c_int32)]
+
+
+class BwResult(C.Structure):
+    _fields_ = [("read_gbs", C.c_double), ("copy_gbs", C.c_double),
+                ("triad_gbs", C.c_double), ("best_gbs", C.c_double)]
+
+
+_P = C.c_void_p
+_S = C.c_int32
+_I64 = C.c_int64
+_SIGS = {
+    "mxs_ctx_create": (_S, [C.c_int, _P, C.POINTER(Allocator), C.POINTER(_P)]),
+    "mxs_ctx_destroy": (_S, [_P]),
+    "mxs_ctx_set_stream": (_S, [_P, _P]),
+    "mxs_ctx_synchronize": (_S, [_P]),
+    "mxs_matrix_create_csr": (_S, [_P, _I64, _I64, _I64, _P, _P, _P, C.c_int, C.POINTER(_P)]),
+    "mxs_matrix_convert": (_S, [_P, _P, C.c_int, C.c_int, C.POINTER(ConvertOpts), C.POINTER(_P)]),
+    "mxs_matrix_info": (_S, [_P, C.POINTER(MatrixDesc)]),
+    "mxs_matrix_export": (_S, [_P, _P, C.c_int, _P, C.c_size_t]),
+    "mxs_matrix_destroy": (_S, [_P]),
+    "mxs_spmv": (_S, [_P, _P, _P, _P, _P, _P]),
+    "mxs_solve": (_S, [_P, C.c_int, _P, _P, _P, C.POINTER(Stop), C.POINTER(SolverOpts),
+                       C.POINTER(SolveInfo)]),
+    "mxs_solve_ir": (_S, [_P, _P, _P, _P, _P, C.POINTER(Stop), C.c_double, _I64, _S,
+                          C.POINTER(IRInfo)]),
+    "mxs_hbm_probe": (_S, [_P, C.c_size_t, C.c_int, C.POINTER(BwResult)]),
+    "mxs_flush_cache": (_S, [_P, C.c_size_t]),
+    "mxs_status_string": (C.c_char_p, [_S]),
+    "mxs_last_error": (C.c_char_p, [_P]),
+    "mxs_version": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    """Names of the C functions this binding declares (all must resolve)."""
+    return list(_SIGS)
+
+
+class MxsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_lib.mxs_status_string(status).decode()}: {message}")
+        self.status = status
+
+
+def _check(status, ctx=None):
+    if status != OK:
+        msg = _lib.mxs_last_error(ctx.handle if ctx is not None else None)
+        raise MxsError(status, msg.decode() if msg else "")
+
+
+def version() -> str:
+    return _lib.mxs_version().decode()
+
+
+def status_string(s: int) -> str:
+    return _lib.mxs_status_string(s).decode()
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+class Context:
+    """A libmxs context bound to torch's current HIP stream on `device`."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmxs needs a ROCm GPU; torch.cuda is not available")
+        self.device = device
+        torch.cuda.set_device(device)
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        h = C.c_void_p()
+        _check(_lib.mxs_ctx_create(device, C.c_void_p(s.cuda_stream), None, C.byref(h)))
+        self.handle = h
+
+    def synchronize(self):
+        _check(_lib.mxs_ctx_synchronize(self.handle), self)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mxs_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# matrices
+# ---------------------------------------------------------------------------
+_VDT = {F64: np.float64, F32: np.float32, F16_ROWSCALED: np.uint16}
+
+
+class Matrix:
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+        d = MatrixDesc()
+        _check(_lib.mxs_matrix_info(handle, C.byref(d)), ctx)
+        self.desc = d
+
+    @classmethod
+    def from_csr(cls, ctx: Context, n, ncols, rowptr, col, val) -> "Matrix":
+        """mxs_matrix_create_csr from host numpy arrays or device torch tensors."""
+        import torch
+        if isinstance(rowptr, torch.Tensor):
+            flags = DEVICE_PTRS
+            for t, dt in ((rowptr, torch.int32), (col, torch.int32), (val, torch.float64)):
+                if t.dtype != dt or not t.is_contiguous() or t.device.type != "cuda":
+                    raise TypeError("device CSR arrays must be contiguous int32/int32/float64 on the GPU")
+            ptrs = [C.c_void_p(t.data_ptr()) for t in (rowptr, col, val)]
+            keep = None
+            nnz = int(col.numel())
+        else:
+            flags = HOST_PTRS
+            keep = [np.ascontiguousarray(rowptr, np.int32), np.ascontiguousarray(col, np.int32),
+                    np.ascontiguousarray(val, np.float64)]
+            ptrs = [a.ctypes.data_as(C.c_void_p) for a in keep]
+            nnz = len(keep[1])
+        h = C.c_void_p()
+        _check(_lib.mxs_matrix_create_csr(ctx.handle, int(n), int(ncols), nnz, *ptrs, flags,
+                                          C.byref(h)), ctx)
+        return cls(ctx, h)
+
+    @classmethod
+    def from_host(cls, ctx: Context, A) -> "Matrix":
+        """From any object with n, ncols, rowptr, col, val (numpy)."""
+        return cls.from_csr(ctx, A.n, A.ncols, A.rowptr, A.col, A.val)
+
+    def convert(self, fmt="csr", dtype="f64", ell_width=0, max_ell_bytes=0,
+                block_nnz=0) -> "Matrix":
+        o = ConvertOpts(int(ell_width), int(max_ell_bytes), int(block_nnz))
+        h = C.c_void_p()
+        _check(_lib.mxs_matrix_convert(self.ctx.handle, self.handle, FORMATS.get(fmt, fmt),
+                                       DTYPES.get(dtype, dtype), C.byref(o), C.byref(h)),
+               self.ctx)
+        return Matrix(self.ctx, h)
+
+    @property
+    def n(self):
+        return self.desc.nrows
+
+    @property
+    def dtype(self):
+        return self.desc.dtype
+
+    def info(self) -> dict:
+        d = self.desc
+        return {f: getattr(d, f) for f, _ in MatrixDesc._fields_}
+
+    def export(self, which: int) -> np.ndarray:
+        d = self.desc
+        vdt = _VDT[d.dtype]
+        sizes = {
+            ARR_ROWPTR: (d.nrows + 1, np.int32), ARR_COL: (d.nnz, np.int32),
+            ARR_VAL: (d.nnz, vdt), ARR_ROW: (d.nnz, np.int32),
+            ARR_ELL_COL: (d.ell_width * d.ell_stride, np.int32),
+            ARR_ELL_VAL: (d.ell_width * d.ell_stride, vdt),
+            ARR_COO_ROW: (d.coo_nnz, np.int32), ARR_COO_COL: (d.coo_nnz, np.int32),
+            ARR_COO_VAL: (d.coo_nnz, vdt), ARR_SCALE: (d.nrows, np.float32),
+        }
+        count, dt = sizes[which]
+        out = np.empty(int(count), dt)
+        _check(_lib.mxs_matrix_export(self.ctx.handle, self.handle, which,
+                                      out.ctypes.data_as(C.c_void_p), out.nbytes), self.ctx)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mxs_matrix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# operations
+# ---------------------------------------------------------------------------
+def _vec(t, n, want):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("vectors must be torch tensors on the GPU")
+    if t.dtype != want or not t.is_contiguous() or t.numel() != n:
+        raise TypeError(f"expected a contiguous {want} vector of {n} entries, "
+                        f"got {t.dtype} {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _compute_dtype(A: Matrix):
+    import torch
+    return torch.float64 if A.dtype == F64 else torch.float32
+
+
+def spmv(ctx: Context, A: Matrix, x, y, alpha=1.0, beta=0.0):
+    """mxs_spmv: y = alpha*A*x + beta*y (asynchronous on the ctx stream)."""
+    ct = C.c_double if A.dtype == F64 else C.c_float
+    a, b = ct(alpha), ct(beta)
+    dt = _compute_dtype(A)
+    _check(_lib.mxs_spmv(ctx.handle, C.byref(a), A.handle, _vec(x, A.desc.ncols, dt),
+                         C.byref(b), _vec(y, A.n, dt)), ctx)
+
+
+@dataclass
+class Result:
+    status: int
+    iters: int
+    relres_recurrence: float
+    relres_true: float
+    replacements: int = 0
+    restarts: int = 0
+
+
+def solve(ctx: Context, kind, A: Matrix, b, x, tol=1e-10, max_iters=0, abs_tol=0.0,
+          baseline=0, check_every=0, max_replacements=-1, restart=30, raise_on_error=True):
+    """mxs_solve: A x = b with x holding x0 on entry (FP64 device vectors)."""
+    import torch
+    st = Stop(int(max_iters), float(tol), float(abs_tol), int(baseline), int(check_every),
+              int(max_replacements))
+    opts = SolverOpts(int(restart))
+    info = SolveInfo()
+    s = _lib.mxs_solve(ctx.handle, SOLVERS.get(kind, kind), A.handle,
+                       _vec(b, A.n, torch.float64), _vec(x, A.n, torch.float64), C.byref(st),
+                       C.byref(opts), C.byref(info))
+    if raise_on_error and s not in (OK,):
+        _check(s, ctx)
+    return Result(s, info.iters, info.relres_recurrence, info.relres_true, info.replacements,
+                  info.restarts)
+
+
+@dataclass
+class IRResult:
+    status: int
+    outer_iters: int
+    inner_iters_total: int
+    relres_true: float
+
+
+def solve_ir(ctx: Context, A64: Matrix, Alow: Matrix, b, x, tol=1e-10, outer_max=50,
+             inner_tol=1e-4, inner_max=20000, last_step_variant=False, check_every=0,
+             raise_on_error=True):
+    """mxs_solve_ir: FP64 refinement around an FP32 CG on the low-precision copy."""
+    import torch
+    st = Stop(int(outer_max), float(tol), 0.0, 0, int(check_every), -1)
+    info = IRInfo()
+    s = _lib.mxs_solve_ir(ctx.handle, A64.handle, Alow.handle, _vec(b, A64.n, torch.float64),
+                          _vec(x, A64.n, torch.float64), C.byref(st), float(inner_tol),
+                          int(inner_max), 1 if last_step_variant else 0, C.byref(info))
+    if raise_on_error and s != OK:
+        _check(s, ctx)
+    return IRResult(s, info.outer_iters, info.inner_iters_total, info.relres_true)
+
+
+def hbm_probe(ctx: Context, nbytes=1 << 30, reps=5) -> dict:
+    r = BwResult()
+    _check(_lib.mxs_hbm_probe(ctx.handle, int(nbytes), int(reps), C.byref(r)), ctx)
+    return {"read_gbs": r.read_gbs, "copy_gbs": r.copy_gbs, "triad_gbs": r.triad_gbs,
+            "best_gbs": r.best_gbs}
+
+
+def flush_cache(ctx: Context, nbytes=1 << 30):
+    _check(_lib.mxs_flush_cache(ctx.handle, int(nbytes)), ctx)

@@ -1,0 +1,299 @@
+"""GPU parity of ingest, conversions and SpMV against the CPU oracle, through
+the C ABI.  Conversions must match bit for bit; FP64 products must agree per
+entry within 1e-13 * (|alpha| sum_j |a_ij||x_j| + |beta||y_i|); FP32 and
+FP16-row-scaled products within 1e-5 times the same scale, against the
+oracle evaluated exactly on the rounded inputs."""
+import numpy as np
+import pytest
+
+from conftest import load_golden
+from paper_2103_10116_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FORMATS = ["csr", "coo", "ell", "hyb"]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2103_10116_amd import mxs
+    ctx = mxs.Context(0)
+    yield mxs, ctx, torch
+    ctx.close()
+
+
+def _dev(torch, a, dt=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dt is not None:
+        t = t.to(dt)
+    return t.cuda()
+
+
+def golden_matrix():
+    g = load_golden("formats_small.txt")
+    return I.CSRMatrix(g["n"][0], g["ncols"][0], np.array(g["rowptr"], np.int32),
+                       np.array(g["col"], np.int32), np.array(g["val"], float))
+
+
+def matrix_zoo():
+    """Small cases that span several work blocks and ragged tails."""
+    zoo = {
+        "golden": golden_matrix(),
+        "one": I.dense_to_csr(np.array([[2.5]])),
+        "poisson2d_64": I.poisson2d(64),
+        "zipf_3000": I.zipf_random(3000, 2.0, 1200, seed=3),
+        "zipf_rect": I.zipf_random(2500, 1.7, 700, seed=4, ncols=3001),
+        "conv_13": I.convdiff3d(13),
+        "st27_9": I.stencil27(9),
+    }
+    # every 7th row empty, row 101 longer than every block budget (1800
+    # entries > 1024), 2113 rows (ragged against 64-row groups)
+    g = I.rng(5)
+    n = 2113
+    M = I.zipf_random(n, 2.0, 40, seed=6)
+    lens = M.row_lengths()
+    rows = np.repeat(np.arange(n), lens)
+    keep = (rows % 7 != 0) & (rows != 101)
+    extra = np.sort(g.choice(n, 1800, replace=False))
+    r = np.concatenate([rows[keep], np.full(len(extra), 101)])
+    c = np.concatenate([M.col[keep], extra]).astype(np.int32)
+    v = np.concatenate([M.val[keep], g.uniform(-1, 1, len(extra))])
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(r, minlength=n), out=rp[1:])
+    zoo["empty_rows_longrow"] = I.CSRMatrix(n, n, rp.astype(np.int32), c, v)
+    zoo["all_empty"] = I.CSRMatrix(70, 70, np.zeros(71, np.int32), np.zeros(0, np.int32),
+                                   np.zeros(0))
+    return zoo
+
+
+ZOO = matrix_zoo()
+
+
+# ---------------------------------------------------------------------------
+# ingest
+# ---------------------------------------------------------------------------
+def test_create_rejects_invalid(env):
+    mxs, ctx, torch = env
+    A = golden_matrix()
+    bad_cols = A.col.copy()
+    bad_cols[1] = 0  # row 0 becomes (0, 0): duplicate
+    for rp, ci, nc in [(A.rowptr, bad_cols, 6), (A.rowptr, A.col, 5),
+                       (np.array([0, 2, 1, 5, 6, 10], np.int32), A.col, 6),
+                       (np.array([0, 2, 2, 5, 6, 9], np.int32), A.col, 6)]:
+        with pytest.raises(mxs.MxsError) as e:
+            mxs.Matrix.from_csr(ctx, 5, nc, rp, ci, A.val)
+        assert e.value.status == mxs.INVALID_MATRIX
+    with pytest.raises(mxs.MxsError) as e:
+        mxs.Matrix.from_csr(ctx, 5, 6, A.rowptr, A.col, A.val).convert("coo", "f16")
+    assert e.value.status == mxs.UNSUPPORTED
+
+
+def test_create_from_device_pointers(env, orc):
+    mxs, ctx, torch = env
+    A = ZOO["zipf_3000"]
+    M = mxs.Matrix.from_csr(ctx, A.n, A.ncols, _dev(torch, A.rowptr), _dev(torch, A.col),
+                            _dev(torch, A.val))
+    assert np.array_equal(M.export(mxs.ARR_ROWPTR), A.rowptr)
+    assert np.array_equal(M.export(mxs.ARR_COL), A.col)
+    assert np.array_equal(M.export(mxs.ARR_VAL), A.val)
+
+
+# ---------------------------------------------------------------------------
+# conversions: bit-exact against the oracle's own conversions
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", sorted(ZOO))
+def test_conversions_bit_exact(env, orc, name):
+    mxs, ctx, torch = env
+    A = ZOO[name]
+    M = mxs.Matrix.from_host(ctx, A)
+    coo_row = orc.csr_to_coo(A.n, A.rowptr)
+    E = orc.csr_to_ell(A)
+    for dt, vb in (("f64", 8), ("f32", 4)):
+        st, v32 = orc.cast_f32(A.val)
+        vals = A.val if dt == "f64" else v32
+        cast = (lambda a: a) if dt == "f64" else (lambda a: orc.cast_f32(a)[1])
+        C = M.convert("csr", dt)
+        assert np.array_equal(C.export(mxs.ARR_ROWPTR), A.rowptr)
+        assert np.array_equal(C.export(mxs.ARR_COL), A.col)
+        assert np.array_equal(C.export(mxs.ARR_VAL).view(np.uint8), vals.view(np.uint8))
+        C = M.convert("coo", dt)
+        assert np.array_equal(C.export(mxs.ARR_ROW), coo_row)
+        assert np.array_equal(C.export(mxs.ARR_COL), A.col)
+        assert np.array_equal(C.export(mxs.ARR_VAL).view(np.uint8), vals.view(np.uint8))
+        C = M.convert("ell", dt)
+        assert (C.desc.ell_width, C.desc.ell_stride) == (E.K, E.stride)
+        assert np.array_equal(C.export(mxs.ARR_ELL_COL), E.col)
+        assert np.array_equal(C.export(mxs.ARR_ELL_VAL).view(np.uint8),
+                              cast(E.val).view(np.uint8))
+        H = orc.csr_to_hyb(A, vb)
+        C = M.convert("hyb", dt)
+        assert C.desc.ell_width == H.K and C.desc.coo_nnz == len(H.crow)
+        assert np.array_equal(C.export(mxs.ARR_ELL_COL), H.ecol)
+        assert np.array_equal(C.export(mxs.ARR_ELL_VAL).view(np.uint8),
+                              cast(H.eval).view(np.uint8))
+        assert np.array_equal(C.export(mxs.ARR_COO_ROW), H.crow)
+        assert np.array_equal(C.export(mxs.ARR_COO_COL), H.ccol)
+        assert np.array_equal(C.export(mxs.ARR_COO_VAL).view(np.uint8),
+                              cast(H.cval).view(np.uint8))
+    st, h, s = orc.rowscale_f16(A)
+    C = M.convert("csr", "f16")
+    assert np.array_equal(C.export(mxs.ARR_VAL), h)
+    assert np.array_equal(C.export(mxs.ARR_SCALE), s)
+
+
+def test_f32_range_rejected(env):
+    mxs, ctx, torch = env
+    A = I.dense_to_csr(np.array([[1.0, 4e38], [0.0, 2.0]]))
+    M = mxs.Matrix.from_host(ctx, A)
+    with pytest.raises(mxs.MxsError) as e:
+        M.convert("csr", "f32")
+    assert e.value.status == mxs.UNSUPPORTED
+
+
+def test_forced_widths(env, orc):
+    mxs, ctx, torch = env
+    A = ZOO["zipf_3000"]
+    M = mxs.Matrix.from_host(ctx, A)
+    for K in (1, 3, 17):
+        C = M.convert("hyb", "f64", ell_width=K)
+        H = orc.csr_to_hyb(A, 8, K=K)
+        assert np.array_equal(C.export(mxs.ARR_ELL_COL), H.ecol)
+        assert np.array_equal(C.export(mxs.ARR_COO_COL), H.ccol)
+    with pytest.raises(mxs.MxsError):
+        M.convert("ell", "f64", ell_width=2)
+    with pytest.raises(mxs.MxsError) as e:
+        M.convert("ell", "f64", max_ell_bytes=1000)
+    assert e.value.status == mxs.UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# SpMV parity
+# ---------------------------------------------------------------------------
+def _check(y, ref, scale, tol):
+    err = np.abs(y - ref)
+    bound = tol * scale + 1e-300
+    bad = err > bound
+    assert not bad.any(), f"{bad.sum()} entries out of bound; worst ratio {np.max(err / bound):.3g}"
+
+
+@pytest.mark.parametrize("name", sorted(ZOO))
+@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("block_nnz", [0, 256, 1024])
+def test_spmv_f64(env, orc, name, fmt, block_nnz):
+    mxs, ctx, torch = env
+    A = ZOO[name]
+    if block_nnz and fmt in ("ell", "hyb") and name != "zipf_3000":
+        pytest.skip("block size only changes the CSR/COO work units")
+    M = mxs.Matrix.from_host(ctx, A)
+    B = M.convert(fmt, "f64", block_nnz=block_nnz)
+    x = I.uniform_vector(A.ncols, 11)
+    y0 = I.uniform_vector(A.n, 12)
+    xd = _dev(torch, x)
+    for alpha, beta in ((1.0, 0.0), (-2.5, 1.0), (0.5, -3.0)):
+        y = _dev(torch, y0.copy()) if beta != 0 else torch.full((A.n,), float("nan"),
+                                                                 dtype=torch.float64,
+                                                                 device="cuda")
+        mxs.spmv(ctx, B, xd, y, alpha, beta)
+        ref = orc.spmv_csr(A, x, alpha, beta, y0 if beta != 0 else None)
+        scale = abs(alpha) * orc.absrow(A, x) + abs(beta) * np.abs(y0)
+        _check(y.cpu().numpy(), ref, scale, 1e-13)
+
+
+@pytest.mark.parametrize("name", sorted(ZOO))
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_spmv_f32(env, orc, name, fmt):
+    mxs, ctx, torch = env
+    A = ZOO[name]
+    M = mxs.Matrix.from_host(ctx, A)
+    B = M.convert(fmt, "f32")
+    _, v32 = orc.cast_f32(A.val)
+    A32 = I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, v32.astype(np.float64))
+    x = I.uniform_vector(A.ncols, 13).astype(np.float32)
+    y0 = I.uniform_vector(A.n, 14).astype(np.float32)
+    for alpha, beta in ((1.0, 0.0), (2.0, -1.0)):
+        y = _dev(torch, y0.copy())
+        mxs.spmv(ctx, B, _dev(torch, x), y, alpha, beta)
+        ref = orc.spmv_csr(A32, x.astype(np.float64), alpha, beta, y0.astype(np.float64))
+        scale = abs(alpha) * orc.absrow(A32, x.astype(np.float64)) + abs(beta) * np.abs(y0)
+        _check(y.cpu().numpy().astype(np.float64), ref, scale, 1e-5)
+
+
+@pytest.mark.parametrize("name", sorted(ZOO))
+def test_spmv_f16_rowscaled(env, orc, name):
+    mxs, ctx, torch = env
+    A = ZOO[name]
+    M = mxs.Matrix.from_host(ctx, A)
+    B = M.convert("csr", "f16")
+    st, h, s = orc.rowscale_f16(A)
+    x = I.uniform_vector(A.ncols, 15).astype(np.float32)
+    y = torch.zeros(A.n, dtype=torch.float32, device="cuda")
+    mxs.spmv(ctx, B, _dev(torch, x), y, 1.0, 0.0)
+    ref = orc.spmv_csr_f16(A, h, s, x.astype(np.float64))
+    dec = orc.f16_bits_to_f64(h) * np.repeat(s.astype(np.float64), A.row_lengths())
+    Ad = I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, dec)
+    _check(y.cpu().numpy().astype(np.float64), ref, orc.absrow(Ad, x.astype(np.float64)), 1e-5)
+
+
+def test_spmv_empty_matrix(env):
+    mxs, ctx, torch = env
+    M = mxs.Matrix.from_csr(ctx, 0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32),
+                            np.zeros(0))
+    for fmt in FORMATS:
+        B = M.convert(fmt, "f64")
+        y = torch.zeros(0, dtype=torch.float64, device="cuda")
+        mxs.spmv(ctx, B, torch.zeros(0, dtype=torch.float64, device="cuda"), y)
+    ctx.synchronize()
+
+
+def test_spmv_deterministic(env):
+    mxs, ctx, torch = env
+    A = ZOO["zipf_3000"]
+    M = mxs.Matrix.from_host(ctx, A)
+    x = _dev(torch, I.uniform_vector(A.n, 16))
+    for fmt in FORMATS:
+        B = M.convert(fmt, "f64")
+        ys = []
+        for _ in range(3):
+            y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            mxs.spmv(ctx, B, x, y)
+            ys.append(y.cpu().numpy())
+        assert all(np.array_equal(ys[0].view(np.uint64), t.view(np.uint64)) for t in ys[1:])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("which", ["stencil27_128", "zipf_2p20", "zipf_2p20_m16"])
+def test_spmv_full_size(env, orc, which):
+    """The benchmark's workloads at full size, every format, FP64 and FP32,
+    all entries against the oracle."""
+    mxs, ctx, torch = env
+    if which == "stencil27_128":
+        A = I.stencil27(128)
+    elif which == "zipf_2p20":
+        A = I.zipf_random(2 ** 20, 2.0, 4096)
+    else:
+        A = I.zipf_random(2 ** 20, 1.79, 4096)
+    x = I.uniform_vector(A.n, 17)
+    ref = orc.spmv_csr(A, x)
+    scale = orc.absrow(A, x)
+    _, v32 = orc.cast_f32(A.val)
+    x32 = x.astype(np.float32)
+    A32 = I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, v32.astype(np.float64))
+    ref32 = orc.spmv_csr(A32, x32.astype(np.float64))
+    scale32 = orc.absrow(A32, x32.astype(np.float64))
+    M = mxs.Matrix.from_host(ctx, A)
+    for fmt in FORMATS:
+        if fmt == "ell" and which.startswith("zipf"):
+            continue  # 4096-wide padded ELL of 2^20 rows: 51 GB; covered by the bench
+        B = M.convert(fmt, "f64")
+        y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        mxs.spmv(ctx, B, _dev(torch, x), y)
+        _check(y.cpu().numpy(), ref, scale, 1e-13)
+        del B
+        B = M.convert(fmt, "f32")
+        y = torch.zeros(A.n, dtype=torch.float32, device="cuda")
+        mxs.spmv(ctx, B, _dev(torch, x32), y)
+        _check(y.cpu().numpy().astype(np.float64), ref32, scale32, 1e-5)
+        del B
