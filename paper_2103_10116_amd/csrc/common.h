@@ -65,14 +65,19 @@ namespace mxs {
 
 // CSR: rows partitioned into blocks of at most block_nnz entries (a row
 // longer than that is a block on its own); one wave per block.
+// CSR: either the "stream" kernel over row blocks (lanes == 0) or the
+// "vector" kernel with `lanes` lanes per row and `rpg` rows per lane group.
 struct CsrPart {
   int32_t* rowptr = nullptr;
   int32_t* col = nullptr;
   void* val = nullptr;
   float* scale = nullptr;  // F16_ROWSCALED only
-  int32_t* blocks = nullptr;
+  int32_t* blocks = nullptr;  // first row of each block (nblocks + 1)
+  int32_t* bnnz = nullptr;    // first entry of each block (nblocks + 1)
   int64_t nblocks = 0;
   int block_nnz = 512;
+  int lanes = 0;
+  int rpg = 4;
 };
 
 // COO: equal chunks of block_nnz entries, one wave per chunk.  Rows cut by

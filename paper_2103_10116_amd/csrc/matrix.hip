@@ -267,13 +267,39 @@ T* upload(mxs_ctx* ctx, mxs_matrix* A, const std::vector<T>& h) {
   return d;
 }
 
-mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz) {
-  std::vector<int32_t> blocks;
+// Chooses the CSR kernel from the row lengths (or the caller's options) and
+// builds the row-block partition the stream kernel needs.
+mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
+                               const mxs_convert_opts* opts = nullptr) {
+  const std::vector<int32_t>& rp = A->h_rowptr;
+  int64_t maxL = 0;
+  for (int64_t i = 0; i < A->n; ++i) maxL = std::max<int64_t>(maxL, rp[i + 1] - rp[i]);
+  const double mean = A->n ? (double)A->nnz / (double)A->n : 0.0;
+  int G = 4;
+  while (G < 64 && G < mean) G <<= 1;
+  const int kind = opts ? opts->csr_kernel : MXS_CSR_AUTO;
+  if (opts && opts->lanes_per_row > 0) {
+    G = 4;
+    while (G < 64 && G < opts->lanes_per_row) G <<= 1;
+  }
+  // AUTO keeps the stream kernel: on the stencil matrices it gathers x with
+  // fewer cache lines per instruction than the lanes-along-a-row layout
+  (void)maxL;
+  bool vec = kind == MXS_CSR_VECTOR;
+  A->csr.lanes = vec ? G : 0;
+  int rpg = (opts && opts->rows_per_group > 0) ? opts->rows_per_group : (G >= 8 ? 8 : 4);
+  A->csr.rpg = rpg <= 2 ? 2 : rpg <= 4 ? 4 : 8;
+  if (A->csr.rpg > G) A->csr.rpg = G;
+  std::vector<int32_t> blocks, bnnz;
   A->csr.block_nnz = block_nnz;
-  A->csr.nblocks = csr_partition(A->h_rowptr.data(), A->n, block_nnz, blocks);
+  A->csr.nblocks = csr_partition(rp.data(), A->n, block_nnz, blocks);
+  bnnz.resize(blocks.size());
+  for (size_t b = 0; b < blocks.size(); ++b) bnnz[b] = rp[blocks[b]];
   A->csr.blocks = upload(ctx, A, blocks);
-  if (!A->csr.blocks) return fail(ctx, MXS_OOM, "cannot upload the row-block partition");
-  // the host vector is freed on return: the copy must finish first
+  A->csr.bnnz = upload(ctx, A, bnnz);
+  if (!A->csr.blocks || !A->csr.bnnz)
+    return fail(ctx, MXS_OOM, "cannot upload the row-block partition");
+  // the host vectors are freed on return: the copies must finish first
   MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return MXS_OK;
 }
@@ -330,7 +356,7 @@ mxs_status convert_typed(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, mxs_f
     mxs_status st = cast_into<V>(ctx, nnz, (const double*)S->csr.val, A->csr.val, d_err);
     if (st) return st;
     A->h_rowptr = hrp;
-    return build_csr_partition(ctx, A, bnnz);
+    return build_csr_partition(ctx, A, bnnz, opts);
   }
 
   if (fmt == MXS_COO) {
@@ -556,7 +582,7 @@ mxs_status mxs_matrix_convert(mxs_ctx* ctx, const mxs_matrix* src, mxs_format fm
             n, src->csr.rowptr, (const double*)src->csr.val, (uint16_t*)A->csr.val, A->csr.scale,
             d_err);
       A->h_rowptr = src->h_rowptr;
-      st = build_csr_partition(ctx, A, clamp_block_nnz(opts ? opts->block_nnz : 0));
+      st = build_csr_partition(ctx, A, clamp_block_nnz(opts ? opts->block_nnz : 0), opts);
     }
     if (st) break;
     int err = 0;
@@ -594,6 +620,8 @@ mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
                 : (A->fmt == MXS_COO || A->fmt == MXS_HYB) ? A->coo.nchunks
                                                            : (A->ell.stride / 64);
   out->block_nnz = A->fmt == MXS_CSR ? A->csr.block_nnz : A->coo.block_nnz;
+  out->lanes_per_row = A->fmt == MXS_CSR ? A->csr.lanes : 0;
+  out->rows_per_group = A->fmt == MXS_CSR ? A->csr.rpg : 0;
   out->bytes = A->bytes;
   return MXS_OK;
 }

@@ -72,26 +72,56 @@ bool pinned_reserve(mxs_ctx* ctx, size_t bytes) {
 // ---------------------------------------------------------------------------
 // HBM probe kernels: 16-byte accesses, grid-stride, 256 threads
 // ---------------------------------------------------------------------------
+// Each thread moves four 16-byte elements per iteration, all loads issued
+// before any use, so a wave keeps 4 KB in flight.
+constexpr int kProbeUnroll = 2;
+
 __global__ __launch_bounds__(256) void k_probe_read(const double2* __restrict__ a, int64_t n2,
                                                     double* __restrict__ sink) {
-  double s0 = 0.0, s1 = 0.0;
+  double s = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    const double2 v = a[i];
-    s0 += v.x;
-    s1 += v.y;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (kProbeUnroll - 1) * stride < n2; i += kProbeUnroll * stride) {
+    double2 v[kProbeUnroll];
+#pragma unroll
+    for (int u = 0; u < kProbeUnroll; ++u) v[u] = a[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < kProbeUnroll; ++u) s += v[u].x + v[u].y;
   }
-  double s = wave_sum(s0 + s1);
-  // keep the loads alive; the sink is a single slot written by whichever
-  // lane ends up with a value that is never exactly this sentinel
+  for (; i < n2; i += stride) s += a[i].x + a[i].y;
+  s = wave_sum(s);
+  // keeps the loads alive; never true for the fill values used here
   if (s == 1.2345e300) sink[0] = s;
+}
+
+// one 16-byte element per thread, no loop: the grid covers the array
+__global__ __launch_bounds__(256) void k_probe_read1(const double2* __restrict__ a, int64_t n2,
+                                                     double* __restrict__ sink) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < n2) s = a[i].x + a[i].y;
+  s = wave_sum(s);
+  if (s == 1.2345e300) sink[0] = s;
+}
+
+__global__ __launch_bounds__(256) void k_probe_copy1(const double2* __restrict__ a,
+                                                     double2* __restrict__ b, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n2) b[i] = a[i];
 }
 
 __global__ __launch_bounds__(256) void k_probe_copy(const double2* __restrict__ a,
                                                     double2* __restrict__ b, int64_t n2) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
-    b[i] = a[i];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (kProbeUnroll - 1) * stride < n2; i += kProbeUnroll * stride) {
+    double2 v[kProbeUnroll];
+#pragma unroll
+    for (int u = 0; u < kProbeUnroll; ++u) v[u] = a[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < kProbeUnroll; ++u) b[i + u * stride] = v[u];
+  }
+  for (; i < n2; i += stride) b[i] = a[i];
 }
 
 __global__ __launch_bounds__(256) void k_probe_triad(double2* __restrict__ a,
@@ -99,12 +129,26 @@ __global__ __launch_bounds__(256) void k_probe_triad(double2* __restrict__ a,
                                                      const double2* __restrict__ c, double s,
                                                      int64_t n2) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    const double2 bv = b[i];
-    const double2 cv = c[i];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (kProbeUnroll - 1) * stride < n2; i += kProbeUnroll * stride) {
+    double2 bv[kProbeUnroll], cv[kProbeUnroll];
+#pragma unroll
+    for (int u = 0; u < kProbeUnroll; ++u) {
+      bv[u] = b[i + u * stride];
+      cv[u] = c[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < kProbeUnroll; ++u) {
+      double2 r;
+      r.x = bv[u].x + s * cv[u].x;
+      r.y = bv[u].y + s * cv[u].y;
+      a[i + u * stride] = r;
+    }
+  }
+  for (; i < n2; i += stride) {
     double2 r;
-    r.x = bv.x + s * cv.x;
-    r.y = bv.y + s * cv.y;
+    r.x = b[i].x + s * c[i].x;
+    r.y = b[i].y + s * c[i].y;
     a[i] = r;
   }
 }
@@ -227,18 +271,24 @@ mxs_status mxs_hbm_probe(mxs_ctx* ctx, size_t bytes, int reps, mxs_bw_result* ou
     k_fill<<<grid, 256, 0, ctx->stream>>>(a, n2, 1.0);
     k_fill<<<grid, 256, 0, ctx->stream>>>(b, n2, 2.0);
     k_fill<<<grid, 256, 0, ctx->stream>>>(c, n2, 3.0);
+    // each kernel in two launch shapes (a grid-stride loop over 16 blocks
+    // per CU, and one element per thread); the faster one counts
+    const unsigned one_shot = (unsigned)((n2 + 255) / 256);
     float best[3] = {1e30f, 1e30f, 1e30f};
     for (int r = 0; r < reps + 1; ++r) {
-      for (int kk = 0; kk < 3; ++kk) {
+      for (int kk = 0; kk < 5; ++kk) {
         (void)hipEventRecord(e0, ctx->stream);
         if (kk == 0) k_probe_read<<<grid, 256, 0, ctx->stream>>>(a, n2, sink);
-        if (kk == 1) k_probe_copy<<<grid, 256, 0, ctx->stream>>>(a, b, n2);
-        if (kk == 2) k_probe_triad<<<grid, 256, 0, ctx->stream>>>(a, b, c, 0.5, n2);
+        if (kk == 1) k_probe_read1<<<one_shot, 256, 0, ctx->stream>>>(a, n2, sink);
+        if (kk == 2) k_probe_copy<<<grid, 256, 0, ctx->stream>>>(a, b, n2);
+        if (kk == 3) k_probe_copy1<<<one_shot, 256, 0, ctx->stream>>>(a, b, n2);
+        if (kk == 4) k_probe_triad<<<grid, 256, 0, ctx->stream>>>(a, b, c, 0.5, n2);
         (void)hipEventRecord(e1, ctx->stream);
         (void)hipEventSynchronize(e1);
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (r > 0 && ms < best[kk]) best[kk] = ms;  // first round is warm-up
+        const int slot = kk < 2 ? 0 : kk < 4 ? 1 : 2;
+        if (r > 0 && ms < best[slot]) best[slot] = ms;  // first round is warm-up
       }
     }
     hipError_t err = hipGetLastError();

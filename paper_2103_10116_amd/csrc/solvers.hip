@@ -25,8 +25,8 @@
 namespace mxs {
 namespace {
 
-constexpr int RB = 256;      // threads per reduction block
-constexpr int MAXG = 1024;   // reduction grid cap
+constexpr int RB = 512;      // threads per reduction block
+constexpr int MAXG = 512;    // reduction grid cap (partials per reduction)
 constexpr int MAXM = 32;     // largest GMRES restart length
 
 enum : int32_t {
@@ -38,14 +38,20 @@ enum : int32_t {
   ST_MAXIT = 5
 };
 
+// Device-resident solver state.  Within one kernel no field is written that
+// another block of the same launch reads, except the terminal status `done`
+// (every block reaches the same decision from the same partials, so an
+// early or late read of it is equivalent).  Scalars that change every
+// iteration and are read by the kernel that replaces them are kept in two
+// slots indexed by the iteration's parity.
 struct KState {
-  double rho, rho1, alpha, beta, omega, thr, res2, dot[2];
+  double rho[2];    // CG: r.r ; BiCGSTAB: r_hat.r (both by iteration parity)
+  double alpha, omega, thr, res2, dot[2], restart_rhr;
   int64_t iters, max_iters;
   int32_t done;     // one of the ST_* values; every kernel returns at once if set
   int32_t cycle;    // GMRES: 1 once the current cycle must end
   int32_t k;        // GMRES: Arnoldi steps taken in the current cycle
   int32_t m;        // GMRES restart length
-  uint32_t ticket[4];
   double est;       // GMRES residual estimate |g_{k}|
   double H[(MAXM + 1) * MAXM];  // column-major, leading dimension MAXM+1
   double cs[MAXM], sn[MAXM], g[MAXM + 1], y[MAXM], h2[MAXM + 1];
@@ -56,103 +62,120 @@ int red_grid(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, MAXG));
 }
 
-// Sums NV per-thread values over the grid.  Every block writes its NV
-// partials; the last block to arrive adds all partials in block order and
-// returns true with the totals in out[] (all its threads).
+// Sums NV per-thread values over the block with one barrier: every wave
+// reduces its values with butterflies, lane 0 stores them to LDS, and thread
+// v adds value v over the waves in wave order.  Result valid in thread v.
 template <int NV>
-__device__ bool grid_reduce(const double (&acc)[NV], double* __restrict__ partials,
-                            uint32_t* ticket, double (&out)[NV]) {
-  __shared__ double lds[RB / 64];
+__device__ __forceinline__ double block_sum_multi(const double (&acc)[NV], double (*lds)[NV]) {
+  const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(acc[i]);
+    if (lane == 0) lds[w][i] = s;
+  }
+  __syncthreads();
+  double s = 0.0;
+  if ((int)threadIdx.x < NV) {
+    s = lds[0][threadIdx.x];
+#pragma unroll
+    for (int q = 1; q < RB / 64; ++q) s += lds[q][threadIdx.x];
+  }
+  return s;
+}
+
+// Block partial sums of NV values to part[blockIdx.x * NV + v] (plain
+// stores: the consumer is a later kernel).
+template <int NV>
+__device__ __forceinline__ void block_partials(const double (&acc)[NV], double* __restrict__ part) {
+  __shared__ double lds[RB / 64][NV];
+  const double s = block_sum_multi<NV>(acc, lds);
+  if ((int)threadIdx.x < NV) part[(int64_t)blockIdx.x * NV + threadIdx.x] = s;
+}
+
+// Adds the `g` block partials of NV values written by an earlier kernel, in
+// block order; every thread of every calling block gets the same totals.
+template <int NV>
+__device__ __forceinline__ void finish(const double* __restrict__ part, int g, double (&out)[NV]) {
+  __shared__ double lds[RB / 64][NV];
   __shared__ double res[NV];
-  __shared__ int is_last;
+  // g <= MAXG == RB: thread b holds block b's partials; all NV loads are
+  // issued before any is used
+  static_assert(MAXG <= RB, "one partial row per thread");
+  double acc[NV];
+  const bool has = (int)threadIdx.x < g;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const double s = block_sum<double, RB>(acc[v], lds);
-    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * NV + v] = s;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += RB)
-      s += __builtin_nontemporal_load(&partials[(int64_t)b * NV + v]);
-    s = block_sum<double, RB>(s, lds);
-    if (threadIdx.x == 0) res[v] = s;
-  }
-  if (threadIdx.x == 0) *ticket = 0u;
+  for (int v = 0; v < NV; ++v) acc[v] = has ? part[(int64_t)threadIdx.x * NV + v] : 0.0;
+  const double s = block_sum_multi<NV>(acc, lds);
+  if ((int)threadIdx.x < NV) res[threadIdx.x] = s;
   __syncthreads();
 #pragma unroll
   for (int v = 0; v < NV; ++v) out[v] = res[v];
-  return true;
 }
 
-#define GRID_STRIDE(i, n)                                                        \
-  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < (n); \
-       i += (int64_t)gridDim.x * RB)
+__device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < (n); i += (int64_t)gridDim.x * RB)
 
 // ---------------------------------------------------------------------------
-// generic kernels
+// generic reductions
 // ---------------------------------------------------------------------------
-// dot[0] = a.b, dot[1] = c.d (c may be NULL)
+// partials of a.b and c.d (c may be NULL)
 template <typename T>
 __global__ __launch_bounds__(RB) void k_dots(int64_t n, const T* __restrict__ a,
                                              const T* __restrict__ b, const T* __restrict__ c,
-                                             const T* __restrict__ d, double* partials,
-                                             KState* st) {
+                                             const T* __restrict__ d, double* part) {
   double acc[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
     acc[0] += (double)a[i] * (double)b[i];
     if (c) acc[1] += (double)c[i] * (double)d[i];
   }
+  block_partials<2>(acc, part);
+}
+
+__global__ __launch_bounds__(RB) void k_dots_fin(const double* part, int g, KState* st) {
   double out[2];
-  if (grid_reduce<2>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
+  finish<2>(part, g, out);
+  if (threadIdx.x == 0) {
     st->dot[0] = out[0];
     st->dot[1] = out[1];
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(RB) void k_copy(int64_t n, const T* __restrict__ a,
-                                             T* __restrict__ b) {
-  GRID_STRIDE(i, n) b[i] = a[i];
-}
-
 // ---------------------------------------------------------------------------
-// CG (Hestenes-Stiefel)
+// CG (Hestenes-Stiefel).  Iteration k (parity par = k & 1):
+//   q = A p;  k_cg_pq: partials of p.q;
+//   k_cg_update: alpha = rho[par] / (p.q), x += alpha p, r -= alpha q,
+//                partials of r.r;
+//   k_cg_direction: rho' = r.r, stopping test, beta = rho'/rho[par],
+//                p = r + beta p, rho[1-par] = rho'.
 // ---------------------------------------------------------------------------
-// alpha = rho / (p.q)
 template <typename T>
-__global__ __launch_bounds__(RB) void k_cg_alpha(int64_t n, const T* __restrict__ p,
-                                                 const T* __restrict__ q, double* partials,
-                                                 KState* st) {
+__global__ __launch_bounds__(RB) void k_cg_pq(int64_t n, const T* __restrict__ p,
+                                              const T* __restrict__ q, double* __restrict__ pa,
+                                              const KState* st) {
   if (st->done) return;
   double acc[1] = {0.0};
   GRID_STRIDE(i, n) acc[0] += (double)p[i] * (double)q[i];
-  double out[1];
-  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
-    const double pq = out[0];
-    if (!isfinite(pq))
-      st->done = ST_NONFINITE;
-    else if (pq <= 0.0)
-      st->done = ST_BREAKDOWN;
-    else
-      st->alpha = st->rho / pq;
-  }
+  block_partials<1>(acc, pa);
 }
 
-// x += alpha p; r -= alpha q; rho' = r.r; beta = rho'/rho; stopping test
 template <typename T>
 __global__ __launch_bounds__(RB) void k_cg_update(int64_t n, T* __restrict__ x,
                                                   const T* __restrict__ p, T* __restrict__ r,
-                                                  const T* __restrict__ q, double* partials,
-                                                  KState* st) {
+                                                  const T* __restrict__ q,
+                                                  const double* __restrict__ pa, int g,
+                                                  double* __restrict__ pb, KState* st, int par) {
   if (st->done) return;
-  const T a = (T)st->alpha;
+  double pq[1];
+  finish<1>(pa, g, pq);
+  if (!isfinite(pq[0]) || pq[0] <= 0.0) {
+    if (lead()) st->done = isfinite(pq[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+    return;
+  }
+  const double alpha = st->rho[par] / pq[0];
+  if (lead()) st->alpha = alpha;
+  const T a = (T)alpha;
   double acc[1] = {0.0};
   GRID_STRIDE(i, n) {
     x[i] += a * p[i];
@@ -160,84 +183,172 @@ __global__ __launch_bounds__(RB) void k_cg_update(int64_t n, T* __restrict__ x,
     r[i] = ri;
     acc[0] += (double)ri * (double)ri;
   }
-  double out[1];
-  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
-    const double rn = out[0];
-    st->iters += 1;
-    st->res2 = rn;
-    if (!isfinite(rn)) {
-      st->done = ST_NONFINITE;
-    } else {
-      st->beta = rn / st->rho;
-      st->rho = rn;
-      if (sqrt(rn) <= st->thr)
-        st->done = ST_CONVERGED;
-      else if (st->iters >= st->max_iters)
-        st->done = ST_MAXIT;
-    }
-  }
+  block_partials<1>(acc, pb);
 }
 
 template <typename T>
 __global__ __launch_bounds__(RB) void k_cg_direction(int64_t n, const T* __restrict__ r,
-                                                     T* __restrict__ p, const KState* st) {
+                                                     T* __restrict__ p,
+                                                     const double* __restrict__ pb, int g,
+                                                     KState* st, int par, int64_t k) {
   if (st->done) return;
-  const T b = (T)st->beta;
-  GRID_STRIDE(i, n) p[i] = r[i] + b * p[i];
+  double rr[1];
+  finish<1>(pb, g, rr);
+  const double rn = rr[0];
+  const bool bad = !isfinite(rn);
+  const bool conv = !bad && sqrt(rn) <= st->thr;
+  const bool maxit = k + 1 >= st->max_iters;
+  if (lead()) {
+    st->iters = k + 1;
+    st->res2 = rn;
+    st->rho[1 - par] = rn;
+    if (bad)
+      st->done = ST_NONFINITE;
+    else if (conv)
+      st->done = ST_CONVERGED;
+    else if (maxit)
+      st->done = ST_MAXIT;
+  }
+  if (bad || conv || maxit) return;
+  const T beta = (T)(rn / st->rho[par]);
+  GRID_STRIDE(i, n) p[i] = r[i] + beta * p[i];
 }
 
 // ---------------------------------------------------------------------------
-// BiCGSTAB (r_hat = r0)
+// BiCGSTAB (r_hat = r0).  Iteration k (par = k & 1), rho[par] = previous
+// r_hat.r, rho[1-par] = current one:
+//   k_bi_p: (from the last update's partials) stopping test on ||r||,
+//           beta = (rho'/rho)(alpha/omega), p = r + beta (p - omega v)
+//   v = A p;  k_bi_rv: partials of r_hat.v
+//   k_bi_s: alpha = rho' / (r_hat.v), s = r - alpha v, partials of s.s
+//   t = A s;  k_bi_omega: ||s|| test (half step), partials of t.s, t.t
+//   k_bi_update: omega, x += alpha p + omega s, r = s - omega t,
+//                partials of r.r and r_hat.r
 // ---------------------------------------------------------------------------
-// p = r + beta (p - omega v)
 __global__ __launch_bounds__(RB) void k_bi_p(int64_t n, const double* __restrict__ r,
                                              double* __restrict__ p,
-                                             const double* __restrict__ v, const KState* st) {
+                                             const double* __restrict__ v,
+                                             const double* __restrict__ pc, int g, KState* st,
+                                             int par, int64_t k, int first) {
   if (st->done) return;
-  const double b = st->beta, w = st->omega;
-  GRID_STRIDE(i, n) p[i] = r[i] + b * (p[i] - w * v[i]);
+  double rr_rhr[2];
+  if (first) {
+    rr_rhr[0] = st->res2;
+    rr_rhr[1] = st->restart_rhr;
+  } else {
+    finish<2>(pc, g, rr_rhr);
+  }
+  const double rn = rr_rhr[0], rhr = rr_rhr[1];
+  const double w = st->omega, a = st->alpha;
+  int32_t verdict = RUN;
+  if (!isfinite(rn) || !isfinite(rhr))
+    verdict = ST_NONFINITE;
+  else if (sqrt(rn) <= st->thr)
+    verdict = ST_CONVERGED;
+  else if (k >= st->max_iters)
+    verdict = ST_MAXIT;
+  else if (rhr == 0.0 || w == 0.0)
+    verdict = ST_BREAKDOWN;
+  if (lead()) {
+    st->res2 = rn;
+    st->rho[1 - par] = rhr;
+    if (verdict != RUN) st->done = verdict;
+  }
+  if (verdict != RUN) return;
+  const double beta = (rhr / st->rho[par]) * (a / w);
+  GRID_STRIDE(i, n) p[i] = r[i] + beta * (p[i] - w * v[i]);
 }
 
-// alpha = rho1 / (r_hat . v)
-__global__ __launch_bounds__(RB) void k_bi_alpha(int64_t n, const double* __restrict__ rh,
-                                                 const double* __restrict__ v,
-                                                 double* partials, KState* st) {
+__global__ __launch_bounds__(RB) void k_bi_rv(int64_t n, const double* __restrict__ rh,
+                                              const double* __restrict__ v,
+                                              double* __restrict__ pa, const KState* st) {
   if (st->done) return;
   double acc[1] = {0.0};
   GRID_STRIDE(i, n) acc[0] += rh[i] * v[i];
-  double out[1];
-  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
-    if (!isfinite(out[0]))
-      st->done = ST_NONFINITE;
-    else if (out[0] == 0.0)
-      st->done = ST_BREAKDOWN;
-    else
-      st->alpha = st->rho1 / out[0];
-  }
+  block_partials<1>(acc, pa);
 }
 
-// s = r - alpha v; ||s|| test (a met tolerance leaves x += alpha p pending)
 __global__ __launch_bounds__(RB) void k_bi_s(int64_t n, const double* __restrict__ r,
                                              const double* __restrict__ v,
-                                             double* __restrict__ s, double* partials,
-                                             KState* st) {
+                                             double* __restrict__ s,
+                                             const double* __restrict__ pa, int g,
+                                             double* __restrict__ pb, KState* st, int par) {
   if (st->done) return;
-  const double a = st->alpha;
+  double rv[1];
+  finish<1>(pa, g, rv);
+  if (!isfinite(rv[0]) || rv[0] == 0.0) {
+    if (lead()) st->done = isfinite(rv[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+    return;
+  }
+  const double a = st->rho[1 - par] / rv[0];
+  if (lead()) st->alpha = a;
   double acc[1] = {0.0};
   GRID_STRIDE(i, n) {
     const double si = r[i] - a * v[i];
     s[i] = si;
     acc[0] += si * si;
   }
-  double out[1];
-  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
-    st->iters += 1;
-    st->res2 = out[0];
-    if (!isfinite(out[0]))
-      st->done = ST_NONFINITE;
-    else if (sqrt(out[0]) <= st->thr)
-      st->done = ST_HALF;
+  block_partials<1>(acc, pb);
+}
+
+__global__ __launch_bounds__(RB) void k_bi_omega(int64_t n, const double* __restrict__ t,
+                                                 const double* __restrict__ s,
+                                                 const double* __restrict__ pb, int g,
+                                                 double* __restrict__ pd, KState* st, int64_t k) {
+  if (st->done) return;
+  double ss[1];
+  finish<1>(pb, g, ss);
+  if (!isfinite(ss[0])) {
+    if (lead()) st->done = ST_NONFINITE;
+    return;
   }
+  if (sqrt(ss[0]) <= st->thr) {
+    if (lead()) {
+      st->res2 = ss[0];
+      st->iters = k + 1;
+      st->done = ST_HALF;
+    }
+    return;
+  }
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    acc[0] += t[i] * s[i];
+    acc[1] += t[i] * t[i];
+  }
+  block_partials<2>(acc, pd);
+}
+
+__global__ __launch_bounds__(RB) void k_bi_update(int64_t n, double* __restrict__ x,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ s,
+                                                  const double* __restrict__ t,
+                                                  double* __restrict__ r,
+                                                  const double* __restrict__ rh,
+                                                  const double* __restrict__ pd, int g,
+                                                  double* __restrict__ pc, KState* st,
+                                                  int64_t k) {
+  if (st->done) return;
+  double tstt[2];
+  finish<2>(pd, g, tstt);
+  if (!isfinite(tstt[0]) || !isfinite(tstt[1]) || tstt[1] == 0.0) {
+    if (lead()) st->done = tstt[1] == 0.0 ? ST_BREAKDOWN : ST_NONFINITE;
+    return;
+  }
+  const double w = tstt[0] / tstt[1];
+  const double a = st->alpha;
+  if (lead()) {
+    st->omega = w;
+    st->iters = k + 1;
+  }
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    x[i] = x[i] + a * p[i] + w * s[i];
+    const double ri = s[i] - w * t[i];
+    r[i] = ri;
+    acc[0] += ri * ri;
+    acc[1] += rh[i] * ri;
+  }
+  block_partials<2>(acc, pc);
 }
 
 // the half step x += alpha p, launched once by the host after it read
@@ -250,95 +361,40 @@ __global__ __launch_bounds__(RB) void k_bi_half(int64_t n, double* __restrict__ 
   GRID_STRIDE(i, n) x[i] += a * p[i];
 }
 
-// omega = (t.s)/(t.t)
-__global__ __launch_bounds__(RB) void k_bi_omega(int64_t n, const double* __restrict__ t,
-                                                 const double* __restrict__ s,
-                                                 double* partials, KState* st) {
-  if (st->done) return;
-  double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    acc[0] += t[i] * s[i];
-    acc[1] += t[i] * t[i];
-  }
-  double out[2];
-  if (grid_reduce<2>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
-    if (!isfinite(out[0]) || !isfinite(out[1]))
-      st->done = ST_NONFINITE;
-    else if (out[1] == 0.0)
-      st->done = ST_BREAKDOWN;
-    else
-      st->omega = out[0] / out[1];
-  }
-}
-
-// x += alpha p + omega s; r = s - omega t; ||r|| test; rho1' = r_hat.r and
-// beta for the next iteration
-__global__ __launch_bounds__(RB) void k_bi_update(int64_t n, double* __restrict__ x,
-                                                  const double* __restrict__ p,
-                                                  const double* __restrict__ s,
-                                                  const double* __restrict__ t,
-                                                  double* __restrict__ r,
-                                                  const double* __restrict__ rh,
-                                                  double* partials, KState* st) {
-  if (st->done) return;
-  const double a = st->alpha, w = st->omega;
-  double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    x[i] = x[i] + a * p[i] + w * s[i];
-    const double ri = s[i] - w * t[i];
-    r[i] = ri;
-    acc[0] += ri * ri;
-    acc[1] += rh[i] * ri;
-  }
-  double out[2];
-  if (grid_reduce<2>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
-    st->res2 = out[0];
-    if (!isfinite(out[0]) || !isfinite(out[1])) {
-      st->done = ST_NONFINITE;
-    } else if (sqrt(out[0]) <= st->thr) {
-      st->done = ST_CONVERGED;
-    } else if (st->iters >= st->max_iters) {
-      st->done = ST_MAXIT;
-    } else if (out[1] == 0.0 || w == 0.0) {
-      st->done = ST_BREAKDOWN;
-    } else {
-      st->beta = (out[1] / st->rho1) * (a / w);
-      st->rho1 = out[1];
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// GMRES(m): classical Gram-Schmidt with one reorthogonalisation pass
+// GMRES(m): classical Gram-Schmidt with one reorthogonalisation pass.  The
+// multi-dot partials of (j+1) values per block are finished by a one-block
+// kernel that also owns the small dense work (Hessenberg column, Givens).
 // ---------------------------------------------------------------------------
-// h(0..j) = V(:,0..j)^T w  (first pass)
+// partials of V(:,0..j)^T w
 __global__ __launch_bounds__(RB) void k_gm_dots(int64_t n, int64_t ldv, int j,
                                                 const double* __restrict__ V,
                                                 const double* __restrict__ w,
-                                                double* partials, KState* st) {
+                                                double* __restrict__ part, const KState* st) {
   if (st->done || st->cycle) return;
   double acc[MAXM];
 #pragma unroll
   for (int i = 0; i < MAXM; ++i) acc[i] = 0.0;
   GRID_STRIDE(r, n) {
     const double wr = w[r];
+    double vr[MAXM];
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i <= j) acc[i] += V[i * ldv + r] * wr;
+    for (int i = 0; i < MAXM; ++i) vr[i] = i <= j ? V[i * ldv + r] : 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) acc[i] += vr[i] * wr;
   }
-  double out[MAXM];
-  if (grid_reduce<MAXM>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0)
-    for (int i = 0; i <= j; ++i) st->H[j * (MAXM + 1) + i] = out[i];
+  block_partials<MAXM>(acc, part);
 }
 
-// w -= V h (h from the first pass); then h2 = V^T w on the updated rows
+// w -= V h (first-pass coefficients); partials of V^T w on the updated rows
 __global__ __launch_bounds__(RB) void k_gm_orth(int64_t n, int64_t ldv, int j,
                                                 const double* __restrict__ V,
-                                                double* __restrict__ w, double* partials,
-                                                KState* st) {
+                                                double* __restrict__ w,
+                                                double* __restrict__ part, const KState* st) {
   if (st->done || st->cycle) return;
   __shared__ double h[MAXM];
-  if (threadIdx.x < MAXM) h[threadIdx.x] = threadIdx.x <= j ? st->H[j * (MAXM + 1) + threadIdx.x] : 0.0;
+  if (threadIdx.x < MAXM)
+    h[threadIdx.x] = (int)threadIdx.x <= j ? st->H[j * (MAXM + 1) + threadIdx.x] : 0.0;
   __syncthreads();
   double acc[MAXM];
 #pragma unroll
@@ -355,66 +411,86 @@ __global__ __launch_bounds__(RB) void k_gm_orth(int64_t n, int64_t ldv, int j,
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) acc[i] += vr[i] * wr;
   }
-  double out[MAXM];
-  if (grid_reduce<MAXM>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0)
-    for (int i = 0; i <= j; ++i) {
-      st->h2[i] = out[i];
-      st->H[j * (MAXM + 1) + i] += out[i];
-    }
+  block_partials<MAXM>(acc, part);
 }
 
-// w -= V h2; h_{j+1,j} = ||w||; Givens rotations; residual estimate
+// w -= V h2; partials of w.w
 __global__ __launch_bounds__(RB) void k_gm_norm(int64_t n, int64_t ldv, int j,
                                                 const double* __restrict__ V,
-                                                double* __restrict__ w, double* partials,
-                                                KState* st) {
+                                                double* __restrict__ w,
+                                                double* __restrict__ part, const KState* st) {
   if (st->done || st->cycle) return;
   __shared__ double h[MAXM];
-  if (threadIdx.x < MAXM) h[threadIdx.x] = threadIdx.x <= j ? st->h2[threadIdx.x] : 0.0;
+  if (threadIdx.x < MAXM) h[threadIdx.x] = (int)threadIdx.x <= j ? st->h2[threadIdx.x] : 0.0;
   __syncthreads();
   double acc[1] = {0.0};
   GRID_STRIDE(r, n) {
+    double vr[MAXM];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) vr[i] = i <= j ? V[i * ldv + r] : 0.0;
     double wr = w[r];
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i <= j) wr -= h[i] * V[i * ldv + r];
+    for (int i = 0; i < MAXM; ++i) wr -= h[i] * vr[i];
     w[r] = wr;
     acc[0] += wr * wr;
   }
-  double out[1];
-  if (grid_reduce<1>(acc, partials, &st->ticket[0], out) && threadIdx.x == 0) {
-    const int L = MAXM + 1;
-    double* Hj = st->H + j * L;
-    const double hn = sqrt(out[0]);
-    st->iters += 1;
-    if (!isfinite(hn)) {
-      st->done = ST_NONFINITE;
-      return;
-    }
-    Hj[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-      const double a = Hj[i], c = Hj[i + 1];
-      Hj[i] = st->cs[i] * a + st->sn[i] * c;
-      Hj[i + 1] = -st->sn[i] * a + st->cs[i] * c;
-    }
-    const double a = Hj[j], c = Hj[j + 1];
-    const double d = sqrt(a * a + c * c);
-    if (d == 0.0) {
-      st->done = ST_BREAKDOWN;
-      return;
-    }
-    st->cs[j] = a / d;
-    st->sn[j] = c / d;
-    Hj[j] = d;
-    Hj[j + 1] = 0.0;
-    st->g[j + 1] = -st->sn[j] * st->g[j];
-    st->g[j] = st->cs[j] * st->g[j];
-    st->k = j + 1;
-    st->est = fabs(st->g[j + 1]);
-    st->res2 = hn;  // h_{j+1,j} for the scaling kernel
-    if (st->est <= st->thr || hn == 0.0 || st->iters >= st->max_iters || j + 1 >= st->m)
-      st->cycle = 1;
+  block_partials<1>(acc, part);
+}
+
+// One block.  stage 1: H(:,j) = first-pass coefficients; stage 2: second
+// pass h2 added to H(:,j); stage 3: h_{j+1,j} = ||w||, Givens rotations,
+// residual estimate, end-of-cycle test.
+__global__ __launch_bounds__(RB) void k_gm_fin(const double* __restrict__ part, int g, int j,
+                                               int stage, KState* st) {
+  if (st->done || st->cycle) return;
+  const int L = MAXM + 1;
+  double* Hj = st->H + j * L;
+  if (stage < 3) {
+    double out[MAXM];
+    finish<MAXM>(part, g, out);
+    if (threadIdx.x == 0)
+      for (int i = 0; i <= j; ++i) {
+        if (stage == 1) {
+          Hj[i] = out[i];
+        } else {
+          st->h2[i] = out[i];
+          Hj[i] += out[i];
+        }
+      }
+    return;
   }
+  double ww[1];
+  finish<1>(part, g, ww);
+  if (threadIdx.x != 0) return;
+  const double hn = sqrt(ww[0]);
+  st->iters += 1;
+  if (!isfinite(hn)) {
+    st->done = ST_NONFINITE;
+    return;
+  }
+  Hj[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = Hj[i], c = Hj[i + 1];
+    Hj[i] = st->cs[i] * a + st->sn[i] * c;
+    Hj[i + 1] = -st->sn[i] * a + st->cs[i] * c;
+  }
+  const double a = Hj[j], c = Hj[j + 1];
+  const double d = sqrt(a * a + c * c);
+  if (d == 0.0) {
+    st->done = ST_BREAKDOWN;
+    return;
+  }
+  st->cs[j] = a / d;
+  st->sn[j] = c / d;
+  Hj[j] = d;
+  Hj[j + 1] = 0.0;
+  st->g[j + 1] = -st->sn[j] * st->g[j];
+  st->g[j] = st->cs[j] * st->g[j];
+  st->k = j + 1;
+  st->est = fabs(st->g[j + 1]);
+  st->res2 = hn;  // h_{j+1,j} for the scaling kernel
+  if (st->est <= st->thr || hn == 0.0 || st->iters >= st->max_iters || j + 1 >= st->m)
+    st->cycle = 1;
 }
 
 // v_{j+1} = w / h_{j+1,j}
@@ -443,7 +519,7 @@ __global__ __launch_bounds__(RB) void k_gm_xupdate(int64_t n, int64_t ldv,
   if (st->done) return;
   __shared__ double y[MAXM];
   const int k = st->k;
-  if (threadIdx.x < MAXM) y[threadIdx.x] = threadIdx.x < k ? st->y[threadIdx.x] : 0.0;
+  if (threadIdx.x < MAXM) y[threadIdx.x] = (int)threadIdx.x < k ? st->y[threadIdx.x] : 0.0;
   __syncthreads();
   GRID_STRIDE(r, n) {
     double xr = x[r];
@@ -454,18 +530,20 @@ __global__ __launch_bounds__(RB) void k_gm_xupdate(int64_t n, int64_t ldv,
   }
 }
 
-// v_0 = r / beta; g = beta e_1; new cycle (beta = sqrt(dot[0]))
-__global__ __launch_bounds__(RB) void k_gm_start(int64_t n, const double* __restrict__ r,
-                                                 double* __restrict__ v0, KState* st) {
+// v_0 = r / beta with beta = sqrt(dot[0]); the one-block kernel below
+// resets the cycle state first
+__global__ void k_gm_reset(KState* st) {
   const double beta = sqrt(st->dot[0]);
-  const double inv = 1.0 / beta;
+  for (int i = 0; i <= MAXM; ++i) st->g[i] = 0.0;
+  st->g[0] = beta;
+  st->k = 0;
+  st->cycle = 0;
+}
+
+__global__ __launch_bounds__(RB) void k_gm_start(int64_t n, const double* __restrict__ r,
+                                                 double* __restrict__ v0, const KState* st) {
+  const double inv = 1.0 / st->g[0];
   GRID_STRIDE(i, n) v0[i] = r[i] * inv;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    for (int i = 0; i <= MAXM; ++i) st->g[i] = 0.0;
-    st->g[0] = beta;
-    st->k = 0;
-    st->cycle = 0;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -489,7 +567,11 @@ __global__ __launch_bounds__(RB) void k_ir_update(int64_t n, double* __restrict_
 struct Work {
   KState* st;        // device
   KState* hst;       // pinned mirror
-  double* partials;  // MAXG * MAXM doubles
+  double* pa;        // four partial buffers of MAXG * 2 doubles
+  double* pb;
+  double* pc;
+  double* pd;
+  double* pm;        // MAXG * MAXM doubles (GMRES multi-dots)
   char* vec;         // vectors
 };
 
@@ -497,16 +579,20 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 mxs_status get_work(mxs_ctx* ctx, size_t vec_bytes, Work* w) {
   const size_t st_bytes = align_up(sizeof(KState), 256);
-  const size_t part_bytes = (size_t)MAXG * MAXM * sizeof(double);
-  if (!ws_reserve(ctx, st_bytes + part_bytes + vec_bytes + 256))
-    return fail(ctx, MXS_OOM, "solver workspace of %zu bytes", st_bytes + part_bytes + vec_bytes);
+  const size_t p2 = (size_t)MAXG * 2 * sizeof(double);
+  const size_t pm = (size_t)MAXG * MAXM * sizeof(double);
+  const size_t total = st_bytes + 4 * p2 + pm + vec_bytes + 256;
+  if (!ws_reserve(ctx, total)) return fail(ctx, MXS_OOM, "solver workspace of %zu bytes", total);
   if (!pinned_reserve(ctx, st_bytes)) return fail(ctx, MXS_OOM, "pinned state mirror");
   char* base = (char*)ctx->ws.ptr;
   w->st = (KState*)base;
-  w->partials = (double*)(base + st_bytes);
-  w->vec = base + st_bytes + part_bytes;
+  w->pa = (double*)(base + st_bytes);
+  w->pb = (double*)(base + st_bytes + p2);
+  w->pc = (double*)(base + st_bytes + 2 * p2);
+  w->pd = (double*)(base + st_bytes + 3 * p2);
+  w->pm = (double*)(base + st_bytes + 4 * p2);
+  w->vec = base + st_bytes + 4 * p2 + pm;
   w->hst = (KState*)ctx->pinned;
-  // zero the device state: its reduction tickets must start at 0
   MXS_HIP_TRY(ctx, hipMemsetAsync(w->st, 0, sizeof(KState), ctx->stream));
   return MXS_OK;
 }
@@ -526,11 +612,20 @@ mxs_status pull_state(mxs_ctx* ctx, Work& w) {
   return MXS_OK;
 }
 
+// enqueues a.b (and c.d) into st->dot without synchronising
+template <typename T>
+void enqueue_dots(mxs_ctx* ctx, Work& w, int64_t n, const T* a, const T* b, const T* c,
+                  const T* d) {
+  const int g = red_grid(n);
+  k_dots<T><<<g, RB, 0, ctx->stream>>>(n, a, b, c, d, w.pa);
+  k_dots_fin<<<1, RB, 0, ctx->stream>>>(w.pa, g, w.st);
+}
+
 // dot products of device vectors into the host mirror (synchronising)
 template <typename T>
 mxs_status dots(mxs_ctx* ctx, Work& w, int64_t n, const T* a, const T* b, const T* c,
                 const T* d, double* out0, double* out1) {
-  k_dots<T><<<red_grid(n), RB, 0, ctx->stream>>>(n, a, b, c, d, w.partials, w.st);
+  enqueue_dots<T>(ctx, w, n, a, b, c, d);
   MXS_HIP_TRY(ctx, hipGetLastError());
   MXS_HIP_TRY(ctx, hipMemcpyAsync(w.hst->dot, w.st->dot, 2 * sizeof(double),
                                   hipMemcpyDeviceToHost, ctx->stream));
@@ -586,22 +681,24 @@ mxs_status cg_loop(mxs_ctx* ctx, const mxs_matrix* A, Work& w, T* x, T* r, T* p,
   const int64_t n = A->n;
   const int g = red_grid(n);
   const T one = 1, zero = 0;
-  int64_t before = -1;
+  int64_t k = w.hst->iters;
   for (;;) {
-    for (int it = 0; it < check_every; ++it) {
+    const int64_t before = k;
+    for (int it = 0; it < check_every; ++it, ++k) {
+      const int par = (int)(k & 1);
       mxs_status s = launch_spmv(ctx, A, &one, p, &zero, q, &w.st->done);
       if (s) return s;
-      k_cg_alpha<T><<<g, RB, 0, ctx->stream>>>(n, p, q, w.partials, w.st);
-      k_cg_update<T><<<g, RB, 0, ctx->stream>>>(n, x, p, r, q, w.partials, w.st);
-      k_cg_direction<T><<<g, RB, 0, ctx->stream>>>(n, r, p, w.st);
+      k_cg_pq<T><<<g, RB, 0, ctx->stream>>>(n, p, q, w.pa, w.st);
+      k_cg_update<T><<<g, RB, 0, ctx->stream>>>(n, x, p, r, q, w.pa, g, w.pb, w.st, par);
+      k_cg_direction<T><<<g, RB, 0, ctx->stream>>>(n, r, p, w.pb, g, w.st, par, k);
     }
     MXS_HIP_TRY(ctx, hipGetLastError());
     mxs_status s = pull_state(ctx, w);
     if (s) return s;
     if (w.hst->done) return MXS_OK;
-    if (w.hst->iters == before)
+    if (w.hst->iters <= before)
       return fail(ctx, MXS_HIP, "CG made no progress (device state not updated)");
-    before = w.hst->iters;
+    k = w.hst->iters;
   }
 }
 
@@ -614,6 +711,14 @@ void fill_info(mxs_solve_info* info, const KState& h, double base, double relres
   info->replacements = repl;
   info->restarts = restarts;
   info->status = st;
+}
+
+mxs_status zero_solution(mxs_ctx* ctx, double* x, int64_t n, mxs_solve_info* info) {
+  MXS_HIP_TRY(ctx, hipMemsetAsync(x, 0, n * sizeof(double), ctx->stream));
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  KState z{};
+  fill_info(info, z, 1.0, 0.0, 0, 0, MXS_OK);
+  return MXS_OK;
 }
 
 mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
@@ -631,19 +736,13 @@ mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* 
   if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
   const double nb = sqrt(nb2), nr0 = sqrt(nr2);
   if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
-  if (nb == 0.0) {
-    MXS_HIP_TRY(ctx, hipMemsetAsync(x, 0, n * sizeof(double), ctx->stream));
-    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    KState z{};
-    fill_info(info, z, 1.0, 0.0, 0, 0, MXS_OK);
-    return MXS_OK;
-  }
+  if (nb == 0.0) return zero_solution(ctx, x, n, info);
   if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
   const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
   const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
   KState& h = *w.hst;
   std::memset(&h, 0, sizeof(KState));
-  h.rho = nr2;
+  h.rho[0] = nr2;
   h.res2 = nr2;
   h.thr = thr;
   h.max_iters = stop.max_iters;
@@ -682,7 +781,7 @@ mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* 
     }
     // residual replacement: r = b - A x (already in r), restart p = r
     repl++;
-    h.rho = rt2;
+    h.rho[h.iters & 1] = rt2;
     h.res2 = rt2;
     h.done = RUN;
     if ((s = push_state(ctx, w))) return s;
@@ -709,13 +808,7 @@ mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, do
   if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
   const double nb = sqrt(nb2), nr0 = sqrt(nr2);
   if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
-  if (nb == 0.0) {
-    MXS_HIP_TRY(ctx, hipMemsetAsync(x, 0, n * sizeof(double), ctx->stream));
-    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    KState z{};
-    fill_info(info, z, 1.0, 0.0, 0, 0, MXS_OK);
-    return MXS_OK;
-  }
+  if (nb == 0.0) return zero_solution(ctx, x, n, info);
   if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
   const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
   const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
@@ -725,47 +818,49 @@ mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, do
   std::memset(&h, 0, sizeof(KState));
   int64_t repl = 0;
   double relres_true = nr0 / base;
-  bool restart = true;
   int32_t done = nr0 <= thr ? ST_CONVERGED : RUN;
   int64_t iters = 0;
   double rr = nr2;
   for (;;) {
-    if (done == RUN && restart) {
-      // r_hat = r, p = v = 0, rho = alpha = omega = 1; first beta = rho1
+    if (done == RUN) {
+      // (re)start: r_hat = r, p = v = 0, rho = alpha = omega = 1
       MXS_HIP_TRY(ctx, hipMemcpyAsync(rh, r, n * sizeof(double), hipMemcpyDeviceToDevice,
                                       ctx->stream));
       MXS_HIP_TRY(ctx, hipMemsetAsync(p, 0, n * sizeof(double), ctx->stream));
       MXS_HIP_TRY(ctx, hipMemsetAsync(v, 0, n * sizeof(double), ctx->stream));
       std::memset(&h, 0, sizeof(KState));
-      h.rho1 = rr;
+      h.rho[iters & 1] = 1.0;
       h.alpha = 1.0;
       h.omega = 1.0;
-      h.beta = rr;  // (rho1 / 1) * (1 / 1)
+      h.restart_rhr = rr;  // r_hat . r = r . r
       h.res2 = rr;
       h.thr = thr;
       h.iters = iters;
       h.max_iters = stop.max_iters;
-      h.done = rr == 0.0 ? ST_BREAKDOWN : RUN;
       if ((s = push_state(ctx, w))) return s;
-      restart = false;
     }
+    bool first = true;
+    int64_t k = iters;
     while (done == RUN) {
-      for (int it = 0; it < stop.check_every; ++it) {
-        k_bi_p<<<g, RB, 0, ctx->stream>>>(n, r, p, v, w.st);
+      for (int it = 0; it < stop.check_every; ++it, ++k) {
+        const int par = (int)(k & 1);
+        k_bi_p<<<g, RB, 0, ctx->stream>>>(n, r, p, v, w.pc, g, w.st, par, k, first ? 1 : 0);
+        first = false;
         if ((s = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return s;
-        k_bi_alpha<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.partials, w.st);
-        k_bi_s<<<g, RB, 0, ctx->stream>>>(n, r, v, sv, w.partials, w.st);
+        k_bi_rv<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
+        k_bi_s<<<g, RB, 0, ctx->stream>>>(n, r, v, sv, w.pa, g, w.pb, w.st, par);
         if ((s = launch_spmv(ctx, A, &one, sv, &zero, t, &w.st->done))) return s;
-        k_bi_omega<<<g, RB, 0, ctx->stream>>>(n, t, sv, w.partials, w.st);
-        k_bi_update<<<g, RB, 0, ctx->stream>>>(n, x, p, sv, t, r, rh, w.partials, w.st);
+        k_bi_omega<<<g, RB, 0, ctx->stream>>>(n, t, sv, w.pb, g, w.pd, w.st, k);
+        k_bi_update<<<g, RB, 0, ctx->stream>>>(n, x, p, sv, t, r, rh, w.pd, g, w.pc, w.st, k);
       }
       MXS_HIP_TRY(ctx, hipGetLastError());
       const int64_t before = iters;
       if ((s = pull_state(ctx, w))) return s;
       done = h.done;
       iters = h.iters;
-      if (done == RUN && iters == before)
+      if (done == RUN && iters <= before)
         return fail(ctx, MXS_HIP, "BiCGSTAB made no progress (device state not updated)");
+      k = iters;
       if (done == ST_HALF) {
         k_bi_half<<<g, RB, 0, ctx->stream>>>(n, x, p, w.st);
         MXS_HIP_TRY(ctx, hipGetLastError());
@@ -795,7 +890,6 @@ mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, do
     }
     repl++;
     rr = rt2;
-    restart = true;
     done = RUN;
   }
 }
@@ -817,13 +911,7 @@ mxs_status solve_gmres(mxs_ctx* ctx, const mxs_matrix* A, const double* b, doubl
   if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
   const double nb = sqrt(nb2), nr0 = sqrt(nr2);
   if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
-  if (nb == 0.0) {
-    MXS_HIP_TRY(ctx, hipMemsetAsync(x, 0, n * sizeof(double), ctx->stream));
-    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    KState z{};
-    fill_info(info, z, 1.0, 0.0, 0, 0, MXS_OK);
-    return MXS_OK;
-  }
+  if (nb == 0.0) return zero_solution(ctx, x, n, info);
   if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
   const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
   const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
@@ -846,27 +934,32 @@ mxs_status solve_gmres(mxs_ctx* ctx, const mxs_matrix* A, const double* b, doubl
       return fail(ctx, MXS_NOT_CONVERGED, "GMRES stopped after %lld steps, relres %.3e",
                   (long long)h.iters, beta / base);
     }
+    const int64_t before = h.iters;
+    k_gm_reset<<<1, 1, 0, ctx->stream>>>(w.st);
     k_gm_start<<<g, RB, 0, ctx->stream>>>(n, r, V, w.st);
     for (int j = 0; j < m; ++j) {
       double* vj = V + (size_t)j * ld;
       if ((s = launch_spmv(ctx, A, &one, vj, &zero, wv, &w.st->cycle))) return s;
-      k_gm_dots<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.partials, w.st);
-      k_gm_orth<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.partials, w.st);
-      k_gm_norm<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.partials, w.st);
+      k_gm_dots<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pm, w.st);
+      k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pm, g, j, 1, w.st);
+      k_gm_orth<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pm, w.st);
+      k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pm, g, j, 2, w.st);
+      k_gm_norm<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pa, w.st);
+      k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pa, g, j, 3, w.st);
       k_gm_scale<<<g, RB, 0, ctx->stream>>>(n, wv, V + (size_t)(j + 1) * ld, w.st);
     }
     k_gm_backsolve<<<1, 1, 0, ctx->stream>>>(w.st);
     k_gm_xupdate<<<g, RB, 0, ctx->stream>>>(n, ld, V, x, w.st);
     MXS_HIP_TRY(ctx, hipGetLastError());
     if ((s = residual(ctx, A, b, x, r))) return s;
-    k_dots<double><<<g, RB, 0, ctx->stream>>>(n, r, r, nullptr, nullptr, w.partials, w.st);
+    enqueue_dots<double>(ctx, w, n, r, r, nullptr, nullptr);
     if ((s = pull_state(ctx, w))) return s;
     if (h.done == ST_BREAKDOWN || h.done == ST_NONFINITE) {
       s = map_done(h.done);
       fill_info(info, h, base, beta / base, 0, restarts, s);
       return fail(ctx, s, "GMRES %s", h.done == ST_BREAKDOWN ? "breakdown" : "non-finite value");
     }
-    if (h.k == 0 && h.done == RUN)
+    if (h.iters <= before)
       return fail(ctx, MXS_HIP, "GMRES made no progress (device state not updated)");
     est = h.est;
     beta = sqrt(h.dot[0]);
@@ -954,7 +1047,7 @@ mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* 
     double f2;
     if ((s = dots<float>(ctx, w, n, rf, rf, nullptr, nullptr, &f2, nullptr))) return s;
     std::memset(&h, 0, sizeof(KState));
-    h.rho = f2;
+    h.rho[0] = f2;
     h.res2 = f2;
     h.thr = itol * sqrt(f2);
     h.max_iters = inner_max;

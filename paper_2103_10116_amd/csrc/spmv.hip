@@ -46,6 +46,7 @@ __device__ __forceinline__ T combine(T alpha, T s, T beta, const T* __restrict__
 // ---------------------------------------------------------------------------
 template <typename V, typename T, int NPL, bool SCALED>
 __global__ __launch_bounds__(64) void k_csr(const int32_t* __restrict__ blocks,
+                                            const int32_t* __restrict__ bnnz,
                                             const int32_t* __restrict__ rowptr,
                                             const int32_t* __restrict__ col,
                                             const V* __restrict__ val,
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(64) void k_csr(const int32_t* __restrict__ blocks,
   const int lane = threadIdx.x;
   const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
   const int32_t r0 = blocks[b], r1 = blocks[b + 1];
-  const int32_t s = rowptr[r0], e = rowptr[r1];
+  const int32_t s = bnnz[b], e = bnnz[b + 1];  // = rowptr[r0], rowptr[r1]
   const int nr = r1 - r0, len = e - s;
 
   auto emit = [&](int r, T sum) {
@@ -175,6 +176,68 @@ __global__ __launch_bounds__(64) void k_csr(const int32_t* __restrict__ blocks,
     } else if (tend) {
       emit(hrow, v);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CSR, vector variant for regular row lengths: G lanes per row, each group
+// of G lanes owns RPG consecutive rows and issues the loads of all of them
+// before using any (one entry per lane per row, a tail loop for rows longer
+// than G).  No LDS; the butterfly over the G lanes leaves every row sum in
+// every lane of the group, and lane r of the group stores row r.
+// ---------------------------------------------------------------------------
+template <typename V, typename T, int G, int RPG, bool SCALED>
+__global__ __launch_bounds__(256) void k_csr_vec(int64_t n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const V* __restrict__ val,
+                                                 const float* __restrict__ scale,
+                                                 const T* __restrict__ x, T* __restrict__ y,
+                                                 T alpha, T beta,
+                                                 const int32_t* __restrict__ skip) {
+  static_assert(RPG <= G, "lane r of a group stores row r");
+  if (skip && *skip) return;
+  constexpr int GROUPS = 256 / G;
+  const int li = threadIdx.x % G;
+  const int64_t base =
+      (xcd_remap(blockIdx.x, gridDim.x) * GROUPS + threadIdx.x / G) * (int64_t)RPG;
+  if (base >= n) return;
+  int32_t rp[RPG + 1];
+#pragma unroll
+  for (int r = 0; r <= RPG; ++r) rp[r] = rowptr[min<int64_t>(base + r, n)];
+  int32_t c[RPG];
+  T v[RPG];
+#pragma unroll
+  for (int r = 0; r < RPG; ++r) {
+    const int32_t k = rp[r] + li;
+    c[r] = 0;
+    v[r] = 0;
+    if (k < rp[r + 1]) {
+      c[r] = col[k];
+      v[r] = to_acc(val[k]);
+    }
+  }
+  T sum[RPG];
+#pragma unroll
+  for (int r = 0; r < RPG; ++r) {
+    sum[r] = T(0);
+    if (rp[r] + li < rp[r + 1]) sum[r] = v[r] * x[c[r]];
+  }
+#pragma unroll
+  for (int r = 0; r < RPG; ++r)
+    for (int32_t k = rp[r] + li + G; k < rp[r + 1]; k += G) sum[r] += to_acc(val[k]) * x[col[k]];
+#pragma unroll
+  for (int r = 0; r < RPG; ++r) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) sum[r] += __shfl_xor(sum[r], o, 64);
+  }
+  T mine = sum[0];
+#pragma unroll
+  for (int r = 1; r < RPG; ++r)
+    if (li == r) mine = sum[r];
+  const int64_t i = base + li;
+  if (li < RPG && i < n) {
+    if (SCALED) mine *= (T)scale[i];
+    y[i] = combine(alpha, mine, beta, y, i);
   }
 }
 
@@ -369,25 +432,56 @@ __global__ __launch_bounds__(64 * W) void k_ell(int64_t n, int64_t K, int64_t ld
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+template <typename V, typename T, int G, bool SCALED>
+void launch_csr_vec(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
+                    const int32_t* skip) {
+  const CsrPart& P = A->csr;
+  const V* val = (const V*)P.val;
+  const int rows_per_wg = (256 / G) * P.rpg;
+  const dim3 grid((unsigned)((A->n + rows_per_wg - 1) / rows_per_wg));
+  if (P.rpg == 8)
+    k_csr_vec<V, T, G, (G >= 8 ? 8 : G), SCALED><<<grid, 256, 0, ctx->stream>>>(
+        A->n, P.rowptr, P.col, val, P.scale, x, y, alpha, beta, skip);
+  else if (P.rpg == 2)
+    k_csr_vec<V, T, G, 2, SCALED><<<grid, 256, 0, ctx->stream>>>(
+        A->n, P.rowptr, P.col, val, P.scale, x, y, alpha, beta, skip);
+  else
+    k_csr_vec<V, T, G, 4, SCALED><<<grid, 256, 0, ctx->stream>>>(
+        A->n, P.rowptr, P.col, val, P.scale, x, y, alpha, beta, skip);
+}
+
 template <typename V, typename T, bool SCALED>
 void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
                 const int32_t* skip) {
   const CsrPart& P = A->csr;
+  if (P.lanes > 0) {
+    switch (P.lanes) {
+      case 4: launch_csr_vec<V, T, 4, SCALED>(ctx, A, alpha, x, beta, y, skip); break;
+      case 8: launch_csr_vec<V, T, 8, SCALED>(ctx, A, alpha, x, beta, y, skip); break;
+      case 16: launch_csr_vec<V, T, 16, SCALED>(ctx, A, alpha, x, beta, y, skip); break;
+      case 32: launch_csr_vec<V, T, 32, SCALED>(ctx, A, alpha, x, beta, y, skip); break;
+      default: launch_csr_vec<V, T, 64, SCALED>(ctx, A, alpha, x, beta, y, skip); break;
+    }
+    return;
+  }
   if (P.nblocks == 0) return;
   const V* val = (const V*)P.val;
   const dim3 grid((unsigned)P.nblocks);
   switch (P.block_nnz) {
     case 256:
-      k_csr<V, T, 4, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.rowptr, P.col, val,
-                                                           P.scale, x, y, alpha, beta, skip);
+      k_csr<V, T, 4, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.bnnz, P.rowptr, P.col,
+                                                           val, P.scale, x, y, alpha, beta,
+                                                           skip);
       break;
     case 1024:
-      k_csr<V, T, 16, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.rowptr, P.col, val,
-                                                            P.scale, x, y, alpha, beta, skip);
+      k_csr<V, T, 16, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.bnnz, P.rowptr, P.col,
+                                                            val, P.scale, x, y, alpha, beta,
+                                                            skip);
       break;
     default:
-      k_csr<V, T, 8, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.rowptr, P.col, val,
-                                                           P.scale, x, y, alpha, beta, skip);
+      k_csr<V, T, 8, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.bnnz, P.rowptr, P.col,
+                                                           val, P.scale, x, y, alpha, beta,
+                                                           skip);
   }
 }
 

@@ -202,6 +202,44 @@ def test_spmv_f64(env, orc, name, fmt, block_nnz):
         _check(y.cpu().numpy(), ref, scale, 1e-13)
 
 
+CSR_VARIANTS = [dict(csr_kernel="stream", block_nnz=b) for b in (256, 512, 1024)] + [
+    dict(csr_kernel="vector", lanes_per_row=g, rows_per_group=r)
+    for g in (4, 8, 16, 32, 64) for r in (2, 4, 8)]
+
+
+@pytest.mark.parametrize("name", sorted(ZOO))
+@pytest.mark.parametrize("dt", ["f64", "f32", "f16"])
+def test_spmv_csr_kernels(env, orc, name, dt):
+    """Both CSR kernels with every work-unit shape, against the oracle."""
+    mxs, ctx, torch = env
+    A = ZOO[name]
+    M = mxs.Matrix.from_host(ctx, A)
+    x = I.uniform_vector(A.ncols, 18)
+    y0 = I.uniform_vector(A.n, 19)
+    if dt == "f64":
+        Aref, xr, tol = A, x, 1e-13
+    elif dt == "f32":
+        _, v32 = orc.cast_f32(A.val)
+        Aref = I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, v32.astype(np.float64))
+        xr, tol = x.astype(np.float32).astype(np.float64), 1e-5
+    else:
+        _, h, sc = orc.rowscale_f16(A)
+        dec = orc.f16_bits_to_f64(h) * np.repeat(sc.astype(np.float64), A.row_lengths())
+        Aref = I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, dec)
+        xr, tol = x.astype(np.float32).astype(np.float64), 1e-5
+    y0r = y0.astype(np.float32).astype(np.float64) if dt != "f64" else y0
+    ref = orc.spmv_csr(Aref, xr, 1.5, -0.5, y0r)
+    scale = 1.5 * orc.absrow(Aref, xr) + 0.5 * np.abs(y0r)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    for opts in CSR_VARIANTS:
+        B = M.convert("csr", dt, **opts)
+        d = B.info()
+        assert (d["lanes_per_row"] > 0) == (opts["csr_kernel"] == "vector")
+        y = torch.from_numpy(y0r).to(tdt).cuda()
+        mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
+        _check(y.cpu().numpy().astype(np.float64), ref, scale, tol)
+
+
 @pytest.mark.parametrize("name", sorted(ZOO))
 @pytest.mark.parametrize("fmt", FORMATS)
 def test_spmv_f32(env, orc, name, fmt):
