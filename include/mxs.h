@@ -249,6 +249,70 @@ mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A
                         mxs_ir_info* info);
 
 /* ---------------------------------------------------------------------- */
+/* batched CG and continuous batching                                      */
+/* ---------------------------------------------------------------------- */
+/* Not in the paper: many independent SPD systems A_i x_i = b_i solved by
+ * the CG of the solvers above, one work-group per system, in a persistent
+ * kernel per size class captured in one hipGraph per step.  The engine
+ * holds the systems' matrices and Krylov state in a device arena of
+ * budget_bytes; requests wait in a FIFO and are admitted (first fit, with a
+ * starvation guard) when their class has a free slot and their footprint
+ * 4(n+1) + 12 nnz + 32 n bytes (rounded to 256-byte pieces) fits the arena.
+ * A system's arithmetic depends only on its own data and on its class's
+ * threads-per-system (a function of n alone), so each result is bitwise
+ * identical whether it ran alone or among others. */
+typedef struct mxs_batch mxs_batch;
+
+typedef struct {
+  size_t budget_bytes;      /* device arena for matrices and vectors */
+  int32_t max_slots;        /* systems resident at once (all classes) */
+  int32_t iters_per_step;   /* CG iterations per slot per step (0 = 16) */
+  int32_t nclasses;         /* 0 = defaults (n <= 1024, 2304, 4096, 10240) */
+  int32_t class_max_n[8];   /* increasing upper bounds of n per class */
+  int32_t class_block[8];   /* threads per system: 128, 256, 512 or 1024 (autotuner output) */
+  int32_t class_slots[8];   /* slots per class; 0 = an even share of the rest */
+} mxs_batch_opts;
+
+typedef struct {
+  int32_t active;           /* slots holding a system after this step's admission */
+  int32_t pending;          /* submitted, not yet admitted */
+  int32_t slots;
+  int32_t reserved;
+  int64_t completed;        /* systems retired so far */
+  int64_t arena_used, arena_size;
+} mxs_batch_stats;
+
+mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch** out);
+mxs_status mxs_batch_destroy(mxs_batch* batch);
+
+/* Queues A x = b (host CSR arrays and b, copied; x0 = 0) to relative
+ * tolerance rel_tol (relative to ||b||).  MXS_BUDGET if its footprint alone
+ * exceeds the arena, MXS_UNSUPPORTED if n exceeds the largest class,
+ * MXS_INVALID_MATRIX if the CSR is malformed (checked on the host). */
+mxs_status mxs_batch_submit(mxs_batch* batch, int64_t n, int64_t nnz, const int32_t* rowptr,
+                            const int32_t* col, const double* val, const double* b,
+                            double rel_tol, int64_t max_iters, uint64_t* ticket);
+
+/* One step: retire the systems the previous step finished, admit waiting
+ * requests, run iters_per_step CG iterations on every resident system and
+ * read their status back.  Synchronous. */
+mxs_status mxs_batch_step(mxs_batch* batch, mxs_batch_stats* stats);
+
+/* MXS_PENDING while the request runs or waits; otherwise copies x (n
+ * doubles) to x_host (nullable), fills info (nullable), forgets the ticket
+ * and returns the solve's status (MXS_OK when it converged). */
+mxs_status mxs_batch_poll(mxs_batch* batch, uint64_t ticket, double* x_host,
+                          mxs_solve_info* info);
+
+/* Moves up to `cap` tickets retired since the previous call into
+ * tickets[] (oldest first); *count receives how many were written. */
+mxs_status mxs_batch_completed(mxs_batch* batch, uint64_t* tickets, int64_t cap, int64_t* count);
+
+/* The configuration of size class `cls` (for reports and the autotuner). */
+mxs_status mxs_batch_config(const mxs_batch* batch, int32_t cls, int32_t* max_n, int32_t* block,
+                            int32_t* rows_per_thread, int32_t* slots, int32_t* uses_lds);
+
+/* ---------------------------------------------------------------------- */
 /* measurement                                                             */
 /* ---------------------------------------------------------------------- */
 typedef struct {

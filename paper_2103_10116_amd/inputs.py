@@ -235,34 +235,36 @@ def serving_system(m: int, seed: int) -> CSRMatrix:
     whole diagonal is shifted by one sigma ~ U[0, 1].  SPD."""
     g = rng(seed)
     n = m * m
-    idx = np.arange(n).reshape(m, m)  # idx[y, x]
     wx = g.uniform(0.5, 1.5, size=(m, m - 1))  # edge (y,x)-(y,x+1)
     wy = g.uniform(0.5, 1.5, size=(m - 1, m))  # edge (y,x)-(y+1,x)
-    ghost = g.uniform(0.5, 1.5, size=4 * m)
+    ghost = g.uniform(0.5, 1.5, size=4 * m)    # left, right, bottom, top sides
     sigma = g.uniform(0.0, 1.0)
-    rows, cols, vals = [], [], []
-    a, b = idx[:, :-1].ravel(), idx[:, 1:].ravel()
-    rows += [a, b]
-    cols += [b, a]
-    vals += [-wx.ravel(), -wx.ravel()]
-    a, b = idx[:-1, :].ravel(), idx[1:, :].ravel()
-    rows += [a, b]
-    cols += [b, a]
-    vals += [-wy.ravel(), -wy.ravel()]
-    diag = np.zeros(n)
-    np.add.at(diag, idx[:, :-1].ravel(), wx.ravel())
-    np.add.at(diag, idx[:, 1:].ravel(), wx.ravel())
-    np.add.at(diag, idx[:-1, :].ravel(), wy.ravel())
-    np.add.at(diag, idx[1:, :].ravel(), wy.ravel())
-    # ghost edges: left column, right column, bottom row, top row
-    bnd = np.concatenate([idx[:, 0], idx[:, -1], idx[0, :], idx[-1, :]])
-    np.add.at(diag, bnd, ghost)
+    diag = np.zeros((m, m))
+    diag[:, :-1] += wx
+    diag[:, 1:] += wx
+    diag[:-1, :] += wy
+    diag[1:, :] += wy
+    diag[:, 0] += ghost[:m]
+    diag[:, -1] += ghost[m:2 * m]
+    diag[0, :] += ghost[2 * m:3 * m]
+    diag[-1, :] += ghost[3 * m:]
     diag += sigma
-    rows.append(np.arange(n))
-    cols.append(np.arange(n))
-    vals.append(diag)
-    return _coo_to_sorted_csr(n, np.concatenate(rows), np.concatenate(cols),
-                              np.concatenate(vals))
+    # columns ascend: south (i-m), west (i-1), self, east (i+1), north (i+m)
+    idx = np.arange(n, dtype=np.int64).reshape(m, m)
+    cols = np.stack([idx - m, idx - 1, idx, idx + 1, idx + m], axis=-1).reshape(n, 5)
+    vals = np.zeros((m, m, 5))
+    mask = np.zeros((m, m, 5), bool)
+    vals[1:, :, 0] = -wy
+    mask[1:, :, 0] = True
+    vals[:, 1:, 1] = -wx
+    mask[:, 1:, 1] = True
+    vals[:, :, 2] = diag
+    mask[:, :, 2] = True
+    vals[:, :-1, 3] = -wx
+    mask[:, :-1, 3] = True
+    vals[:-1, :, 4] = -wy
+    mask[:-1, :, 4] = True
+    return _from_dense_mask(cols, vals.reshape(n, 5), mask.reshape(n, 5))
 
 
 @dataclass

@@ -85,6 +85,19 @@ class BwResult(C.Structure):
                 ("triad_gbs", C.c_double), ("best_gbs", C.c_double)]
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
+                ("iters_per_step", C.c_int32), ("nclasses", C.c_int32),
+                ("class_max_n", C.c_int32 * 8), ("class_block", C.c_int32 * 8),
+                ("class_slots", C.c_int32 * 8)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("active", C.c_int32), ("pending", C.c_int32), ("slots", C.c_int32),
+                ("reserved", C.c_int32), ("completed", C.c_int64),
+                ("arena_used", C.c_int64), ("arena_size", C.c_int64)]
+
+
 _P = C.c_void_p
 _S = C.c_int32
 _I64 = C.c_int64
@@ -103,6 +116,15 @@ _SIGS = {
                        C.POINTER(SolveInfo)]),
     "mxs_solve_ir": (_S, [_P, _P, _P, _P, _P, C.POINTER(Stop), C.c_double, _I64, _S,
                           C.POINTER(IRInfo)]),
+    "mxs_batch_create": (_S, [_P, C.POINTER(BatchOpts), C.POINTER(_P)]),
+    "mxs_batch_destroy": (_S, [_P]),
+    "mxs_batch_submit": (_S, [_P, _I64, _I64, _P, _P, _P, _P, C.c_double, _I64,
+                              C.POINTER(C.c_uint64)]),
+    "mxs_batch_step": (_S, [_P, C.POINTER(BatchStats)]),
+    "mxs_batch_poll": (_S, [_P, C.c_uint64, _P, C.POINTER(SolveInfo)]),
+    "mxs_batch_completed": (_S, [_P, C.POINTER(C.c_uint64), _I64, C.POINTER(_I64)]),
+    "mxs_batch_config": (_S, [_P, _S, C.POINTER(_S), C.POINTER(_S), C.POINTER(_S),
+                              C.POINTER(_S), C.POINTER(_S)]),
     "mxs_hbm_probe": (_S, [_P, C.c_size_t, C.c_int, C.POINTER(BwResult)]),
     "mxs_flush_cache": (_S, [_P, C.c_size_t]),
     "mxs_status_string": (C.c_char_p, [_S]),
@@ -360,3 +382,88 @@ def hbm_probe(ctx: Context, nbytes=1 << 30, reps=5) -> dict:
 
 def flush_cache(ctx: Context, nbytes=1 << 30):
     _check(_lib.mxs_flush_cache(ctx.handle, int(nbytes)), ctx)
+
+
+# ---------------------------------------------------------------------------
+# batched CG engine
+# ---------------------------------------------------------------------------
+class Batch:
+    """mxs_batch_*: continuous batching of independent SPD solves.
+
+    classes: None for the library defaults, or a list of
+    (max_n, threads_per_system, slots) tuples (slots 0 = even share)."""
+
+    def __init__(self, ctx: Context, budget_bytes=2 << 30, max_slots=512,
+                 iters_per_step=16, classes=None):
+        o = BatchOpts()
+        o.budget_bytes = int(budget_bytes)
+        o.max_slots = int(max_slots)
+        o.iters_per_step = int(iters_per_step)
+        if classes:
+            o.nclasses = len(classes)
+            for i, (mn, blk, sl) in enumerate(classes):
+                o.class_max_n[i] = int(mn)
+                o.class_block[i] = int(blk)
+                o.class_slots[i] = int(sl)
+        h = C.c_void_p()
+        _check(_lib.mxs_batch_create(ctx.handle, C.byref(o), C.byref(h)), ctx)
+        self.ctx = ctx
+        self.handle = h
+        self._buf = (C.c_uint64 * 4096)()
+
+    def submit(self, A, b, tol=1e-10, max_iters=0) -> int:
+        rp = np.ascontiguousarray(A.rowptr, np.int32)
+        ci = np.ascontiguousarray(A.col, np.int32)
+        v = np.ascontiguousarray(A.val, np.float64)
+        bb = np.ascontiguousarray(b, np.float64)
+        t = C.c_uint64()
+        _check(_lib.mxs_batch_submit(self.handle, int(A.n), len(ci), rp.ctypes.data_as(_P),
+                                     ci.ctypes.data_as(_P), v.ctypes.data_as(_P),
+                                     bb.ctypes.data_as(_P), float(tol), int(max_iters),
+                                     C.byref(t)), self.ctx)
+        return t.value
+
+    def step(self) -> dict:
+        s = BatchStats()
+        _check(_lib.mxs_batch_step(self.handle, C.byref(s)), self.ctx)
+        return {f: getattr(s, f) for f, _ in BatchStats._fields_}
+
+    def completed(self) -> list:
+        out = []
+        while True:
+            cnt = C.c_int64()
+            _check(_lib.mxs_batch_completed(self.handle, self._buf, len(self._buf),
+                                            C.byref(cnt)), self.ctx)
+            out.extend(self._buf[i] for i in range(cnt.value))
+            if cnt.value < len(self._buf):
+                return out
+
+    def poll(self, ticket: int, n: int):
+        """(status, x or None, Result); status PENDING while running."""
+        x = np.empty(int(n), np.float64)
+        info = SolveInfo()
+        s = _lib.mxs_batch_poll(self.handle, int(ticket), x.ctypes.data_as(_P), C.byref(info))
+        if s == PENDING:
+            return s, None, None
+        if s == INVALID_ARG:
+            _check(s, self.ctx)
+        return s, x, Result(s, info.iters, info.relres_recurrence, info.relres_true,
+                            info.replacements, info.restarts)
+
+    def config(self, cls: int) -> dict:
+        vals = [C.c_int32() for _ in range(5)]
+        _check(_lib.mxs_batch_config(self.handle, int(cls), *[C.byref(v) for v in vals]),
+               self.ctx)
+        return dict(zip(("max_n", "block", "rows_per_thread", "slots", "uses_lds"),
+                        (v.value for v in vals)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mxs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

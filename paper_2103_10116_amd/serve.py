@@ -1,0 +1,131 @@
+"""Serving loop: a stream of independent SPD solves, continuous batching.
+
+Requests arrive at given times (seconds after the start).  In "batched" mode
+every arrived request is submitted to the libmxs batch engine, which admits
+it into a free slot of its size class as soon as its footprint fits the HBM
+budget, so new requests join while others are still iterating on the GPU.
+In "plain" mode the same stream is served one request at a time by the
+single-system CG (mxs_solve).  Latency of a request is completion time minus
+arrival time on the host's monotonic clock.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs as I
+
+
+@dataclass
+class ServeReport:
+    mode: str
+    count: int
+    wall_s: float                 # first arrival to last completion
+    solves_per_s: float
+    p50_ms: float
+    p99_ms: float
+    mean_ms: float
+    iters_median: float
+    statuses: dict
+    steps: int = 0
+    max_active: int = 0
+    latencies_ms: np.ndarray = field(default=None, repr=False)
+    x: dict = field(default=None, repr=False)
+
+    def summary(self) -> dict:
+        d = {k: getattr(self, k) for k in ("mode", "count", "wall_s", "solves_per_s", "p50_ms",
+                                            "p99_ms", "mean_ms", "iters_median", "statuses",
+                                            "steps", "max_active")}
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+
+def build_systems(reqs):
+    """(A, b) of every request, from its seed."""
+    out = {}
+    for r in reqs:
+        A = I.serving_system(r.m, r.seed)
+        out[r.rid] = (A, I.serving_rhs(A.n, r.seed))
+    return out
+
+
+def _report(mode, reqs, arrival, done, iters, statuses, t_first, keep_x, xs, steps=0,
+            max_active=0):
+    lat = np.array([done[r.rid] - arrival[r.rid] for r in reqs]) * 1e3
+    wall = max(done.values()) - t_first
+    st = {}
+    for s in statuses.values():
+        st[int(s)] = st.get(int(s), 0) + 1
+    return ServeReport(mode, len(reqs), wall, len(reqs) / wall, float(np.percentile(lat, 50)),
+                       float(np.percentile(lat, 99)), float(lat.mean()),
+                       float(np.median(list(iters.values()))), st, steps, max_active, lat,
+                       xs if keep_x else None)
+
+
+def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1024,
+                iters_per_step=16, classes=None, keep_x=False) -> ServeReport:
+    from . import mxs
+    B = mxs.Batch(ctx, budget_bytes, max_slots, iters_per_step, classes)
+    order = sorted(reqs, key=lambda r: r.arrival)
+    ticket_of = {}
+    rid_of = {}
+    arrival, done, iters, statuses, xs = {}, {}, {}, {}, {}
+    i = 0
+    steps = 0
+    max_active = 0
+    t0 = time.perf_counter()
+    while len(done) < len(order):
+        now = time.perf_counter() - t0
+        while i < len(order) and order[i].arrival <= now:
+            r = order[i]
+            A, b = systems[r.rid]
+            t = B.submit(A, b, tol)
+            ticket_of[r.rid] = t
+            rid_of[t] = r
+            arrival[r.rid] = r.arrival
+            i += 1
+        if len(arrival) > len(done):
+            st = B.step()
+            steps += 1
+            max_active = max(max_active, st["active"])
+            for t in B.completed():
+                r = rid_of[t]
+                s, x, res = B.poll(t, systems[r.rid][0].n)
+                done[r.rid] = time.perf_counter() - t0
+                iters[r.rid] = res.iters
+                statuses[r.rid] = s
+                if keep_x:
+                    xs[r.rid] = x
+        elif i < len(order):
+            time.sleep(max(0.0, order[i].arrival - (time.perf_counter() - t0)))
+    B.close()
+    return _report("batched", order, arrival, done, iters, statuses, order[0].arrival, keep_x,
+                   xs, steps, max_active)
+
+
+def run_plain(ctx, reqs, systems, tol=1e-10, keep_x=False) -> ServeReport:
+    """One request at a time: upload, single-system CG, download."""
+    import torch
+    from . import mxs
+    order = sorted(reqs, key=lambda r: r.arrival)
+    arrival, done, iters, statuses, xs = {}, {}, {}, {}, {}
+    t0 = time.perf_counter()
+    for r in order:
+        now = time.perf_counter() - t0
+        if r.arrival > now:
+            time.sleep(r.arrival - now)
+        A, b = systems[r.rid]
+        M = mxs.Matrix.from_host(ctx, A)
+        bd = torch.from_numpy(b).cuda()
+        x = torch.zeros_like(bd)
+        res = mxs.solve(ctx, "cg", M, bd, x, tol=tol, raise_on_error=False)
+        xh = x.cpu().numpy()
+        M.close()
+        done[r.rid] = time.perf_counter() - t0
+        arrival[r.rid] = r.arrival
+        iters[r.rid] = res.iters
+        statuses[r.rid] = res.status
+        if keep_x:
+            xs[r.rid] = xh
+    return _report("plain", order, arrival, done, iters, statuses, order[0].arrival, keep_x, xs)

@@ -1,0 +1,173 @@
+"""Batched persistent CG and the continuous-batching engine, through the C
+ABI: every result meets the tolerance by the oracle's residual, each system's
+result is bitwise the same alone and in a mix, admission respects the HBM
+budget, and the serving loop completes every request."""
+import numpy as np
+import pytest
+
+from paper_2103_10116_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2103_10116_amd import mxs
+    ctx = mxs.Context(0)
+    yield mxs, ctx, torch
+    ctx.close()
+
+
+def _systems(ms, seed0=0):
+    out = []
+    for i, m in enumerate(ms):
+        A = I.serving_system(int(m), seed0 + i)
+        out.append((A, I.serving_rhs(A.n, seed0 + i)))
+    return out
+
+
+def _drain(B, limit=100000):
+    for _ in range(limit):
+        st = B.step()
+        assert st["arena_used"] <= st["arena_size"]
+        if st["active"] == 0 and st["pending"] == 0:
+            return
+    raise AssertionError("batch did not drain")
+
+
+def _slack(orc, A, b, x):
+    return 64 * U * np.linalg.norm(np.abs(b) + orc.absrow(A, x)) / np.linalg.norm(b)
+
+
+def test_default_classes(env):
+    mxs, ctx, torch = env
+    B = mxs.Batch(ctx, 64 << 20, 64)
+    cfg = [B.config(c) for c in range(4)]
+    assert [c["max_n"] for c in cfg] == [1024, 2304, 4096, 10240]
+    assert sum(c["slots"] for c in cfg) == 64
+    assert all(c["block"] * c["rows_per_thread"] >= c["max_n"] for c in cfg)
+    B.close()
+    with pytest.raises(mxs.MxsError):
+        mxs.Batch(ctx, 64 << 20, 8, classes=[(100, 256, 0), (50, 256, 0)])
+    with pytest.raises(mxs.MxsError):
+        mxs.Batch(ctx, 64 << 20, 8, classes=[(100, 300, 0)])
+    with pytest.raises(mxs.MxsError) as e:  # 10240 / 512 = 20 rows per thread > 16
+        mxs.Batch(ctx, 64 << 20, 8, classes=[(2304, 512, 0), (10240, 512, 0)])
+    assert e.value.status == mxs.UNSUPPORTED
+
+
+@pytest.mark.parametrize("classes", [None, [(1024, 128, 0), (4096, 256, 0), (10240, 1024, 0)],
+                                     [(2304, 512, 0), (10240, 1024, 0)]])
+def test_batch_matches_oracle(env, orc, classes):
+    mxs, ctx, torch = env
+    g = I.rng(41)
+    ms = np.concatenate([[8, 9, 31, 32, 33, 48, 64, 95, 96], g.integers(8, 97, 23)])
+    sys_ = _systems(ms, 100)
+    B = mxs.Batch(ctx, 256 << 20, 16, iters_per_step=8, classes=classes)
+    tickets = [B.submit(A, b, 1e-10) for A, b in sys_]
+    _drain(B)
+    done = set(B.completed())
+    assert done == set(tickets)
+    for (A, b), t in zip(sys_, tickets):
+        s, x, res = B.poll(t, A.n)
+        assert s == mxs.OK, res
+        rel = orc.true_relres(A, b, x)
+        assert rel <= 1e-10 + _slack(orc, A, b, x), (A.n, rel, res)
+        ref = orc.cg(A, b, tol=1e-10)
+        assert abs(res.iters - ref.iters) <= 2 + ref.iters // 20, (res.iters, ref.iters)
+    B.close()
+
+
+def test_alone_equals_mix_bitwise(env):
+    mxs, ctx, torch = env
+    probe = _systems([17, 64, 96], 200)
+    others = _systems(I.rng(43).integers(8, 97, 40), 300)
+    alone = []
+    for A, b in probe:
+        B = mxs.Batch(ctx, 64 << 20, 4, iters_per_step=5)
+        t = B.submit(A, b, 1e-10)
+        _drain(B)
+        s, x, _ = B.poll(t, A.n)
+        assert s == mxs.OK
+        alone.append(x)
+        B.close()
+    # mixed: probes submitted among other systems, different slots and steps
+    B = mxs.Batch(ctx, 512 << 20, 24, iters_per_step=7)
+    order = others[:13] + [probe[0]] + others[13:30] + [probe[1]] + others[30:] + [probe[2]]
+    tickets = [B.submit(A, b, 1e-10) for A, b in order]
+    _drain(B)
+    pos = [13, 31, len(order) - 1]
+    for k, i in enumerate(pos):
+        s, x, _ = B.poll(tickets[i], order[i][0].n)
+        assert s == mxs.OK
+        assert np.array_equal(x.view(np.uint64), alone[k].view(np.uint64)), k
+    B.close()
+
+
+def test_budget_and_queueing(env, orc):
+    mxs, ctx, torch = env
+    big = _systems([96], 400)[0]  # footprint about 0.88 MB
+    B = mxs.Batch(ctx, 512 << 10, 8)
+    with pytest.raises(mxs.MxsError) as e:
+        B.submit(*big, 1e-10)
+    assert e.value.status == mxs.BUDGET
+    B.close()
+    # 4 MiB budget, 30 systems of ~0.2-1 MB: most wait for space
+    sys_ = _systems(I.rng(44).integers(40, 97, 30), 500)
+    B = mxs.Batch(ctx, 4 << 20, 32, iters_per_step=8)
+    tickets = [B.submit(A, b, 1e-10) for A, b in sys_]
+    max_active = 0
+    for _ in range(100000):
+        st = B.step()
+        assert st["arena_used"] <= st["arena_size"] == 4 << 20
+        max_active = max(max_active, st["active"])
+        if st["active"] == 0 and st["pending"] == 0:
+            break
+    assert max_active < len(sys_)
+    for (A, b), t in zip(sys_, tickets):
+        s, x, _ = B.poll(t, A.n)
+        assert s == mxs.OK
+        assert orc.true_relres(A, b, x) <= 1e-10 + _slack(orc, A, b, x)
+    B.close()
+
+
+def test_special_requests(env):
+    mxs, ctx, torch = env
+    A, b = _systems([12], 600)[0]
+    B = mxs.Batch(ctx, 64 << 20, 8)
+    t0 = B.submit(A, np.zeros(A.n), 1e-10)
+    t1 = B.submit(A, b, 1e-10, max_iters=3)
+    bad = I.CSRMatrix(A.n, A.n, A.rowptr, A.col.copy(), A.val)
+    bad.col[1] = bad.col[0]
+    with pytest.raises(mxs.MxsError) as e:
+        B.submit(bad, b, 1e-10)
+    assert e.value.status == mxs.INVALID_MATRIX
+    with pytest.raises(mxs.MxsError) as e:
+        B.submit(I.serving_system(110, 1), np.ones(110 * 110), 1e-10)
+    assert e.value.status == mxs.UNSUPPORTED
+    assert B.poll(t0, A.n)[0] == mxs.PENDING
+    _drain(B)
+    s, x, res = B.poll(t0, A.n)
+    assert s == mxs.OK and not x.any() and res.iters == 0
+    s, x, res = B.poll(t1, A.n)
+    assert s == mxs.NOT_CONVERGED and res.iters == 3
+    B.close()
+
+
+def test_serving_loop(env, orc):
+    mxs, ctx, torch = env
+    from paper_2103_10116_amd import serve
+    reqs = I.serving_stream(40, rate=2000.0, seed=7)
+    systems = serve.build_systems(reqs)
+    rb = serve.run_batched(ctx, reqs, systems, budget_bytes=64 << 20, max_slots=32,
+                           keep_x=True)
+    rp = serve.run_plain(ctx, reqs, systems, keep_x=True)
+    assert rb.statuses == {mxs.OK: 40} and rp.statuses == {mxs.OK: 40}
+    assert rb.max_active > 1  # requests overlapped on the device
+    for r in reqs:
+        A, b = systems[r.rid]
+        for xs in (rb.x, rp.x):
+            assert orc.true_relres(A, b, xs[r.rid]) <= 1e-10 + _slack(orc, A, b, xs[r.rid])
+    assert rb.p99_ms > 0 and rp.p99_ms > 0
