@@ -54,6 +54,36 @@ def ell_streamed_bytes(desc, vb, xb):
     return desc["ell_width"] * desc["ell_stride"] * (vb + 4) + 2 * desc["nrows"] * xb
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_stencil27_128_traffic.txt")
+
+
+def measured_traffic(fmt, dt, info):
+    """HBM bytes per launch of this SpMV from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors), or
+    None when the summary predates the current kernels or lacks them."""
+    from paper_2103_10116_amd import profile_summary
+    table = profile_summary.load_traffic(TRAFFIC_FILE)
+    if not table:
+        return None
+    t = "double,double" if dt == "f64" else "float,float"
+    npl = {256: 4, 512: 8, 1024: 16}.get(info["block_nnz"], 8)
+    keys = []
+    if fmt == "csr" and info["lanes_per_row"] == 0:
+        keys.append((f"k_csr<{t},{npl},false>", info["blocks"] * 64))
+    if fmt == "coo":
+        keys.append((f"k_coo<{t},{npl},false>", info["blocks"] * 64))
+    if fmt in ("ell", "hyb"):
+        w = 1
+        while w < 16 and (info["ell_width"] + w - 1) // w > 256:
+            w *= 2
+        keys.append((f"k_ell<{t},{w}>", info["ell_stride"] * w))
+    if fmt == "hyb" and info["coo_nnz"]:
+        keys.append((f"k_coo<{t},{npl},true>", info["blocks"] * 64))
+    if not keys or any(k not in table for k in keys):
+        return None
+    return int(sum(table[k] for k in keys))
+
+
 class Timer:
     """HIP events on the ctx stream (torch's current stream)."""
 
@@ -89,7 +119,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sections", default="probe,spmv,zipf,krylov,ir,cpu")
+    ap.add_argument("--sections", default="probe,spmv,zipf,krylov,ir,serve,cpu")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--plain-requests", type=int, default=1000)
     ap.add_argument("--grid", type=int, default=128, help="stencil grid side (128 = full size)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -174,11 +206,12 @@ def main():
     # dominant kernel: the slowest of the step
     dom = max(per, key=lambda k: per[k]["us"])
     d = per[dom]
+    fmt_d, dt_d = dom.split("_")
     out["roofline"] = {"bound": "hbm", "kernel": f"spmv_{dom}", "achieved": d["GBs"],
                        "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": round(d["GBs"] / PEAK_HBM_GBS, 4),
                        "bytes_per_launch": d["bytes"], "us_per_launch": d["us"],
-                       "traffic": None}
+                       "traffic": measured_traffic(fmt_d, dt_d, mats[(fmt_d, dt_d)].info())}
     if peak_meas:
         out["roofline"]["measured_peak"] = round(peak_meas, 1)
         out["roofline"]["frac_measured"] = round(d["GBs"] / peak_meas, 4)
@@ -322,6 +355,45 @@ def main():
             log(name, json.dumps(e))
             Qm.close()
         extra["iterative_refinement"] = irr
+
+    # ---------------- batched CG serving vs plain CG ----------------
+    if "serve" in sections:
+        from paper_2103_10116_amd import serve
+        classes = None
+        if "tune" in sections:
+            from paper_2103_10116_amd import autotune
+            classes = autotune.tune_batch_classes(ctx, log=log)
+        count = args.serve_requests
+        closed = I.serving_stream(count, rate=0.0)
+        log(f"generating {count} serving systems")
+        systems = serve.build_systems(closed)
+        sv = {"requests": count, "tol": 1e-10,
+              "system": "weighted 5-point Laplacian, m x m grid, m ~ U{8..96}, diagonal shift U[0,1]"}
+        bkw = dict(budget_bytes=4 << 30, max_slots=2048, iters_per_step=16, classes=classes)
+        rb = serve.run_batched(ctx, closed, systems, **bkw)
+        sv["batched_closed"] = rb.summary()
+        log("batched closed", sv["batched_closed"])
+        mu_b = rb.solves_per_s
+        nplain = min(count, args.plain_requests)
+        rp = serve.run_plain(ctx, closed[:nplain], systems)
+        sv["plain_closed"] = rp.summary()
+        log("plain closed", sv["plain_closed"])
+        mu_p = rp.solves_per_s
+        # one open stream both paths can sustain (half the plain path's capacity)
+        lam = 0.5 * mu_p
+        s_open = I.serving_stream(nplain, rate=lam)
+        sv["open_stream_plain_rate"] = {"rate_per_s": round(lam, 2), "requests": nplain,
+                                        "batched": serve.run_batched(ctx, s_open, systems, **bkw).summary(),
+                                        "plain": serve.run_plain(ctx, s_open, systems).summary()}
+        log("open stream at 0.5 x plain capacity", sv["open_stream_plain_rate"])
+        # the batched path near its own saturation
+        lam_b = 0.9 * mu_b
+        s_hi = I.serving_stream(count, rate=lam_b)
+        sv["open_stream_batched_rate"] = {"rate_per_s": round(lam_b, 2), "requests": count,
+                                          "batched": serve.run_batched(ctx, s_hi, systems, **bkw).summary()}
+        log("open stream at 0.9 x batched capacity", sv["open_stream_batched_rate"])
+        sv["speedup_solves_per_s"] = round(mu_b / mu_p, 2)
+        extra["serving"] = sv
 
     # ---------------- CPU oracle baseline ----------------
     if "cpu" in sections:

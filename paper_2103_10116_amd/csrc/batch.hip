@@ -655,6 +655,7 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
       if (!B->slots[i].busy) return i;
     return -1;
   };
+  std::vector<Request> uploading;
   size_t idx = 0;
   while (idx < B->pending.size()) {
     Request& R = B->pending[idx];
@@ -715,9 +716,14 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
     s.bytes = R.bytes;
     s.n = n;
     s.x_dev = d_x;
-    // the host copies in R must stay alive until the uploads completed
-    MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
+    // the host copies in R must stay alive until the uploads completed:
+    // keep them until the synchronisation below
+    uploading.push_back(std::move(R));
     B->pending.erase(B->pending.begin() + idx);
+  }
+  if (!uploading.empty()) {
+    MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
+    uploading.clear();
   }
   // 3. run K iterations of every active slot and read the statuses back
   int active = 0;

@@ -461,36 +461,58 @@ __global__ __launch_bounds__(RB) void k_gm_fin(const double* __restrict__ part, 
   }
   double ww[1];
   finish<1>(part, g, ww);
-  if (threadIdx.x != 0) return;
-  const double hn = sqrt(ww[0]);
-  st->iters += 1;
-  if (!isfinite(hn)) {
-    st->done = ST_NONFINITE;
-    return;
+  // stage the column, the rotations and g in LDS with parallel loads; one
+  // thread then runs the short sequential recurrence on LDS
+  __shared__ double hc[MAXM + 1], c_[MAXM], s_[MAXM], gg[2];
+  __shared__ int verdict;
+  const int t = threadIdx.x;
+  if (t <= j) hc[t] = Hj[t];
+  if (t < j) {
+    c_[t] = st->cs[t];
+    s_[t] = st->sn[t];
   }
-  Hj[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = Hj[i], c = Hj[i + 1];
-    Hj[i] = st->cs[i] * a + st->sn[i] * c;
-    Hj[i + 1] = -st->sn[i] * a + st->cs[i] * c;
+  if (t == 0) gg[0] = st->g[j];
+  __syncthreads();
+  if (t == 0) {
+    const double hn = sqrt(ww[0]);
+    const int64_t it = st->iters + 1;
+    verdict = 0;
+    if (!isfinite(hn)) {
+      verdict = ST_NONFINITE;
+    } else {
+      hc[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = hc[i], c = hc[i + 1];
+        hc[i] = c_[i] * a + s_[i] * c;
+        hc[i + 1] = -s_[i] * a + c_[i] * c;
+      }
+      const double a = hc[j], c = hc[j + 1];
+      const double d = sqrt(a * a + c * c);
+      if (d == 0.0) {
+        verdict = ST_BREAKDOWN;
+      } else {
+        c_[j] = a / d;
+        s_[j] = c / d;
+        hc[j] = d;
+        hc[j + 1] = 0.0;
+        gg[1] = -s_[j] * gg[0];
+        gg[0] = c_[j] * gg[0];
+        const double est = fabs(gg[1]);
+        st->k = j + 1;
+        st->est = est;
+        st->res2 = hn;  // h_{j+1,j} for the scaling kernel
+        st->cs[j] = c_[j];
+        st->sn[j] = s_[j];
+        st->g[j] = gg[0];
+        st->g[j + 1] = gg[1];
+        if (est <= st->thr || hn == 0.0 || it >= st->max_iters || j + 1 >= st->m) st->cycle = 1;
+      }
+    }
+    st->iters = it;
+    if (verdict) st->done = verdict;
   }
-  const double a = Hj[j], c = Hj[j + 1];
-  const double d = sqrt(a * a + c * c);
-  if (d == 0.0) {
-    st->done = ST_BREAKDOWN;
-    return;
-  }
-  st->cs[j] = a / d;
-  st->sn[j] = c / d;
-  Hj[j] = d;
-  Hj[j + 1] = 0.0;
-  st->g[j + 1] = -st->sn[j] * st->g[j];
-  st->g[j] = st->cs[j] * st->g[j];
-  st->k = j + 1;
-  st->est = fabs(st->g[j + 1]);
-  st->res2 = hn;  // h_{j+1,j} for the scaling kernel
-  if (st->est <= st->thr || hn == 0.0 || st->iters >= st->max_iters || j + 1 >= st->m)
-    st->cycle = 1;
+  __syncthreads();
+  if (verdict == 0 && t <= j + 1) Hj[t] = hc[t];
 }
 
 // v_{j+1} = w / h_{j+1,j}
@@ -501,15 +523,24 @@ __global__ __launch_bounds__(RB) void k_gm_scale(int64_t n, const double* __rest
   GRID_STRIDE(r, n) vn[r] = w[r] * inv;
 }
 
-// back substitution R y = g on one thread (k <= 32)
-__global__ void k_gm_backsolve(KState* st) {
+// back substitution R y = g: the triangle is staged in LDS by all threads,
+// then solved by one (k <= 32)
+__global__ __launch_bounds__(RB) void k_gm_backsolve(KState* st) {
   if (st->done) return;
-  const int L = MAXM + 1, k = st->k;
-  for (int i = k - 1; i >= 0; --i) {
-    double s = st->g[i];
-    for (int l = i + 1; l < k; ++l) s -= st->H[l * L + i] * st->y[l];
-    st->y[i] = s / st->H[i * L + i];
-  }
+  constexpr int L = MAXM + 1;
+  __shared__ double R[MAXM * L], gy[MAXM];
+  const int k = st->k;
+  for (int e = threadIdx.x; e < k * L; e += RB) R[e] = st->H[e];
+  if ((int)threadIdx.x < k) gy[threadIdx.x] = st->g[threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = k - 1; i >= 0; --i) {
+      double s = gy[i];
+      for (int l = i + 1; l < k; ++l) s -= R[l * L + i] * gy[l];
+      gy[i] = s / R[i * L + i];
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < k) st->y[threadIdx.x] = gy[threadIdx.x];
 }
 
 // x += V(:, 0..k-1) y
@@ -948,7 +979,7 @@ mxs_status solve_gmres(mxs_ctx* ctx, const mxs_matrix* A, const double* b, doubl
       k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pa, g, j, 3, w.st);
       k_gm_scale<<<g, RB, 0, ctx->stream>>>(n, wv, V + (size_t)(j + 1) * ld, w.st);
     }
-    k_gm_backsolve<<<1, 1, 0, ctx->stream>>>(w.st);
+    k_gm_backsolve<<<1, RB, 0, ctx->stream>>>(w.st);
     k_gm_xupdate<<<g, RB, 0, ctx->stream>>>(n, ld, V, x, w.st);
     MXS_HIP_TRY(ctx, hipGetLastError());
     if ((s = residual(ctx, A, b, x, r))) return s;

@@ -281,11 +281,12 @@ def serving_stream(count: int, rate: float, seed: int = SERVING_SEED,
     sides uniform in [m_lo, m_hi]."""
     g = rng(seed)
     ms = g.integers(m_lo, m_hi + 1, size=count)
+    seeds = g.integers(1, 2**31 - 1, size=count)
+    # arrival times last, so that the systems do not depend on the rate
     if rate > 0:
         t = np.cumsum(g.exponential(1.0 / rate, size=count))
     else:
         t = np.zeros(count)
-    seeds = g.integers(1, 2**31 - 1, size=count)
     return [ServingRequest(i, float(t[i]), int(ms[i]), int(seeds[i])) for i in range(count)]
 
 
