@@ -67,18 +67,22 @@ def measured_traffic(fmt, dt, info):
         return None
     t = "double,double" if dt == "f64" else "float,float"
     npl = {256: 4, 512: 8, 1024: 16}.get(info["block_nnz"], 8)
+    wpg = info["waves_per_group"]
+    chunked = -(-info["blocks"] // wpg) * 64 * wpg  # threads of the stream/COO grid
     keys = []
     if fmt == "csr" and info["lanes_per_row"] == 0:
-        keys.append((f"k_csr<{t},{npl},false>", info["blocks"] * 64))
+        keys.append((f"k_csr<{t},{npl},false,{wpg}>", chunked))
+    if fmt == "csr" and info["lanes_per_row"] == 1:
+        keys.append((f"k_csr_row<{t},false>", -(-info["nrows"] // 256) * 256))
     if fmt == "coo":
-        keys.append((f"k_coo<{t},{npl},false>", info["blocks"] * 64))
+        keys.append((f"k_coo<{t},{npl},false,{wpg}>", chunked))
     if fmt in ("ell", "hyb"):
         w = 1
         while w < 16 and (info["ell_width"] + w - 1) // w > 256:
             w *= 2
         keys.append((f"k_ell<{t},{w}>", info["ell_stride"] * w))
     if fmt == "hyb" and info["coo_nnz"]:
-        keys.append((f"k_coo<{t},{npl},true>", info["blocks"] * 64))
+        keys.append((f"k_coo<{t},{npl},true,{wpg}>", chunked))
     if not keys or any(k not in table for k in keys):
         return None
     return int(sum(table[k] for k in keys))

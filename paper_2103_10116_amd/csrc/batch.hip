@@ -70,14 +70,67 @@ __device__ __forceinline__ double bsum(double v, double* red) {
   return s;
 }
 
+template <int BS>
+__device__ __forceinline__ int bmax(int v, int* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  int s = red[0];
+#pragma unroll
+  for (int i = 1; i < BS / 64; ++i) s = max(s, red[i]);
+  __syncthreads();
+  return s;
+}
+
+// q = A v for the thread's rows (rows tid + k*BS).  The loop over the
+// entry index is outermost so that the loads of all RPT rows are in flight
+// together; row pointers come from LDS.
+template <int BS, int RPT>
+__device__ __forceinline__ void rows_times(const int32_t* __restrict__ rpl,
+                                           const int32_t* __restrict__ col,
+                                           const double* __restrict__ val,
+                                           const double* __restrict__ vec, int n, int maxlen,
+                                           double (&q)[RPT]) {
+  const int tid = threadIdx.x;
+  int32_t rs[RPT], re[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * BS;
+    rs[k] = i < n ? rpl[i] : 0;
+    re[k] = i < n ? rpl[i + 1] : 0;
+    q[k] = 0.0;
+  }
+  for (int j = 0; j < maxlen; ++j) {
+    int32_t c[RPT];
+    double v[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      c[k] = 0;
+      v[k] = 0.0;
+      if (rs[k] + j < re[k]) {
+        c[k] = col[rs[k] + j];
+        v[k] = val[rs[k] + j];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+      if (rs[k] + j < re[k]) q[k] += v[k] * vec[c[k]];
+  }
+}
+
 // One work-group per slot.  BS threads, RPT rows per thread (rows
-// tid + k*BS), LDS holds a vector of the class's largest n (p, and x for
-// the true-residual check) when USE_LDS, otherwise the slot's p in HBM is
-// used in place.
+// tid + k*BS).  LDS holds the slot's row pointers and, when USE_LDS, the
+// gather vector (p, or x during the true-residual check); otherwise the
+// slot's p array in HBM serves as the gather vector.  x, r and q of the
+// thread's rows live in registers for the whole launch.
 template <int BS, int RPT, bool USE_LDS>
-__global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, int base, int K) {
-  extern __shared__ double vlds[];
+__global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, int base, int K,
+                                                 int vec_cap) {
+  extern __shared__ double dyn[];
   __shared__ double red[BS / 64];
+  __shared__ int ired[BS / 64];
   SlotDesc* S = slots + base + blockIdx.x;
   if (!S->active || S->status >= SLOT_CONVERGED) return;
   const int n = S->n;
@@ -86,9 +139,19 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
   const double* __restrict__ val = S->val;
   const double* __restrict__ b = S->b;
   double* __restrict__ pg = S->p;
-  double* __restrict__ vec = USE_LDS ? vlds : pg;  // the shared gather vector
+  double* __restrict__ vec = USE_LDS ? dyn : pg;
+  int32_t* rpl = (int32_t*)(dyn + (USE_LDS ? vec_cap : 0));
   const int tid = threadIdx.x;
-  double x[RPT], r[RPT], p[RPT], q[RPT];
+  int mylen = 0;
+  for (int i = tid; i <= n; i += BS) rpl[i] = rp[i];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * BS;
+    if (i < n) mylen = max(mylen, rpl[i + 1] - rpl[i]);
+  }
+  const int maxlen = bmax<BS>(mylen, ired);
+  double x[RPT], r[RPT], q[RPT];
   double rho, thr;
   int status = SLOT_RUN;
   int it = S->iters, repl = S->repl;
@@ -100,7 +163,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
       const int i = tid + k * BS;
       x[k] = 0.0;
       r[k] = i < n ? b[i] : 0.0;
-      p[k] = r[k];
+      if (i < n) vec[i] = r[k];
       acc += r[k] * r[k];
     }
     rho = bsum<BS>(acc, red);
@@ -113,29 +176,20 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
       const int i = tid + k * BS;
       x[k] = i < n ? S->x[i] : 0.0;
       r[k] = i < n ? S->r[i] : 0.0;
-      p[k] = i < n ? pg[i] : 0.0;
+      if (USE_LDS && i < n) vec[i] = pg[i];
     }
     rho = S->rho;
     thr = S->thr;
   }
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * BS;
-    if (i < n) vec[i] = p[k];
-  }
   __syncthreads();
   double rr = rho;
   for (int s = 0; s < K && status == SLOT_RUN; ++s) {
-    // q = A p
+    rows_times<BS, RPT>(rpl, col, val, vec, n, maxlen, q);
     double pq = 0.0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      double sum = 0.0;
-      if (i < n)
-        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) sum += val[e] * vec[col[e]];
-      q[k] = sum;
-      pq += p[k] * sum;
+      if (i < n) pq += vec[i] * q[k];
     }
     pq = bsum<BS>(pq, red);
     if (!(pq > 0.0)) {
@@ -146,7 +200,8 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      x[k] += alpha * p[k];
+      const int i = tid + k * BS;
+      if (i < n) x[k] += alpha * vec[i];
       r[k] -= alpha * q[k];
       acc += r[k] * r[k];
     }
@@ -157,24 +212,20 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
       break;
     }
     if (sqrt(rr) <= thr) {
-      // true residual r_t = b - A x, computed from x staged in the vector
+      // true residual r_t = b - A x, with x staged in the gather vector
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int i = tid + k * BS;
         if (i < n) vec[i] = x[k];
       }
       __syncthreads();
+      rows_times<BS, RPT>(rpl, col, val, vec, n, maxlen, q);
       double tt = 0.0;
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int i = tid + k * BS;
-        double sum = 0.0;
-        if (i < n) {
-          sum = b[i];
-          for (int32_t e = rp[i]; e < rp[i + 1]; ++e) sum -= val[e] * vec[col[e]];
-        }
-        q[k] = sum;
-        tt += sum * sum;
+        q[k] = i < n ? b[i] - q[k] : 0.0;
+        tt += q[k] * q[k];
       }
       tt = bsum<BS>(tt, red);
       if (sqrt(tt) <= thr) {
@@ -193,8 +244,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
       for (int k = 0; k < RPT; ++k) {
         const int i = tid + k * BS;
         r[k] = q[k];
-        p[k] = q[k];
-        if (i < n) vec[i] = p[k];
+        if (i < n) vec[i] = q[k];
       }
       rho = tt;
       rr = tt;
@@ -210,19 +260,18 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      p[k] = r[k] + beta * p[k];
-      if (i < n) vec[i] = p[k];
+      if (i < n) vec[i] = r[k] + beta * vec[i];
     }
     __syncthreads();
   }
-  // write the state back
+  // write the state back (p persists in HBM between launches)
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int i = tid + k * BS;
     if (i < n) {
       S->x[i] = x[k];
       S->r[i] = r[k];
-      if (USE_LDS) pg[i] = p[k];
+      if (USE_LDS) pg[i] = vec[i];
     }
   }
   if (tid == 0) {
@@ -342,6 +391,12 @@ struct mxs_batch {
   uint64_t next_ticket = 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipStream_t branch[mxs::kMaxClasses] = {};  // capture-time fork streams
+  hipEvent_t fork = nullptr, join[mxs::kMaxClasses] = {};
+  char* up_stage = nullptr;    // pinned: request data on its way to the arena
+  size_t up_bytes = 0;
+  char* down_stage = nullptr;  // pinned: solutions on their way back
+  size_t down_bytes = 0;
   bool launched = false;  // a step's graph is in flight / its status is fresh
   int64_t completed = 0;
   std::vector<uint64_t> newly_done;  // tickets retired since the last mxs_batch_completed
@@ -356,9 +411,11 @@ size_t footprint(int64_t n, int64_t nnz) {
   return up((n + 1) * 4) + up(nnz * 4) + up(nnz * 8) + 4 * up(n * 8);
 }
 
-using BatchKernel = void (*)(SlotDesc*, int, int);
+using BatchKernel = void (*)(SlotDesc*, int, int, int);
 
-// (block, rows per thread) -> kernel; rows per thread in {1, 2, 4, 8, 16}
+// (block, rows per thread) -> kernel; rows per thread in {1, 2, 4, 6, 8, 10, 12, 16}
+constexpr int kRpt[] = {1, 2, 4, 6, 8, 10, 12, 16};
+
 template <bool L>
 BatchKernel pick(int block, int rpt) {
 #define MXS_BK(B)                                          \
@@ -366,7 +423,10 @@ BatchKernel pick(int block, int rpt) {
     if (rpt <= 1) return k_batch_cg<B, 1, L>;              \
     if (rpt <= 2) return k_batch_cg<B, 2, L>;              \
     if (rpt <= 4) return k_batch_cg<B, 4, L>;              \
+    if (rpt <= 6) return k_batch_cg<B, 6, L>;              \
     if (rpt <= 8) return k_batch_cg<B, 8, L>;              \
+    if (rpt <= 10) return k_batch_cg<B, 10, L>;            \
+    if (rpt <= 12) return k_batch_cg<B, 12, L>;            \
     return k_batch_cg<B, 16, L>;                           \
   }
   MXS_BK(128)
@@ -378,10 +438,15 @@ BatchKernel pick(int block, int rpt) {
 }
 
 int rpt_for(int max_n, int block) {
-  int need = (max_n + block - 1) / block;
-  int r = 1;
-  while (r < need) r <<= 1;
-  return r;
+  const int need = (max_n + block - 1) / block;
+  for (int r : kRpt)
+    if (r >= need) return r;
+  return need;  // > 16: rejected by the caller
+}
+
+// LDS bytes of a class: row pointers, plus the gather vector when it fits
+size_t class_lds(const ClassCfg& C) {
+  return (C.lds ? (size_t)C.max_n * sizeof(double) : 0) + (size_t)(C.max_n + 1) * 4;
 }
 
 mxs_status build_graph(mxs_batch* B) {
@@ -392,14 +457,19 @@ mxs_status build_graph(mxs_batch* B) {
     B->exec = nullptr;
     B->graph = nullptr;
   }
+  // the class kernels are independent: each runs on its own branch of the
+  // graph (fork from the main stream, join back before the status copy)
   MXS_HIP_TRY(ctx, hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+  (void)hipEventRecord(B->fork, B->stream);
   for (int c = 0; c < B->nclasses; ++c) {
     const ClassCfg& C = B->cls[c];
     if (C.slots == 0) continue;
+    (void)hipStreamWaitEvent(B->branch[c], B->fork, 0);
     BatchKernel k = C.lds ? pick<true>(C.block, C.rpt) : pick<false>(C.block, C.rpt);
-    const size_t lds = C.lds ? (size_t)C.max_n * sizeof(double) : 0;
-    hipLaunchKernelGGL(k, dim3(C.slots), dim3(C.block), lds, B->stream, B->d_slots, C.base,
-                       B->K);
+    hipLaunchKernelGGL(k, dim3(C.slots), dim3(C.block), class_lds(C), B->branch[c], B->d_slots,
+                       C.base, B->K, C.max_n);
+    (void)hipEventRecord(B->join[c], B->branch[c]);
+    (void)hipStreamWaitEvent(B->stream, B->join[c], 0);
   }
   (void)hipMemcpyAsync(B->h_status, B->d_slots, sizeof(SlotDesc) * B->nslots,
                        hipMemcpyDeviceToHost, B->stream);
@@ -502,13 +572,23 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
     C.slots = nsl[c] > 0 ? nsl[c]
                          : rest / unassigned + (c == last_unassigned ? rest % unassigned : 0);
     C.base = base;
-    const size_t lds = (size_t)C.max_n * sizeof(double);
-    C.lds = lds + 1024 <= (size_t)prop.sharedMemPerBlock;
-    if (C.lds && lds > 65536) {
-      BatchKernel k = pick<true>(C.block, C.rpt);
-      C.lds = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds) == hipSuccess;
+    // the gather vector lives in LDS when it fits beside the row pointers
+    const size_t limit = (size_t)prop.sharedMemPerBlock - 1024;
+    C.lds = true;
+    if (class_lds(C) > limit) C.lds = false;
+    if (class_lds(C) > limit) {
+      delete B;
+      return fail(ctx, MXS_UNSUPPORTED, "class max n %d: row pointers exceed the LDS", C.max_n);
+    }
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      const size_t lds = class_lds(C);
+      if (lds <= 65536) break;
+      BatchKernel k = C.lds ? pick<true>(C.block, C.rpt) : pick<false>(C.block, C.rpt);
+      if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds) == hipSuccess)
+        break;
       (void)hipGetLastError();
+      C.lds = false;  // fall back to the gather vector in HBM
     }
     base += C.slots;
   }
@@ -517,8 +597,21 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
   B->slots.resize(B->nslots);
   mxs_status st = MXS_OK;
   do {
-    if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess) {
-      st = fail(ctx, MXS_HIP, "stream creation failed");
+    bool ok = hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) == hipSuccess;
+    for (int c = 0; ok && c < nc; ++c)
+      ok = hipStreamCreateWithFlags(&B->branch[c], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&B->join[c], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      st = fail(ctx, MXS_HIP, "stream or event creation failed");
+      break;
+    }
+    B->up_bytes = std::min<size_t>(opts->budget_bytes, (size_t)256 << 20);
+    B->down_bytes = (size_t)32 << 20;
+    if (hipHostMalloc((void**)&B->up_stage, B->up_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&B->down_stage, B->down_bytes, hipHostMallocDefault) !=
+            hipSuccess) {
+      st = fail(ctx, MXS_OOM, "pinned staging buffers");
       break;
     }
     B->arena_mem = ctx->alloc.alloc(opts->budget_bytes);
@@ -564,6 +657,13 @@ mxs_status mxs_batch_destroy(mxs_batch* B) {
   }
   if (B->h_slots) (void)hipHostFree(B->h_slots);
   if (B->h_status) (void)hipHostFree(B->h_status);
+  if (B->up_stage) (void)hipHostFree(B->up_stage);
+  if (B->down_stage) (void)hipHostFree(B->down_stage);
+  for (int c = 0; c < mxs::kMaxClasses; ++c) {
+    if (B->branch[c]) (void)hipStreamDestroy(B->branch[c]);
+    if (B->join[c]) (void)hipEventDestroy(B->join[c]);
+  }
+  if (B->fork) (void)hipEventDestroy(B->fork);
   if (B->stream) (void)hipStreamDestroy(B->stream);
   delete B;
   return MXS_OK;
@@ -608,16 +708,21 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
   MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
   // 1. retire slots the last step finished (h_status is that step's copy)
   std::vector<int> retired;
+  std::vector<size_t> stage_off;
   if (B->launched) {
+    size_t down = 0;
     for (int i = 0; i < B->nslots; ++i) {
       Slot& s = B->slots[i];
       if (!s.busy) continue;
       const SlotDesc& d = B->h_status[i];
       if (d.status < SLOT_CONVERGED) continue;
+      const size_t xb = up(s.n * sizeof(double));
+      if (down + xb > B->down_bytes) break;  // the rest retires next step
       Result& R = B->results[s.ticket];
-      R.x.resize((size_t)s.n);
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(R.x.data(), s.x_dev, s.n * sizeof(double),
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(B->down_stage + down, s.x_dev, s.n * sizeof(double),
                                       hipMemcpyDeviceToHost, B->stream));
+      stage_off.push_back(down);
+      down += xb;
       std::memset(&R.info, 0, sizeof(R.info));
       R.info.iters = d.iters;
       R.info.replacements = d.repl;
@@ -633,9 +738,13 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
       retired.push_back(i);
     }
     MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
-    for (int i : retired) {
+    for (size_t q = 0; q < retired.size(); ++q) {
+      const int i = retired[q];
       Slot& s = B->slots[i];
-      B->results[s.ticket].done = true;
+      Result& R = B->results[s.ticket];
+      const double* xs = (const double*)(B->down_stage + stage_off[q]);
+      R.x.assign(xs, xs + s.n);
+      R.done = true;
       B->newly_done.push_back(s.ticket);
       B->arena.release(s.off, s.bytes);
       s.busy = false;
@@ -656,9 +765,12 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
     return -1;
   };
   std::vector<Request> uploading;
+  size_t staged = 0;
   size_t idx = 0;
   while (idx < B->pending.size()) {
     Request& R = B->pending[idx];
+    const bool via_stage = R.bytes <= B->up_bytes;
+    if (via_stage && staged + R.bytes > B->up_bytes) break;  // stage full: next step
     const int si = find_free(R.cls);
     size_t off = 0;
     if (si < 0 || !B->arena.alloc(R.bytes, &off)) {
@@ -683,15 +795,29 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
     double* d_x = (double*)((char*)d_b + up(n * 8));
     double* d_r = (double*)((char*)d_x + up(n * 8));
     double* d_p = (double*)((char*)d_r + up(n * 8));
-    MXS_HIP_TRY(ctx, hipMemcpyAsync(d_rp, R.rowptr.data(), (n + 1) * 4, hipMemcpyHostToDevice,
-                                    B->stream));
-    if (nnz) {
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(d_col, R.col.data(), nnz * 4, hipMemcpyHostToDevice,
-                                      B->stream));
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(d_val, R.val.data(), nnz * 8, hipMemcpyHostToDevice,
+    // the matrix and b are packed in the pinned stage in their arena layout
+    // and travel in one copy
+    const size_t in_bytes = (size_t)((char*)d_x - p);
+    if (via_stage) {
+      char* sp = B->up_stage + staged;
+      std::memcpy(sp, R.rowptr.data(), (n + 1) * 4);
+      std::memcpy(sp + ((char*)d_col - p), R.col.data(), nnz * 4);
+      std::memcpy(sp + ((char*)d_val - p), R.val.data(), nnz * 8);
+      std::memcpy(sp + ((char*)d_b - p), R.b.data(), n * 8);
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(p, sp, in_bytes, hipMemcpyHostToDevice, B->stream));
+      staged += up(in_bytes);
+    } else {  // larger than the stage: copy from the request's own buffers
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(d_rp, R.rowptr.data(), (n + 1) * 4,
+                                      hipMemcpyHostToDevice, B->stream));
+      if (nnz) {
+        MXS_HIP_TRY(ctx, hipMemcpyAsync(d_col, R.col.data(), nnz * 4, hipMemcpyHostToDevice,
+                                        B->stream));
+        MXS_HIP_TRY(ctx, hipMemcpyAsync(d_val, R.val.data(), nnz * 8, hipMemcpyHostToDevice,
+                                        B->stream));
+      }
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(d_b, R.b.data(), n * 8, hipMemcpyHostToDevice,
                                       B->stream));
     }
-    MXS_HIP_TRY(ctx, hipMemcpyAsync(d_b, R.b.data(), n * 8, hipMemcpyHostToDevice, B->stream));
     SlotDesc& d = B->h_slots[si];
     std::memset(&d, 0, sizeof(d));
     d.rowptr = d_rp;

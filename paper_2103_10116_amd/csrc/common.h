@@ -76,8 +76,10 @@ struct CsrPart {
   int32_t* bnnz = nullptr;    // first entry of each block (nblocks + 1)
   int64_t nblocks = 0;
   int block_nnz = 512;
-  int lanes = 0;
+  int lanes = 0;  // 0: stream kernel; 1: thread per row; >1: lanes per row
   int rpg = 4;
+  int wpb = 4;    // stream kernel: independent waves per work-group (1 or 4)
+  bool rows_lds = false;  // rows-from-LDS kernel (blocks of <= 64 rows, block_nnz entries)
 };
 
 // COO: equal chunks of block_nnz entries, one wave per chunk.  Rows cut by
@@ -94,6 +96,7 @@ struct CooPart {
   void* cont_val = nullptr;
   int32_t* empty_rows = nullptr;
   int64_t nempty = 0;
+  int wpb = 4;  // independent waves per work-group (1 or 4)
 };
 
 // ELL: column-major padded slots; `waves` waves per 64 rows split the
@@ -140,7 +143,7 @@ inline size_t value_bytes(mxs_dtype dt) {
 mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, const void* x,
                        const void* beta, void* y, const int32_t* skip);
 int64_t csr_partition(const int32_t* rowptr, int64_t n, int block_nnz,
-                      std::vector<int32_t>& blocks);
+                      std::vector<int32_t>& blocks, int64_t max_rows = -1);
 
 }  // namespace mxs
 

@@ -27,7 +27,9 @@ void* mat_alloc(mxs_matrix* A, size_t bytes) {
 // Greedy row-block partition: consecutive rows are packed while the block
 // holds at most `C` entries and `C` rows; a row longer than C is a block of
 // its own.  Returns the block count; blocks[b]..blocks[b+1] are the rows.
-int64_t csr_partition(const int32_t* rp, int64_t n, int C, std::vector<int32_t>& blocks) {
+int64_t csr_partition(const int32_t* rp, int64_t n, int C, std::vector<int32_t>& blocks,
+                      int64_t max_rows) {
+  if (max_rows < 0) max_rows = C;
   blocks.clear();
   blocks.push_back(0);
   int64_t cur_nnz = 0, cur_rows = 0;
@@ -39,7 +41,7 @@ int64_t csr_partition(const int32_t* rp, int64_t n, int C, std::vector<int32_t>&
       cur_nnz = cur_rows = 0;
       continue;
     }
-    if (cur_rows && (cur_nnz + L > C || cur_rows + 1 > C)) {
+    if (cur_rows && (cur_nnz + L > C || cur_rows + 1 > max_rows)) {
       blocks.push_back((int32_t)i);
       cur_nnz = cur_rows = 0;
     }
@@ -279,20 +281,38 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
   while (G < 64 && G < mean) G <<= 1;
   const int kind = opts ? opts->csr_kernel : MXS_CSR_AUTO;
   if (opts && opts->lanes_per_row > 0) {
-    G = 4;
+    G = 1;
     while (G < 64 && G < opts->lanes_per_row) G <<= 1;
+    if (G == 2) G = 4;
   }
   // AUTO keeps the stream kernel: on the stencil matrices it gathers x with
   // fewer cache lines per instruction than the lanes-along-a-row layout
-  (void)maxL;
-  bool vec = kind == MXS_CSR_VECTOR;
+  // AUTO: rows-from-LDS when every row fits a lane's walk (longest row <=
+  // 64 entries), else the row-block stream kernel (power-law rows)
+  int kind_eff = kind;
+  if (kind == MXS_CSR_AUTO) kind_eff = maxL <= 64 ? MXS_CSR_ROWS_LDS : MXS_CSR_STREAM;
+  bool vec = kind_eff == MXS_CSR_VECTOR;
   A->csr.lanes = vec ? G : 0;
+  A->csr.wpb = (opts && opts->waves_per_group == 1) ? 1 : 4;
   int rpg = (opts && opts->rows_per_group > 0) ? opts->rows_per_group : (G >= 8 ? 8 : 4);
   A->csr.rpg = rpg <= 2 ? 2 : rpg <= 4 ? 4 : 8;
   if (A->csr.rpg > G) A->csr.rpg = G;
   std::vector<int32_t> blocks, bnnz;
+  A->csr.rows_lds = kind_eff == MXS_CSR_ROWS_LDS;
+  if (A->csr.rows_lds) {
+    // rows-from-LDS blocks: at most 64 rows; entry budget 64 * (longest row)
+    // rounded up to 512 or 1024 (2048 only on request: its LDS footprint
+    // halves the waves per CU); rows longer than it get a wave of their own
+    const int64_t want = 64 * std::max<int64_t>(maxL, 1);
+    block_nnz = want <= 512 ? 512 : 1024;
+    if (opts && opts->block_nnz > 0) block_nnz = opts->block_nnz <= 512 ? 512
+                                                : opts->block_nnz <= 1024 ? 1024 : 2048;
+  } else if (kind == MXS_CSR_AUTO && !(opts && opts->block_nnz > 0)) {
+    block_nnz = 1024;
+  }
   A->csr.block_nnz = block_nnz;
-  A->csr.nblocks = csr_partition(rp.data(), A->n, block_nnz, blocks);
+  A->csr.nblocks = csr_partition(rp.data(), A->n, block_nnz, blocks,
+                                 A->csr.rows_lds ? 64 : -1);
   bnnz.resize(blocks.size());
   for (size_t b = 0; b < blocks.size(); ++b) bnnz[b] = rp[blocks[b]];
   A->csr.blocks = upload(ctx, A, blocks);
@@ -305,7 +325,8 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
 }
 
 mxs_status setup_coo_part(mxs_ctx* ctx, mxs_matrix* A, mxs::CooPart& P, int64_t nnz,
-                          int block_nnz, const std::vector<int32_t>& empty) {
+                          int block_nnz, const std::vector<int32_t>& empty, int wpb) {
+  P.wpb = wpb == 1 ? 1 : 4;
   P.nnz = nnz;
   P.block_nnz = block_nnz;
   P.nchunks = (nnz + block_nnz - 1) / block_nnz;
@@ -374,7 +395,7 @@ mxs_status convert_typed(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, mxs_f
     std::vector<int32_t> empty;
     for (int64_t i = 0; i < n; ++i)
       if (hrp[i + 1] == hrp[i]) empty.push_back((int32_t)i);
-    return setup_coo_part(ctx, A, A->coo, nnz, bnnz, empty);
+    return setup_coo_part(ctx, A, A->coo, nnz, bnnz, empty, opts ? opts->waves_per_group : 0);
   }
 
   // ELL and HYB
@@ -441,7 +462,7 @@ mxs_status convert_typed(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, mxs_f
         (V*)A->coo.val, d_err);
     MXS_HIP_TRY(ctx, hipGetLastError());
   }
-  return setup_coo_part(ctx, A, A->coo, cnnz, bnnz, empty);
+  return setup_coo_part(ctx, A, A->coo, cnnz, bnnz, empty, opts ? opts->waves_per_group : 0);
 }
 
 }  // namespace
@@ -622,6 +643,7 @@ mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
   out->block_nnz = A->fmt == MXS_CSR ? A->csr.block_nnz : A->coo.block_nnz;
   out->lanes_per_row = A->fmt == MXS_CSR ? A->csr.lanes : 0;
   out->rows_per_group = A->fmt == MXS_CSR ? A->csr.rpg : 0;
+  out->waves_per_group = A->fmt == MXS_CSR ? A->csr.wpb : A->coo.wpb;
   out->bytes = A->bytes;
   return MXS_OK;
 }

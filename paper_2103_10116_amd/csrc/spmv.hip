@@ -44,21 +44,34 @@ __device__ __forceinline__ T combine(T alpha, T s, T beta, const T* __restrict__
 // ---------------------------------------------------------------------------
 // CSR
 // ---------------------------------------------------------------------------
-template <typename V, typename T, int NPL, bool SCALED>
-__global__ __launch_bounds__(64) void k_csr(const int32_t* __restrict__ blocks,
-                                            const int32_t* __restrict__ bnnz,
-                                            const int32_t* __restrict__ rowptr,
-                                            const int32_t* __restrict__ col,
-                                            const V* __restrict__ val,
-                                            const float* __restrict__ scale,
-                                            const T* __restrict__ x, T* __restrict__ y, T alpha,
-                                            T beta, const int32_t* __restrict__ skip) {
+// Synchronises the lanes of one wave (LDS written by some lanes is then
+// visible to the others); the waves of a work-group stay independent.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename V, typename T, int NPL, bool SCALED, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_csr(int64_t nblocks,
+                                                  const int32_t* __restrict__ blocks,
+                                                  const int32_t* __restrict__ bnnz,
+                                                  const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const V* __restrict__ val,
+                                                  const float* __restrict__ scale,
+                                                  const T* __restrict__ x, T* __restrict__ y,
+                                                  T alpha, T beta,
+                                                  const int32_t* __restrict__ skip) {
   constexpr int C = 64 * NPL;
-  __shared__ T prod[C + C / 32];
-  __shared__ int32_t rp[C + 1];
+  __shared__ T prod_all[WPB][C + C / 32];
+  __shared__ int32_t rp_all[WPB][C + 1];
   if (skip && *skip) return;
-  const int lane = threadIdx.x;
-  const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  T* prod = prod_all[wv];
+  int32_t* rp = rp_all[wv];
+  const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if (b >= nblocks) return;
   const int32_t r0 = blocks[b], r1 = blocks[b + 1];
   const int32_t s = bnnz[b], e = bnnz[b + 1];  // = rowptr[r0], rowptr[r1]
   const int nr = r1 - r0, len = e - s;
@@ -107,7 +120,7 @@ __global__ __launch_bounds__(64) void k_csr(const int32_t* __restrict__ blocks,
       if (k < len) prod[pad(k)] = v[t] * x[c[t]];
     }
   }
-  __syncthreads();
+  wave_sync();
 
   for (int i = lane; i < nr; i += 64)
     if (rp[i] == rp[i + 1]) emit(i, T(0));  // empty rows
@@ -242,23 +255,154 @@ __global__ __launch_bounds__(256) void k_csr_vec(int64_t n, const int32_t* __res
 }
 
 // ---------------------------------------------------------------------------
+// CSR, rows from LDS: a wave owns a block of at most 64 rows and CMAX
+// entries.  It copies the block's column indices and values into LDS with
+// fully coalesced loads, then lane i walks row i out of LDS, so the x
+// gathers of one step come from 64 neighbouring rows (contiguous on banded
+// and stencil matrices, as in ELL) while HBM sees only contiguous reads.  A
+// row longer than CMAX is a block of its own and takes the whole wave.
+// ---------------------------------------------------------------------------
+template <typename V, typename T, int CMAX, bool SCALED, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
+                                                     const int32_t* __restrict__ blocks,
+                                                     const int32_t* __restrict__ bnnz,
+                                                     const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const V* __restrict__ val,
+                                                     const float* __restrict__ scale,
+                                                     const T* __restrict__ x, T* __restrict__ y,
+                                                     T alpha, T beta,
+                                                     const int32_t* __restrict__ skip) {
+  __shared__ V vl_all[WPB][CMAX];
+  __shared__ int32_t cl_all[WPB][CMAX];
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  V* vl = vl_all[wv];
+  int32_t* cl = cl_all[wv];
+  const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if (b >= nblocks) return;
+  const int32_t r0 = blocks[b], r1 = blocks[b + 1];
+  const int32_t s = bnnz[b], e = bnnz[b + 1];
+  const int nr = r1 - r0, len = e - s;
+  if (len > CMAX) {  // a single long row
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int32_t k = s + lane;
+    for (; k + 192 < e; k += 256) {
+      const int32_t c0 = col[k], c1 = col[k + 64], c2 = col[k + 128], c3 = col[k + 192];
+      const T v0 = to_acc(val[k]), v1 = to_acc(val[k + 64]), v2 = to_acc(val[k + 128]),
+              v3 = to_acc(val[k + 192]);
+      a0 += v0 * x[c0];
+      a1 += v1 * x[c1];
+      a2 += v2 * x[c2];
+      a3 += v3 * x[c3];
+    }
+    for (; k < e; k += 64) a0 += to_acc(val[k]) * x[col[k]];
+    T acc = wave_sum((a0 + a1) + (a2 + a3));
+    if (lane == 0) {
+      if (SCALED) acc *= (T)scale[r0];
+      y[r0] = combine(alpha, acc, beta, y, r0);
+    }
+    return;
+  }
+  const int32_t ra = lane < nr ? rowptr[r0 + lane] - s : 0;
+  const int32_t rb = lane < nr ? rowptr[r0 + lane + 1] - s : 0;
+  // coalesced copy into LDS, eight loads per lane in flight per round
+  for (int base = 0; base < len; base += 8 * 64) {
+    int32_t c[8];
+    V v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = base + t * 64 + lane;
+      if (k < len) {
+        c[t] = col[s + k];
+        v[t] = val[s + k];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = base + t * 64 + lane;
+      if (k < len) {
+        cl[k] = c[t];
+        vl[k] = v[t];
+      }
+    }
+  }
+  wave_sync();
+  if (lane >= nr) return;
+  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int32_t k = ra;
+  for (; k + 3 < rb; k += 4) {
+    s0 += to_acc(vl[k]) * x[cl[k]];
+    s1 += to_acc(vl[k + 1]) * x[cl[k + 1]];
+    s2 += to_acc(vl[k + 2]) * x[cl[k + 2]];
+    s3 += to_acc(vl[k + 3]) * x[cl[k + 3]];
+  }
+  for (; k < rb; ++k) s0 += to_acc(vl[k]) * x[cl[k]];
+  T sum = (s0 + s1) + (s2 + s3);
+  const int64_t i = (int64_t)r0 + lane;
+  if (SCALED) sum *= (T)scale[i];
+  y[i] = combine(alpha, sum, beta, y, i);
+}
+
+// ---------------------------------------------------------------------------
+// CSR, one thread per row: neighbouring lanes hold neighbouring rows, so on
+// banded/stencil matrices the x gathers of one instruction are contiguous
+// (as in ELL); the row's entries stream through the L1 over the iterations
+// of the lane's loop.  Four independent accumulators per lane.
+// ---------------------------------------------------------------------------
+template <typename V, typename T, bool SCALED>
+__global__ __launch_bounds__(256) void k_csr_row(int64_t n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const V* __restrict__ val,
+                                                 const float* __restrict__ scale,
+                                                 const T* __restrict__ x, T* __restrict__ y,
+                                                 T alpha, T beta,
+                                                 const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int32_t a = rowptr[i], e = rowptr[i + 1];
+  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int32_t k = a;
+  for (; k + 3 < e; k += 4) {
+    const int32_t c0 = col[k], c1 = col[k + 1], c2 = col[k + 2], c3 = col[k + 3];
+    const T v0 = to_acc(val[k]), v1 = to_acc(val[k + 1]), v2 = to_acc(val[k + 2]),
+            v3 = to_acc(val[k + 3]);
+    s0 += v0 * x[c0];
+    s1 += v1 * x[c1];
+    s2 += v2 * x[c2];
+    s3 += v3 * x[c3];
+  }
+  for (; k < e; ++k) s0 += to_acc(val[k]) * x[col[k]];
+  T sum = (s0 + s1) + (s2 + s3);
+  if (SCALED) sum *= (T)scale[i];
+  y[i] = combine(alpha, sum, beta, y, i);
+}
+
+// ---------------------------------------------------------------------------
 // COO
 // ---------------------------------------------------------------------------
-template <typename V, typename T, int NPL, bool ACCUM>
-__global__ __launch_bounds__(64) void k_coo(int64_t nnz, const int32_t* __restrict__ row,
-                                            const int32_t* __restrict__ col,
-                                            const V* __restrict__ val, const T* __restrict__ x,
-                                            T* __restrict__ y, T alpha, T beta,
-                                            int32_t* __restrict__ cont_row,
-                                            T* __restrict__ cont_val,
-                                            const int32_t* __restrict__ skip) {
+template <typename V, typename T, int NPL, bool ACCUM, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
+                                                  const int32_t* __restrict__ row,
+                                                  const int32_t* __restrict__ col,
+                                                  const V* __restrict__ val,
+                                                  const T* __restrict__ x, T* __restrict__ y,
+                                                  T alpha, T beta,
+                                                  int32_t* __restrict__ cont_row,
+                                                  T* __restrict__ cont_val,
+                                                  const int32_t* __restrict__ skip) {
   constexpr int C = 64 * NPL;
   if (skip && *skip) return;
-  __shared__ T prod[C + C / 32];
-  __shared__ int32_t rw[C + C / 32];
-  __shared__ int32_t edge[2];
-  const int lane = threadIdx.x;
-  const int64_t ch = xcd_remap(blockIdx.x, gridDim.x);
+  __shared__ T prod_all[WPB][C + C / 32];
+  __shared__ int32_t rw_all[WPB][C + C / 32];
+  __shared__ int32_t edge_all[WPB][2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  T* prod = prod_all[wv];
+  int32_t* rw = rw_all[wv];
+  int32_t* edge = edge_all[wv];
+  const int64_t ch = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if (ch >= nchunks) return;
   const int64_t s = ch * C;
   const int len = (int)((nnz - s) < C ? (nnz - s) : C);
   if (lane == 0) {
@@ -288,7 +432,7 @@ __global__ __launch_bounds__(64) void k_coo(int64_t nnz, const int32_t* __restri
       }
     }
   }
-  __syncthreads();
+  wave_sync();
   const int32_t first = rw[0];
   const bool first_continues = edge[0] == first;
 
@@ -450,11 +594,58 @@ void launch_csr_vec(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T be
         A->n, P.rowptr, P.col, val, P.scale, x, y, alpha, beta, skip);
 }
 
+template <typename V, typename T, bool SCALED, int WPB>
+void launch_csr_stream(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
+                       const int32_t* skip) {
+  const V* val = (const V*)P.val;
+  const dim3 grid((unsigned)((P.nblocks + WPB - 1) / WPB));
+  switch (P.block_nnz) {
+    case 256:
+      k_csr<V, T, 4, SCALED, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, val, P.scale, x, y, alpha, beta, skip);
+      break;
+    case 1024:
+      k_csr<V, T, 16, SCALED, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, val, P.scale, x, y, alpha, beta, skip);
+      break;
+    default:
+      k_csr<V, T, 8, SCALED, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, val, P.scale, x, y, alpha, beta, skip);
+  }
+}
+
+template <typename V, typename T, bool SCALED, int CMAX>
+void launch_csr_rl(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
+                   const int32_t* skip) {
+  constexpr int WPB = 2;
+  const dim3 grid((unsigned)((P.nblocks + WPB - 1) / WPB));
+  k_csr_rl<V, T, CMAX, SCALED, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+      P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
+      skip);
+}
+
 template <typename V, typename T, bool SCALED>
 void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
                 const int32_t* skip) {
   const CsrPart& P = A->csr;
-  if (P.lanes > 0) {
+  if (P.rows_lds) {
+    if (P.nblocks == 0) return;
+    if (P.block_nnz <= 512)
+      launch_csr_rl<V, T, SCALED, 512>(ctx, P, alpha, x, beta, y, skip);
+    else if (P.block_nnz <= 1024)
+      launch_csr_rl<V, T, SCALED, 1024>(ctx, P, alpha, x, beta, y, skip);
+    else
+      launch_csr_rl<V, T, SCALED, 2048>(ctx, P, alpha, x, beta, y, skip);
+    return;
+  }
+  if (P.lanes == 1) {
+    const dim3 grid((unsigned)((A->n + 255) / 256));
+    k_csr_row<V, T, SCALED><<<grid, 256, 0, ctx->stream>>>(A->n, P.rowptr, P.col,
+                                                          (const V*)P.val, P.scale, x, y,
+                                                          alpha, beta, skip);
+    return;
+  }
+  if (P.lanes > 1) {
     switch (P.lanes) {
       case 4: launch_csr_vec<V, T, 4, SCALED>(ctx, A, alpha, x, beta, y, skip); break;
       case 8: launch_csr_vec<V, T, 8, SCALED>(ctx, A, alpha, x, beta, y, skip); break;
@@ -465,23 +656,30 @@ void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, 
     return;
   }
   if (P.nblocks == 0) return;
+  if (P.wpb == 4)
+    launch_csr_stream<V, T, SCALED, 4>(ctx, P, alpha, x, beta, y, skip);
+  else
+    launch_csr_stream<V, T, SCALED, 1>(ctx, P, alpha, x, beta, y, skip);
+}
+
+template <typename V, typename T, bool ACCUM, int WPB>
+void launch_coo_chunks(mxs_ctx* ctx, const CooPart& P, T alpha, const T* x, T beta, T* y,
+                       const int32_t* skip) {
   const V* val = (const V*)P.val;
-  const dim3 grid((unsigned)P.nblocks);
+  const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
+  T* cv = (T*)P.cont_val;
   switch (P.block_nnz) {
     case 256:
-      k_csr<V, T, 4, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.bnnz, P.rowptr, P.col,
-                                                           val, P.scale, x, y, alpha, beta,
-                                                           skip);
+      k_coo<V, T, 4, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
       break;
     case 1024:
-      k_csr<V, T, 16, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.bnnz, P.rowptr, P.col,
-                                                            val, P.scale, x, y, alpha, beta,
-                                                            skip);
+      k_coo<V, T, 16, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
       break;
     default:
-      k_csr<V, T, 8, SCALED><<<grid, 64, 0, ctx->stream>>>(P.blocks, P.bnnz, P.rowptr, P.col,
-                                                           val, P.scale, x, y, alpha, beta,
-                                                           skip);
+      k_coo<V, T, 8, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
   }
 }
 
@@ -492,25 +690,13 @@ void launch_coo(mxs_ctx* ctx, const CooPart& P, int64_t n, T alpha, const T* x, 
     k_empty_rows<T><<<(unsigned)((P.nempty + 255) / 256), 256, 0, ctx->stream>>>(
         P.nempty, P.empty_rows, y, beta, skip);
   if (P.nchunks == 0) return;
-  const V* val = (const V*)P.val;
-  const dim3 grid((unsigned)P.nchunks);
-  T* cv = (T*)P.cont_val;
-  switch (P.block_nnz) {
-    case 256:
-      k_coo<V, T, 4, ACCUM><<<grid, 64, 0, ctx->stream>>>(P.nnz, P.row, P.col, val, x, y, alpha,
-                                                          beta, P.cont_row, cv, skip);
-      break;
-    case 1024:
-      k_coo<V, T, 16, ACCUM><<<grid, 64, 0, ctx->stream>>>(P.nnz, P.row, P.col, val, x, y,
-                                                           alpha, beta, P.cont_row, cv, skip);
-      break;
-    default:
-      k_coo<V, T, 8, ACCUM><<<grid, 64, 0, ctx->stream>>>(P.nnz, P.row, P.col, val, x, y, alpha,
-                                                          beta, P.cont_row, cv, skip);
-  }
+  if (P.wpb == 4)
+    launch_coo_chunks<V, T, ACCUM, 4>(ctx, P, alpha, x, beta, y, skip);
+  else
+    launch_coo_chunks<V, T, ACCUM, 1>(ctx, P, alpha, x, beta, y, skip);
   if (P.nchunks > 1)
     k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
-        P.nchunks, P.cont_row, cv, y, alpha, skip);
+        P.nchunks, P.cont_row, (T*)P.cont_val, y, alpha, skip);
 }
 
 template <typename V, typename T>

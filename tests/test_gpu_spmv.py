@@ -181,14 +181,14 @@ def _check(y, ref, scale, tol):
 
 @pytest.mark.parametrize("name", sorted(ZOO))
 @pytest.mark.parametrize("fmt", FORMATS)
-@pytest.mark.parametrize("block_nnz", [0, 256, 1024])
-def test_spmv_f64(env, orc, name, fmt, block_nnz):
+@pytest.mark.parametrize("block_nnz,wpg", [(0, 0), (256, 1), (1024, 4), (512, 1)])
+def test_spmv_f64(env, orc, name, fmt, block_nnz, wpg):
     mxs, ctx, torch = env
     A = ZOO[name]
     if block_nnz and fmt in ("ell", "hyb") and name != "zipf_3000":
         pytest.skip("block size only changes the CSR/COO work units")
     M = mxs.Matrix.from_host(ctx, A)
-    B = M.convert(fmt, "f64", block_nnz=block_nnz)
+    B = M.convert(fmt, "f64", block_nnz=block_nnz, waves_per_group=wpg)
     x = I.uniform_vector(A.ncols, 11)
     y0 = I.uniform_vector(A.n, 12)
     xd = _dev(torch, x)
@@ -202,9 +202,12 @@ def test_spmv_f64(env, orc, name, fmt, block_nnz):
         _check(y.cpu().numpy(), ref, scale, 1e-13)
 
 
-CSR_VARIANTS = [dict(csr_kernel="stream", block_nnz=b) for b in (256, 512, 1024)] + [
+CSR_VARIANTS = [dict(csr_kernel="stream", block_nnz=b, waves_per_group=w)
+                for b in (256, 512, 1024) for w in (1, 4)] + [
     dict(csr_kernel="vector", lanes_per_row=g, rows_per_group=r)
-    for g in (4, 8, 16, 32, 64) for r in (2, 4, 8)]
+    for g in (4, 8, 16, 32, 64) for r in (2, 4, 8)] + [
+    dict(csr_kernel="vector", lanes_per_row=1)] + [
+    dict(csr_kernel="rows_lds", block_nnz=b) for b in (0, 512, 1024, 2048)]
 
 
 @pytest.mark.parametrize("name", sorted(ZOO))
@@ -235,6 +238,8 @@ def test_spmv_csr_kernels(env, orc, name, dt):
         B = M.convert("csr", dt, **opts)
         d = B.info()
         assert (d["lanes_per_row"] > 0) == (opts["csr_kernel"] == "vector")
+        if opts["csr_kernel"] == "rows_lds" and opts["block_nnz"]:
+            assert d["block_nnz"] == opts["block_nnz"]
         y = torch.from_numpy(y0r).to(tdt).cuda()
         mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
         _check(y.cpu().numpy().astype(np.float64), ref, scale, tol)
