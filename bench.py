@@ -373,7 +373,8 @@ def main():
         systems = serve.build_systems(closed)
         sv = {"requests": count, "tol": 1e-10,
               "system": "weighted 5-point Laplacian, m x m grid, m ~ U{8..96}, diagonal shift U[0,1]"}
-        bkw = dict(budget_bytes=4 << 30, max_slots=2048, iters_per_step=16, classes=classes)
+        bkw = dict(budget_bytes=4 << 30, max_slots=2048, iters_per_step=16, classes=classes,
+                   staging_bytes=4 << 30)
         rb = serve.run_batched(ctx, closed, systems, **bkw)
         sv["batched_closed"] = rb.summary()
         log("batched closed", sv["batched_closed"])

@@ -274,10 +274,13 @@ typedef struct {
   int32_t class_max_n[8];   /* increasing upper bounds of n per class */
   int32_t class_block[8];   /* threads per system: 128, 256, 512 or 1024 (autotuner output) */
   int32_t class_slots[8];   /* slots per class; 0 = an even share of the rest */
+  size_t staging_bytes;     /* pinned host pool holding submitted inputs until their first
+                               step; 0 = min(budget_bytes, 1 GiB).  Requests beyond it are
+                               kept as ordinary host copies and packed at admission. */
 } mxs_batch_opts;
 
 typedef struct {
-  int32_t active;           /* slots holding a system after this step's admission */
+  int32_t active;           /* slots still holding a system after this step */
   int32_t pending;          /* submitted, not yet admitted */
   int32_t slots;
   int32_t reserved;
@@ -288,17 +291,44 @@ typedef struct {
 mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch** out);
 mxs_status mxs_batch_destroy(mxs_batch* batch);
 
-/* Queues A x = b (host CSR arrays and b, copied; x0 = 0) to relative
- * tolerance rel_tol (relative to ||b||).  MXS_BUDGET if its footprint alone
- * exceeds the arena, MXS_UNSUPPORTED if n exceeds the largest class,
- * MXS_INVALID_MATRIX if the CSR is malformed (checked on the host). */
+/* Queues A x = b (host CSR arrays and b, copied before the call returns;
+ * x0 = 0) to relative tolerance rel_tol (relative to ||b||).  MXS_BUDGET if
+ * its footprint alone exceeds the arena (or its inputs the pinned staging
+ * pool), MXS_UNSUPPORTED if n exceeds the
+ * largest class, MXS_INVALID_MATRIX if the CSR is malformed (checked on the
+ * host). */
 mxs_status mxs_batch_submit(mxs_batch* batch, int64_t n, int64_t nnz, const int32_t* rowptr,
                             const int32_t* col, const double* val, const double* b,
                             double rel_tol, int64_t max_iters, uint64_t* ticket);
 
-/* One step: retire the systems the previous step finished, admit waiting
- * requests, run iters_per_step CG iterations on every resident system and
- * read their status back.  Synchronous. */
+/* One request of mxs_batch_submit_many: the arguments of mxs_batch_submit. */
+typedef struct {
+  int64_t n, nnz;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const double* b;
+  double rel_tol;
+  int64_t max_iters;        /* 0 = 20000 */
+} mxs_batch_request;
+
+/* Queues `count` requests as mxs_batch_submit would, validating and
+ * packing them on up to 16 host threads.  tickets[i] receives request i's
+ * ticket (0 if it was rejected) and statuses[i] its status (the codes of
+ * mxs_batch_submit); tickets are issued in array order.  Returns
+ * MXS_INVALID_ARG for bad arguments of the call itself, else MXS_OK. */
+mxs_status mxs_batch_submit_many(mxs_batch* batch, int64_t count, const mxs_batch_request* reqs,
+                                 uint64_t* tickets, mxs_status* statuses);
+
+/* One step: admit waiting requests, run iters_per_step CG iterations on
+ * every resident system, read their states back and retire the systems
+ * that finished (their results can be polled when this returns).
+ * Synchronous.  Per step the host exchanges three things with the device
+ * whatever the number of requests: the slot descriptor table (up), the
+ * slot state table (down) and the graph launch; a new slot's inputs are
+ * pulled by its work-group from pinned host memory (packed there once at
+ * submit) and a finished slot's x is written by its work-group into pinned
+ * host memory. */
 mxs_status mxs_batch_step(mxs_batch* batch, mxs_batch_stats* stats);
 
 /* MXS_PENDING while the request runs or waits; otherwise copies x (n

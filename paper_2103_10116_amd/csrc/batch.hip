@@ -1,28 +1,38 @@
 // batch.hip -- batched persistent CG and the continuous-batching engine.
 //
 // Many independent SPD systems are solved by one kernel per size class:
-// work-group i owns slot i, keeps the search direction p in LDS (the
-// gathers of its SpMV never leave the CU) and x, r, p, q in registers for
-// the rows it owns, and runs up to K CG iterations per launch (the CG of
-// Saad 2003, ch. 6, with the true-residual check and up to three residual
-// replacements).  The state is written back to HBM at the end of a launch,
-// so launches can be repeated until every slot has finished.  A system's
+// work-group i owns slot i, keeps the slot's row pointers and the search
+// direction p in LDS (the gathers of its SpMV never leave the CU) and x, r
+// and q of the rows it owns in registers, and runs up to K CG iterations per
+// launch (the CG of Saad 2003, ch. 6, with the true-residual check and up to
+// three residual replacements).  The state is written back to HBM at the end
+// of a launch, so launches repeat until every slot has finished.  A system's
 // arithmetic depends only on its own data and on the threads-per-system of
 // its size class (a function of n), never on the other slots, so a result
 // is bitwise the same alone and in any mix.
 //
+// Host/device traffic per step is three transfers whatever the number of
+// requests: the host-written descriptor table goes up in one copy, the
+// kernel-written state table comes back in one copy, and a newly admitted
+// slot's work-group pulls the request's packed inputs (CSR arrays and b,
+// packed once at submit into pinned host memory in the slot's arena
+// layout) into the arena on its first launch.  A finished slot's
+// work-group writes x straight into the slot's pinned host output.
+//
 // The host engine owns a device arena of `budget_bytes` managed first-fit,
-// a slot table in device memory, a FIFO of submitted requests, and one
-// hipGraph per step (one kernel per class + the status read-back).  Each
-// mxs_batch_step retires finished slots, admits waiting requests whose
-// footprint fits the arena and whose class has a free slot, uploads them,
-// and launches the graph.
+// the slot tables, a FIFO of submitted requests and one hipGraph per step
+// (one kernel per class, on parallel branches, then the state read-back).
+// Each mxs_batch_step admits waiting requests whose footprint fits the
+// arena and whose class has a free slot, launches the graph, waits for it,
+// and retires the slots that finished.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <new>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -41,20 +51,30 @@ enum : int32_t {
   SLOT_NOTCONV = 6
 };
 
+// written by the host, uploaded before every launch
 struct SlotDesc {
-  const int32_t* rowptr;
-  const int32_t* col;
-  const double* val;
-  const double* b;
+  int32_t* rowptr;     // arena: rowptr | col | val | b | x | r | p
+  int32_t* col;
+  double* val;
+  double* b;
   double* x;
   double* r;
   double* p;
+  const uint4* src;    // pinned host: rowptr | col | val | b in the same layout
+  double* xout;        // pinned host: x of a finished system
   double tol;
-  double rho, thr, res2;
   int32_t n, nnz;
   int32_t max_iters;
   int32_t active;
-  int32_t iters, status, repl, pad;
+  uint32_t gen;        // admission number; the state's gen differs until the first launch
+  int32_t in_words;    // 16-byte words from src to rowptr
+};
+
+// written by the kernel, read back after every launch
+struct SlotState {
+  double rho, thr, res2;
+  int32_t iters, status, repl;
+  uint32_t gen;
 };
 
 template <int BS>
@@ -126,22 +146,43 @@ __device__ __forceinline__ void rows_times(const int32_t* __restrict__ rpl,
 // slot's p array in HBM serves as the gather vector.  x, r and q of the
 // thread's rows live in registers for the whole launch.
 template <int BS, int RPT, bool USE_LDS>
-__global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, int base, int K,
+__global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ desc,
+                                                 SlotState* __restrict__ state, int base, int K,
                                                  int vec_cap) {
   extern __shared__ double dyn[];
   __shared__ double red[BS / 64];
   __shared__ int ired[BS / 64];
-  SlotDesc* S = slots + base + blockIdx.x;
-  if (!S->active || S->status >= SLOT_CONVERGED) return;
-  const int n = S->n;
-  const int32_t* __restrict__ rp = S->rowptr;
-  const int32_t* __restrict__ col = S->col;
-  const double* __restrict__ val = S->val;
-  const double* __restrict__ b = S->b;
-  double* __restrict__ pg = S->p;
+  const SlotDesc& D = desc[base + blockIdx.x];
+  SlotState* S = state + base + blockIdx.x;
+  if (!D.active) return;
+  const bool fresh = S->gen != D.gen;
+  if (!fresh && S->status >= SLOT_CONVERGED) return;
+  const int n = D.n;
+  const int tid = threadIdx.x;
+  if (fresh) {
+    // first launch: pull the packed inputs from pinned host memory
+    const uint4* __restrict__ src = D.src;
+    uint4* __restrict__ dst = (uint4*)D.rowptr;
+    const int words = D.in_words;
+    for (int w0 = tid; w0 < words; w0 += 4 * BS) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (w0 + u * BS < words) v[u] = src[w0 + u * BS];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (w0 + u * BS < words) dst[w0 + u * BS] = v[u];
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  const int32_t* __restrict__ rp = D.rowptr;
+  const int32_t* __restrict__ col = D.col;
+  const double* __restrict__ val = D.val;
+  const double* __restrict__ b = D.b;
+  double* __restrict__ pg = D.p;
   double* __restrict__ vec = USE_LDS ? dyn : pg;
   int32_t* rpl = (int32_t*)(dyn + (USE_LDS ? vec_cap : 0));
-  const int tid = threadIdx.x;
   int mylen = 0;
   for (int i = tid; i <= n; i += BS) rpl[i] = rp[i];
   __syncthreads();
@@ -154,8 +195,8 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
   double x[RPT], r[RPT], q[RPT];
   double rho, thr;
   int status = SLOT_RUN;
-  int it = S->iters, repl = S->repl;
-  if (S->status == SLOT_NEW) {
+  int it = 0, repl = 0;
+  if (fresh) {
     // x0 = 0: r = b, p = r, thr = tol * ||b||
     double acc = 0.0;
 #pragma unroll
@@ -167,19 +208,21 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
       acc += r[k] * r[k];
     }
     rho = bsum<BS>(acc, red);
-    thr = S->tol * sqrt(rho);
+    thr = D.tol * sqrt(rho);
     if (!isfinite(rho)) status = SLOT_NONFINITE;
     if (rho == 0.0) status = SLOT_CONVERGED;  // b = 0: x = 0
   } else {
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      x[k] = i < n ? S->x[i] : 0.0;
-      r[k] = i < n ? S->r[i] : 0.0;
+      x[k] = i < n ? D.x[i] : 0.0;
+      r[k] = i < n ? D.r[i] : 0.0;
       if (USE_LDS && i < n) vec[i] = pg[i];
     }
     rho = S->rho;
     thr = S->thr;
+    it = S->iters;
+    repl = S->repl;
   }
   __syncthreads();
   double rr = rho;
@@ -251,7 +294,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
       __syncthreads();
       continue;
     }
-    if (it >= S->max_iters) {
+    if (it >= D.max_iters) {
       status = SLOT_MAXIT;
       break;
     }
@@ -264,14 +307,24 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
     }
     __syncthreads();
   }
-  // write the state back (p persists in HBM between launches)
+  if (status >= SLOT_CONVERGED) {
+    // finished: x goes straight to the slot's pinned host output
+    double* __restrict__ xo = D.xout;
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * BS;
-    if (i < n) {
-      S->x[i] = x[k];
-      S->r[i] = r[k];
-      if (USE_LDS) pg[i] = vec[i];
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) xo[i] = x[k];
+    }
+  } else {
+    // p persists in HBM between launches
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) {
+        D.x[i] = x[k];
+        D.r[i] = r[k];
+        if (USE_LDS) pg[i] = vec[i];
+      }
     }
   }
   if (tid == 0) {
@@ -281,6 +334,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(SlotDesc* __restrict__ slots, i
     S->iters = it;
     S->repl = repl;
     S->status = status;
+    S->gen = D.gen;
   }
 }
 
@@ -292,44 +346,33 @@ constexpr size_t kAlign = 256;
 
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-struct Request {
-  uint64_t ticket;
-  int64_t n, nnz;
-  std::vector<int32_t> rowptr, col;
-  std::vector<double> val, b;
-  double tol;
-  int64_t max_iters;
-  size_t bytes;
-  int cls;
+// arena layout of one system: rowptr | col | val | b | x | r | p
+struct Layout {
+  size_t col, val, b, x, r, p, total;
 };
 
-struct Result {
-  std::vector<double> x;
-  mxs_solve_info info;
-  bool done = false;
-};
+Layout layout(int64_t n, int64_t nnz) {
+  Layout L;
+  L.col = up((n + 1) * 4);
+  L.val = L.col + up(nnz * 4);
+  L.b = L.val + up(nnz * 8);
+  L.x = L.b + up(n * 8);
+  L.r = L.x + up(n * 8);
+  L.p = L.r + up(n * 8);
+  L.total = L.p + up(n * 8);
+  return L;
+}
 
-struct ClassCfg {
-  int max_n;
-  int block;  // threads per system
-  int rpt;
-  int slots;
-  int base;   // first slot index
-  bool lds;
-};
-
+// first-fit allocator over [0, size)
 struct Arena {
-  char* base = nullptr;
   size_t size = 0, used = 0;
   std::map<size_t, size_t> free_;  // offset -> length
-  void init(char* p, size_t s) {
-    base = p;
+  void init(size_t s) {
     size = s;
     free_.clear();
-    free_[0] = s;
+    if (s) free_[0] = s;
     used = 0;
   }
-  // first fit
   bool alloc(size_t bytes, size_t* off) {
     for (auto it = free_.begin(); it != free_.end(); ++it) {
       if (it->second >= bytes) {
@@ -362,12 +405,43 @@ struct Arena {
   }
 };
 
+struct Request {
+  uint64_t ticket;
+  int64_t n, nnz;
+  double tol;
+  int64_t max_iters;
+  size_t bytes;       // arena footprint
+  size_t in_bytes;    // packed inputs (rowptr | col | val | b)
+  int cls;
+  bool packed = false;   // inputs packed in the pinned input pool at in_off
+  size_t in_off = 0;
+  // copies of the inputs while the pinned pool had no room at submit
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> val, b;
+};
+
+struct Result {
+  std::vector<double> x;
+  mxs_solve_info info;
+  bool done = false;
+};
+
+struct ClassCfg {
+  int max_n;
+  int block;  // threads per system
+  int rpt;
+  int slots;
+  int base;   // first slot index
+  bool lds;
+};
+
 struct Slot {
   bool busy = false;
+  bool holds_input = false;  // its packed inputs are still in the pinned pool
   uint64_t ticket = 0;
   size_t off = 0, bytes = 0;
+  size_t in_off = 0, in_bytes = 0;
   int64_t n = 0;
-  double* x_dev = nullptr;
 };
 
 }  // namespace
@@ -376,11 +450,20 @@ struct Slot {
 struct mxs_batch {
   mxs_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
-  mxs::Arena arena;
-  void* arena_mem = nullptr;
-  mxs::SlotDesc* d_slots = nullptr;
-  mxs::SlotDesc* h_slots = nullptr;    // pinned: uploads
-  mxs::SlotDesc* h_status = nullptr;   // pinned: read-back of every step
+  mxs::Arena arena;                    // device memory
+  char* arena_mem = nullptr;
+  mxs::Arena inpool;                   // pinned host memory for packed inputs
+  char* in_mem = nullptr;              // host address
+  char* in_dev = nullptr;              // the same memory as the device sees it
+  double* xout_mem = nullptr;          // pinned: per-slot output regions (host address)
+  double* xout_dev = nullptr;
+  std::vector<size_t> xout_off;        // per slot, in doubles
+  mxs::SlotDesc* d_desc = nullptr;
+  mxs::SlotDesc* h_desc = nullptr;     // pinned
+  mxs::SlotState* d_state = nullptr;
+  mxs::SlotState* h_state = nullptr;   // pinned: read back by every step
+  bool desc_dirty = true;
+  uint32_t gen = 0;
   int nslots = 0;
   int K = 16;
   int nclasses = 0;
@@ -393,11 +476,6 @@ struct mxs_batch {
   hipGraphExec_t exec = nullptr;
   hipStream_t branch[mxs::kMaxClasses] = {};  // capture-time fork streams
   hipEvent_t fork = nullptr, join[mxs::kMaxClasses] = {};
-  char* up_stage = nullptr;    // pinned: request data on its way to the arena
-  size_t up_bytes = 0;
-  char* down_stage = nullptr;  // pinned: solutions on their way back
-  size_t down_bytes = 0;
-  bool launched = false;  // a step's graph is in flight / its status is fresh
   int64_t completed = 0;
   std::vector<uint64_t> newly_done;  // tickets retired since the last mxs_batch_completed
   uint64_t starve_ticket = 0;
@@ -407,11 +485,9 @@ struct mxs_batch {
 namespace mxs {
 namespace {
 
-size_t footprint(int64_t n, int64_t nnz) {
-  return up((n + 1) * 4) + up(nnz * 4) + up(nnz * 8) + 4 * up(n * 8);
-}
+size_t footprint(int64_t n, int64_t nnz) { return layout(n, nnz).total; }
 
-using BatchKernel = void (*)(SlotDesc*, int, int, int);
+using BatchKernel = void (*)(const SlotDesc*, SlotState*, int, int, int);
 
 // (block, rows per thread) -> kernel; rows per thread in {1, 2, 4, 6, 8, 10, 12, 16}
 constexpr int kRpt[] = {1, 2, 4, 6, 8, 10, 12, 16};
@@ -458,7 +534,7 @@ mxs_status build_graph(mxs_batch* B) {
     B->graph = nullptr;
   }
   // the class kernels are independent: each runs on its own branch of the
-  // graph (fork from the main stream, join back before the status copy)
+  // graph (fork from the main stream, join back before the state copy)
   MXS_HIP_TRY(ctx, hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
   (void)hipEventRecord(B->fork, B->stream);
   for (int c = 0; c < B->nclasses; ++c) {
@@ -466,12 +542,12 @@ mxs_status build_graph(mxs_batch* B) {
     if (C.slots == 0) continue;
     (void)hipStreamWaitEvent(B->branch[c], B->fork, 0);
     BatchKernel k = C.lds ? pick<true>(C.block, C.rpt) : pick<false>(C.block, C.rpt);
-    hipLaunchKernelGGL(k, dim3(C.slots), dim3(C.block), class_lds(C), B->branch[c], B->d_slots,
-                       C.base, B->K, C.max_n);
+    hipLaunchKernelGGL(k, dim3(C.slots), dim3(C.block), class_lds(C), B->branch[c], B->d_desc,
+                       B->d_state, C.base, B->K, C.max_n);
     (void)hipEventRecord(B->join[c], B->branch[c]);
     (void)hipStreamWaitEvent(B->stream, B->join[c], 0);
   }
-  (void)hipMemcpyAsync(B->h_status, B->d_slots, sizeof(SlotDesc) * B->nslots,
+  (void)hipMemcpyAsync(B->h_state, B->d_state, sizeof(SlotState) * B->nslots,
                        hipMemcpyDeviceToHost, B->stream);
   hipError_t e = hipStreamEndCapture(B->stream, &B->graph);
   if (e != hipSuccess) return fail(ctx, MXS_HIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -485,16 +561,47 @@ int class_of(const mxs_batch* B, int64_t n) {
   return -1;
 }
 
+// rowptr[0] = 0, rowptr[n] = nnz, rowptr monotone, 0 <= col < n and
+// columns strictly increasing within each row.  The increasing test runs
+// over all entries at once (a descent col[k] <= col[k-1] is allowed only
+// where a row starts), so the entry loops vectorise.
 bool validate_csr(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* col) {
   if (rp[0] != 0 || rp[n] != nnz) return false;
-  for (int64_t i = 0; i < n; ++i) {
-    if (rp[i + 1] < rp[i]) return false;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-      if (col[k] < 0 || col[k] >= n) return false;
-      if (k > rp[i] && col[k] <= col[k - 1]) return false;
-    }
+  int bad = 0;
+  for (int64_t i = 0; i < n; ++i) bad |= rp[i + 1] < rp[i];
+  if (bad) return false;
+  const uint32_t un = (uint32_t)n;
+  int64_t descents = 0;
+  for (int64_t k = 0; k < nnz; ++k) bad |= (uint32_t)col[k] >= un;
+  for (int64_t k = 1; k < nnz; ++k) descents += col[k] <= col[k - 1];
+  if (bad) return false;
+  // descents at row starts (each start position counted once)
+  int64_t allowed = 0;
+  for (int64_t i = 1; i < n; ++i) {
+    const int32_t s = rp[i];
+    if (s > rp[i - 1] && s < nnz) allowed += col[s] <= col[s - 1];
   }
-  return true;
+  return descents == allowed;
+}
+
+// packs rowptr | col | val | b at `dst` in the arena layout
+void pack(char* dst, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+          const double* val, const double* b) {
+  const Layout L = layout(n, nnz);
+  std::memcpy(dst, rp, (n + 1) * 4);
+  if (nnz) {
+    std::memcpy(dst + L.col, col, nnz * 4);
+    std::memcpy(dst + L.val, val, nnz * 8);
+  }
+  std::memcpy(dst + L.b, b, n * 8);
+}
+
+mxs_status upload_desc(mxs_batch* B) {
+  if (!B->desc_dirty) return MXS_OK;
+  MXS_HIP_TRY(B->ctx, hipMemcpyAsync(B->d_desc, B->h_desc, sizeof(SlotDesc) * B->nslots,
+                                     hipMemcpyHostToDevice, B->stream));
+  B->desc_dirty = false;
+  return MXS_OK;
 }
 
 }  // namespace
@@ -555,6 +662,7 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
     return fail(ctx, MXS_INVALID_ARG, "class_slots exceed max_slots");
   }
   int base = 0;
+  size_t xout_total = 0;
   for (int c = 0; c < nc; ++c) {
     ClassCfg& C = B->cls[c];
     C.max_n = max_n[c];
@@ -590,6 +698,10 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
       (void)hipGetLastError();
       C.lds = false;  // fall back to the gather vector in HBM
     }
+    for (int i = 0; i < C.slots; ++i) {
+      B->xout_off.push_back(xout_total);
+      xout_total += up((size_t)C.max_n * sizeof(double)) / sizeof(double);
+    }
     base += C.slots;
   }
   B->nclasses = nc;
@@ -606,36 +718,52 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
       st = fail(ctx, MXS_HIP, "stream or event creation failed");
       break;
     }
-    B->up_bytes = std::min<size_t>(opts->budget_bytes, (size_t)256 << 20);
-    B->down_bytes = (size_t)32 << 20;
-    if (hipHostMalloc((void**)&B->up_stage, B->up_bytes, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&B->down_stage, B->down_bytes, hipHostMallocDefault) !=
-            hipSuccess) {
-      st = fail(ctx, MXS_OOM, "pinned staging buffers");
+    // pinned host memory that kernels read (packed inputs) and write
+    // (finished iterates); the device addresses come from the runtime
+    const size_t in_size = up(opts->staging_bytes
+                                  ? opts->staging_bytes
+                                  : std::min<size_t>(opts->budget_bytes, (size_t)1 << 30));
+    // coherent: kernels see what the host packed, the host sees what
+    // kernels wrote, with no cache maintenance in between
+    const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc((void**)&B->in_mem, in_size, fl) != hipSuccess ||
+        hipHostMalloc((void**)&B->xout_mem, xout_total * sizeof(double), fl) != hipSuccess) {
+      st = fail(ctx, MXS_OOM, "pinned input / output pools");
       break;
     }
-    B->arena_mem = ctx->alloc.alloc(opts->budget_bytes);
+    if (hipHostGetDevicePointer((void**)&B->in_dev, B->in_mem, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&B->xout_dev, B->xout_mem, 0) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "device view of pinned host memory");
+      break;
+    }
+    B->inpool.init(in_size);
+    B->arena_mem = (char*)ctx->alloc.alloc(opts->budget_bytes);
     if (!B->arena_mem) {
       st = fail(ctx, MXS_OOM, "cannot allocate the %zu-byte batch arena", opts->budget_bytes);
       break;
     }
-    B->arena.init((char*)B->arena_mem, opts->budget_bytes / kAlign * kAlign);
-    B->d_slots = (SlotDesc*)ctx->alloc.alloc(sizeof(SlotDesc) * B->nslots);
-    if (!B->d_slots || hipHostMalloc((void**)&B->h_slots, sizeof(SlotDesc) * B->nslots,
-                                     hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&B->h_status, sizeof(SlotDesc) * B->nslots,
+    B->arena.init(opts->budget_bytes / kAlign * kAlign);
+    B->d_desc = (SlotDesc*)ctx->alloc.alloc(sizeof(SlotDesc) * B->nslots);
+    B->d_state = (SlotState*)ctx->alloc.alloc(sizeof(SlotState) * B->nslots);
+    if (!B->d_desc || !B->d_state ||
+        hipHostMalloc((void**)&B->h_desc, sizeof(SlotDesc) * B->nslots, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void**)&B->h_state, sizeof(SlotState) * B->nslots,
                       hipHostMallocDefault) != hipSuccess) {
       st = fail(ctx, MXS_OOM, "slot tables");
       break;
     }
-    std::memset(B->h_slots, 0, sizeof(SlotDesc) * B->nslots);
-    std::memset(B->h_status, 0, sizeof(SlotDesc) * B->nslots);
-    if (hipMemcpyAsync(B->d_slots, B->h_slots, sizeof(SlotDesc) * B->nslots,
+    std::memset(B->h_desc, 0, sizeof(SlotDesc) * B->nslots);
+    std::memset(B->h_state, 0, sizeof(SlotState) * B->nslots);
+    if (hipMemcpyAsync(B->d_desc, B->h_desc, sizeof(SlotDesc) * B->nslots,
+                       hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+        hipMemcpyAsync(B->d_state, B->h_state, sizeof(SlotState) * B->nslots,
                        hipMemcpyHostToDevice, B->stream) != hipSuccess ||
         hipStreamSynchronize(B->stream) != hipSuccess) {
       st = fail(ctx, MXS_HIP, "slot table upload failed");
       break;
     }
+    B->desc_dirty = false;
     st = build_graph(B);
   } while (0);
   if (st) {
@@ -653,12 +781,13 @@ mxs_status mxs_batch_destroy(mxs_batch* B) {
   if (B->graph) (void)hipGraphDestroy(B->graph);
   if (B->ctx) {
     B->ctx->alloc.release(B->arena_mem);
-    B->ctx->alloc.release(B->d_slots);
+    B->ctx->alloc.release(B->d_desc);
+    B->ctx->alloc.release(B->d_state);
   }
-  if (B->h_slots) (void)hipHostFree(B->h_slots);
-  if (B->h_status) (void)hipHostFree(B->h_status);
-  if (B->up_stage) (void)hipHostFree(B->up_stage);
-  if (B->down_stage) (void)hipHostFree(B->down_stage);
+  if (B->h_desc) (void)hipHostFree(B->h_desc);
+  if (B->h_state) (void)hipHostFree(B->h_state);
+  if (B->in_mem) (void)hipHostFree(B->in_mem);
+  if (B->xout_mem) (void)hipHostFree(B->xout_mem);
   for (int c = 0; c < mxs::kMaxClasses; ++c) {
     if (B->branch[c]) (void)hipStreamDestroy(B->branch[c]);
     if (B->join[c]) (void)hipEventDestroy(B->join[c]);
@@ -669,92 +798,119 @@ mxs_status mxs_batch_destroy(mxs_batch* B) {
   return MXS_OK;
 }
 
+mxs_status mxs_batch_submit_many(mxs_batch* B, int64_t count, const mxs_batch_request* reqs,
+                                 uint64_t* tickets, mxs_status* statuses) {
+  if (!B || count < 0 || (count && (!reqs || !tickets || !statuses))) return MXS_INVALID_ARG;
+  mxs_ctx* ctx = B->ctx;
+  // 1. sizes, class and budget, and a place in the pinned pool (in order)
+  std::vector<Request> R((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    const mxs_batch_request& q = reqs[i];
+    tickets[i] = 0;
+    statuses[i] = MXS_OK;
+    if (q.n < 1 || q.nnz < 0 || !q.rowptr || !q.b || (q.nnz && (!q.col || !q.val))) {
+      statuses[i] = MXS_INVALID_ARG;
+      continue;
+    }
+    if (q.n > INT32_MAX || q.nnz > INT32_MAX) {
+      statuses[i] = fail(ctx, MXS_UNSUPPORTED, "sizes beyond int32");
+      continue;
+    }
+    const int c = class_of(B, q.n);
+    if (c < 0) {
+      statuses[i] = fail(ctx, MXS_UNSUPPORTED, "n = %lld exceeds the largest size class",
+                         (long long)q.n);
+      continue;
+    }
+    const Layout L = layout(q.n, q.nnz);
+    if (L.total > B->arena.size) {
+      statuses[i] = fail(ctx, MXS_BUDGET, "request needs %zu bytes, budget is %zu", L.total,
+                         B->arena.size);
+      continue;
+    }
+    if (L.x > B->inpool.size) {
+      statuses[i] = fail(ctx, MXS_BUDGET, "request inputs need %zu bytes of staging, have %zu",
+                         L.x, B->inpool.size);
+      continue;
+    }
+    Request& r = R[i];
+    r.n = q.n;
+    r.nnz = q.nnz;
+    r.tol = q.rel_tol;
+    r.max_iters = q.max_iters > 0 ? q.max_iters : 20000;
+    r.bytes = L.total;
+    r.in_bytes = L.x;
+    r.cls = c;
+    // pack into pinned memory when there is room; otherwise keep a copy and
+    // pack at admission
+    r.packed = B->inpool.alloc(r.in_bytes, &r.in_off);
+  }
+  // 2. validate and pack / copy, on worker threads for large submissions
+  std::vector<char> valid((size_t)count, 0);
+  auto work = [&](int64_t i) {
+    if (statuses[i] != MXS_OK) return;
+    const mxs_batch_request& q = reqs[i];
+    Request& r = R[i];
+    if (!validate_csr(q.n, q.nnz, q.rowptr, q.col)) return;
+    valid[i] = 1;
+    if (r.packed) {
+      pack(B->in_mem + r.in_off, q.n, q.nnz, q.rowptr, q.col, q.val, q.b);
+    } else {
+      r.rowptr.assign(q.rowptr, q.rowptr + q.n + 1);
+      r.col.assign(q.col, q.col + q.nnz);
+      r.val.assign(q.val, q.val + q.nnz);
+      r.b.assign(q.b, q.b + q.n);
+    }
+  };
+  int64_t bytes_total = 0;
+  for (int64_t i = 0; i < count; ++i)
+    if (statuses[i] == MXS_OK) bytes_total += (int64_t)R[i].in_bytes;
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int64_t nthreads =
+      std::min<int64_t>({(int64_t)std::min(hw, 16u), count, bytes_total >> 20});
+  if (nthreads <= 1) {
+    for (int64_t i = 0; i < count; ++i) work(i);
+  } else {
+    std::atomic<int64_t> next{0};
+    auto loop = [&]() {
+      for (int64_t i; (i = next.fetch_add(1, std::memory_order_relaxed)) < count;) work(i);
+    };
+    std::vector<std::thread> pool;
+    for (int64_t t = 1; t < nthreads; ++t) pool.emplace_back(loop);
+    loop();
+    for (auto& t : pool) t.join();
+  }
+  // 3. queue the valid ones in order
+  for (int64_t i = 0; i < count; ++i) {
+    if (statuses[i] != MXS_OK) continue;
+    Request& r = R[i];
+    if (!valid[i]) {
+      if (r.packed) B->inpool.release(r.in_off, r.in_bytes);
+      statuses[i] = fail(ctx, MXS_INVALID_MATRIX, "submitted CSR failed validation");
+      continue;
+    }
+    r.ticket = B->next_ticket++;
+    tickets[i] = r.ticket;
+    B->pending.push_back(std::move(r));
+  }
+  return MXS_OK;
+}
+
 mxs_status mxs_batch_submit(mxs_batch* B, int64_t n, int64_t nnz, const int32_t* rowptr,
                             const int32_t* col, const double* val, const double* b,
                             double rel_tol, int64_t max_iters, uint64_t* ticket) {
-  if (!B || !ticket || n < 1 || nnz < 0 || !rowptr || !b || (nnz && (!col || !val)))
-    return MXS_INVALID_ARG;
-  mxs_ctx* ctx = B->ctx;
-  if (n > INT32_MAX || nnz > INT32_MAX) return fail(ctx, MXS_UNSUPPORTED, "sizes beyond int32");
-  const int c = class_of(B, n);
-  if (c < 0)
-    return fail(ctx, MXS_UNSUPPORTED, "n = %lld exceeds the largest size class",
-                (long long)n);
-  const size_t bytes = footprint(n, nnz);
-  if (bytes > B->arena.size)
-    return fail(ctx, MXS_BUDGET, "request needs %zu bytes, budget is %zu", bytes, B->arena.size);
-  if (!validate_csr(n, nnz, rowptr, col))
-    return fail(ctx, MXS_INVALID_MATRIX, "submitted CSR failed validation");
-  Request R;
-  R.ticket = B->next_ticket++;
-  R.n = n;
-  R.nnz = nnz;
-  R.rowptr.assign(rowptr, rowptr + n + 1);
-  R.col.assign(col, col + nnz);
-  R.val.assign(val, val + nnz);
-  R.b.assign(b, b + n);
-  R.tol = rel_tol;
-  R.max_iters = max_iters > 0 ? max_iters : 20000;
-  R.bytes = bytes;
-  R.cls = c;
-  B->pending.push_back(std::move(R));
-  *ticket = B->pending.back().ticket;
-  return MXS_OK;
+  if (!B || !ticket) return MXS_INVALID_ARG;
+  mxs_batch_request q = {n, nnz, rowptr, col, val, b, rel_tol, max_iters};
+  mxs_status st = MXS_OK;
+  const mxs_status call = mxs_batch_submit_many(B, 1, &q, ticket, &st);
+  return call ? call : st;
 }
 
 mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
   if (!B) return MXS_INVALID_ARG;
   mxs_ctx* ctx = B->ctx;
   MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  // 1. retire slots the last step finished (h_status is that step's copy)
-  std::vector<int> retired;
-  std::vector<size_t> stage_off;
-  if (B->launched) {
-    size_t down = 0;
-    for (int i = 0; i < B->nslots; ++i) {
-      Slot& s = B->slots[i];
-      if (!s.busy) continue;
-      const SlotDesc& d = B->h_status[i];
-      if (d.status < SLOT_CONVERGED) continue;
-      const size_t xb = up(s.n * sizeof(double));
-      if (down + xb > B->down_bytes) break;  // the rest retires next step
-      Result& R = B->results[s.ticket];
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(B->down_stage + down, s.x_dev, s.n * sizeof(double),
-                                      hipMemcpyDeviceToHost, B->stream));
-      stage_off.push_back(down);
-      down += xb;
-      std::memset(&R.info, 0, sizeof(R.info));
-      R.info.iters = d.iters;
-      R.info.replacements = d.repl;
-      const double nb = d.tol > 0 ? d.thr / d.tol : 0.0;
-      R.info.relres_recurrence = nb > 0 ? sqrt(d.res2) / nb : 0.0;
-      R.info.relres_true = d.status == SLOT_CONVERGED || d.status == SLOT_NOTCONV
-                               ? (nb > 0 ? sqrt(d.res2) / nb : 0.0)
-                               : -1.0;
-      R.info.status = d.status == SLOT_CONVERGED   ? MXS_OK
-                      : d.status == SLOT_BREAKDOWN ? MXS_BREAKDOWN
-                      : d.status == SLOT_NONFINITE ? MXS_NONFINITE
-                                                   : MXS_NOT_CONVERGED;
-      retired.push_back(i);
-    }
-    MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
-    for (size_t q = 0; q < retired.size(); ++q) {
-      const int i = retired[q];
-      Slot& s = B->slots[i];
-      Result& R = B->results[s.ticket];
-      const double* xs = (const double*)(B->down_stage + stage_off[q]);
-      R.x.assign(xs, xs + s.n);
-      R.done = true;
-      B->newly_done.push_back(s.ticket);
-      B->arena.release(s.off, s.bytes);
-      s.busy = false;
-      std::memset(&B->h_slots[i], 0, sizeof(SlotDesc));
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(&B->d_slots[i], &B->h_slots[i], sizeof(SlotDesc),
-                                      hipMemcpyHostToDevice, B->stream));
-      B->completed++;
-    }
-  }
-  // 2. admit in FIFO order, first fit: a request that does not fit (no free
+  // 1. admit in FIFO order, first fit: a request that does not fit (no free
   // slot in its class, or no arena gap) is passed over by later ones,
   // unless it has been the oldest waiting request for more than 64 steps;
   // then nothing behind it is admitted until it fits (starvation guard)
@@ -764,16 +920,27 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
       if (!B->slots[i].busy) return i;
     return -1;
   };
-  std::vector<Request> uploading;
-  size_t staged = 0;
   size_t idx = 0;
   while (idx < B->pending.size()) {
     Request& R = B->pending[idx];
-    const bool via_stage = R.bytes <= B->up_bytes;
-    if (via_stage && staged + R.bytes > B->up_bytes) break;  // stage full: next step
     const int si = find_free(R.cls);
     size_t off = 0;
-    if (si < 0 || !B->arena.alloc(R.bytes, &off)) {
+    bool fits = si >= 0 && B->arena.alloc(R.bytes, &off);
+    if (fits && !R.packed) {
+      if (B->inpool.alloc(R.in_bytes, &R.in_off)) {
+        pack(B->in_mem + R.in_off, R.n, R.nnz, R.rowptr.data(), R.col.data(), R.val.data(),
+             R.b.data());
+        R.packed = true;
+        std::vector<int32_t>().swap(R.rowptr);
+        std::vector<int32_t>().swap(R.col);
+        std::vector<double>().swap(R.val);
+        std::vector<double>().swap(R.b);
+      } else {
+        B->arena.release(off, R.bytes);
+        fits = false;
+      }
+    }
+    if (!fits) {
       if (idx == 0) {
         if (R.ticket == B->starve_ticket) {
           B->starve_steps++;
@@ -786,83 +953,88 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
       ++idx;
       continue;
     }
-    char* p = B->arena.base + off;
-    const int64_t n = R.n, nnz = R.nnz;
-    int32_t* d_rp = (int32_t*)p;
-    int32_t* d_col = (int32_t*)(p + up((n + 1) * 4));
-    double* d_val = (double*)(p + up((n + 1) * 4) + up(nnz * 4));
-    double* d_b = (double*)((char*)d_val + up(nnz * 8));
-    double* d_x = (double*)((char*)d_b + up(n * 8));
-    double* d_r = (double*)((char*)d_x + up(n * 8));
-    double* d_p = (double*)((char*)d_r + up(n * 8));
-    // the matrix and b are packed in the pinned stage in their arena layout
-    // and travel in one copy
-    const size_t in_bytes = (size_t)((char*)d_x - p);
-    if (via_stage) {
-      char* sp = B->up_stage + staged;
-      std::memcpy(sp, R.rowptr.data(), (n + 1) * 4);
-      std::memcpy(sp + ((char*)d_col - p), R.col.data(), nnz * 4);
-      std::memcpy(sp + ((char*)d_val - p), R.val.data(), nnz * 8);
-      std::memcpy(sp + ((char*)d_b - p), R.b.data(), n * 8);
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(p, sp, in_bytes, hipMemcpyHostToDevice, B->stream));
-      staged += up(in_bytes);
-    } else {  // larger than the stage: copy from the request's own buffers
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(d_rp, R.rowptr.data(), (n + 1) * 4,
-                                      hipMemcpyHostToDevice, B->stream));
-      if (nnz) {
-        MXS_HIP_TRY(ctx, hipMemcpyAsync(d_col, R.col.data(), nnz * 4, hipMemcpyHostToDevice,
-                                        B->stream));
-        MXS_HIP_TRY(ctx, hipMemcpyAsync(d_val, R.val.data(), nnz * 8, hipMemcpyHostToDevice,
-                                        B->stream));
-      }
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(d_b, R.b.data(), n * 8, hipMemcpyHostToDevice,
-                                      B->stream));
-    }
-    SlotDesc& d = B->h_slots[si];
+    char* p = (char*)B->arena_mem + off;
+    const Layout L = layout(R.n, R.nnz);
+    SlotDesc& d = B->h_desc[si];
     std::memset(&d, 0, sizeof(d));
-    d.rowptr = d_rp;
-    d.col = d_col;
-    d.val = d_val;
-    d.b = d_b;
-    d.x = d_x;
-    d.r = d_r;
-    d.p = d_p;
+    d.rowptr = (int32_t*)p;
+    d.col = (int32_t*)(p + L.col);
+    d.val = (double*)(p + L.val);
+    d.b = (double*)(p + L.b);
+    d.x = (double*)(p + L.x);
+    d.r = (double*)(p + L.r);
+    d.p = (double*)(p + L.p);
+    d.src = (const uint4*)(B->in_dev + R.in_off);
+    d.xout = B->xout_dev + B->xout_off[si];
     d.tol = R.tol;
-    d.n = (int32_t)n;
-    d.nnz = (int32_t)nnz;
+    d.n = (int32_t)R.n;
+    d.nnz = (int32_t)R.nnz;
     d.max_iters = (int32_t)std::min<int64_t>(R.max_iters, INT32_MAX);
     d.active = 1;
-    d.status = SLOT_NEW;
-    MXS_HIP_TRY(ctx, hipMemcpyAsync(&B->d_slots[si], &d, sizeof(SlotDesc), hipMemcpyHostToDevice,
-                                    B->stream));
+    if (++B->gen == 0) ++B->gen;  // 0 marks a state no launch has written
+    d.gen = B->gen;
+    d.in_words = (int32_t)(R.in_bytes / 16);
+    B->desc_dirty = true;
     Slot& s = B->slots[si];
     s.busy = true;
+    s.holds_input = true;
     s.ticket = R.ticket;
     s.off = off;
     s.bytes = R.bytes;
-    s.n = n;
-    s.x_dev = d_x;
-    // the host copies in R must stay alive until the uploads completed:
-    // keep them until the synchronisation below
-    uploading.push_back(std::move(R));
+    s.in_off = R.in_off;
+    s.in_bytes = R.in_bytes;
+    s.n = R.n;
     B->pending.erase(B->pending.begin() + idx);
   }
-  if (!uploading.empty()) {
-    MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
-    uploading.clear();
-  }
-  // 3. run K iterations of every active slot and read the statuses back
+  // 2. run K iterations of every resident system, read the states back
   int active = 0;
   for (const Slot& s : B->slots) active += s.busy ? 1 : 0;
   if (active > 0) {
+    mxs_status st = upload_desc(B);
+    if (st) return st;
     MXS_HIP_TRY(ctx, hipGraphLaunch(B->exec, B->stream));
     MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
-    B->launched = true;
-  } else {
-    B->launched = false;
+  }
+  // 3. every resident slot has copied its inputs by now; retire the
+  // finished ones (their x is already in the pinned output)
+  for (int i = 0; i < B->nslots && active > 0; ++i) {
+    Slot& s = B->slots[i];
+    if (!s.busy) continue;
+    if (s.holds_input) {
+      B->inpool.release(s.in_off, s.in_bytes);
+      s.holds_input = false;
+    }
+    const SlotState& d = B->h_state[i];
+    if (d.gen != B->h_desc[i].gen || d.status < SLOT_CONVERGED) continue;
+    Result& R = B->results[s.ticket];
+    const double* xs = B->xout_mem + B->xout_off[i];
+    R.x.assign(xs, xs + s.n);
+    std::memset(&R.info, 0, sizeof(R.info));
+    R.info.iters = d.iters;
+    R.info.replacements = d.repl;
+    const double tol = B->h_desc[i].tol;
+    const double nb = tol > 0 ? d.thr / tol : 0.0;
+    R.info.relres_recurrence = nb > 0 ? sqrt(d.res2) / nb : 0.0;
+    R.info.relres_true = d.status == SLOT_CONVERGED || d.status == SLOT_NOTCONV
+                             ? (nb > 0 ? sqrt(d.res2) / nb : 0.0)
+                             : -1.0;
+    R.info.status = d.status == SLOT_CONVERGED   ? MXS_OK
+                    : d.status == SLOT_BREAKDOWN ? MXS_BREAKDOWN
+                    : d.status == SLOT_NONFINITE ? MXS_NONFINITE
+                                                 : MXS_NOT_CONVERGED;
+    R.done = true;
+    B->newly_done.push_back(s.ticket);
+    B->arena.release(s.off, s.bytes);
+    s.busy = false;
+    B->h_desc[i].active = 0;
+    B->desc_dirty = true;
+    B->completed++;
+    active--;
   }
   if (stats) {
-    stats->active = active;
+    int resident = 0;
+    for (const Slot& s : B->slots) resident += s.busy ? 1 : 0;
+    stats->active = resident;
     stats->pending = (int32_t)B->pending.size();
     stats->completed = B->completed;
     stats->arena_used = (int64_t)B->arena.used;

@@ -92,7 +92,7 @@ class BatchOpts(C.Structure):
     _fields_ = [("budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
                 ("iters_per_step", C.c_int32), ("nclasses", C.c_int32),
                 ("class_max_n", C.c_int32 * 8), ("class_block", C.c_int32 * 8),
-                ("class_slots", C.c_int32 * 8)]
+                ("class_slots", C.c_int32 * 8), ("staging_bytes", C.c_size_t)]
 
 
 class BatchStats(C.Structure):
@@ -123,6 +123,7 @@ _SIGS = {
     "mxs_batch_destroy": (_S, [_P]),
     "mxs_batch_submit": (_S, [_P, _I64, _I64, _P, _P, _P, _P, C.c_double, _I64,
                               C.POINTER(C.c_uint64)]),
+    "mxs_batch_submit_many": (_S, [_P, _I64, _P, _P, _P]),
     "mxs_batch_step": (_S, [_P, C.POINTER(BatchStats)]),
     "mxs_batch_poll": (_S, [_P, C.c_uint64, _P, C.POINTER(SolveInfo)]),
     "mxs_batch_completed": (_S, [_P, C.POINTER(C.c_uint64), _I64, C.POINTER(_I64)]),
@@ -397,9 +398,10 @@ class Batch:
     (max_n, threads_per_system, slots) tuples (slots 0 = even share)."""
 
     def __init__(self, ctx: Context, budget_bytes=2 << 30, max_slots=512,
-                 iters_per_step=16, classes=None):
+                 iters_per_step=16, classes=None, staging_bytes=0):
         o = BatchOpts()
         o.budget_bytes = int(budget_bytes)
+        o.staging_bytes = int(staging_bytes)
         o.max_slots = int(max_slots)
         o.iters_per_step = int(iters_per_step)
         if classes:
@@ -425,6 +427,30 @@ class Batch:
                                      bb.ctypes.data_as(_P), float(tol), int(max_iters),
                                      C.byref(t)), self.ctx)
         return t.value
+
+    # mxs_batch_request, field for field
+    _REQ = np.dtype([("n", "<i8"), ("nnz", "<i8"), ("rowptr", "<u8"), ("col", "<u8"),
+                     ("val", "<u8"), ("b", "<u8"), ("rel_tol", "<f8"), ("max_iters", "<i8")])
+
+    def submit_many(self, systems, tol=1e-10, max_iters=0):
+        """Queues [(A, b), ...] in one call (validated and packed on host
+        threads).  Returns (tickets, statuses) as numpy arrays; ticket 0
+        marks a rejected request, whose status says why."""
+        k = len(systems)
+        req = np.zeros(k, self._REQ)
+        keep = []
+        for i, (A, b) in enumerate(systems):
+            arrs = (np.ascontiguousarray(A.rowptr, np.int32), np.ascontiguousarray(A.col, np.int32),
+                    np.ascontiguousarray(A.val, np.float64), np.ascontiguousarray(b, np.float64))
+            keep.append(arrs)
+            req[i] = (A.n, arrs[1].size, arrs[0].ctypes.data, arrs[1].ctypes.data,
+                      arrs[2].ctypes.data, arrs[3].ctypes.data, tol, max_iters)
+        tickets = np.zeros(k, np.uint64)
+        statuses = np.zeros(k, np.int32)
+        _check(_lib.mxs_batch_submit_many(self.handle, k, req.ctypes.data, tickets.ctypes.data,
+                                          statuses.ctypes.data), self.ctx)
+        del keep
+        return tickets, statuses
 
     def step(self) -> dict:
         s = BatchStats()

@@ -64,9 +64,9 @@ def _report(mode, reqs, arrival, done, iters, statuses, t_first, keep_x, xs, ste
 
 
 def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1024,
-                iters_per_step=16, classes=None, keep_x=False) -> ServeReport:
+                iters_per_step=16, classes=None, staging_bytes=0, keep_x=False) -> ServeReport:
     from . import mxs
-    B = mxs.Batch(ctx, budget_bytes, max_slots, iters_per_step, classes)
+    B = mxs.Batch(ctx, budget_bytes, max_slots, iters_per_step, classes, staging_bytes)
     order = sorted(reqs, key=lambda r: r.arrival)
     ticket_of = {}
     rid_of = {}
@@ -77,14 +77,20 @@ def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1
     t0 = time.perf_counter()
     while len(done) < len(order):
         now = time.perf_counter() - t0
-        while i < len(order) and order[i].arrival <= now:
-            r = order[i]
-            A, b = systems[r.rid]
-            t = B.submit(A, b, tol)
-            ticket_of[r.rid] = t
-            rid_of[t] = r
-            arrival[r.rid] = r.arrival
-            i += 1
+        j = i
+        while j < len(order) and order[j].arrival <= now:
+            j += 1
+        if j > i:
+            # everything that arrived since the last step, in one call
+            arrived = order[i:j]
+            tickets, sts = B.submit_many([systems[r.rid] for r in arrived], tol)
+            for r, t, s in zip(arrived, tickets.tolist(), sts.tolist()):
+                if s != mxs.OK:
+                    raise mxs.MxsError(s, f"request {r.rid} rejected")
+                ticket_of[r.rid] = t
+                rid_of[t] = r
+                arrival[r.rid] = r.arrival
+            i = j
         if len(arrival) > len(done):
             st = B.step()
             steps += 1

@@ -171,3 +171,35 @@ def test_serving_loop(env, orc):
         for xs in (rb.x, rp.x):
             assert orc.true_relres(A, b, xs[r.rid]) <= 1e-10 + _slack(orc, A, b, xs[r.rid])
     assert rb.p99_ms > 0 and rp.p99_ms > 0
+
+
+def test_submit_many(env):
+    """Requests queued in one call (validated and packed on host threads)
+    give the same tickets order and bitwise the same results as one at a
+    time; malformed ones are rejected individually."""
+    mxs, ctx, torch = env
+    sys_ = _systems(I.rng(45).integers(8, 97, 60), 700)
+    A0, b0 = sys_[5]
+    bad = I.CSRMatrix(A0.n, A0.n, A0.rowptr, A0.col.copy(), A0.val)
+    bad.col[2] = bad.col[1]  # duplicate column
+    big = I.serving_system(110, 1)
+    reqs = sys_[:20] + [(bad, b0)] + sys_[20:40] + [(big, np.ones(big.n))] + sys_[40:]
+    B = mxs.Batch(ctx, 256 << 20, 32, iters_per_step=8)
+    tickets, sts = B.submit_many(reqs, 1e-10)
+    assert sts[20] == mxs.INVALID_MATRIX and tickets[20] == 0
+    assert sts[41] == mxs.UNSUPPORTED and tickets[41] == 0
+    ok = [i for i in range(len(reqs)) if i not in (20, 41)]
+    assert (sts[ok] == mxs.OK).all()
+    assert np.all(np.diff(tickets[ok].astype(np.int64)) > 0)
+    _drain(B)
+    many = {i: B.poll(int(tickets[i]), reqs[i][0].n) for i in ok}
+    B.close()
+    B = mxs.Batch(ctx, 256 << 20, 32, iters_per_step=8)
+    one = {i: B.submit(*reqs[i], 1e-10) for i in ok}
+    _drain(B)
+    for i in ok:
+        s1, x1, r1 = B.poll(one[i], reqs[i][0].n)
+        sm, xm, rm = many[i]
+        assert s1 == sm == mxs.OK and r1.iters == rm.iters
+        assert np.array_equal(x1.view(np.uint64), xm.view(np.uint64)), i
+    B.close()
