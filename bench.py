@@ -309,11 +309,36 @@ def main():
             t = float(np.median(ts))
             err = float(torch.linalg.norm(xq - xstar) / torch.linalg.norm(xstar))
             csr_b = Q.nnz * 12 + 4 * (Q.n + 1) + 16 * Q.n
+            # fixed 1000 iterations (no convergence test can stop it), for
+            # GFLOP/s and GB/s under the per-iteration models: CG 2nnz+10n
+            # flops and B_csr+64n bytes; BiCGSTAB 4nnz+20n and 2B_csr+144n;
+            # GMRES(30) step j 2nnz+8(j+1)n+3n and B_csr+(4(j+1)+9)8n,
+            # averaged over j = 0..29
+            n_, z_ = Q.n, Q.nnz
+            fl, by = {"cg": (2 * z_ + 10 * n_, csr_b + 64 * n_),
+                      "bicgstab": (4 * z_ + 20 * n_, 2 * csr_b + 144 * n_),
+                      "gmres": (2 * z_ + 8 * 15.5 * n_ + 3 * n_,
+                                csr_b + (4 * 15.5 + 9) * 8 * n_)}[solver]
+            xq.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rf = mxs.solve(ctx, solver, Qm, bq, xq, tol=0.0, max_iters=1000, restart=30,
+                           raise_on_error=False)
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - t0
+            itf = max(rf.iters, 1)
+            fixed = {"iters": rf.iters, "status": rf.status, "time_s": round(tf, 4),
+                     "ms_per_iter": round(tf / itf * 1e3, 4),
+                     "GFLOPs": round(fl * itf / tf / 1e9, 1),
+                     "GBs_model": round(by * itf / tf / 1e9, 1),
+                     "frac_spec": round(by * itf / tf / 1e9 / PEAK_HBM_GBS, 4)}
+            if peak_meas:
+                fixed["frac_measured"] = round(by * itf / tf / 1e9 / peak_meas, 4)
             kr[name] = {"n": Q.n, "nnz": Q.nnz, "iters": r.iters, "restarts": r.restarts,
                         "relres_true": r.relres_true, "err_vs_xstar": err,
                         "time_s": round(t, 4), "solves_per_s": round(1 / t, 2),
                         "ms_per_iter": round(t / max(r.iters, 1) * 1e3, 4),
-                        "spmv_bytes": csr_b}
+                        "spmv_bytes": csr_b, "fixed_1000_iters": fixed}
             log(name, kr[name])
             Qm.close()
         extra["krylov"] = kr
@@ -379,6 +404,10 @@ def main():
         sv["batched_closed"] = rb.summary()
         log("batched closed", sv["batched_closed"])
         mu_b = rb.solves_per_s
+        # the same requests with FP32 storage inside FP64 refinement
+        rbi = serve.run_batched(ctx, closed, systems, mode="ir32", **bkw)
+        sv["batched_ir32_closed"] = rbi.summary()
+        log("batched ir32 closed", sv["batched_ir32_closed"])
         nplain = min(count, args.plain_requests)
         rp = serve.run_plain(ctx, closed[:nplain], systems)
         sv["plain_closed"] = rp.summary()

@@ -309,8 +309,22 @@ typedef struct {
   const double* val;
   const double* b;
   double rel_tol;
-  int64_t max_iters;        /* 0 = 20000 */
+  int64_t max_iters;        /* 0 = 20000 (refinement mode: inner iterations in total) */
+  int32_t mode;             /* MXS_BATCH_FP64 or MXS_BATCH_IR_FP32 */
+  int32_t reserved;
+  double inner_rel_tol;     /* refinement mode: inner tolerance, 0 = 1e-4 */
 } mxs_batch_request;
+
+/* Batch modes.  MXS_BATCH_FP64: CG in FP64.  MXS_BATCH_IR_FP32: the
+ * mixed-precision scheme of mxs_solve_ir with an F32 copy of the values
+ * (rounded to nearest by the kernel on the request's first step): FP64
+ * residual r = b - A x and update x += ||r|| d, inner FP32 CG on
+ * A d = r / ||r|| to inner_rel_tol (reductions accumulated in FP64),
+ * at most 50 outer steps; the footprint grows by 4 nnz bytes.  Its result
+ * reports inner iterations in total as `iters` and outer steps as
+ * `restarts`. */
+#define MXS_BATCH_FP64 0
+#define MXS_BATCH_IR_FP32 1
 
 /* Queues `count` requests as mxs_batch_submit would, validating and
  * packing them on up to 16 host threads.  tickets[i] receives request i's

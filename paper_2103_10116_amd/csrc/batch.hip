@@ -68,6 +68,9 @@ struct SlotDesc {
   int32_t active;
   uint32_t gen;        // admission number; the state's gen differs until the first launch
   int32_t in_words;    // 16-byte words from src to rowptr
+  float* v32;          // arena, refinement mode: the values rounded to FP32
+  int32_t mode;        // 0: FP64 CG; 1: FP32-storage CG inside FP64 refinement
+  float inner_tol;     // refinement mode: inner relative tolerance
 };
 
 // written by the kernel, read back after every launch
@@ -75,7 +78,15 @@ struct SlotState {
   double rho, thr, res2;
   int32_t iters, status, repl;
   uint32_t gen;
+  // refinement mode: inner threshold, norm of the residual being refined,
+  // inner iterations of the current inner solve, phase, outer steps
+  double ithr, rn;
+  int32_t inner, phase, outer, pad;
 };
+
+enum : int32_t { PH_OUTER = 0, PH_INNER = 1 };
+constexpr int kIrOuterMax = 50;
+constexpr int kIrInnerMax = 20000;
 
 template <int BS>
 __device__ __forceinline__ double bsum(double v, double* red) {
@@ -105,38 +116,249 @@ __device__ __forceinline__ int bmax(int v, int* red) {
 }
 
 // q = A v for the thread's rows (rows tid + k*BS).  The loop over the
-// entry index is outermost so that the loads of all RPT rows are in flight
-// together; row pointers come from LDS.
-template <int BS, int RPT>
+// entry index is outermost so that the loads of a group of LG rows are in
+// flight together (LG = RPT up to 8 rows, else half of them, to stay within
+// the 128 registers of a 1024-thread work-group); the row bounds are
+// re-read from LDS rather than held in registers.
+template <int BS, int RPT, typename V = double>
 __device__ __forceinline__ void rows_times(const int32_t* __restrict__ rpl,
                                            const int32_t* __restrict__ col,
-                                           const double* __restrict__ val,
-                                           const double* __restrict__ vec, int n, int maxlen,
-                                           double (&q)[RPT]) {
+                                           const V* __restrict__ val,
+                                           const V* __restrict__ vec, int n, int maxlen,
+                                           V (&q)[RPT]) {
+  constexpr int LG = RPT <= 8 ? RPT : (RPT + 1) / 2;
   const int tid = threadIdx.x;
-  int32_t rs[RPT], re[RPT];
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * BS;
-    rs[k] = i < n ? rpl[i] : 0;
-    re[k] = i < n ? rpl[i + 1] : 0;
-    q[k] = 0.0;
-  }
+  for (int k = 0; k < RPT; ++k) q[k] = V(0);
   for (int j = 0; j < maxlen; ++j) {
-    int32_t c[RPT];
-    double v[RPT];
+#pragma unroll
+    for (int g = 0; g < RPT; g += LG) {
+      int32_t c[LG];
+      V v[LG];
+      bool h[LG];
+#pragma unroll
+      for (int u = 0; u < LG; ++u) {
+        const int i = tid + (g + u) * BS;
+        const bool in = g + u < RPT && i < n;
+        const int32_t e = in ? rpl[i] + j : 0;
+        h[u] = in && e < rpl[i + 1];
+        c[u] = 0;
+        v[u] = V(0);
+        if (h[u]) {
+          c[u] = col[e];
+          v[u] = val[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LG; ++u)
+        if (h[u]) q[g + u] += v[u] * vec[c[u]];
+    }
+  }
+}
+
+// Refinement mode (a slot's share of the mixed-precision scheme of the
+// single-system solver): outer steps r = b - A x with the FP64 values and
+// x += ||r|| d, inner CG in FP32 on the FP32-rounded values for
+// A d = r / ||r|| to inner_tol, reductions accumulated in FP64 and rounded
+// once to FP32.  An outer step and an inner iteration each take one of the
+// launch's K units.  x lives in registers (FP64), the inner r and d in
+// registers (FP32); the gather vector (x for an outer step, the inner p
+// otherwise) is the same LDS region read as FP64 or FP32.
+template <int BS, int RPT, bool USE_LDS>
+__device__ __forceinline__ void ir_body(const SlotDesc& D, SlotState* S, int K, bool fresh,
+                                        const int32_t* rpl, int maxlen, double* dyn,
+                                        double* red) {
+  const int n = D.n;
+  const int tid = threadIdx.x;
+  const int32_t* __restrict__ col = D.col;
+  const double* __restrict__ val = D.val;
+  const float* __restrict__ v32 = D.v32;
+  const double* __restrict__ b = D.b;
+  double* __restrict__ vec64 = USE_LDS ? dyn : D.x;
+  float* __restrict__ vec32 = USE_LDS ? (float*)dyn : (float*)D.p;
+  float* __restrict__ rin_g = (float*)D.r;
+  float* __restrict__ d_g = (float*)D.r + n;
+  double x[RPT];
+  float d[RPT], rin[RPT], q[RPT];
+  double thr, rn, res2;
+  float rho, ithr;
+  int status = SLOT_RUN, phase, inner, outer, tot;
+  if (fresh) {
+    double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      c[k] = 0;
-      v[k] = 0.0;
-      if (rs[k] + j < re[k]) {
-        c[k] = col[rs[k] + j];
-        v[k] = val[rs[k] + j];
+      const int i = tid + k * BS;
+      x[k] = 0.0;
+      d[k] = 0.0f;
+      rin[k] = 0.0f;
+      const double bi = i < n ? b[i] : 0.0;
+      acc += bi * bi;
+    }
+    res2 = bsum<BS>(acc, red);
+    thr = D.tol * sqrt(res2);
+    rn = 0.0;
+    rho = 0.0f;
+    ithr = 0.0f;
+    phase = PH_OUTER;
+    inner = outer = tot = 0;
+    if (!isfinite(res2)) status = SLOT_NONFINITE;
+    if (res2 == 0.0) status = SLOT_CONVERGED;  // b = 0: x = 0
+  } else {
+    thr = S->thr;
+    rn = S->rn;
+    res2 = S->res2;
+    rho = (float)S->rho;
+    ithr = (float)S->ithr;
+    phase = S->phase;
+    inner = S->inner;
+    outer = S->outer;
+    tot = S->iters;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      x[k] = i < n ? D.x[i] : 0.0;
+      d[k] = i < n && phase == PH_INNER ? d_g[i] : 0.0f;
+      rin[k] = i < n && phase == PH_INNER ? rin_g[i] : 0.0f;
+      if (USE_LDS && i < n && phase == PH_INNER) vec32[i] = ((const float*)D.p)[i];
+    }
+  }
+  __syncthreads();
+  for (int u = 0; u < K && status == SLOT_RUN; ++u) {
+    if (phase == PH_OUTER) {
+      // r = b - A x in FP64, x staged in the gather vector
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        if (i < n) vec64[i] = x[k];
+      }
+      __syncthreads();
+      double r64[RPT];
+      rows_times<BS, RPT, double>(rpl, col, val, vec64, n, maxlen, r64);
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        r64[k] = i < n ? b[i] - r64[k] : 0.0;
+        acc += r64[k] * r64[k];
+      }
+      res2 = bsum<BS>(acc, red);  // its barriers end every read of vec64
+      if (!isfinite(res2)) {
+        status = SLOT_NONFINITE;
+        break;
+      }
+      const double nr = sqrt(res2);
+      if (nr <= thr) {
+        status = SLOT_CONVERGED;
+        break;
+      }
+      if (outer >= kIrOuterMax || tot >= D.max_iters) {
+        status = SLOT_NOTCONV;
+        break;
+      }
+      // inner solve of A d = r / ||r|| from d = 0: its r and p start as f
+      rn = nr;
+      double f2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        rin[k] = i < n ? (float)(r64[k] / nr) : 0.0f;
+        d[k] = 0.0f;
+        if (i < n) vec32[i] = rin[k];
+        f2 += (double)rin[k] * (double)rin[k];
+      }
+      rho = (float)bsum<BS>(f2, red);
+      ithr = D.inner_tol * sqrtf(rho);
+      inner = 0;
+      phase = PH_INNER;
+      if (!(sqrtf(rho) > ithr)) {  // nothing to solve: the correction is zero
+        outer++;
+        phase = PH_OUTER;
+      }
+      continue;
+    }
+    // one inner FP32 CG iteration
+    rows_times<BS, RPT, float>(rpl, col, v32, vec32, n, maxlen, q);
+    double pq_acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) pq_acc += (double)vec32[i] * (double)q[k];
+    }
+    const float pq = (float)bsum<BS>(pq_acc, red);
+    bool finish = false;
+    if (!(pq > 0.0f)) {
+      finish = true;  // breakdown: the correction so far is still usable
+    } else {
+      const float alpha = rho / pq;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        if (i < n) d[k] = d[k] + alpha * vec32[i];
+        rin[k] = rin[k] - alpha * q[k];
+        acc += (double)rin[k] * (double)rin[k];
+      }
+      const float rho_new = (float)bsum<BS>(acc, red);
+      ++inner;
+      ++tot;
+      if (!isfinite(rho_new)) {
+        status = SLOT_NONFINITE;
+        break;
+      }
+      if (sqrtf(rho_new) <= ithr || inner >= kIrInnerMax || tot >= D.max_iters) {
+        finish = true;
+      } else {
+        const float beta = rho_new / rho;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int i = tid + k * BS;
+          if (i < n) vec32[i] = rin[k] + beta * vec32[i];
+        }
+        rho = rho_new;
+        __syncthreads();
       }
     }
+    if (finish) {
 #pragma unroll
-    for (int k = 0; k < RPT; ++k)
-      if (rs[k] + j < re[k]) q[k] += v[k] * vec[c[k]];
+      for (int k = 0; k < RPT; ++k) x[k] = x[k] + rn * (double)d[k];
+      outer++;
+      phase = PH_OUTER;
+    }
+  }
+  if (status >= SLOT_CONVERGED) {
+    double* __restrict__ xo = D.xout;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) xo[i] = x[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) {
+        D.x[i] = x[k];
+        if (phase == PH_INNER) {
+          rin_g[i] = rin[k];
+          d_g[i] = d[k];
+          if (USE_LDS) ((float*)D.p)[i] = vec32[i];
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    S->rho = rho;
+    S->thr = thr;
+    S->res2 = res2;
+    S->iters = tot;
+    S->repl = 0;
+    S->status = status;
+    S->ithr = ithr;
+    S->rn = rn;
+    S->inner = inner;
+    S->phase = phase;
+    S->outer = outer;
+    S->gen = D.gen;
   }
 }
 
@@ -145,7 +367,7 @@ __device__ __forceinline__ void rows_times(const int32_t* __restrict__ rpl,
 // gather vector (p, or x during the true-residual check); otherwise the
 // slot's p array in HBM serves as the gather vector.  x, r and q of the
 // thread's rows live in registers for the whole launch.
-template <int BS, int RPT, bool USE_LDS>
+template <int BS, int RPT, bool USE_LDS, int MODE>
 __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ desc,
                                                  SlotState* __restrict__ state, int base, int K,
                                                  int vec_cap) {
@@ -154,7 +376,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
   __shared__ int ired[BS / 64];
   const SlotDesc& D = desc[base + blockIdx.x];
   SlotState* S = state + base + blockIdx.x;
-  if (!D.active) return;
+  if (!D.active || D.mode != MODE) return;
   const bool fresh = S->gen != D.gen;
   if (!fresh && S->status >= SLOT_CONVERGED) return;
   const int n = D.n;
@@ -175,6 +397,14 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
     }
     __threadfence_block();
     __syncthreads();
+    if (MODE == 1) {
+      // refinement mode: the FP32 copy of the values, rounded to nearest
+      const double* __restrict__ v = D.val;
+      float* __restrict__ w = D.v32;
+      for (int k = tid; k < D.nnz; k += BS) w[k] = (float)v[k];
+      __threadfence_block();
+      __syncthreads();
+    }
   }
   const int32_t* __restrict__ rp = D.rowptr;
   const int32_t* __restrict__ col = D.col;
@@ -192,6 +422,10 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
     if (i < n) mylen = max(mylen, rpl[i + 1] - rpl[i]);
   }
   const int maxlen = bmax<BS>(mylen, ired);
+  if (MODE == 1) {
+    ir_body<BS, RPT, USE_LDS>(D, S, K, fresh, rpl, maxlen, dyn, red);
+    return;
+  }
   double x[RPT], r[RPT], q[RPT];
   double rho, thr;
   int status = SLOT_RUN;
@@ -346,12 +580,14 @@ constexpr size_t kAlign = 256;
 
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// arena layout of one system: rowptr | col | val | b | x | r | p
+// arena layout of one system: rowptr | col | val | b | x | r | p, plus the
+// FP32 values in refinement mode (there r holds the inner r and d, p the
+// inner p, all FP32)
 struct Layout {
-  size_t col, val, b, x, r, p, total;
+  size_t col, val, b, x, r, p, v32, total;
 };
 
-Layout layout(int64_t n, int64_t nnz) {
+Layout layout(int64_t n, int64_t nnz, int mode) {
   Layout L;
   L.col = up((n + 1) * 4);
   L.val = L.col + up(nnz * 4);
@@ -359,7 +595,8 @@ Layout layout(int64_t n, int64_t nnz) {
   L.x = L.b + up(n * 8);
   L.r = L.x + up(n * 8);
   L.p = L.r + up(n * 8);
-  L.total = L.p + up(n * 8);
+  L.v32 = L.p + up(n * 8);
+  L.total = L.v32 + (mode == 1 ? up(nnz * 4) : 0);
   return L;
 }
 
@@ -413,6 +650,8 @@ struct Request {
   size_t bytes;       // arena footprint
   size_t in_bytes;    // packed inputs (rowptr | col | val | b)
   int cls;
+  int mode;
+  float inner_tol;
   bool packed = false;   // inputs packed in the pinned input pool at in_off
   size_t in_off = 0;
   // copies of the inputs while the pinned pool had no room at submit
@@ -472,8 +711,8 @@ struct mxs_batch {
   std::deque<mxs::Request> pending;
   std::unordered_map<uint64_t, mxs::Result> results;
   uint64_t next_ticket = 1;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[4] = {};       // by mask of resident modes
+  hipGraphExec_t exec[4] = {};
   hipStream_t branch[mxs::kMaxClasses] = {};  // capture-time fork streams
   hipEvent_t fork = nullptr, join[mxs::kMaxClasses] = {};
   int64_t completed = 0;
@@ -485,25 +724,23 @@ struct mxs_batch {
 namespace mxs {
 namespace {
 
-size_t footprint(int64_t n, int64_t nnz) { return layout(n, nnz).total; }
-
 using BatchKernel = void (*)(const SlotDesc*, SlotState*, int, int, int);
 
 // (block, rows per thread) -> kernel; rows per thread in {1, 2, 4, 6, 8, 10, 12, 16}
 constexpr int kRpt[] = {1, 2, 4, 6, 8, 10, 12, 16};
 
-template <bool L>
-BatchKernel pick(int block, int rpt) {
+template <bool L, int M>
+BatchKernel pick_m(int block, int rpt) {
 #define MXS_BK(B)                                          \
   if (block == B) {                                        \
-    if (rpt <= 1) return k_batch_cg<B, 1, L>;              \
-    if (rpt <= 2) return k_batch_cg<B, 2, L>;              \
-    if (rpt <= 4) return k_batch_cg<B, 4, L>;              \
-    if (rpt <= 6) return k_batch_cg<B, 6, L>;              \
-    if (rpt <= 8) return k_batch_cg<B, 8, L>;              \
-    if (rpt <= 10) return k_batch_cg<B, 10, L>;            \
-    if (rpt <= 12) return k_batch_cg<B, 12, L>;            \
-    return k_batch_cg<B, 16, L>;                           \
+    if (rpt <= 1) return k_batch_cg<B, 1, L, M>;           \
+    if (rpt <= 2) return k_batch_cg<B, 2, L, M>;           \
+    if (rpt <= 4) return k_batch_cg<B, 4, L, M>;           \
+    if (rpt <= 6) return k_batch_cg<B, 6, L, M>;           \
+    if (rpt <= 8) return k_batch_cg<B, 8, L, M>;           \
+    if (rpt <= 10) return k_batch_cg<B, 10, L, M>;         \
+    if (rpt <= 12) return k_batch_cg<B, 12, L, M>;         \
+    return k_batch_cg<B, 16, L, M>;                        \
   }
   MXS_BK(128)
   MXS_BK(256)
@@ -511,6 +748,11 @@ BatchKernel pick(int block, int rpt) {
   MXS_BK(1024)
 #undef MXS_BK
   return nullptr;
+}
+
+BatchKernel pick(bool lds, int mode, int block, int rpt) {
+  if (mode == 0) return lds ? pick_m<true, 0>(block, rpt) : pick_m<false, 0>(block, rpt);
+  return lds ? pick_m<true, 1>(block, rpt) : pick_m<false, 1>(block, rpt);
 }
 
 int rpt_for(int max_n, int block) {
@@ -525,33 +767,32 @@ size_t class_lds(const ClassCfg& C) {
   return (C.lds ? (size_t)C.max_n * sizeof(double) : 0) + (size_t)(C.max_n + 1) * 4;
 }
 
-mxs_status build_graph(mxs_batch* B) {
+// One graph per set of resident modes (bit 0: FP64 CG, bit 1: refinement):
+// the class kernels are independent, so each class runs on its own branch
+// (fork from the main stream, join back before the state copy), with the
+// kernel of each present mode in turn.
+mxs_status build_graph(mxs_batch* B, int mask) {
   mxs_ctx* ctx = B->ctx;
-  if (B->exec) {
-    (void)hipGraphExecDestroy(B->exec);
-    (void)hipGraphDestroy(B->graph);
-    B->exec = nullptr;
-    B->graph = nullptr;
-  }
-  // the class kernels are independent: each runs on its own branch of the
-  // graph (fork from the main stream, join back before the state copy)
   MXS_HIP_TRY(ctx, hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
   (void)hipEventRecord(B->fork, B->stream);
   for (int c = 0; c < B->nclasses; ++c) {
     const ClassCfg& C = B->cls[c];
     if (C.slots == 0) continue;
     (void)hipStreamWaitEvent(B->branch[c], B->fork, 0);
-    BatchKernel k = C.lds ? pick<true>(C.block, C.rpt) : pick<false>(C.block, C.rpt);
-    hipLaunchKernelGGL(k, dim3(C.slots), dim3(C.block), class_lds(C), B->branch[c], B->d_desc,
-                       B->d_state, C.base, B->K, C.max_n);
+    for (int mode = 0; mode < 2; ++mode) {
+      if (!(mask >> mode & 1)) continue;
+      BatchKernel k = pick(C.lds, mode, C.block, C.rpt);
+      hipLaunchKernelGGL(k, dim3(C.slots), dim3(C.block), class_lds(C), B->branch[c],
+                         B->d_desc, B->d_state, C.base, B->K, C.max_n);
+    }
     (void)hipEventRecord(B->join[c], B->branch[c]);
     (void)hipStreamWaitEvent(B->stream, B->join[c], 0);
   }
   (void)hipMemcpyAsync(B->h_state, B->d_state, sizeof(SlotState) * B->nslots,
                        hipMemcpyDeviceToHost, B->stream);
-  hipError_t e = hipStreamEndCapture(B->stream, &B->graph);
+  hipError_t e = hipStreamEndCapture(B->stream, &B->graph[mask]);
   if (e != hipSuccess) return fail(ctx, MXS_HIP, "graph capture failed: %s", hipGetErrorString(e));
-  MXS_HIP_TRY(ctx, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+  MXS_HIP_TRY(ctx, hipGraphInstantiate(&B->exec[mask], B->graph[mask], nullptr, nullptr, 0));
   return MXS_OK;
 }
 
@@ -587,7 +828,7 @@ bool validate_csr(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* col)
 // packs rowptr | col | val | b at `dst` in the arena layout
 void pack(char* dst, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
           const double* val, const double* b) {
-  const Layout L = layout(n, nnz);
+  const Layout L = layout(n, nnz, 0);
   std::memcpy(dst, rp, (n + 1) * 4);
   if (nnz) {
     std::memcpy(dst + L.col, col, nnz * 4);
@@ -691,10 +932,12 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
     for (int attempt = 0; attempt < 2; ++attempt) {
       const size_t lds = class_lds(C);
       if (lds <= 65536) break;
-      BatchKernel k = C.lds ? pick<true>(C.block, C.rpt) : pick<false>(C.block, C.rpt);
-      if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds) == hipSuccess)
-        break;
+      bool ok = true;
+      for (int mode = 0; mode < 2; ++mode)
+        ok = ok && hipFuncSetAttribute((const void*)pick(C.lds, mode, C.block, C.rpt),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds) == hipSuccess;
+      if (ok) break;
       (void)hipGetLastError();
       C.lds = false;  // fall back to the gather vector in HBM
     }
@@ -764,7 +1007,7 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
       break;
     }
     B->desc_dirty = false;
-    st = build_graph(B);
+    for (int mask = 1; mask < 4 && !st; ++mask) st = build_graph(B, mask);
   } while (0);
   if (st) {
     mxs_batch_destroy(B);
@@ -777,8 +1020,10 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
 mxs_status mxs_batch_destroy(mxs_batch* B) {
   if (!B) return MXS_OK;
   if (B->stream) (void)hipStreamSynchronize(B->stream);
-  if (B->exec) (void)hipGraphExecDestroy(B->exec);
-  if (B->graph) (void)hipGraphDestroy(B->graph);
+  for (int m = 0; m < 4; ++m) {
+    if (B->exec[m]) (void)hipGraphExecDestroy(B->exec[m]);
+    if (B->graph[m]) (void)hipGraphDestroy(B->graph[m]);
+  }
   if (B->ctx) {
     B->ctx->alloc.release(B->arena_mem);
     B->ctx->alloc.release(B->d_desc);
@@ -816,13 +1061,21 @@ mxs_status mxs_batch_submit_many(mxs_batch* B, int64_t count, const mxs_batch_re
       statuses[i] = fail(ctx, MXS_UNSUPPORTED, "sizes beyond int32");
       continue;
     }
+    if (q.mode != 0 && q.mode != 1) {
+      statuses[i] = fail(ctx, MXS_INVALID_ARG, "unknown batch mode %d", (int)q.mode);
+      continue;
+    }
+    if (q.mode == 1 && !(q.inner_rel_tol >= 0.0 && q.inner_rel_tol < 1.0)) {
+      statuses[i] = fail(ctx, MXS_INVALID_ARG, "inner tolerance must be in [0, 1)");
+      continue;
+    }
     const int c = class_of(B, q.n);
     if (c < 0) {
       statuses[i] = fail(ctx, MXS_UNSUPPORTED, "n = %lld exceeds the largest size class",
                          (long long)q.n);
       continue;
     }
-    const Layout L = layout(q.n, q.nnz);
+    const Layout L = layout(q.n, q.nnz, q.mode);
     if (L.total > B->arena.size) {
       statuses[i] = fail(ctx, MXS_BUDGET, "request needs %zu bytes, budget is %zu", L.total,
                          B->arena.size);
@@ -841,6 +1094,8 @@ mxs_status mxs_batch_submit_many(mxs_batch* B, int64_t count, const mxs_batch_re
     r.bytes = L.total;
     r.in_bytes = L.x;
     r.cls = c;
+    r.mode = q.mode;
+    r.inner_tol = q.inner_rel_tol > 0.0 ? (float)q.inner_rel_tol : 1e-4f;
     // pack into pinned memory when there is room; otherwise keep a copy and
     // pack at admission
     r.packed = B->inpool.alloc(r.in_bytes, &r.in_off);
@@ -900,7 +1155,7 @@ mxs_status mxs_batch_submit(mxs_batch* B, int64_t n, int64_t nnz, const int32_t*
                             const int32_t* col, const double* val, const double* b,
                             double rel_tol, int64_t max_iters, uint64_t* ticket) {
   if (!B || !ticket) return MXS_INVALID_ARG;
-  mxs_batch_request q = {n, nnz, rowptr, col, val, b, rel_tol, max_iters};
+  mxs_batch_request q = {n, nnz, rowptr, col, val, b, rel_tol, max_iters, 0, 0, 0.0};
   mxs_status st = MXS_OK;
   const mxs_status call = mxs_batch_submit_many(B, 1, &q, ticket, &st);
   return call ? call : st;
@@ -954,7 +1209,7 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
       continue;
     }
     char* p = (char*)B->arena_mem + off;
-    const Layout L = layout(R.n, R.nnz);
+    const Layout L = layout(R.n, R.nnz, R.mode);
     SlotDesc& d = B->h_desc[si];
     std::memset(&d, 0, sizeof(d));
     d.rowptr = (int32_t*)p;
@@ -974,6 +1229,9 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
     if (++B->gen == 0) ++B->gen;  // 0 marks a state no launch has written
     d.gen = B->gen;
     d.in_words = (int32_t)(R.in_bytes / 16);
+    d.v32 = (float*)(p + L.v32);
+    d.mode = R.mode;
+    d.inner_tol = R.inner_tol;
     B->desc_dirty = true;
     Slot& s = B->slots[si];
     s.busy = true;
@@ -987,12 +1245,16 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
     B->pending.erase(B->pending.begin() + idx);
   }
   // 2. run K iterations of every resident system, read the states back
-  int active = 0;
-  for (const Slot& s : B->slots) active += s.busy ? 1 : 0;
+  int active = 0, mask = 0;
+  for (int i = 0; i < B->nslots; ++i) {
+    if (!B->slots[i].busy) continue;
+    active++;
+    mask |= 1 << B->h_desc[i].mode;
+  }
   if (active > 0) {
     mxs_status st = upload_desc(B);
     if (st) return st;
-    MXS_HIP_TRY(ctx, hipGraphLaunch(B->exec, B->stream));
+    MXS_HIP_TRY(ctx, hipGraphLaunch(B->exec[mask], B->stream));
     MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
   }
   // 3. every resident slot has copied its inputs by now; retire the
@@ -1010,8 +1272,9 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
     const double* xs = B->xout_mem + B->xout_off[i];
     R.x.assign(xs, xs + s.n);
     std::memset(&R.info, 0, sizeof(R.info));
-    R.info.iters = d.iters;
+    R.info.iters = d.iters;  // refinement mode: inner iterations in total
     R.info.replacements = d.repl;
+    R.info.restarts = B->h_desc[i].mode == 1 ? d.outer : 0;  // refinement: outer steps
     const double tol = B->h_desc[i].tol;
     const double nb = tol > 0 ? d.thr / tol : 0.0;
     R.info.relres_recurrence = nb > 0 ? sqrt(d.res2) / nb : 0.0;

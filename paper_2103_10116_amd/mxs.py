@@ -430,12 +430,17 @@ class Batch:
 
     # mxs_batch_request, field for field
     _REQ = np.dtype([("n", "<i8"), ("nnz", "<i8"), ("rowptr", "<u8"), ("col", "<u8"),
-                     ("val", "<u8"), ("b", "<u8"), ("rel_tol", "<f8"), ("max_iters", "<i8")])
+                     ("val", "<u8"), ("b", "<u8"), ("rel_tol", "<f8"), ("max_iters", "<i8"),
+                     ("mode", "<i4"), ("reserved", "<i4"), ("inner_rel_tol", "<f8")])
+    MODES = {"f64": 0, "ir32": 1}
 
-    def submit_many(self, systems, tol=1e-10, max_iters=0):
+    def submit_many(self, systems, tol=1e-10, max_iters=0, mode="f64", inner_tol=0.0):
         """Queues [(A, b), ...] in one call (validated and packed on host
-        threads).  Returns (tickets, statuses) as numpy arrays; ticket 0
-        marks a rejected request, whose status says why."""
+        threads).  mode "f64" (CG in FP64) or "ir32" (FP32-storage CG inside
+        FP64 iterative refinement, inner tolerance inner_tol, 0 = 1e-4).
+        Returns (tickets, statuses) as numpy arrays; ticket 0 marks a
+        rejected request, whose status says why."""
+        md = self.MODES.get(mode, mode)
         k = len(systems)
         req = np.zeros(k, self._REQ)
         keep = []
@@ -444,7 +449,7 @@ class Batch:
                     np.ascontiguousarray(A.val, np.float64), np.ascontiguousarray(b, np.float64))
             keep.append(arrs)
             req[i] = (A.n, arrs[1].size, arrs[0].ctypes.data, arrs[1].ctypes.data,
-                      arrs[2].ctypes.data, arrs[3].ctypes.data, tol, max_iters)
+                      arrs[2].ctypes.data, arrs[3].ctypes.data, tol, max_iters, md, 0, inner_tol)
         tickets = np.zeros(k, np.uint64)
         statuses = np.zeros(k, np.int32)
         _check(_lib.mxs_batch_submit_many(self.handle, k, req.ctypes.data, tickets.ctypes.data,

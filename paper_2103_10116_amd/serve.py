@@ -64,7 +64,8 @@ def _report(mode, reqs, arrival, done, iters, statuses, t_first, keep_x, xs, ste
 
 
 def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1024,
-                iters_per_step=16, classes=None, staging_bytes=0, keep_x=False) -> ServeReport:
+                iters_per_step=16, classes=None, staging_bytes=0, mode="f64",
+                keep_x=False) -> ServeReport:
     from . import mxs
     B = mxs.Batch(ctx, budget_bytes, max_slots, iters_per_step, classes, staging_bytes)
     order = sorted(reqs, key=lambda r: r.arrival)
@@ -83,7 +84,7 @@ def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1
         if j > i:
             # everything that arrived since the last step, in one call
             arrived = order[i:j]
-            tickets, sts = B.submit_many([systems[r.rid] for r in arrived], tol)
+            tickets, sts = B.submit_many([systems[r.rid] for r in arrived], tol, mode=mode)
             for r, t, s in zip(arrived, tickets.tolist(), sts.tolist()):
                 if s != mxs.OK:
                     raise mxs.MxsError(s, f"request {r.rid} rejected")
@@ -106,8 +107,8 @@ def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1
         elif i < len(order):
             time.sleep(max(0.0, order[i].arrival - (time.perf_counter() - t0)))
     B.close()
-    return _report("batched", order, arrival, done, iters, statuses, order[0].arrival, keep_x,
-                   xs, steps, max_active)
+    return _report("batched" if mode == "f64" else f"batched_{mode}", order, arrival, done,
+                   iters, statuses, order[0].arrival, keep_x, xs, steps, max_active)
 
 
 def run_plain(ctx, reqs, systems, tol=1e-10, keep_x=False) -> ServeReport:

@@ -203,3 +203,71 @@ def test_submit_many(env):
         assert s1 == sm == mxs.OK and r1.iters == rm.iters
         assert np.array_equal(x1.view(np.uint64), xm.view(np.uint64)), i
     B.close()
+
+
+def test_ir32_matches_oracle(env, orc):
+    """Refinement mode (FP32 storage, FP64 residual and update): every
+    result meets 1e-10 by the oracle's FP64 residual, with the oracle's
+    refinement taking the same number of outer steps and about the same
+    inner iterations."""
+    mxs, ctx, torch = env
+    ms = np.concatenate([[8, 9, 33, 64, 96], I.rng(46).integers(8, 97, 19)])
+    sys_ = _systems(ms, 800)
+    B = mxs.Batch(ctx, 256 << 20, 16, iters_per_step=8)
+    tickets, sts = B.submit_many(sys_, 1e-10, mode="ir32")
+    assert (sts == mxs.OK).all()
+    _drain(B)
+    for (A, b), t in zip(sys_, tickets.tolist()):
+        s, x, res = B.poll(t, A.n)
+        assert s == mxs.OK, (A.n, res)
+        rel = orc.true_relres(A, b, x)
+        assert rel <= 1e-10 + _slack(orc, A, b, x), (A.n, rel)
+        ref = orc.ir(A, b, low="f32", tol=1e-10, outer_max=50, inner_tol=1e-4)
+        assert ref.status == 0
+        assert abs(res.restarts - ref.outer_iters) <= 1, (A.n, res.restarts, ref.outer_iters)
+        assert abs(res.iters - ref.inner_iters_total) <= 3 + ref.inner_iters_total // 10, \
+            (A.n, res.iters, ref.inner_iters_total)
+    B.close()
+
+
+def test_modes_mixed_and_alone_bitwise(env):
+    """FP64 and refinement requests share one batch; each result is
+    bitwise the one it gives alone."""
+    mxs, ctx, torch = env
+    sys_ = _systems(I.rng(47).integers(8, 97, 30), 900)
+    modes = ["f64" if i % 3 else "ir32" for i in range(len(sys_))]
+    B = mxs.Batch(ctx, 256 << 20, 24, iters_per_step=6)
+    tk = []
+    for (A, b), md in zip(sys_, modes):
+        t, s = B.submit_many([(A, b)], 1e-10, mode=md)
+        assert s[0] == mxs.OK
+        tk.append(int(t[0]))
+    _drain(B)
+    mixed = [B.poll(t, A.n) for t, (A, b) in zip(tk, sys_)]
+    B.close()
+    for k in (0, 3, 4, 29):
+        A, b = sys_[k]
+        B = mxs.Batch(ctx, 64 << 20, 4, iters_per_step=6)
+        t, _ = B.submit_many([(A, b)], 1e-10, mode=modes[k])
+        _drain(B)
+        s, x, res = B.poll(int(t[0]), A.n)
+        B.close()
+        assert s == mixed[k][0] == mxs.OK
+        assert np.array_equal(x.view(np.uint64), mixed[k][1].view(np.uint64)), (k, modes[k])
+        assert res.iters == mixed[k][2].iters and res.restarts == mixed[k][2].restarts
+
+
+def test_ir32_limits(env):
+    mxs, ctx, torch = env
+    A, b = _systems([40], 950)[0]
+    B = mxs.Batch(ctx, 64 << 20, 4)
+    t, s = B.submit_many([(A, b), (A, np.zeros(A.n)), (A, b)], 1e-10, max_iters=5,
+                         mode="ir32")
+    t2, s2 = B.submit_many([(A, b)], 1e-10, mode="ir32", inner_tol=1.5)
+    assert s2[0] == mxs.INVALID_ARG and t2[0] == 0
+    _drain(B)
+    s0, x0, r0 = B.poll(int(t[0]), A.n)
+    assert s0 == mxs.NOT_CONVERGED and r0.iters <= 5
+    s1, x1, r1 = B.poll(int(t[1]), A.n)
+    assert s1 == mxs.OK and not x1.any() and r1.iters == 0
+    B.close()
