@@ -70,7 +70,13 @@ def measured_traffic(fmt, dt, info):
     wpg = info["waves_per_group"]
     chunked = -(-info["blocks"] // wpg) * 64 * wpg  # threads of the stream/COO grid
     keys = []
-    if fmt == "csr" and info["lanes_per_row"] == 0:
+    ck = info["csr_kernel"]
+    if fmt == "csr" and ck == 4:  # products through LDS
+        keys.append((f"k_csr_pr<{t},{info['block_nnz']},false,{wpg}>", chunked))
+    if fmt == "csr" and ck == 3:  # rows from LDS, two waves per group
+        keys.append((f"k_csr_rl<{t},{info['block_nnz']},false,2>",
+                     -(-info["blocks"] // 2) * 128))
+    if fmt == "csr" and ck == 1:
         keys.append((f"k_csr<{t},{npl},false,{wpg}>", chunked))
     if fmt == "csr" and info["lanes_per_row"] == 1:
         keys.append((f"k_csr_row<{t},false>", -(-info["nrows"] // 256) * 256))

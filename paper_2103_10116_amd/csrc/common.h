@@ -80,6 +80,7 @@ struct CsrPart {
   int rpg = 4;
   int wpb = 4;    // stream kernel: independent waves per work-group (1 or 4)
   bool rows_lds = false;  // rows-from-LDS kernel (blocks of <= 64 rows, block_nnz entries)
+  bool products = false;  // products-through-LDS kernel (the same blocks)
 };
 
 // COO: equal chunks of block_nnz entries, one wave per chunk.  Rows cut by

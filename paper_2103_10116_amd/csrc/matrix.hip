@@ -285,26 +285,37 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
     while (G < 64 && G < opts->lanes_per_row) G <<= 1;
     if (G == 2) G = 4;
   }
-  // AUTO keeps the stream kernel: on the stencil matrices it gathers x with
-  // fewer cache lines per instruction than the lanes-along-a-row layout
-  // AUTO: rows-from-LDS when every row fits a lane's walk (longest row <=
-  // 64 entries), else the row-block stream kernel (power-law rows)
+  // AUTO: the row-block stream kernel when some row is longer than 64
+  // entries (power-law rows); otherwise one of the two LDS kernels over
+  // blocks of <= 64 rows.  Measured on the stencil matrices: with FP64
+  // values and rows of more than 16 entries the products kernel (512-entry
+  // blocks) is the faster (27-point: 176 vs 198 us); with shorter rows or
+  // narrower values the rows-from-LDS kernel is.  (The lanes-along-a-row
+  // layout gathers x with more cache lines per instruction on stencils.)
   int kind_eff = kind;
-  if (kind == MXS_CSR_AUTO) kind_eff = maxL <= 64 ? MXS_CSR_ROWS_LDS : MXS_CSR_STREAM;
+  if (kind == MXS_CSR_AUTO)
+    kind_eff = maxL > 64                           ? MXS_CSR_STREAM
+               : (A->dt == MXS_F64 && maxL > 16) ? MXS_CSR_PRODUCTS
+                                                 : MXS_CSR_ROWS_LDS;
   bool vec = kind_eff == MXS_CSR_VECTOR;
   A->csr.lanes = vec ? G : 0;
   A->csr.wpb = (opts && opts->waves_per_group == 1) ? 1 : 4;
+  if (kind_eff == MXS_CSR_PRODUCTS)
+    A->csr.wpb = (opts && opts->waves_per_group > 0)
+                     ? (opts->waves_per_group == 1 ? 1 : opts->waves_per_group == 2 ? 2 : 4)
+                     : 2;
   int rpg = (opts && opts->rows_per_group > 0) ? opts->rows_per_group : (G >= 8 ? 8 : 4);
   A->csr.rpg = rpg <= 2 ? 2 : rpg <= 4 ? 4 : 8;
   if (A->csr.rpg > G) A->csr.rpg = G;
   std::vector<int32_t> blocks, bnnz;
   A->csr.rows_lds = kind_eff == MXS_CSR_ROWS_LDS;
-  if (A->csr.rows_lds) {
+  A->csr.products = kind_eff == MXS_CSR_PRODUCTS;
+  if (A->csr.rows_lds || A->csr.products) {
     // rows-from-LDS blocks: at most 64 rows; entry budget 64 * (longest row)
     // rounded up to 512 or 1024 (2048 only on request: its LDS footprint
     // halves the waves per CU); rows longer than it get a wave of their own
     const int64_t want = 64 * std::max<int64_t>(maxL, 1);
-    block_nnz = want <= 512 ? 512 : 1024;
+    block_nnz = A->csr.products || want <= 512 ? 512 : 1024;
     if (opts && opts->block_nnz > 0) block_nnz = opts->block_nnz <= 512 ? 512
                                                 : opts->block_nnz <= 1024 ? 1024 : 2048;
   } else if (kind == MXS_CSR_AUTO && !(opts && opts->block_nnz > 0)) {
@@ -312,7 +323,7 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
   }
   A->csr.block_nnz = block_nnz;
   A->csr.nblocks = csr_partition(rp.data(), A->n, block_nnz, blocks,
-                                 A->csr.rows_lds ? 64 : -1);
+                                 A->csr.rows_lds || A->csr.products ? 64 : -1);
   bnnz.resize(blocks.size());
   for (size_t b = 0; b < blocks.size(); ++b) bnnz[b] = rp[blocks[b]];
   A->csr.blocks = upload(ctx, A, blocks);
@@ -644,6 +655,11 @@ mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
   out->lanes_per_row = A->fmt == MXS_CSR ? A->csr.lanes : 0;
   out->rows_per_group = A->fmt == MXS_CSR ? A->csr.rpg : 0;
   out->waves_per_group = A->fmt == MXS_CSR ? A->csr.wpb : A->coo.wpb;
+  out->csr_kernel = A->fmt != MXS_CSR  ? 0
+                    : A->csr.products ? MXS_CSR_PRODUCTS
+                    : A->csr.rows_lds ? MXS_CSR_ROWS_LDS
+                    : A->csr.lanes >= 1 ? MXS_CSR_VECTOR
+                                       : MXS_CSR_STREAM;
   out->bytes = A->bytes;
   return MXS_OK;
 }

@@ -345,6 +345,94 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
 }
 
 // ---------------------------------------------------------------------------
+// CSR, products through LDS: the same row blocks as above (<= 64 rows,
+// <= CMAX entries), but every lane of the wave first forms products
+// val[k] * x[col[k]] for a contiguous slice of the block's entries (loads
+// coalesced, all gathers of a round in flight together) and stores them in
+// LDS; then lane r sums row r's products in entry order with four
+// interleaved accumulators.  LDS holds one value per entry (8 bytes in
+// FP64) instead of a value and an index.
+// ---------------------------------------------------------------------------
+template <typename V, typename T, int CMAX, bool SCALED, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_csr_pr(int64_t nblocks,
+                                                     const int32_t* __restrict__ blocks,
+                                                     const int32_t* __restrict__ bnnz,
+                                                     const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const V* __restrict__ val,
+                                                     const float* __restrict__ scale,
+                                                     const T* __restrict__ x, T* __restrict__ y,
+                                                     T alpha, T beta,
+                                                     const int32_t* __restrict__ skip) {
+  __shared__ T pl_all[WPB][CMAX];
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  T* pl = pl_all[wv];
+  const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if (b >= nblocks) return;
+  const int32_t r0 = blocks[b], r1 = blocks[b + 1];
+  const int32_t s = bnnz[b], e = bnnz[b + 1];
+  const int nr = r1 - r0, len = e - s;
+  if (len > CMAX) {  // a single long row
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int32_t k = s + lane;
+    for (; k + 192 < e; k += 256) {
+      const int32_t c0 = col[k], c1 = col[k + 64], c2 = col[k + 128], c3 = col[k + 192];
+      const T v0 = to_acc(val[k]), v1 = to_acc(val[k + 64]), v2 = to_acc(val[k + 128]),
+              v3 = to_acc(val[k + 192]);
+      a0 += v0 * x[c0];
+      a1 += v1 * x[c1];
+      a2 += v2 * x[c2];
+      a3 += v3 * x[c3];
+    }
+    for (; k < e; k += 64) a0 += to_acc(val[k]) * x[col[k]];
+    T acc = wave_sum((a0 + a1) + (a2 + a3));
+    if (lane == 0) {
+      if (SCALED) acc *= (T)scale[r0];
+      y[r0] = combine(alpha, acc, beta, y, r0);
+    }
+    return;
+  }
+  const int32_t ra = lane < nr ? rowptr[r0 + lane] - s : 0;
+  const int32_t rb = lane < nr ? rowptr[r0 + lane + 1] - s : 0;
+  // products, eight entries per lane in flight per round
+  for (int base = 0; base < len; base += 8 * 64) {
+    int32_t c[8];
+    T v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = base + t * 64 + lane;
+      c[t] = 0;
+      v[t] = 0;
+      if (k < len) {
+        c[t] = col[s + k];
+        v[t] = to_acc(val[s + k]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = base + t * 64 + lane;
+      if (k < len) pl[k] = v[t] * x[c[t]];
+    }
+  }
+  wave_sync();
+  if (lane >= nr) return;
+  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int32_t k = ra;
+  for (; k + 3 < rb; k += 4) {
+    s0 += pl[k];
+    s1 += pl[k + 1];
+    s2 += pl[k + 2];
+    s3 += pl[k + 3];
+  }
+  for (; k < rb; ++k) s0 += pl[k];
+  T sum = (s0 + s1) + (s2 + s3);
+  const int64_t i = (int64_t)r0 + lane;
+  if (SCALED) sum *= (T)scale[i];
+  y[i] = combine(alpha, sum, beta, y, i);
+}
+
+// ---------------------------------------------------------------------------
 // CSR, one thread per row: neighbouring lanes hold neighbouring rows, so on
 // banded/stencil matrices the x gathers of one instruction are contiguous
 // (as in ELL); the row's entries stream through the L1 over the iterations
@@ -624,10 +712,40 @@ void launch_csr_rl(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, 
       skip);
 }
 
+template <typename V, typename T, bool SCALED, int CMAX, int WPB>
+void launch_csr_pr_w(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
+                     const int32_t* skip) {
+  const dim3 grid((unsigned)((P.nblocks + WPB - 1) / WPB));
+  k_csr_pr<V, T, CMAX, SCALED, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+      P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
+      skip);
+}
+
+template <typename V, typename T, bool SCALED, int CMAX>
+void launch_csr_pr(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
+                   const int32_t* skip) {
+  if (P.wpb == 1)
+    launch_csr_pr_w<V, T, SCALED, CMAX, 1>(ctx, P, alpha, x, beta, y, skip);
+  else if (P.wpb == 2)
+    launch_csr_pr_w<V, T, SCALED, CMAX, 2>(ctx, P, alpha, x, beta, y, skip);
+  else
+    launch_csr_pr_w<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip);
+}
+
 template <typename V, typename T, bool SCALED>
 void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
                 const int32_t* skip) {
   const CsrPart& P = A->csr;
+  if (P.products) {
+    if (P.nblocks == 0) return;
+    if (P.block_nnz <= 512)
+      launch_csr_pr<V, T, SCALED, 512>(ctx, P, alpha, x, beta, y, skip);
+    else if (P.block_nnz <= 1024)
+      launch_csr_pr<V, T, SCALED, 1024>(ctx, P, alpha, x, beta, y, skip);
+    else
+      launch_csr_pr<V, T, SCALED, 2048>(ctx, P, alpha, x, beta, y, skip);
+    return;
+  }
   if (P.rows_lds) {
     if (P.nblocks == 0) return;
     if (P.block_nnz <= 512)

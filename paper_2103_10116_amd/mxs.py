@@ -48,9 +48,9 @@ class ConvertOpts(C.Structure):
                 ("waves_per_group", C.c_int32)]
 
 
-CSR_AUTO, CSR_STREAM, CSR_VECTOR, CSR_ROWS_LDS = 0, 1, 2, 3
+CSR_AUTO, CSR_STREAM, CSR_VECTOR, CSR_ROWS_LDS, CSR_PRODUCTS = 0, 1, 2, 3, 4
 CSR_KERNELS = {"auto": CSR_AUTO, "stream": CSR_STREAM, "vector": CSR_VECTOR,
-               "rows_lds": CSR_ROWS_LDS}
+               "rows_lds": CSR_ROWS_LDS, "products": CSR_PRODUCTS}
 
 
 class MatrixDesc(C.Structure):
@@ -59,7 +59,8 @@ class MatrixDesc(C.Structure):
                 ("ell_stride", C.c_int64), ("coo_nnz", C.c_int64), ("blocks", C.c_int64),
                 ("bytes", C.c_int64), ("block_nnz", C.c_int32),
                 ("lanes_per_row", C.c_int32), ("rows_per_group", C.c_int32),
-                ("waves_per_group", C.c_int32)]
+                ("waves_per_group", C.c_int32), ("csr_kernel", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Stop(C.Structure):

@@ -207,7 +207,9 @@ CSR_VARIANTS = [dict(csr_kernel="stream", block_nnz=b, waves_per_group=w)
     dict(csr_kernel="vector", lanes_per_row=g, rows_per_group=r)
     for g in (4, 8, 16, 32, 64) for r in (2, 4, 8)] + [
     dict(csr_kernel="vector", lanes_per_row=1)] + [
-    dict(csr_kernel="rows_lds", block_nnz=b) for b in (0, 512, 1024, 2048)]
+    dict(csr_kernel="rows_lds", block_nnz=b) for b in (0, 512, 1024, 2048)] + [
+    dict(csr_kernel="products", block_nnz=b, waves_per_group=w)
+    for b in (0, 512, 1024, 2048) for w in (0, 1, 2, 4)]
 
 
 @pytest.mark.parametrize("name", sorted(ZOO))
@@ -238,7 +240,8 @@ def test_spmv_csr_kernels(env, orc, name, dt):
         B = M.convert("csr", dt, **opts)
         d = B.info()
         assert (d["lanes_per_row"] > 0) == (opts["csr_kernel"] == "vector")
-        if opts["csr_kernel"] == "rows_lds" and opts["block_nnz"]:
+        assert d["csr_kernel"] == mxs.CSR_KERNELS[opts["csr_kernel"]]
+        if opts["csr_kernel"] in ("rows_lds", "products") and opts["block_nnz"]:
             assert d["block_nnz"] == opts["block_nnz"]
         y = torch.from_numpy(y0r).to(tdt).cuda()
         mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
