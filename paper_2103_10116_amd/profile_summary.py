@@ -33,7 +33,7 @@ def _short(name: str) -> str:
         .replace("void ", "").split("(")[0]
 
 
-def stats(trace_csv: str, out: str, command: str) -> None:
+def stats(trace_csv: str, out: str, command: str, top: int = 30) -> None:
     rows = list(csv.DictReader(open(trace_csv)))
     agg = collections.defaultdict(list)
     for r in rows:
@@ -42,10 +42,15 @@ def stats(trace_csv: str, out: str, command: str) -> None:
     lines = ["# rocprofv3 kernel trace summary", "", f"Command: `{command}`", "",
              "| kernel | grid (threads) | wg | calls | mean us | median us | total ms |",
              "|---|---|---|---|---|---|---|"]
-    for (name, grid, wg), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+    ranked = sorted(agg.items(), key=lambda kv: -sum(kv[1]))
+    for (name, grid, wg), v in ranked[:top]:
         v = sorted(v)
         lines.append(f"| `{name}` | {grid} | {wg} | {len(v)} | {sum(v)/len(v):.2f} | "
                      f"{v[len(v)//2]:.2f} | {sum(v)/1e3:.3f} |")
+    if len(ranked) > top:
+        rest = [t for _, v in ranked[top:] for t in v]
+        lines.append(f"| ({len(ranked) - top} more kernel/grid pairs) | | | {len(rest)} | | | "
+                     f"{sum(rest)/1e3:.3f} |")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
