@@ -3,7 +3,8 @@
 This package wraps ``oracle.c``, a plain single-threaded FP64 C implementation
 of the operations the GPU library computes: CSR/COO/ELL/hybrid storage and
 conversions, the sparse matrix-vector product, CG, BiCGSTAB, GMRES(m),
-mixed-precision iterative refinement and a dense LU solver.  Each C function
+Jacobi and block-Jacobi preconditioned CG, mixed-precision iterative
+refinement and a dense LU solver.  Each C function
 cites the passage of the paper (or the textbook the paper refers to) that it
 writes out.
 
@@ -102,6 +103,11 @@ def _declare(L):
         "orc_bicgstab": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info)]),
         "orc_gmres": (C.c_int, [_I64, _P, _P, _P, _P, _P, _I64, C.POINTER(Stop), C.POINTER(Info), _P, _I64]),
         "orc_ir": (C.c_int, [_I64, _P, _P, _P, C.c_int, _P, _P, _P, _P, _P, _D, _I64, _D, _I64, C.c_int, C.POINTER(IRInfo)]),
+        "orc_ir_pc": (C.c_int, [_I64, _P, _P, _P, C.c_int, _P, _P, _P, _P, _P, _D, _I64, _D, _I64, C.c_int, C.c_int, _I64, _P, C.POINTER(IRInfo)]),
+        "orc_jacobi": (C.c_int, [_I64, _P, _P, _P, _P]),
+        "orc_block_jacobi": (C.c_int, [_I64, _P, _P, _P, _I64, _P]),
+        "orc_prec_apply": (None, [_I64, C.c_int, _I64, _P, _P, _P]),
+        "orc_pcg": (C.c_int, [_I64, _P, _P, _P, C.c_int, _I64, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -358,6 +364,49 @@ def cg(A, b, x0=None, tol=1e-10, maxit=20000, abs_tol=0.0, hist=False, baseline=
     return _result(st, x, info, h[: 2 * info.iters].reshape(-1, 2) if hist else None)
 
 
+PRECONDS = {"jacobi": 1, "block_jacobi": 2}
+
+
+@dataclass
+class Precond:
+    kind: int
+    bs: int
+    minv: np.ndarray   # Jacobi: 1/a_ii; block Jacobi: column-major bs x bs inverses
+
+
+def jacobi(A) -> tuple[int, Precond]:
+    n, rp, ci, v = _csr(A)
+    d = np.zeros(n)
+    st = lib().orc_jacobi(n, _p(rp), _p(ci), _p(v), _p(d))
+    return st, Precond(1, 1, d)
+
+
+def block_jacobi(A, bs) -> tuple[int, Precond]:
+    n, rp, ci, v = _csr(A)
+    nb = -(-n // bs)
+    m = np.zeros(nb * bs * bs)
+    st = lib().orc_block_jacobi(n, _p(rp), _p(ci), _p(v), int(bs), _p(m))
+    return st, Precond(2, int(bs), m)
+
+
+def prec_apply(M: Precond, r):
+    rr = _c(r, np.float64)
+    z = np.zeros_like(rr)
+    lib().orc_prec_apply(len(rr), M.kind, M.bs, _p(_c(M.minv, np.float64)), _p(rr), _p(z))
+    return z
+
+
+def pcg(A, b, M: Precond, x0=None, tol=1e-10, maxit=20000, abs_tol=0.0, baseline=0):
+    n, rp, ci, v = _csr(A)
+    bb = _c(b, np.float64)
+    x = np.zeros(n) if x0 is None else np.array(x0, np.float64, copy=True)
+    info = Info()
+    mv = _c(M.minv, np.float64)
+    st = lib().orc_pcg(n, _p(rp), _p(ci), _p(v), M.kind, M.bs, _p(mv), _p(bb), _p(x),
+                       C.byref(_stop(tol, maxit, abs_tol, baseline)), C.byref(info))
+    return _result(st, x, info)
+
+
 def bicgstab(A, b, x0=None, tol=1e-10, maxit=10000, abs_tol=0.0):
     n, rp, ci, v = _csr(A)
     bb = _c(b, np.float64)
@@ -390,9 +439,11 @@ class IRResult:
 
 
 def ir(A, b, low="f32", x0=None, tol=1e-10, outer_max=50, inner_tol=1e-4,
-       inner_max=20000, last_step_variant=False, val32=None, h16=None, scale=None):
+       inner_max=20000, last_step_variant=False, val32=None, h16=None, scale=None,
+       precond: Precond | None = None):
     """Iterative refinement; the low-precision copy is built by the oracle's
-    own conversions unless passed in."""
+    own conversions unless passed in.  `precond` (from jacobi/block_jacobi)
+    preconditions the inner CG with its values rounded to FP32."""
     n, rp, ci, v = _csr(A)
     bb = _c(b, np.float64)
     x = np.zeros(n) if x0 is None else np.array(x0, np.float64, copy=True)
@@ -412,9 +463,18 @@ def ir(A, b, low="f32", x0=None, tol=1e-10, outer_max=50, inner_tol=1e-4,
         hh = _c(h16, np.uint16)
         ss = _c(scale, np.float32)
     info = IRInfo()
-    st = lib().orc_ir(n, _p(rp), _p(ci), _p(v), kind, _p(v32), _p(hh), _p(ss), _p(bb), _p(x),
-                      tol, outer_max, inner_tol, inner_max, 1 if last_step_variant else 0,
-                      C.byref(info))
+    if precond is None:
+        st = lib().orc_ir(n, _p(rp), _p(ci), _p(v), kind, _p(v32), _p(hh), _p(ss), _p(bb),
+                          _p(x), tol, outer_max, inner_tol, inner_max,
+                          1 if last_step_variant else 0, C.byref(info))
+    else:
+        st_c, m32 = cast_f32(precond.minv)
+        assert st_c == OK
+        m32 = _c(m32, np.float32)
+        st = lib().orc_ir_pc(n, _p(rp), _p(ci), _p(v), kind, _p(v32), _p(hh), _p(ss), _p(bb),
+                             _p(x), tol, outer_max, inner_tol, inner_max,
+                             1 if last_step_variant else 0, precond.kind, precond.bs,
+                             _p(m32), C.byref(info))
     return IRResult(st, x, info.outer_iters, info.inner_iters_total, info.relres_true)
 
 

@@ -541,6 +541,159 @@ int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Jacobi and block-Jacobi preconditioners, preconditioned CG               */
+/* (Saad 2003, ch. 10 and Algorithm 9.1)                                     */
+/* ------------------------------------------------------------------------ */
+int orc_jacobi(int64_t n, const int32_t* rowptr, const int32_t* col,
+               const double* val, double* dinv) {
+  for (int64_t i = 0; i < n; ++i) {
+    double d = 0.0;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+      if (col[k] == i) d = val[k];
+    if (d == 0.0 || !isfinite(d)) return ORC_BREAKDOWN;
+    dinv[i] = 1.0 / d;
+  }
+  return ORC_OK;
+}
+
+int orc_block_jacobi(int64_t n, const int32_t* rowptr, const int32_t* col,
+                     const double* val, int64_t bs, double* binv) {
+  if (bs < 1) return ORC_INVALID_ARG;
+  int64_t nb = (n + bs - 1) / bs;
+  double* B = (double*)malloc((size_t)(bs * bs) * sizeof(double));
+  double* e = (double*)malloc((size_t)bs * sizeof(double));
+  double* y = (double*)malloc((size_t)bs * sizeof(double));
+  int status = ORC_OK;
+  for (int64_t k = 0; k < nb && status == ORC_OK; ++k) {
+    int64_t r0 = k * bs, m = (n - r0) < bs ? (n - r0) : bs;
+    /* the dense block A[I,I], row-major m x m */
+    for (int64_t t = 0; t < m * m; ++t) B[t] = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t q = rowptr[r0 + i]; q < rowptr[r0 + i + 1]; ++q)
+        if (col[q] >= r0 && col[q] < r0 + m) B[i * m + (col[q] - r0)] = val[q];
+    double* slot = binv + k * bs * bs;
+    for (int64_t t = 0; t < bs * bs; ++t) slot[t] = 0.0;
+    for (int64_t j = 0; j < m; ++j) {
+      for (int64_t i = 0; i < m; ++i) e[i] = i == j ? 1.0 : 0.0;
+      if (orc_dense_lu_solve(m, B, e, y) != ORC_OK) {
+        status = ORC_BREAKDOWN;
+        break;
+      }
+      for (int64_t i = 0; i < m; ++i) {
+        if (!isfinite(y[i])) status = ORC_BREAKDOWN;
+        slot[j * bs + i] = y[i];
+      }
+    }
+  }
+  free(B);
+  free(e);
+  free(y);
+  return status;
+}
+
+void orc_prec_apply(int64_t n, int kind, int64_t bs, const double* minv,
+                    const double* r, double* z) {
+  if (kind == 1) {
+    for (int64_t i = 0; i < n; ++i) z[i] = minv[i] * r[i];
+    return;
+  }
+  for (int64_t r0 = 0; r0 < n; r0 += bs) {
+    int64_t m = (n - r0) < bs ? (n - r0) : bs;
+    const double* slot = minv + (r0 / bs) * bs * bs;
+    for (int64_t i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int64_t j = 0; j < m; ++j) s = s + slot[j * bs + i] * r[r0 + j];
+      z[r0 + i] = s;
+    }
+  }
+}
+
+int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col,
+            const double* val, int kind, int64_t bs, const double* minv,
+            const double* b, double* x, const orc_stop* stop, orc_info* info) {
+  csr_t A = {n, rowptr, col, val};
+  memset(info, 0, sizeof(*info));
+  if (kind != 1 && kind != 2) return ORC_INVALID_ARG;
+  double nb = nrm2(n, b);
+  if (!isfinite(nb)) return ORC_NONFINITE;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    return ORC_OK;
+  }
+  double *r = vec(n), *z = vec(n), *p = vec(n), *q = vec(n);
+  residual(&A, b, x, r);
+  orc_prec_apply(n, kind, bs, minv, r, z);
+  double rho = dot(n, r, z);
+  double nr0 = nrm2(n, r);
+  double thr = threshold(stop, nb, nr0);
+  double base = baseline_norm(stop, nb, nr0);
+  int status = ORC_OK;
+  memcpy(p, z, (size_t)n * sizeof(double));
+  int64_t it = 0, repl = 0;
+  int check = nr0 <= thr;
+  for (;;) {
+    if (check) {
+      residual(&A, b, x, r);
+      double nt = nrm2(n, r);
+      info->relres_true = nt / base;
+      if (nt <= thr) break;
+      if (repl >= stop->max_replacements) {
+        status = ORC_NOT_CONVERGED;
+        break;
+      }
+      repl++;
+      orc_prec_apply(n, kind, bs, minv, r, z);
+      rho = dot(n, r, z);
+      memcpy(p, z, (size_t)n * sizeof(double));
+      check = 0;
+    }
+    if (it >= stop->max_iters) {
+      residual(&A, b, x, q);
+      info->relres_true = nrm2(n, q) / base;
+      status = ORC_NOT_CONVERGED;
+      break;
+    }
+    if (!(rho > 0.0)) {  /* (r, M^{-1} r) > 0 for SPD M and r != 0 */
+      status = isfinite(rho) ? ORC_BREAKDOWN : ORC_NONFINITE;
+      break;
+    }
+    matvec(&A, p, q);
+    double pq = dot(n, p, q);
+    if (!isfinite(pq)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (pq <= 0.0) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    double alpha = rho / pq;
+    for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+    orc_prec_apply(n, kind, bs, minv, r, z);
+    double rho_new = dot(n, r, z);
+    double rr = dot(n, r, r);
+    ++it;
+    info->relres_recurrence = sqrt(rr) / base;
+    if (sqrt(rr) <= thr) {
+      check = 1;
+      continue;
+    }
+    double beta = rho_new / rho;
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+    rho = rho_new;
+  }
+  info->iters = it;
+  info->replacements = repl;
+  free(r);
+  free(z);
+  free(p);
+  free(q);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
 /* BiCGSTAB (van der Vorst 1992; Saad 2003, ch. 7), r_hat = r_0             */
 /* ------------------------------------------------------------------------ */
 int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
@@ -792,36 +945,64 @@ static float fdot(int64_t n, const float* a, const float* b) {
   return (float)s;
 }
 
-/* inner FP32 CG from d = 0 on A_low d = f, to ||r|| <= tol * ||f|| */
+/* z = M^{-1} r in float (kind 0: z = r) */
+static void low_prec_apply(int64_t n, int kind, int64_t bs, const float* minv,
+                           const float* r, float* z) {
+  if (kind == 0) {
+    for (int64_t i = 0; i < n; ++i) z[i] = r[i];
+  } else if (kind == 1) {
+    for (int64_t i = 0; i < n; ++i) z[i] = minv[i] * r[i];
+  } else {
+    for (int64_t r0 = 0; r0 < n; r0 += bs) {
+      int64_t m = (n - r0) < bs ? (n - r0) : bs;
+      const float* slot = minv + (r0 / bs) * bs * bs;
+      for (int64_t i = 0; i < m; ++i) {
+        float s = 0.0f;
+        for (int64_t j = 0; j < m; ++j) s = s + slot[j * bs + i] * r[r0 + j];
+        z[r0 + i] = s;
+      }
+    }
+  }
+}
+
+/* inner FP32 (preconditioned) CG from d = 0 on A_low d = f, to
+ * ||r|| <= tol * ||f||; without a preconditioner z = r and this is plain CG */
 static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
-                      int64_t maxit) {
+                      int64_t maxit, int pc_kind, int64_t bs,
+                      const float* minv) {
   int64_t n = L->n;
   float* r = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+  float* z = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   float* p = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   float* q = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   for (int64_t i = 0; i < n; ++i) {
     d[i] = 0.0f;
     r[i] = f[i];
-    p[i] = f[i];
   }
-  float rho = fdot(n, r, r);
-  float thr = tol * sqrtf(rho);
+  low_prec_apply(n, pc_kind, bs, minv, r, z);
+  for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+  float rho = fdot(n, r, z);
+  float rr = fdot(n, r, r);
+  float thr = tol * sqrtf(rr);
   int64_t it = 0;
-  while (sqrtf(rho) > thr && it < maxit) {
+  while (sqrtf(rr) > thr && it < maxit) {
     low_matvec(L, p, q);
     float pq = fdot(n, p, q);
     if (!(pq > 0.0f)) break;
     float alpha = rho / pq;
     for (int64_t i = 0; i < n; ++i) d[i] = d[i] + alpha * p[i];
     for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
-    float rho_new = fdot(n, r, r);
+    low_prec_apply(n, pc_kind, bs, minv, r, z);
+    float rho_new = fdot(n, r, z);
+    rr = fdot(n, r, r);
     ++it;
-    if (sqrtf(rho_new) <= thr) break;
+    if (sqrtf(rr) <= thr) break;
     float beta = rho_new / rho;
-    for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
     rho = rho_new;
   }
   free(r);
+  free(z);
   free(p);
   free(q);
   return it;
@@ -832,6 +1013,18 @@ int orc_ir(int64_t n, const int32_t* rowptr, const int32_t* col,
            const uint16_t* h16, const float* scale, const double* b,
            double* x, double outer_tol, int64_t outer_max, double inner_tol,
            int64_t inner_max, int last_step_variant, orc_ir_info* info) {
+  return orc_ir_pc(n, rowptr, col, val64, low_kind, val32, h16, scale, b, x,
+                   outer_tol, outer_max, inner_tol, inner_max,
+                   last_step_variant, 0, 1, NULL, info);
+}
+
+int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
+              const double* val64, int low_kind, const float* val32,
+              const uint16_t* h16, const float* scale, const double* b,
+              double* x, double outer_tol, int64_t outer_max,
+              double inner_tol, int64_t inner_max, int last_step_variant,
+              int pc_kind, int64_t bs, const float* minv32,
+              orc_ir_info* info) {
   csr_t A = {n, rowptr, col, val64};
   lowmat_t L = {n, rowptr, col, low_kind, val32, h16, scale};
   memset(info, 0, sizeof(*info));
@@ -866,7 +1059,8 @@ int orc_ir(int64_t n, const int32_t* rowptr, const int32_t* col,
       double t2 = 0.1 * outer_tol / relres;
       if (t2 > tol) tol = t2;
     }
-    info->inner_iters_total += low_cg(&L, f, d, (float)tol, inner_max);
+    info->inner_iters_total +=
+        low_cg(&L, f, d, (float)tol, inner_max, pc_kind, bs, minv32);
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + sigma * (double)d[i];
     info->outer_iters++;
   }

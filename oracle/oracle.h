@@ -116,6 +116,28 @@ int orc_gmres(int64_t n, const int32_t* rowptr, const int32_t* col,
               const orc_stop* stop, orc_info* info, double* hist,
               int64_t hist_cap);
 
+/* ---- preconditioners (Saad 2003, ch. 10) -----------------------------
+ * kind 1, Jacobi: M = diag(A), minv holds dinv_i = 1 / a_ii.
+ * kind 2, block Jacobi: M = the diagonal blocks A[I,I] over consecutive row
+ * ranges I = [k bs, min((k+1) bs, n)); minv holds their inverses, block k
+ * column-major in a bs x bs slot (entry (i, j) at k bs^2 + j bs + i, zero
+ * beyond the block's size).  Column j of an inverse solves A[I,I] y = e_j
+ * with orc_dense_lu_solve.  Both return ORC_BREAKDOWN when a diagonal entry
+ * is zero or missing, or a block is singular. */
+int orc_jacobi(int64_t n, const int32_t* rowptr, const int32_t* col,
+               const double* val, double* dinv);
+int orc_block_jacobi(int64_t n, const int32_t* rowptr, const int32_t* col,
+                     const double* val, int64_t bs, double* binv);
+/* z = M^{-1} r */
+void orc_prec_apply(int64_t n, int kind, int64_t bs, const double* minv,
+                    const double* r, double* z);
+/* Preconditioned CG (Saad 2003, Algorithm 9.1): rho = (r, z), z = M^{-1} r,
+ * p = z + beta p; the stopping test is on ||r|| with the true-residual check
+ * and residual replacement of orc_cg (a replacement restarts p = z). */
+int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col,
+            const double* val, int kind, int64_t bs, const double* minv,
+            const double* b, double* x, const orc_stop* stop, orc_info* info);
+
 /* Mixed-precision iterative refinement: FP64 residual and update, inner CG
  * in FP32 on a low-precision copy of A.  low_kind 0: FP32 values (val32);
  * low_kind 1: FP16 values with a per-row power-of-two scale (h16, scale). */
@@ -129,6 +151,15 @@ int orc_ir(int64_t n, const int32_t* rowptr, const int32_t* col,
            const uint16_t* h16, const float* scale, const double* b,
            double* x, double outer_tol, int64_t outer_max, double inner_tol,
            int64_t inner_max, int last_step_variant, orc_ir_info* info);
+/* The same with a preconditioned inner CG (pc_kind 0: none, 1 / 2 as
+ * above), minv32 = the preconditioner rounded to FP32. */
+int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
+              const double* val64, int low_kind, const float* val32,
+              const uint16_t* h16, const float* scale, const double* b,
+              double* x, double outer_tol, int64_t outer_max,
+              double inner_tol, int64_t inner_max, int last_step_variant,
+              int pc_kind, int64_t bs, const float* minv32,
+              orc_ir_info* info);
 
 #ifdef __cplusplus
 }

@@ -212,3 +212,131 @@ def test_ir_random_spd_small(orc):
     for low in ("f32", "f16"):
         r = orc.ir(A, b, low=low, tol=1e-10, last_step_variant=True)
         assert r.status == orc.OK and r.relres_true <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Jacobi / block-Jacobi preconditioned CG (Saad 2003, ch. 9-10)
+# ---------------------------------------------------------------------------
+def _scaled(A, s):
+    return I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, A.val * s)
+
+
+def test_pcg_unit_diagonal_is_cg(orc):
+    # with a unit diagonal the Jacobi preconditioner is the identity (1/1 = 1
+    # exactly), so PCG must reproduce the independently pinned CG bit for bit
+    A = _scaled(I.poisson2d(24), 0.25)
+    b = I.uniform_vector(A.n, 5)
+    st, M = orc.jacobi(A)
+    assert st == orc.OK and np.all(M.minv == 1.0)
+    p = orc.pcg(A, b, M, tol=1e-10)
+    c = orc.cg(A, b, tol=1e-10)
+    assert p.status == c.status == orc.OK and p.iters == c.iters
+    assert np.array_equal(p.x, c.x)
+
+
+def test_pcg_exact_preconditioner_one_step(orc):
+    # one block covering the matrix: M = A, z = A^{-1} r, one step is exact
+    A = I.poisson2d(10)
+    b = I.uniform_vector(A.n, 6)
+    st, M = orc.block_jacobi(A, A.n)
+    assert st == orc.OK
+    r = orc.pcg(A, b, M, tol=1e-10)
+    assert r.status == orc.OK and r.iters == 1 and r.relres_true <= 1e-12
+    # a diagonal matrix with Jacobi: also one step
+    D = I.dense_to_csr(np.diag(np.linspace(1.0, 50.0, 40)))
+    st, MD = orc.jacobi(D)
+    rd = orc.pcg(D, np.ones(40), MD, tol=1e-12)
+    assert rd.status == orc.OK and rd.iters == 1
+
+
+def test_block_jacobi_size_one_is_jacobi(orc):
+    A = I.random_spd(2000, seed=7)
+    b = I.uniform_vector(A.n, 7)
+    s1, J = orc.jacobi(A)
+    s2, B1 = orc.block_jacobi(A, 1)
+    assert s1 == s2 == orc.OK and np.array_equal(J.minv, B1.minv)
+    r = I.uniform_vector(A.n, 8)
+    assert np.array_equal(orc.prec_apply(J, r), orc.prec_apply(B1, r))
+    pj, pb = orc.pcg(A, b, J), orc.pcg(A, b, B1)
+    assert pj.iters == pb.iters and np.array_equal(pj.x, pb.x)
+
+
+@pytest.mark.parametrize("bs", [3, 8, 32])
+def test_block_jacobi_inverse_vs_numpy(orc, bs):
+    # every stored block is the inverse numpy computes for A[I, I]; the apply
+    # is the block-diagonal product (ragged last block included)
+    A = I.random_spd(1000 + bs // 2, seed=9)
+    n = A.n
+    Dn = np.zeros((n, n))
+    for i in range(n):
+        Dn[i, A.col[A.rowptr[i]:A.rowptr[i + 1]]] = A.val[A.rowptr[i]:A.rowptr[i + 1]]
+    st, M = orc.block_jacobi(A, bs)
+    assert st == orc.OK
+    r = I.uniform_vector(n, 10)
+    z = orc.prec_apply(M, r)
+    for k in range(-(-n // bs)):
+        r0, m = k * bs, min(bs, n - k * bs)
+        inv = np.linalg.inv(Dn[r0:r0 + m, r0:r0 + m])
+        slot = M.minv[k * bs * bs:(k + 1) * bs * bs].reshape(bs, bs).T  # column-major
+        assert np.allclose(slot[:m, :m], inv, rtol=1e-12, atol=1e-14 * np.abs(inv).max())
+        assert not slot[m:, :].any() and not slot[:, m:].any()
+        zr = inv @ r[r0:r0 + m]
+        assert np.abs(z[r0:r0 + m] - zr).max() <= 1e-12 * (np.abs(inv) @ np.abs(r[r0:r0 + m])).max()
+
+
+def test_jacobi_pcg_error_bound(orc):
+    # d_i = 1.1 sum_j |s_ij| puts spec(D^-1 A) in [1 - 1/1.1, 1 + 1/1.1]
+    # (Gershgorin), kappa <= 21; PCG's A-norm error obeys
+    # ||e_k||_A <= 2 ((sqrt(k)-1)/(sqrt(k)+1))^k ||e_0||_A at every k
+    A = I.random_spd(1500, seed=11)
+    n = A.n
+    Dn = np.zeros((n, n))
+    for i in range(n):
+        Dn[i, A.col[A.rowptr[i]:A.rowptr[i + 1]]] = A.val[A.rowptr[i]:A.rowptr[i + 1]]
+    b = I.uniform_vector(n, 12)
+    xs = np.linalg.solve(Dn, b)
+    anorm = lambda e: np.sqrt(e @ Dn @ e)
+    st, M = orc.jacobi(A)
+    kap = (1 + 1 / 1.1) / (1 - 1 / 1.1)
+    rho = (np.sqrt(kap) - 1) / (np.sqrt(kap) + 1)
+    e0 = anorm(xs)
+    full = orc.pcg(A, b, M, tol=1e-10)
+    assert full.status == orc.OK and full.relres_true <= 1e-10
+    for k in (1, 3, 8, 15, full.iters):
+        r = orc.pcg(A, b, M, tol=0.0, maxit=k)
+        assert anorm(r.x - xs) <= 2 * rho ** k * e0 * (1 + 1e-6) + 1e-12 * e0, k
+    plain = orc.cg(A, b, tol=1e-10)
+    assert full.iters < plain.iters
+
+
+def test_preconditioner_failures(orc):
+    A = I.poisson2d(6)
+    bad = I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, A.val.copy())
+    k = [q for q in range(bad.rowptr[7], bad.rowptr[8]) if bad.col[q] == 7][0]
+    bad.val[k] = 0.0
+    assert orc.jacobi(bad)[0] == orc.BREAKDOWN
+    # a singular 2x2 diagonal block [[1, 1], [1, 1]]
+    S = I.dense_to_csr(np.array([[1.0, 1.0, 0, 0], [1.0, 1.0, 0, 0], [0, 0, 2.0, 0],
+                                 [0, 0, 0, 3.0]]))
+    assert orc.block_jacobi(S, 2)[0] == orc.BREAKDOWN
+    assert orc.block_jacobi(S, 1)[0] == orc.OK
+    # an indefinite preconditioner: (r, M^-1 r) < 0 stops PCG with a breakdown
+    neg = I.dense_to_csr(np.diag([1.0, -1.0, 2.0]))
+    st, M = orc.jacobi(neg)
+    r = orc.pcg(neg, np.array([0.0, 1.0, 0.0]), M)
+    assert r.status == orc.BREAKDOWN
+
+
+def test_ir_with_jacobi_inner(orc):
+    A = I.random_spd(3000, seed=13)
+    b = I.uniform_vector(A.n, 14)
+    st, M = orc.jacobi(A)
+    plain = orc.ir(A, b, low="f32", tol=1e-10)
+    pre = orc.ir(A, b, low="f32", tol=1e-10, precond=M)
+    assert plain.status == pre.status == orc.OK
+    assert pre.relres_true <= 1e-10
+    assert pre.inner_iters_total * 5 < plain.inner_iters_total
+    # block Jacobi on FP16 storage too
+    st, MB = orc.block_jacobi(A, 16)
+    r16 = orc.ir(A, b, low="f16", tol=1e-10, precond=MB)
+    assert r16.status == orc.OK and r16.relres_true <= 1e-10
