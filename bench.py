@@ -367,8 +367,43 @@ def main():
             torch.cuda.synchronize()
             t_plain = time.perf_counter() - t0
             x_plain = xq.clone()
+            nxs = float(torch.linalg.norm(xstar))
             e = {"plain_f64_cg": {"iters": r.iters, "status": r.status, "time_s": round(t_plain, 4),
-                                  "relres_true": r.relres_true}}
+                                  "relres_true": r.relres_true,
+                                  "err_vs_xstar": float(torch.linalg.norm(xq - xstar)) / nxs}}
+            # preconditioned CG (Jacobi; block Jacobi with 8-row blocks)
+            pcs = {"jacobi": mxs.Precond(ctx, Qm, "jacobi"),
+                   "block8": mxs.Precond(ctx, Qm, "block_jacobi", 8)}
+            for pname, P in pcs.items():
+                xq.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rp_ = mxs.solve(ctx, "cg", Qm, bq, xq, tol=1e-10, raise_on_error=False,
+                                precond=P)
+                torch.cuda.synchronize()
+                t_p = time.perf_counter() - t0
+                e[f"pcg_{pname}_f64"] = {
+                    "iters": rp_.iters, "status": rp_.status, "time_s": round(t_p, 4),
+                    "relres_true": rp_.relres_true, "speedup_vs_plain": round(t_plain / t_p, 3),
+                    "err_vs_xstar": float(torch.linalg.norm(xq - xstar)) / nxs}
+            for low in ("f32", "f16"):
+                L = Qm.convert("csr", low)
+                xq.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ri = mxs.solve_ir(ctx, Qm, L, bq, xq, tol=1e-10, raise_on_error=False,
+                                  precond=pcs["jacobi"])
+                torch.cuda.synchronize()
+                t_ir = time.perf_counter() - t0
+                e[f"ir_{low}_jacobi_inner"] = {
+                    "outer": ri.outer_iters, "inner_total": ri.inner_iters_total,
+                    "status": ri.status, "relres_true": ri.relres_true,
+                    "time_s": round(t_ir, 4), "speedup_vs_plain": round(t_plain / t_ir, 3),
+                    "speedup_vs_pcg_jacobi": round(e["pcg_jacobi_f64"]["time_s"] / t_ir, 3),
+                    "err_vs_xstar": float(torch.linalg.norm(xq - xstar)) / nxs}
+                L.close()
+            for P in pcs.values():
+                P.close()
             for low in ("f32", "f16"):
                 for variant in (False, True):
                     L = Qm.convert("csr", low)
@@ -384,7 +419,8 @@ def main():
                         "outer": ri.outer_iters, "inner_total": ri.inner_iters_total,
                         "status": ri.status, "relres_true": ri.relres_true,
                         "time_s": round(t_ir, 4), "speedup_vs_plain": round(t_plain / t_ir, 3),
-                        "err_vs_fp64_cg": err}
+                        "err_vs_fp64_cg": err,
+                        "err_vs_xstar": float(torch.linalg.norm(xq - xstar)) / nxs}
                     L.close()
             irr[name] = e
             log(name, json.dumps(e))

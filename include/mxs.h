@@ -205,8 +205,36 @@ typedef struct {
   int32_t max_replacements; /* true-residual replacements before NOT_CONVERGED (default 3 if < 0) */
 } mxs_stop;
 
+/* Preconditioners (the stationary ones of Saad 2003, ch. 10; the paper
+ * lists Jacobi-type preconditioning among the library's functionality):
+ *  MXS_PRECOND_JACOBI: M = diag(A), stored as 1/a_ii.
+ *  MXS_PRECOND_BLOCK_JACOBI: M = the dense diagonal blocks A[I,I] over
+ *    consecutive ranges of block_size rows (1..32, the last range ragged),
+ *    inverted at set-up by Gauss-Jordan elimination with partial pivoting.
+ * Both keep FP64 values and a copy rounded to FP32 (used by the FP32 inner
+ * solve of mxs_solve_ir). */
+typedef struct mxs_precond mxs_precond;
+#define MXS_PRECOND_JACOBI 1
+#define MXS_PRECOND_BLOCK_JACOBI 2
+
+/* Builds M from an F64 CSR matrix (else MXS_UNSUPPORTED).  MXS_BREAKDOWN if
+ * a diagonal entry is zero, missing or non-finite (Jacobi) or a block is
+ * singular (block Jacobi); MXS_INVALID_ARG for an unknown kind or a block
+ * size outside [1, 32].  M owns its device memory and is independent of A.
+ * Synchronises the ctx stream. */
+mxs_status mxs_precond_create(mxs_ctx* ctx, const mxs_matrix* A, int32_t kind,
+                              int32_t block_size, mxs_precond** out);
+mxs_status mxs_precond_destroy(mxs_precond* M);
+/* Copies the FP64 values to host memory: n values 1/a_ii (Jacobi), or
+ * ceil(n/bs) column-major bs x bs inverses, entry (i, j) of block k at
+ * k*bs*bs + j*bs + i, zero beyond a ragged block (block Jacobi).  `bytes`
+ * must hold them all.  Synchronises the ctx stream. */
+mxs_status mxs_precond_export(mxs_ctx* ctx, const mxs_precond* M, double* host, size_t bytes);
+
 typedef struct {
-  int32_t restart; /* GMRES restart length m (0 = 30) */
+  int32_t restart;              /* GMRES restart length m (0 = 30) */
+  int32_t reserved;
+  const mxs_precond* precond;   /* CG only (preconditioned CG); NULL = none */
 } mxs_solver_opts;
 
 typedef struct {
@@ -228,7 +256,11 @@ typedef struct {
  * residual meets the tolerance and then checks the true residual b - A x in
  * FP64; if that fails it replaces r by it (CG/BiCGSTAB restart from the
  * current x) up to max_replacements times.  b == 0 returns x = 0 after 0
- * iterations.  Returns MXS_OK, MXS_NOT_CONVERGED, MXS_BREAKDOWN or
+ * iterations.  With opts->precond, CG is the preconditioned CG of Saad
+ * 2003, Algorithm 9.1 (rho = r.z, z = M^{-1} r, p = z + beta p; the stopping
+ * test stays on ||r||; a replacement restarts p = z; (r, z) <= 0 is a
+ * breakdown); BiCGSTAB and GMRES return MXS_UNSUPPORTED with a
+ * preconditioner.  Returns MXS_OK, MXS_NOT_CONVERGED, MXS_BREAKDOWN or
  * MXS_NONFINITE; `info` (nullable) is filled in all four cases.
  * Synchronises the ctx stream. */
 mxs_status mxs_solve(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, const double* b,
@@ -249,11 +281,12 @@ typedef struct {
  * x += ||r|| d in FP64.  A64: F64 CSR; A_low: F32 or F16_ROWSCALED CSR with
  * the same pattern.  last_step_variant != 0 loosens the inner tolerance to
  * max(inner_rel_tol, 0.1*tol/relres) once relres*inner_rel_tol <= tol.
- * Synchronises the ctx stream. */
+ * inner_precond (nullable, built from A64) turns the inner solve into
+ * preconditioned CG with the FP32 copy of M.  Synchronises the ctx stream. */
 mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A_low,
                         const double* b, double* x, const mxs_stop* outer,
                         double inner_rel_tol, int64_t inner_max, int32_t last_step_variant,
-                        mxs_ir_info* info);
+                        const mxs_precond* inner_precond, mxs_ir_info* info);
 
 /* ---------------------------------------------------------------------- */
 /* batched CG and continuous batching                                      */

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmxs.so")
-SOURCES = ["runtime.hip", "matrix.hip", "spmv.hip", "solvers.hip", "batch.hip"]
+SOURCES = ["runtime.hip", "matrix.hip", "spmv.hip", "solvers.hip", "precond.hip", "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -4,10 +4,9 @@
 //  * wave64 everywhere; reductions inside a wave use xor-butterflies, whose
 //    result is bitwise identical in every lane (each step adds the same two
 //    operands in both partner lanes), so every reduction is deterministic.
-//  * cross-block reductions never use floating-point atomics: blocks write
-//    partial sums to fixed slots and the last block to finish (ticket
-//    counter) adds them in slot order.  The ticket is reset by that block,
-//    so no memset is needed between launches.
+//  * cross-block reductions never use floating-point atomics or
+//    device-scope fences: blocks write partial sums to fixed slots and the
+//    next kernel (or a one-block finishing kernel) adds them in slot order.
 //  * work-groups are dispatched round-robin over the 8 XCDs; kernels that
 //    stream rows remap blockIdx so that each XCD (and its private L2) works
 //    on one contiguous eighth of the rows and of the x-vector window they
@@ -125,6 +124,20 @@ struct mxs_matrix {
   int64_t bytes = 0;
   // host copy of the row pointers (analysis data kept for conversions)
   std::vector<int32_t> h_rowptr;
+};
+
+// Jacobi: 1/a_ii per row; block Jacobi: inverted diagonal blocks,
+// column-major bs x bs slots.  FP64 and the same values rounded to FP32.
+struct mxs_precond {
+  int device = 0;
+  mxs::Allocator alloc;
+  int32_t kind = 0;
+  int64_t n = 0;
+  int32_t bs = 1;
+  int64_t nb = 0;
+  int64_t count = 0;  // stored values
+  double* m64 = nullptr;
+  float* m32 = nullptr;
 };
 
 namespace mxs {

@@ -593,6 +593,139 @@ __global__ __launch_bounds__(RB) void k_ir_update(int64_t n, double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Preconditioned CG (Saad 2003, Algorithm 9.1), PC = 1 Jacobi (z = dinv r,
+// never stored: formed where it is used), PC = 2 block Jacobi (z stored).
+// Iteration k (par = k & 1), rho[par] = (r, z) of the previous step:
+//   q = A p;  k_cg_pq: partials of p.q;
+//   k_pcg_update: alpha = rho[par] / (p.q), x += alpha p, r -= alpha q,
+//                 partials of (r.z, r.r) (Jacobi) or r.r (block);
+//   [block: k_bj_apply: z = M^{-1} r, partials of r.z]
+//   k_pcg_direction: stopping test on r.r, rho[1-par] = r.z,
+//                    p = z + (rho[1-par] / rho[par]) p.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(RB) void k_jac_apply(int64_t n, const T* __restrict__ dinv,
+                                                  const T* __restrict__ r, T* __restrict__ z) {
+  GRID_STRIDE(i, n) z[i] = dinv[i] * r[i];
+}
+
+// z = M^{-1} r for block Jacobi: a wave holds G = 64 / bs blocks, lane l
+// row l % bs of block l / bs; the block's r values travel by shuffles.
+// Grid-stride over waves (fixed order); partials of r.z when `part`.
+template <typename T>
+__global__ __launch_bounds__(RB) void k_bj_apply(int64_t n, int bs, const T* __restrict__ minv,
+                                                 const T* __restrict__ r, T* __restrict__ z,
+                                                 double* __restrict__ part, const KState* st) {
+  if (st && st->done) return;
+  const int lane = threadIdx.x & 63;
+  const int G = 64 / bs;
+  const int gi = lane / bs, i = lane - gi * bs;
+  const int64_t nb = (n + bs - 1) / bs;
+  const int64_t nwaves = (int64_t)gridDim.x * (RB / 64);
+  double acc[1] = {0.0};
+  for (int64_t wb = (int64_t)blockIdx.x * (RB / 64) + threadIdx.x / 64; wb * G < nb;
+       wb += nwaves) {
+    const int64_t blk = wb * G + gi;
+    const bool on = gi < G && blk < nb;
+    const int64_t r0 = blk * bs;
+    const int m = on ? (int)((n - r0) < bs ? (n - r0) : bs) : 0;
+    const bool row = i < m;
+    const T ri = row ? r[r0 + i] : T(0);
+    const T* __restrict__ M = minv + (on ? blk : 0) * bs * bs;
+    T sum = 0;
+    for (int j = 0; j < bs; ++j) {
+      const T rj = __shfl(ri, gi * bs + j, 64);
+      if (row && j < m) sum += M[j * bs + i] * rj;
+    }
+    if (row) {
+      z[r0 + i] = sum;
+      acc[0] += (double)ri * (double)sum;
+    }
+  }
+  if (part) block_partials<1>(acc, part);
+}
+
+template <typename T, int PC>
+__global__ __launch_bounds__(RB) void k_pcg_update(int64_t n, T* __restrict__ x,
+                                                   const T* __restrict__ p, T* __restrict__ r,
+                                                   const T* __restrict__ q,
+                                                   const T* __restrict__ dinv,
+                                                   const double* __restrict__ pa, int g,
+                                                   double* __restrict__ pb, KState* st, int par) {
+  if (st->done) return;
+  double pq[1];
+  finish<1>(pa, g, pq);
+  if (!isfinite(pq[0]) || pq[0] <= 0.0) {
+    if (lead()) st->done = isfinite(pq[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+    return;
+  }
+  const double alpha = st->rho[par] / pq[0];
+  if (lead()) st->alpha = alpha;
+  const T a = (T)alpha;
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    if (PC == 1) acc[1] += (double)ri * (double)(dinv[i] * ri);
+    acc[0] += (double)ri * (double)ri;
+  }
+  if (PC == 1) {
+    block_partials<2>(acc, pb);
+  } else {
+    const double rr[1] = {acc[0]};
+    block_partials<1>(rr, pb);
+  }
+}
+
+template <typename T, int PC>
+__global__ __launch_bounds__(RB) void k_pcg_direction(int64_t n, const T* __restrict__ r,
+                                                      T* __restrict__ p,
+                                                      const T* __restrict__ z,
+                                                      const T* __restrict__ dinv,
+                                                      const double* __restrict__ pb,
+                                                      const double* __restrict__ pc, int g,
+                                                      KState* st, int par, int64_t k) {
+  if (st->done) return;
+  double rr, rz;
+  if (PC == 1) {
+    double t[2];
+    finish<2>(pb, g, t);
+    rr = t[0];
+    rz = t[1];
+  } else {
+    double t1[1], t2[1];
+    finish<1>(pb, g, t1);
+    finish<1>(pc, g, t2);
+    rr = t1[0];
+    rz = t2[0];
+  }
+  const bool bad = !isfinite(rr) || !isfinite(rz);
+  const bool conv = !bad && sqrt(rr) <= st->thr;
+  const bool maxit = k + 1 >= st->max_iters;
+  const bool brk = !(rz > 0.0);
+  if (lead()) {
+    st->iters = k + 1;
+    st->res2 = rr;
+    st->rho[1 - par] = rz;
+    if (bad)
+      st->done = ST_NONFINITE;
+    else if (conv)
+      st->done = ST_CONVERGED;
+    else if (maxit)
+      st->done = ST_MAXIT;
+    else if (brk)
+      st->done = ST_BREAKDOWN;
+  }
+  if (bad || conv || maxit || brk) return;
+  const T beta = (T)(rz / st->rho[par]);
+  GRID_STRIDE(i, n) {
+    const T zi = PC == 1 ? dinv[i] * r[i] : z[i];
+    p[i] = zi + beta * p[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 struct Work {
@@ -821,6 +954,135 @@ mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* 
   }
 }
 
+// z = M^{-1} r (enqueued)
+template <typename T>
+void apply_precond(mxs_ctx* ctx, const mxs_precond* M, const T* mv, int64_t n, const T* r,
+                   T* z) {
+  const int g = red_grid(n);
+  if (M->kind == MXS_PRECOND_JACOBI)
+    k_jac_apply<T><<<g, RB, 0, ctx->stream>>>(n, mv, r, z);
+  else
+    k_bj_apply<T><<<g, RB, 0, ctx->stream>>>(n, M->bs, mv, r, z, nullptr, nullptr);
+}
+
+// Preconditioned CG iterations from the state on the device until the
+// device status is set; mv = M's values in the vector type.
+template <typename T, int PC>
+mxs_status pcg_loop(mxs_ctx* ctx, const mxs_matrix* A, const mxs_precond* M, const T* mv,
+                    Work& w, T* x, T* r, T* p, T* q, T* z, int check_every) {
+  const int64_t n = A->n;
+  const int g = red_grid(n);
+  const T one = 1, zero = 0;
+  int64_t k = w.hst->iters;
+  for (;;) {
+    const int64_t before = k;
+    for (int it = 0; it < check_every; ++it, ++k) {
+      const int par = (int)(k & 1);
+      mxs_status s = launch_spmv(ctx, A, &one, p, &zero, q, &w.st->done);
+      if (s) return s;
+      k_cg_pq<T><<<g, RB, 0, ctx->stream>>>(n, p, q, w.pa, w.st);
+      k_pcg_update<T, PC><<<g, RB, 0, ctx->stream>>>(n, x, p, r, q, mv, w.pa, g, w.pb, w.st,
+                                                     par);
+      if (PC == 2)
+        k_bj_apply<T><<<g, RB, 0, ctx->stream>>>(n, M->bs, mv, r, z, w.pc, w.st);
+      k_pcg_direction<T, PC><<<g, RB, 0, ctx->stream>>>(n, r, p, z, mv, w.pb, w.pc, g, w.st,
+                                                        par, k);
+    }
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    mxs_status s = pull_state(ctx, w);
+    if (s) return s;
+    if (w.hst->done) return MXS_OK;
+    if (w.hst->iters <= before)
+      return fail(ctx, MXS_HIP, "PCG made no progress (device state not updated)");
+    k = w.hst->iters;
+  }
+}
+
+template <typename T>
+mxs_status pcg_run(mxs_ctx* ctx, const mxs_matrix* A, const mxs_precond* M, const T* mv,
+                   Work& w, T* x, T* r, T* p, T* q, T* z, int check_every) {
+  return M->kind == MXS_PRECOND_JACOBI
+             ? pcg_loop<T, 1>(ctx, A, M, mv, w, x, r, p, q, z, check_every)
+             : pcg_loop<T, 2>(ctx, A, M, mv, w, x, r, p, q, z, check_every);
+}
+
+mxs_status solve_pcg(mxs_ctx* ctx, const mxs_matrix* A, const mxs_precond* M, const double* b,
+                     double* x, const Stop& stop, mxs_solve_info* info) {
+  const int64_t n = A->n;
+  const size_t ld = align_up((size_t)n, 64);
+  Work w;
+  mxs_status s = get_work(ctx, 4 * ld * sizeof(double), &w);
+  if (s) return s;
+  double* r = (double*)w.vec;
+  double* p = r + ld;
+  double* q = p + ld;
+  double* z = q + ld;
+  double nb2, nr2, rz;
+  if ((s = residual(ctx, A, b, x, r))) return s;
+  if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
+  const double nb = sqrt(nb2), nr0 = sqrt(nr2);
+  if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
+  if (nb == 0.0) return zero_solution(ctx, x, n, info);
+  if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
+  const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
+  const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
+  KState& h = *w.hst;
+  // z = M^{-1} r, rho = r.z, p = z
+  auto restart = [&](double rr) -> mxs_status {
+    apply_precond<double>(ctx, M, M->m64, n, r, z);
+    mxs_status e = dots<double>(ctx, w, n, r, z, (const double*)nullptr, (const double*)nullptr,
+                                &rz, nullptr);
+    if (e) return e;
+    h.rho[h.iters & 1] = rz;
+    h.res2 = rr;
+    h.done = sqrt(rr) <= thr ? ST_CONVERGED
+             : !std::isfinite(rz) ? ST_NONFINITE
+             : rz > 0.0 ? RUN : ST_BREAKDOWN;
+    if ((e = push_state(ctx, w))) return e;
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    return MXS_OK;
+  };
+  std::memset(&h, 0, sizeof(KState));
+  h.thr = thr;
+  h.max_iters = stop.max_iters;
+  if ((s = restart(nr2))) return s;
+  int64_t repl = 0;
+  double relres_true = nr0 / base;
+  for (;;) {
+    if (h.done == RUN) {
+      if ((s = pcg_run<double>(ctx, A, M, M->m64, w, x, r, p, q, z, stop.check_every)))
+        return s;
+    }
+    if (h.done == ST_BREAKDOWN || h.done == ST_NONFINITE) {
+      s = map_done(h.done);
+      fill_info(info, h, base, relres_true, repl, 0, s);
+      return fail(ctx, s, h.done == ST_BREAKDOWN
+                              ? "PCG breakdown: p.Ap <= 0 or r.z <= 0 (A or M not SPD)"
+                              : "non-finite value in PCG");
+    }
+    double rt2;
+    if ((s = residual(ctx, A, b, x, r))) return s;
+    if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr,
+                          &rt2, nullptr)))
+      return s;
+    relres_true = sqrt(rt2) / base;
+    const int32_t why = h.done;
+    if (why == ST_CONVERGED && sqrt(rt2) <= thr) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_OK);
+      return MXS_OK;
+    }
+    if (why == ST_MAXIT || repl >= stop.max_repl || h.iters >= stop.max_iters) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_NOT_CONVERGED);
+      return fail(ctx, MXS_NOT_CONVERGED, "PCG stopped after %lld iterations, relres %.3e",
+                  (long long)h.iters, relres_true);
+    }
+    // residual replacement: r = b - A x (already in r), restart p = z
+    repl++;
+    if ((s = restart(rt2))) return s;
+  }
+}
+
 mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
                           const Stop& stop, mxs_solve_info* info) {
   const int64_t n = A->n;
@@ -1009,8 +1271,15 @@ mxs_status solve_gmres(mxs_ctx* ctx, const mxs_matrix* A, const double* b, doubl
 mxs_status solve_dispatch(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, const double* b,
                           double* x, const mxs_stop* stop, const mxs_solver_opts* opts,
                           mxs_solve_info* info) {
+  if (opts && opts->precond && kind != MXS_CG)
+    return fail(ctx, MXS_UNSUPPORTED, "preconditioning is implemented for CG only");
   switch (kind) {
     case MXS_CG:
+      if (opts && opts->precond) {
+        const mxs_precond* M = opts->precond;
+        if (M->n != A->n) return fail(ctx, MXS_INVALID_ARG, "preconditioner size differs");
+        return solve_pcg(ctx, A, M, b, x, read_stop(stop, 20000), info);
+      }
       return solve_cg(ctx, A, b, x, read_stop(stop, 20000), info);
     case MXS_BICGSTAB:
       return solve_bicgstab(ctx, A, b, x, read_stop(stop, 10000), info);
@@ -1023,17 +1292,19 @@ mxs_status solve_dispatch(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, co
 
 mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* Al,
                          const double* b, double* x, const mxs_stop* outer, double inner_tol,
-                         int64_t inner_max, int last_step_variant, mxs_ir_info* info) {
+                         int64_t inner_max, int last_step_variant, const mxs_precond* M,
+                         mxs_ir_info* info) {
   const int64_t n = A64->n;
   const size_t ld = align_up((size_t)n, 64);
   Work w;
-  mxs_status s = get_work(ctx, ld * sizeof(double) + 4 * ld * sizeof(float), &w);
+  mxs_status s = get_work(ctx, ld * sizeof(double) + 5 * ld * sizeof(float), &w);
   if (s) return s;
   double* r = (double*)w.vec;
   float* d = (float*)(r + ld);
   float* rf = d + ld;
   float* pf = rf + ld;
   float* qf = pf + ld;
+  float* zf = qf + ld;
   const Stop st = read_stop(outer, 50);
   const int64_t outer_max = st.max_iters;
   const double tol = st.rel_tol;
@@ -1073,19 +1344,33 @@ mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* 
     // inner FP32 CG from d = 0 on A_low d = f, f = r / ||r||
     k_ir_scale<<<g, RB, 0, ctx->stream>>>(n, r, nr, rf);
     MXS_HIP_TRY(ctx, hipMemsetAsync(d, 0, n * sizeof(float), ctx->stream));
-    MXS_HIP_TRY(ctx, hipMemcpyAsync(pf, rf, n * sizeof(float), hipMemcpyDeviceToDevice,
-                                    ctx->stream));
-    double f2;
-    if ((s = dots<float>(ctx, w, n, rf, rf, nullptr, nullptr, &f2, nullptr))) return s;
+    double f2, rz;
+    if (M) {
+      // preconditioned inner solve: z = M^{-1} f, rho = f.z, p = z
+      apply_precond<float>(ctx, M, M->m32, n, rf, zf);
+      if ((s = dots<float>(ctx, w, n, rf, rf, rf, zf, &f2, &rz))) return s;
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(pf, zf, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                      ctx->stream));
+    } else {
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(pf, rf, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                      ctx->stream));
+      if ((s = dots<float>(ctx, w, n, rf, rf, nullptr, nullptr, &f2, nullptr))) return s;
+      rz = f2;
+    }
     std::memset(&h, 0, sizeof(KState));
-    h.rho[0] = f2;
+    h.rho[0] = rz;
     h.res2 = f2;
     h.thr = itol * sqrt(f2);
     h.max_iters = inner_max;
-    h.done = f2 == 0.0 ? ST_CONVERGED : RUN;
+    h.done = f2 == 0.0 ? ST_CONVERGED : rz > 0.0 ? RUN : ST_BREAKDOWN;
     if ((s = push_state(ctx, w))) return s;
-    if (h.done == RUN)
-      if ((s = cg_loop<float>(ctx, Al, w, d, rf, pf, qf, st.check_every))) return s;
+    if (h.done == RUN) {
+      if (M)
+        s = pcg_run<float>(ctx, Al, M, M->m32, w, d, rf, pf, qf, zf, st.check_every);
+      else
+        s = cg_loop<float>(ctx, Al, w, d, rf, pf, qf, st.check_every);
+      if (s) return s;
+    }
     out.inner_iters_total += h.iters;
     if (h.done == ST_NONFINITE) {
       result = fail(ctx, MXS_NONFINITE, "non-finite value in the inner solve");
@@ -1125,7 +1410,7 @@ mxs_status mxs_solve(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, const d
 mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A_low,
                         const double* b, double* x, const mxs_stop* outer,
                         double inner_rel_tol, int64_t inner_max, int32_t last_step_variant,
-                        mxs_ir_info* info) {
+                        const mxs_precond* inner_precond, mxs_ir_info* info) {
   if (!ctx || !A64 || !A_low) return MXS_INVALID_ARG;
   if (A64->dt != MXS_F64 || A_low->dt == MXS_F64)
     return fail(ctx, MXS_UNSUPPORTED, "need an F64 matrix and an F32/F16 copy");
@@ -1137,8 +1422,10 @@ mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A
   if (!(inner_rel_tol > 0.0 && inner_rel_tol < 1.0))
     return fail(ctx, MXS_INVALID_ARG, "inner tolerance must be in (0, 1)");
   MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (inner_precond && inner_precond->n != A64->n)
+    return fail(ctx, MXS_INVALID_ARG, "preconditioner size differs");
   return solve_ir_impl(ctx, A64, A_low, b, x, outer, inner_rel_tol, inner_max,
-                       last_step_variant, info);
+                       last_step_variant, inner_precond, info);
 }
 
 }  // extern "C"

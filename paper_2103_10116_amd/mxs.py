@@ -70,7 +70,7 @@ class Stop(C.Structure):
 
 
 class SolverOpts(C.Structure):
-    _fields_ = [("restart", C.c_int32)]
+    _fields_ = [("restart", C.c_int32), ("reserved", C.c_int32), ("precond", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -118,8 +118,11 @@ _SIGS = {
     "mxs_spmv": (_S, [_P, _P, _P, _P, _P, _P]),
     "mxs_solve": (_S, [_P, C.c_int, _P, _P, _P, C.POINTER(Stop), C.POINTER(SolverOpts),
                        C.POINTER(SolveInfo)]),
-    "mxs_solve_ir": (_S, [_P, _P, _P, _P, _P, C.POINTER(Stop), C.c_double, _I64, _S,
+    "mxs_solve_ir": (_S, [_P, _P, _P, _P, _P, C.POINTER(Stop), C.c_double, _I64, _S, _P,
                           C.POINTER(IRInfo)]),
+    "mxs_precond_create": (_S, [_P, _P, _S, _S, C.POINTER(_P)]),
+    "mxs_precond_destroy": (_S, [_P]),
+    "mxs_precond_export": (_S, [_P, _P, _P, C.c_size_t]),
     "mxs_batch_create": (_S, [_P, C.POINTER(BatchOpts), C.POINTER(_P)]),
     "mxs_batch_destroy": (_S, [_P]),
     "mxs_batch_submit": (_S, [_P, _I64, _I64, _P, _P, _P, _P, C.c_double, _I64,
@@ -301,6 +304,43 @@ class Matrix:
             pass
 
 
+PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 1, 2
+PRECONDS = {"jacobi": PRECOND_JACOBI, "block_jacobi": PRECOND_BLOCK_JACOBI}
+
+
+class Precond:
+    """mxs_precond_create: Jacobi or block-Jacobi preconditioner of an F64
+    CSR matrix (device-resident, FP64 and FP32 copies)."""
+
+    def __init__(self, ctx: Context, A: "Matrix", kind="jacobi", block_size=1):
+        h = C.c_void_p()
+        _check(_lib.mxs_precond_create(ctx.handle, A.handle, PRECONDS.get(kind, kind),
+                                       int(block_size), C.byref(h)), ctx)
+        self.ctx = ctx
+        self.handle = h
+        self.kind = PRECONDS.get(kind, kind)
+        self.n = A.n
+        self.bs = int(block_size) if self.kind == PRECOND_BLOCK_JACOBI else 1
+
+    def export(self) -> np.ndarray:
+        cnt = self.n if self.kind == PRECOND_JACOBI else -(-self.n // self.bs) * self.bs ** 2
+        out = np.empty(cnt, np.float64)
+        _check(_lib.mxs_precond_export(self.ctx.handle, self.handle,
+                                       out.ctypes.data_as(C.c_void_p), out.nbytes), self.ctx)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mxs_precond_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ---------------------------------------------------------------------------
 # operations
 # ---------------------------------------------------------------------------
@@ -339,12 +379,14 @@ class Result:
 
 
 def solve(ctx: Context, kind, A: Matrix, b, x, tol=1e-10, max_iters=0, abs_tol=0.0,
-          baseline=0, check_every=0, max_replacements=-1, restart=30, raise_on_error=True):
-    """mxs_solve: A x = b with x holding x0 on entry (FP64 device vectors)."""
+          baseline=0, check_every=0, max_replacements=-1, restart=30, raise_on_error=True,
+          precond: Precond | None = None):
+    """mxs_solve: A x = b with x holding x0 on entry (FP64 device vectors);
+    `precond` makes CG the preconditioned CG."""
     import torch
     st = Stop(int(max_iters), float(tol), float(abs_tol), int(baseline), int(check_every),
               int(max_replacements))
-    opts = SolverOpts(int(restart))
+    opts = SolverOpts(int(restart), 0, precond.handle if precond is not None else None)
     info = SolveInfo()
     s = _lib.mxs_solve(ctx.handle, SOLVERS.get(kind, kind), A.handle,
                        _vec(b, A.n, torch.float64), _vec(x, A.n, torch.float64), C.byref(st),
@@ -365,14 +407,16 @@ class IRResult:
 
 def solve_ir(ctx: Context, A64: Matrix, Alow: Matrix, b, x, tol=1e-10, outer_max=50,
              inner_tol=1e-4, inner_max=20000, last_step_variant=False, check_every=0,
-             raise_on_error=True):
-    """mxs_solve_ir: FP64 refinement around an FP32 CG on the low-precision copy."""
+             raise_on_error=True, precond: Precond | None = None):
+    """mxs_solve_ir: FP64 refinement around an FP32 CG on the low-precision
+    copy (preconditioned with the FP32 copy of `precond` when given)."""
     import torch
     st = Stop(int(outer_max), float(tol), 0.0, 0, int(check_every), -1)
     info = IRInfo()
     s = _lib.mxs_solve_ir(ctx.handle, A64.handle, Alow.handle, _vec(b, A64.n, torch.float64),
                           _vec(x, A64.n, torch.float64), C.byref(st), float(inner_tol),
-                          int(inner_max), 1 if last_step_variant else 0, C.byref(info))
+                          int(inner_max), 1 if last_step_variant else 0,
+                          precond.handle if precond is not None else None, C.byref(info))
     if raise_on_error and s != OK:
         _check(s, ctx)
     return IRResult(s, info.outer_iters, info.inner_iters_total, info.relres_true)

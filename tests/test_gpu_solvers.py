@@ -233,3 +233,150 @@ def test_full_size_krylov(env, orc):
     _assert_converged(orc, Cd, b, x, r, 1e-10)
     r, x = _solve(env, Cd, b, "gmres", restart=30)
     _assert_converged(orc, Cd, b, x, r, 1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Jacobi / block-Jacobi preconditioning
+# ---------------------------------------------------------------------------
+def test_precond_setup_matches_oracle(env, orc):
+    """1/a_ii is bit-exact (IEEE division on both sides); block inverses
+    (Gauss-Jordan on the GPU, LU solves in the oracle) agree to rounding,
+    with exact zeros outside ragged blocks."""
+    mxs, ctx, torch = env
+    A = I.random_spd(3001, seed=30)
+    M = mxs.Matrix.from_host(ctx, A)
+    P = mxs.Precond(ctx, M, "jacobi")
+    st, J = orc.jacobi(A)
+    assert st == orc.OK and np.array_equal(P.export(), J.minv)
+    P.close()
+    for bs in (1, 3, 8, 16, 32):
+        P = mxs.Precond(ctx, M, "block_jacobi", bs)
+        st, B = orc.block_jacobi(A, bs)
+        g = P.export()
+        assert st == orc.OK and g.shape == B.minv.shape
+        assert np.array_equal(g == 0.0, B.minv == 0.0), bs
+        scale = np.abs(B.minv).reshape(-1, bs * bs).max(axis=1).repeat(bs * bs)
+        assert np.all(np.abs(g - B.minv) <= 1e-12 * scale), bs
+        P.close()
+
+
+CASES = [("poisson2d_64", lambda: I.poisson2d(64)),
+         ("random_spd_20k", lambda: I.random_spd(20000, seed=31)),
+         ("weighted_5pt_70", lambda: I.serving_system(70, 3))]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in CASES])
+@pytest.mark.parametrize("kind,bs", [("jacobi", 1), ("block_jacobi", 4), ("block_jacobi", 32)])
+@pytest.mark.parametrize("fmt", ["csr", "ell"])
+def test_pcg_matches_oracle(env, orc, name, kind, bs, fmt):
+    mxs, ctx, torch = env
+    A = dict(CASES)[name]()
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 32))
+    M = mxs.Matrix.from_host(ctx, A)
+    P = mxs.Precond(ctx, M, kind, bs)
+    B = M if fmt == "csr" else M.convert(fmt, "f64")
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r = mxs.solve(ctx, "cg", B, _dev(torch, b), x, tol=1e-10, raise_on_error=False, precond=P)
+    xh = x.cpu().numpy()
+    _assert_converged(orc, A, b, xh, r, 1e-10)
+    st, OM = orc.jacobi(A) if kind == "jacobi" else orc.block_jacobi(A, bs)
+    ref = orc.pcg(A, b, OM, tol=1e-10)
+    assert ref.status == orc.OK
+    assert abs(r.iters - ref.iters) <= 2 + ref.iters // 20, (r.iters, ref.iters)
+    plain = orc.cg(A, b, tol=1e-10)
+    if name == "random_spd_20k":
+        assert r.iters * 10 < plain.iters
+
+
+def test_pcg_failures(env, orc):
+    mxs, ctx, torch = env
+    A = I.poisson2d(6)
+    bad = I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, A.val.copy())
+    k = [q for q in range(bad.rowptr[7], bad.rowptr[8]) if bad.col[q] == 7][0]
+    bad.val[k] = 0.0
+    Mb = mxs.Matrix.from_host(ctx, bad)
+    with pytest.raises(mxs.MxsError) as e:
+        mxs.Precond(ctx, Mb, "jacobi")
+    assert e.value.status == mxs.BREAKDOWN
+    S = I.dense_to_csr(np.array([[1.0, 1.0, 0, 0], [1.0, 1.0, 0, 0], [0, 0, 2.0, 0],
+                                 [0, 0, 0, 3.0]]))
+    Ms = mxs.Matrix.from_host(ctx, S)
+    with pytest.raises(mxs.MxsError) as e:
+        mxs.Precond(ctx, Ms, "block_jacobi", 2)
+    assert e.value.status == mxs.BREAKDOWN
+    mxs.Precond(ctx, Ms, "block_jacobi", 1).close()
+    M = mxs.Matrix.from_host(ctx, A)
+    for k_, bs in (("block_jacobi", 0), ("block_jacobi", 33), (7, 1)):
+        with pytest.raises(mxs.MxsError) as e:
+            mxs.Precond(ctx, M, k_, bs)
+        assert e.value.status == mxs.INVALID_ARG
+    with pytest.raises(mxs.MxsError) as e:
+        mxs.Precond(ctx, M.convert("csr", "f32"), "jacobi")
+    assert e.value.status == mxs.UNSUPPORTED
+    P = mxs.Precond(ctx, M, "jacobi")
+    b = _dev(torch, np.ones(A.n))
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r = mxs.solve(ctx, "bicgstab", M, b, x, raise_on_error=False, precond=P)
+    assert r.status == mxs.UNSUPPORTED
+    # an indefinite preconditioner: (r, M^-1 r) < 0 is a breakdown, as in the oracle
+    N = I.dense_to_csr(np.diag([1.0, -1.0, 2.0]))
+    Mn = mxs.Matrix.from_host(ctx, N)
+    Pn = mxs.Precond(ctx, Mn, "jacobi")
+    bn = np.array([0.0, 1.0, 0.0])
+    xn = torch.zeros(3, dtype=torch.float64, device="cuda")
+    r = mxs.solve(ctx, "cg", Mn, _dev(torch, bn), xn, raise_on_error=False, precond=Pn)
+    st, OJ = orc.jacobi(N)
+    assert r.status == mxs.BREAKDOWN and orc.pcg(N, bn, OJ).status == orc.BREAKDOWN
+    # size mismatch
+    P7 = mxs.Precond(ctx, mxs.Matrix.from_host(ctx, I.poisson2d(7)), "jacobi")
+    r = mxs.solve(ctx, "cg", M, b, x, raise_on_error=False, precond=P7)
+    assert r.status == mxs.INVALID_ARG
+    # b = 0: x = 0 after 0 iterations
+    x.fill_(1.0)
+    r = mxs.solve(ctx, "cg", M, torch.zeros_like(b), x, raise_on_error=False, precond=P)
+    assert r.status == mxs.OK and r.iters == 0 and not x.any()
+
+
+@pytest.mark.parametrize("low,kind,bs", [("f32", "jacobi", 1), ("f16", "block_jacobi", 16),
+                                         ("f32", "block_jacobi", 8)])
+def test_ir_preconditioned_inner(env, orc, low, kind, bs):
+    mxs, ctx, torch = env
+    A = I.random_spd(20000, seed=33)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 34))
+    M = mxs.Matrix.from_host(ctx, A)
+    P = mxs.Precond(ctx, M, kind, bs)
+    L = M.convert("csr", low)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-10, precond=P)
+    xh = x.cpu().numpy()
+    assert r.status == mxs.OK
+    assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
+    st, OM = orc.jacobi(A) if kind == "jacobi" else orc.block_jacobi(A, bs)
+    ref = orc.ir(A, b, low=low, tol=1e-10, precond=OM)
+    assert ref.status == orc.OK
+    assert abs(r.outer_iters - ref.outer_iters) <= 1
+    assert abs(r.inner_iters_total - ref.inner_iters_total) <= 3 + ref.inner_iters_total // 10
+    plain = orc.ir(A, b, low=low, tol=1e-10)
+    assert r.inner_iters_total * 5 < plain.inner_iters_total
+
+
+@pytest.mark.slow
+def test_full_size_pcg(env, orc):
+    """Jacobi PCG and refinement with a Jacobi-preconditioned inner solve on
+    the 2^20 random SPD matrix (kappa(D^-1 A) <= 21)."""
+    mxs, ctx, torch = env
+    A = I.random_spd(2 ** 20)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 35))
+    M = mxs.Matrix.from_host(ctx, A)
+    P = mxs.Precond(ctx, M, "jacobi")
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r = mxs.solve(ctx, "cg", M, _dev(torch, b), x, tol=1e-10, precond=P)
+    xh = x.cpu().numpy()
+    _assert_converged(orc, A, b, xh, r, 1e-10)
+    assert r.iters <= 54
+    L = M.convert("csr", "f32")
+    x.zero_()
+    ri = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-10, precond=P)
+    xh = x.cpu().numpy()
+    assert ri.status == mxs.OK
+    assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
