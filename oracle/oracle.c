@@ -694,6 +694,111 @@ int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col,
 
 /* ------------------------------------------------------------------------ */
 /* ------------------------------------------------------------------------ */
+/* CGS (Sonneveld 1989; Saad 2003, Algorithm 7.6), r_hat = r_0              */
+/* ------------------------------------------------------------------------ */
+int orc_cgs(int64_t n, const int32_t* rowptr, const int32_t* col,
+            const double* val, const double* b, double* x,
+            const orc_stop* stop, orc_info* info) {
+  csr_t A = {n, rowptr, col, val};
+  memset(info, 0, sizeof(*info));
+  double nb = nrm2(n, b);
+  if (!isfinite(nb)) return ORC_NONFINITE;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    return ORC_OK;
+  }
+  double *r = vec(n), *rh = vec(n), *p = vec(n), *u = vec(n), *q = vec(n),
+         *v = vec(n), *w = vec(n);
+  residual(&A, b, x, r);
+  double nr0 = nrm2(n, r);
+  double thr = threshold(stop, nb, nr0);
+  double base = baseline_norm(stop, nb, nr0);
+  int status = ORC_OK;
+  int64_t it = 0, repl = 0;
+  int restart = 1;
+  int check = nr0 <= thr;
+  double rho = 0.0;
+  for (;;) {
+    if (check) {
+      residual(&A, b, x, r);
+      double nt = nrm2(n, r);
+      info->relres_true = nt / base;
+      if (nt <= thr) break;
+      if (repl >= stop->max_replacements) {
+        status = ORC_NOT_CONVERGED;
+        break;
+      }
+      repl++;
+      restart = 1;
+      check = 0;
+    }
+    if (restart) {
+      memcpy(rh, r, (size_t)n * sizeof(double));
+      memcpy(u, r, (size_t)n * sizeof(double));
+      memcpy(p, r, (size_t)n * sizeof(double));
+      rho = dot(n, rh, r);
+      restart = 0;
+    }
+    if (it >= stop->max_iters) {
+      residual(&A, b, x, w);
+      info->relres_true = nrm2(n, w) / base;
+      status = ORC_NOT_CONVERGED;
+      break;
+    }
+    if (!isfinite(rho)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (rho == 0.0) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    matvec(&A, p, v);
+    double sigma = dot(n, rh, v);
+    if (!isfinite(sigma)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (sigma == 0.0) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    double alpha = rho / sigma;
+    for (int64_t i = 0; i < n; ++i) q[i] = u[i] - alpha * v[i];
+    for (int64_t i = 0; i < n; ++i) w[i] = u[i] + q[i];
+    for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * w[i];
+    matvec(&A, w, v); /* v = A (u + q) */
+    for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * v[i];
+    ++it;
+    double nr = nrm2(n, r);
+    info->relres_recurrence = nr / base;
+    if (!isfinite(nr)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (nr <= thr) {
+      check = 1;
+      continue;
+    }
+    double rho_new = dot(n, rh, r);
+    double beta = rho_new / rho;
+    for (int64_t i = 0; i < n; ++i) u[i] = r[i] + beta * q[i];
+    for (int64_t i = 0; i < n; ++i) p[i] = u[i] + beta * (q[i] + beta * p[i]);
+    rho = rho_new;
+  }
+  info->iters = it;
+  info->replacements = repl;
+  free(r);
+  free(rh);
+  free(p);
+  free(u);
+  free(q);
+  free(v);
+  free(w);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* BiCGSTAB (van der Vorst 1992; Saad 2003, ch. 7), r_hat = r_0             */
 /* ------------------------------------------------------------------------ */
 int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,

@@ -111,6 +111,12 @@ int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
 int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
                  const double* val, const double* b, double* x,
                  const orc_stop* stop, orc_info* info);
+/* CGS (Sonneveld 1989; Saad 2003, Algorithm 7.6), r_hat = r_0; the
+ * stopping rule and replacements of orc_bicgstab (a replacement restarts
+ * with r_hat = u = p = r). */
+int orc_cgs(int64_t n, const int32_t* rowptr, const int32_t* col,
+            const double* val, const double* b, double* x,
+            const orc_stop* stop, orc_info* info);
 int orc_gmres(int64_t n, const int32_t* rowptr, const int32_t* col,
               const double* val, const double* b, double* x, int64_t m,
               const orc_stop* stop, orc_info* info, double* hist,

@@ -340,3 +340,58 @@ def test_ir_with_jacobi_inner(orc):
     st, MB = orc.block_jacobi(A, 16)
     r16 = orc.ir(A, b, low="f16", tol=1e-10, precond=MB)
     assert r16.status == orc.OK and r16.relres_true <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# CGS (Sonneveld 1989; Saad 2003, Algorithm 7.6)
+# ---------------------------------------------------------------------------
+def test_cgs_scaled_identity_one_step(orc):
+    A = _scaled(I.dense_to_csr(np.eye(30)), 3.0)
+    b = I.uniform_vector(30, 40)
+    r = orc.cgs(A, b, tol=1e-14)
+    assert r.status == orc.OK and r.iters == 1
+    assert np.allclose(r.x, b / 3.0, rtol=0, atol=1e-15)
+
+
+def test_cgs_is_squared_cg_on_symmetric(orc):
+    # with r_hat = r0 on a symmetric matrix BiCG is CG, so the CGS residual
+    # after k steps is phi_k(A)^2 r0 where phi_k(A) r0 is CG's residual:
+    # in the eigenbasis c = Q^T r0, d = Q^T r_k(CG), CGS gives d^2 / c
+    n = 12
+    lam = np.linspace(1.0, 6.0, n)
+    Q, _ = np.linalg.qr(I.rng(41).standard_normal((n, n)))
+    Mx = Q @ np.diag(lam) @ Q.T
+    Mx = (Mx + Mx.T) / 2
+    A = I.dense_to_csr(Mx)
+    b = Q @ (1.0 + I.rng(42).random(n))
+    c = Q.T @ b
+    for k in (1, 2, 3, 4):
+        xcg = orc.cg(A, b, tol=0.0, maxit=k).x
+        xcgs = orc.cgs(A, b, tol=0.0, maxit=k).x
+        d = Q.T @ (b - Mx @ xcg)
+        rcgs = Q.T @ (b - Mx @ xcgs)
+        assert np.allclose(rcgs, d * d / c, rtol=1e-7, atol=1e-9 * np.abs(c).max()), k
+
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (20, 2)])
+def test_cgs_nonsymmetric_vs_numpy(orc, n, seed):
+    g = I.rng(seed + 60)
+    Mx = np.eye(n) * 4 + 0.8 * g.standard_normal((n, n)) / np.sqrt(n)
+    A = I.dense_to_csr(Mx)
+    b = g.standard_normal(n)
+    r = orc.cgs(A, b, tol=1e-12, maxit=200)
+    assert r.status == orc.OK and r.relres_true <= 1e-12
+    assert _relerr(r.x, np.linalg.solve(Mx, b)) <= 1e-10
+
+
+def test_cgs_breakdown_and_convdiff(orc):
+    # skew-symmetric: (r_hat, A p) = (r0, A r0) = 0 on the first step
+    S = np.array([[0.0, 1.0, 0.0], [-1.0, 0.0, 2.0], [0.0, -2.0, 0.0]])
+    r = orc.cgs(I.dense_to_csr(S), np.array([1.0, 2.0, 3.0]))
+    assert r.status == orc.BREAKDOWN and r.iters == 0
+    Cd = I.convdiff3d(12)
+    b = orc.spmv_csr(Cd, I.uniform_vector(Cd.n, 43))
+    r = orc.cgs(Cd, b, tol=1e-10)
+    assert r.status == orc.OK and r.relres_true <= 1e-10
+    nm = orc.cgs(Cd, b, tol=1e-10, maxit=3)
+    assert nm.status == orc.NOT_CONVERGED and nm.iters == 3
