@@ -297,6 +297,7 @@ def main():
         # 3D problems at 128^3
         for name, gen, solver in (("cg_poisson3d", I.poisson3d, "cg"),
                                   ("bicgstab_convdiff3d", I.convdiff3d, "bicgstab"),
+                                  ("cgs_convdiff3d", I.convdiff3d, "cgs"),
                                   ("gmres30_convdiff3d", I.convdiff3d, "gmres")):
             Q = gen(N)
             Qm = mxs.Matrix.from_host(ctx, Q)
@@ -318,11 +319,12 @@ def main():
             # fixed 1000 iterations (no convergence test can stop it), for
             # GFLOP/s and GB/s under the per-iteration models: CG 2nnz+10n
             # flops and B_csr+64n bytes; BiCGSTAB 4nnz+20n and 2B_csr+144n;
-            # GMRES(30) step j 2nnz+8(j+1)n+3n and B_csr+(4(j+1)+9)8n,
-            # averaged over j = 0..29
+            # CGS 4nnz+19n and 2B_csr+136n; GMRES(30) step j 2nnz+8(j+1)n+3n
+            # and B_csr+(4(j+1)+9)8n, averaged over j = 0..29
             n_, z_ = Q.n, Q.nnz
             fl, by = {"cg": (2 * z_ + 10 * n_, csr_b + 64 * n_),
                       "bicgstab": (4 * z_ + 20 * n_, 2 * csr_b + 144 * n_),
+                      "cgs": (4 * z_ + 19 * n_, 2 * csr_b + 136 * n_),
                       "gmres": (2 * z_ + 8 * 15.5 * n_ + 3 * n_,
                                 csr_b + (4 * 15.5 + 9) * 8 * n_)}[solver]
             xq.zero_()

@@ -191,7 +191,7 @@ mxs_status mxs_spmv(mxs_ctx* ctx, const void* alpha, const mxs_matrix* A, const 
 /* ---------------------------------------------------------------------- */
 /* Krylov solvers                                                          */
 /* ---------------------------------------------------------------------- */
-typedef enum { MXS_CG = 0, MXS_BICGSTAB = 1, MXS_GMRES = 2 } mxs_solver;
+typedef enum { MXS_CG = 0, MXS_BICGSTAB = 1, MXS_GMRES = 2, MXS_CGS = 3 } mxs_solver;
 
 #define MXS_BASELINE_RHS 0      /* tolerance relative to ||b||_2          */
 #define MXS_BASELINE_INITIAL 1  /* tolerance relative to ||b - A x0||_2   */
@@ -250,7 +250,9 @@ typedef struct {
  * Functionality"; textbook forms from Saad 2003 and, for GMRES, Saad &
  * Schultz 1986).  A: an F64 matrix in any format (else MXS_UNSUPPORTED);
  * b, x: FP64 device vectors of nrows entries, x holds x0 on entry and the
- * iterate on exit.  CG: Hestenes-Stiefel.  BiCGSTAB: r_hat = r0.  GMRES(m):
+ * iterate on exit.  CG: Hestenes-Stiefel.  BiCGSTAB: r_hat = r0.  CGS
+ * (Sonneveld; Saad 2003, Algorithm 7.6): r_hat = r0, two products per
+ * iteration, a replacement restarts r_hat = u = p = r.  GMRES(m):
  * classical Gram-Schmidt with reorthogonalisation, Givens rotations and
  * the triangular solve on the GPU.  The solver stops when the recurrence
  * residual meets the tolerance and then checks the true residual b - A x in

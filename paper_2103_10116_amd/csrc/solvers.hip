@@ -593,6 +593,101 @@ __global__ __launch_bounds__(RB) void k_ir_update(int64_t n, double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// CGS (Sonneveld 1989; Saad 2003, Algorithm 7.6), r_hat = r0.  Iteration k
+// (par = k & 1), rho[par] = (r_hat, r):
+//   v = A p;   k_cgs_sigma: partials of r_hat.v
+//   k_cgs_qw:  alpha = rho[par] / (r_hat.v), q = u - alpha v, w = u + q,
+//              x += alpha w
+//   v = A w;   k_cgs_r: r -= alpha v, partials of (r.r, r_hat.r)
+//   k_cgs_dir: stopping test on r.r, rho[1-par] = r_hat.r,
+//              beta = rho[1-par] / rho[par], u = r + beta q,
+//              p = u + beta (q + beta p)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RB) void k_cgs_sigma(int64_t n, const double* __restrict__ rh,
+                                                  const double* __restrict__ v,
+                                                  double* __restrict__ pa, const KState* st) {
+  if (st->done) return;
+  double acc[1] = {0.0};
+  GRID_STRIDE(i, n) acc[0] += rh[i] * v[i];
+  block_partials<1>(acc, pa);
+}
+
+__global__ __launch_bounds__(RB) void k_cgs_qw(int64_t n, const double* __restrict__ u,
+                                               const double* __restrict__ v,
+                                               double* __restrict__ q, double* __restrict__ w,
+                                               double* __restrict__ x,
+                                               const double* __restrict__ pa, int g, KState* st,
+                                               int par) {
+  if (st->done) return;
+  double sg[1];
+  finish<1>(pa, g, sg);
+  if (!isfinite(sg[0]) || sg[0] == 0.0) {
+    if (lead()) st->done = isfinite(sg[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+    return;
+  }
+  const double a = st->rho[par] / sg[0];
+  if (lead()) st->alpha = a;
+  GRID_STRIDE(i, n) {
+    const double qi = u[i] - a * v[i];
+    const double wi = u[i] + qi;
+    q[i] = qi;
+    w[i] = wi;
+    x[i] += a * wi;
+  }
+}
+
+__global__ __launch_bounds__(RB) void k_cgs_r(int64_t n, double* __restrict__ r,
+                                              const double* __restrict__ v,
+                                              const double* __restrict__ rh,
+                                              double* __restrict__ pb, const KState* st) {
+  if (st->done) return;
+  const double a = st->alpha;
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double ri = r[i] - a * v[i];
+    r[i] = ri;
+    acc[0] += ri * ri;
+    acc[1] += rh[i] * ri;
+  }
+  block_partials<2>(acc, pb);
+}
+
+__global__ __launch_bounds__(RB) void k_cgs_dir(int64_t n, const double* __restrict__ r,
+                                                const double* __restrict__ q,
+                                                double* __restrict__ u, double* __restrict__ p,
+                                                const double* __restrict__ pb, int g, KState* st,
+                                                int par, int64_t k) {
+  if (st->done) return;
+  double t[2];
+  finish<2>(pb, g, t);
+  const double rr = t[0], rhr = t[1];
+  int32_t verdict = RUN;
+  if (!isfinite(rr))
+    verdict = ST_NONFINITE;
+  else if (sqrt(rr) <= st->thr)
+    verdict = ST_CONVERGED;
+  else if (k + 1 >= st->max_iters)
+    verdict = ST_MAXIT;
+  else if (!isfinite(rhr))
+    verdict = ST_NONFINITE;
+  else if (rhr == 0.0)
+    verdict = ST_BREAKDOWN;
+  if (lead()) {
+    st->iters = k + 1;
+    st->res2 = rr;
+    st->rho[1 - par] = rhr;
+    if (verdict != RUN) st->done = verdict;
+  }
+  if (verdict != RUN) return;
+  const double beta = rhr / st->rho[par];
+  GRID_STRIDE(i, n) {
+    const double ui = r[i] + beta * q[i];
+    u[i] = ui;
+    p[i] = ui + beta * (q[i] + beta * p[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Preconditioned CG (Saad 2003, Algorithm 9.1), PC = 1 Jacobi (z = dinv r,
 // never stored: formed where it is used), PC = 2 block Jacobi (z stored).
 // Iteration k (par = k & 1), rho[par] = (r, z) of the previous step:
@@ -1187,6 +1282,99 @@ mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, do
   }
 }
 
+mxs_status solve_cgs(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
+                     const Stop& stop, mxs_solve_info* info) {
+  const int64_t n = A->n;
+  const size_t ld = align_up((size_t)n, 64);
+  Work w;
+  mxs_status s = get_work(ctx, 7 * ld * sizeof(double), &w);
+  if (s) return s;
+  double* r = (double*)w.vec;
+  double* rh = r + ld;
+  double* p = rh + ld;
+  double* u = p + ld;
+  double* q = u + ld;
+  double* v = q + ld;
+  double* wv = v + ld;
+  double nb2, nr2;
+  if ((s = residual(ctx, A, b, x, r))) return s;
+  if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
+  const double nb = sqrt(nb2), nr0 = sqrt(nr2);
+  if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
+  if (nb == 0.0) return zero_solution(ctx, x, n, info);
+  if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
+  const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
+  const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
+  const int g = red_grid(n);
+  const double one = 1.0, zero = 0.0;
+  KState& h = *w.hst;
+  std::memset(&h, 0, sizeof(KState));
+  int64_t repl = 0;
+  double relres_true = nr0 / base;
+  int32_t done = nr0 <= thr ? ST_CONVERGED : RUN;
+  int64_t iters = 0;
+  double rr = nr2;
+  for (;;) {
+    if (done == RUN) {
+      // (re)start: r_hat = u = p = r, rho = r_hat . r = r . r
+      for (double* dst : {rh, u, p})
+        MXS_HIP_TRY(ctx, hipMemcpyAsync(dst, r, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                        ctx->stream));
+      std::memset(&h, 0, sizeof(KState));
+      h.rho[iters & 1] = rr;
+      h.res2 = rr;
+      h.thr = thr;
+      h.iters = iters;
+      h.max_iters = stop.max_iters;
+      if ((s = push_state(ctx, w))) return s;
+    }
+    int64_t k = iters;
+    while (done == RUN) {
+      for (int it = 0; it < stop.check_every; ++it, ++k) {
+        const int par = (int)(k & 1);
+        if ((s = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return s;
+        k_cgs_sigma<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
+        k_cgs_qw<<<g, RB, 0, ctx->stream>>>(n, u, v, q, wv, x, w.pa, g, w.st, par);
+        if ((s = launch_spmv(ctx, A, &one, wv, &zero, v, &w.st->done))) return s;
+        k_cgs_r<<<g, RB, 0, ctx->stream>>>(n, r, v, rh, w.pb, w.st);
+        k_cgs_dir<<<g, RB, 0, ctx->stream>>>(n, r, q, u, p, w.pb, g, w.st, par, k);
+      }
+      MXS_HIP_TRY(ctx, hipGetLastError());
+      const int64_t before = iters;
+      if ((s = pull_state(ctx, w))) return s;
+      done = h.done;
+      iters = h.iters;
+      if (done == RUN && iters <= before)
+        return fail(ctx, MXS_HIP, "CGS made no progress (device state not updated)");
+      k = iters;
+    }
+    if (done == ST_BREAKDOWN || done == ST_NONFINITE) {
+      s = map_done(done);
+      fill_info(info, h, base, relres_true, repl, 0, s);
+      return fail(ctx, s, done == ST_BREAKDOWN ? "CGS breakdown" : "non-finite value in CGS");
+    }
+    double rt2;
+    if ((s = residual(ctx, A, b, x, r))) return s;
+    if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr,
+                          &rt2, nullptr)))
+      return s;
+    relres_true = sqrt(rt2) / base;
+    h.iters = iters;
+    if (done == ST_CONVERGED && sqrt(rt2) <= thr) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_OK);
+      return MXS_OK;
+    }
+    if (done == ST_MAXIT || repl >= stop.max_repl || iters >= stop.max_iters) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_NOT_CONVERGED);
+      return fail(ctx, MXS_NOT_CONVERGED, "CGS stopped after %lld iterations, relres %.3e",
+                  (long long)iters, relres_true);
+    }
+    repl++;
+    rr = rt2;
+    done = RUN;
+  }
+}
+
 mxs_status solve_gmres(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
                        const Stop& stop, int m, mxs_solve_info* info) {
   if (m < 1 || m > MAXM)
@@ -1283,6 +1471,8 @@ mxs_status solve_dispatch(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, co
       return solve_cg(ctx, A, b, x, read_stop(stop, 20000), info);
     case MXS_BICGSTAB:
       return solve_bicgstab(ctx, A, b, x, read_stop(stop, 10000), info);
+    case MXS_CGS:
+      return solve_cgs(ctx, A, b, x, read_stop(stop, 10000), info);
     case MXS_GMRES:
       return solve_gmres(ctx, A, b, x, read_stop(stop, 20000),
                          opts && opts->restart > 0 ? opts->restart : 30, info);

@@ -233,6 +233,8 @@ def test_full_size_krylov(env, orc):
     _assert_converged(orc, Cd, b, x, r, 1e-10)
     r, x = _solve(env, Cd, b, "gmres", restart=30)
     _assert_converged(orc, Cd, b, x, r, 1e-10)
+    r, x = _solve(env, Cd, b, "cgs")
+    _assert_converged(orc, Cd, b, x, r, 1e-10)
 
 
 # ---------------------------------------------------------------------------
@@ -380,3 +382,49 @@ def test_full_size_pcg(env, orc):
     xh = x.cpu().numpy()
     assert ri.status == mxs.OK
     assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
+
+
+# ---------------------------------------------------------------------------
+# CGS
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("fmt", ["csr", "coo", "hyb"])
+def test_cgs_convdiff(env, orc, fmt):
+    A = I.convdiff3d(24)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 50))
+    r, x = _solve(env, A, b, "cgs", fmt)
+    _assert_converged(orc, A, b, x, r, 1e-10)
+    ref = orc.cgs(A, b, tol=1e-10)
+    assert ref.status == orc.OK
+    assert abs(r.iters - ref.iters) <= 2 + ref.iters // 10, (r.iters, ref.iters)
+
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (20, 2)])
+def test_cgs_nonsymmetric_vs_lu(env, orc, n, seed):
+    g = I.rng(seed + 60)
+    Mx = np.eye(n) * 4 + 0.8 * g.standard_normal((n, n)) / np.sqrt(n)
+    A = I.dense_to_csr(Mx)
+    b = g.standard_normal(n)
+    r, x = _solve(env, A, b, "cgs", tol=1e-12)
+    assert r.status == 0
+    st, xl = orc.lu_solve(Mx, b)
+    assert np.linalg.norm(x - xl) <= 1e-10 * np.linalg.norm(xl)
+
+
+def test_cgs_statuses(env, orc):
+    mxs, ctx, torch = env
+    S = np.array([[0.0, 1.0, 0.0], [-1.0, 0.0, 2.0], [0.0, -2.0, 0.0]])
+    r, x = _solve(env, I.dense_to_csr(S), np.array([1.0, 2.0, 3.0]), "cgs")
+    assert r.status == mxs.BREAKDOWN and orc.cgs(I.dense_to_csr(S), np.array([1.0, 2.0, 3.0])).status == orc.BREAKDOWN
+    Cd = I.convdiff3d(12)
+    b = orc.spmv_csr(Cd, I.uniform_vector(Cd.n, 51))
+    r, x = _solve(env, Cd, b, "cgs", max_iters=3)
+    assert r.status == mxs.NOT_CONVERGED and r.iters == 3
+    ref = orc.cgs(Cd, b, maxit=3)
+    assert abs(orc.true_relres(Cd, b, x) - ref.relres_true) <= 1e-9 * ref.relres_true
+    r, x = _solve(env, Cd, np.zeros(Cd.n), "cgs")
+    assert r.status == mxs.OK and r.iters == 0 and not x.any()
+    # a scaled identity: one step
+    E = I.dense_to_csr(np.eye(40) * 3.0)
+    bb = I.uniform_vector(40, 52)
+    r, x = _solve(env, E, bb, "cgs", tol=1e-14)
+    assert r.status == mxs.OK and r.iters == 1
