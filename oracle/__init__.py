@@ -2,7 +2,8 @@
 
 This package wraps ``oracle.c``, a plain single-threaded FP64 C implementation
 of the operations the GPU library computes: CSR/COO/ELL/hybrid storage and
-conversions, the sparse matrix-vector product, CG, BiCGSTAB, CGS, GMRES(m),
+conversions, the sparse matrix-vector product, CG, pipelined CG, BiCGSTAB,
+CGS, GMRES(m),
 Jacobi and block-Jacobi preconditioned CG, mixed-precision iterative
 refinement and a dense LU solver.  Each C function
 cites the passage of the paper (or the textbook the paper refers to) that it
@@ -102,6 +103,7 @@ def _declare(L):
         "orc_cg": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info), _P, _I64]),
         "orc_bicgstab": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info)]),
         "orc_cgs": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info)]),
+        "orc_pipecg": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info)]),
         "orc_gmres": (C.c_int, [_I64, _P, _P, _P, _P, _P, _I64, C.POINTER(Stop), C.POINTER(Info), _P, _I64]),
         "orc_ir": (C.c_int, [_I64, _P, _P, _P, C.c_int, _P, _P, _P, _P, _P, _D, _I64, _D, _I64, C.c_int, C.POINTER(IRInfo)]),
         "orc_ir_pc": (C.c_int, [_I64, _P, _P, _P, C.c_int, _P, _P, _P, _P, _P, _D, _I64, _D, _I64, C.c_int, C.c_int, _I64, _P, C.POINTER(IRInfo)]),
@@ -405,6 +407,16 @@ def pcg(A, b, M: Precond, x0=None, tol=1e-10, maxit=20000, abs_tol=0.0, baseline
     mv = _c(M.minv, np.float64)
     st = lib().orc_pcg(n, _p(rp), _p(ci), _p(v), M.kind, M.bs, _p(mv), _p(bb), _p(x),
                        C.byref(_stop(tol, maxit, abs_tol, baseline)), C.byref(info))
+    return _result(st, x, info)
+
+
+def pipecg(A, b, x0=None, tol=1e-10, maxit=20000, abs_tol=0.0):
+    n, rp, ci, v = _csr(A)
+    bb = _c(b, np.float64)
+    x = np.zeros(n) if x0 is None else np.array(x0, np.float64, copy=True)
+    info = Info()
+    st = lib().orc_pipecg(n, _p(rp), _p(ci), _p(v), _p(bb), _p(x),
+                          C.byref(_stop(tol, maxit, abs_tol)), C.byref(info))
     return _result(st, x, info)
 
 

@@ -694,6 +694,110 @@ int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col,
 
 /* ------------------------------------------------------------------------ */
 /* ------------------------------------------------------------------------ */
+/* Pipelined CG (Ghysels & Vanroose 2014), unpreconditioned                  */
+/* ------------------------------------------------------------------------ */
+int orc_pipecg(int64_t n, const int32_t* rowptr, const int32_t* col,
+               const double* val, const double* b, double* x,
+               const orc_stop* stop, orc_info* info) {
+  csr_t A = {n, rowptr, col, val};
+  memset(info, 0, sizeof(*info));
+  double nb = nrm2(n, b);
+  if (!isfinite(nb)) return ORC_NONFINITE;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    return ORC_OK;
+  }
+  double *r = vec(n), *w = vec(n), *q = vec(n), *z = vec(n), *s = vec(n),
+         *p = vec(n);
+  residual(&A, b, x, r);
+  double nr0 = nrm2(n, r);
+  double thr = threshold(stop, nb, nr0);
+  double base = baseline_norm(stop, nb, nr0);
+  int status = ORC_OK;
+  int64_t it = 0, repl = 0;
+  int fresh = 1;               /* next step starts a recurrence (beta = 0) */
+  double gamma_old = 0.0, alpha_old = 0.0;
+  matvec(&A, r, w);
+  for (;;) {
+    double gamma = dot(n, r, r);
+    double delta = dot(n, w, r);
+    info->relres_recurrence = sqrt(gamma) / base;
+    if (!isfinite(gamma) || !isfinite(delta)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (sqrt(gamma) <= thr) {
+      /* verify b - A x; on disagreement replace r and restart */
+      residual(&A, b, x, r);
+      double nt = nrm2(n, r);
+      info->relres_true = nt / base;
+      if (nt <= thr) break;
+      if (repl >= stop->max_replacements) {
+        status = ORC_NOT_CONVERGED;
+        break;
+      }
+      repl++;
+      matvec(&A, r, w);
+      fresh = 1;
+      continue;
+    }
+    if (it >= stop->max_iters) {
+      residual(&A, b, x, q);
+      info->relres_true = nrm2(n, q) / base;
+      status = ORC_NOT_CONVERGED;
+      break;
+    }
+    matvec(&A, w, q);
+    double beta, alpha, den;
+    if (fresh) {
+      beta = 0.0;
+      den = delta;
+    } else {
+      beta = gamma / gamma_old;
+      den = delta - beta * gamma / alpha_old;
+    }
+    if (!isfinite(den)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (den <= 0.0) { /* (p, A p) > 0 for SPD A */
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    alpha = gamma / den;
+    if (fresh) {
+      for (int64_t i = 0; i < n; ++i) {
+        z[i] = q[i];
+        s[i] = w[i];
+        p[i] = r[i];
+      }
+    } else {
+      for (int64_t i = 0; i < n; ++i) {
+        z[i] = q[i] + beta * z[i];
+        s[i] = w[i] + beta * s[i];
+        p[i] = r[i] + beta * p[i];
+      }
+    }
+    for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * s[i];
+    for (int64_t i = 0; i < n; ++i) w[i] = w[i] - alpha * z[i];
+    gamma_old = gamma;
+    alpha_old = alpha;
+    fresh = 0;
+    ++it;
+  }
+  info->iters = it;
+  info->replacements = repl;
+  free(r);
+  free(w);
+  free(q);
+  free(z);
+  free(s);
+  free(p);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* CGS (Sonneveld 1989; Saad 2003, Algorithm 7.6), r_hat = r_0              */
 /* ------------------------------------------------------------------------ */
 int orc_cgs(int64_t n, const int32_t* rowptr, const int32_t* col,

@@ -111,6 +111,17 @@ int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
 int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
                  const double* val, const double* b, double* x,
                  const orc_stop* stop, orc_info* info);
+/* Pipelined CG (Ghysels & Vanroose 2014, unpreconditioned): the same
+ * iterates as CG in exact arithmetic, with the two inner products of an
+ * iteration, gamma = (r, r) and delta = (w, r) for w = A r, computed
+ * together and independent of that iteration's product q = A w.  The
+ * stopping test is on sqrt(gamma); the true-residual check and
+ * replacements of orc_cg apply (a replacement restarts with w = A r and
+ * beta = 0). */
+int orc_pipecg(int64_t n, const int32_t* rowptr, const int32_t* col,
+               const double* val, const double* b, double* x,
+               const orc_stop* stop, orc_info* info);
+
 /* CGS (Sonneveld 1989; Saad 2003, Algorithm 7.6), r_hat = r_0; the
  * stopping rule and replacements of orc_bicgstab (a replacement restarts
  * with r_hat = u = p = r). */

@@ -395,3 +395,49 @@ def test_cgs_breakdown_and_convdiff(orc):
     assert r.status == orc.OK and r.relres_true <= 1e-10
     nm = orc.cgs(Cd, b, tol=1e-10, maxit=3)
     assert nm.status == orc.NOT_CONVERGED and nm.iters == 3
+
+
+# ---------------------------------------------------------------------------
+# pipelined CG (Ghysels & Vanroose 2014)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,seed", [(8, 1), (16, 3)])
+def test_pipecg_iterates_are_cg_iterates(orc, n, seed):
+    # the same Krylov iterates as CG in exact arithmetic: after k steps the
+    # two agree to rounding (CG is pinned independently above)
+    Mx = I.random_spd_small(n, 10.0, seed)
+    A = I.dense_to_csr(Mx)
+    b = I.rng(seed + 70).standard_normal(n)
+    for k in range(1, n):
+        xc = orc.cg(A, b, tol=0.0, maxit=k).x
+        xp = orc.pipecg(A, b, tol=0.0, maxit=k).x
+        assert np.linalg.norm(xp - xc) <= 1e-11 * np.linalg.norm(xc), k
+    r = orc.pipecg(A, b, tol=1e-12, maxit=n + 2)
+    assert r.status == orc.OK and r.iters <= n + 1
+
+
+def test_pipecg_poisson_and_eigenvector(orc):
+    A = I.poisson2d(64)
+    b = orc.spmv_csr(A, np.ones(A.n))
+    r = orc.pipecg(A, b, tol=1e-10)
+    c = orc.cg(A, b, tol=1e-10)
+    assert r.status == orc.OK and r.relres_true <= 1e-10
+    assert abs(r.iters - c.iters) <= 2
+    m = 12
+    P = I.poisson2d(m)
+    s = lambda kk: np.sin(np.arange(1, m + 1) * kk * np.pi / (m + 1))
+    v = np.outer(s(5), s(3)).ravel()
+    r1 = orc.pipecg(P, v, tol=1e-12)
+    assert r1.status == orc.OK and r1.iters == 1
+
+
+def test_pipecg_failures(orc):
+    # indefinite: (p, A p) <= 0 on the first step
+    D = I.dense_to_csr(np.diag([1.0, -2.0, 3.0]))
+    r = orc.pipecg(D, np.array([0.0, 1.0, 0.0]))
+    assert r.status == orc.BREAKDOWN and r.iters == 0
+    A = I.poisson2d(16)
+    b = np.ones(A.n)
+    r = orc.pipecg(A, b, tol=1e-10, maxit=5)
+    assert r.status == orc.NOT_CONVERGED and r.iters == 5
+    z = orc.pipecg(A, np.zeros(A.n))
+    assert z.status == orc.OK and z.iters == 0 and not z.x.any()
