@@ -295,7 +295,22 @@ def main():
                                  "p99_ms": round(np.percentile(lat, 99) * 1e3, 3)}
         log("cg poisson2d 64", kr["cg_poisson2d_64"])
         # 3D problems at 128^3
+        # the same with pipelined CG (two launches per iteration)
+        lat = []
+        for i in range(25):
+            xs.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = mxs.solve(ctx, "pipecg", Pm, b, xs, tol=1e-10)
+            lat.append(time.perf_counter() - t0)
+        lat = np.array(lat[3:])
+        kr["pipecg_poisson2d_64"] = {"iters": r.iters, "relres_true": r.relres_true,
+                                     "solves_per_s": round(1.0 / lat.mean(), 1),
+                                     "p50_ms": round(np.percentile(lat, 50) * 1e3, 3),
+                                     "p99_ms": round(np.percentile(lat, 99) * 1e3, 3)}
+        log("pipecg poisson2d 64", kr["pipecg_poisson2d_64"])
         for name, gen, solver in (("cg_poisson3d", I.poisson3d, "cg"),
+                                  ("pipecg_poisson3d", I.poisson3d, "pipecg"),
                                   ("bicgstab_convdiff3d", I.convdiff3d, "bicgstab"),
                                   ("cgs_convdiff3d", I.convdiff3d, "cgs"),
                                   ("gmres30_convdiff3d", I.convdiff3d, "gmres")):
@@ -319,10 +334,13 @@ def main():
             # fixed 1000 iterations (no convergence test can stop it), for
             # GFLOP/s and GB/s under the per-iteration models: CG 2nnz+10n
             # flops and B_csr+64n bytes; BiCGSTAB 4nnz+20n and 2B_csr+144n;
-            # CGS 4nnz+19n and 2B_csr+136n; GMRES(30) step j 2nnz+8(j+1)n+3n
+            # pipelined CG 2nnz+16n and B_csr+104n (q, z, w, s, r, p, x read,
+            # z, s, p, x, r, w written); CGS 4nnz+19n and 2B_csr+136n;
+            # GMRES(30) step j 2nnz+8(j+1)n+3n
             # and B_csr+(4(j+1)+9)8n, averaged over j = 0..29
             n_, z_ = Q.n, Q.nnz
             fl, by = {"cg": (2 * z_ + 10 * n_, csr_b + 64 * n_),
+                      "pipecg": (2 * z_ + 16 * n_, csr_b + 104 * n_),
                       "bicgstab": (4 * z_ + 20 * n_, 2 * csr_b + 144 * n_),
                       "cgs": (4 * z_ + 19 * n_, 2 * csr_b + 136 * n_),
                       "gmres": (2 * z_ + 8 * 15.5 * n_ + 3 * n_,

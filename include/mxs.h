@@ -191,7 +191,13 @@ mxs_status mxs_spmv(mxs_ctx* ctx, const void* alpha, const mxs_matrix* A, const 
 /* ---------------------------------------------------------------------- */
 /* Krylov solvers                                                          */
 /* ---------------------------------------------------------------------- */
-typedef enum { MXS_CG = 0, MXS_BICGSTAB = 1, MXS_GMRES = 2, MXS_CGS = 3 } mxs_solver;
+typedef enum {
+  MXS_CG = 0,
+  MXS_BICGSTAB = 1,
+  MXS_GMRES = 2,
+  MXS_CGS = 3,
+  MXS_PIPECG = 4
+} mxs_solver;
 
 #define MXS_BASELINE_RHS 0      /* tolerance relative to ||b||_2          */
 #define MXS_BASELINE_INITIAL 1  /* tolerance relative to ||b - A x0||_2   */
@@ -252,7 +258,11 @@ typedef struct {
  * b, x: FP64 device vectors of nrows entries, x holds x0 on entry and the
  * iterate on exit.  CG: Hestenes-Stiefel.  BiCGSTAB: r_hat = r0.  CGS
  * (Sonneveld; Saad 2003, Algorithm 7.6): r_hat = r0, two products per
- * iteration, a replacement restarts r_hat = u = p = r.  GMRES(m):
+ * iteration, a replacement restarts r_hat = u = p = r.  Pipelined CG
+ * (Ghysels & Vanroose 2014, unpreconditioned): CG's iterates in exact
+ * arithmetic, with both inner products of an iteration independent of its
+ * product, so an iteration is one product and one fused update kernel; a
+ * replacement restarts the recurrences.  GMRES(m):
  * classical Gram-Schmidt with reorthogonalisation, Givens rotations and
  * the triangular solve on the GPU.  The solver stops when the recurrence
  * residual meets the tolerance and then checks the true residual b - A x in

@@ -55,6 +55,10 @@ struct KState {
   double est;       // GMRES residual estimate |g_{k}|
   double H[(MAXM + 1) * MAXM];  // column-major, leading dimension MAXM+1
   double cs[MAXM], sn[MAXM], g[MAXM + 1], y[MAXM], h2[MAXM + 1];
+  // pipelined CG: gamma and alpha by iteration parity, and the iteration
+  // that starts a recurrence (beta = 0, gamma and delta from dot[])
+  double pg[2], palpha[2];
+  int64_t restart_at;
 };
 
 int red_grid(int64_t n) {
@@ -590,6 +594,91 @@ __global__ __launch_bounds__(RB) void k_ir_scale(int64_t n, const double* __rest
 __global__ __launch_bounds__(RB) void k_ir_update(int64_t n, double* __restrict__ x,
                                                   const float* __restrict__ d, double sigma) {
   GRID_STRIDE(i, n) x[i] += sigma * (double)d[i];
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined CG (Ghysels & Vanroose 2014, unpreconditioned).  Iteration k
+// (par = k & 1) is two launches: q = A w, then k_pipe_update, which
+// finishes the partials of gamma = r.r and delta = w.r written by the
+// previous update (they do not depend on q), tests gamma, forms
+// beta = gamma / gamma_prev and alpha = gamma / (delta - beta gamma /
+// alpha_prev), updates z = q + beta z, s = w + beta s, p = r + beta p,
+// x += alpha p, r -= alpha s, w -= alpha z, and writes the partials of the
+// next gamma and delta.  Partial buffers alternate by parity.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RB) void k_pipe_update(int64_t n, double* __restrict__ x,
+                                                    double* __restrict__ r,
+                                                    double* __restrict__ w,
+                                                    const double* __restrict__ q,
+                                                    double* __restrict__ z,
+                                                    double* __restrict__ s,
+                                                    double* __restrict__ p,
+                                                    const double* __restrict__ pin, int g,
+                                                    double* __restrict__ pout, KState* st,
+                                                    int64_t k) {
+  if (st->done) return;
+  const int par = (int)(k & 1);
+  const bool fresh = k == st->restart_at;
+  double gd[2];
+  if (fresh) {
+    gd[0] = st->dot[0];
+    gd[1] = st->dot[1];
+  } else {
+    finish<2>(pin, g, gd);
+  }
+  const double gamma = gd[0], delta = gd[1];
+  double beta = 0.0, den = delta;
+  if (!fresh) {
+    beta = gamma / st->pg[1 - par];
+    den = delta - beta * gamma / st->palpha[1 - par];
+  }
+  int32_t verdict = RUN;
+  if (!isfinite(gamma) || !isfinite(delta))
+    verdict = ST_NONFINITE;
+  else if (sqrt(gamma) <= st->thr)
+    verdict = ST_CONVERGED;
+  else if (k >= st->max_iters)
+    verdict = ST_MAXIT;
+  else if (!isfinite(den))
+    verdict = ST_NONFINITE;
+  else if (den <= 0.0)
+    verdict = ST_BREAKDOWN;
+  const double alpha = gamma / den;
+  if (lead()) {
+    st->res2 = gamma;
+    st->iters = verdict == RUN ? k + 1 : k;
+    if (verdict != RUN) {
+      st->done = verdict;
+    } else {
+      st->pg[par] = gamma;
+      st->palpha[par] = alpha;
+    }
+  }
+  if (verdict != RUN) return;
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    double zi, si, pi;
+    if (fresh) {
+      zi = q[i];
+      si = w[i];
+      pi = r[i];
+    } else {
+      zi = q[i] + beta * z[i];
+      si = w[i] + beta * s[i];
+      pi = r[i] + beta * p[i];
+    }
+    z[i] = zi;
+    s[i] = si;
+    p[i] = pi;
+    x[i] += alpha * pi;
+    const double ri = r[i] - alpha * si;
+    const double wi = w[i] - alpha * zi;
+    r[i] = ri;
+    w[i] = wi;
+    acc[0] += ri * ri;
+    acc[1] += wi * ri;
+  }
+  block_partials<2>(acc, pout);
 }
 
 // ---------------------------------------------------------------------------
@@ -1282,6 +1371,100 @@ mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, do
   }
 }
 
+mxs_status solve_pipecg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
+                        const Stop& stop, mxs_solve_info* info) {
+  const int64_t n = A->n;
+  const size_t ld = align_up((size_t)n, 64);
+  Work w;
+  mxs_status s = get_work(ctx, 6 * ld * sizeof(double), &w);
+  if (s) return s;
+  double* r = (double*)w.vec;
+  double* wv = r + ld;
+  double* q = wv + ld;
+  double* z = q + ld;
+  double* sv = z + ld;
+  double* p = sv + ld;
+  double nb2, nr2;
+  if ((s = residual(ctx, A, b, x, r))) return s;
+  if ((s = dots<double>(ctx, w, n, b, b, r, r, &nb2, &nr2))) return s;
+  const double nb = sqrt(nb2), nr0 = sqrt(nr2);
+  if (!std::isfinite(nb)) return fail(ctx, MXS_NONFINITE, "non-finite right-hand side");
+  if (nb == 0.0) return zero_solution(ctx, x, n, info);
+  if (!std::isfinite(nr0)) return fail(ctx, MXS_NONFINITE, "non-finite initial residual");
+  const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
+  const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
+  const int g = red_grid(n);
+  const double one = 1.0, zero = 0.0;
+  KState& h = *w.hst;
+  std::memset(&h, 0, sizeof(KState));
+  h.thr = thr;
+  h.max_iters = stop.max_iters;
+  h.res2 = nr2;
+  // (re)start: w = A r, gamma = r.r and delta = w.r into dot[]
+  auto restart = [&]() -> mxs_status {
+    mxs_status e = launch_spmv(ctx, A, &one, r, &zero, wv, nullptr);
+    if (e) return e;
+    double gm, dl;
+    if ((e = dots<double>(ctx, w, n, r, r, wv, r, &gm, &dl))) return e;
+    h.dot[0] = gm;
+    h.dot[1] = dl;
+    h.restart_at = h.iters;
+    h.done = RUN;
+    return push_state(ctx, w);
+  };
+  int64_t repl = 0;
+  double relres_true = nr0 / base;
+  if (nr0 <= thr) {
+    h.done = ST_CONVERGED;
+  } else if ((s = restart())) {
+    return s;
+  }
+  for (;;) {
+    int64_t k = h.iters;
+    while (h.done == RUN) {
+      const int64_t before = k;
+      for (int it = 0; it < stop.check_every; ++it, ++k) {
+        double* pin = (k & 1) ? w.pb : w.pa;
+        double* pout = (k & 1) ? w.pa : w.pb;
+        if ((s = launch_spmv(ctx, A, &one, wv, &zero, q, &w.st->done))) return s;
+        k_pipe_update<<<g, RB, 0, ctx->stream>>>(n, x, r, wv, q, z, sv, p, pin, g, pout, w.st,
+                                                 k);
+      }
+      MXS_HIP_TRY(ctx, hipGetLastError());
+      if ((s = pull_state(ctx, w))) return s;
+      if (h.done == RUN && h.iters <= before)
+        return fail(ctx, MXS_HIP, "pipelined CG made no progress (device state not updated)");
+      k = h.iters;
+    }
+    if (h.done == ST_BREAKDOWN || h.done == ST_NONFINITE) {
+      s = map_done(h.done);
+      fill_info(info, h, base, relres_true, repl, 0, s);
+      return fail(ctx, s, h.done == ST_BREAKDOWN ? "pipelined CG breakdown: p.Ap <= 0"
+                                                 : "non-finite value in pipelined CG");
+    }
+    double rt2;
+    if ((s = residual(ctx, A, b, x, r))) return s;
+    if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr,
+                          &rt2, nullptr)))
+      return s;
+    relres_true = sqrt(rt2) / base;
+    if (h.done == ST_CONVERGED && sqrt(rt2) <= thr) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_OK);
+      return MXS_OK;
+    }
+    if (h.done == ST_MAXIT || repl >= stop.max_repl || h.iters >= stop.max_iters) {
+      fill_info(info, h, base, relres_true, repl, 0, MXS_NOT_CONVERGED);
+      return fail(ctx, MXS_NOT_CONVERGED,
+                  "pipelined CG stopped after %lld iterations, relres %.3e",
+                  (long long)h.iters, relres_true);
+    }
+    // residual replacement: r = b - A x (already in r), restart the recurrences
+    repl++;
+    h.res2 = rt2;
+    if ((s = restart())) return s;
+  }
+}
+
 mxs_status solve_cgs(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
                      const Stop& stop, mxs_solve_info* info) {
   const int64_t n = A->n;
@@ -1473,6 +1656,8 @@ mxs_status solve_dispatch(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, co
       return solve_bicgstab(ctx, A, b, x, read_stop(stop, 10000), info);
     case MXS_CGS:
       return solve_cgs(ctx, A, b, x, read_stop(stop, 10000), info);
+    case MXS_PIPECG:
+      return solve_pipecg(ctx, A, b, x, read_stop(stop, 20000), info);
     case MXS_GMRES:
       return solve_gmres(ctx, A, b, x, read_stop(stop, 20000),
                          opts && opts->restart > 0 ? opts->restart : 30, info);

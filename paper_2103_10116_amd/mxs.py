@@ -29,8 +29,8 @@ CSR, COO, ELL, HYB = 0, 1, 2, 3
 F64, F32, F16_ROWSCALED = 0, 1, 2
 FORMATS = {"csr": CSR, "coo": COO, "ell": ELL, "hyb": HYB}
 DTYPES = {"f64": F64, "f32": F32, "f16": F16_ROWSCALED}
-CG, BICGSTAB, GMRES, CGS = 0, 1, 2, 3
-SOLVERS = {"cg": CG, "bicgstab": BICGSTAB, "gmres": GMRES, "cgs": CGS}
+CG, BICGSTAB, GMRES, CGS, PIPECG = 0, 1, 2, 3, 4
+SOLVERS = {"cg": CG, "bicgstab": BICGSTAB, "gmres": GMRES, "cgs": CGS, "pipecg": PIPECG}
 HOST_PTRS, DEVICE_PTRS = 0, 1
 
 (ARR_ROWPTR, ARR_COL, ARR_VAL, ARR_ROW, ARR_ELL_COL, ARR_ELL_VAL,

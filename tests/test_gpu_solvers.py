@@ -227,6 +227,9 @@ def test_full_size_krylov(env, orc):
     r, x = _solve(env, P, b, "cg")
     _assert_converged(orc, P, b, x, r, 1e-10)
     assert 300 <= r.iters <= 600
+    rp_, x = _solve(env, P, b, "pipecg")
+    _assert_converged(orc, P, b, x, rp_, 1e-10)
+    assert abs(rp_.iters - r.iters) <= 10
     Cd = I.convdiff3d(128)
     b = orc.spmv_csr(Cd, I.uniform_vector(Cd.n, 29))
     r, x = _solve(env, Cd, b, "bicgstab")
@@ -427,4 +430,49 @@ def test_cgs_statuses(env, orc):
     E = I.dense_to_csr(np.eye(40) * 3.0)
     bb = I.uniform_vector(40, 52)
     r, x = _solve(env, E, bb, "cgs", tol=1e-14)
+    assert r.status == mxs.OK and r.iters == 1
+
+
+# ---------------------------------------------------------------------------
+# pipelined CG
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("fmt", ["csr", "ell", "coo"])
+def test_pipecg_poisson64(env, orc, fmt):
+    A = I.poisson2d(64)
+    b = orc.spmv_csr(A, np.ones(A.n))
+    r, x = _solve(env, A, b, "pipecg", fmt)
+    _assert_converged(orc, A, b, x, r, 1e-10)
+    ref = orc.pipecg(A, b, tol=1e-10)
+    assert ref.status == orc.OK and abs(r.iters - ref.iters) <= 2
+
+
+@pytest.mark.parametrize("n,seed", [(5, 1), (16, 2)])
+def test_pipecg_tiny_vs_lu(env, orc, n, seed):
+    Mx = I.random_spd_small(n, 10.0, seed)
+    A = I.dense_to_csr(Mx)
+    b = I.rng(seed + 80).standard_normal(n)
+    r, x = _solve(env, A, b, "pipecg", tol=1e-12)
+    assert r.status == 0 and r.iters <= n + 2
+    st, xl = orc.lu_solve(Mx, b)
+    assert np.linalg.norm(x - xl) <= 1e-9 * np.linalg.norm(xl)
+
+
+def test_pipecg_statuses(env, orc):
+    mxs, ctx, torch = env
+    D = I.dense_to_csr(np.diag([1.0, -2.0, 3.0]))
+    r, x = _solve(env, D, np.array([0.0, 1.0, 0.0]), "pipecg")
+    assert r.status == mxs.BREAKDOWN and r.iters == 0
+    A = I.poisson2d(16)
+    b = np.ones(A.n)
+    r, x = _solve(env, A, b, "pipecg", max_iters=5)
+    ref = orc.pipecg(A, b, maxit=5)
+    assert r.status == mxs.NOT_CONVERGED and r.iters == 5
+    assert abs(orc.true_relres(A, b, x) - ref.relres_true) <= 1e-9 * ref.relres_true
+    r, x = _solve(env, A, np.zeros(A.n), "pipecg")
+    assert r.status == mxs.OK and r.iters == 0 and not x.any()
+    m = 12
+    P = I.poisson2d(m)
+    s = lambda kk: np.sin(np.arange(1, m + 1) * kk * np.pi / (m + 1))
+    v = np.outer(s(5), s(3)).ravel()
+    r, x = _solve(env, P, v, "pipecg", tol=1e-12)
     assert r.status == mxs.OK and r.iters == 1
