@@ -4,8 +4,8 @@ This package wraps ``oracle.c``, a plain single-threaded FP64 C implementation
 of the operations the GPU library computes: CSR/COO/ELL/hybrid storage and
 conversions, the sparse matrix-vector product, CG, pipelined CG, BiCGSTAB,
 CGS, GMRES(m),
-Jacobi and block-Jacobi preconditioned CG, mixed-precision iterative
-refinement and a dense LU solver.  Each C function
+Jacobi and block-Jacobi preconditioned CG, PageRank by power iteration,
+mixed-precision iterative refinement and a dense LU solver.  Each C function
 cites the passage of the paper (or the textbook the paper refers to) that it
 writes out.
 
@@ -104,6 +104,7 @@ def _declare(L):
         "orc_bicgstab": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info)]),
         "orc_cgs": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info)]),
         "orc_pipecg": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info)]),
+        "orc_pagerank": (C.c_int, [_I64, _P, _P, _D, _D, _I64, _P, C.POINTER(_I64), C.POINTER(_D)]),
         "orc_gmres": (C.c_int, [_I64, _P, _P, _P, _P, _P, _I64, C.POINTER(Stop), C.POINTER(Info), _P, _I64]),
         "orc_ir": (C.c_int, [_I64, _P, _P, _P, C.c_int, _P, _P, _P, _P, _P, _D, _I64, _D, _I64, C.c_int, C.POINTER(IRInfo)]),
         "orc_ir_pc": (C.c_int, [_I64, _P, _P, _P, C.c_int, _P, _P, _P, _P, _P, _D, _I64, _D, _I64, C.c_int, C.c_int, _I64, _P, C.POINTER(IRInfo)]),
@@ -408,6 +409,18 @@ def pcg(A, b, M: Precond, x0=None, tol=1e-10, maxit=20000, abs_tol=0.0, baseline
     st = lib().orc_pcg(n, _p(rp), _p(ci), _p(v), M.kind, M.bs, _p(mv), _p(bb), _p(x),
                        C.byref(_stop(tol, maxit, abs_tol, baseline)), C.byref(info))
     return _result(st, x, info)
+
+
+def pagerank(G, damping=0.85, tol=1e-10, maxit=1000):
+    """(status, x, iters, delta) for the in-link CSR pattern of G."""
+    rp = _c(G.rowptr, np.int32)
+    ci = _c(G.col, np.int32)
+    x = np.zeros(int(G.n))
+    it = _I64()
+    dl = _D()
+    st = lib().orc_pagerank(int(G.n), _p(rp), _p(ci), float(damping), float(tol), int(maxit),
+                            _p(x), C.byref(it), C.byref(dl))
+    return st, x, it.value, dl.value
 
 
 def pipecg(A, b, x0=None, tol=1e-10, maxit=20000, abs_tol=0.0):

@@ -541,6 +541,49 @@ int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
 }
 
 /* ------------------------------------------------------------------------ */
+/* PageRank by power iteration (Page, Brin, Motwani & Winograd 1998)        */
+/* ------------------------------------------------------------------------ */
+int orc_pagerank(int64_t n, const int32_t* rowptr, const int32_t* col,
+                 double damping, double tol, int64_t max_iters, double* x,
+                 int64_t* iters, double* delta) {
+  *iters = 0;
+  *delta = 0.0;
+  if (n <= 0) return ORC_OK;
+  int64_t* d = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+  double* xn = vec(n);
+  for (int64_t k = 0; k < rowptr[n]; ++k) d[col[k]]++;
+  for (int64_t i = 0; i < n; ++i) x[i] = 1.0 / (double)n;
+  int status = ORC_NOT_CONVERGED;
+  for (int64_t it = 0; it < max_iters; ++it) {
+    double dangling = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+      if (d[i] == 0) dangling = dangling + x[i];
+    double ch = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int64_t k = rowptr[j]; k < rowptr[j + 1]; ++k)
+        s = s + x[col[k]] / (double)d[col[k]];
+      xn[j] = damping * (s + dangling / (double)n) + (1.0 - damping) / (double)n;
+      ch = ch + fabs(xn[j] - x[j]);
+    }
+    memcpy(x, xn, (size_t)n * sizeof(double));
+    *iters = it + 1;
+    *delta = ch;
+    if (!isfinite(ch)) {
+      status = ORC_NONFINITE;
+      break;
+    }
+    if (ch <= tol) {
+      status = ORC_OK;
+      break;
+    }
+  }
+  free(d);
+  free(xn);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Jacobi and block-Jacobi preconditioners, preconditioned CG               */
 /* (Saad 2003, ch. 10 and Algorithm 9.1)                                     */
 /* ------------------------------------------------------------------------ */

@@ -155,6 +155,19 @@ int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col,
             const double* val, int kind, int64_t bs, const double* minv,
             const double* b, double* x, const orc_stop* stop, orc_info* info);
 
+/* ---- PageRank (Page, Brin, Motwani & Winograd 1998) --------------------
+ * The graph is given by its in-links: row j of (rowptr, col) lists the
+ * sources i of the edges i -> j (sorted, no repeats), every edge of weight
+ * one.  With d_i the out-degree of i (its occurrences in col) and D the
+ * nodes without out-links, the power iteration from x_0 = 1/n is
+ *   x_{k+1,j} = damping * (sum_{i -> j} x_{k,i} / d_i + sum_{i in D} x_{k,i} / n)
+ *               + (1 - damping) / n
+ * until ||x_{k+1} - x_k||_1 <= tol (then x = x_{k+1}, *iters = k + 1) or
+ * max_iters steps (ORC_NOT_CONVERGED).  *delta = the last L1 change. */
+int orc_pagerank(int64_t n, const int32_t* rowptr, const int32_t* col,
+                 double damping, double tol, int64_t max_iters, double* x,
+                 int64_t* iters, double* delta);
+
 /* Mixed-precision iterative refinement: FP64 residual and update, inner CG
  * in FP32 on a low-precision copy of A.  low_kind 0: FP32 values (val32);
  * low_kind 1: FP16 values with a per-row power-of-two scale (h16, scale). */

@@ -293,3 +293,47 @@ def serving_stream(count: int, rate: float, seed: int = SERVING_SEED,
 def serving_rhs(n: int, seed: int) -> np.ndarray:
     """Right-hand side of a served system: U[-1, 1] entries."""
     return rng(seed + 7919).uniform(-1.0, 1.0, size=n)
+
+
+# ---------------------------------------------------------------------------
+# directed graphs, stored by in-links (row j lists the sources of the edges
+# i -> j, sorted and distinct), every stored value 1
+# ---------------------------------------------------------------------------
+def inlinks(n: int, src, dst) -> CSRMatrix:
+    """In-link CSR of the edge list (repeated edges and self-loops kept once)."""
+    src = np.asarray(src, np.int64)
+    dst = np.asarray(dst, np.int64)
+    key = np.unique(dst * n + src)
+    rows, cols = key // n, key % n
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    return CSRMatrix(n, n, rowptr, cols.astype(np.int32), np.ones(len(cols)))
+
+
+def cycle_graph(n: int) -> CSRMatrix:
+    i = np.arange(n)
+    return inlinks(n, i, (i + 1) % n)
+
+
+def star_graph(m: int) -> CSRMatrix:
+    """Hub 0 and leaves 1..m: every leaf links to the hub, the hub to every leaf."""
+    leaves = np.arange(1, m + 1)
+    return inlinks(m + 1, np.concatenate([leaves, np.zeros(m, np.int64)]),
+                   np.concatenate([np.zeros(m, np.int64), leaves]))
+
+
+def random_graph(n: int, p: float, seed: int) -> CSRMatrix:
+    """Each ordered pair (i, j), i != j, is an edge with probability p."""
+    g = rng(seed)
+    a = g.random((n, n)) < p
+    np.fill_diagonal(a, False)
+    src, dst = np.nonzero(a)
+    return inlinks(n, src, dst)
+
+
+def powerlaw_graph(n: int, s: float = 1.79, kmax: int = 4096, seed: int = MATRIX_SEED) -> CSRMatrix:
+    """In-degrees Zipf(s) clipped to [1, kmax] and sources uniform: the
+    power-law pattern of zipf_random read as in-links."""
+    Z = zipf_random(n, s, kmax, seed)
+    return CSRMatrix(Z.n, Z.ncols, Z.rowptr, Z.col, np.ones(Z.nnz))
