@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sections", default="probe,spmv,zipf,krylov,ir,serve,cpu")
+    ap.add_argument("--sections", default="probe,spmv,zipf,krylov,ir,pagerank,serve,cpu")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--plain-requests", type=int, default=1000)
     ap.add_argument("--grid", type=int, default=128, help="stencil grid side (128 = full size)")
@@ -446,6 +446,38 @@ def main():
             log(name, json.dumps(e))
             Qm.close()
         extra["iterative_refinement"] = irr
+
+    # ---------------- PageRank over the SpMV ----------------
+    if "pagerank" in sections:
+        prr = {}
+        for label, s_ in (("powerlaw_2p20_s1.79", 1.79), ("powerlaw_2p20_s2.0", 2.0)):
+            Gh = I.powerlaw_graph(2 ** 20, s_)
+            g = mxs.Graph(ctx, Gh)
+            xg = torch.zeros(Gh.n, dtype=torch.float64, device=dev)
+            e = {"n": Gh.n, "edges": Gh.nnz}
+            for fmt in ("csr", "coo", "hyb"):
+                op = None if fmt == "csr" else g.transition().convert(fmt, "f64")
+                mxs.pagerank(ctx, g, xg, 0.85, 1e-10, op=op)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = mxs.pagerank(ctx, g, xg, 0.85, 1e-10, op=op)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                # per step: the SpMV (format bytes, FP64) + the update (z, x
+                # read, x written, one mask byte)
+                d = (op or g.transition()).info()
+                sp = spmv_bytes(fmt, d, 8, 8)
+                step_b = sp + 25 * Gh.n
+                e[fmt] = {"iters": r.iters, "delta": r.delta, "time_s": round(t, 4),
+                          "ms_per_iter": round(t / r.iters * 1e3, 4),
+                          "GBs_model": round(step_b * r.iters / t / 1e9, 1),
+                          "bytes_per_step": step_b}
+                if op is not None:
+                    op.close()
+            prr[label] = e
+            log("pagerank", label, json.dumps(e))
+            g.close()
+        extra["pagerank"] = prr
 
     # ---------------- batched CG serving vs plain CG ----------------
     if "serve" in sections:

@@ -301,6 +301,42 @@ mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A
                         const mxs_precond* inner_precond, mxs_ir_info* info);
 
 /* ---------------------------------------------------------------------- */
+/* PageRank                                                                */
+/* ---------------------------------------------------------------------- */
+/* PageRank by power iteration over the SpMV (Page, Brin, Motwani & Winograd
+ * 1998; the paper names it beside the Krylov solvers as an SpMV-based
+ * method).  A graph is given by its in-links: row j of (rowptr, col) lists
+ * the sources i of the edges i -> j, sorted and distinct (validated as a
+ * CSR pattern; MXS_INVALID_MATRIX otherwise); every edge has weight one.
+ * mxs_graph_create counts out-degrees d_i on the GPU and stores the
+ * transition matrix T[j,i] = 1/d_i as an F64 CSR matrix
+ * (mxs_graph_transition; it may be converted to any format and passed as
+ * `op`) and the set D of nodes without out-links.  flags: MXS_HOST_PTRS or
+ * MXS_DEVICE_PTRS. */
+typedef struct mxs_graph mxs_graph;
+
+typedef struct {
+  int64_t iters;    /* power steps taken */
+  double delta;     /* ||x_k - x_{k-1}||_1 of the last step */
+  int32_t status;
+} mxs_pagerank_info;
+
+mxs_status mxs_graph_create(mxs_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr,
+                            const int32_t* col, int32_t flags, mxs_graph** out);
+mxs_status mxs_graph_destroy(mxs_graph* G);
+/* The transition matrix T owned by G (valid until mxs_graph_destroy). */
+const mxs_matrix* mxs_graph_transition(const mxs_graph* G);
+
+/* From x_0 = 1/n: x_{k+1} = damping (T x_k + m_k/n) + (1 - damping)/n with
+ * m_k = sum of x_k over D, until ||x_{k+1} - x_k||_1 <= tol (MXS_OK) or
+ * max_iters steps (0 = 1000; MXS_NOT_CONVERGED).  x: device FP64 vector of
+ * n entries (output).  op: NULL for T, else T in another format.  damping
+ * in [0, 1).  Every reduction is in fixed order (no floating-point
+ * atomics), so the result is reproducible.  Synchronises the ctx stream. */
+mxs_status mxs_pagerank(mxs_ctx* ctx, const mxs_graph* G, const mxs_matrix* op, double damping,
+                        double tol, int64_t max_iters, double* x, mxs_pagerank_info* info);
+
+/* ---------------------------------------------------------------------- */
 /* batched CG and continuous batching                                      */
 /* ---------------------------------------------------------------------- */
 /* Not in the paper: many independent SPD systems A_i x_i = b_i solved by

@@ -140,6 +140,18 @@ struct mxs_precond {
   float* m32 = nullptr;
 };
 
+// A directed graph stored by in-links with its transition matrix
+// T[j,i] = 1/d_i (d_i = out-degree of i) as an F64 CSR matrix, and the
+// nodes without out-links.
+struct mxs_graph {
+  int device = 0;
+  mxs::Allocator alloc;
+  int64_t n = 0, nnz = 0;
+  mxs_matrix* T = nullptr;
+  uint8_t* dangling = nullptr;
+  int64_t ndangling = 0;
+};
+
 namespace mxs {
 
 mxs_status fail(mxs_ctx* ctx, mxs_status s, const char* fmt, ...);
@@ -158,6 +170,11 @@ mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, con
                        const void* beta, void* y, const int32_t* skip);
 int64_t csr_partition(const int32_t* rowptr, int64_t n, int block_nnz,
                       std::vector<int32_t>& blocks, int64_t max_rows = -1);
+// validated F64 CSR matrix from host or device arrays (flags as in
+// mxs_matrix_create_csr); val == NULL gives zero values
+mxs_status create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
+                      const int32_t* rowptr, const int32_t* col, const double* val, int flags,
+                      mxs_matrix** out);
 
 }  // namespace mxs
 

@@ -487,11 +487,22 @@ mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int
                                  const int32_t* rowptr, const int32_t* col, const double* val,
                                  int flags, mxs_matrix** out) {
   if (!ctx || !out) return MXS_INVALID_ARG;
+  if (nnz > 0 && !val) return fail(ctx, MXS_INVALID_ARG, "NULL array");
+  return mxs::create_csr(ctx, nrows, ncols, nnz, rowptr, col, val, flags, out);
+}
+
+}  // extern "C"
+
+// validated CSR from host or device arrays; val == NULL gives zero values
+mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
+                           const int32_t* rowptr, const int32_t* col, const double* val,
+                           int flags, mxs_matrix** out) {
+  if (!ctx || !out) return MXS_INVALID_ARG;
   if (nrows < 0 || ncols < 0 || nnz < 0)
     return fail(ctx, MXS_INVALID_ARG, "negative size");
   if (nrows > INT32_MAX - 1 || ncols > INT32_MAX || nnz > INT32_MAX)
     return fail(ctx, MXS_UNSUPPORTED, "sizes beyond int32 indices");
-  if (!rowptr || (nnz > 0 && (!col || !val)))
+  if (!rowptr || (nnz > 0 && !col))
     return fail(ctx, MXS_INVALID_ARG, "NULL array");
   if (flags != MXS_HOST_PTRS && flags != MXS_DEVICE_PTRS)
     return fail(ctx, MXS_INVALID_ARG, "unknown flags %d", flags);
@@ -516,7 +527,8 @@ mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int
         flags == MXS_HOST_PTRS ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     if (hipMemcpyAsync(A->csr.rowptr, rowptr, (nrows + 1) * 4, kind, ctx->stream) ||
         (nnz && hipMemcpyAsync(A->csr.col, col, nnz * 4, kind, ctx->stream)) ||
-        (nnz && hipMemcpyAsync(A->csr.val, val, nnz * 8, kind, ctx->stream))) {
+        (nnz && val && hipMemcpyAsync(A->csr.val, val, nnz * 8, kind, ctx->stream)) ||
+        (nnz && !val && hipMemsetAsync(A->csr.val, 0, nnz * 8, ctx->stream))) {
       st = fail(ctx, MXS_HIP, "copying the CSR arrays failed");
       break;
     }
@@ -562,6 +574,8 @@ mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int
   *out = A;
   return MXS_OK;
 }
+
+extern "C" {
 
 mxs_status mxs_matrix_convert(mxs_ctx* ctx, const mxs_matrix* src, mxs_format fmt,
                               mxs_dtype dt, const mxs_convert_opts* opts, mxs_matrix** out) {

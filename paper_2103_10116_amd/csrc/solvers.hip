@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 
 #include "common.h"
 
@@ -907,6 +908,86 @@ __global__ __launch_bounds__(RB) void k_pcg_direction(int64_t n, const T* __rest
     const T zi = PC == 1 ? dinv[i] * r[i] : z[i];
     p[i] = zi + beta * p[i];
   }
+}
+
+// ---------------------------------------------------------------------------
+// PageRank by power iteration (Page, Brin, Motwani & Winograd 1998) over the
+// transition matrix T (T[j,i] = 1/d_i, stored by in-links).  Iteration k:
+//   z = T x (the library's SpMV, any format);
+//   k_pr_update: finishes the partials written by the previous update (or
+//   the set-up), the dangling mass m = sum of x over nodes without
+//   out-links and the L1 change of the previous step; stops on that change;
+//   x = damping (z + m/n) + (1 - damping)/n in place; partials of the new
+//   dangling mass and of |x_new - x_old|.  Partial buffers alternate.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_outdeg(int64_t nnz, const int32_t* __restrict__ col,
+                                                int32_t* __restrict__ d) {
+  // integer counts: the result does not depend on the order of the adds
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * 256)
+    atomicAdd(&d[col[k]], 1);
+}
+
+__global__ __launch_bounds__(256) void k_transition(int64_t nnz, const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ d,
+                                                    double* __restrict__ val) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * 256)
+    val[k] = 1.0 / (double)d[col[k]];
+}
+
+__global__ __launch_bounds__(256) void k_dangling(int64_t n, const int32_t* __restrict__ d,
+                                                  uint8_t* __restrict__ mask) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) mask[i] = d[i] == 0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(RB) void k_pr_init(int64_t n, double* __restrict__ x,
+                                                const uint8_t* __restrict__ mask,
+                                                double* __restrict__ pout) {
+  const double u = 1.0 / (double)n;
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    x[i] = u;
+    if (mask[i]) acc[0] += u;
+  }
+  block_partials<2>(acc, pout);
+}
+
+__global__ __launch_bounds__(RB) void k_pr_update(int64_t n, double* __restrict__ x,
+                                                  const double* __restrict__ z,
+                                                  const uint8_t* __restrict__ mask,
+                                                  double damping, const double* __restrict__ pin,
+                                                  int g, double* __restrict__ pout, KState* st,
+                                                  int64_t k) {
+  if (st->done) return;
+  double md[2];
+  finish<2>(pin, g, md);
+  const double mass = md[0], change = md[1];
+  int32_t verdict = RUN;
+  if (k > 0 && !isfinite(change))
+    verdict = ST_NONFINITE;
+  else if (k > 0 && change <= st->thr)
+    verdict = ST_CONVERGED;
+  else if (k >= st->max_iters)
+    verdict = ST_MAXIT;
+  if (lead()) {
+    if (k > 0) st->res2 = change;
+    st->iters = verdict == RUN ? k + 1 : k;  // steps taken once this one is done
+    if (verdict != RUN) st->done = verdict;
+  }
+  if (verdict != RUN) return;
+  const double nd = (double)n;
+  const double tele = (1.0 - damping) / nd;
+  const double share = mass / nd;
+  double acc[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double xn = damping * (z[i] + share) + tele;
+    acc[1] += fabs(xn - x[i]);
+    x[i] = xn;
+    if (mask[i]) acc[0] += xn;
+  }
+  block_partials<2>(acc, pout);
 }
 
 // ---------------------------------------------------------------------------
@@ -1801,6 +1882,126 @@ mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A
     return fail(ctx, MXS_INVALID_ARG, "preconditioner size differs");
   return solve_ir_impl(ctx, A64, A_low, b, x, outer, inner_rel_tol, inner_max,
                        last_step_variant, inner_precond, info);
+}
+
+mxs_status mxs_graph_create(mxs_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr,
+                            const int32_t* col, int32_t flags, mxs_graph** out) {
+  if (!ctx || !out) return MXS_INVALID_ARG;
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  mxs_graph* G = new (std::nothrow) mxs_graph();
+  if (!G) return MXS_OOM;
+  G->device = ctx->device;
+  G->alloc = ctx->alloc;
+  G->n = n;
+  G->nnz = nnz;
+  // the pattern is validated by the CSR constructor (rows ascending,
+  // sources in range, sorted and distinct) before any index is used
+  mxs_status st = create_csr(ctx, n, n, nnz, rowptr, col, nullptr, flags, &G->T);
+  if (st) {
+    delete G;
+    return st;
+  }
+  int32_t* d = (int32_t*)G->alloc.alloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  G->dangling = (uint8_t*)G->alloc.alloc((size_t)(n > 0 ? n : 1));
+  std::vector<int32_t> hd((size_t)n);
+  do {
+    if (!d || !G->dangling) {
+      st = fail(ctx, MXS_OOM, "graph set-up");
+      break;
+    }
+    if (n == 0) break;
+    if (hipMemsetAsync(d, 0, n * sizeof(int32_t), ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "memset failed");
+      break;
+    }
+    const unsigned ge = (unsigned)std::min<int64_t>((nnz + 255) / 256 + 1, 65536);
+    k_outdeg<<<ge, 256, 0, ctx->stream>>>(nnz, G->T->csr.col, d);
+    k_transition<<<ge, 256, 0, ctx->stream>>>(nnz, G->T->csr.col, d, (double*)G->T->csr.val);
+    k_dangling<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(n, d, G->dangling);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(hd.data(), d, n * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "graph set-up kernels failed");
+      break;
+    }
+    for (int32_t v : hd) G->ndangling += v == 0;
+  } while (0);
+  G->alloc.release(d);
+  if (st) {
+    mxs_graph_destroy(G);
+    return st;
+  }
+  *out = G;
+  return MXS_OK;
+}
+
+mxs_status mxs_graph_destroy(mxs_graph* G) {
+  if (!G) return MXS_OK;
+  (void)hipSetDevice(G->device);
+  if (G->T) mxs_matrix_destroy(G->T);
+  G->alloc.release(G->dangling);
+  delete G;
+  return MXS_OK;
+}
+
+const mxs_matrix* mxs_graph_transition(const mxs_graph* G) { return G ? G->T : nullptr; }
+
+mxs_status mxs_pagerank(mxs_ctx* ctx, const mxs_graph* G, const mxs_matrix* op, double damping,
+                        double tol, int64_t max_iters, double* x, mxs_pagerank_info* info) {
+  if (!ctx || !G || (G->n > 0 && !x)) return MXS_INVALID_ARG;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (!(damping >= 0.0 && damping < 1.0))
+    return fail(ctx, MXS_INVALID_ARG, "damping must lie in [0, 1)");
+  if (!(tol >= 0.0)) return fail(ctx, MXS_INVALID_ARG, "negative tolerance");
+  const mxs_matrix* T = op ? op : G->T;
+  if (T->n != G->n || T->ncols != G->n || T->dt != MXS_F64)
+    return fail(ctx, MXS_INVALID_ARG, "the operator must be the graph's F64 transition matrix");
+  const int64_t n = G->n;
+  if (n == 0) return MXS_OK;
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Work w;
+  mxs_status s = get_work(ctx, align_up((size_t)n, 64) * sizeof(double), &w);
+  if (s) return s;
+  double* z = (double*)w.vec;
+  const int g = red_grid(n);
+  KState& h = *w.hst;
+  std::memset(&h, 0, sizeof(KState));
+  h.thr = tol;
+  h.max_iters = max_iters > 0 ? max_iters : 1000;
+  if ((s = push_state(ctx, w))) return s;
+  k_pr_init<<<g, RB, 0, ctx->stream>>>(n, x, G->dangling, w.pa);
+  const double one = 1.0, zero = 0.0;
+  int64_t k = 0;
+  const int check_every = 16;
+  while (h.done == RUN) {
+    const int64_t before = k;
+    for (int it = 0; it < check_every; ++it, ++k) {
+      double* pin = (k & 1) ? w.pb : w.pa;
+      double* pout = (k & 1) ? w.pa : w.pb;
+      if ((s = launch_spmv(ctx, T, &one, x, &zero, z, &w.st->done))) return s;
+      k_pr_update<<<g, RB, 0, ctx->stream>>>(n, x, z, G->dangling, damping, pin, g, pout, w.st,
+                                             k);
+    }
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    if ((s = pull_state(ctx, w))) return s;
+    if (h.done == RUN && h.iters <= before)
+      return fail(ctx, MXS_HIP, "PageRank made no progress (device state not updated)");
+    k = h.iters;
+  }
+  const mxs_status res = h.done == ST_CONVERGED ? MXS_OK
+                         : h.done == ST_MAXIT   ? MXS_NOT_CONVERGED
+                                                : MXS_NONFINITE;
+  if (info) {
+    info->iters = h.iters;
+    info->delta = h.res2;
+    info->status = res;
+  }
+  if (res == MXS_NOT_CONVERGED)
+    return fail(ctx, res, "PageRank stopped after %lld iterations, L1 change %.3e",
+                (long long)h.iters, h.res2);
+  if (res == MXS_NONFINITE) return fail(ctx, res, "non-finite value in PageRank");
+  return MXS_OK;
 }
 
 }  // extern "C"

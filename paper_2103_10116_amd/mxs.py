@@ -69,6 +69,10 @@ class Stop(C.Structure):
                 ("max_replacements", C.c_int32)]
 
 
+class PageRankInfo(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("delta", C.c_double), ("status", C.c_int32)]
+
+
 class SolverOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("reserved", C.c_int32), ("precond", C.c_void_p)]
 
@@ -120,6 +124,11 @@ _SIGS = {
                        C.POINTER(SolveInfo)]),
     "mxs_solve_ir": (_S, [_P, _P, _P, _P, _P, C.POINTER(Stop), C.c_double, _I64, _S, _P,
                           C.POINTER(IRInfo)]),
+    "mxs_graph_create": (_S, [_P, _I64, _I64, _P, _P, _S, C.POINTER(_P)]),
+    "mxs_graph_destroy": (_S, [_P]),
+    "mxs_graph_transition": (_P, [_P]),
+    "mxs_pagerank": (_S, [_P, _P, _P, C.c_double, C.c_double, _I64, _P,
+                          C.POINTER(PageRankInfo)]),
     "mxs_precond_create": (_S, [_P, _P, _S, _S, C.POINTER(_P)]),
     "mxs_precond_destroy": (_S, [_P]),
     "mxs_precond_export": (_S, [_P, _P, _P, C.c_size_t]),
@@ -216,9 +225,11 @@ _VDT = {F64: np.float64, F32: np.float32, F16_ROWSCALED: np.uint16}
 
 
 class Matrix:
-    def __init__(self, ctx: Context, handle):
+    def __init__(self, ctx: Context, handle, owner=None):
+        """owner: the object that owns `handle` (then close() leaves it be)."""
         self.ctx = ctx
         self.handle = handle
+        self._owner = owner
         d = MatrixDesc()
         _check(_lib.mxs_matrix_info(handle, C.byref(d)), ctx)
         self.desc = d
@@ -294,7 +305,8 @@ class Matrix:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.mxs_matrix_destroy(self.handle)
+            if getattr(self, "_owner", None) is None:
+                _lib.mxs_matrix_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -302,6 +314,56 @@ class Matrix:
             self.close()
         except Exception:
             pass
+
+
+class Graph:
+    """mxs_graph_create: a directed graph by in-links (row j lists the
+    sources of the edges into j) with its transition matrix on the GPU."""
+
+    def __init__(self, ctx: Context, G):
+        rp = np.ascontiguousarray(G.rowptr, np.int32)
+        ci = np.ascontiguousarray(G.col, np.int32)
+        h = C.c_void_p()
+        _check(_lib.mxs_graph_create(ctx.handle, int(G.n), len(ci), rp.ctypes.data_as(_P),
+                                     ci.ctypes.data_as(_P), HOST_PTRS, C.byref(h)), ctx)
+        self.ctx = ctx
+        self.handle = h
+        self.n = int(G.n)
+
+    def transition(self) -> "Matrix":
+        """T (owned by the graph): convert it to run PageRank in another format."""
+        return Matrix(self.ctx, _lib.mxs_graph_transition(self.handle), owner=self)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mxs_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class PageRankResult:
+    status: int
+    iters: int
+    delta: float
+
+
+def pagerank(ctx: Context, G: Graph, x, damping=0.85, tol=1e-10, max_iters=0, op=None,
+             raise_on_error=True) -> PageRankResult:
+    """mxs_pagerank into the FP64 device vector x (n entries)."""
+    import torch
+    info = PageRankInfo()
+    s = _lib.mxs_pagerank(ctx.handle, G.handle, op.handle if op is not None else None,
+                          float(damping), float(tol), int(max_iters), _vec(x, G.n, torch.float64),
+                          C.byref(info))
+    if raise_on_error and s != OK:
+        _check(s, ctx)
+    return PageRankResult(s, info.iters, info.delta)
 
 
 PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 1, 2
