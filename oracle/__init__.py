@@ -98,6 +98,8 @@ def _declare(L):
         "orc_spmv_hyb": (None, [_I64, _I64, _I64, _P, _P, _I64, _P, _P, _P, _P, _D, _D, _P]),
         "orc_spmv_csr_f16": (None, [_I64, _P, _P, _P, _P, _P, _D, _D, _P]),
         "orc_absrow": (None, [_I64, _P, _P, _P, _P, _P]),
+        "orc_spmv_csr_z": (None, [_I64, _P, _P, _P, _P, _P, _P, _P]),
+        "orc_absrow_z": (None, [_I64, _P, _P, _P, _P, _P]),
         "orc_dense_matvec": (None, [_I64, _I64, _P, _P, _P]),
         "orc_dense_lu_solve": (C.c_int, [_I64, _P, _P, _P]),
         "orc_cg": (C.c_int, [_I64, _P, _P, _P, _P, _P, C.POINTER(Stop), C.POINTER(Info), _P, _I64]),
@@ -260,6 +262,31 @@ def spmv_csr(A, x, alpha=1.0, beta=0.0, y=None, mode="accurate"):
     out = _y(n, y, beta)
     lib().orc_spmv_csr(n, _p(rp), _p(ci), _p(v), _p(xx), alpha, beta, _p(out),
                        0 if mode == "accurate" else 1)
+    return out
+
+
+
+def spmv_csr_z(n, rowptr, col, val, x, alpha=1.0, beta=0.0, y=None):
+    """Complex CSR product; val, x, y complex128 numpy arrays."""
+    rp = _c(rowptr, np.int32)
+    ci = _c(col, np.int32)
+    v = _c(np.asarray(val, np.complex128).view(np.float64), np.float64)
+    xx = _c(np.asarray(x, np.complex128).view(np.float64), np.float64)
+    out = np.zeros(2 * n) if y is None else _c(np.asarray(y, np.complex128).view(np.float64),
+                                                np.float64).copy()
+    a = np.array([complex(alpha).real, complex(alpha).imag])
+    b = np.array([complex(beta).real, complex(beta).imag])
+    lib().orc_spmv_csr_z(int(n), _p(rp), _p(ci), _p(v), _p(xx), _p(a), _p(b), _p(out))
+    return out.view(np.complex128)
+
+
+def absrow_z(n, rowptr, col, val, x):
+    rp = _c(rowptr, np.int32)
+    ci = _c(col, np.int32)
+    v = _c(np.asarray(val, np.complex128).view(np.float64), np.float64)
+    xx = _c(np.asarray(x, np.complex128).view(np.float64), np.float64)
+    out = np.zeros(int(n))
+    lib().orc_absrow_z(int(n), _p(rp), _p(ci), _p(v), _p(xx), _p(out))
     return out
 
 

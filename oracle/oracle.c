@@ -283,6 +283,47 @@ void orc_spmv_csr(int64_t n, const int32_t* rowptr, const int32_t* col,
   }
 }
 
+void orc_spmv_csr_z(int64_t n, const int32_t* rowptr, const int32_t* col,
+                    const double* val, const double* x, const double* alpha,
+                    const double* beta, double* y) {
+  const int beta0 = beta[0] == 0.0 && beta[1] == 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    acc_t re, im;
+    acc_init(&re, 0.0);
+    acc_init(&im, 0.0);
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      const double ar = val[2 * k], ai = val[2 * k + 1];
+      const double xr = x[2 * col[k]], xi = x[2 * col[k] + 1];
+      acc_add(&re, ar, xr);
+      acc_add(&re, -ai, xi);
+      acc_add(&im, ar, xi);
+      acc_add(&im, ai, xr);
+    }
+    const double sr = acc_result(&re), si = acc_result(&im);
+    double yr = alpha[0] * sr - alpha[1] * si;
+    double yi = alpha[0] * si + alpha[1] * sr;
+    if (!beta0) {
+      const double br = beta[0], bi = beta[1];
+      const double or_ = y[2 * i], oi = y[2 * i + 1];
+      yr = yr + (br * or_ - bi * oi);
+      yi = yi + (br * oi + bi * or_);
+    }
+    y[2 * i] = yr;
+    y[2 * i + 1] = yi;
+  }
+}
+
+void orc_absrow_z(int64_t n, const int32_t* rowptr, const int32_t* col,
+                  const double* val, const double* x, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+      s = s + hypot(val[2 * k], val[2 * k + 1]) *
+                  hypot(x[2 * col[k]], x[2 * col[k] + 1]);
+    out[i] = s;
+  }
+}
+
 void orc_spmv_coo(int64_t n, int64_t nnz, const int32_t* row,
                   const int32_t* col, const double* val, const double* x,
                   double alpha, double beta, double* y) {

@@ -75,6 +75,18 @@ void orc_spmv_hyb(int64_t n, int64_t K, int64_t stride, const int32_t* ecol,
 void orc_spmv_csr_f16(int64_t n, const int32_t* rowptr, const int32_t* col,
                       const uint16_t* h, const float* scale, const double* x,
                       double alpha, double beta, double* y);
+/* Complex CSR product (the library's complex value types, named in the
+ * paper's experiment-setup footnote): val, x, y, alpha, beta hold (re, im)
+ * pairs.  Each row's real and imaginary sums are accumulated with the
+ * compensated dot product (real part: re*re and -im*im terms; imaginary
+ * part: re*im and im*re terms) and rounded once; then
+ * y = alpha s + beta y in complex arithmetic (beta == 0 never reads y).
+ * absrow_z gives sum_j |a_ij| |x_j| with complex moduli. */
+void orc_spmv_csr_z(int64_t n, const int32_t* rowptr, const int32_t* col,
+                    const double* val, const double* x, const double* alpha,
+                    const double* beta, double* y);
+void orc_absrow_z(int64_t n, const int32_t* rowptr, const int32_t* col,
+                  const double* val, const double* x, double* out);
 /* sum_j |a_ij| |x_j| per row (the scale of the per-entry error bound) */
 void orc_absrow(int64_t n, const int32_t* rowptr, const int32_t* col,
                 const double* val, const double* x, double* out);
