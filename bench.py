@@ -226,6 +226,27 @@ def main():
         out["roofline"]["measured_peak"] = round(peak_meas, 1)
         out["roofline"]["frac_measured"] = round(d["GBs"] / peak_meas, 4)
     extra["stencil27_per_kernel"] = per
+    # complex values (CSR only): the same pattern with U[-1,1] imaginary parts
+    cx = {}
+    zval = A.val + 1j * I.uniform_vector(A.nnz, I.VECTOR_SEED + 1)
+    Mz = mxs.Matrix.from_host_complex(ctx, A.n, A.ncols, A.rowptr, A.col, zval)
+    for dtz, tdt, vbz in (("c128", torch.complex128, 16), ("c64", torch.complex64, 8)):
+        Bz = Mz if dtz == "c128" else Mz.convert("csr", dtz)
+        xz = torch.from_numpy(x64 + 0.5j * x64).to(tdt).to(dev)
+        yz = torch.zeros(A.n, dtype=tdt, device=dev)
+        fn = lambda Bz=Bz, xz=xz, yz=yz: mxs.spmv(ctx, Bz, xz, yz)
+        for _ in range(args.warmup):
+            fn()
+        t, _ = timer.time(fn, max(args.steps, 10))
+        nbz = A.nnz * (vbz + 4) + 4 * (A.n + 1) + 2 * A.n * vbz
+        cx[f"csr_{dtz}"] = {"us": round(t * 1e6, 2), "GBs": round(nbz / t / 1e9, 1), "bytes": nbz,
+                            "GFLOPs": round(8 * A.nnz / t / 1e9, 1),
+                            "kernel": Bz.info()["csr_kernel"]}
+        log(f"stencil27 csr {dtz}: {t*1e6:.1f} us  {nbz/t/1e9:.0f} GB/s")
+        if Bz is not Mz:
+            Bz.close()
+    Mz.close()
+    extra["stencil27_complex"] = cx
     for k in list(mats):
         if k != ("csr", "f64"):
             mats[k].close()

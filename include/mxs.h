@@ -49,8 +49,16 @@ typedef enum { MXS_CSR = 0, MXS_COO = 1, MXS_ELL = 2, MXS_HYB = 3 } mxs_format;
 
 /* Value storage: FP64; FP32 (round to nearest even from FP64); FP16 with a
  * per-row power-of-two scale s_i = 2^ceil(log2 max_j |a_ij|) held in FP32
- * and binary16 codes of a_ij / s_i (CSR only). */
-typedef enum { MXS_F64 = 0, MXS_F32 = 1, MXS_F16_ROWSCALED = 2 } mxs_dtype;
+ * and binary16 codes of a_ij / s_i (CSR only); complex FP64 and complex
+ * FP32 as (re, im) pairs (CSR only; the library's complex value types, named
+ * in the paper's experiment-setup footnote). */
+typedef enum {
+  MXS_F64 = 0,
+  MXS_F32 = 1,
+  MXS_F16_ROWSCALED = 2,
+  MXS_C128 = 3,
+  MXS_C64 = 4
+} mxs_dtype;
 
 typedef struct mxs_ctx mxs_ctx;
 typedef struct mxs_matrix mxs_matrix;
@@ -98,6 +106,17 @@ mxs_status mxs_ctx_synchronize(mxs_ctx* ctx);
 mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
                                  const int32_t* rowptr, const int32_t* col,
                                  const double* val, int flags, mxs_matrix** out);
+
+/* The same for complex FP64 values: val holds 2*nnz doubles, (re, im) of
+ * each entry in CSR order.  The matrix has dtype MXS_C128; mxs_matrix_convert
+ * turns it into CSR MXS_C128 (other kernel options) or MXS_C64 (each part
+ * rounded to nearest even; MXS_UNSUPPORTED beyond the FP32 range).  Other
+ * formats are not offered for complex values.  mxs_spmv takes alpha, beta
+ * as host (re, im) pairs of the compute type (double or float) and x, y as
+ * device arrays of pairs. */
+mxs_status mxs_matrix_create_csr_complex(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
+                                         const int32_t* rowptr, const int32_t* col,
+                                         const double* val, int flags, mxs_matrix** out);
 
 typedef struct {
   int64_t ell_width;      /* ELL: 0 = max row length; HYB: 0 = byte-model width, else forced K */

@@ -160,7 +160,7 @@ bool ws_reserve(mxs_ctx* ctx, size_t bytes);
 bool pinned_reserve(mxs_ctx* ctx, size_t bytes);
 
 inline size_t value_bytes(mxs_dtype dt) {
-  return dt == MXS_F64 ? 8 : dt == MXS_F32 ? 4 : 2;
+  return dt == MXS_C128 ? 16 : (dt == MXS_F64 || dt == MXS_C64) ? 8 : dt == MXS_F32 ? 4 : 2;
 }
 
 // launchers shared between translation units (all enqueue on ctx->stream)
@@ -170,11 +170,11 @@ mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, con
                        const void* beta, void* y, const int32_t* skip);
 int64_t csr_partition(const int32_t* rowptr, int64_t n, int block_nnz,
                       std::vector<int32_t>& blocks, int64_t max_rows = -1);
-// validated F64 CSR matrix from host or device arrays (flags as in
-// mxs_matrix_create_csr); val == NULL gives zero values
+// validated F64 (or C128) CSR matrix from host or device arrays (flags as
+// in mxs_matrix_create_csr); val == NULL gives zero values
 mxs_status create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
                       const int32_t* rowptr, const int32_t* col, const double* val, int flags,
-                      mxs_matrix** out);
+                      mxs_matrix** out, mxs_dtype dt = MXS_F64);
 
 }  // namespace mxs
 
@@ -223,5 +223,60 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* BS/64 entries */) {
 __device__ __forceinline__ double to_acc(double v) { return v; }
 __device__ __forceinline__ float to_acc(float v) { return v; }
 __device__ __forceinline__ float to_acc(_Float16 v) { return (float)v; }
+
+// Complex values as (re, im) pairs; the CSR kernels are instantiated with
+// it as value and vector type.
+template <typename R>
+struct cplx {
+  R re, im;
+  cplx() = default;
+  __host__ __device__ constexpr cplx(R r) : re(r), im(0) {}
+  __host__ __device__ constexpr cplx(R r, R i) : re(r), im(i) {}
+};
+template <typename R>
+__device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> operator*(cplx<R> a, cplx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cplx<R>& operator+=(cplx<R>& a, cplx<R> b) {
+  a = a + b;
+  return a;
+}
+template <typename R>
+__device__ __forceinline__ cplx<R>& operator*=(cplx<R>& a, cplx<R> b) {
+  a = a * b;
+  return a;
+}
+template <typename R>
+__device__ __forceinline__ bool operator==(cplx<R> a, cplx<R> b) {
+  return a.re == b.re && a.im == b.im;
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> to_acc(cplx<R> v) {
+  return v;
+}
+
+// Lane exchanges of complex values, part by part.  The built-in overloads
+// are brought into this namespace so that these do not hide them; templates
+// reach these through argument-dependent lookup.
+using ::__shfl;
+using ::__shfl_up;
+using ::__shfl_xor;
+template <typename R>
+__device__ __forceinline__ cplx<R> __shfl(cplx<R> v, int src, int width) {
+  return {::__shfl(v.re, src, width), ::__shfl(v.im, src, width)};
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> __shfl_up(cplx<R> v, unsigned int d, int width) {
+  return {::__shfl_up(v.re, d, width), ::__shfl_up(v.im, d, width)};
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> __shfl_xor(cplx<R> v, int m, int width) {
+  return {::__shfl_xor(v.re, m, width), ::__shfl_xor(v.im, m, width)};
+}
 
 }  // namespace mxs

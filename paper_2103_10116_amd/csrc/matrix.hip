@@ -294,9 +294,9 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
   // layout gathers x with more cache lines per instruction on stencils.)
   int kind_eff = kind;
   if (kind == MXS_CSR_AUTO)
-    kind_eff = maxL > 64                           ? MXS_CSR_STREAM
-               : (A->dt == MXS_F64 && maxL > 16) ? MXS_CSR_PRODUCTS
-                                                 : MXS_CSR_ROWS_LDS;
+    kind_eff = maxL > 64 ? MXS_CSR_STREAM
+               : ((A->dt == MXS_F64 || A->dt == MXS_C128) && maxL > 16) ? MXS_CSR_PRODUCTS
+                                                                        : MXS_CSR_ROWS_LDS;
   bool vec = kind_eff == MXS_CSR_VECTOR;
   A->csr.lanes = vec ? G : 0;
   A->csr.wpb = (opts && opts->waves_per_group == 1) ? 1 : 4;
@@ -491,12 +491,21 @@ mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int
   return mxs::create_csr(ctx, nrows, ncols, nnz, rowptr, col, val, flags, out);
 }
 
+mxs_status mxs_matrix_create_csr_complex(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
+                                         const int32_t* rowptr, const int32_t* col,
+                                         const double* val, int flags, mxs_matrix** out) {
+  if (!ctx || !out) return MXS_INVALID_ARG;
+  if (nnz > 0 && !val) return fail(ctx, MXS_INVALID_ARG, "NULL array");
+  return mxs::create_csr(ctx, nrows, ncols, nnz, rowptr, col, val, flags, out, MXS_C128);
+}
+
 }  // extern "C"
 
 // validated CSR from host or device arrays; val == NULL gives zero values
 mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
                            const int32_t* rowptr, const int32_t* col, const double* val,
-                           int flags, mxs_matrix** out) {
+                           int flags, mxs_matrix** out, mxs_dtype dt) {
+  const size_t vb = dt == MXS_C128 ? 16 : 8;
   if (!ctx || !out) return MXS_INVALID_ARG;
   if (nrows < 0 || ncols < 0 || nnz < 0)
     return fail(ctx, MXS_INVALID_ARG, "negative size");
@@ -513,12 +522,12 @@ mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t n
   A->ncols = ncols;
   A->nnz = nnz;
   A->fmt = MXS_CSR;
-  A->dt = MXS_F64;
+  A->dt = dt;
   mxs_status st = MXS_OK;
   do {
     A->csr.rowptr = (int32_t*)mat_alloc(A, (nrows + 1) * 4);
     A->csr.col = (int32_t*)mat_alloc(A, nnz * 4 + 4);
-    A->csr.val = mat_alloc(A, nnz * 8 + 8);
+    A->csr.val = mat_alloc(A, nnz * vb + 16);
     if (!A->csr.rowptr || !A->csr.col || !A->csr.val || !ws_reserve(ctx, 256)) {
       st = fail(ctx, MXS_OOM, "cannot allocate CSR arrays (%lld entries)", (long long)nnz);
       break;
@@ -527,8 +536,8 @@ mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t n
         flags == MXS_HOST_PTRS ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     if (hipMemcpyAsync(A->csr.rowptr, rowptr, (nrows + 1) * 4, kind, ctx->stream) ||
         (nnz && hipMemcpyAsync(A->csr.col, col, nnz * 4, kind, ctx->stream)) ||
-        (nnz && val && hipMemcpyAsync(A->csr.val, val, nnz * 8, kind, ctx->stream)) ||
-        (nnz && !val && hipMemsetAsync(A->csr.val, 0, nnz * 8, ctx->stream))) {
+        (nnz && val && hipMemcpyAsync(A->csr.val, val, nnz * vb, kind, ctx->stream)) ||
+        (nnz && !val && hipMemsetAsync(A->csr.val, 0, nnz * vb, ctx->stream))) {
       st = fail(ctx, MXS_HIP, "copying the CSR arrays failed");
       break;
     }
@@ -575,15 +584,83 @@ mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t n
   return MXS_OK;
 }
 
+namespace mxs {
+namespace {
+
+// complex CSR to complex CSR: the same pattern, values copied (C128) or
+// each part rounded to FP32 (C64), a partition for the new options
+mxs_status convert_complex(mxs_ctx* ctx, const mxs_matrix* src, mxs_dtype dt,
+                           const mxs_convert_opts* opts, mxs_matrix** out) {
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (!ws_reserve(ctx, 256)) return fail(ctx, MXS_OOM, "workspace");
+  mxs_matrix* A = new_matrix(ctx);
+  if (!A) return MXS_OOM;
+  const int64_t n = src->n, nnz = src->nnz;
+  A->n = n;
+  A->ncols = src->ncols;
+  A->nnz = nnz;
+  A->fmt = MXS_CSR;
+  A->dt = dt;
+  int* d_err = (int*)ctx->ws.ptr;
+  mxs_status st = MXS_OK;
+  do {
+    A->csr.rowptr = (int32_t*)mat_alloc(A, (n + 1) * 4);
+    A->csr.col = (int32_t*)mat_alloc(A, nnz * 4 + 4);
+    A->csr.val = mat_alloc(A, nnz * value_bytes(dt) + 16);
+    if (!A->csr.rowptr || !A->csr.col || !A->csr.val) {
+      st = fail(ctx, MXS_OOM, "complex csr arrays");
+      break;
+    }
+    if (hipMemsetAsync(d_err, 0, sizeof(int), ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(A->csr.rowptr, src->csr.rowptr, (n + 1) * 4, hipMemcpyDeviceToDevice,
+                       ctx->stream) != hipSuccess ||
+        (nnz && hipMemcpyAsync(A->csr.col, src->csr.col, nnz * 4, hipMemcpyDeviceToDevice,
+                               ctx->stream) != hipSuccess)) {
+      st = fail(ctx, MXS_HIP, "copy failed");
+      break;
+    }
+    // (re, im) pairs are 2 nnz doubles: the elementwise casts apply as is
+    st = dt == MXS_C128
+             ? cast_into<double>(ctx, 2 * nnz, (const double*)src->csr.val, A->csr.val, d_err)
+             : cast_into<float>(ctx, 2 * nnz, (const double*)src->csr.val, A->csr.val, d_err);
+    if (st) break;
+    int err = 0;
+    if ((st = read_err(ctx, d_err, &err))) break;
+    if (err & kErrRange) {
+      st = fail(ctx, MXS_UNSUPPORTED, "a value exceeds the FP32 range");
+      break;
+    }
+    A->h_rowptr = src->h_rowptr;
+    st = build_csr_partition(ctx, A, clamp_block_nnz(opts ? opts->block_nnz : 0), opts);
+  } while (0);
+  if (st) {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_matrix(A);
+    return st;
+  }
+  *out = A;
+  return MXS_OK;
+}
+
+}  // namespace
+}  // namespace mxs
+
 extern "C" {
 
 mxs_status mxs_matrix_convert(mxs_ctx* ctx, const mxs_matrix* src, mxs_format fmt,
                               mxs_dtype dt, const mxs_convert_opts* opts, mxs_matrix** out) {
   if (!ctx || !src || !out) return MXS_INVALID_ARG;
-  if (src->fmt != MXS_CSR || src->dt != MXS_F64)
-    return fail(ctx, MXS_UNSUPPORTED, "conversion source must be an F64 CSR matrix");
-  if (fmt < MXS_CSR || fmt > MXS_HYB || dt < MXS_F64 || dt > MXS_F16_ROWSCALED)
+  if (fmt < MXS_CSR || fmt > MXS_HYB || dt < MXS_F64 || dt > MXS_C64)
     return fail(ctx, MXS_INVALID_ARG, "unknown format or dtype");
+  if (src->fmt == MXS_CSR && src->dt == MXS_C128) {
+    if (fmt != MXS_CSR || (dt != MXS_C128 && dt != MXS_C64))
+      return fail(ctx, MXS_UNSUPPORTED, "complex values convert to complex CSR only");
+    return convert_complex(ctx, src, dt, opts, out);
+  }
+  if (src->fmt != MXS_CSR || src->dt != MXS_F64)
+    return fail(ctx, MXS_UNSUPPORTED, "conversion source must be an F64 or C128 CSR matrix");
+  if (dt > MXS_F16_ROWSCALED)
+    return fail(ctx, MXS_UNSUPPORTED, "real values convert to real types only");
   if (dt == MXS_F16_ROWSCALED && fmt != MXS_CSR)
     return fail(ctx, MXS_UNSUPPORTED, "F16_ROWSCALED is offered for CSR only");
   MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));

@@ -876,6 +876,14 @@ mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, con
   } else if (A->dt == MXS_F32) {
     launch_typed<float, float, false>(ctx, A, *(const float*)alpha, (const float*)x,
                                       *(const float*)beta, (float*)y, skip);
+  } else if (A->dt == MXS_C128) {
+    using Z = cplx<double>;
+    if (A->fmt != MXS_CSR) return fail(ctx, MXS_UNSUPPORTED, "complex values are CSR only");
+    launch_csr<Z, Z, false>(ctx, A, *(const Z*)alpha, (const Z*)x, *(const Z*)beta, (Z*)y, skip);
+  } else if (A->dt == MXS_C64) {
+    using Z = cplx<float>;
+    if (A->fmt != MXS_CSR) return fail(ctx, MXS_UNSUPPORTED, "complex values are CSR only");
+    launch_csr<Z, Z, false>(ctx, A, *(const Z*)alpha, (const Z*)x, *(const Z*)beta, (Z*)y, skip);
   } else {
     launch_typed<_Float16, float, true>(ctx, A, *(const float*)alpha, (const float*)x,
                                         *(const float*)beta, (float*)y, skip);

@@ -26,9 +26,9 @@ OK, INVALID_ARG, INVALID_MATRIX, UNSUPPORTED, OOM, HIP = 0, 1, 2, 3, 4, 5
 NOT_CONVERGED, BREAKDOWN, NONFINITE, BUDGET, PENDING = 6, 7, 8, 9, 10
 
 CSR, COO, ELL, HYB = 0, 1, 2, 3
-F64, F32, F16_ROWSCALED = 0, 1, 2
+F64, F32, F16_ROWSCALED, C128, C64 = 0, 1, 2, 3, 4
 FORMATS = {"csr": CSR, "coo": COO, "ell": ELL, "hyb": HYB}
-DTYPES = {"f64": F64, "f32": F32, "f16": F16_ROWSCALED}
+DTYPES = {"f64": F64, "f32": F32, "f16": F16_ROWSCALED, "c128": C128, "c64": C64}
 CG, BICGSTAB, GMRES, CGS, PIPECG = 0, 1, 2, 3, 4
 SOLVERS = {"cg": CG, "bicgstab": BICGSTAB, "gmres": GMRES, "cgs": CGS, "pipecg": PIPECG}
 HOST_PTRS, DEVICE_PTRS = 0, 1
@@ -119,6 +119,8 @@ _SIGS = {
     "mxs_matrix_info": (_S, [_P, C.POINTER(MatrixDesc)]),
     "mxs_matrix_export": (_S, [_P, _P, C.c_int, _P, C.c_size_t]),
     "mxs_matrix_destroy": (_S, [_P]),
+    "mxs_matrix_create_csr_complex": (_S, [_P, _I64, _I64, _I64, _P, _P, _P, C.c_int,
+                                           C.POINTER(_P)]),
     "mxs_spmv": (_S, [_P, _P, _P, _P, _P, _P]),
     "mxs_solve": (_S, [_P, C.c_int, _P, _P, _P, C.POINTER(Stop), C.POINTER(SolverOpts),
                        C.POINTER(SolveInfo)]),
@@ -221,7 +223,8 @@ class Context:
 # ---------------------------------------------------------------------------
 # matrices
 # ---------------------------------------------------------------------------
-_VDT = {F64: np.float64, F32: np.float32, F16_ROWSCALED: np.uint16}
+_VDT = {F64: np.float64, F32: np.float32, F16_ROWSCALED: np.uint16, C128: np.complex128,
+        C64: np.complex64}
 
 
 class Matrix:
@@ -261,6 +264,19 @@ class Matrix:
     def from_host(cls, ctx: Context, A) -> "Matrix":
         """From any object with n, ncols, rowptr, col, val (numpy)."""
         return cls.from_csr(ctx, A.n, A.ncols, A.rowptr, A.col, A.val)
+
+    @classmethod
+    def from_host_complex(cls, ctx: Context, n, ncols, rowptr, col, val) -> "Matrix":
+        """mxs_matrix_create_csr_complex from host numpy arrays (val complex)."""
+        rp = np.ascontiguousarray(rowptr, np.int32)
+        ci = np.ascontiguousarray(col, np.int32)
+        v = np.ascontiguousarray(np.asarray(val, np.complex128))
+        h = C.c_void_p()
+        _check(_lib.mxs_matrix_create_csr_complex(ctx.handle, int(n), int(ncols), len(ci),
+                                                  rp.ctypes.data_as(_P), ci.ctypes.data_as(_P),
+                                                  v.ctypes.data_as(_P), HOST_PTRS, C.byref(h)),
+               ctx)
+        return cls(ctx, h)
 
     def convert(self, fmt="csr", dtype="f64", ell_width=0, max_ell_bytes=0,
                 block_nnz=0, csr_kernel="auto", lanes_per_row=0,
@@ -418,13 +434,19 @@ def _vec(t, n, want):
 
 def _compute_dtype(A: Matrix):
     import torch
-    return torch.float64 if A.dtype == F64 else torch.float32
+    return {F64: torch.float64, C128: torch.complex128,
+            C64: torch.complex64}.get(A.dtype, torch.float32)
 
 
 def spmv(ctx: Context, A: Matrix, x, y, alpha=1.0, beta=0.0):
     """mxs_spmv: y = alpha*A*x + beta*y (asynchronous on the ctx stream)."""
-    ct = C.c_double if A.dtype == F64 else C.c_float
-    a, b = ct(alpha), ct(beta)
+    if A.dtype in (C128, C64):
+        ct = C.c_double if A.dtype == C128 else C.c_float
+        a = (ct * 2)(complex(alpha).real, complex(alpha).imag)
+        b = (ct * 2)(complex(beta).real, complex(beta).imag)
+    else:
+        ct = C.c_double if A.dtype == F64 else C.c_float
+        a, b = ct(alpha), ct(beta)
     dt = _compute_dtype(A)
     _check(_lib.mxs_spmv(ctx.handle, C.byref(a), A.handle, _vec(x, A.desc.ncols, dt),
                          C.byref(b), _vec(y, A.n, dt)), ctx)
