@@ -846,6 +846,76 @@ mxs_status upload_desc(mxs_batch* B) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// one system through the batched kernel (the single-system solver's path for
+// small matrices): a one-slot descriptor in device scratch, one work-group
+// of 1024 threads, up to 1024 iterations per launch
+// ---------------------------------------------------------------------------
+constexpr int kSmallBlock = 1024;
+
+bool small_cg_fits(int64_t n, int64_t max_row) { return n >= 1 && n <= 8192 && max_row <= 64; }
+
+size_t small_cg_scratch(int64_t n) { return 2 * kAlign + 2 * up((size_t)n * sizeof(double)); }
+
+mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double* out,
+                    double tol, int64_t max_iters, void* scratch, SmallCgResult* res) {
+  const int64_t n = A->n;
+  char* base = (char*)scratch;
+  SlotDesc* d_desc = (SlotDesc*)base;
+  SlotState* d_state = (SlotState*)(base + kAlign);
+  double* r = (double*)(base + 2 * kAlign);
+  double* p = (double*)(base + 2 * kAlign + up((size_t)n * sizeof(double)));
+  SlotDesc hd;
+  std::memset(&hd, 0, sizeof(hd));
+  hd.rowptr = A->csr.rowptr;
+  hd.col = A->csr.col;
+  hd.val = (double*)A->csr.val;
+  hd.b = const_cast<double*>(rhs);
+  hd.x = out;
+  hd.r = r;
+  hd.p = p;
+  hd.xout = out;
+  hd.tol = tol;
+  hd.n = (int32_t)n;
+  hd.nnz = (int32_t)A->nnz;
+  hd.max_iters = (int32_t)std::min<int64_t>(max_iters, INT32_MAX);
+  hd.active = 1;
+  hd.gen = 1;
+  ClassCfg C{};
+  C.max_n = (int)n;
+  C.block = kSmallBlock;
+  C.rpt = rpt_for(C.max_n, C.block);
+  C.lds = true;
+  const size_t lds = class_lds(C);
+  BatchKernel k = pick(true, 0, C.block, C.rpt);
+  if (lds > 65536) {
+    MXS_HIP_TRY(ctx, hipFuncSetAttribute((const void*)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(d_desc, &hd, sizeof(hd), hipMemcpyHostToDevice, ctx->stream));
+  MXS_HIP_TRY(ctx, hipMemsetAsync(d_state, 0, sizeof(SlotState), ctx->stream));
+  SlotState hs;
+  std::memset(&hs, 0, sizeof(hs));
+  for (;;) {
+    hipLaunchKernelGGL(k, dim3(1), dim3(C.block), lds, ctx->stream, d_desc, d_state, 0, 1024,
+                       C.max_n);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(&hs, d_state, sizeof(hs), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (hs.status >= SLOT_CONVERGED) break;
+  }
+  res->iters = hs.iters;
+  res->replacements = hs.repl;
+  res->res2 = hs.res2;
+  res->status = hs.status == SLOT_CONVERGED   ? MXS_OK
+                : hs.status == SLOT_BREAKDOWN ? MXS_BREAKDOWN
+                : hs.status == SLOT_NONFINITE ? MXS_NONFINITE
+                                              : MXS_NOT_CONVERGED;
+  return MXS_OK;
+}
+
 }  // namespace mxs
 
 using namespace mxs;

@@ -170,6 +170,20 @@ mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, con
                        const void* beta, void* y, const int32_t* skip);
 int64_t csr_partition(const int32_t* rowptr, int64_t n, int block_nnz,
                       std::vector<int32_t>& blocks, int64_t max_rows = -1);
+// Small systems (n <= 8192, rows of <= 64 entries): CG by the batched
+// engine's one-work-group kernel on one slot; solves A d = rhs from d = 0
+// to ||rhs - A d|| <= tol ||rhs|| (true residual checked, up to three
+// replacements); scratch of small_cg_scratch(n) device bytes.
+struct SmallCgResult {
+  int64_t iters = 0, replacements = 0;
+  double res2 = 0.0;   // last squared residual norm (true one when converged)
+  mxs_status status = MXS_OK;
+};
+bool small_cg_fits(int64_t n, int64_t max_row);
+size_t small_cg_scratch(int64_t n);
+mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double* out,
+                    double tol, int64_t max_iters, void* scratch, SmallCgResult* res);
+
 // validated F64 (or C128) CSR matrix from host or device arrays (flags as
 // in mxs_matrix_create_csr); val == NULL gives zero values
 mxs_status create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,

@@ -591,6 +591,12 @@ __global__ __launch_bounds__(RB) void k_ir_scale(int64_t n, const double* __rest
   GRID_STRIDE(i, n) f[i] = (float)(r[i] / sigma);
 }
 
+// x += d
+__global__ __launch_bounds__(RB) void k_add(int64_t n, double* __restrict__ x,
+                                            const double* __restrict__ d) {
+  GRID_STRIDE(i, n) x[i] += d[i];
+}
+
 // x += sigma * double(d)
 __global__ __launch_bounds__(RB) void k_ir_update(int64_t n, double* __restrict__ x,
                                                   const float* __restrict__ d, double sigma) {
@@ -1150,12 +1156,22 @@ mxs_status zero_solution(mxs_ctx* ctx, double* x, int64_t n, mxs_solve_info* inf
   return MXS_OK;
 }
 
+bool small_path(const mxs_matrix* A, const Stop& stop) {
+  if (A->fmt != MXS_CSR || A->dt != MXS_F64 || stop.max_repl != 3 || A->n > 8192) return false;
+  int64_t maxL = 0;
+  for (int64_t i = 0; i < A->n; ++i)
+    maxL = std::max<int64_t>(maxL, A->h_rowptr[i + 1] - A->h_rowptr[i]);
+  return small_cg_fits(A->n, maxL);
+}
+
 mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
                     const Stop& stop, mxs_solve_info* info) {
   const int64_t n = A->n;
   const size_t ld = align_up((size_t)n, 64);
+  const bool small = small_path(A, stop);
   Work w;
-  mxs_status s = get_work(ctx, 3 * ld * sizeof(double), &w);
+  mxs_status s = get_work(
+      ctx, 3 * ld * sizeof(double) + (small ? ld * sizeof(double) + small_cg_scratch(n) : 0), &w);
   if (s) return s;
   double* r = (double*)w.vec;
   double* p = r + ld;
@@ -1170,6 +1186,30 @@ mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* 
   const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
   const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
   KState& h = *w.hst;
+  if (small && nr0 > thr) {
+    // one work-group runs every iteration: A d = r0 from d = 0, then x += d
+    double* d = q + ld;
+    SmallCgResult sr;
+    if ((s = small_cg(ctx, A, r, d, thr / nr0, stop.max_iters, d + ld, &sr))) return s;
+    k_add<<<red_grid(n), RB, 0, ctx->stream>>>(n, x, d);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    double rt2;
+    if ((s = residual(ctx, A, b, x, r))) return s;
+    if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr,
+                          &rt2, nullptr)))
+      return s;
+    std::memset(&h, 0, sizeof(KState));
+    h.iters = sr.iters;
+    h.res2 = sr.res2;
+    mxs_status st = sr.status;
+    if (st == MXS_OK && !(sqrt(rt2) <= thr)) st = MXS_NOT_CONVERGED;
+    fill_info(info, h, base, sqrt(rt2) / base, sr.replacements, 0, st);
+    if (st == MXS_OK) return MXS_OK;
+    return fail(ctx, st, st == MXS_BREAKDOWN   ? "CG breakdown: p.Ap <= 0 (matrix not SPD)"
+                         : st == MXS_NONFINITE ? "non-finite value in CG"
+                                               : "CG stopped after %lld iterations, relres %.3e",
+                (long long)sr.iters, sqrt(rt2) / base);
+  }
   std::memset(&h, 0, sizeof(KState));
   h.rho[0] = nr2;
   h.res2 = nr2;
