@@ -2,8 +2,9 @@
 
 * Batched CG: for each size class, the threads per system (128 ... 1024)
   that solves a batch of systems of that class fastest.
-* SpMV: for a CSR matrix, the kernel (row-block stream or lanes-per-row
-  vector) and its work-unit shape with the shortest product.
+* SpMV: for a CSR matrix, the kernel (row-block stream, lanes-per-row
+  vector, thread per row, rows from LDS or products through LDS) and its
+  work-unit shape with the shortest product.
 
 Results are cached as JSON keyed by the device name and the problem
 signature, so a configuration depends only on the inputs' sizes, never on
@@ -68,7 +69,8 @@ def tune_batch_classes(ctx, bounds=CLASS_BOUNDS, per_class=128, tol=1e-10, cache
                 continue
             classes = [(b_, blk if b_ == mx else 256, per_class if b_ == mx else 1)
                        for b_ in bounds]
-            B = mxs.Batch(ctx, 4 << 30, sum(c[2] for c in classes), 32, classes)
+            B = mxs.Batch(ctx, 1 << 30, sum(c[2] for c in classes), 32, classes,
+                          staging_bytes=64 << 20)
             for A, b in zip(systems, rhs):
                 B.submit(A, b, tol)
             t0 = time.perf_counter()
@@ -92,7 +94,10 @@ def tune_batch_classes(ctx, bounds=CLASS_BOUNDS, per_class=128, tol=1e-10, cache
 
 CSR_CANDIDATES = ([dict(csr_kernel="stream", block_nnz=b) for b in (256, 512, 1024)] +
                   [dict(csr_kernel="vector", lanes_per_row=g, rows_per_group=r)
-                   for g in (4, 8, 16, 32) for r in (4, 8)])
+                   for g in (4, 8, 16, 32) for r in (4, 8)] +
+                  [dict(csr_kernel="vector", lanes_per_row=1)] +
+                  [dict(csr_kernel=k, block_nnz=b) for k in ("rows_lds", "products")
+                   for b in (512, 1024)])
 
 
 def tune_spmv(ctx, M, dtype="f64", reps=20, cache=DEFAULT_CACHE, signature=None, refresh=False,

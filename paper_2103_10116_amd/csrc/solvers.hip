@@ -1,15 +1,17 @@
 // solvers.hip -- fused BLAS-1 reduction kernels and the Krylov solver
-// drivers (CG, BiCGSTAB, restarted GMRES) plus mixed-precision iterative
-// refinement, all on the GPU.
+// drivers (CG, preconditioned CG, pipelined CG, BiCGSTAB, CGS, restarted
+// GMRES), mixed-precision iterative refinement and PageRank, all on the GPU.
 //
-// The paper names CG, BiCGSTAB and GMRES as the solvers built on SpMV (its
-// section "Central Sparse Linear Algebra Functionality"; textbook forms in
-// Saad 2003 and Saad & Schultz 1986) and runs them in its "Krylov Solver
-// Performance Analysis" subsection.  Design for one MI355X:
+// The paper names CG, BiCGSTAB, CGS and GMRES as the solvers built on SpMV,
+// and PageRank's power iteration beside them (its section "Central Sparse
+// Linear Algebra Functionality"; textbook forms in Saad 2003 and Saad &
+// Schultz 1986), and runs the solvers in its "Krylov Solver Performance
+// Analysis" subsection.  Design for one MI355X:
 //  * every scalar of the recurrences (rho, alpha, beta, omega, the Hessenberg
-//    column, Givens rotations) lives in device memory and is produced by the
-//    last block of the reduction kernel that computes it, so an iteration
-//    never waits for the host;
+//    column, Givens rotations) lives in device memory: a reduction kernel's
+//    blocks write partial sums and the next kernel's blocks (or a one-block
+//    finishing kernel) add them in block order, so an iteration never waits
+//    for the host and needs no device-scope fence;
 //  * a device status word stops all queued work once the solver converged
 //    or broke down: the host enqueues `check_every` iterations, then reads
 //    the status once (pinned memory);
