@@ -67,7 +67,9 @@ __global__ __launch_bounds__(64 * WPB) void k_csr(int64_t nblocks,
   __shared__ T prod_all[WPB][C + C / 32];
   __shared__ int32_t rp_all[WPB][C + 1];
   if (skip && *skip) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // wave-uniform (scalar block-bound loads)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   T* prod = prod_all[wv];
   int32_t* rp = rp_all[wv];
   const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
@@ -100,7 +102,6 @@ __global__ __launch_bounds__(64 * WPB) void k_csr(int64_t nblocks,
     return;
   }
 
-  for (int i = lane; i <= nr; i += 64) rp[i] = rowptr[r0 + i] - s;
   {
     int32_t c[NPL];
     T v[NPL];
@@ -114,12 +115,19 @@ __global__ __launch_bounds__(64 * WPB) void k_csr(int64_t nblocks,
         v[t] = to_acc(val[s + k]);
       }
     }
+    // gathers issued for every slot (column 0 where the block has ended,
+    // so all of them are in flight together); the product of an unused
+    // slot is discarded, never stored
+    T g[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) g[t] = x[c[t]];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const int k = t * 64 + lane;
-      if (k < len) prod[pad(k)] = v[t] * x[c[t]];
+      if (k < len) prod[pad(k)] = v[t] * g[t];
     }
   }
+  for (int i = lane; i <= nr; i += 64) rp[i] = rowptr[r0 + i] - s;
   wave_sync();
 
   for (int i = lane; i < nr; i += 64)
@@ -276,7 +284,9 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
   __shared__ V vl_all[WPB][CMAX];
   __shared__ int32_t cl_all[WPB][CMAX];
   if (skip && *skip) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // wave-uniform (scalar block-bound loads)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   V* vl = vl_all[wv];
   int32_t* cl = cl_all[wv];
   const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
@@ -304,8 +314,10 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
     }
     return;
   }
-  const int32_t ra = lane < nr ? rowptr[r0 + lane] - s : 0;
-  const int32_t rb = lane < nr ? rowptr[r0 + lane + 1] - s : 0;
+  // row bounds of lane `lane` (an empty range at len for lanes past the
+  // block): loaded unconditionally so that their wait can be deferred
+  const int32_t ra = rowptr[r0 + (lane < nr ? lane : nr)] - s;
+  const int32_t rb = rowptr[r0 + (lane < nr ? lane + 1 : nr)] - s;
   // coalesced copy into LDS, eight loads per lane in flight per round
   for (int base = 0; base < len; base += 8 * 64) {
     int32_t c[8];
@@ -366,7 +378,9 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_pr(int64_t nblocks,
                                                      const int32_t* __restrict__ skip) {
   __shared__ T pl_all[WPB][CMAX];
   if (skip && *skip) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // wave-uniform (scalar block-bound loads)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   T* pl = pl_all[wv];
   const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
   if (b >= nblocks) return;
@@ -393,8 +407,10 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_pr(int64_t nblocks,
     }
     return;
   }
-  const int32_t ra = lane < nr ? rowptr[r0 + lane] - s : 0;
-  const int32_t rb = lane < nr ? rowptr[r0 + lane + 1] - s : 0;
+  // row bounds of lane `lane` (an empty range at len for lanes past the
+  // block): loaded unconditionally so that their wait can be deferred
+  const int32_t ra = rowptr[r0 + (lane < nr ? lane : nr)] - s;
+  const int32_t rb = rowptr[r0 + (lane < nr ? lane + 1 : nr)] - s;
   // products, eight entries per lane in flight per round
   for (int base = 0; base < len; base += 8 * 64) {
     int32_t c[8];
@@ -409,10 +425,15 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_pr(int64_t nblocks,
         v[t] = to_acc(val[s + k]);
       }
     }
+    // every gather in flight together (column 0 for unused slots, whose
+    // products are discarded)
+    T g[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) g[t] = x[c[t]];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int k = base + t * 64 + lane;
-      if (k < len) pl[k] = v[t] * x[c[t]];
+      if (k < len) pl[k] = v[t] * g[t];
     }
   }
   wave_sync();
@@ -485,7 +506,9 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
   __shared__ T prod_all[WPB][C + C / 32];
   __shared__ int32_t rw_all[WPB][C + C / 32];
   __shared__ int32_t edge_all[WPB][2];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // wave-uniform (scalar block-bound loads)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   T* prod = prod_all[wv];
   int32_t* rw = rw_all[wv];
   int32_t* edge = edge_all[wv];
@@ -493,9 +516,12 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
   if (ch >= nchunks) return;
   const int64_t s = ch * C;
   const int len = (int)((nnz - s) < C ? (nnz - s) : C);
+  // rows just outside the chunk (lane 0 loads them with the entries; they
+  // reach LDS after the products, so no load waits on them)
+  int32_t e0 = -1, e1 = -1;
   if (lane == 0) {
-    edge[0] = s > 0 ? row[s - 1] : -1;
-    edge[1] = (s + len < nnz) ? row[s + len] : -1;
+    e0 = s > 0 ? row[s - 1] : -1;
+    e1 = (s + len < nnz) ? row[s + len] : -1;
   }
   {
     int32_t r[NPL], c[NPL];
@@ -511,14 +537,23 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
         v[t] = to_acc(val[s + k]);
       }
     }
+    // every gather in flight together (column 0 for unused slots, whose
+    // products are discarded)
+    T g[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) g[t] = x[c[t]];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const int k = t * 64 + lane;
       if (k < len) {
-        prod[pad(k)] = v[t] * x[c[t]];
+        prod[pad(k)] = v[t] * g[t];
         rw[pad(k)] = r[t];
       }
     }
+  }
+  if (lane == 0) {
+    edge[0] = e0;
+    edge[1] = e1;
   }
   wave_sync();
   const int32_t first = rw[0];
@@ -635,18 +670,49 @@ __global__ __launch_bounds__(64 * W) void k_ell(int64_t n, int64_t K, int64_t ld
   const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t i = g * 64 + lane;  // < ld: the grid covers ld / 64 groups
+  // Four slots per round, in one of two forms chosen by measurement on the
+  // 27-point 128^3 matrix.  With FP64 values the per-slot form (each slot's
+  // value load and gather under its own test) runs at 136 us against 140 us
+  // for the batched form; with FP32 values the batched form (index and
+  // value loads of all four slots together, slots past K re-reading slot j
+  // so every load is unconditional, then the four gathers, padding reading
+  // x[0] with its product discarded by a select) runs at 93 us against
+  // 101 us.  In both, padding never multiplies x.
   T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   for (int64_t j = w; j < K; j += 4 * W) {
-    const int64_t o0 = j * ld + i;
-    const int32_t c0 = ecol[o0];
-    const int32_t c1 = (j + W < K) ? ecol[o0 + W * ld] : -1;
-    const int32_t c2 = (j + 2 * W < K) ? ecol[o0 + 2 * W * ld] : -1;
-    const int32_t c3 = (j + 3 * W < K) ? ecol[o0 + 3 * W * ld] : -1;
-    if (c0 >= 0) a0 += to_acc(eval[o0]) * x[c0];
-    if (c1 >= 0) a1 += to_acc(eval[o0 + W * ld]) * x[c1];
-    if (c2 >= 0) a2 += to_acc(eval[o0 + 2 * W * ld]) * x[c2];
-    if (c3 >= 0) a3 += to_acc(eval[o0 + 3 * W * ld]) * x[c3];
-    if (!__any(c3 >= 0)) break;  // every later slot of these rows is padding
+    if constexpr (sizeof(V) == 8) {
+      const int64_t o0 = j * ld + i;
+      const int32_t c0 = ecol[o0];
+      const int32_t c1 = (j + W < K) ? ecol[o0 + W * ld] : -1;
+      const int32_t c2 = (j + 2 * W < K) ? ecol[o0 + 2 * W * ld] : -1;
+      const int32_t c3 = (j + 3 * W < K) ? ecol[o0 + 3 * W * ld] : -1;
+      if (c0 >= 0) a0 += to_acc(eval[o0]) * x[c0];
+      if (c1 >= 0) a1 += to_acc(eval[o0 + W * ld]) * x[c1];
+      if (c2 >= 0) a2 += to_acc(eval[o0 + 2 * W * ld]) * x[c2];
+      if (c3 >= 0) a3 += to_acc(eval[o0 + 3 * W * ld]) * x[c3];
+      if (!__any(c3 >= 0)) break;  // every later slot of these rows is padding
+    } else {
+      int32_t c[4];
+      V v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t jj = j + u * W;
+        const int64_t o = (jj < K ? jj : j) * ld + i;
+        c[u] = ecol[o];
+        v[u] = eval[o];
+      }
+#pragma unroll
+      for (int u = 1; u < 4; ++u)
+        if (j + u * W >= K) c[u] = -1;
+      T g[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) g[u] = x[c[u] >= 0 ? c[u] : 0];
+      a0 += c[0] >= 0 ? to_acc(v[0]) * g[0] : T(0);
+      a1 += c[1] >= 0 ? to_acc(v[1]) * g[1] : T(0);
+      a2 += c[2] >= 0 ? to_acc(v[2]) * g[2] : T(0);
+      a3 += c[3] >= 0 ? to_acc(v[3]) * g[3] : T(0);
+      if (!__any(c[3] >= 0)) break;  // every later slot of these rows is padding
+    }
   }
   T acc = (a0 + a1) + (a2 + a3);
   if (W > 1) {
