@@ -128,8 +128,8 @@ typedef struct {
   int32_t waves_per_group;/* CSR stream / COO: independent waves per work-group, 1 or 4 (0 = 4) */
 } mxs_convert_opts;
 
-#define MXS_CSR_AUTO 0   /* STREAM if a row exceeds 64 entries; else PRODUCTS for F64 rows
-                            of more than 16 entries, ROWS_LDS otherwise */
+#define MXS_CSR_AUTO 0   /* STREAM if a row exceeds 64 entries; else PRODUCTS, except
+                            ROWS_LDS for F32/F16 values when no row exceeds 16 entries */
 #define MXS_CSR_STREAM 1
 #define MXS_CSR_VECTOR 2
 #define MXS_CSR_ROWS_LDS 3 /* blocks of <= 64 rows staged in LDS, one lane per row */

@@ -287,16 +287,20 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
   }
   // AUTO: the row-block stream kernel when some row is longer than 64
   // entries (power-law rows); otherwise one of the two LDS kernels over
-  // blocks of <= 64 rows.  Measured on the stencil matrices: with FP64
-  // values and rows of more than 16 entries the products kernel (512-entry
-  // blocks) is the faster (27-point: 176 vs 198 us); with shorter rows or
-  // narrower values the rows-from-LDS kernel is.  (The lanes-along-a-row
-  // layout gathers x with more cache lines per instruction on stencils.)
+  // blocks of <= 64 rows.  Measured on the 128^3 stencils: the products
+  // kernel (512-entry blocks) is the faster for 8- and 16-byte values
+  // (27-point FP64 146 vs 187 us, 7-point FP64 39 vs 41 us) and for
+  // narrower values with rows of more than 16 entries (27-point FP32 117 vs
+  // 123 us); rows from LDS for narrower values and shorter rows (7-point
+  // FP32 31 vs 34 us).  (The lanes-along-a-row layout gathers x with more
+  // cache lines per instruction on stencils.)
   int kind_eff = kind;
-  if (kind == MXS_CSR_AUTO)
-    kind_eff = maxL > 64 ? MXS_CSR_STREAM
-               : ((A->dt == MXS_F64 || A->dt == MXS_C128) && maxL > 16) ? MXS_CSR_PRODUCTS
-                                                                        : MXS_CSR_ROWS_LDS;
+  if (kind == MXS_CSR_AUTO) {
+    const bool wide = A->dt == MXS_F64 || A->dt == MXS_C128 || A->dt == MXS_C64;
+    kind_eff = maxL > 64                ? MXS_CSR_STREAM
+               : (wide || maxL > 16)   ? MXS_CSR_PRODUCTS
+                                       : MXS_CSR_ROWS_LDS;
+  }
   bool vec = kind_eff == MXS_CSR_VECTOR;
   A->csr.lanes = vec ? G : 0;
   A->csr.wpb = (opts && opts->waves_per_group == 1) ? 1 : 4;
