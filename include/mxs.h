@@ -123,17 +123,18 @@ typedef struct {
   int64_t max_ell_bytes;  /* 0 = no limit; ELL/HYB larger than this -> MXS_UNSUPPORTED */
   int32_t block_nnz;      /* CSR/COO: entries per work unit (256, 512 or 1024; others are rounded up); 0 = 512 */
   int32_t csr_kernel;     /* CSR: MXS_CSR_AUTO, MXS_CSR_STREAM (row blocks), MXS_CSR_VECTOR (lanes per row), MXS_CSR_ROWS_LDS, MXS_CSR_PRODUCTS */
-  int32_t lanes_per_row;  /* CSR vector kernel: 1 (thread per row), 4, 8, 16, 32 or 64; 0 = from the mean row length */
+  int32_t lanes_per_row;  /* CSR vector kernel: 1 (thread per row), 4, 8, 16, 32 or 64; 0 = from the mean row length.
+                             CSR rows-from-LDS kernel: 1, 2 or 4 lanes per row; 0 = the fewest that fill a wave */
   int32_t rows_per_group; /* CSR vector kernel: 2, 4 or 8 rows per lane group; 0 = default */
   int32_t waves_per_group;/* CSR stream / COO: independent waves per work-group, 1 or 4 (0 = 4) */
 } mxs_convert_opts;
 
-#define MXS_CSR_AUTO 0   /* STREAM if a row exceeds 64 entries; else PRODUCTS, except
-                            ROWS_LDS for F32/F16 values when no row exceeds 16 entries */
+#define MXS_CSR_AUTO 0   /* STREAM if a row exceeds 64 entries; else ROWS_LDS for F32/F16
+                            values and for F64 rows of at most 8 entries, PRODUCTS otherwise */
 #define MXS_CSR_STREAM 1
 #define MXS_CSR_VECTOR 2
-#define MXS_CSR_ROWS_LDS 3 /* blocks of <= 64 rows staged in LDS, one lane per row */
-#define MXS_CSR_PRODUCTS 4 /* the same blocks; products formed by all lanes, summed per row from LDS */
+#define MXS_CSR_ROWS_LDS 3 /* blocks of <= 64/G rows staged in LDS, G = 1, 2 or 4 lanes per row */
+#define MXS_CSR_PRODUCTS 4 /* blocks of <= 64 rows; products formed by all lanes, summed per row from LDS */
 
 /* Converts `src` (an FP64 CSR matrix from mxs_matrix_create_csr) to another
  * format and value type, on the GPU.  Layouts (all int32 indices):
@@ -163,7 +164,8 @@ typedef struct {
   int64_t blocks;                /* work units of the SpMV kernel */
   int64_t bytes;                 /* device bytes owned by the matrix */
   int32_t block_nnz;
-  int32_t lanes_per_row;         /* CSR: 0 = stream kernel, 1 = thread per row, else lanes per row */
+  int32_t lanes_per_row;         /* CSR vector kernel: 1 = thread per row, else lanes per row;
+                                    rows-from-LDS kernel: lanes per row; other kernels 0 */
   int32_t rows_per_group;
   int32_t waves_per_group;       /* CSR stream / COO work-group shape */
   int32_t csr_kernel;            /* CSR: the kernel in use (MXS_CSR_STREAM ... MXS_CSR_PRODUCTS) */

@@ -96,8 +96,9 @@ CSR_CANDIDATES = ([dict(csr_kernel="stream", block_nnz=b) for b in (256, 512, 10
                   [dict(csr_kernel="vector", lanes_per_row=g, rows_per_group=r)
                    for g in (4, 8, 16, 32) for r in (4, 8)] +
                   [dict(csr_kernel="vector", lanes_per_row=1)] +
-                  [dict(csr_kernel=k, block_nnz=b) for k in ("rows_lds", "products")
-                   for b in (512, 1024)])
+                  [dict(csr_kernel="rows_lds", block_nnz=b, lanes_per_row=g)
+                   for b in (512, 1024) for g in (1, 2)] +
+                  [dict(csr_kernel="products", block_nnz=b) for b in (512, 1024)])
 
 
 def tune_spmv(ctx, M, dtype="f64", reps=20, cache=DEFAULT_CACHE, signature=None, refresh=False,

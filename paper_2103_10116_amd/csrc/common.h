@@ -78,7 +78,8 @@ struct CsrPart {
   int lanes = 0;  // 0: stream kernel; 1: thread per row; >1: lanes per row
   int rpg = 4;
   int wpb = 4;    // stream kernel: independent waves per work-group (1 or 4)
-  bool rows_lds = false;  // rows-from-LDS kernel (blocks of <= 64 rows, block_nnz entries)
+  bool rows_lds = false;  // rows-from-LDS kernel (blocks of <= 64/rl_lanes rows, block_nnz entries)
+  int rl_lanes = 1;       // rows-from-LDS kernel: lanes per row (1, 2 or 4)
   bool products = false;  // products-through-LDS kernel (the same blocks)
 };
 

@@ -287,19 +287,18 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
   }
   // AUTO: the row-block stream kernel when some row is longer than 64
   // entries (power-law rows); otherwise one of the two LDS kernels over
-  // blocks of <= 64 rows.  Measured on the 128^3 stencils: the products
-  // kernel (512-entry blocks) is the faster for 8- and 16-byte values
-  // (27-point FP64 146 vs 187 us, 7-point FP64 39 vs 41 us) and for
-  // narrower values with rows of more than 16 entries (27-point FP32 117 vs
-  // 123 us); rows from LDS for narrower values and shorter rows (7-point
-  // FP32 31 vs 34 us).  (The lanes-along-a-row layout gathers x with more
-  // cache lines per instruction on stencils.)
+  // blocks of <= 64 rows.  Measured on the 128^3 stencils: rows from LDS for
+  // 4- and 2-byte values (27-point FP32 98 vs 117 us for products, FP16 83
+  // vs 132 us, 7-point FP32 27 vs 34 us) and for FP64 rows of at most 8
+  // entries (7-point 36.8 vs 39.1 us); products otherwise (27-point FP64 146
+  // vs 150 us, complex values), whose LDS holds one value per entry instead
+  // of a value and an index.
   int kind_eff = kind;
   if (kind == MXS_CSR_AUTO) {
-    const bool wide = A->dt == MXS_F64 || A->dt == MXS_C128 || A->dt == MXS_C64;
-    kind_eff = maxL > 64                ? MXS_CSR_STREAM
-               : (wide || maxL > 16)   ? MXS_CSR_PRODUCTS
-                                       : MXS_CSR_ROWS_LDS;
+    const bool narrow = A->dt == MXS_F32 || A->dt == MXS_F16_ROWSCALED;
+    kind_eff = maxL > 64                             ? MXS_CSR_STREAM
+               : (narrow || (A->dt == MXS_F64 && maxL <= 8)) ? MXS_CSR_ROWS_LDS
+                                                             : MXS_CSR_PRODUCTS;
   }
   bool vec = kind_eff == MXS_CSR_VECTOR;
   A->csr.lanes = vec ? G : 0;
@@ -314,20 +313,33 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
   std::vector<int32_t> blocks, bnnz;
   A->csr.rows_lds = kind_eff == MXS_CSR_ROWS_LDS;
   A->csr.products = kind_eff == MXS_CSR_PRODUCTS;
+  A->csr.rl_lanes = 1;
+  int max_rows = -1;
   if (A->csr.rows_lds || A->csr.products) {
-    // rows-from-LDS blocks: at most 64 rows; entry budget 64 * (longest row)
+    // LDS-kernel blocks: at most 64 rows; entry budget 64 * (longest row)
     // rounded up to 512 or 1024 (2048 only on request: its LDS footprint
     // halves the waves per CU); rows longer than it get a wave of their own
     const int64_t want = 64 * std::max<int64_t>(maxL, 1);
     block_nnz = A->csr.products || want <= 512 ? 512 : 1024;
     if (opts && opts->block_nnz > 0) block_nnz = opts->block_nnz <= 512 ? 512
                                                 : opts->block_nnz <= 1024 ? 1024 : 2048;
+    max_rows = 64;
+    if (A->csr.rows_lds) {
+      // lanes per row: the fewest that fill the wave when 64/G rows of the
+      // longest length fit the entry budget (or the caller's 1, 2 or 4)
+      int g = 1;
+      if (opts && opts->lanes_per_row > 0)
+        g = opts->lanes_per_row >= 4 ? 4 : opts->lanes_per_row >= 2 ? 2 : 1;
+      else
+        while (g < 4 && (64 / g) * std::max<int64_t>(maxL, 1) > block_nnz) g <<= 1;
+      A->csr.rl_lanes = g;
+      max_rows = 64 / g;
+    }
   } else if (kind == MXS_CSR_AUTO && !(opts && opts->block_nnz > 0)) {
     block_nnz = 1024;
   }
   A->csr.block_nnz = block_nnz;
-  A->csr.nblocks = csr_partition(rp.data(), A->n, block_nnz, blocks,
-                                 A->csr.rows_lds || A->csr.products ? 64 : -1);
+  A->csr.nblocks = csr_partition(rp.data(), A->n, block_nnz, blocks, max_rows);
   bnnz.resize(blocks.size());
   for (size_t b = 0; b < blocks.size(); ++b) bnnz[b] = rp[blocks[b]];
   A->csr.blocks = upload(ctx, A, blocks);
@@ -747,7 +759,7 @@ mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
                 : (A->fmt == MXS_COO || A->fmt == MXS_HYB) ? A->coo.nchunks
                                                            : (A->ell.stride / 64);
   out->block_nnz = A->fmt == MXS_CSR ? A->csr.block_nnz : A->coo.block_nnz;
-  out->lanes_per_row = A->fmt == MXS_CSR ? A->csr.lanes : 0;
+  out->lanes_per_row = A->fmt != MXS_CSR ? 0 : A->csr.rows_lds ? A->csr.rl_lanes : A->csr.lanes;
   out->rows_per_group = A->fmt == MXS_CSR ? A->csr.rpg : 0;
   out->waves_per_group = A->fmt == MXS_CSR ? A->csr.wpb : A->coo.wpb;
   out->csr_kernel = A->fmt != MXS_CSR  ? 0

@@ -41,6 +41,31 @@ __device__ __forceinline__ T combine(T alpha, T s, T beta, const T* __restrict__
   return beta == T(0) ? alpha * s : alpha * s + beta * y[i];
 }
 
+// Matrix values staged in registers as raw bits: a 2-byte value takes a
+// whole register, so that a predicated load never has to merge into a
+// register that an earlier load still fills (which would make each load wait
+// for the one before it).
+template <typename V>
+struct Raw {
+  using type = V;
+  static __device__ __forceinline__ V load(const V* p, int64_t i) { return p[i]; }
+  static __device__ __forceinline__ V value(V r) { return r; }
+  static __device__ __forceinline__ void store(V* d, int i, V r) { d[i] = r; }
+};
+template <>
+struct Raw<_Float16> {
+  using type = uint32_t;
+  static __device__ __forceinline__ uint32_t load(const _Float16* p, int64_t i) {
+    return reinterpret_cast<const uint16_t*>(p)[i];
+  }
+  static __device__ __forceinline__ _Float16 value(uint32_t r) {
+    return __builtin_bit_cast(_Float16, (uint16_t)r);
+  }
+  static __device__ __forceinline__ void store(_Float16* d, int i, uint32_t r) {
+    reinterpret_cast<uint16_t*>(d)[i] = (uint16_t)r;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // CSR
 // ---------------------------------------------------------------------------
@@ -263,14 +288,19 @@ __global__ __launch_bounds__(256) void k_csr_vec(int64_t n, const int32_t* __res
 }
 
 // ---------------------------------------------------------------------------
-// CSR, rows from LDS: a wave owns a block of at most 64 rows and CMAX
-// entries.  It copies the block's column indices and values into LDS with
-// fully coalesced loads, then lane i walks row i out of LDS, so the x
-// gathers of one step come from 64 neighbouring rows (contiguous on banded
-// and stencil matrices, as in ELL) while HBM sees only contiguous reads.  A
-// row longer than CMAX is a block of its own and takes the whole wave.
+// CSR, rows from LDS: a wave owns a block of at most 64/G rows and CMAX
+// entries.  All of the block's column indices and values are loaded at once
+// (fully coalesced, CMAX/64 of each per lane in flight together) and copied
+// into LDS; then G neighbouring lanes walk each row out of LDS (lane h of a
+// row takes its entries h, h+G, h+2G, ...), so the x gathers of one step
+// come from neighbouring rows (contiguous on banded and stencil matrices, as
+// in ELL) while HBM sees only contiguous reads.  G > 1 keeps every lane busy
+// when a block holds fewer than 64 rows.  A row longer than CMAX is a block
+// of its own and takes the whole wave, reading straight from global memory.
+// (Staging the next block while walking the current one was measured
+// slower: the extra registers cost more occupancy than the overlap gains.)
 // ---------------------------------------------------------------------------
-template <typename V, typename T, int CMAX, bool SCALED, int WPB>
+template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G>
 __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
                                                      const int32_t* __restrict__ blocks,
                                                      const int32_t* __restrict__ bnnz,
@@ -281,6 +311,7 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
                                                      const T* __restrict__ x, T* __restrict__ y,
                                                      T alpha, T beta,
                                                      const int32_t* __restrict__ skip) {
+  constexpr int U = CMAX / 64;  // entries per lane of a full block
   __shared__ V vl_all[WPB][CMAX];
   __shared__ int32_t cl_all[WPB][CMAX];
   if (skip && *skip) return;
@@ -314,44 +345,56 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
     }
     return;
   }
-  // row bounds of lane `lane` (an empty range at len for lanes past the
+  // bounds of the lane's row (an empty range at len for lanes past the
   // block): loaded unconditionally so that their wait can be deferred
-  const int32_t ra = rowptr[r0 + (lane < nr ? lane : nr)] - s;
-  const int32_t rb = rowptr[r0 + (lane < nr ? lane + 1 : nr)] - s;
-  // coalesced copy into LDS, eight loads per lane in flight per round
-  for (int base = 0; base < len; base += 8 * 64) {
-    int32_t c[8];
-    V v[8];
+  const int rl = lane / G, h = lane % G;
+  const int32_t ra = rowptr[r0 + (rl < nr ? rl : nr)] - s;
+  const int32_t rb = rowptr[r0 + (rl < nr ? rl + 1 : nr)] - s;
+  {
+    int32_t c[U];
+    typename Raw<V>::type v[U];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int k = base + t * 64 + lane;
+    for (int t = 0; t < U; ++t) {
+      const int k = t * 64 + lane;
       if (k < len) {
         c[t] = col[s + k];
-        v[t] = val[s + k];
+        v[t] = Raw<V>::load(val, s + k);
       }
     }
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int k = base + t * 64 + lane;
+    for (int t = 0; t < U; ++t) {
+      const int k = t * 64 + lane;
       if (k < len) {
         cl[k] = c[t];
-        vl[k] = v[t];
+        Raw<V>::store(vl, k, v[t]);
       }
     }
   }
   wave_sync();
-  if (lane >= nr) return;
-  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  int32_t k = ra;
-  for (; k + 3 < rb; k += 4) {
-    s0 += to_acc(vl[k]) * x[cl[k]];
-    s1 += to_acc(vl[k + 1]) * x[cl[k + 1]];
-    s2 += to_acc(vl[k + 2]) * x[cl[k + 2]];
-    s3 += to_acc(vl[k + 3]) * x[cl[k + 3]];
+  // eight of the lane's entries per step, their gathers in flight together;
+  // slots past the row's end read the row's first entry and add nothing
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  for (int32_t k = ra + h; k < rb; k += 8 * G) {
+    int32_t cc[8];
+    T vv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int32_t kk = k + t * G < rb ? k + t * G : ra;
+      cc[t] = cl[kk];
+      vv[t] = to_acc(vl[kk]);
+    }
+    T g[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) g[t] = x[cc[t]];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (k + t * G < rb) acc[t & 3] += vv[t] * g[t];
   }
-  for (; k < rb; ++k) s0 += to_acc(vl[k]) * x[cl[k]];
-  T sum = (s0 + s1) + (s2 + s3);
-  const int64_t i = (int64_t)r0 + lane;
+  T sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (h != 0 || rl >= nr) return;
+  const int64_t i = (int64_t)r0 + rl;
   if (SCALED) sum *= (T)scale[i];
   y[i] = combine(alpha, sum, beta, y, i);
 }
@@ -411,29 +454,30 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_pr(int64_t nblocks,
   // block): loaded unconditionally so that their wait can be deferred
   const int32_t ra = rowptr[r0 + (lane < nr ? lane : nr)] - s;
   const int32_t rb = rowptr[r0 + (lane < nr ? lane + 1 : nr)] - s;
-  // products, eight entries per lane in flight per round
-  for (int base = 0; base < len; base += 8 * 64) {
-    int32_t c[8];
-    T v[8];
+  // products, U entries per lane in flight per round (sixteen for 4-byte
+  // values in blocks of 1024 entries or more, else eight)
+  constexpr int U = sizeof(T) == 4 && CMAX >= 1024 ? 16 : 8;
+  for (int base = 0; base < len; base += U * 64) {
+    int32_t c[U];
+    typename Raw<V>::type v[U];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < U; ++t) {
       const int k = base + t * 64 + lane;
-      c[t] = 0;
-      v[t] = 0;
+      c[t] = 0;  // (v[t] of an unused slot is never read)
       if (k < len) {
         c[t] = col[s + k];
-        v[t] = to_acc(val[s + k]);
+        v[t] = Raw<V>::load(val, s + k);
       }
     }
     // every gather in flight together (column 0 for unused slots, whose
     // products are discarded)
-    T g[8];
+    T g[U];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) g[t] = x[c[t]];
+    for (int t = 0; t < U; ++t) g[t] = x[c[t]];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < U; ++t) {
       const int k = base + t * 64 + lane;
-      if (k < len) pl[k] = v[t] * g[t];
+      if (k < len) pl[k] = to_acc(Raw<V>::value(v[t])) * g[t];
     }
   }
   wave_sync();
@@ -768,14 +812,25 @@ void launch_csr_stream(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T be
   }
 }
 
+template <typename V, typename T, bool SCALED, int CMAX, int G>
+void launch_csr_rl_g(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
+                     const int32_t* skip) {
+  constexpr int WPB = 2;
+  const dim3 grid((unsigned)((P.nblocks + WPB - 1) / WPB));
+  k_csr_rl<V, T, CMAX, SCALED, WPB, G><<<grid, 64 * WPB, 0, ctx->stream>>>(
+      P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
+      skip);
+}
+
 template <typename V, typename T, bool SCALED, int CMAX>
 void launch_csr_rl(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
                    const int32_t* skip) {
-  constexpr int WPB = 2;
-  const dim3 grid((unsigned)((P.nblocks + WPB - 1) / WPB));
-  k_csr_rl<V, T, CMAX, SCALED, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-      P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
-      skip);
+  if (P.rl_lanes == 4)
+    launch_csr_rl_g<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip);
+  else if (P.rl_lanes == 2)
+    launch_csr_rl_g<V, T, SCALED, CMAX, 2>(ctx, P, alpha, x, beta, y, skip);
+  else
+    launch_csr_rl_g<V, T, SCALED, CMAX, 1>(ctx, P, alpha, x, beta, y, skip);
 }
 
 template <typename V, typename T, bool SCALED, int CMAX, int WPB>

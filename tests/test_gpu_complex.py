@@ -35,7 +35,8 @@ def _zoo():
 ZOO = _zoo()
 KERNELS = [dict(), dict(csr_kernel="stream", block_nnz=256), dict(csr_kernel="stream", block_nnz=1024),
            dict(csr_kernel="products", block_nnz=512), dict(csr_kernel="products", block_nnz=2048),
-           dict(csr_kernel="rows_lds", block_nnz=1024), dict(csr_kernel="vector", lanes_per_row=8),
+           dict(csr_kernel="rows_lds", block_nnz=1024), dict(csr_kernel="rows_lds", block_nnz=512, lanes_per_row=2),
+           dict(csr_kernel="rows_lds", block_nnz=2048, lanes_per_row=4), dict(csr_kernel="vector", lanes_per_row=8),
            dict(csr_kernel="vector", lanes_per_row=1)]
 
 

@@ -208,6 +208,8 @@ CSR_VARIANTS = [dict(csr_kernel="stream", block_nnz=b, waves_per_group=w)
     for g in (4, 8, 16, 32, 64) for r in (2, 4, 8)] + [
     dict(csr_kernel="vector", lanes_per_row=1)] + [
     dict(csr_kernel="rows_lds", block_nnz=b) for b in (0, 512, 1024, 2048)] + [
+    dict(csr_kernel="rows_lds", block_nnz=b, lanes_per_row=g)
+    for b in (512, 1024, 2048) for g in (1, 2, 4)] + [
     dict(csr_kernel="products", block_nnz=b, waves_per_group=w)
     for b in (0, 512, 1024, 2048) for w in (0, 1, 2, 4)]
 
@@ -239,7 +241,10 @@ def test_spmv_csr_kernels(env, orc, name, dt):
     for opts in CSR_VARIANTS:
         B = M.convert("csr", dt, **opts)
         d = B.info()
-        assert (d["lanes_per_row"] > 0) == (opts["csr_kernel"] == "vector")
+        assert (d["lanes_per_row"] > 0) == (opts["csr_kernel"] in ("vector", "rows_lds"))
+        if opts["csr_kernel"] == "rows_lds":
+            g = d["lanes_per_row"]
+            assert g == opts.get("lanes_per_row", g) and g in (1, 2, 4)
         assert d["csr_kernel"] == mxs.CSR_KERNELS[opts["csr_kernel"]]
         if opts["csr_kernel"] in ("rows_lds", "products") and opts["block_nnz"]:
             assert d["block_nnz"] == opts["block_nnz"]
