@@ -264,6 +264,10 @@ def main():
             zy = {"f64": torch.zeros(Z.n, dtype=torch.float64, device=dev),
                   "f32": torch.zeros(Z.n, dtype=torch.float32, device=dev)}
             r = {"nnz": Z.nnz, "max_row": int(Z.row_lengths().max())}
+            # columns uniform over all of x: every entry's x load is a cache
+            # line of its own, so the random-gather rate bounds the product
+            gp = {dt: mxs.gather_probe(ctx, Z.ncols, Z.nnz, vb, 5) for dt, vb in (("f64", 8), ("f32", 4))}
+            r["gather_probe_per_s"] = {dt: round(v / 1e9, 2) for dt, v in gp.items()}
             for fmt in ("csr", "coo", "hyb", "ell"):
                 for dt in ("f64", "f32"):
                     B = Zm if (fmt, dt) == ("csr", "f64") else Zm.convert(fmt, dt)
@@ -277,6 +281,12 @@ def main():
                     e = {"cold_us": round(t_cold * 1e6, 2), "cold_GBs": round(nbytes / t_cold / 1e9, 1),
                          "warm_us": round(t_warm * 1e6, 2), "warm_GBs_cache_assisted": round(nbytes / t_warm / 1e9, 1),
                          "bytes": nbytes}
+                    # bound: the x gathers at the probe's rate, or the rest of
+                    # the bytes at the measured HBM rate, whichever is longer
+                    t_g = Z.nnz / gp[dt]
+                    t_b = (nbytes - Z.ncols * vb) / (peak_meas * 1e9) if peak_meas else 0.0
+                    e["gather_bound_us"] = round(max(t_g, t_b) * 1e6, 2)
+                    e["frac_of_gather_bound"] = round(max(t_g, t_b) / t_cold, 3)
                     if fmt == "ell":
                         e["ell_width"] = info["ell_width"]
                         e["streamed_bytes_if_fully_read"] = ell_streamed_bytes(info, vb, vb)
@@ -285,7 +295,7 @@ def main():
                         e["coo_nnz"] = info["coo_nnz"]
                     r[f"{fmt}_{dt}"] = e
                     log(f"{label} {fmt} {dt}: cold {t_cold*1e6:.1f} us {nbytes/t_cold/1e9:.0f} GB/s, "
-                        f"warm {t_warm*1e6:.1f} us")
+                        f"warm {t_warm*1e6:.1f} us, gather bound {e['gather_bound_us']:.1f} us")
                     if B is not Zm:
                         B.close()
             Zm.close()

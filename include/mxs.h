@@ -482,6 +482,17 @@ typedef struct {
  * Counts bytes read + written.  Synchronises the ctx stream. */
 mxs_status mxs_hbm_probe(mxs_ctx* ctx, size_t bytes, int reps, mxs_bw_result* out);
 
+/* Random-gather throughput, the ceiling of SpMV on matrices whose columns
+ * are scattered over all of x (the power-law patterns): each entry's x load
+ * then touches a cache line of its own, so gathers per second, not HBM
+ * bytes, bound the product.  Times `count` loads x[idx[k]] from an x of `nx`
+ * values of `value_bytes` (4 or 8), idx uniform over [0, nx) (a fixed hash
+ * of k, streamed as int32), eight gathers per thread in flight; best of
+ * `reps` runs after a warm-up run (x stays in whatever cache level holds
+ * it).  Writes gathers per second.  Synchronises the ctx stream. */
+mxs_status mxs_gather_probe(mxs_ctx* ctx, int64_t nx, int64_t count, int value_bytes, int reps,
+                            double* gathers_per_s);
+
 /* Writes `bytes` bytes of a ctx-owned scratch buffer so that later reads
  * come from HBM rather than from the last-level cache.  Asynchronous. */
 mxs_status mxs_flush_cache(mxs_ctx* ctx, size_t bytes);

@@ -104,6 +104,45 @@ __global__ __launch_bounds__(256) void k_probe_read1(const double2* __restrict__
   if (s == 1.2345e300) sink[0] = s;
 }
 
+// Random indices in [0, nx): the finaliser of MurmurHash3 (a published
+// 64-bit mixing function) applied to the entry number.
+__global__ __launch_bounds__(256) void k_fill_random_index(int32_t* __restrict__ idx,
+                                                           int64_t count, int64_t nx) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride) {
+    uint64_t h = (uint64_t)k + 0x9E3779B97F4A7C15ull;
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    h *= 0xc4ceb9fe1a85ec53ull;
+    h ^= h >> 33;
+    idx[k] = (int32_t)(h % (uint64_t)nx);
+  }
+}
+
+// count loads x[idx[k]]: each thread takes eight indices per step (index
+// loads coalesced across the block), all eight gathers in flight together
+template <typename T>
+__global__ __launch_bounds__(256) void k_probe_gather(const int32_t* __restrict__ idx,
+                                                      const T* __restrict__ x, int64_t count,
+                                                      double* __restrict__ sink) {
+  const int64_t stride = (int64_t)gridDim.x * 256 * 8;
+  T acc = 0;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * 8 + threadIdx.x; base < count;
+       base += stride) {
+    int32_t c[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) c[t] = base + t * 256 < count ? idx[base + t * 256] : 0;
+    T g[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) g[t] = x[c[t]];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (base + t * 256 < count) acc += g[t];
+  }
+  if (acc == T(1.2345e30)) sink[0] = (double)acc;
+}
+
 __global__ __launch_bounds__(256) void k_probe_copy1(const double2* __restrict__ a,
                                                      double2* __restrict__ b, int64_t n2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,6 +346,53 @@ mxs_status mxs_hbm_probe(mxs_ctx* ctx, size_t bytes, int reps, mxs_bw_result* ou
   ctx->alloc.release(a);
   ctx->alloc.release(b);
   ctx->alloc.release(c);
+  ctx->alloc.release(sink);
+  return st;
+}
+
+mxs_status mxs_gather_probe(mxs_ctx* ctx, int64_t nx, int64_t count, int value_bytes, int reps,
+                            double* gathers_per_s) {
+  if (!ctx || !gathers_per_s || nx < 1 || nx > INT32_MAX || count < 1 || reps < 1 ||
+      (value_bytes != 4 && value_bytes != 8))
+    return MXS_INVALID_ARG;
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* x = ctx->alloc.alloc((size_t)nx * value_bytes + 16);
+  int32_t* idx = (int32_t*)ctx->alloc.alloc((size_t)count * 4 + 16);
+  double* sink = (double*)ctx->alloc.alloc(64);
+  mxs_status st = MXS_OK;
+  if (!x || !idx || !sink) {
+    st = fail(ctx, MXS_OOM, "gather_probe: cannot allocate %lld values and %lld indices",
+              (long long)nx, (long long)count);
+  } else {
+    const int grid = ctx->num_cus * 16;
+    const int64_t n2 = (int64_t)((size_t)nx * value_bytes / 16);
+    if (n2 > 0) k_fill<<<grid, 256, 0, ctx->stream>>>((double2*)x, n2, 1.0);
+    k_fill_random_index<<<grid, 256, 0, ctx->stream>>>(idx, count, nx);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best = 1e30f;
+    for (int r = 0; r < reps + 1; ++r) {  // first run is warm-up
+      (void)hipEventRecord(e0, ctx->stream);
+      if (value_bytes == 8)
+        k_probe_gather<double><<<grid, 256, 0, ctx->stream>>>(idx, (const double*)x, count, sink);
+      else
+        k_probe_gather<float><<<grid, 256, 0, ctx->stream>>>(idx, (const float*)x, count, sink);
+      (void)hipEventRecord(e1, ctx->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0 && ms < best) best = ms;
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) st = fail(ctx, MXS_HIP, "gather_probe: %s", hipGetErrorString(err));
+    *gathers_per_s = (double)count / (best * 1e-3);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->alloc.release(x);
+  ctx->alloc.release(idx);
   ctx->alloc.release(sink);
   return st;
 }

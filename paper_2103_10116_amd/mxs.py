@@ -20,6 +20,12 @@ LIB_PATH = os.path.join(_HERE, "libmxs.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                       "(paper_2103_10116_amd/build.py or __graft_entry__.build())")
+# torch first: its HIP runtime is then already in the process when libmxs is
+# loaded, so both bind to the same runtime and share devices and streams
+# (loading libmxs first brings in a second runtime, on which context
+# creation fails).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 OK, INVALID_ARG, INVALID_MATRIX, UNSUPPORTED, OOM, HIP = 0, 1, 2, 3, 4, 5
@@ -145,6 +151,7 @@ _SIGS = {
     "mxs_batch_config": (_S, [_P, _S, C.POINTER(_S), C.POINTER(_S), C.POINTER(_S),
                               C.POINTER(_S), C.POINTER(_S)]),
     "mxs_hbm_probe": (_S, [_P, C.c_size_t, C.c_int, C.POINTER(BwResult)]),
+    "mxs_gather_probe": (_S, [_P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     "mxs_flush_cache": (_S, [_P, C.c_size_t]),
     "mxs_status_string": (C.c_char_p, [_S]),
     "mxs_last_error": (C.c_char_p, [_P]),
@@ -511,6 +518,14 @@ def hbm_probe(ctx: Context, nbytes=1 << 30, reps=5) -> dict:
     _check(_lib.mxs_hbm_probe(ctx.handle, int(nbytes), int(reps), C.byref(r)), ctx)
     return {"read_gbs": r.read_gbs, "copy_gbs": r.copy_gbs, "triad_gbs": r.triad_gbs,
             "best_gbs": r.best_gbs}
+
+
+def gather_probe(ctx: Context, nx: int, count: int, value_bytes=8, reps=5) -> float:
+    """Random gathers per second from an x of nx values (see mxs_gather_probe)."""
+    r = C.c_double(0.0)
+    _check(_lib.mxs_gather_probe(ctx.handle, int(nx), int(count), int(value_bytes), int(reps),
+                                 C.byref(r)), ctx)
+    return r.value
 
 
 def flush_cache(ctx: Context, nbytes=1 << 30):
