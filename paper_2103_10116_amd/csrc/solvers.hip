@@ -119,6 +119,85 @@ __device__ __forceinline__ void finish(const double* __restrict__ part, int g, d
   for (int v = 0; v < NV; ++v) out[v] = res[v];
 }
 
+// Wave sums of NV (a power of two <= 32) per-lane values by a transposing
+// butterfly: at each of the first log2(NV) steps a lane keeps half of its
+// values and adds its partner's copy of them (NV-1 exchanges in all instead
+// of 6 NV), then plain butterflies finish.  Lane l ends with the sum of
+// value (l >> (6 - log2 NV)) over the wave; the order is fixed, so the
+// result is deterministic.
+template <int H, int O, int NV>
+__device__ __forceinline__ void transposed_steps(double (&a)[NV], int lane) {
+  if constexpr (H > 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int q = 0; q < H / 2; ++q) {
+      const double keep = up ? a[q + H / 2] : a[q];
+      const double send = up ? a[q] : a[q + H / 2];
+      a[q] = keep + __shfl_xor(send, O, 64);
+    }
+    transposed_steps<H / 2, O / 2, NV>(a, lane);
+  } else {
+#pragma unroll
+    for (int o = O; o > 0; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ double wave_sum_transposed(double (&a)[NV]) {
+  transposed_steps<NV, 32, NV>(a, threadIdx.x & 63);
+  return a[0];
+}
+
+// Block partial sums of NV values (a power of two <= 32) to
+// part[blockIdx.x * MAXM + v]: transposed wave sums, then thread v adds
+// value v over the waves in wave order.
+template <int NV>
+__device__ __forceinline__ void block_partials_m(double (&acc)[NV], double* __restrict__ part) {
+  static_assert(NV <= 32 && (NV & (NV - 1)) == 0, "power of two up to 32");
+  __shared__ double lds[RB / 64][NV];
+  constexpr int SH = NV == 1 ? 6 : NV == 2 ? 5 : NV == 4 ? 4 : NV == 8 ? 3 : NV == 16 ? 2 : 1;
+  const double s = wave_sum_transposed<NV>(acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+  if ((lane & ((1 << SH) - 1)) == 0) lds[w][lane >> SH] = s;
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    double t = lds[0][threadIdx.x];
+#pragma unroll
+    for (int q = 1; q < RB / 64; ++q) t += lds[q][threadIdx.x];
+    part[(int64_t)blockIdx.x * MAXM + threadIdx.x] = t;
+  }
+}
+
+// Totals of the first `nv` values of g block partials laid out as
+// part[b * MAXM + v] (b < g <= RB), for the one-block finishing kernel.
+// Loads are coalesced: thread t reads entries t, t + RB, t + 2 RB, ... of the
+// flat array, all of value t % MAXM (RB is a multiple of MAXM), and adds
+// them in block order; the RB / MAXM threads of one value are then added in
+// thread order.  Thread v < nv gets total v in `out`.
+__device__ __forceinline__ double finish_m(const double* __restrict__ part, int g) {
+  static_assert(RB % MAXM == 0 && MAXM == 32, "flat layout");
+  __shared__ double lds[RB / 64][MAXM];
+  const int t = threadIdx.x, total = g * MAXM;
+  double v[MAXM];
+#pragma unroll
+  for (int k = 0; k < MAXM; ++k) v[k] = t + k * RB < total ? part[t + k * RB] : 0.0;
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < MAXM; ++k) a += v[k];
+  // lanes l and l + 32 of a wave hold the same value
+  a += __shfl_xor(a, 32, 64);
+  const int lane = t & 63, w = t / 64;
+  if (lane < MAXM) lds[w][lane] = a;
+  __syncthreads();
+  double out = 0.0;
+  if (t < MAXM) {
+    out = lds[0][t];
+#pragma unroll
+    for (int q = 1; q < RB / 64; ++q) out += lds[q][t];
+  }
+  return out;
+}
+
 __device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
 #define GRID_STRIDE(i, n) \
@@ -373,71 +452,77 @@ __global__ __launch_bounds__(RB) void k_bi_half(int64_t n, double* __restrict__ 
 // multi-dot partials of (j+1) values per block are finished by a one-block
 // kernel that also owns the small dense work (Hessenberg column, Givens).
 // ---------------------------------------------------------------------------
+// The three passes over the basis are instantiated for JB = 8, 16 and 32
+// vectors (the smallest that holds v_0..v_j), so that short bases do not pay
+// registers, and occupancy, for 32.
 // partials of V(:,0..j)^T w
+template <int JB>
 __global__ __launch_bounds__(RB) void k_gm_dots(int64_t n, int64_t ldv, int j,
                                                 const double* __restrict__ V,
                                                 const double* __restrict__ w,
                                                 double* __restrict__ part, const KState* st) {
   if (st->done || st->cycle) return;
-  double acc[MAXM];
+  double acc[JB];
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) acc[i] = 0.0;
+  for (int i = 0; i < JB; ++i) acc[i] = 0.0;
   GRID_STRIDE(r, n) {
     const double wr = w[r];
-    double vr[MAXM];
+    double vr[JB];
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) vr[i] = i <= j ? V[i * ldv + r] : 0.0;
+    for (int i = 0; i < JB; ++i) vr[i] = i <= j ? V[i * ldv + r] : 0.0;
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) acc[i] += vr[i] * wr;
+    for (int i = 0; i < JB; ++i) acc[i] += vr[i] * wr;
   }
-  block_partials<MAXM>(acc, part);
+  block_partials_m<JB>(acc, part);
 }
 
 // w -= V h (first-pass coefficients); partials of V^T w on the updated rows
+template <int JB>
 __global__ __launch_bounds__(RB) void k_gm_orth(int64_t n, int64_t ldv, int j,
                                                 const double* __restrict__ V,
                                                 double* __restrict__ w,
                                                 double* __restrict__ part, const KState* st) {
   if (st->done || st->cycle) return;
-  __shared__ double h[MAXM];
-  if (threadIdx.x < MAXM)
+  __shared__ double h[JB];
+  if (threadIdx.x < JB)
     h[threadIdx.x] = (int)threadIdx.x <= j ? st->H[j * (MAXM + 1) + threadIdx.x] : 0.0;
   __syncthreads();
-  double acc[MAXM];
+  double acc[JB];
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) acc[i] = 0.0;
+  for (int i = 0; i < JB; ++i) acc[i] = 0.0;
   GRID_STRIDE(r, n) {
-    double vr[MAXM];
+    double vr[JB];
     double wr = w[r];
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
+    for (int i = 0; i < JB; ++i) {
       vr[i] = i <= j ? V[i * ldv + r] : 0.0;
       wr -= h[i] * vr[i];
     }
     w[r] = wr;
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) acc[i] += vr[i] * wr;
+    for (int i = 0; i < JB; ++i) acc[i] += vr[i] * wr;
   }
-  block_partials<MAXM>(acc, part);
+  block_partials_m<JB>(acc, part);
 }
 
 // w -= V h2; partials of w.w
+template <int JB>
 __global__ __launch_bounds__(RB) void k_gm_norm(int64_t n, int64_t ldv, int j,
                                                 const double* __restrict__ V,
                                                 double* __restrict__ w,
                                                 double* __restrict__ part, const KState* st) {
   if (st->done || st->cycle) return;
-  __shared__ double h[MAXM];
-  if (threadIdx.x < MAXM) h[threadIdx.x] = (int)threadIdx.x <= j ? st->h2[threadIdx.x] : 0.0;
+  __shared__ double h[JB];
+  if (threadIdx.x < JB) h[threadIdx.x] = (int)threadIdx.x <= j ? st->h2[threadIdx.x] : 0.0;
   __syncthreads();
   double acc[1] = {0.0};
   GRID_STRIDE(r, n) {
-    double vr[MAXM];
+    double vr[JB];
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) vr[i] = i <= j ? V[i * ldv + r] : 0.0;
+    for (int i = 0; i < JB; ++i) vr[i] = i <= j ? V[i * ldv + r] : 0.0;
     double wr = w[r];
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) wr -= h[i] * vr[i];
+    for (int i = 0; i < JB; ++i) wr -= h[i] * vr[i];
     w[r] = wr;
     acc[0] += wr * wr;
   }
@@ -453,17 +538,16 @@ __global__ __launch_bounds__(RB) void k_gm_fin(const double* __restrict__ part, 
   const int L = MAXM + 1;
   double* Hj = st->H + j * L;
   if (stage < 3) {
-    double out[MAXM];
-    finish<MAXM>(part, g, out);
-    if (threadIdx.x == 0)
-      for (int i = 0; i <= j; ++i) {
-        if (stage == 1) {
-          Hj[i] = out[i];
-        } else {
-          st->h2[i] = out[i];
-          Hj[i] += out[i];
-        }
+    const double out = finish_m(part, g);
+    const int i = threadIdx.x;
+    if (i <= j) {
+      if (stage == 1) {
+        Hj[i] = out;
+      } else {
+        st->h2[i] = out;
+        Hj[i] += out;
       }
+    }
     return;
   }
   double ww[1];
@@ -1681,6 +1765,29 @@ mxs_status solve_cgs(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double*
   }
 }
 
+// the three Gram-Schmidt passes of step j and their finishing kernels
+template <int JB>
+void gm_passes_jb(mxs_ctx* ctx, int g, int64_t n, size_t ld, int j, const double* V,
+                  double* wv, const Work& w) {
+  k_gm_dots<JB><<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pm, w.st);
+  k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pm, g, j, 1, w.st);
+  k_gm_orth<JB><<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pm, w.st);
+  k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pm, g, j, 2, w.st);
+  k_gm_norm<JB><<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pa, w.st);
+  k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pa, g, j, 3, w.st);
+}
+
+void gm_passes(mxs_ctx* ctx, int g, int64_t n, size_t ld, int j, const double* V, double* wv,
+               const Work& w) {
+  static_assert(MAXM == 32, "buckets of 8, 16 and 32 basis vectors");
+  if (j < 8)
+    gm_passes_jb<8>(ctx, g, n, ld, j, V, wv, w);
+  else if (j < 16)
+    gm_passes_jb<16>(ctx, g, n, ld, j, V, wv, w);
+  else
+    gm_passes_jb<32>(ctx, g, n, ld, j, V, wv, w);
+}
+
 mxs_status solve_gmres(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
                        const Stop& stop, int m, mxs_solve_info* info) {
   if (m < 1 || m > MAXM)
@@ -1727,12 +1834,7 @@ mxs_status solve_gmres(mxs_ctx* ctx, const mxs_matrix* A, const double* b, doubl
     for (int j = 0; j < m; ++j) {
       double* vj = V + (size_t)j * ld;
       if ((s = launch_spmv(ctx, A, &one, vj, &zero, wv, &w.st->cycle))) return s;
-      k_gm_dots<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pm, w.st);
-      k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pm, g, j, 1, w.st);
-      k_gm_orth<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pm, w.st);
-      k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pm, g, j, 2, w.st);
-      k_gm_norm<<<g, RB, 0, ctx->stream>>>(n, ld, j, V, wv, w.pa, w.st);
-      k_gm_fin<<<1, RB, 0, ctx->stream>>>(w.pa, g, j, 3, w.st);
+      gm_passes(ctx, g, n, ld, j, V, wv, w);
       k_gm_scale<<<g, RB, 0, ctx->stream>>>(n, wv, V + (size_t)(j + 1) * ld, w.st);
     }
     k_gm_backsolve<<<1, RB, 0, ctx->stream>>>(w.st);

@@ -129,15 +129,14 @@ __global__ __launch_bounds__(64 * WPB) void k_csr(int64_t nblocks,
 
   {
     int32_t c[NPL];
-    T v[NPL];
+    typename Raw<V>::type v[NPL];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const int k = t * 64 + lane;
-      c[t] = 0;
-      v[t] = 0;
+      c[t] = 0;  // (v[t] of an unused slot is never read)
       if (k < len) {
         c[t] = col[s + k];
-        v[t] = to_acc(val[s + k]);
+        v[t] = Raw<V>::load(val, s + k);
       }
     }
     // gathers issued for every slot (column 0 where the block has ended,
@@ -149,7 +148,7 @@ __global__ __launch_bounds__(64 * WPB) void k_csr(int64_t nblocks,
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const int k = t * 64 + lane;
-      if (k < len) prod[pad(k)] = v[t] * g[t];
+      if (k < len) prod[pad(k)] = to_acc(Raw<V>::value(v[t])) * g[t];
     }
   }
   for (int i = lane; i <= nr; i += 64) rp[i] = rowptr[r0 + i] - s;
