@@ -394,6 +394,12 @@ typedef struct {
   int64_t arena_used, arena_size;
 } mxs_batch_stats;
 
+/* Threads: submissions (mxs_batch_submit, mxs_batch_submit_many) may run on
+ * one thread while another steps, polls and lists completed tickets; the
+ * engine serializes its queue, pools and results internally and holds its
+ * lock neither while a submission validates and packs its inputs nor while
+ * a step is waited for.  Two steps, or create/destroy, must not overlap
+ * other calls on the same batch. */
 mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch** out);
 mxs_status mxs_batch_destroy(mxs_batch* batch);
 
@@ -450,6 +456,17 @@ mxs_status mxs_batch_submit_many(mxs_batch* batch, int64_t count, const mxs_batc
  * submit) and a finished slot's x is written by its work-group into pinned
  * host memory. */
 mxs_status mxs_batch_step(mxs_batch* batch, mxs_batch_stats* stats);
+
+/* mxs_batch_step in two halves, so that host work overlaps the device's.
+ * mxs_batch_step_launch admits waiting requests and launches the step
+ * without waiting for it; mxs_batch_step_finish waits for it, retires the
+ * finished systems and fills stats (nullable).  Between the two the caller
+ * may submit (the packing of new inputs then overlaps the step), poll and
+ * list completed tickets; a second launch before the finish, or a finish
+ * without a launch, returns MXS_INVALID_ARG.  mxs_batch_destroy waits for a
+ * launched step. */
+mxs_status mxs_batch_step_launch(mxs_batch* batch);
+mxs_status mxs_batch_step_finish(mxs_batch* batch, mxs_batch_stats* stats);
 
 /* MXS_PENDING while the request runs or waits; otherwise copies x (n
  * doubles) to x_host (nullable), fills info (nullable), forgets the ticket

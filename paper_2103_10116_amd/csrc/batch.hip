@@ -31,6 +31,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <unordered_map>
@@ -702,6 +703,8 @@ struct mxs_batch {
   mxs::SlotState* d_state = nullptr;
   mxs::SlotState* h_state = nullptr;   // pinned: read back by every step
   bool desc_dirty = true;
+  bool in_flight = false;  // a launched step not yet finished
+  int flight_active = 0;   // resident systems of the launched step
   uint32_t gen = 0;
   int nslots = 0;
   int K = 16;
@@ -719,6 +722,10 @@ struct mxs_batch {
   std::vector<uint64_t> newly_done;  // tickets retired since the last mxs_batch_completed
   uint64_t starve_ticket = 0;
   int64_t starve_steps = 0;
+  // guards the queue, the pools, the slots and the results, so that one
+  // thread may submit while another steps; held neither while inputs are
+  // validated and packed nor while a step is waited for
+  std::mutex mu;
 };
 
 namespace mxs {
@@ -823,6 +830,46 @@ bool validate_csr(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* col)
     if (s > rp[i - 1] && s < nnz) allowed += col[s] <= col[s - 1];
   }
   return descents == allowed;
+}
+
+// validate_csr and pack in one pass over rowptr and col: the checks run on
+// the values as they are copied (false leaves `dst` partly written)
+bool validate_pack(char* dst, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                   const double* val, const double* b) {
+  const Layout L = layout(n, nnz, 0);
+  if (rp[0] != 0 || rp[n] != nnz) return false;
+  int32_t* drp = (int32_t*)dst;
+  int bad = 0;
+  drp[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t v = rp[i + 1];
+    drp[i + 1] = v;
+    bad |= v < rp[i];
+  }
+  if (bad) return false;
+  const uint32_t un = (uint32_t)n;
+  int64_t descents = 0;
+  if (nnz) {
+    int32_t* dc = (int32_t*)(dst + L.col);
+    dc[0] = col[0];
+    bad |= (uint32_t)col[0] >= un;
+    for (int64_t k = 1; k < nnz; ++k) {
+      const int32_t c = col[k];
+      dc[k] = c;
+      bad |= (uint32_t)c >= un;
+      descents += c <= col[k - 1];
+    }
+  }
+  if (bad) return false;
+  int64_t allowed = 0;
+  for (int64_t i = 1; i < n; ++i) {
+    const int32_t st = rp[i];
+    if (st > rp[i - 1] && st < nnz) allowed += col[st] <= col[st - 1];
+  }
+  if (descents != allowed) return false;
+  if (nnz) std::memcpy(dst + L.val, val, nnz * 8);
+  std::memcpy(dst + L.b, b, n * 8);
+  return true;
 }
 
 // packs rowptr | col | val | b at `dst` in the arena layout
@@ -1119,6 +1166,7 @@ mxs_status mxs_batch_submit_many(mxs_batch* B, int64_t count, const mxs_batch_re
   mxs_ctx* ctx = B->ctx;
   // 1. sizes, class and budget, and a place in the pinned pool (in order)
   std::vector<Request> R((size_t)count);
+  std::unique_lock<std::mutex> lock(B->mu);
   for (int64_t i = 0; i < count; ++i) {
     const mxs_batch_request& q = reqs[i];
     tickets[i] = 0;
@@ -1170,17 +1218,21 @@ mxs_status mxs_batch_submit_many(mxs_batch* B, int64_t count, const mxs_batch_re
     // pack at admission
     r.packed = B->inpool.alloc(r.in_bytes, &r.in_off);
   }
+  lock.unlock();
   // 2. validate and pack / copy, on worker threads for large submissions
+  // (each request's pool region is its own until it is queued)
   std::vector<char> valid((size_t)count, 0);
   auto work = [&](int64_t i) {
     if (statuses[i] != MXS_OK) return;
     const mxs_batch_request& q = reqs[i];
     Request& r = R[i];
+    if (r.packed) {
+      valid[i] = validate_pack(B->in_mem + r.in_off, q.n, q.nnz, q.rowptr, q.col, q.val, q.b);
+      return;
+    }
     if (!validate_csr(q.n, q.nnz, q.rowptr, q.col)) return;
     valid[i] = 1;
-    if (r.packed) {
-      pack(B->in_mem + r.in_off, q.n, q.nnz, q.rowptr, q.col, q.val, q.b);
-    } else {
+    {
       r.rowptr.assign(q.rowptr, q.rowptr + q.n + 1);
       r.col.assign(q.col, q.col + q.nnz);
       r.val.assign(q.val, q.val + q.nnz);
@@ -1206,6 +1258,7 @@ mxs_status mxs_batch_submit_many(mxs_batch* B, int64_t count, const mxs_batch_re
     for (auto& t : pool) t.join();
   }
   // 3. queue the valid ones in order
+  lock.lock();
   for (int64_t i = 0; i < count; ++i) {
     if (statuses[i] != MXS_OK) continue;
     Request& r = R[i];
@@ -1231,9 +1284,11 @@ mxs_status mxs_batch_submit(mxs_batch* B, int64_t n, int64_t nnz, const int32_t*
   return call ? call : st;
 }
 
-mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
+mxs_status mxs_batch_step_launch(mxs_batch* B) {
   if (!B) return MXS_INVALID_ARG;
   mxs_ctx* ctx = B->ctx;
+  std::lock_guard<std::mutex> lock(B->mu);
+  if (B->in_flight) return fail(ctx, MXS_INVALID_ARG, "batch step launched twice without finish");
   MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
   // 1. admit in FIFO order, first fit: a request that does not fit (no free
   // slot in its class, or no arena gap) is passed over by later ones,
@@ -1325,8 +1380,24 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
     mxs_status st = upload_desc(B);
     if (st) return st;
     MXS_HIP_TRY(ctx, hipGraphLaunch(B->exec[mask], B->stream));
-    MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
   }
+  B->in_flight = true;
+  B->flight_active = active;
+  return MXS_OK;
+}
+
+mxs_status mxs_batch_step_finish(mxs_batch* B, mxs_batch_stats* stats) {
+  if (!B) return MXS_INVALID_ARG;
+  mxs_ctx* ctx = B->ctx;
+  std::unique_lock<std::mutex> lock(B->mu);
+  if (!B->in_flight) return fail(ctx, MXS_INVALID_ARG, "no batch step in flight");
+  int active = B->flight_active;
+  lock.unlock();
+  // wait without the lock, so that submissions proceed meanwhile
+  MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (active > 0) MXS_HIP_TRY(ctx, hipStreamSynchronize(B->stream));
+  lock.lock();
+  B->in_flight = false;
   // 3. every resident slot has copied its inputs by now; retire the
   // finished ones (their x is already in the pinned output)
   for (int i = 0; i < B->nslots && active > 0; ++i) {
@@ -1377,8 +1448,15 @@ mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
   return MXS_OK;
 }
 
+mxs_status mxs_batch_step(mxs_batch* B, mxs_batch_stats* stats) {
+  const mxs_status st = mxs_batch_step_launch(B);
+  if (st) return st;
+  return mxs_batch_step_finish(B, stats);
+}
+
 mxs_status mxs_batch_poll(mxs_batch* B, uint64_t ticket, double* x_host, mxs_solve_info* info) {
   if (!B) return MXS_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(B->mu);
   auto it = B->results.find(ticket);
   if (it == B->results.end() || !it->second.done) {
     if (ticket == 0 || ticket >= B->next_ticket) return MXS_INVALID_ARG;
@@ -1393,6 +1471,7 @@ mxs_status mxs_batch_poll(mxs_batch* B, uint64_t ticket, double* x_host, mxs_sol
 
 mxs_status mxs_batch_completed(mxs_batch* B, uint64_t* tickets, int64_t cap, int64_t* count) {
   if (!B || !count || (cap > 0 && !tickets)) return MXS_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(B->mu);
   const int64_t k = std::min<int64_t>(cap, (int64_t)B->newly_done.size());
   for (int64_t i = 0; i < k; ++i) tickets[i] = B->newly_done[i];
   B->newly_done.erase(B->newly_done.begin(), B->newly_done.begin() + k);

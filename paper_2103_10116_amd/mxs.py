@@ -146,6 +146,8 @@ _SIGS = {
                               C.POINTER(C.c_uint64)]),
     "mxs_batch_submit_many": (_S, [_P, _I64, _P, _P, _P]),
     "mxs_batch_step": (_S, [_P, C.POINTER(BatchStats)]),
+    "mxs_batch_step_launch": (_S, [_P]),
+    "mxs_batch_step_finish": (_S, [_P, C.POINTER(BatchStats)]),
     "mxs_batch_poll": (_S, [_P, C.c_uint64, _P, C.POINTER(SolveInfo)]),
     "mxs_batch_completed": (_S, [_P, C.POINTER(C.c_uint64), _I64, C.POINTER(_I64)]),
     "mxs_batch_config": (_S, [_P, _S, C.POINTER(_S), C.POINTER(_S), C.POINTER(_S),
@@ -520,6 +522,13 @@ def hbm_probe(ctx: Context, nbytes=1 << 30, reps=5) -> dict:
             "best_gbs": r.best_gbs}
 
 
+def _as(a, dt):
+    """a itself when it is already a C-contiguous array of dtype dt."""
+    if type(a) is np.ndarray and a.dtype == dt and a.flags.c_contiguous:
+        return a
+    return np.ascontiguousarray(a, dt)
+
+
 def gather_probe(ctx: Context, nx: int, count: int, value_bytes=8, reps=5) -> float:
     """Random gathers per second from an x of nx values (see mxs_gather_probe)."""
     r = C.c_double(0.0)
@@ -588,12 +597,25 @@ class Batch:
         k = len(systems)
         req = np.zeros(k, self._REQ)
         keep = []
+        ns = np.empty(k, np.int64)
+        nnzs = np.empty(k, np.int64)
+        ptrs = np.empty((4, k), np.uint64)
         for i, (A, b) in enumerate(systems):
-            arrs = (np.ascontiguousarray(A.rowptr, np.int32), np.ascontiguousarray(A.col, np.int32),
-                    np.ascontiguousarray(A.val, np.float64), np.ascontiguousarray(b, np.float64))
+            arrs = (_as(A.rowptr, np.int32), _as(A.col, np.int32), _as(A.val, np.float64),
+                    _as(b, np.float64))
             keep.append(arrs)
-            req[i] = (A.n, arrs[1].size, arrs[0].ctypes.data, arrs[1].ctypes.data,
-                      arrs[2].ctypes.data, arrs[3].ctypes.data, tol, max_iters, md, 0, inner_tol)
+            ns[i] = A.n
+            nnzs[i] = arrs[1].size
+            for q in range(4):
+                ptrs[q, i] = arrs[q].__array_interface__["data"][0]
+        req["n"] = ns
+        req["nnz"] = nnzs
+        for q, f in enumerate(("rowptr", "col", "val", "b")):
+            req[f] = ptrs[q]
+        req["rel_tol"] = tol
+        req["max_iters"] = max_iters
+        req["mode"] = md
+        req["inner_rel_tol"] = inner_tol
         tickets = np.zeros(k, np.uint64)
         statuses = np.zeros(k, np.int32)
         _check(_lib.mxs_batch_submit_many(self.handle, k, req.ctypes.data, tickets.ctypes.data,
@@ -604,6 +626,16 @@ class Batch:
     def step(self) -> dict:
         s = BatchStats()
         _check(_lib.mxs_batch_step(self.handle, C.byref(s)), self.ctx)
+        return {f: getattr(s, f) for f, _ in BatchStats._fields_}
+
+    def step_launch(self):
+        """First half of step(): admit and launch without waiting."""
+        _check(_lib.mxs_batch_step_launch(self.handle), self.ctx)
+
+    def step_finish(self) -> dict:
+        """Second half of step(): wait, retire, report."""
+        s = BatchStats()
+        _check(_lib.mxs_batch_step_finish(self.handle, C.byref(s)), self.ctx)
         return {f: getattr(s, f) for f, _ in BatchStats._fields_}
 
     def completed(self) -> list:

@@ -10,6 +10,7 @@ arrival time on the host's monotonic clock.
 """
 from __future__ import annotations
 
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -65,47 +66,76 @@ def _report(mode, reqs, arrival, done, iters, statuses, t_first, keep_x, xs, ste
 
 def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1024,
                 iters_per_step=16, classes=None, staging_bytes=0, mode="f64",
-                keep_x=False) -> ServeReport:
+                keep_x=False, chunk=512) -> ServeReport:
+    """Continuous batching.  A submitter thread hands arrived requests to the
+    engine (at most `chunk` per call) while the main thread steps: the host's
+    validation and packing of new requests overlaps the device's steps, and
+    requests join the batch at the next step after they are queued."""
     from . import mxs
     B = mxs.Batch(ctx, budget_bytes, max_slots, iters_per_step, classes, staging_bytes)
     order = sorted(reqs, key=lambda r: r.arrival)
-    ticket_of = {}
     rid_of = {}
     arrival, done, iters, statuses, xs = {}, {}, {}, {}, {}
-    i = 0
+    lock = threading.Lock()
+    failure = []
+    queued = [0]
+    t0 = time.perf_counter()
+
+    def submitter():
+        i = 0
+        try:
+            while i < len(order):
+                now = time.perf_counter() - t0
+                if order[i].arrival > now:
+                    time.sleep(order[i].arrival - now)
+                    continue
+                j = i
+                while j < len(order) and j - i < chunk and order[j].arrival <= now:
+                    j += 1
+                arrived = order[i:j]
+                tickets, sts = B.submit_many([systems[r.rid] for r in arrived], tol, mode=mode)
+                with lock:
+                    for r, t, s in zip(arrived, tickets.tolist(), sts.tolist()):
+                        if s != mxs.OK:
+                            raise mxs.MxsError(s, f"request {r.rid} rejected")
+                        rid_of[t] = r
+                        arrival[r.rid] = r.arrival
+                    queued[0] = j
+                i = j
+        except BaseException as e:  # reported by the stepping thread
+            failure.append(e)
+
+    th = threading.Thread(target=submitter, daemon=True)
+    th.start()
     steps = 0
     max_active = 0
-    t0 = time.perf_counter()
+    early = []   # retired before the submitter recorded their tickets
     while len(done) < len(order):
-        now = time.perf_counter() - t0
-        j = i
-        while j < len(order) and order[j].arrival <= now:
-            j += 1
-        if j > i:
-            # everything that arrived since the last step, in one call
-            arrived = order[i:j]
-            tickets, sts = B.submit_many([systems[r.rid] for r in arrived], tol, mode=mode)
-            for r, t, s in zip(arrived, tickets.tolist(), sts.tolist()):
-                if s != mxs.OK:
-                    raise mxs.MxsError(s, f"request {r.rid} rejected")
-                ticket_of[r.rid] = t
-                rid_of[t] = r
-                arrival[r.rid] = r.arrival
-            i = j
-        if len(arrival) > len(done):
-            st = B.step()
-            steps += 1
-            max_active = max(max_active, st["active"])
-            for t in B.completed():
-                r = rid_of[t]
-                s, x, res = B.poll(t, systems[r.rid][0].n)
-                done[r.rid] = time.perf_counter() - t0
-                iters[r.rid] = res.iters
-                statuses[r.rid] = s
-                if keep_x:
-                    xs[r.rid] = x
-        elif i < len(order):
-            time.sleep(max(0.0, order[i].arrival - (time.perf_counter() - t0)))
+        if failure:
+            th.join()
+            B.close()
+            raise failure[0]
+        with lock:
+            work = queued[0] > len(done)
+        if not work:
+            time.sleep(50e-6)
+            continue
+        st = B.step()
+        steps += 1
+        max_active = max(max_active, st["active"])
+        early.extend(B.completed())
+        with lock:
+            ready = [t for t in early if t in rid_of]
+            early = [t for t in early if t not in rid_of]
+            rs = [rid_of[t] for t in ready]
+        for t, r in zip(ready, rs):
+            s, x, res = B.poll(t, systems[r.rid][0].n)
+            done[r.rid] = time.perf_counter() - t0
+            iters[r.rid] = res.iters
+            statuses[r.rid] = s
+            if keep_x:
+                xs[r.rid] = x
+    th.join()
     B.close()
     return _report("batched" if mode == "f64" else f"batched_{mode}", order, arrival, done,
                    iters, statuses, order[0].arrival, keep_x, xs, steps, max_active)

@@ -271,3 +271,66 @@ def test_ir32_limits(env):
     s1, x1, r1 = B.poll(int(t[1]), A.n)
     assert s1 == mxs.OK and not x1.any() and r1.iters == 0
     B.close()
+
+
+def test_step_halves_and_submit_in_flight(env, orc):
+    """step_launch / step_finish: misuse is refused, and requests submitted
+    while a step runs are solved bitwise as when submitted before it."""
+    mxs, ctx, torch = env
+    B = mxs.Batch(ctx, 256 << 20, 16, iters_per_step=6)
+    with pytest.raises(mxs.MxsError):
+        B.step_finish()
+    B.step_launch()
+    with pytest.raises(mxs.MxsError):
+        B.step_launch()
+    B.step_finish()
+    first = _systems([12, 40, 90, 23], 500)
+    later = _systems([64, 8, 77, 31, 50], 600)
+    t1 = [B.submit(A, b, 1e-10) for A, b in first]
+    B.step_launch()
+    t2, sts = B.submit_many(later, 1e-10)           # packed while the step runs
+    assert all(s == mxs.OK for s in sts.tolist())
+    B.step_finish()
+    for _ in range(10000):
+        B.step_launch()
+        st = B.step_finish()
+        if st["active"] == 0 and st["pending"] == 0:
+            break
+    got = {}
+    for t, (A, b) in zip(t1 + t2.tolist(), first + later):
+        s, x, res = B.poll(t, A.n)
+        assert s == mxs.OK
+        r = b - orc.spmv_csr(A, x)
+        assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10 + _slack(orc, A, b, x)
+        got[id(A)] = x
+    B.close()
+    # the same systems through the synchronous step, all submitted first
+    B = mxs.Batch(ctx, 256 << 20, 16, iters_per_step=6)
+    tk = [B.submit(A, b, 1e-10) for A, b in first + later]
+    _drain(B)
+    for t, (A, b) in zip(tk, first + later):
+        s, x, _ = B.poll(t, A.n)
+        assert s == mxs.OK
+        assert np.array_equal(x.view(np.uint64), got[id(A)].view(np.uint64))
+    B.close()
+
+
+def test_serving_concurrent_submission_bitwise(env):
+    """The serving loop's submitter thread queues small chunks while the main
+    thread steps; every result is bitwise the one of a plain submit-then-drain
+    run of the same engine."""
+    mxs, ctx, torch = env
+    from paper_2103_10116_amd import serve
+    reqs = I.serving_stream(60, rate=0.0, seed=11)
+    systems = serve.build_systems(reqs)
+    rb = serve.run_batched(ctx, reqs, systems, budget_bytes=128 << 20, max_slots=24,
+                           iters_per_step=5, keep_x=True, chunk=5)
+    assert rb.statuses == {mxs.OK: 60}
+    B = mxs.Batch(ctx, 128 << 20, 24, iters_per_step=5)
+    tk = {r.rid: B.submit(*systems[r.rid], 1e-10) for r in reqs}
+    _drain(B)
+    for r in reqs:
+        s, x, _ = B.poll(tk[r.rid], systems[r.rid][0].n)
+        assert s == mxs.OK
+        assert np.array_equal(x.view(np.uint64), rb.x[r.rid].view(np.uint64)), r.rid
+    B.close()
