@@ -137,22 +137,23 @@ __device__ __forceinline__ void rows_times(const int32_t* __restrict__ rpl,
       int32_t c[LG];
       V v[LG];
       bool h[LG];
+      // every load of the group issued together: a slot past its row's end
+      // (or past n) reads entry 0 of the system, whose product is dropped
 #pragma unroll
       for (int u = 0; u < LG; ++u) {
         const int i = tid + (g + u) * BS;
         const bool in = g + u < RPT && i < n;
         const int32_t e = in ? rpl[i] + j : 0;
         h[u] = in && e < rpl[i + 1];
-        c[u] = 0;
-        v[u] = V(0);
-        if (h[u]) {
-          c[u] = col[e];
-          v[u] = val[e];
-        }
+        const int32_t es = h[u] ? e : 0;
+        c[u] = col[es];
+        v[u] = val[es];
       }
 #pragma unroll
-      for (int u = 0; u < LG; ++u)
-        if (h[u]) q[g + u] += v[u] * vec[c[u]];
+      for (int u = 0; u < LG; ++u) {
+        const V gv = vec[c[u]];
+        if (h[u]) q[g + u] += v[u] * gv;
+      }
     }
   }
 }
@@ -387,15 +388,15 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
     const uint4* __restrict__ src = D.src;
     uint4* __restrict__ dst = (uint4*)D.rowptr;
     const int words = D.in_words;
-    for (int w0 = tid; w0 < words; w0 += 4 * BS) {
-      uint4 v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (w0 + u * BS < words) v[u] = src[w0 + u * BS];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (w0 + u * BS < words) dst[w0 + u * BS] = v[u];
+    int w0 = tid;
+    for (; w0 + 3 * BS < words; w0 += 4 * BS) {  // four 16-byte loads in flight
+      const uint4 v0 = src[w0], v1 = src[w0 + BS], v2 = src[w0 + 2 * BS], v3 = src[w0 + 3 * BS];
+      dst[w0] = v0;
+      dst[w0 + BS] = v1;
+      dst[w0 + 2 * BS] = v2;
+      dst[w0 + 3 * BS] = v3;
     }
+    for (; w0 < words; w0 += BS) dst[w0] = src[w0];
     __threadfence_block();
     __syncthreads();
     if (MODE == 1) {
@@ -427,7 +428,11 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
     ir_body<BS, RPT, USE_LDS>(D, S, K, fresh, rpl, maxlen, dyn, red);
     return;
   }
-  double x[RPT], r[RPT], q[RPT];
+  // x stays in the slot's HBM vector instead of registers when a thread
+  // owns 10 or more rows (1024-thread classes run at 128 registers a lane)
+  constexpr bool XG = RPT >= 10;
+  double* __restrict__ xg = D.x;
+  double x[XG ? 1 : RPT], r[RPT], q[RPT];
   double rho, thr;
   int status = SLOT_RUN;
   int it = 0, repl = 0;
@@ -437,7 +442,11 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      x[k] = 0.0;
+      if constexpr (XG) {
+        if (i < n) xg[i] = 0.0;
+      } else {
+        x[k] = 0.0;
+      }
       r[k] = i < n ? b[i] : 0.0;
       if (i < n) vec[i] = r[k];
       acc += r[k] * r[k];
@@ -450,7 +459,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      x[k] = i < n ? D.x[i] : 0.0;
+      if constexpr (!XG) x[k] = i < n ? D.x[i] : 0.0;
       r[k] = i < n ? D.r[i] : 0.0;
       if (USE_LDS && i < n) vec[i] = pg[i];
     }
@@ -479,7 +488,11 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      if (i < n) x[k] += alpha * vec[i];
+      if constexpr (XG) {
+        if (i < n) xg[i] += alpha * vec[i];
+      } else {
+        if (i < n) x[k] += alpha * vec[i];
+      }
       r[k] -= alpha * q[k];
       acc += r[k] * r[k];
     }
@@ -494,7 +507,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int i = tid + k * BS;
-        if (i < n) vec[i] = x[k];
+        if (i < n) vec[i] = XG ? xg[i] : x[XG ? 0 : k];
       }
       __syncthreads();
       rows_times<BS, RPT>(rpl, col, val, vec, n, maxlen, q);
@@ -548,7 +561,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      if (i < n) xo[i] = x[k];
+      if (i < n) xo[i] = XG ? xg[i] : x[XG ? 0 : k];
     }
   } else {
     // p persists in HBM between launches
@@ -556,7 +569,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
       if (i < n) {
-        D.x[i] = x[k];
+        if constexpr (!XG) D.x[i] = x[k];
         D.r[i] = r[k];
         if (USE_LDS) pg[i] = vec[i];
       }
@@ -597,7 +610,9 @@ Layout layout(int64_t n, int64_t nnz, int mode) {
   L.r = L.x + up(n * 8);
   L.p = L.r + up(n * 8);
   L.v32 = L.p + up(n * 8);
-  L.total = L.v32 + (mode == 1 ? up(nnz * 4) : 0);
+  // (at least one FP32 value: the SpMV's loads of a system without entries
+  // read entry 0, which must lie inside the system's piece)
+  L.total = L.v32 + (mode == 1 ? up(std::max<int64_t>(nnz, 1) * 4) : 0);
   return L;
 }
 
@@ -1097,6 +1112,23 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
       break;
     }
     B->inpool.init(in_size);
+    // touch every page of the pools now, on up to 16 threads: the first
+    // write to a page of pinned memory costs several times a later one, and
+    // would otherwise land on the submissions of a running service
+    {
+      const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+      const size_t nt = std::max<size_t>(1, std::min<size_t>({(size_t)std::min(hw, 16u),
+                                                              in_size >> 24}));
+      const size_t per = (in_size / nt + 4095) / 4096 * 4096;
+      std::vector<std::thread> pool;
+      for (size_t t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+          const size_t a = std::min(in_size, t * per), e = std::min(in_size, a + per);
+          if (e > a) std::memset(B->in_mem + a, 0, e - a);
+        });
+      for (auto& th : pool) th.join();
+      std::memset(B->xout_mem, 0, xout_total * sizeof(double));
+    }
     B->arena_mem = (char*)ctx->alloc.alloc(opts->budget_bytes);
     if (!B->arena_mem) {
       st = fail(ctx, MXS_OOM, "cannot allocate the %zu-byte batch arena", opts->budget_bytes);
