@@ -525,6 +525,10 @@ def main():
               "system": "weighted 5-point Laplacian, m x m grid, m ~ U{8..96}, diagonal shift U[0,1]"}
         bkw = dict(budget_bytes=4 << 30, max_slots=2048, iters_per_step=16, classes=classes,
                    staging_bytes=4 << 30)
+        # untimed warm-up of both paths (first launches of their kernels)
+        serve.run_batched(ctx, closed[:256], systems, **bkw)
+        serve.run_batched(ctx, closed[:256], systems, mode="ir32", **bkw)
+        serve.run_plain(ctx, closed[:16], systems)
         rb = serve.run_batched(ctx, closed, systems, **bkw)
         sv["batched_closed"] = rb.summary()
         log("batched closed", sv["batched_closed"])

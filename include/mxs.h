@@ -376,7 +376,9 @@ typedef struct {
   size_t budget_bytes;      /* device arena for matrices and vectors */
   int32_t max_slots;        /* systems resident at once (all classes) */
   int32_t iters_per_step;   /* CG iterations per slot per step (0 = 16) */
-  int32_t nclasses;         /* 0 = defaults (n <= 1024, 2304, 4096, 10240) */
+  int32_t nclasses;         /* 0 = defaults (n <= 1024, 2304, 4096, 8192, 10240 with 256, 256,
+                               512, 1024, 1024 threads per system; below 5 slots the
+                               8192 class is left out) */
   int32_t class_max_n[8];   /* increasing upper bounds of n per class */
   int32_t class_block[8];   /* threads per system: 128, 256, 512 or 1024 (autotuner output) */
   int32_t class_slots[8];   /* slots per class; 0 = an even share of the rest */

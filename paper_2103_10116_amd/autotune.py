@@ -21,7 +21,7 @@ import numpy as np
 from . import inputs as I
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mxs", "autotune.json")
-CLASS_BOUNDS = (1024, 2304, 4096, 10240)
+CLASS_BOUNDS = (1024, 2304, 4096, 8192, 10240)
 BLOCKS = (128, 256, 512, 1024)
 
 

@@ -998,12 +998,17 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
   int nc = opts->nclasses;
   int max_n[kMaxClasses], block[kMaxClasses], nsl[kMaxClasses];
   if (nc <= 0) {
-    const int dn[4] = {1024, 2304, 4096, 10240}, db[4] = {256, 256, 512, 1024};
-    nc = 4;
-    for (int c = 0; c < nc; ++c) {
-      max_n[c] = dn[c];
-      block[c] = db[c];
-      nsl[c] = 0;
+    // (n <= 8192 and n <= 10240 are separate 1024-thread classes: 8 rows a
+    // thread fit the registers, 10 do not; with fewer than 5 slots the two
+    // are one class)
+    const int dn[5] = {1024, 2304, 4096, 8192, 10240}, db[5] = {256, 256, 512, 1024, 1024};
+    nc = 0;
+    for (int c = 0; c < 5; ++c) {
+      if (c == 3 && opts->max_slots < 5) continue;
+      max_n[nc] = dn[c];
+      block[nc] = db[c];
+      nsl[nc] = 0;
+      ++nc;
     }
   } else {
     if (nc > kMaxClasses) {

@@ -44,8 +44,8 @@ def _slack(orc, A, b, x):
 def test_default_classes(env):
     mxs, ctx, torch = env
     B = mxs.Batch(ctx, 64 << 20, 64)
-    cfg = [B.config(c) for c in range(4)]
-    assert [c["max_n"] for c in cfg] == [1024, 2304, 4096, 10240]
+    cfg = [B.config(c) for c in range(5)]
+    assert [c["max_n"] for c in cfg] == [1024, 2304, 4096, 8192, 10240]
     assert sum(c["slots"] for c in cfg) == 64
     assert all(c["block"] * c["rows_per_thread"] >= c["max_n"] for c in cfg)
     B.close()
