@@ -73,8 +73,8 @@ def measured_traffic(fmt, dt, info):
     ck = info["csr_kernel"]
     if fmt == "csr" and ck == 4:  # products through LDS
         keys.append((f"k_csr_pr<{t},{info['block_nnz']},false,{wpg}>", chunked))
-    if fmt == "csr" and ck == 3:  # rows from LDS, two waves per group
-        keys.append((f"k_csr_rl<{t},{info['block_nnz']},false,2>",
+    if fmt == "csr" and ck == 3:  # rows from LDS, two waves per group, G lanes per row
+        keys.append((f"k_csr_rl<{t},{info['block_nnz']},false,2,{info['lanes_per_row']}>",
                      -(-info["blocks"] // 2) * 128))
     if fmt == "csr" and ck == 1:
         keys.append((f"k_csr<{t},{npl},false,{wpg}>", chunked))

@@ -33,7 +33,10 @@ def _short(name: str) -> str:
         .replace("void ", "").split("(")[0]
 
 
-def stats(trace_csv: str, out: str, command: str, top: int = 30) -> None:
+def stats(trace_csv: str, out: str, command: str, top: int = 30,
+          always=("k_csr", "k_coo", "k_ell")) -> None:
+    """Per-kernel summary: the `top` kernel/grid pairs by total time, then
+    every SpMV kernel (names starting with one of `always`) not among them."""
     rows = list(csv.DictReader(open(trace_csv)))
     agg = collections.defaultdict(list)
     for r in rows:
@@ -43,13 +46,14 @@ def stats(trace_csv: str, out: str, command: str, top: int = 30) -> None:
              "| kernel | grid (threads) | wg | calls | mean us | median us | total ms |",
              "|---|---|---|---|---|---|---|"]
     ranked = sorted(agg.items(), key=lambda kv: -sum(kv[1]))
-    for (name, grid, wg), v in ranked[:top]:
+    shown = ranked[:top] + [kv for kv in ranked[top:] if kv[0][0].startswith(tuple(always))]
+    for (name, grid, wg), v in shown:
         v = sorted(v)
         lines.append(f"| `{name}` | {grid} | {wg} | {len(v)} | {sum(v)/len(v):.2f} | "
                      f"{v[len(v)//2]:.2f} | {sum(v)/1e3:.3f} |")
-    if len(ranked) > top:
-        rest = [t for _, v in ranked[top:] for t in v]
-        lines.append(f"| ({len(ranked) - top} more kernel/grid pairs) | | | {len(rest)} | | | "
+    if len(ranked) > len(shown):
+        rest = [t for kv in ranked if kv not in shown for t in kv[1]]
+        lines.append(f"| ({len(ranked) - len(shown)} more kernel/grid pairs) | | | {len(rest)} | | | "
                      f"{sum(rest)/1e3:.3f} |")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
