@@ -369,65 +369,16 @@ __device__ __forceinline__ void ir_body(const SlotDesc& D, SlotState* S, int K, 
 // gather vector (p, or x during the true-residual check); otherwise the
 // slot's p array in HBM serves as the gather vector.  x, r and q of the
 // thread's rows live in registers for the whole launch.
-template <int BS, int RPT, bool USE_LDS, int MODE>
-__global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ desc,
-                                                 SlotState* __restrict__ state, int base, int K,
-                                                 int vec_cap) {
-  extern __shared__ double dyn[];
-  __shared__ double red[BS / 64];
-  __shared__ int ired[BS / 64];
-  const SlotDesc& D = desc[base + blockIdx.x];
-  SlotState* S = state + base + blockIdx.x;
-  if (!D.active || D.mode != MODE) return;
-  const bool fresh = S->gen != D.gen;
-  if (!fresh && S->status >= SLOT_CONVERGED) return;
+// The FP64 CG of one slot for K iterations (the kernel's mode 0), with the
+// product q = A v supplied by `spmv`: streamed from the slot's arrays, or
+// from registers for systems small enough to hold there.
+template <int BS, int RPT, bool USE_LDS, typename F>
+__device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, bool fresh,
+                                        double* __restrict__ vec, double* __restrict__ pg,
+                                        double* red, F&& spmv) {
   const int n = D.n;
   const int tid = threadIdx.x;
-  if (fresh) {
-    // first launch: pull the packed inputs from pinned host memory
-    const uint4* __restrict__ src = D.src;
-    uint4* __restrict__ dst = (uint4*)D.rowptr;
-    const int words = D.in_words;
-    int w0 = tid;
-    for (; w0 + 3 * BS < words; w0 += 4 * BS) {  // four 16-byte loads in flight
-      const uint4 v0 = src[w0], v1 = src[w0 + BS], v2 = src[w0 + 2 * BS], v3 = src[w0 + 3 * BS];
-      dst[w0] = v0;
-      dst[w0 + BS] = v1;
-      dst[w0 + 2 * BS] = v2;
-      dst[w0 + 3 * BS] = v3;
-    }
-    for (; w0 < words; w0 += BS) dst[w0] = src[w0];
-    __threadfence_block();
-    __syncthreads();
-    if (MODE == 1) {
-      // refinement mode: the FP32 copy of the values, rounded to nearest
-      const double* __restrict__ v = D.val;
-      float* __restrict__ w = D.v32;
-      for (int k = tid; k < D.nnz; k += BS) w[k] = (float)v[k];
-      __threadfence_block();
-      __syncthreads();
-    }
-  }
-  const int32_t* __restrict__ rp = D.rowptr;
-  const int32_t* __restrict__ col = D.col;
-  const double* __restrict__ val = D.val;
   const double* __restrict__ b = D.b;
-  double* __restrict__ pg = D.p;
-  double* __restrict__ vec = USE_LDS ? dyn : pg;
-  int32_t* rpl = (int32_t*)(dyn + (USE_LDS ? vec_cap : 0));
-  int mylen = 0;
-  for (int i = tid; i <= n; i += BS) rpl[i] = rp[i];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * BS;
-    if (i < n) mylen = max(mylen, rpl[i + 1] - rpl[i]);
-  }
-  const int maxlen = bmax<BS>(mylen, ired);
-  if (MODE == 1) {
-    ir_body<BS, RPT, USE_LDS>(D, S, K, fresh, rpl, maxlen, dyn, red);
-    return;
-  }
   // x stays in the slot's HBM vector instead of registers when a thread
   // owns 10 or more rows (1024-thread classes run at 128 registers a lane)
   constexpr bool XG = RPT >= 10;
@@ -471,7 +422,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
   __syncthreads();
   double rr = rho;
   for (int s = 0; s < K && status == SLOT_RUN; ++s) {
-    rows_times<BS, RPT>(rpl, col, val, vec, n, maxlen, q);
+    spmv(vec, q);
     double pq = 0.0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -510,7 +461,7 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
         if (i < n) vec[i] = XG ? xg[i] : x[XG ? 0 : k];
       }
       __syncthreads();
-      rows_times<BS, RPT>(rpl, col, val, vec, n, maxlen, q);
+      spmv(vec, q);
       double tt = 0.0;
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
@@ -584,6 +535,110 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
     S->status = status;
     S->gen = D.gen;
   }
+}
+
+template <int BS, int RPT, bool USE_LDS, int MODE>
+__global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ desc,
+                                                 SlotState* __restrict__ state, int base, int K,
+                                                 int vec_cap) {
+  extern __shared__ double dyn[];
+  __shared__ double red[BS / 64];
+  __shared__ int ired[BS / 64];
+  const SlotDesc& D = desc[base + blockIdx.x];
+  SlotState* S = state + base + blockIdx.x;
+  if (!D.active || D.mode != MODE) return;
+  const bool fresh = S->gen != D.gen;
+  if (!fresh && S->status >= SLOT_CONVERGED) return;
+  const int n = D.n;
+  const int tid = threadIdx.x;
+  if (fresh) {
+    // first launch: pull the packed inputs from pinned host memory
+    const uint4* __restrict__ src = D.src;
+    uint4* __restrict__ dst = (uint4*)D.rowptr;
+    const int words = D.in_words;
+    int w0 = tid;
+    for (; w0 + 3 * BS < words; w0 += 4 * BS) {  // four 16-byte loads in flight
+      const uint4 v0 = src[w0], v1 = src[w0 + BS], v2 = src[w0 + 2 * BS], v3 = src[w0 + 3 * BS];
+      dst[w0] = v0;
+      dst[w0 + BS] = v1;
+      dst[w0 + 2 * BS] = v2;
+      dst[w0 + 3 * BS] = v3;
+    }
+    for (; w0 < words; w0 += BS) dst[w0] = src[w0];
+    __threadfence_block();
+    __syncthreads();
+    if (MODE == 1) {
+      // refinement mode: the FP32 copy of the values, rounded to nearest
+      const double* __restrict__ v = D.val;
+      float* __restrict__ w = D.v32;
+      for (int k = tid; k < D.nnz; k += BS) w[k] = (float)v[k];
+      __threadfence_block();
+      __syncthreads();
+    }
+  }
+  const int32_t* __restrict__ rp = D.rowptr;
+  const int32_t* __restrict__ col = D.col;
+  const double* __restrict__ val = D.val;
+  const double* __restrict__ b = D.b;
+  double* __restrict__ pg = D.p;
+  double* __restrict__ vec = USE_LDS ? dyn : pg;
+  int32_t* rpl = (int32_t*)(dyn + (USE_LDS ? vec_cap : 0));
+  int mylen = 0;
+  for (int i = tid; i <= n; i += BS) rpl[i] = rp[i];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * BS;
+    if (i < n) mylen = max(mylen, rpl[i + 1] - rpl[i]);
+  }
+  const int maxlen = bmax<BS>(mylen, ired);
+  if (MODE == 1) {
+    ir_body<BS, RPT, USE_LDS>(D, S, K, fresh, rpl, maxlen, dyn, red);
+    return;
+  }
+  // matrices small enough for registers (at most 24 entries a thread, 20 at
+  // 1024 threads, whose lanes have 128 registers; a row's entries at most
+  // that / RPT) are loaded once per launch and every product of the launch
+  // reads them there; the rest stream theirs
+  constexpr int ML = USE_LDS && RPT <= 4 ? (BS == 1024 ? 20 : 24) / RPT : 0;
+  if constexpr (ML > 0) {
+    if (maxlen <= ML) {
+      int32_t cr[RPT * ML];
+      double vr[RPT * ML];
+      uint32_t hm = 0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        const int32_t a = i < n ? rpl[i] : 0, e = i < n ? rpl[i + 1] : 0;
+#pragma unroll
+        for (int j = 0; j < ML; ++j) {
+          const bool h = a + j < e;
+          const int32_t es = h ? a + j : 0;
+          cr[k * ML + j] = col[es];
+          vr[k * ML + j] = val[es];
+          hm |= (h ? 1u : 0u) << (k * ML + j);
+        }
+      }
+      auto spmv_reg = [&](const double* __restrict__ v, double (&q)[RPT]) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < ML; ++j) {
+            const double g = v[cr[k * ML + j]];
+            if ((hm >> (k * ML + j)) & 1u) acc += vr[k * ML + j] * g;
+          }
+          q[k] = acc;
+        }
+      };
+      cg_body<BS, RPT, USE_LDS>(D, S, K, fresh, vec, pg, red, spmv_reg);
+      return;
+    }
+  }
+  auto spmv_mem = [&](const double* __restrict__ v, double (&q)[RPT]) {
+    rows_times<BS, RPT>(rpl, col, val, v, n, maxlen, q);
+  };
+  cg_body<BS, RPT, USE_LDS>(D, S, K, fresh, vec, pg, red, spmv_mem);
 }
 
 // ---------------------------------------------------------------------------
