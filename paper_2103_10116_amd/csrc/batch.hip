@@ -102,6 +102,22 @@ __device__ __forceinline__ double bsum(double v, double* red) {
   return s;
 }
 
+// bsum with one barrier: the caller alternates two `red` buffers between
+// consecutive calls, so a call's writes cannot meet the previous call's
+// reads (a barrier of the call in between orders them).  The barrier also
+// orders every read of shared memory before it against writes after it.
+template <int BS>
+__device__ __forceinline__ double bsum1(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int i = 1; i < BS / 64; ++i) s += red[i];
+  return s;
+}
+
 template <int BS>
 __device__ __forceinline__ int bmax(int v, int* red) {
 #pragma unroll
@@ -429,7 +445,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
       const int i = tid + k * BS;
       if (i < n) pq += vec[i] * q[k];
     }
-    pq = bsum<BS>(pq, red);
+    pq = bsum1<BS>(pq, red + BS / 64);
     if (!(pq > 0.0)) {
       status = isfinite(pq) ? SLOT_BREAKDOWN : SLOT_NONFINITE;
       break;
@@ -447,7 +463,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
       r[k] -= alpha * q[k];
       acc += r[k] * r[k];
     }
-    rr = bsum<BS>(acc, red);
+    rr = bsum1<BS>(acc, red + 2 * (BS / 64));
     ++it;
     if (!isfinite(rr)) {
       status = SLOT_NONFINITE;
@@ -542,7 +558,9 @@ __global__ __launch_bounds__(BS) void k_batch_cg(const SlotDesc* __restrict__ de
                                                  SlotState* __restrict__ state, int base, int K,
                                                  int vec_cap) {
   extern __shared__ double dyn[];
-  __shared__ double red[BS / 64];
+  // three reduction buffers: bsum's, and the two that the CG loop's
+  // one-barrier reductions alternate
+  __shared__ double red[3 * (BS / 64)];
   __shared__ int ired[BS / 64];
   const SlotDesc& D = desc[base + blockIdx.x];
   SlotState* S = state + base + blockIdx.x;
