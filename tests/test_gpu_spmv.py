@@ -339,8 +339,8 @@ def test_spmv_full_size(env, orc, which):
     scale32 = orc.absrow(A32, x32.astype(np.float64))
     M = mxs.Matrix.from_host(ctx, A)
     for fmt in FORMATS:
-        if fmt == "ell" and which.startswith("zipf"):
-            continue  # 4096-wide padded ELL of 2^20 rows: 51 GB; covered by the bench
+        if fmt == "ell" and which == "zipf_2p20_m16":
+            continue  # the same 4096-wide padded layout as zipf_2p20 (51.5 GB in FP64)
         B = M.convert(fmt, "f64")
         y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         mxs.spmv(ctx, B, _dev(torch, x), y)
