@@ -1051,6 +1051,331 @@ mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double
   return MXS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// one small system by pipelined CG (Ghysels & Vanroose 2014, unpreconditioned)
+// in one work-group of 1024 threads: the matrix lives in registers (rows
+// tid + k*1024, at most 20 entries a thread), the gather vector w in one of
+// two LDS buffers (w_{i+1} goes to the other one), so an iteration needs a
+// single barrier, the one that completes both the (gamma, delta) partials
+// and w_i.  The true-residual check and replacement follow the CG protocol
+// (at most three replacements, then restart with beta = 0).
+// ---------------------------------------------------------------------------
+struct PipeArgs {
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const double* b;
+  double* x;     // the iterate (x0 = 0 on the first launch)
+  double* vecs;  // r | w | z | s | p, ld doubles each, kept between launches
+  double tol;    // threshold on ||r|| relative to ||b||
+  int32_t n, ld, max_iters;
+};
+
+struct PipeState {
+  double gprev, aprev, res2, thr;  // thr: tol * ||b||, set by the first launch
+  int32_t iters, status, repl, restart, started, pad;
+};
+
+constexpr int kPipeBlock = 1024;
+
+template <int RPT>
+__global__ __launch_bounds__(kPipeBlock) void k_small_pipecg(PipeArgs a, PipeState* st, int K) {
+  constexpr int BS = kPipeBlock, ML = 20 / RPT;
+  extern __shared__ double dyn[];  // two gather buffers, then z and s, ld doubles each
+  __shared__ double red[2][2][BS / 64];
+  __shared__ double red2[BS / 64];
+  const int n = a.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // buffer 0 at dyn, buffer 1 at dyn + ld (chosen by ternaries, not an
+  // indexed pointer array, which would live in scratch)
+  double* const wb0 = dyn;
+  double* const wb1 = dyn + a.ld;
+  double* __restrict__ const zl = dyn + 2 * a.ld;  // a thread's own rows only
+  double* __restrict__ const sl = dyn + 3 * a.ld;
+  int32_t cr[RPT * ML];
+  double vr[RPT * ML];
+  uint32_t hm = 0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * BS;
+    const int32_t a0 = i < n ? a.rowptr[i] : 0, e0 = i < n ? a.rowptr[i + 1] : 0;
+#pragma unroll
+    for (int j = 0; j < ML; ++j) {
+      const bool h = a0 + j < e0;
+      const int32_t es = h ? a0 + j : 0;
+      cr[k * ML + j] = a.col[es] * (int32_t)sizeof(double);  // byte offset
+      vr[k * ML + j] = a.val[es];
+      hm |= (h ? 1u : 0u) << (k * ML + j);
+    }
+  }
+  auto spmv = [&](const double* __restrict__ v, double (&q)[RPT]) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < ML; ++j) {
+        const double g = *(const double*)((const char*)v + cr[k * ML + j]);
+        if ((hm >> (k * ML + j)) & 1u) acc += vr[k * ML + j] * g;
+      }
+      q[k] = acc;
+    }
+  };
+  double* __restrict__ R = a.vecs;
+  double* __restrict__ W = R + a.ld;
+  double* __restrict__ Z = W + a.ld;
+  double* __restrict__ Sg = Z + a.ld;
+  double* __restrict__ P = Sg + a.ld;
+  // p lives in HBM (P) like x, w only in its LDS buffer, z and s in LDS:
+  // the 1024-thread work-group has 128 registers a lane, and the matrix
+  // takes most of them
+  double r[RPT];
+  const PipeState ps = *st;
+  int status = SLOT_RUN, it = ps.iters, repl = ps.repl;
+  bool restart = ps.restart != 0;
+  double gprev = ps.gprev, aprev = ps.aprev, res2 = ps.res2, thr = ps.thr;
+  bool need_thr = !ps.started;
+  if (!ps.started) {
+    // x0 = 0: r = b, then w = A r (r staged in the second buffer)
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      r[k] = i < n ? a.b[i] : 0.0;
+      if (i < n) {
+        a.x[i] = 0.0;
+        P[i] = 0.0;
+        zl[i] = sl[i] = 0.0;
+        wb1[i] = r[k];
+      }
+    }
+    __syncthreads();
+    double w[RPT];
+    spmv(wb1, w);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) wb0[i] = w[k];
+    }
+    restart = true;
+  } else {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      r[k] = i < n ? R[i] : 0.0;
+      if (i < n) {
+        zl[i] = Z[i];
+        sl[i] = Sg[i];
+        wb0[i] = W[i];
+      }
+    }
+  }
+  // w_i lives in buffer `par` (a thread reads its own rows there); the
+  // loop-top barrier completes it
+  int par = 0;
+  for (int step = 0; step < K; ++step) {
+    double* __restrict__ other = par ? wb0 : wb1;
+    double* __restrict__ cur = par ? wb1 : wb0;
+    double gp = 0.0, dp = 0.0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      gp += r[k] * r[k];
+      if (i < n) dp += cur[i] * r[k];
+    }
+    gp = wave_sum(gp);
+    dp = wave_sum(dp);
+    if (lane == 0) {
+      red[par][0][wv] = gp;
+      red[par][1][wv] = dp;
+    }
+    __syncthreads();
+    double gm = red[par][0][0], dl = red[par][1][0];
+#pragma unroll
+    for (int q = 1; q < BS / 64; ++q) {
+      gm += red[par][0][q];
+      dl += red[par][1][q];
+    }
+    if (!isfinite(gm) || !isfinite(dl)) {
+      status = SLOT_NONFINITE;
+      break;
+    }
+    if (need_thr) {  // x0 = 0: the first gamma is ||b||^2
+      thr = a.tol * sqrt(gm);
+      need_thr = false;
+    }
+    if (sqrt(gm) <= thr) {
+      // true residual t = b - A x, x staged in the other buffer (its last
+      // readers, the previous product, are behind the barrier above)
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        if (i < n) other[i] = a.x[i];
+      }
+      __syncthreads();
+      double t[RPT];
+      spmv(other, t);
+      double tt = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        t[k] = i < n ? a.b[i] - t[k] : 0.0;
+        tt += t[k] * t[k];
+      }
+      tt = bsum<BS>(tt, red2);  // its barriers end every read of `other`
+      res2 = tt;
+      if (sqrt(tt) <= thr) {
+        status = SLOT_CONVERGED;
+        break;
+      }
+      if (repl >= 3) {
+        status = SLOT_NOTCONV;
+        break;
+      }
+      // replacement: r = t, w = A r, restart (beta = 0)
+      ++repl;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        r[k] = t[k];
+        if (i < n) {
+          zl[i] = sl[i] = 0.0;
+          other[i] = r[k];
+        }
+      }
+      __syncthreads();
+      double w[RPT];
+      spmv(other, w);
+      // nobody reads w_i's buffer before the next loop-top barrier
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        if (i < n) cur[i] = w[k];
+      }
+      restart = true;
+      continue;
+    }
+    double q[RPT];
+    spmv(cur, q);
+    double beta, den;
+    if (restart) {
+      beta = 0.0;
+      den = dl;
+    } else {
+      beta = gm / gprev;
+      den = dl - beta * gm / aprev;
+    }
+    if (!(den > 0.0)) {
+      status = isfinite(den) ? SLOT_BREAKDOWN : SLOT_NONFINITE;
+      break;
+    }
+    const double alpha = gm / den;
+    restart = false;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) {
+        const double wk = cur[i];
+        const double zk = q[k] + beta * zl[i];
+        const double sk = wk + beta * sl[i];
+        const double pk = r[k] + beta * P[i];
+        zl[i] = zk;
+        sl[i] = sk;
+        P[i] = pk;
+        a.x[i] += alpha * pk;
+        r[k] -= alpha * sk;
+        // w_{i+1}: its buffer's last readers are behind the barrier
+        other[i] = wk - alpha * zk;
+      }
+    }
+    gprev = gm;
+    aprev = alpha;
+    par ^= 1;
+    res2 = gm;
+    if (++it >= a.max_iters) {
+      status = SLOT_MAXIT;
+      break;
+    }
+  }
+  if (status == SLOT_RUN) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) {
+        R[i] = r[k];
+        W[i] = (par ? wb1 : wb0)[i];
+        Z[i] = zl[i];
+        Sg[i] = sl[i];
+      }
+    }
+  }
+  if (tid == 0) {
+    PipeState o;
+    o.gprev = gprev;
+    o.aprev = aprev;
+    o.res2 = res2;
+    o.thr = thr;
+    o.iters = it;
+    o.status = status;
+    o.repl = repl;
+    o.restart = restart ? 1 : 0;
+    o.started = 1;
+    o.pad = 0;
+    *st = o;
+  }
+}
+
+bool small_pipecg_fits(int64_t n, int64_t max_row) {
+  if (n < 1 || n > 4 * kPipeBlock) return false;
+  const int64_t rpt = (n + kPipeBlock - 1) / kPipeBlock;
+  const int64_t r = rpt <= 1 ? 1 : rpt <= 2 ? 2 : 4;
+  return max_row <= 20 / r;
+}
+
+size_t small_pipecg_scratch(int64_t n) {
+  return kAlign + 5 * up((size_t)n * sizeof(double));
+}
+
+mxs_status small_pipecg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double* out,
+                        double tol, int64_t max_iters, void* scratch, SmallCgResult* res) {
+  const int64_t n = A->n;
+  const size_t ld = up((size_t)n * sizeof(double)) / sizeof(double);
+  PipeState* d_st = (PipeState*)scratch;
+  PipeArgs a;
+  a.rowptr = A->csr.rowptr;
+  a.col = A->csr.col;
+  a.val = (const double*)A->csr.val;
+  a.b = rhs;
+  a.x = out;
+  a.vecs = (double*)((char*)scratch + kAlign);
+  a.tol = tol;
+  a.n = (int32_t)n;
+  a.ld = (int32_t)ld;
+  a.max_iters = (int32_t)std::min<int64_t>(max_iters, INT32_MAX);
+  const int64_t rpt = (n + kPipeBlock - 1) / kPipeBlock;
+  void (*k)(PipeArgs, PipeState*, int) =
+      rpt <= 1 ? k_small_pipecg<1> : rpt <= 2 ? k_small_pipecg<2> : k_small_pipecg<4>;
+  const size_t lds = 4 * ld * sizeof(double);
+  if (lds > 65536)
+    MXS_HIP_TRY(ctx, hipFuncSetAttribute((const void*)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  MXS_HIP_TRY(ctx, hipMemsetAsync(d_st, 0, sizeof(PipeState), ctx->stream));
+  PipeState hs;
+  std::memset(&hs, 0, sizeof(hs));
+  for (;;) {
+    hipLaunchKernelGGL(k, dim3(1), dim3(kPipeBlock), lds, ctx->stream, a, d_st, 1024);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(&hs, d_st, sizeof(hs), hipMemcpyDeviceToHost, ctx->stream));
+    MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (hs.status != 0 && hs.status != SLOT_RUN) break;
+  }
+  res->iters = hs.iters;
+  res->replacements = hs.repl;
+  res->res2 = hs.res2;
+  res->status = hs.status == SLOT_CONVERGED   ? MXS_OK
+                : hs.status == SLOT_BREAKDOWN ? MXS_BREAKDOWN
+                : hs.status == SLOT_NONFINITE ? MXS_NONFINITE
+                                              : MXS_NOT_CONVERGED;
+  return MXS_OK;
+}
+
 }  // namespace mxs
 
 using namespace mxs;

@@ -185,6 +185,14 @@ size_t small_cg_scratch(int64_t n);
 mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double* out,
                     double tol, int64_t max_iters, void* scratch, SmallCgResult* res);
 
+// Small systems (n <= 4096, at most 20 / ceil(n / 1024) entries a row) by
+// pipelined CG in one work-group, same contract as small_cg; scratch of
+// small_pipecg_scratch(n) device bytes.
+bool small_pipecg_fits(int64_t n, int64_t max_row);
+size_t small_pipecg_scratch(int64_t n);
+mxs_status small_pipecg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double* out,
+                        double tol, int64_t max_iters, void* scratch, SmallCgResult* res);
+
 // validated F64 (or C128) CSR matrix from host or device arrays (flags as
 // in mxs_matrix_create_csr); val == NULL gives zero values
 mxs_status create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,

@@ -1578,12 +1578,24 @@ mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, do
   }
 }
 
+// small systems for the one-work-group pipelined CG (see small_pipecg)
+bool small_pipe_path(const mxs_matrix* A, const Stop& stop) {
+  if (A->fmt != MXS_CSR || A->dt != MXS_F64 || stop.max_repl != 3 || A->n > 4096) return false;
+  int64_t maxL = 0;
+  for (int64_t i = 0; i < A->n; ++i)
+    maxL = std::max<int64_t>(maxL, A->h_rowptr[i + 1] - A->h_rowptr[i]);
+  return small_pipecg_fits(A->n, maxL);
+}
+
 mxs_status solve_pipecg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
                         const Stop& stop, mxs_solve_info* info) {
   const int64_t n = A->n;
   const size_t ld = align_up((size_t)n, 64);
+  const bool small = small_pipe_path(A, stop);
   Work w;
-  mxs_status s = get_work(ctx, 6 * ld * sizeof(double), &w);
+  mxs_status s = get_work(
+      ctx, 6 * ld * sizeof(double) + (small ? ld * sizeof(double) + small_pipecg_scratch(n) : 0),
+      &w);
   if (s) return s;
   double* r = (double*)w.vec;
   double* wv = r + ld;
@@ -1603,6 +1615,30 @@ mxs_status solve_pipecg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, doub
   const int g = red_grid(n);
   const double one = 1.0, zero = 0.0;
   KState& h = *w.hst;
+  if (small && nr0 > thr) {
+    // one work-group runs every iteration: A d = r0 from d = 0, then x += d
+    double* d = p + ld;
+    SmallCgResult sr;
+    if ((s = small_pipecg(ctx, A, r, d, thr / nr0, stop.max_iters, d + ld, &sr))) return s;
+    k_add<<<red_grid(n), RB, 0, ctx->stream>>>(n, x, d);
+    MXS_HIP_TRY(ctx, hipGetLastError());
+    double rt2;
+    if ((s = residual(ctx, A, b, x, r))) return s;
+    if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr,
+                          &rt2, nullptr)))
+      return s;
+    std::memset(&h, 0, sizeof(KState));
+    h.iters = sr.iters;
+    h.res2 = sr.res2;
+    mxs_status st = sr.status;
+    if (st == MXS_OK && !(sqrt(rt2) <= thr)) st = MXS_NOT_CONVERGED;
+    fill_info(info, h, base, sqrt(rt2) / base, sr.replacements, 0, st);
+    if (st == MXS_OK) return MXS_OK;
+    return fail(ctx, st, st == MXS_BREAKDOWN   ? "pipelined CG breakdown: p.Ap <= 0"
+                         : st == MXS_NONFINITE ? "non-finite value in pipelined CG"
+                                               : "pipelined CG stopped after %lld iterations, relres %.3e",
+                (long long)sr.iters, sqrt(rt2) / base);
+  }
   std::memset(&h, 0, sizeof(KState));
   h.thr = thr;
   h.max_iters = stop.max_iters;
