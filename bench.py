@@ -577,6 +577,39 @@ def main():
                                "sample": f"{reps} FP64 CSR products of the 27-point {N}^3 matrix "
                                          f"(accurate row sums, 1 thread), {tcpu:.3f} s each",
                                "cpu": _cpu_model()}
+        # the oracle's solvers on the same workloads (1 thread), beside the
+        # GPU's numbers: whole solves where they take well under a second,
+        # else a few iterations timed and reported per iteration
+        co = {"cores": 1, "kind": "oracle", "cpu": _cpu_model()}
+        P2 = I.poisson2d(64)
+        b2 = oracle.spmv_csr(P2, np.ones(P2.n))
+        t0 = time.perf_counter()
+        nrep = 0
+        while time.perf_counter() - t0 < 1.0:
+            rc = oracle.cg(P2, b2, tol=1e-10)
+            nrep += 1
+        t1 = (time.perf_counter() - t0) / nrep
+        co["cg_poisson2d_64"] = {"iters": rc.iters, "s_per_solve": round(t1, 5),
+                                 "solves_per_s": round(1.0 / t1, 1)}
+        CD = I.convdiff3d(N)
+        for label, Q, fn, its in (("cg_poisson3d_128", I.poisson3d(N), oracle.cg, 4),
+                                  ("bicgstab_convdiff3d_128", CD, oracle.bicgstab, 3),
+                                  ("gmres30_convdiff3d_128_first_steps", CD, oracle.gmres, 8)):
+            bq = oracle.spmv_csr(Q, I.uniform_vector(Q.n, I.VECTOR_SEED))
+            t0 = time.perf_counter()
+            rq = fn(Q, bq, tol=1e-10, maxit=its)
+            tq = time.perf_counter() - t0
+            co[label] = {"iters_timed": rq.iters, "s_per_iter": round(tq / max(rq.iters, 1), 4)}
+        reqs = I.serving_stream(100, rate=0.0)
+        sysm = [(I.serving_system(int(r.m), r.seed), I.serving_rhs(r.m * r.m, r.seed))
+                for r in reqs]
+        t0 = time.perf_counter()
+        for Aq, bq in sysm:
+            oracle.cg(Aq, bq, tol=1e-10)
+        ts = time.perf_counter() - t0
+        co["serving_cg_first_100"] = {"solves_per_s": round(len(sysm) / ts, 1)}
+        extra["cpu_oracle"] = co
+        log("cpu oracle", json.dumps(co))
     out["extra"] = extra
     print(json.dumps(out), flush=True)
     M.close()
