@@ -512,8 +512,10 @@ mxs_status mxs_hbm_probe(mxs_ctx* ctx, size_t bytes, int reps, mxs_bw_result* ou
 mxs_status mxs_gather_probe(mxs_ctx* ctx, int64_t nx, int64_t count, int value_bytes, int reps,
                             double* gathers_per_s);
 
-/* Writes `bytes` bytes of a ctx-owned scratch buffer so that later reads
- * come from HBM rather than from the last-level cache.  Asynchronous. */
+/* Reads `bytes` bytes of a ctx-owned scratch buffer (written once, when it
+ * is allocated or grown) so that later reads of other data come from HBM
+ * rather than from the last-level cache; the caches are left holding clean
+ * lines, so the next kernel pays no write-backs for them.  Asynchronous. */
 mxs_status mxs_flush_cache(mxs_ctx* ctx, size_t bytes);
 
 const char* mxs_status_string(mxs_status s);

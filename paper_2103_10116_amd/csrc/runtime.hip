@@ -202,14 +202,18 @@ __global__ __launch_bounds__(256) void k_fill(double2* __restrict__ a, int64_t n
   }
 }
 
-// a cache-evicting pass: read-modify-write of every line
+// a cache-evicting pass that only reads: the caches end up holding clean
+// lines of the buffer, so the next kernel's misses evict them without
+// write-backs (a writing pass would leave up to the Infinity Cache's size
+// of dirty lines for the timed kernel to write back)
 __global__ __launch_bounds__(256) void k_flush(double2* __restrict__ a, int64_t n2) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    double2 r = a[i];
-    r.x += 1.0;
-    a[i] = r;
+    const double2 r = a[i];
+    s += r.x + r.y;
   }
+  if (s == 1.2345e300) a[0].x = s;  // never true: keeps the reads
 }
 
 }  // namespace mxs
