@@ -523,7 +523,7 @@ def main():
         systems = serve.build_systems(closed)
         sv = {"requests": count, "tol": 1e-10,
               "system": "weighted 5-point Laplacian, m x m grid, m ~ U{8..96}, diagonal shift U[0,1]"}
-        bkw = dict(budget_bytes=4 << 30, max_slots=2048, iters_per_step=16, classes=classes,
+        bkw = dict(budget_bytes=4 << 30, max_slots=2048, iters_per_step=32, classes=classes,
                    staging_bytes=4 << 30)
         # untimed warm-up of both paths (first launches of their kernels)
         serve.run_batched(ctx, closed[:256], systems, **bkw)
