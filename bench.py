@@ -135,8 +135,8 @@ def main():
     ap.add_argument("--grid", type=int, default=128, help="stencil grid side (128 = full size)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "design is described in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding over "
+              "several GPUs is a design, not built", file=sys.stderr)
         sys.exit(2)
     sections = set(args.sections.split(","))
 
