@@ -241,8 +241,22 @@ __global__ __launch_bounds__(RB) void k_cg_pq(int64_t n, const T* __restrict__ p
                                               const T* __restrict__ q, double* __restrict__ pa,
                                               const KState* st) {
   if (st->done) return;
+  // four strided elements per round, their loads issued together; the sum
+  // still runs over the thread's elements in index order
+  const int64_t S = (int64_t)gridDim.x * RB;
+  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
   double acc[1] = {0.0};
-  GRID_STRIDE(i, n) acc[0] += (double)p[i] * (double)q[i];
+  for (; i + 3 * S < n; i += 4 * S) {
+    T pv[4], qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      pv[u] = p[i + u * S];
+      qv[u] = q[i + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[0] += (double)pv[u] * (double)qv[u];
+  }
+  for (; i < n; i += S) acc[0] += (double)p[i] * (double)q[i];
   block_partials<1>(acc, pa);
 }
 
@@ -263,7 +277,26 @@ __global__ __launch_bounds__(RB) void k_cg_update(int64_t n, T* __restrict__ x,
   if (lead()) st->alpha = alpha;
   const T a = (T)alpha;
   double acc[1] = {0.0};
-  GRID_STRIDE(i, n) {
+  const int64_t S = (int64_t)gridDim.x * RB;
+  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+  for (; i + 3 * S < n; i += 4 * S) {  // four strided elements, loads first
+    T xv[4], pv[4], rv[4], qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xv[u] = x[i + u * S];
+      pv[u] = p[i + u * S];
+      rv[u] = r[i + u * S];
+      qv[u] = q[i + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[i + u * S] = xv[u] + a * pv[u];
+      const T ri = rv[u] - a * qv[u];
+      r[i + u * S] = ri;
+      acc[0] += (double)ri * (double)ri;
+    }
+  }
+  for (; i < n; i += S) {
     x[i] += a * p[i];
     const T ri = r[i] - a * q[i];
     r[i] = ri;
@@ -297,7 +330,19 @@ __global__ __launch_bounds__(RB) void k_cg_direction(int64_t n, const T* __restr
   }
   if (bad || conv || maxit) return;
   const T beta = (T)(rn / st->rho[par]);
-  GRID_STRIDE(i, n) p[i] = r[i] + beta * p[i];
+  const int64_t S = (int64_t)gridDim.x * RB;
+  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+  for (; i + 3 * S < n; i += 4 * S) {  // four strided elements, loads first
+    T rv[4], pv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      rv[u] = r[i + u * S];
+      pv[u] = p[i + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) p[i + u * S] = rv[u] + beta * pv[u];
+  }
+  for (; i < n; i += S) p[i] = r[i] + beta * p[i];
 }
 
 // ---------------------------------------------------------------------------
