@@ -203,6 +203,36 @@ __device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x =
 #define GRID_STRIDE(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < (n); i += (int64_t)gridDim.x * RB)
 
+// The values one element of a vector kernel reads.
+template <typename T, int N>
+struct Pack {
+  T v[N];
+};
+
+// Visits the thread's grid-stride elements i = first, first + S, ... < n
+// (S = gridDim.x * RB) four per round: load(i) returns the Pack element i
+// reads, use(i, pack) does its arithmetic and stores.  A round issues the
+// loads of all four elements before the first use, so the memory system sees
+// four independent loads per vector instead of one; the uses run in index
+// order, so a sum over the thread's elements adds in the same order as a
+// plain grid-stride loop.
+template <typename Load, typename Use>
+__device__ __forceinline__ void strided4(int64_t n, Load load, Use use) {
+  const int64_t S = (int64_t)gridDim.x * RB;
+  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+  for (; i + 3 * S < n; i += 4 * S) {
+    const auto e0 = load(i);
+    const auto e1 = load(i + S);
+    const auto e2 = load(i + 2 * S);
+    const auto e3 = load(i + 3 * S);
+    use(i, e0);
+    use(i + S, e1);
+    use(i + 2 * S, e2);
+    use(i + 3 * S, e3);
+  }
+  for (; i < n; i += S) use(i, load(i));
+}
+
 // ---------------------------------------------------------------------------
 // generic reductions
 // ---------------------------------------------------------------------------
@@ -212,10 +242,17 @@ __global__ __launch_bounds__(RB) void k_dots(int64_t n, const T* __restrict__ a,
                                              const T* __restrict__ b, const T* __restrict__ c,
                                              const T* __restrict__ d, double* part) {
   double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    acc[0] += (double)a[i] * (double)b[i];
-    if (c) acc[1] += (double)c[i] * (double)d[i];
-  }
+  if (c)
+    strided4(
+        n, [&](int64_t i) { return Pack<T, 4>{{a[i], b[i], c[i], d[i]}}; },
+        [&](int64_t, const Pack<T, 4>& e) {
+          acc[0] += (double)e.v[0] * (double)e.v[1];
+          acc[1] += (double)e.v[2] * (double)e.v[3];
+        });
+  else
+    strided4(
+        n, [&](int64_t i) { return Pack<T, 2>{{a[i], b[i]}}; },
+        [&](int64_t, const Pack<T, 2>& e) { acc[0] += (double)e.v[0] * (double)e.v[1]; });
   block_partials<2>(acc, part);
 }
 
@@ -241,22 +278,10 @@ __global__ __launch_bounds__(RB) void k_cg_pq(int64_t n, const T* __restrict__ p
                                               const T* __restrict__ q, double* __restrict__ pa,
                                               const KState* st) {
   if (st->done) return;
-  // four strided elements per round, their loads issued together; the sum
-  // still runs over the thread's elements in index order
-  const int64_t S = (int64_t)gridDim.x * RB;
-  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
   double acc[1] = {0.0};
-  for (; i + 3 * S < n; i += 4 * S) {
-    T pv[4], qv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      pv[u] = p[i + u * S];
-      qv[u] = q[i + u * S];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[0] += (double)pv[u] * (double)qv[u];
-  }
-  for (; i < n; i += S) acc[0] += (double)p[i] * (double)q[i];
+  strided4(
+      n, [&](int64_t i) { return Pack<T, 2>{{p[i], q[i]}}; },
+      [&](int64_t, const Pack<T, 2>& e) { acc[0] += (double)e.v[0] * (double)e.v[1]; });
   block_partials<1>(acc, pa);
 }
 
@@ -277,31 +302,14 @@ __global__ __launch_bounds__(RB) void k_cg_update(int64_t n, T* __restrict__ x,
   if (lead()) st->alpha = alpha;
   const T a = (T)alpha;
   double acc[1] = {0.0};
-  const int64_t S = (int64_t)gridDim.x * RB;
-  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
-  for (; i + 3 * S < n; i += 4 * S) {  // four strided elements, loads first
-    T xv[4], pv[4], rv[4], qv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      xv[u] = x[i + u * S];
-      pv[u] = p[i + u * S];
-      rv[u] = r[i + u * S];
-      qv[u] = q[i + u * S];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      x[i + u * S] = xv[u] + a * pv[u];
-      const T ri = rv[u] - a * qv[u];
-      r[i + u * S] = ri;
-      acc[0] += (double)ri * (double)ri;
-    }
-  }
-  for (; i < n; i += S) {
-    x[i] += a * p[i];
-    const T ri = r[i] - a * q[i];
-    r[i] = ri;
-    acc[0] += (double)ri * (double)ri;
-  }
+  strided4(
+      n, [&](int64_t i) { return Pack<T, 4>{{x[i], p[i], r[i], q[i]}}; },
+      [&](int64_t i, const Pack<T, 4>& e) {
+        x[i] = e.v[0] + a * e.v[1];
+        const T ri = e.v[2] - a * e.v[3];
+        r[i] = ri;
+        acc[0] += (double)ri * (double)ri;
+      });
   block_partials<1>(acc, pb);
 }
 
@@ -330,19 +338,9 @@ __global__ __launch_bounds__(RB) void k_cg_direction(int64_t n, const T* __restr
   }
   if (bad || conv || maxit) return;
   const T beta = (T)(rn / st->rho[par]);
-  const int64_t S = (int64_t)gridDim.x * RB;
-  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
-  for (; i + 3 * S < n; i += 4 * S) {  // four strided elements, loads first
-    T rv[4], pv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      rv[u] = r[i + u * S];
-      pv[u] = p[i + u * S];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) p[i + u * S] = rv[u] + beta * pv[u];
-  }
-  for (; i < n; i += S) p[i] = r[i] + beta * p[i];
+  strided4(
+      n, [&](int64_t i) { return Pack<T, 2>{{r[i], p[i]}}; },
+      [&](int64_t i, const Pack<T, 2>& e) { p[i] = e.v[0] + beta * e.v[1]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -387,7 +385,9 @@ __global__ __launch_bounds__(RB) void k_bi_p(int64_t n, const double* __restrict
   }
   if (verdict != RUN) return;
   const double beta = (rhr / st->rho[par]) * (a / w);
-  GRID_STRIDE(i, n) p[i] = r[i] + beta * (p[i] - w * v[i]);
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 3>{{r[i], p[i], v[i]}}; },
+      [&](int64_t i, const Pack<double, 3>& e) { p[i] = e.v[0] + beta * (e.v[1] - w * e.v[2]); });
 }
 
 __global__ __launch_bounds__(RB) void k_bi_rv(int64_t n, const double* __restrict__ rh,
@@ -395,7 +395,9 @@ __global__ __launch_bounds__(RB) void k_bi_rv(int64_t n, const double* __restric
                                               double* __restrict__ pa, const KState* st) {
   if (st->done) return;
   double acc[1] = {0.0};
-  GRID_STRIDE(i, n) acc[0] += rh[i] * v[i];
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 2>{{rh[i], v[i]}}; },
+      [&](int64_t, const Pack<double, 2>& e) { acc[0] += e.v[0] * e.v[1]; });
   block_partials<1>(acc, pa);
 }
 
@@ -414,11 +416,13 @@ __global__ __launch_bounds__(RB) void k_bi_s(int64_t n, const double* __restrict
   const double a = st->rho[1 - par] / rv[0];
   if (lead()) st->alpha = a;
   double acc[1] = {0.0};
-  GRID_STRIDE(i, n) {
-    const double si = r[i] - a * v[i];
-    s[i] = si;
-    acc[0] += si * si;
-  }
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 2>{{r[i], v[i]}}; },
+      [&](int64_t i, const Pack<double, 2>& e) {
+        const double si = e.v[0] - a * e.v[1];
+        s[i] = si;
+        acc[0] += si * si;
+      });
   block_partials<1>(acc, pb);
 }
 
@@ -442,10 +446,12 @@ __global__ __launch_bounds__(RB) void k_bi_omega(int64_t n, const double* __rest
     return;
   }
   double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    acc[0] += t[i] * s[i];
-    acc[1] += t[i] * t[i];
-  }
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 2>{{t[i], s[i]}}; },
+      [&](int64_t, const Pack<double, 2>& e) {
+        acc[0] += e.v[0] * e.v[1];
+        acc[1] += e.v[0] * e.v[0];
+      });
   block_partials<2>(acc, pd);
 }
 
@@ -472,13 +478,15 @@ __global__ __launch_bounds__(RB) void k_bi_update(int64_t n, double* __restrict_
     st->iters = k + 1;
   }
   double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    x[i] = x[i] + a * p[i] + w * s[i];
-    const double ri = s[i] - w * t[i];
-    r[i] = ri;
-    acc[0] += ri * ri;
-    acc[1] += rh[i] * ri;
-  }
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 5>{{x[i], p[i], s[i], t[i], rh[i]}}; },
+      [&](int64_t i, const Pack<double, 5>& e) {
+        x[i] = e.v[0] + a * e.v[1] + w * e.v[2];
+        const double ri = e.v[2] - w * e.v[3];
+        r[i] = ri;
+        acc[0] += ri * ri;
+        acc[1] += e.v[4] * ri;
+      });
   block_partials<2>(acc, pc);
 }
 
@@ -489,7 +497,9 @@ __global__ __launch_bounds__(RB) void k_bi_half(int64_t n, double* __restrict__ 
                                                 const double* __restrict__ p,
                                                 const KState* st) {
   const double a = st->alpha;
-  GRID_STRIDE(i, n) x[i] += a * p[i];
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 2>{{x[i], p[i]}}; },
+      [&](int64_t i, const Pack<double, 2>& e) { x[i] = e.v[0] + a * e.v[1]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -656,7 +666,9 @@ __global__ __launch_bounds__(RB) void k_gm_scale(int64_t n, const double* __rest
                                                  double* __restrict__ vn, const KState* st) {
   if (st->done || st->cycle) return;
   const double inv = 1.0 / st->res2;
-  GRID_STRIDE(r, n) vn[r] = w[r] * inv;
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 1>{{w[i]}}; },
+      [&](int64_t i, const Pack<double, 1>& e) { vn[i] = e.v[0] * inv; });
 }
 
 // back substitution R y = g: the triangle is staged in LDS by all threads,
@@ -710,7 +722,9 @@ __global__ void k_gm_reset(KState* st) {
 __global__ __launch_bounds__(RB) void k_gm_start(int64_t n, const double* __restrict__ r,
                                                  double* __restrict__ v0, const KState* st) {
   const double inv = 1.0 / st->g[0];
-  GRID_STRIDE(i, n) v0[i] = r[i] * inv;
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 1>{{r[i]}}; },
+      [&](int64_t i, const Pack<double, 1>& e) { v0[i] = e.v[0] * inv; });
 }
 
 // ---------------------------------------------------------------------------
@@ -719,19 +733,25 @@ __global__ __launch_bounds__(RB) void k_gm_start(int64_t n, const double* __rest
 // f = float(r / sigma)
 __global__ __launch_bounds__(RB) void k_ir_scale(int64_t n, const double* __restrict__ r,
                                                  double sigma, float* __restrict__ f) {
-  GRID_STRIDE(i, n) f[i] = (float)(r[i] / sigma);
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 1>{{r[i]}}; },
+      [&](int64_t i, const Pack<double, 1>& e) { f[i] = (float)(e.v[0] / sigma); });
 }
 
 // x += d
 __global__ __launch_bounds__(RB) void k_add(int64_t n, double* __restrict__ x,
                                             const double* __restrict__ d) {
-  GRID_STRIDE(i, n) x[i] += d[i];
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 2>{{x[i], d[i]}}; },
+      [&](int64_t i, const Pack<double, 2>& e) { x[i] = e.v[0] + e.v[1]; });
 }
 
 // x += sigma * double(d)
 __global__ __launch_bounds__(RB) void k_ir_update(int64_t n, double* __restrict__ x,
                                                   const float* __restrict__ d, double sigma) {
-  GRID_STRIDE(i, n) x[i] += sigma * (double)d[i];
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 2>{{x[i], (double)d[i]}}; },
+      [&](int64_t i, const Pack<double, 2>& e) { x[i] = e.v[0] + sigma * e.v[1]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -794,28 +814,31 @@ __global__ __launch_bounds__(RB) void k_pipe_update(int64_t n, double* __restric
   }
   if (verdict != RUN) return;
   double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    double zi, si, pi;
-    if (fresh) {
-      zi = q[i];
-      si = w[i];
-      pi = r[i];
-    } else {
-      zi = q[i] + beta * z[i];
-      si = w[i] + beta * s[i];
-      pi = r[i] + beta * p[i];
-    }
+  // e = (q, w, r, x, z, s, p); a fresh recurrence (beta = 0) reads no z, s, p
+  const auto use = [&](int64_t i, const Pack<double, 7>& e) {
+    const double zi = e.v[0] + beta * e.v[4];
+    const double si = e.v[1] + beta * e.v[5];
+    const double pi = e.v[2] + beta * e.v[6];
     z[i] = zi;
     s[i] = si;
     p[i] = pi;
-    x[i] += alpha * pi;
-    const double ri = r[i] - alpha * si;
-    const double wi = w[i] - alpha * zi;
+    x[i] = e.v[3] + alpha * pi;
+    const double ri = e.v[2] - alpha * si;
+    const double wi = e.v[1] - alpha * zi;
     r[i] = ri;
     w[i] = wi;
     acc[0] += ri * ri;
     acc[1] += wi * ri;
-  }
+  };
+  if (fresh)
+    strided4(
+        n, [&](int64_t i) { return Pack<double, 7>{{q[i], w[i], r[i], x[i], 0.0, 0.0, 0.0}}; },
+        use);
+  else
+    strided4(
+        n,
+        [&](int64_t i) { return Pack<double, 7>{{q[i], w[i], r[i], x[i], z[i], s[i], p[i]}}; },
+        use);
   block_partials<2>(acc, pout);
 }
 
@@ -835,7 +858,9 @@ __global__ __launch_bounds__(RB) void k_cgs_sigma(int64_t n, const double* __res
                                                   double* __restrict__ pa, const KState* st) {
   if (st->done) return;
   double acc[1] = {0.0};
-  GRID_STRIDE(i, n) acc[0] += rh[i] * v[i];
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 2>{{rh[i], v[i]}}; },
+      [&](int64_t, const Pack<double, 2>& e) { acc[0] += e.v[0] * e.v[1]; });
   block_partials<1>(acc, pa);
 }
 
@@ -854,13 +879,15 @@ __global__ __launch_bounds__(RB) void k_cgs_qw(int64_t n, const double* __restri
   }
   const double a = st->rho[par] / sg[0];
   if (lead()) st->alpha = a;
-  GRID_STRIDE(i, n) {
-    const double qi = u[i] - a * v[i];
-    const double wi = u[i] + qi;
-    q[i] = qi;
-    w[i] = wi;
-    x[i] += a * wi;
-  }
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 3>{{u[i], v[i], x[i]}}; },
+      [&](int64_t i, const Pack<double, 3>& e) {
+        const double qi = e.v[0] - a * e.v[1];
+        const double wi = e.v[0] + qi;
+        q[i] = qi;
+        w[i] = wi;
+        x[i] = e.v[2] + a * wi;
+      });
 }
 
 __global__ __launch_bounds__(RB) void k_cgs_r(int64_t n, double* __restrict__ r,
@@ -870,12 +897,14 @@ __global__ __launch_bounds__(RB) void k_cgs_r(int64_t n, double* __restrict__ r,
   if (st->done) return;
   const double a = st->alpha;
   double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    const double ri = r[i] - a * v[i];
-    r[i] = ri;
-    acc[0] += ri * ri;
-    acc[1] += rh[i] * ri;
-  }
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 3>{{r[i], v[i], rh[i]}}; },
+      [&](int64_t i, const Pack<double, 3>& e) {
+        const double ri = e.v[0] - a * e.v[1];
+        r[i] = ri;
+        acc[0] += ri * ri;
+        acc[1] += e.v[2] * ri;
+      });
   block_partials<2>(acc, pb);
 }
 
@@ -907,11 +936,13 @@ __global__ __launch_bounds__(RB) void k_cgs_dir(int64_t n, const double* __restr
   }
   if (verdict != RUN) return;
   const double beta = rhr / st->rho[par];
-  GRID_STRIDE(i, n) {
-    const double ui = r[i] + beta * q[i];
-    u[i] = ui;
-    p[i] = ui + beta * (q[i] + beta * p[i]);
-  }
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 3>{{r[i], q[i], p[i]}}; },
+      [&](int64_t i, const Pack<double, 3>& e) {
+        const double ui = e.v[0] + beta * e.v[1];
+        u[i] = ui;
+        p[i] = ui + beta * (e.v[1] + beta * e.v[2]);
+      });
 }
 
 // ---------------------------------------------------------------------------
@@ -928,7 +959,9 @@ __global__ __launch_bounds__(RB) void k_cgs_dir(int64_t n, const double* __restr
 template <typename T>
 __global__ __launch_bounds__(RB) void k_jac_apply(int64_t n, const T* __restrict__ dinv,
                                                   const T* __restrict__ r, T* __restrict__ z) {
-  GRID_STRIDE(i, n) z[i] = dinv[i] * r[i];
+  strided4(
+      n, [&](int64_t i) { return Pack<T, 2>{{dinv[i], r[i]}}; },
+      [&](int64_t i, const Pack<T, 2>& e) { z[i] = e.v[0] * e.v[1]; });
 }
 
 // z = M^{-1} r for block Jacobi: a wave holds G = 64 / bs blocks, lane l
@@ -985,13 +1018,20 @@ __global__ __launch_bounds__(RB) void k_pcg_update(int64_t n, T* __restrict__ x,
   if (lead()) st->alpha = alpha;
   const T a = (T)alpha;
   double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    x[i] += a * p[i];
-    const T ri = r[i] - a * q[i];
+  // e = (x, p, r, q, dinv); block Jacobi reads no dinv
+  const auto use = [&](int64_t i, const Pack<T, 5>& e) {
+    x[i] = e.v[0] + a * e.v[1];
+    const T ri = e.v[2] - a * e.v[3];
     r[i] = ri;
-    if (PC == 1) acc[1] += (double)ri * (double)(dinv[i] * ri);
+    if (PC == 1) acc[1] += (double)ri * (double)(e.v[4] * ri);
     acc[0] += (double)ri * (double)ri;
-  }
+  };
+  strided4(
+      n,
+      [&](int64_t i) {
+        return Pack<T, 5>{{x[i], p[i], r[i], q[i], PC == 1 ? dinv[i] : T(0)}};
+      },
+      use);
   if (PC == 1) {
     block_partials<2>(acc, pb);
   } else {
@@ -1041,10 +1081,14 @@ __global__ __launch_bounds__(RB) void k_pcg_direction(int64_t n, const T* __rest
   }
   if (bad || conv || maxit || brk) return;
   const T beta = (T)(rz / st->rho[par]);
-  GRID_STRIDE(i, n) {
-    const T zi = PC == 1 ? dinv[i] * r[i] : z[i];
-    p[i] = zi + beta * p[i];
-  }
+  if (PC == 1)
+    strided4(
+        n, [&](int64_t i) { return Pack<T, 3>{{dinv[i], r[i], p[i]}}; },
+        [&](int64_t i, const Pack<T, 3>& e) { p[i] = e.v[0] * e.v[1] + beta * e.v[2]; });
+  else
+    strided4(
+        n, [&](int64_t i) { return Pack<T, 2>{{z[i], p[i]}}; },
+        [&](int64_t i, const Pack<T, 2>& e) { p[i] = e.v[0] + beta * e.v[1]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -1118,12 +1162,14 @@ __global__ __launch_bounds__(RB) void k_pr_update(int64_t n, double* __restrict_
   const double tele = (1.0 - damping) / nd;
   const double share = mass / nd;
   double acc[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    const double xn = damping * (z[i] + share) + tele;
-    acc[1] += fabs(xn - x[i]);
-    x[i] = xn;
-    if (mask[i]) acc[0] += xn;
-  }
+  strided4(
+      n, [&](int64_t i) { return Pack<double, 3>{{z[i], x[i], mask[i] ? 1.0 : 0.0}}; },
+      [&](int64_t i, const Pack<double, 3>& e) {
+        const double xn = damping * (e.v[0] + share) + tele;
+        acc[1] += fabs(xn - e.v[1]);
+        x[i] = xn;
+        if (e.v[2] != 0.0) acc[0] += xn;
+      });
   block_partials<2>(acc, pout);
 }
 
