@@ -127,6 +127,7 @@ typedef struct {
                              CSR rows-from-LDS kernel: 1, 2 or 4 lanes per row; 0 = the fewest that fill a wave */
   int32_t rows_per_group; /* CSR vector kernel: 2, 4 or 8 rows per lane group; 0 = default */
   int32_t waves_per_group;/* CSR stream / COO: independent waves per work-group, 1 or 4 (0 = 4) */
+  int32_t coo_kernel;     /* COO and the COO part of HYB: MXS_COO_AUTO, MXS_COO_LDS, MXS_COO_RUNS */
 } mxs_convert_opts;
 
 #define MXS_CSR_AUTO 0   /* STREAM if a row exceeds 64 entries; else ROWS_LDS for F32/F16
@@ -135,6 +136,14 @@ typedef struct {
 #define MXS_CSR_VECTOR 2
 #define MXS_CSR_ROWS_LDS 3 /* blocks of <= 64/G rows staged in LDS, G = 1, 2 or 4 lanes per row */
 #define MXS_CSR_PRODUCTS 4 /* blocks of <= 64 rows; products formed by all lanes, summed per row from LDS */
+
+#define MXS_COO_AUTO 0 /* RUNS for FP32/FP16 values when no row has more than 16 entries in
+                          the part, else LDS */
+#define MXS_COO_LDS 1  /* a chunk's col and val loaded coalesced (entry t*64 + lane) and the products
+                          staged in LDS; each lane then sums a run of consecutive entries, whose
+                          row indices it loads itself */
+#define MXS_COO_RUNS 2 /* each lane loads its run of consecutive entries itself (16-byte loads)
+                          and keeps it in registers; neighbouring rows by shuffles, no LDS */
 
 /* Converts `src` (an FP64 CSR matrix from mxs_matrix_create_csr) to another
  * format and value type, on the GPU.  Layouts (all int32 indices):
@@ -169,7 +178,8 @@ typedef struct {
   int32_t rows_per_group;
   int32_t waves_per_group;       /* CSR stream / COO work-group shape */
   int32_t csr_kernel;            /* CSR: the kernel in use (MXS_CSR_STREAM ... MXS_CSR_PRODUCTS) */
-  int32_t reserved;
+  int32_t coo_kernel;            /* COO / COO part of HYB: the kernel in use (MXS_COO_LDS or
+                                    MXS_COO_RUNS); other formats 0 */
 } mxs_matrix_desc;
 
 mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out);

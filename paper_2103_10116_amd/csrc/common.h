@@ -98,6 +98,7 @@ struct CooPart {
   int32_t* empty_rows = nullptr;
   int64_t nempty = 0;
   int wpb = 4;  // independent waves per work-group (1 or 4)
+  int kernel = MXS_COO_LDS;  // MXS_COO_LDS or MXS_COO_RUNS
 };
 
 // ELL: column-major padded slots; `waves` waves per 64 rows split the

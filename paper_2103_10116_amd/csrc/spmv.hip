@@ -534,143 +534,257 @@ __global__ __launch_bounds__(256) void k_csr_row(int64_t n, const int32_t* __res
 // ---------------------------------------------------------------------------
 // COO
 // ---------------------------------------------------------------------------
-template <typename V, typename T, int NPL, bool ACCUM, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
-                                                  const int32_t* __restrict__ row,
-                                                  const int32_t* __restrict__ col,
-                                                  const V* __restrict__ val,
-                                                  const T* __restrict__ x, T* __restrict__ y,
-                                                  T alpha, T beta,
-                                                  int32_t* __restrict__ cont_row,
-                                                  T* __restrict__ cont_val,
-                                                  const int32_t* __restrict__ skip) {
+// Loads the NPL consecutive elements p[0..NPL) into out: 16-byte loads when
+// VEC (p is 16-byte aligned) and the run is a whole number of them, else one
+// load each.
+template <int NPL, bool VEC, typename E>
+__device__ __forceinline__ void load_run(const E* __restrict__ p, E (&out)[NPL]) {
+  if constexpr (VEC && (NPL * sizeof(E)) % 16 == 0) {
+    constexpr int NW = (int)(NPL * sizeof(E) / 16);
+    uint4 w[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) w[j] = reinterpret_cast<const uint4*>(p)[j];
+    __builtin_memcpy(out, w, sizeof(out));
+  } else {
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) out[t] = p[t];
+  }
+}
+
+// COO, one wave per chunk of 64*NPL entries, each lane's run held in
+// registers: lane l loads entries l*NPL .. l*NPL+NPL-1 of the chunk itself
+// (16-byte loads of row, col and val; the arrays are padded to whole chunks,
+// so no load is masked), forms the products and sums the rows inside its
+// run.  A segmented scan over the lanes (a lane's value is the sum of its
+// last row; the flag says that row starts in the lane) joins rows across
+// lanes; neighbouring lanes' rows come by shuffles.  A row that continues
+// from the previous chunk leaves its partial in cont_row/cont_val for the
+// fix-up pass, so no floating-point atomics are used and the result does not
+// depend on scheduling.  k_coo adds in the same order (there the products
+// are rounded before they are added; here they may be fused into the adds).
+template <typename V, typename T, int NPL, bool ACCUM, int WPB, bool VEC>
+__global__ __launch_bounds__(64 * WPB) void k_coo_runs(int64_t nnz, int64_t nchunks,
+                                                      const int32_t* __restrict__ row,
+                                                      const int32_t* __restrict__ col,
+                                                      const V* __restrict__ val,
+                                                      const T* __restrict__ x, T* __restrict__ y,
+                                                      T alpha, T beta,
+                                                      int32_t* __restrict__ cont_row,
+                                                      T* __restrict__ cont_val,
+                                                      const int32_t* __restrict__ skip) {
   constexpr int C = 64 * NPL;
   if (skip && *skip) return;
-  __shared__ T prod_all[WPB][C + C / 32];
-  __shared__ int32_t rw_all[WPB][C + C / 32];
-  __shared__ int32_t edge_all[WPB][2];
   const int lane = threadIdx.x & 63;
-  // wave-uniform (scalar block-bound loads)
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  T* prod = prod_all[wv];
-  int32_t* rw = rw_all[wv];
-  int32_t* edge = edge_all[wv];
   const int64_t ch = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
   if (ch >= nchunks) return;
   const int64_t s = ch * C;
   const int len = (int)((nnz - s) < C ? (nnz - s) : C);
-  // rows just outside the chunk (lane 0 loads them with the entries; they
-  // reach LDS after the products, so no load waits on them)
-  int32_t e0 = -1, e1 = -1;
-  if (lane == 0) {
-    e0 = s > 0 ? row[s - 1] : -1;
-    e1 = (s + len < nnz) ? row[s + len] : -1;
-  }
-  {
-    int32_t r[NPL], c[NPL];
-    T v[NPL];
+  const int k0 = lane * NPL;
+  const int m = len - k0 < 0 ? 0 : (len - k0 < NPL ? len - k0 : NPL);  // entries of this lane
+  const int32_t e0 = s > 0 ? row[s - 1] : -1;  // row just before the chunk
+  // the arrays are padded to whole chunks with zeros, so every lane loads a
+  // full run; entries past len are never summed (their column 0 is gathered)
+  int32_t r[NPL], c[NPL];
+  V v[NPL];
+  load_run<NPL, VEC>(row + s + k0, r);
+  load_run<NPL, VEC>(col + s + k0, c);
+  load_run<NPL, VEC>(val + s + k0, v);
+  T prod[NPL];
 #pragma unroll
-    for (int t = 0; t < NPL; ++t) {
-      const int k = t * 64 + lane;
-      r[t] = c[t] = 0;
-      v[t] = 0;
-      if (k < len) {
-        r[t] = row[s + k];
-        c[t] = col[s + k];
-        v[t] = to_acc(val[s + k]);
-      }
-    }
-    // every gather in flight together (column 0 for unused slots, whose
-    // products are discarded)
-    T g[NPL];
+  for (int t = 0; t < NPL; ++t) prod[t] = x[c[t]];
 #pragma unroll
-    for (int t = 0; t < NPL; ++t) g[t] = x[c[t]];
-#pragma unroll
-    for (int t = 0; t < NPL; ++t) {
-      const int k = t * 64 + lane;
-      if (k < len) {
-        prod[pad(k)] = v[t] * g[t];
-        rw[pad(k)] = r[t];
-      }
-    }
-  }
-  if (lane == 0) {
-    edge[0] = e0;
-    edge[1] = e1;
-  }
-  wave_sync();
-  const int32_t first = rw[0];
-  const bool first_continues = edge[0] == first;
+  for (int t = 0; t < NPL; ++t) prod[t] = to_acc(v[t]) * prod[t];
 
-  auto emit = [&](int32_t r, T sum) {
-    if (first_continues && r == first) {
-      cont_row[ch] = r;
+  const int32_t first = __shfl(r[0], 0, 64);
+  const int32_t prev_last = __shfl_up(r[NPL - 1], 1, 64);
+  const int32_t next_first = __shfl_down(r[0], 1, 64);
+  const bool first_continues = e0 == first;
+
+  auto emit = [&](int32_t rr, T sum) {
+    if (first_continues && rr == first) {
+      cont_row[ch] = rr;
       cont_val[ch] = sum;
     } else if (ACCUM) {
-      y[r] = alpha * sum + y[r];
+      y[rr] = alpha * sum + y[rr];
     } else {
-      y[r] = combine(alpha, sum, beta, y, r);
+      y[rr] = combine(alpha, sum, beta, y, rr);
     }
   };
   if (lane == 0 && !first_continues) cont_row[ch] = -1;
 
-  const int k0 = lane * NPL;
-  const bool active = k0 < len;
-  const int k1 = min(k0 + NPL, len);
-  T v = 0, hsum = 0, tsum = 0;
+  const bool active = m > 0;
+  T vs = 0, hsum = 0, tsum = 0;
   int f = 1;
   int32_t hrow = 0, trow = 0;
   bool multi = false, hstart = false, tend = false;
   if (active) {
-    hrow = rw[pad(k0)];
-    hstart = (k0 == 0 ? edge[0] : rw[pad(k0 - 1)]) != hrow;
-    int32_t r = hrow;
+    hrow = r[0];
+    hstart = (lane == 0 ? e0 : prev_last) != hrow;
+    int32_t cur = hrow;
     T sum = 0;
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
-      const int k = k0 + t;
-      if (k < k1) {
-        const int32_t rk = rw[pad(k)];
-        if (rk != r) {
+      if (t < m) {
+        if (r[t] != cur) {
           if (!multi) {
             hsum = sum;
             multi = true;
           } else {
-            emit(r, sum);
+            emit(cur, sum);
           }
-          r = rk;
+          cur = r[t];
           sum = 0;
         }
-        sum += prod[pad(k)];
+        sum += prod[t];
       }
     }
-    trow = r;
+    trow = cur;
     tsum = sum;
-    // done within this chunk: the row ends here or the chunk ends here
-    tend = (k1 == len) || rw[pad(k1)] != r;
+    tend = (k0 + m == len) || next_first != cur;
     if (!multi) hsum = sum;
-    v = multi ? tsum : hsum;
+    vs = multi ? tsum : hsum;
     f = (multi || hstart) ? 1 : 0;
   }
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const T ov = __shfl_up(v, d, 64);
+    const T ov = __shfl_up(vs, d, 64);
     const int of = __shfl_up(f, d, 64);
     if (lane >= d) {
-      if (!f) v = ov + v;
+      if (!f) vs = ov + vs;
       f |= of;
     }
   }
-  // lane 0 has no predecessor: its head either starts here or continues a
-  // row from the previous chunk (that part is added by the fix-up pass)
-  const T up = __shfl_up(v, 1, 64);
+  const T up = __shfl_up(vs, 1, 64);
   const T before = lane > 0 ? up : T(0);
   if (active) {
     if (multi) {
       emit(hrow, hstart ? hsum : before + hsum);
       if (tend) emit(trow, tsum);
     } else if (tend) {
-      emit(hrow, v);
+      emit(hrow, vs);
+    }
+  }
+}
+
+// COO, products staged in LDS: a chunk's col and val are loaded coalesced
+// (slot t of lane l is entry t*64 + l), so neighbouring lanes gather
+// neighbouring entries' x; the products go to LDS and lane l reads back the
+// run l*NPL .. l*NPL+NPL-1, whose row indices it loads itself.  The run is
+// summed and rows are joined across lanes as in k_coo_runs.
+template <typename V, typename T, int NPL, bool ACCUM, int WPB, bool VEC>
+__global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
+                                                      const int32_t* __restrict__ row,
+                                                      const int32_t* __restrict__ col,
+                                                      const V* __restrict__ val,
+                                                      const T* __restrict__ x, T* __restrict__ y,
+                                                      T alpha, T beta,
+                                                      int32_t* __restrict__ cont_row,
+                                                      T* __restrict__ cont_val,
+                                                      const int32_t* __restrict__ skip) {
+  constexpr int C = 64 * NPL;
+  if (skip && *skip) return;
+  __shared__ T prod_all[WPB][C + C / 32];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T* prod = prod_all[wv];
+  const int64_t ch = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if (ch >= nchunks) return;
+  const int64_t s = ch * C;
+  const int len = (int)((nnz - s) < C ? (nnz - s) : C);
+  const int k0 = lane * NPL;
+  const int m = len - k0 < 0 ? 0 : (len - k0 < NPL ? len - k0 : NPL);
+  const int32_t e0 = s > 0 ? row[s - 1] : -1;
+  int32_t r[NPL];
+  {
+    // padded arrays: every slot of the chunk is loadable; slots past len
+    // gather x[0] and are never summed
+    int32_t c[NPL];
+    V v[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      c[t] = col[s + t * 64 + lane];
+      v[t] = val[s + t * 64 + lane];
+    }
+    load_run<NPL, VEC>(row + s + k0, r);
+    T g[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) g[t] = x[c[t]];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) prod[pad(t * 64 + lane)] = to_acc(v[t]) * g[t];
+  }
+  wave_sync();
+  const int32_t first = __shfl(r[0], 0, 64);
+  const int32_t prev_last = __shfl_up(r[NPL - 1], 1, 64);
+  const int32_t next_first = __shfl_down(r[0], 1, 64);
+  const bool first_continues = e0 == first;
+
+  auto emit = [&](int32_t rr, T sum) {
+    if (first_continues && rr == first) {
+      cont_row[ch] = rr;
+      cont_val[ch] = sum;
+    } else if (ACCUM) {
+      y[rr] = alpha * sum + y[rr];
+    } else {
+      y[rr] = combine(alpha, sum, beta, y, rr);
+    }
+  };
+  if (lane == 0 && !first_continues) cont_row[ch] = -1;
+
+  // the lane's products, all read before the first is used
+  T pv[NPL];
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) pv[t] = prod[pad(k0 + t)];
+  const bool active = m > 0;
+  T vs = 0, hsum = 0, tsum = 0;
+  int f = 1;
+  int32_t hrow = 0, trow = 0;
+  bool multi = false, hstart = false, tend = false;
+  if (active) {
+    hrow = r[0];
+    hstart = (lane == 0 ? e0 : prev_last) != hrow;
+    int32_t cur = hrow;
+    T sum = 0;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      if (t < m) {
+        if (r[t] != cur) {
+          if (!multi) {
+            hsum = sum;
+            multi = true;
+          } else {
+            emit(cur, sum);
+          }
+          cur = r[t];
+          sum = 0;
+        }
+        sum += pv[t];
+      }
+    }
+    trow = cur;
+    tsum = sum;
+    tend = (k0 + m == len) || next_first != cur;
+    if (!multi) hsum = sum;
+    vs = multi ? tsum : hsum;
+    f = (multi || hstart) ? 1 : 0;
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T ov = __shfl_up(vs, d, 64);
+    const int of = __shfl_up(f, d, 64);
+    if (lane >= d) {
+      if (!f) vs = ov + vs;
+      f |= of;
+    }
+  }
+  const T up = __shfl_up(vs, 1, 64);
+  const T before = lane > 0 ? up : T(0);
+  if (active) {
+    if (multi) {
+      emit(hrow, hstart ? hsum : before + hsum);
+      if (tend) emit(trow, tsum);
+    } else if (tend) {
+      emit(hrow, vs);
     }
   }
 }
@@ -906,19 +1020,37 @@ void launch_coo_chunks(mxs_ctx* ctx, const CooPart& P, T alpha, const T* x, T be
   const V* val = (const V*)P.val;
   const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
   T* cv = (T*)P.cont_val;
-  switch (P.block_nnz) {
-    case 256:
-      k_coo<V, T, 4, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
-      break;
-    case 1024:
-      k_coo<V, T, 16, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
-      break;
-    default:
-      k_coo<V, T, 8, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+  if (P.kernel == MXS_COO_RUNS) {
+    const bool vec = (((uintptr_t)P.row | (uintptr_t)P.col | (uintptr_t)val) & 15) == 0;
+#define MXS_COO_RUNS_CASE(NN)                                                           \
+  if (vec)                                                                              \
+    k_coo_runs<V, T, NN, ACCUM, WPB, true><<<grid, 64 * WPB, 0, ctx->stream>>>(         \
+        P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);  \
+  else                                                                                  \
+    k_coo_runs<V, T, NN, ACCUM, WPB, false><<<grid, 64 * WPB, 0, ctx->stream>>>(        \
+        P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+    switch (P.block_nnz) {
+      case 256: MXS_COO_RUNS_CASE(4) break;
+      case 1024: MXS_COO_RUNS_CASE(16) break;
+      default: MXS_COO_RUNS_CASE(8)
+    }
+#undef MXS_COO_RUNS_CASE
+    return;
   }
+  const bool vec = ((uintptr_t)P.row & 15) == 0;
+#define MXS_COO_LDS_CASE(NN)                                                           \
+  if (vec)                                                                             \
+    k_coo<V, T, NN, ACCUM, WPB, true><<<grid, 64 * WPB, 0, ctx->stream>>>(             \
+        P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip); \
+  else                                                                                 \
+    k_coo<V, T, NN, ACCUM, WPB, false><<<grid, 64 * WPB, 0, ctx->stream>>>(            \
+        P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+  switch (P.block_nnz) {
+    case 256: MXS_COO_LDS_CASE(4) break;
+    case 1024: MXS_COO_LDS_CASE(16) break;
+    default: MXS_COO_LDS_CASE(8)
+  }
+#undef MXS_COO_LDS_CASE
 }
 
 template <typename V, typename T, bool ACCUM>

@@ -51,12 +51,14 @@ class ConvertOpts(C.Structure):
     _fields_ = [("ell_width", C.c_int64), ("max_ell_bytes", C.c_int64),
                 ("block_nnz", C.c_int32), ("csr_kernel", C.c_int32),
                 ("lanes_per_row", C.c_int32), ("rows_per_group", C.c_int32),
-                ("waves_per_group", C.c_int32)]
+                ("waves_per_group", C.c_int32), ("coo_kernel", C.c_int32)]
 
 
 CSR_AUTO, CSR_STREAM, CSR_VECTOR, CSR_ROWS_LDS, CSR_PRODUCTS = 0, 1, 2, 3, 4
 CSR_KERNELS = {"auto": CSR_AUTO, "stream": CSR_STREAM, "vector": CSR_VECTOR,
                "rows_lds": CSR_ROWS_LDS, "products": CSR_PRODUCTS}
+COO_AUTO, COO_LDS, COO_RUNS = 0, 1, 2
+COO_KERNELS = {"auto": COO_AUTO, "lds": COO_LDS, "runs": COO_RUNS}
 
 
 class MatrixDesc(C.Structure):
@@ -66,7 +68,7 @@ class MatrixDesc(C.Structure):
                 ("bytes", C.c_int64), ("block_nnz", C.c_int32),
                 ("lanes_per_row", C.c_int32), ("rows_per_group", C.c_int32),
                 ("waves_per_group", C.c_int32), ("csr_kernel", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("coo_kernel", C.c_int32)]
 
 
 class Stop(C.Structure):
@@ -289,10 +291,11 @@ class Matrix:
 
     def convert(self, fmt="csr", dtype="f64", ell_width=0, max_ell_bytes=0,
                 block_nnz=0, csr_kernel="auto", lanes_per_row=0,
-                rows_per_group=0, waves_per_group=0) -> "Matrix":
+                rows_per_group=0, waves_per_group=0, coo_kernel="auto") -> "Matrix":
         o = ConvertOpts(int(ell_width), int(max_ell_bytes), int(block_nnz),
                         CSR_KERNELS.get(csr_kernel, csr_kernel), int(lanes_per_row),
-                        int(rows_per_group), int(waves_per_group))
+                        int(rows_per_group), int(waves_per_group),
+                        COO_KERNELS.get(coo_kernel, coo_kernel))
         h = C.c_void_p()
         _check(_lib.mxs_matrix_convert(self.ctx.handle, self.handle, FORMATS.get(fmt, fmt),
                                        DTYPES.get(dtype, dtype), C.byref(o), C.byref(h)),

@@ -257,6 +257,58 @@ def test_spmv_csr_kernels(env, orc, name, dt):
 
 
 @pytest.mark.parametrize("name", sorted(ZOO))
+@pytest.mark.parametrize("kernel", ["lds", "runs"])
+def test_spmv_coo_kernels(env, orc, name, kernel):
+    """Both COO kernels (and the COO part of HYB, which the power-law matrices
+    have at a forced width) at every chunk size and work-group shape, FP64
+    and FP32; chunks of 256 entries leave ragged last chunks on every matrix."""
+    mxs, ctx, torch = env
+    A = ZOO[name]
+    M = mxs.Matrix.from_host(ctx, A)
+    x = I.uniform_vector(A.ncols, 21)
+    y0 = I.uniform_vector(A.n, 22)
+    _, v32 = orc.cast_f32(A.val)
+    A32 = I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, v32.astype(np.float64))
+    fmts = [("coo", 0)] + ([("hyb", 2)] if name.startswith("zipf") else [])
+    for fmt, width in fmts:
+        for dt, tdt, Ar, tol in (("f64", torch.float64, A, 1e-13),
+                                 ("f32", torch.float32, A32, 1e-5)):
+            xr = x.astype(np.float32).astype(np.float64) if dt == "f32" else x
+            yr = y0.astype(np.float32).astype(np.float64) if dt == "f32" else y0
+            ref = orc.spmv_csr(Ar, xr, 1.5, -0.5, yr)
+            scale = 1.5 * orc.absrow(Ar, xr) + 0.5 * np.abs(yr)
+            for bn in (256, 512, 1024):
+                for wpg in (1, 4):
+                    B = M.convert(fmt, dt, block_nnz=bn, waves_per_group=wpg,
+                                  coo_kernel=kernel, ell_width=width)
+                    d = B.info()
+                    assert d["block_nnz"] == bn and d["waves_per_group"] == wpg
+                    if d["coo_nnz"]:
+                        assert d["coo_kernel"] == mxs.COO_KERNELS[kernel]
+                    y = torch.from_numpy(yr).to(tdt).cuda()
+                    mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
+                    _check(y.cpu().numpy().astype(np.float64), ref, scale, tol)
+                    B.close()
+
+
+def test_coo_kernel_auto_choice(env):
+    """AUTO keeps runs in registers for FP32 values when no row has more
+    than 16 entries and stages products through LDS otherwise; an unknown
+    kernel is rejected."""
+    mxs, ctx, torch = env
+    for name, want in (("poisson2d_64", mxs.COO_RUNS), ("conv_13", mxs.COO_RUNS),
+                       ("zipf_3000", mxs.COO_LDS), ("st27_9", mxs.COO_LDS)):
+        A = ZOO[name]
+        assert (A.row_lengths().max() <= 16) == (want == mxs.COO_RUNS)
+        M = mxs.Matrix.from_host(ctx, A)
+        assert M.convert("coo", "f32").info()["coo_kernel"] == want
+        assert M.convert("coo", "f64").info()["coo_kernel"] == mxs.COO_LDS
+        assert M.convert("csr", "f64").info()["coo_kernel"] == 0
+    with pytest.raises(mxs.MxsError):
+        M.convert("coo", "f64", coo_kernel=3)
+
+
+@pytest.mark.parametrize("name", sorted(ZOO))
 @pytest.mark.parametrize("fmt", FORMATS)
 def test_spmv_f32(env, orc, name, fmt):
     mxs, ctx, torch = env
@@ -338,15 +390,18 @@ def test_spmv_full_size(env, orc, which):
     ref32 = orc.spmv_csr(A32, x32.astype(np.float64))
     scale32 = orc.absrow(A32, x32.astype(np.float64))
     M = mxs.Matrix.from_host(ctx, A)
-    for fmt in FORMATS:
+    # COO in both kernels (AUTO picks one of them)
+    cases = [("csr", {}), ("coo", {"coo_kernel": "lds"}), ("coo", {"coo_kernel": "runs"}),
+             ("ell", {}), ("hyb", {})]
+    for fmt, opts in cases:
         if fmt == "ell" and which == "zipf_2p20_m16":
             continue  # the same 4096-wide padded layout as zipf_2p20 (51.5 GB in FP64)
-        B = M.convert(fmt, "f64")
+        B = M.convert(fmt, "f64", **opts)
         y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         mxs.spmv(ctx, B, _dev(torch, x), y)
         _check(y.cpu().numpy(), ref, scale, 1e-13)
         del B
-        B = M.convert(fmt, "f32")
+        B = M.convert(fmt, "f32", **opts)
         y = torch.zeros(A.n, dtype=torch.float32, device="cuda")
         mxs.spmv(ctx, B, _dev(torch, x32), y)
         _check(y.cpu().numpy().astype(np.float64), ref32, scale32, 1e-5)
