@@ -72,6 +72,12 @@ struct SlotDesc {
   float* v32;          // arena, refinement mode: the values rounded to FP32
   int32_t mode;        // 0: FP64 CG; 1: FP32-storage CG inside FP64 refinement
   float inner_tol;     // refinement mode: inner relative tolerance
+  // a single solve (FP64 CG): x holds x0, the first launch forms
+  // r0 = b - A x0 and stops at max(tol * base, abs_tol), base = ||r0|| when
+  // base_r0, else ||b||; b = 0 gives x = 0.  Otherwise x0 = 0 and the
+  // threshold is tol * ||b||.
+  int32_t x0_given, base_r0;
+  double abs_tol;
 };
 
 // written by the kernel, read back after every launch
@@ -83,15 +89,50 @@ struct SlotState {
   // inner iterations of the current inner solve, phase, outer steps
   double ithr, rn;
   int32_t inner, phase, outer, pad;
+  double base;  // FP64 CG: the norm the threshold is relative to
 };
 
 enum : int32_t { PH_OUTER = 0, PH_INNER = 1 };
 constexpr int kIrOuterMax = 50;
 constexpr int kIrInnerMax = 20000;
 
+// A double moved across lanes by a DPP pattern (both 32-bit halves alike).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+// Sum over the wave, the same value in every lane.  Within each row of 16
+// lanes, DPP moves add the neighbour (lane ^ 1), the other pair of the quad
+// (lane ^ 2), the mirrored quad of the half and the mirrored half of the row;
+// the two operands of each add are the same two values in either lane, so
+// every lane of a row ends with the same row sum.  The four row sums are then
+// read from lanes 15, 31, 47 and 63 and added in row order.  DPP moves cost a
+// few cycles where the cross-lane shuffles of a butterfly go through the LDS
+// crossbar; the batched kernels take two such sums per CG iteration.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return ((lane_value(v, 15) + lane_value(v, 31)) + lane_value(v, 47)) + lane_value(v, 63);
+}
+
 template <int BS>
 __device__ __forceinline__ double bsum(double v, double* red) {
-  v = wave_sum(v);
+  v = wave_total(v);
   const int w = threadIdx.x / 64;
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
@@ -108,7 +149,7 @@ __device__ __forceinline__ double bsum(double v, double* red) {
 // orders every read of shared memory before it against writes after it.
 template <int BS>
 __device__ __forceinline__ double bsum1(double v, double* red) {
-  v = wave_sum(v);
+  v = wave_total(v);
   const int w = threadIdx.x / 64;
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
@@ -403,7 +444,55 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
   double rho, thr;
   int status = SLOT_RUN;
   int it = 0, repl = 0;
-  if (fresh) {
+  double base = 0.0;
+  if (fresh && D.x0_given) {
+    // r0 = b - A x0 (x0 staged in the gather vector), ||b|| and ||r0||
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      const double xi = i < n ? D.x[i] : 0.0;
+      if constexpr (!XG) x[k] = xi;
+      if (i < n) vec[i] = xi;
+    }
+    __syncthreads();
+    spmv(vec, q);
+    double bb = 0.0, acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      const double bi = i < n ? b[i] : 0.0;
+      r[k] = i < n ? bi - q[k] : 0.0;
+      bb += bi * bi;
+      acc += r[k] * r[k];
+    }
+    const double nb2 = bsum<BS>(bb, red);  // its barriers end every read of vec
+    rho = bsum<BS>(acc, red);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * BS;
+      if (i < n) vec[i] = r[k];
+    }
+    base = D.base_r0 ? sqrt(rho) : sqrt(nb2);
+    thr = fmax(D.tol * base, D.abs_tol);
+    if (!isfinite(nb2) || !isfinite(rho)) {
+      status = SLOT_NONFINITE;
+    } else if (nb2 == 0.0) {
+      // b = 0: the solution is x = 0
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * BS;
+        if constexpr (XG) {
+          if (i < n) xg[i] = 0.0;
+        } else {
+          x[k] = 0.0;
+        }
+      }
+      rho = 0.0;
+      status = SLOT_CONVERGED;
+    } else if (sqrt(rho) <= thr) {
+      status = SLOT_CONVERGED;  // x0 is the answer; rho is its true residual
+    }
+  } else if (fresh) {
     // x0 = 0: r = b, p = r, thr = tol * ||b||
     double acc = 0.0;
 #pragma unroll
@@ -419,7 +508,8 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
       acc += r[k] * r[k];
     }
     rho = bsum<BS>(acc, red);
-    thr = D.tol * sqrt(rho);
+    base = sqrt(rho);
+    thr = D.tol * base;
     if (!isfinite(rho)) status = SLOT_NONFINITE;
     if (rho == 0.0) status = SLOT_CONVERGED;  // b = 0: x = 0
   } else {
@@ -434,6 +524,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
     thr = S->thr;
     it = S->iters;
     repl = S->repl;
+    base = S->base;
   }
   __syncthreads();
   double rr = rho;
@@ -549,6 +640,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
     S->iters = it;
     S->repl = repl;
     S->status = status;
+    S->base = base;
     S->gen = D.gen;
   }
 }
@@ -993,30 +1085,39 @@ bool small_cg_fits(int64_t n, int64_t max_row) { return n >= 1 && n <= 8192 && m
 
 size_t small_cg_scratch(int64_t n) { return 2 * kAlign + 2 * up((size_t)n * sizeof(double)); }
 
-mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double* out,
-                    double tol, int64_t max_iters, void* scratch, SmallCgResult* res) {
+mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
+                    double rel_tol, double abs_tol, bool base_r0, int64_t max_iters,
+                    void* scratch, void* pinned, SmallCgResult* res) {
+  static_assert(sizeof(SlotDesc) <= kAlign && sizeof(SlotState) <= kAlign, "staging layout");
   const int64_t n = A->n;
+  // device: desc | state | r | p; pinned: desc | zeroed state (uploaded
+  // together) | the state read back after each launch
   char* base = (char*)scratch;
   SlotDesc* d_desc = (SlotDesc*)base;
   SlotState* d_state = (SlotState*)(base + kAlign);
   double* r = (double*)(base + 2 * kAlign);
   double* p = (double*)(base + 2 * kAlign + up((size_t)n * sizeof(double)));
-  SlotDesc hd;
-  std::memset(&hd, 0, sizeof(hd));
+  char* hp = (char*)pinned;
+  std::memset(hp, 0, 2 * kAlign);
+  SlotDesc& hd = *(SlotDesc*)hp;
+  SlotState& hs = *(SlotState*)(hp + 2 * kAlign);
   hd.rowptr = A->csr.rowptr;
   hd.col = A->csr.col;
   hd.val = (double*)A->csr.val;
-  hd.b = const_cast<double*>(rhs);
-  hd.x = out;
+  hd.b = const_cast<double*>(b);
+  hd.x = x;
   hd.r = r;
   hd.p = p;
-  hd.xout = out;
-  hd.tol = tol;
+  hd.xout = x;
+  hd.tol = rel_tol;
+  hd.abs_tol = abs_tol;
+  hd.x0_given = 1;
+  hd.base_r0 = base_r0 ? 1 : 0;
   hd.n = (int32_t)n;
   hd.nnz = (int32_t)A->nnz;
   hd.max_iters = (int32_t)std::min<int64_t>(max_iters, INT32_MAX);
   hd.active = 1;
-  hd.gen = 1;
+  hd.gen = 1;  // the zeroed state's gen differs: the first launch starts fresh
   ClassCfg C{};
   C.max_n = (int)n;
   C.block = kSmallBlock;
@@ -1028,15 +1129,12 @@ mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double
     MXS_HIP_TRY(ctx, hipFuncSetAttribute((const void*)k,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   }
-  MXS_HIP_TRY(ctx, hipMemcpyAsync(d_desc, &hd, sizeof(hd), hipMemcpyHostToDevice, ctx->stream));
-  MXS_HIP_TRY(ctx, hipMemsetAsync(d_state, 0, sizeof(SlotState), ctx->stream));
-  SlotState hs;
-  std::memset(&hs, 0, sizeof(hs));
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(d_desc, hp, 2 * kAlign, hipMemcpyHostToDevice, ctx->stream));
   for (;;) {
     hipLaunchKernelGGL(k, dim3(1), dim3(C.block), lds, ctx->stream, d_desc, d_state, 0, 1024,
                        C.max_n);
     MXS_HIP_TRY(ctx, hipGetLastError());
-    MXS_HIP_TRY(ctx, hipMemcpyAsync(&hs, d_state, sizeof(hs), hipMemcpyDeviceToHost,
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(&hs, d_state, sizeof(SlotState), hipMemcpyDeviceToHost,
                                     ctx->stream));
     MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (hs.status >= SLOT_CONVERGED) break;
@@ -1044,6 +1142,7 @@ mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double
   res->iters = hs.iters;
   res->replacements = hs.repl;
   res->res2 = hs.res2;
+  res->base = hs.base;
   res->status = hs.status == SLOT_CONVERGED   ? MXS_OK
                 : hs.status == SLOT_BREAKDOWN ? MXS_BREAKDOWN
                 : hs.status == SLOT_NONFINITE ? MXS_NONFINITE
@@ -1180,8 +1279,8 @@ __global__ __launch_bounds__(kPipeBlock) void k_small_pipecg(PipeArgs a, PipeSta
       gp += r[k] * r[k];
       if (i < n) dp += cur[i] * r[k];
     }
-    gp = wave_sum(gp);
-    dp = wave_sum(dp);
+    gp = wave_total(gp);
+    dp = wave_total(dp);
     if (lane == 0) {
       red[par][0][wv] = gp;
       red[par][1][wv] = dp;

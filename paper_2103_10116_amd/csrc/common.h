@@ -179,12 +179,19 @@ int64_t csr_partition(const int32_t* rowptr, int64_t n, int block_nnz,
 struct SmallCgResult {
   int64_t iters = 0, replacements = 0;
   double res2 = 0.0;   // last squared residual norm (true one when converged)
+  double base = 0.0;   // the norm the threshold is relative to
   mxs_status status = MXS_OK;
 };
 bool small_cg_fits(int64_t n, int64_t max_row);
 size_t small_cg_scratch(int64_t n);
-mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* rhs, double* out,
-                    double tol, int64_t max_iters, void* scratch, SmallCgResult* res);
+constexpr size_t kSmallCgPinned = 768;  // pinned staging bytes small_cg needs
+// FP64 CG on one small CSR system in one work-group, from x0 = x (updated in
+// place): r0 = b - A x0, the threshold max(rel_tol * base, abs_tol) with
+// base = ||r0|| (base_r0) or ||b||, every iteration and the true-residual
+// check run in the kernel; b = 0 gives x = 0.
+mxs_status small_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
+                    double rel_tol, double abs_tol, bool base_r0, int64_t max_iters,
+                    void* scratch, void* pinned, SmallCgResult* res);
 
 // Small systems (n <= 4096, at most 20 / ceil(n / 1024) entries a row) by
 // pipelined CG in one work-group, same contract as small_cg; scratch of

@@ -1341,14 +1341,57 @@ bool small_path(const mxs_matrix* A, const Stop& stop) {
   return small_cg_fits(A->n, maxL);
 }
 
+// CG on a small CSR system: one work-group runs the whole solve (initial
+// residual, norms, iterations, true-residual check) and x is updated in
+// place; the host only reads the final state.
+mxs_status solve_cg_small(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
+                          const Stop& stop, mxs_solve_info* info) {
+  const int64_t n = A->n;
+  if (!ws_reserve(ctx, small_cg_scratch(n)))
+    return fail(ctx, MXS_OOM, "solver workspace of %zu bytes", small_cg_scratch(n));
+  if (!pinned_reserve(ctx, kSmallCgPinned)) return fail(ctx, MXS_OOM, "pinned staging");
+  SmallCgResult sr;
+  mxs_status s = small_cg(ctx, A, b, x, stop.rel_tol, stop.abs_tol,
+                          stop.baseline == MXS_BASELINE_INITIAL, stop.max_iters, ctx->ws.ptr,
+                          ctx->pinned, &sr);
+  if (s) return s;
+  const double base = sr.base > 0 ? sr.base : 1.0;
+  KState h{};
+  h.iters = sr.iters;
+  h.res2 = sr.res2;
+  if (sr.status == MXS_OK) {
+    // res2 is the kernel's true residual of the returned x (0 when b = 0)
+    fill_info(info, h, base, sqrt(sr.res2) / base, sr.replacements, 0, MXS_OK);
+    return MXS_OK;
+  }
+  if (sr.status == MXS_NONFINITE) {
+    fill_info(info, h, base, NAN, sr.replacements, 0, MXS_NONFINITE);
+    return fail(ctx, MXS_NONFINITE, "non-finite value in CG (right-hand side, x0 or iterate)");
+  }
+  // stopped early: the true residual of the returned x for the report
+  const size_t ld = align_up((size_t)n, 64);
+  Work w;
+  if ((s = get_work(ctx, ld * sizeof(double), &w))) return s;
+  double* r = (double*)w.vec;
+  double rt2;
+  if ((s = residual(ctx, A, b, x, r))) return s;
+  if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr, &rt2,
+                        nullptr)))
+    return s;
+  fill_info(info, h, base, sqrt(rt2) / base, sr.replacements, 0, sr.status);
+  return fail(ctx, sr.status, sr.status == MXS_BREAKDOWN
+                                  ? "CG breakdown: p.Ap <= 0 (matrix not SPD)"
+                                  : "CG stopped after %lld iterations, relres %.3e",
+              (long long)sr.iters, sqrt(rt2) / base);
+}
+
 mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* x,
                     const Stop& stop, mxs_solve_info* info) {
+  if (small_path(A, stop)) return solve_cg_small(ctx, A, b, x, stop, info);
   const int64_t n = A->n;
   const size_t ld = align_up((size_t)n, 64);
-  const bool small = small_path(A, stop);
   Work w;
-  mxs_status s = get_work(
-      ctx, 3 * ld * sizeof(double) + (small ? ld * sizeof(double) + small_cg_scratch(n) : 0), &w);
+  mxs_status s = get_work(ctx, 3 * ld * sizeof(double), &w);
   if (s) return s;
   double* r = (double*)w.vec;
   double* p = r + ld;
@@ -1363,30 +1406,6 @@ mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* 
   const double base = stop.baseline == MXS_BASELINE_INITIAL ? (nr0 > 0 ? nr0 : 1.0) : nb;
   const double thr = std::max(stop.rel_tol * base, stop.abs_tol);
   KState& h = *w.hst;
-  if (small && nr0 > thr) {
-    // one work-group runs every iteration: A d = r0 from d = 0, then x += d
-    double* d = q + ld;
-    SmallCgResult sr;
-    if ((s = small_cg(ctx, A, r, d, thr / nr0, stop.max_iters, d + ld, &sr))) return s;
-    k_add<<<red_grid(n), RB, 0, ctx->stream>>>(n, x, d);
-    MXS_HIP_TRY(ctx, hipGetLastError());
-    double rt2;
-    if ((s = residual(ctx, A, b, x, r))) return s;
-    if ((s = dots<double>(ctx, w, n, r, r, (const double*)nullptr, (const double*)nullptr,
-                          &rt2, nullptr)))
-      return s;
-    std::memset(&h, 0, sizeof(KState));
-    h.iters = sr.iters;
-    h.res2 = sr.res2;
-    mxs_status st = sr.status;
-    if (st == MXS_OK && !(sqrt(rt2) <= thr)) st = MXS_NOT_CONVERGED;
-    fill_info(info, h, base, sqrt(rt2) / base, sr.replacements, 0, st);
-    if (st == MXS_OK) return MXS_OK;
-    return fail(ctx, st, st == MXS_BREAKDOWN   ? "CG breakdown: p.Ap <= 0 (matrix not SPD)"
-                         : st == MXS_NONFINITE ? "non-finite value in CG"
-                                               : "CG stopped after %lld iterations, relres %.3e",
-                (long long)sr.iters, sqrt(rt2) / base);
-  }
   std::memset(&h, 0, sizeof(KState));
   h.rho[0] = nr2;
   h.res2 = nr2;
