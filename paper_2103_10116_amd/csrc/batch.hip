@@ -440,7 +440,9 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
   // owns 10 or more rows (1024-thread classes run at 128 registers a lane)
   constexpr bool XG = RPT >= 10;
   double* __restrict__ xg = D.x;
-  double x[XG ? 1 : RPT], r[RPT], q[RPT];
+  // p of the thread's own rows is also kept in registers (pr), so that only
+  // the product's gathers read the gather vector
+  double x[XG ? 1 : RPT], r[RPT], q[RPT], pr[RPT];
   double rho, thr;
   int status = SLOT_RUN;
   int it = 0, repl = 0;
@@ -470,6 +472,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
+      pr[k] = r[k];
       if (i < n) vec[i] = r[k];
     }
     base = D.base_r0 ? sqrt(rho) : sqrt(nb2);
@@ -504,6 +507,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
         x[k] = 0.0;
       }
       r[k] = i < n ? b[i] : 0.0;
+      pr[k] = r[k];
       if (i < n) vec[i] = r[k];
       acc += r[k] * r[k];
     }
@@ -518,7 +522,8 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
       const int i = tid + k * BS;
       if constexpr (!XG) x[k] = i < n ? D.x[i] : 0.0;
       r[k] = i < n ? D.r[i] : 0.0;
-      if (USE_LDS && i < n) vec[i] = pg[i];
+      pr[k] = i < n ? pg[i] : 0.0;
+      if (USE_LDS && i < n) vec[i] = pr[k];
     }
     rho = S->rho;
     thr = S->thr;
@@ -534,7 +539,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      if (i < n) pq += vec[i] * q[k];
+      pq += pr[k] * q[k];
     }
     pq = bsum1<BS>(pq, red + BS / 64);
     if (!(pq > 0.0)) {
@@ -547,9 +552,9 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
       if constexpr (XG) {
-        if (i < n) xg[i] += alpha * vec[i];
+        if (i < n) xg[i] += alpha * pr[k];
       } else {
-        if (i < n) x[k] += alpha * vec[i];
+        x[k] += alpha * pr[k];
       }
       r[k] -= alpha * q[k];
       acc += r[k] * r[k];
@@ -593,6 +598,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
       for (int k = 0; k < RPT; ++k) {
         const int i = tid + k * BS;
         r[k] = q[k];
+        pr[k] = q[k];
         if (i < n) vec[i] = q[k];
       }
       rho = tt;
@@ -609,7 +615,8 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = tid + k * BS;
-      if (i < n) vec[i] = r[k] + beta * vec[i];
+      pr[k] = r[k] + beta * pr[k];
+      if (i < n) vec[i] = pr[k];
     }
     __syncthreads();
   }
@@ -629,7 +636,7 @@ __device__ __forceinline__ void cg_body(const SlotDesc& D, SlotState* S, int K, 
       if (i < n) {
         if constexpr (!XG) D.x[i] = x[k];
         D.r[i] = r[k];
-        if (USE_LDS) pg[i] = vec[i];
+        if (USE_LDS) pg[i] = pr[k];
       }
     }
   }
