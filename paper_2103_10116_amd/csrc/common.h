@@ -80,6 +80,7 @@ struct CsrPart {
   int wpb = 4;    // stream kernel: independent waves per work-group (1 or 4)
   bool rows_lds = false;  // rows-from-LDS kernel (blocks of <= 64/rl_lanes rows, block_nnz entries)
   int rl_lanes = 1;       // rows-from-LDS kernel: lanes per row (1, 2 or 4)
+  int rl_step = 8;        // rows-from-LDS kernel: a lane's entries per step (8 or 16)
   bool products = false;  // products-through-LDS kernel (the same blocks)
 };
 

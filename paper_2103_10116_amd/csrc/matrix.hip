@@ -333,6 +333,8 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
       else
         while (g < 4 && (64 / g) * std::max<int64_t>(maxL, 1) > block_nnz) g <<= 1;
       A->csr.rl_lanes = g;
+      // a lane's share of the longest row in one step when it exceeds 8
+      A->csr.rl_step = (std::max<int64_t>(maxL, 1) + g - 1) / g > 8 ? 16 : 8;
       max_rows = 64 / g;
     }
   } else if (kind == MXS_CSR_AUTO && !(opts && opts->block_nnz > 0)) {

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_csr_vec(int64_t n, const int32_t* __res
 // (Staging the next block while walking the current one was measured
 // slower: the extra registers cost more occupancy than the overlap gains.)
 // ---------------------------------------------------------------------------
-template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G>
+template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G, int ST>
 __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
                                                      const int32_t* __restrict__ blocks,
                                                      const int32_t* __restrict__ bnnz,
@@ -370,23 +370,24 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
     }
   }
   wave_sync();
-  // eight of the lane's entries per step, their gathers in flight together;
-  // slots past the row's end read the row's first entry and add nothing
+  // ST (8 or 16) of the lane's entries per step, their gathers in flight
+  // together; slots past the row's end read the row's first entry and add
+  // nothing
   T acc[4] = {T(0), T(0), T(0), T(0)};
-  for (int32_t k = ra + h; k < rb; k += 8 * G) {
-    int32_t cc[8];
-    T vv[8];
+  for (int32_t k = ra + h; k < rb; k += ST * G) {
+    int32_t cc[ST];
+    T vv[ST];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < ST; ++t) {
       const int32_t kk = k + t * G < rb ? k + t * G : ra;
       cc[t] = cl[kk];
       vv[t] = to_acc(vl[kk]);
     }
-    T g[8];
+    T g[ST];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) g[t] = x[cc[t]];
+    for (int t = 0; t < ST; ++t) g[t] = x[cc[t]];
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < ST; ++t)
       if (k + t * G < rb) acc[t & 3] += vv[t] * g[t];
   }
   T sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
@@ -930,9 +931,14 @@ void launch_csr_rl_g(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta
                      const int32_t* skip) {
   constexpr int WPB = 2;
   const dim3 grid((unsigned)((P.nblocks + WPB - 1) / WPB));
-  k_csr_rl<V, T, CMAX, SCALED, WPB, G><<<grid, 64 * WPB, 0, ctx->stream>>>(
-      P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
-      skip);
+  if (P.rl_step == 16)
+    k_csr_rl<V, T, CMAX, SCALED, WPB, G, 16><<<grid, 64 * WPB, 0, ctx->stream>>>(
+        P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha,
+        beta, skip);
+  else
+    k_csr_rl<V, T, CMAX, SCALED, WPB, G, 8><<<grid, 64 * WPB, 0, ctx->stream>>>(
+        P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha,
+        beta, skip);
 }
 
 template <typename V, typename T, bool SCALED, int CMAX>
