@@ -57,7 +57,7 @@ def ell_streamed_bytes(desc, vb, xb):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_stencil27_128_traffic.txt")
 
 
-def measured_traffic(fmt, dt, info):
+def measured_traffic(fmt, dt, info, max_row):
     """HBM bytes per launch of this SpMV from the committed rocprofv3 --pmc
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors), or
     None when the summary predates the current kernels or lacks them."""
@@ -74,7 +74,9 @@ def measured_traffic(fmt, dt, info):
     if fmt == "csr" and ck == 4:  # products through LDS
         keys.append((f"k_csr_pr<{t},{info['block_nnz']},false,{wpg}>", chunked))
     if fmt == "csr" and ck == 3:  # rows from LDS, two waves per group, G lanes per row
-        keys.append((f"k_csr_rl<{t},{info['block_nnz']},false,2,{info['lanes_per_row']}>",
+        g = info["lanes_per_row"]
+        st = 16 if -(-max_row // g) > 8 else 8  # a lane's entries per step
+        keys.append((f"k_csr_rl<{t},{info['block_nnz']},false,2,{g},{st}>",
                      -(-info["blocks"] // 2) * 128))
     if fmt == "csr" and ck == 1:
         keys.append((f"k_csr<{t},{npl},false,{wpg}>", chunked))
@@ -223,7 +225,8 @@ def main():
                        "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": round(d["GBs"] / PEAK_HBM_GBS, 4),
                        "bytes_per_launch": d["bytes"], "us_per_launch": d["us"],
-                       "traffic": measured_traffic(fmt_d, dt_d, mats[(fmt_d, dt_d)].info())}
+                       "traffic": measured_traffic(fmt_d, dt_d, mats[(fmt_d, dt_d)].info(),
+                                                   int(A.row_lengths().max()))}
     if peak_meas:
         out["roofline"]["measured_peak"] = round(peak_meas, 1)
         out["roofline"]["frac_measured"] = round(d["GBs"] / peak_meas, 4)
