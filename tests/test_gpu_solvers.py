@@ -93,6 +93,48 @@ def test_cg_statuses(env, orc):
     assert r.status == mxs.OK and r.iters == 0
 
 
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_cg_stopping_rules(env, orc, fmt):
+    """The stopping rule max(rel_tol * base, abs_tol) with base = ||b|| or
+    ||b - A x0||, from a non-zero x0, on the one-work-group path (CSR) and
+    the multi-kernel path (COO): the returned x meets it, relres_true is
+    ||b - A x|| / base, and both paths stop after the same iterations."""
+    from paper_2103_10116_amd import mxs
+    A = I.poisson2d(40)
+    b = orc.spmv_csr(A, np.ones(A.n))
+    x0 = I.uniform_vector(A.n, 31)
+    nb = np.linalg.norm(b)
+    nr0 = orc.true_relres(A, b, x0) * nb
+    ref_its = {}
+    for baseline, base in ((0, nb), (1, nr0)):
+        r, x = _solve(env, A, b, "cg", fmt, tol=1e-8, x0=x0, baseline=baseline)
+        res = orc.true_relres(A, b, x) * nb
+        assert r.status == mxs.OK and res <= 1e-8 * base * (1 + 1e-6) + 1e-13 * nb, (baseline, r)
+        assert abs(r.relres_true - res / base) <= 1e-6 * res / base + 1e-13 * nb / base
+        ref_its[baseline] = r.iters
+    # an absolute floor above rel_tol * ||b|| decides
+    r, x = _solve(env, A, b, "cg", fmt, tol=1e-14, x0=x0, abs_tol=1e-4 * nb)
+    res = orc.true_relres(A, b, x) * nb
+    assert r.status == mxs.OK and res <= 1e-4 * nb * (1 + 1e-6)
+    assert r.iters < ref_its[0]
+    # x0 already within the threshold: no iteration, x0 returned
+    r, x = _solve(env, A, b, "cg", fmt, tol=1.0, x0=x0, baseline=1)
+    assert r.status == mxs.OK and r.iters == 0 and np.array_equal(x, x0)
+
+
+def test_cg_paths_agree(env, orc):
+    """The one-work-group path (CSR) and the multi-kernel path (COO) take
+    the same iterations for the same stopping rules (within two)."""
+    A = I.poisson2d(40)
+    b = orc.spmv_csr(A, np.ones(A.n))
+    x0 = I.uniform_vector(A.n, 31)
+    for kw in ({"baseline": 0}, {"baseline": 1}, {"tol": 1e-14, "abs_tol": 1e-4 * np.linalg.norm(b)}):
+        tol = kw.pop("tol", 1e-8)
+        rc, _ = _solve(env, A, b, "cg", "csr", tol=tol, x0=x0, **kw)
+        ro, _ = _solve(env, A, b, "cg", "coo", tol=tol, x0=x0, **kw)
+        assert abs(rc.iters - ro.iters) <= 2, (kw, rc.iters, ro.iters)
+
+
 def test_cg_eigenvector_one_step(env, orc):
     m = 12
     A = I.poisson2d(m)
