@@ -64,7 +64,10 @@ typedef struct mxs_ctx mxs_ctx;
 typedef struct mxs_matrix mxs_matrix;
 
 /* Optional device allocator.  alloc returns device memory of at least
- * `bytes` bytes usable on `stream` (NULL on failure); free releases it. */
+ * `bytes` bytes usable on `stream`, 16-byte aligned at least (hipMalloc and
+ * torch's caching allocator give 256 or more), or NULL on failure; free
+ * releases it.  A block that is not 16-byte aligned is freed again at once
+ * and the call that needed it fails with MXS_OOM. */
 typedef struct {
   void* (*alloc)(size_t bytes, void* stream, void* user);
   void (*free)(void* ptr, void* stream, void* user);

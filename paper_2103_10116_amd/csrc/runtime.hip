@@ -10,7 +10,16 @@ namespace mxs {
 
 void* Allocator::alloc(size_t bytes) const {
   if (bytes == 0) bytes = 1;
-  if (custom) return cb.alloc(bytes, stream, cb.user);
+  if (custom) {
+    // the kernels load 16-byte words from every array: a block that is not
+    // 16-byte aligned is handed back and counts as a failed allocation
+    void* p = cb.alloc(bytes, stream, cb.user);
+    if (p && ((uintptr_t)p & 15) != 0) {
+      cb.free(p, stream, cb.user);
+      return nullptr;
+    }
+    return p;
+  }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();

@@ -195,10 +195,45 @@ def status_string(s: int) -> str:
 # ---------------------------------------------------------------------------
 # context
 # ---------------------------------------------------------------------------
-class Context:
-    """A libmxs context bound to torch's current HIP stream on `device`."""
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
-    def __init__(self, device: int = 0, stream=None):
+
+class TorchAllocator:
+    """Device memory for a context from torch's caching allocator: each block
+    is a uint8 tensor kept alive until the library frees it.  `offset` shifts
+    every pointer by that many bytes (a way to hand out misaligned blocks)."""
+
+    def __init__(self, device: int = 0, offset: int = 0):
+        self.device, self.offset = device, int(offset)
+        self.live = {}
+        self.calls = 0
+        self._alloc = _ALLOC_FN(self._on_alloc)
+        self._free = _FREE_FN(self._on_free)
+        self.struct = Allocator(C.cast(self._alloc, C.c_void_p), C.cast(self._free, C.c_void_p),
+                                None)
+
+    def _on_alloc(self, nbytes, stream, user):
+        import torch
+        try:
+            t = torch.empty(int(nbytes) + self.offset, dtype=torch.uint8,
+                            device=f"cuda:{self.device}")
+        except RuntimeError:
+            return None
+        p = t.data_ptr() + self.offset
+        self.live[p] = t
+        self.calls += 1
+        return p
+
+    def _on_free(self, ptr, stream, user):
+        self.live.pop(ptr, None)
+
+
+class Context:
+    """A libmxs context bound to torch's current HIP stream on `device`;
+    device memory from hipMalloc, or from `allocator` (a TorchAllocator)."""
+
+    def __init__(self, device: int = 0, stream=None, allocator=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libmxs needs a ROCm GPU; torch.cuda is not available")
@@ -206,8 +241,10 @@ class Context:
         torch.cuda.set_device(device)
         s = stream if stream is not None else torch.cuda.current_stream(device)
         self.stream = s
+        self.allocator = allocator
         h = C.c_void_p()
-        _check(_lib.mxs_ctx_create(device, C.c_void_p(s.cuda_stream), None, C.byref(h)))
+        a = C.byref(allocator.struct) if allocator is not None else None
+        _check(_lib.mxs_ctx_create(device, C.c_void_p(s.cuda_stream), a, C.byref(h)))
         self.handle = h
 
     def synchronize(self):
