@@ -83,16 +83,15 @@ def measured_traffic(fmt, dt, info, max_row):
     if fmt == "csr" and info["lanes_per_row"] == 1:
         keys.append((f"k_csr_row<{t},false>", -(-info["nrows"] // 256) * 256))
     coo = "k_coo_runs" if info["coo_kernel"] == 2 else "k_coo"
-    vec = ",true"  # the arrays are 16-byte aligned
     if fmt == "coo":
-        keys.append((f"{coo}<{t},{npl},false,{wpg}{vec}>", chunked))
+        keys.append((f"{coo}<{t},{npl},false,{wpg}>", chunked))
     if fmt in ("ell", "hyb"):
         w = 1
         while w < 16 and (info["ell_width"] + w - 1) // w > 256:
             w *= 2
         keys.append((f"k_ell<{t},{w}>", info["ell_stride"] * w))
     if fmt == "hyb" and info["coo_nnz"]:
-        keys.append((f"{coo}<{t},{npl},true,{wpg}{vec}>", chunked))
+        keys.append((f"{coo}<{t},{npl},true,{wpg}>", chunked))
     if not keys or any(k not in table for k in keys):
         return None
     return int(sum(table[k] for k in keys))

@@ -536,11 +536,12 @@ __global__ __launch_bounds__(256) void k_csr_row(int64_t n, const int32_t* __res
 // COO
 // ---------------------------------------------------------------------------
 // Loads the NPL consecutive elements p[0..NPL) into out: 16-byte loads when
-// VEC (p is 16-byte aligned) and the run is a whole number of them, else one
-// load each.
-template <int NPL, bool VEC, typename E>
+// the run is a whole number of them (p is then 16-byte aligned: every device
+// allocation is, and runs start at multiples of NPL elements), else one load
+// each.
+template <int NPL, typename E>
 __device__ __forceinline__ void load_run(const E* __restrict__ p, E (&out)[NPL]) {
-  if constexpr (VEC && (NPL * sizeof(E)) % 16 == 0) {
+  if constexpr ((NPL * sizeof(E)) % 16 == 0) {
     constexpr int NW = (int)(NPL * sizeof(E) / 16);
     uint4 w[NW];
 #pragma unroll
@@ -563,7 +564,7 @@ __device__ __forceinline__ void load_run(const E* __restrict__ p, E (&out)[NPL])
 // fix-up pass, so no floating-point atomics are used and the result does not
 // depend on scheduling.  k_coo adds in the same order (there the products
 // are rounded before they are added; here they may be fused into the adds).
-template <typename V, typename T, int NPL, bool ACCUM, int WPB, bool VEC>
+template <typename V, typename T, int NPL, bool ACCUM, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_coo_runs(int64_t nnz, int64_t nchunks,
                                                       const int32_t* __restrict__ row,
                                                       const int32_t* __restrict__ col,
@@ -588,9 +589,9 @@ __global__ __launch_bounds__(64 * WPB) void k_coo_runs(int64_t nnz, int64_t nchu
   // full run; entries past len are never summed (their column 0 is gathered)
   int32_t r[NPL], c[NPL];
   V v[NPL];
-  load_run<NPL, VEC>(row + s + k0, r);
-  load_run<NPL, VEC>(col + s + k0, c);
-  load_run<NPL, VEC>(val + s + k0, v);
+  load_run<NPL>(row + s + k0, r);
+  load_run<NPL>(col + s + k0, c);
+  load_run<NPL>(val + s + k0, v);
   T prod[NPL];
 #pragma unroll
   for (int t = 0; t < NPL; ++t) prod[t] = x[c[t]];
@@ -673,7 +674,7 @@ __global__ __launch_bounds__(64 * WPB) void k_coo_runs(int64_t nnz, int64_t nchu
 // neighbouring entries' x; the products go to LDS and lane l reads back the
 // run l*NPL .. l*NPL+NPL-1, whose row indices it loads itself.  The run is
 // summed and rows are joined across lanes as in k_coo_runs.
-template <typename V, typename T, int NPL, bool ACCUM, int WPB, bool VEC>
+template <typename V, typename T, int NPL, bool ACCUM, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
                                                       const int32_t* __restrict__ row,
                                                       const int32_t* __restrict__ col,
@@ -707,7 +708,7 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
       c[t] = col[s + t * 64 + lane];
       v[t] = val[s + t * 64 + lane];
     }
-    load_run<NPL, VEC>(row + s + k0, r);
+    load_run<NPL>(row + s + k0, r);
     T g[NPL];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) g[t] = x[c[t]];
@@ -1027,36 +1028,34 @@ void launch_coo_chunks(mxs_ctx* ctx, const CooPart& P, T alpha, const T* x, T be
   const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
   T* cv = (T*)P.cont_val;
   if (P.kernel == MXS_COO_RUNS) {
-    const bool vec = (((uintptr_t)P.row | (uintptr_t)P.col | (uintptr_t)val) & 15) == 0;
-#define MXS_COO_RUNS_CASE(NN)                                                           \
-  if (vec)                                                                              \
-    k_coo_runs<V, T, NN, ACCUM, WPB, true><<<grid, 64 * WPB, 0, ctx->stream>>>(         \
-        P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);  \
-  else                                                                                  \
-    k_coo_runs<V, T, NN, ACCUM, WPB, false><<<grid, 64 * WPB, 0, ctx->stream>>>(        \
-        P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
     switch (P.block_nnz) {
-      case 256: MXS_COO_RUNS_CASE(4) break;
-      case 1024: MXS_COO_RUNS_CASE(16) break;
-      default: MXS_COO_RUNS_CASE(8)
+      case 256:
+        k_coo_runs<V, T, 4, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+        break;
+      case 1024:
+        k_coo_runs<V, T, 16, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+        break;
+      default:
+        k_coo_runs<V, T, 8, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
     }
-#undef MXS_COO_RUNS_CASE
     return;
   }
-  const bool vec = ((uintptr_t)P.row & 15) == 0;
-#define MXS_COO_LDS_CASE(NN)                                                           \
-  if (vec)                                                                             \
-    k_coo<V, T, NN, ACCUM, WPB, true><<<grid, 64 * WPB, 0, ctx->stream>>>(             \
-        P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip); \
-  else                                                                                 \
-    k_coo<V, T, NN, ACCUM, WPB, false><<<grid, 64 * WPB, 0, ctx->stream>>>(            \
-        P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
   switch (P.block_nnz) {
-    case 256: MXS_COO_LDS_CASE(4) break;
-    case 1024: MXS_COO_LDS_CASE(16) break;
-    default: MXS_COO_LDS_CASE(8)
+    case 256:
+      k_coo<V, T, 4, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+      break;
+    case 1024:
+      k_coo<V, T, 16, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+      break;
+    default:
+      k_coo<V, T, 8, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
   }
-#undef MXS_COO_LDS_CASE
 }
 
 template <typename V, typename T, bool ACCUM>
