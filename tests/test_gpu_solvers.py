@@ -122,6 +122,21 @@ def test_cg_stopping_rules(env, orc, fmt):
     assert r.status == mxs.OK and r.iters == 0 and np.array_equal(x, x0)
 
 
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_cg_special_starts(env, orc, fmt):
+    """From a non-zero x0: b = 0 returns x = 0 at once; a NaN in x0 is
+    reported as non-finite (both CG paths)."""
+    from paper_2103_10116_amd import mxs
+    A = I.poisson2d(24)
+    x0 = I.uniform_vector(A.n, 51)
+    r, x = _solve(env, A, np.zeros(A.n), "cg", fmt, x0=x0)
+    assert r.status == mxs.OK and r.iters == 0 and not x.any()
+    bad = x0.copy()
+    bad[7] = np.nan
+    r, _ = _solve(env, A, np.ones(A.n), "cg", fmt, x0=bad)
+    assert r.status == mxs.NONFINITE
+
+
 def test_cg_paths_agree(env, orc):
     """The one-work-group path (CSR) and the multi-kernel path (COO) take
     the same iterations for the same stopping rules (within two)."""
