@@ -100,15 +100,21 @@ CSR_CANDIDATES = ([dict(csr_kernel="stream", block_nnz=b) for b in (256, 512, 10
                    for b in (512, 1024) for g in (1, 2)] +
                   [dict(csr_kernel="products", block_nnz=b) for b in (512, 1024)])
 
+COO_CANDIDATES = [dict(coo_kernel=k, block_nnz=b, waves_per_group=w)
+                  for k in ("lds", "runs") for b in (256, 512, 1024) for w in (1, 4)]
+CANDIDATES = {"csr": CSR_CANDIDATES, "coo": COO_CANDIDATES}
+
 
 def tune_spmv(ctx, M, dtype="f64", reps=20, cache=DEFAULT_CACHE, signature=None, refresh=False,
-              log=None):
-    """Best convert options for the CSR product of F64 CSR matrix M."""
+              log=None, fmt="csr"):
+    """Best convert options for the product of F64 CSR matrix M stored in
+    format `fmt` ("csr": kernel, block and lanes; "coo": kernel, chunk and
+    work-group shape), timed on this device and cached by matrix signature."""
     import torch
     from . import mxs
     d = M.info()
     sig = signature or f"{d['nrows']}x{d['ncols']}:{d['nnz']}"
-    key = f"spmv|{_device_name()}|{sig}|{dtype}"
+    key = f"spmv|{_device_name()}|{sig}|{dtype}" + ("" if fmt == "csr" else f"|{fmt}")
     data = _load(cache)
     if not refresh and key in data:
         return data[key]["opts"]
@@ -117,8 +123,8 @@ def tune_spmv(ctx, M, dtype="f64", reps=20, cache=DEFAULT_CACHE, signature=None,
     y = torch.zeros(d["nrows"], dtype=tdt, device="cuda")
     best = None
     timings = {}
-    for opts in CSR_CANDIDATES:
-        B = M.convert("csr", dtype, **opts)
+    for opts in CANDIDATES[fmt]:
+        B = M.convert(fmt, dtype, **opts)
         for _ in range(3):
             mxs.spmv(ctx, B, x, y)
         e0 = torch.cuda.Event(enable_timing=True)

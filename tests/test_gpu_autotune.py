@@ -31,6 +31,29 @@ def test_tune_spmv_and_cache(tmp_path):
     ctx.close()
 
 
+def test_tune_coo(tmp_path):
+    """COO tuning: kernel, chunk size and work-group shape; cached apart from
+    the CSR choice of the same matrix."""
+    import torch
+    from paper_2103_10116_amd import autotune, mxs
+    ctx = mxs.Context(0)
+    A = I.poisson3d(12)
+    M = mxs.Matrix.from_host(ctx, A)
+    cache = str(tmp_path / "tune.json")
+    opts = autotune.tune_spmv(ctx, M, "f32", reps=2, cache=cache, fmt="coo")
+    assert opts in autotune.COO_CANDIDATES
+    B = M.convert("coo", "f32", **opts)
+    assert B.info()["coo_kernel"] == mxs.COO_KERNELS[opts["coo_kernel"]]
+    x = torch.rand(A.n, dtype=torch.float32, device="cuda")
+    y = torch.zeros_like(x)
+    mxs.spmv(ctx, B, x, y)
+    torch.cuda.synchronize()
+    keys = list(json.load(open(cache)))
+    assert any(k.endswith("|coo") for k in keys)
+    assert autotune.tune_spmv(ctx, M, "f32", reps=2, cache=cache) in autotune.CSR_CANDIDATES
+    ctx.close()
+
+
 def test_tune_batch_classes(tmp_path):
     from paper_2103_10116_amd import autotune, mxs
     ctx = mxs.Context(0)
