@@ -237,6 +237,42 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// A double moved across lanes by a DPP pattern (both 32-bit halves alike).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+// Sum over the wave, the same value in every lane.  Within each row of 16
+// lanes, DPP moves add the neighbour (lane ^ 1), the other pair of the quad
+// (lane ^ 2), the mirrored quad of the half and the mirrored half of the row;
+// the two operands of each add are the same two values in either lane, so
+// every lane of a row ends with the same row sum.  The four row sums are then
+// read from lanes 15, 31, 47 and 63 and added in row order.  DPP moves cost a
+// few cycles where the cross-lane shuffles of a butterfly go through the LDS
+// crossbar; the batched kernels take two such sums per CG iteration, and every
+// solver kernel takes them at its start (finishing the previous kernel's
+// partials) and at its end.  All lanes of the wave must be active.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return ((lane_value(v, 15) + lane_value(v, 31)) + lane_value(v, 47)) + lane_value(v, 63);
+}
+
 // Sum over a work-group of BS threads; every thread gets the result.  Wave
 // partials are added in wave order by all lanes (deterministic).
 template <typename T, int BS>

@@ -77,7 +77,7 @@ __device__ __forceinline__ double block_sum_multi(const double (&acc)[NV], doubl
   const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    const double s = wave_sum(acc[i]);
+    const double s = wave_total(acc[i]);
     if (lane == 0) lds[w][i] = s;
   }
   __syncthreads();
