@@ -98,7 +98,8 @@ CSR_CANDIDATES = ([dict(csr_kernel="stream", block_nnz=b) for b in (256, 512, 10
                   [dict(csr_kernel="vector", lanes_per_row=1)] +
                   [dict(csr_kernel="rows_lds", block_nnz=b, lanes_per_row=g)
                    for b in (512, 1024) for g in (1, 2)] +
-                  [dict(csr_kernel="products", block_nnz=b) for b in (512, 1024)])
+                  [dict(csr_kernel="products", block_nnz=b) for b in (512, 1024)] +
+                  [dict(csr_kernel="merge", block_nnz=b) for b in (256, 512)])
 
 COO_CANDIDATES = [dict(coo_kernel=k, block_nnz=b, waves_per_group=w)
                   for k in ("lds", "runs") for b in (256, 512, 1024) for w in (1, 4)]

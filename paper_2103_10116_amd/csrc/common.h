@@ -82,6 +82,15 @@ struct CsrPart {
   int rl_lanes = 1;       // rows-from-LDS kernel: lanes per row (1, 2 or 4)
   int rl_step = 8;        // rows-from-LDS kernel: a lane's entries per step (8 or 16)
   bool products = false;  // products-through-LDS kernel (the same blocks)
+  // merge-path kernel: equal chunks of block_nnz entries; crow[c] is the row
+  // of entry c * block_nnz (crow[nchunks]: the row of the last entry)
+  bool merge = false;
+  int32_t* crow = nullptr;
+  int64_t nchunks = 0;
+  int32_t* cont_row = nullptr;  // per-chunk continuation partials (fix-up pass)
+  void* cont_val = nullptr;
+  int32_t* empty_rows = nullptr;
+  int64_t nempty = 0;
 };
 
 // COO: equal chunks of block_nnz entries, one wave per chunk.  Rows cut by

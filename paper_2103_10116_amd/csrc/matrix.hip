@@ -269,6 +269,73 @@ T* upload(mxs_ctx* ctx, mxs_matrix* A, const std::vector<T>& h) {
   return d;
 }
 
+// Merge-path partition: equal chunks of C entries, the row of each chunk's
+// first entry (and of the last entry overall), continuation scratch and the
+// list of empty rows.  A chunk's rows must fit its LDS table of C + 2 row
+// pointers, which long runs of empty rows can break.
+int merge_chunk(const mxs_convert_opts* opts) {
+  return opts && opts->block_nnz > 0
+             ? (opts->block_nnz <= 256 ? 256 : opts->block_nnz <= 512 ? 512 : 1024)
+             : 512;
+}
+
+// The row of each chunk's first entry (crow[nchunks]: the row of the last
+// entry); false when some chunk's rows outgrow its table of C + 2 pointers.
+bool merge_rows(const std::vector<int32_t>& rp, int64_t nnz, int C, std::vector<int32_t>& crow,
+                int64_t* bad_chunk) {
+  const int64_t nchunks = (nnz + C - 1) / C;
+  crow.assign((size_t)nchunks + 1, 0);
+  int64_t r = 0;
+  for (int64_t c = 0; c < nchunks; ++c) {
+    while (rp[r + 1] <= c * C) ++r;
+    crow[c] = (int32_t)r;
+  }
+  if (nnz > 0) {
+    while (rp[r + 1] <= nnz - 1) ++r;
+    crow[nchunks] = (int32_t)r;
+  }
+  for (int64_t c = 0; c < nchunks; ++c)
+    if (crow[c + 1] - crow[c] + 1 > C + 1) {
+      *bad_chunk = c;
+      return false;
+    }
+  return true;
+}
+
+mxs_status build_csr_merge(mxs_ctx* ctx, mxs_matrix* A, const mxs_convert_opts* opts) {
+  if (A->dt != MXS_F64 && A->dt != MXS_F32)
+    return fail(ctx, MXS_UNSUPPORTED, "the merge-path CSR kernel takes FP64 or FP32 values");
+  const std::vector<int32_t>& rp = A->h_rowptr;
+  const int64_t n = A->n, nnz = A->nnz;
+  const int C = merge_chunk(opts);
+  std::vector<int32_t> crow, empty;
+  int64_t bad = 0;
+  if (!merge_rows(rp, nnz, C, crow, &bad))
+    return fail(ctx, MXS_UNSUPPORTED,
+                "merge-path CSR: chunk %lld spans %d rows (empty rows), more than %d",
+                (long long)bad, crow[bad + 1] - crow[bad] + 1, C + 1);
+  CsrPart& P = A->csr;
+  P.merge = true;
+  P.block_nnz = C;
+  // one wave per work-group unless asked (power law, cold: FP32 s = 2.0
+  // 56.5 vs 58.0 us, s = 1.79 119.1 vs 119.5 us)
+  P.wpb = (opts && opts->waves_per_group > 1) ? 4 : 1;
+  P.nchunks = (nnz + C - 1) / C;
+  P.nblocks = P.nchunks;
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] == rp[i]) empty.push_back((int32_t)i);
+  P.nempty = (int64_t)empty.size();
+  P.crow = upload(ctx, A, crow);
+  P.empty_rows = upload(ctx, A, empty);
+  P.cont_row = (int32_t*)mat_alloc(A, (size_t)(P.nchunks + 1) * sizeof(int32_t));
+  P.cont_val = mat_alloc(A, (size_t)(P.nchunks + 1) * sizeof(double));
+  if (!P.crow || !P.empty_rows || !P.cont_row || !P.cont_val)
+    return fail(ctx, MXS_OOM, "merge-path CSR set-up");
+  // the host vectors are freed on return: the copies must finish first
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MXS_OK;
+}
+
 // Chooses the CSR kernel from the row lengths (or the caller's options) and
 // builds the row-block partition the stream kernel needs.
 mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
@@ -299,7 +366,17 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
     kind_eff = maxL > 64                             ? MXS_CSR_STREAM
                : (narrow || (A->dt == MXS_F64 && maxL <= 8)) ? MXS_CSR_ROWS_LDS
                                                              : MXS_CSR_PRODUCTS;
+    // rows over 64 entries (power law): the merge path for FP64/FP32 values
+    // when every chunk's rows fit its table (cold, 2^20 rows: s = 2.0 FP32
+    // 56.5 vs 65.6 us for the row-block stream kernel, FP64 84.8 vs 90.8;
+    // s = 1.79 FP32 119.1 vs 134.5, FP64 198.3 vs 201.5)
+    std::vector<int32_t> crow;
+    int64_t bad = 0;
+    if (maxL > 64 && (A->dt == MXS_F64 || A->dt == MXS_F32) &&
+        merge_rows(rp, A->nnz, merge_chunk(opts), crow, &bad))
+      kind_eff = MXS_CSR_MERGE;
   }
+  if (kind_eff == MXS_CSR_MERGE) return build_csr_merge(ctx, A, opts);
   bool vec = kind_eff == MXS_CSR_VECTOR;
   A->csr.lanes = vec ? G : 0;
   A->csr.wpb = (opts && opts->waves_per_group == 1) ? 1 : 4;
@@ -795,6 +872,7 @@ mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
   out->rows_per_group = A->fmt == MXS_CSR ? A->csr.rpg : 0;
   out->waves_per_group = A->fmt == MXS_CSR ? A->csr.wpb : A->coo.wpb;
   out->csr_kernel = A->fmt != MXS_CSR  ? 0
+                    : A->csr.merge    ? MXS_CSR_MERGE
                     : A->csr.products ? MXS_CSR_PRODUCTS
                     : A->csr.rows_lds ? MXS_CSR_ROWS_LDS
                     : A->csr.lanes >= 1 ? MXS_CSR_VECTOR

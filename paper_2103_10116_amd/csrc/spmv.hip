@@ -27,6 +27,8 @@
 // Per-lane sequential chains are at most NPL (+ the scan depth of 6) for
 // CSR/COO blocks and at most a quarter of a row's entries per wave for long
 // rows and ELL; the FP64 error stays far below 1e-13 * sum|a_ij||x_j|.
+#include <type_traits>
+
 #include "common.h"
 
 namespace mxs {
@@ -791,6 +793,154 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
   }
 }
 
+// CSR by the merge path: chunk `ch` holds entries s .. s+len-1 (equal
+// chunks of C = 64 * NPL entries whatever the rows).  Its col and val are
+// loaded coalesced (slot t of lane l is entry t*64 + l; slots past the
+// matrix's last entry re-read it, their products are never summed), the
+// products go to LDS, and the row pointers of rows crow[ch] .. crow[ch+1]
+// (at most C + 2 values, checked at set-up) go to a second LDS table, where
+// each lane finds the row of the first entry of its run
+// (l*NPL .. l*NPL+NPL-1) by binary search and steps through the rest.  The
+// runs are then summed and joined across lanes exactly as in k_coo, and rows
+// cut by chunk edges are completed by k_coo_fix.  Against COO it reads no
+// row index per entry; against the row-block stream kernel every wave gets
+// the same number of entries whatever the row lengths.
+template <typename V, typename T, int NPL, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nchunks,
+                                                       const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ crow,
+                                                       const int32_t* __restrict__ col,
+                                                       const V* __restrict__ val,
+                                                       const T* __restrict__ x, T* __restrict__ y,
+                                                       T alpha, T beta,
+                                                       int32_t* __restrict__ cont_row,
+                                                       T* __restrict__ cont_val,
+                                                       const int32_t* __restrict__ skip) {
+  constexpr int C = 64 * NPL;
+  if (skip && *skip) return;
+  __shared__ T prod_all[WPB][C + C / 32];
+  __shared__ int32_t rl_all[WPB][C + 2];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T* prod = prod_all[wv];
+  int32_t* rl = rl_all[wv];
+  const int64_t ch = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if (ch >= nchunks) return;
+  const int64_t s = ch * C;
+  const int len = (int)((nnz - s) < C ? (nnz - s) : C);
+  const int32_t r0 = crow[ch], r1 = crow[ch + 1];
+  const int span = r1 - r0 + 2;  // row pointers r0 .. r1 + 1 (<= C + 2)
+  for (int j = lane; j < span; j += 64) rl[j] = rowptr[r0 + j];
+  {
+    int32_t c[NPL];
+    V v[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int k = t * 64 + lane;
+      const int64_t kk = s + (k < len ? k : len - 1);
+      c[t] = col[kk];
+      v[t] = val[kk];
+    }
+    T g[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) g[t] = x[c[t]];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) prod[pad(t * 64 + lane)] = to_acc(v[t]) * g[t];
+  }
+  wave_sync();
+  const int k0 = lane * NPL;
+  const int m = len - k0 < 0 ? 0 : (len - k0 < NPL ? len - k0 : NPL);  // entries of this lane
+  T pv[NPL];
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) pv[t] = prod[pad(k0 + t)];
+  // rows of the run: the last table index j with rl[j] <= entry (rl[0] <= s,
+  // and rl[span - 1] lies past the chunk's last entry, so j stays in range)
+  int32_t r[NPL];
+  {
+    const int32_t kg = (int32_t)s + (m > 0 ? k0 : 0);
+    int lo = 0, hi = span - 2;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rl[mid] <= kg) lo = mid;
+      else hi = mid - 1;
+    }
+    int j = lo;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      if (t < m)
+        while (rl[j + 1] <= kg + t) ++j;
+      r[t] = r0 + j;
+    }
+  }
+  const int32_t first = r0;
+  const int32_t prev_last = __shfl_up(r[NPL - 1], 1, 64);
+  const int32_t next_first = __shfl_down(r[0], 1, 64);
+  const bool first_continues = rl[0] < s;  // row r0 began in an earlier chunk
+
+  auto emit = [&](int32_t rr, T sum) {
+    if (first_continues && rr == first) {
+      cont_row[ch] = rr;
+      cont_val[ch] = sum;
+    } else {
+      y[rr] = combine(alpha, sum, beta, y, rr);
+    }
+  };
+  if (lane == 0 && !first_continues) cont_row[ch] = -1;
+
+  const bool active = m > 0;
+  T vs = 0, hsum = 0, tsum = 0;
+  int f = 1;
+  int32_t hrow = 0, trow = 0;
+  bool multi = false, hstart = false, tend = false;
+  if (active) {
+    hrow = r[0];
+    hstart = lane == 0 ? !first_continues : prev_last != hrow;
+    int32_t cur = hrow;
+    T sum = 0;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      if (t < m) {
+        if (r[t] != cur) {
+          if (!multi) {
+            hsum = sum;
+            multi = true;
+          } else {
+            emit(cur, sum);
+          }
+          cur = r[t];
+          sum = 0;
+        }
+        sum += pv[t];
+      }
+    }
+    trow = cur;
+    tsum = sum;
+    tend = (k0 + m == len) || next_first != cur;
+    if (!multi) hsum = sum;
+    vs = multi ? tsum : hsum;
+    f = (multi || hstart) ? 1 : 0;
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T ov = __shfl_up(vs, d, 64);
+    const int of = __shfl_up(f, d, 64);
+    if (lane >= d) {
+      if (!f) vs = ov + vs;
+      f |= of;
+    }
+  }
+  const T up = __shfl_up(vs, 1, 64);
+  const T before = lane > 0 ? up : T(0);
+  if (active) {
+    if (multi) {
+      emit(hrow, hstart ? hsum : before + hsum);
+      if (tend) emit(trow, tsum);
+    } else if (tend) {
+      emit(hrow, vs);
+    }
+  }
+}
+
 // Adds the continuation partials of rows that straddle chunks, in chunk
 // order, to the value their first chunk wrote.
 template <typename T>
@@ -973,10 +1123,54 @@ void launch_csr_pr(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, 
     launch_csr_pr_w<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip);
 }
 
+template <typename V, typename T, int NPL, int WPB>
+void launch_csr_merge_w(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
+                        T beta, T* y, const int32_t* skip) {
+  const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
+  k_csr_merge<V, T, NPL, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
+      nnz, P.nchunks, P.rowptr, P.crow, P.col, (const V*)P.val, x, y, alpha, beta, P.cont_row,
+      (T*)P.cont_val, skip);
+}
+
+template <typename V, typename T, int NPL>
+void launch_csr_merge_n(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
+                        T beta, T* y, const int32_t* skip) {
+  if (P.wpb == 1)
+    launch_csr_merge_w<V, T, NPL, 1>(ctx, P, nnz, alpha, x, beta, y, skip);
+  else
+    launch_csr_merge_w<V, T, NPL, 4>(ctx, P, nnz, alpha, x, beta, y, skip);
+}
+
+// merge-path CSR: empty rows, the chunks, then the fix-up of cut rows
+template <typename V, typename T>
+void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
+                      const int32_t* skip) {
+  const CsrPart& P = A->csr;
+  if (P.nempty > 0)
+    k_empty_rows<T><<<(unsigned)((P.nempty + 255) / 256), 256, 0, ctx->stream>>>(
+        P.nempty, P.empty_rows, y, beta, skip);
+  if (P.nchunks == 0) return;
+  switch (P.block_nnz) {
+    case 256: launch_csr_merge_n<V, T, 4>(ctx, P, A->nnz, alpha, x, beta, y, skip); break;
+    case 512: launch_csr_merge_n<V, T, 8>(ctx, P, A->nnz, alpha, x, beta, y, skip); break;
+    default: launch_csr_merge_n<V, T, 16>(ctx, P, A->nnz, alpha, x, beta, y, skip);
+  }
+  if (P.nchunks > 1)
+    k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
+        P.nchunks, P.cont_row, (T*)P.cont_val, y, alpha, skip);
+}
+
 template <typename V, typename T, bool SCALED>
 void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
                 const int32_t* skip) {
   const CsrPart& P = A->csr;
+  if (P.merge) {
+    // set-up admits FP64 and FP32 values only
+    if constexpr (!SCALED && std::is_same_v<V, T> &&
+                  (std::is_same_v<T, double> || std::is_same_v<T, float>))
+      launch_csr_merge<V, T>(ctx, A, alpha, x, beta, y, skip);
+    return;
+  }
   if (P.products) {
     if (P.nblocks == 0) return;
     if (P.block_nnz <= 512)

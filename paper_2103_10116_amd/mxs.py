@@ -56,7 +56,8 @@ class ConvertOpts(C.Structure):
 
 CSR_AUTO, CSR_STREAM, CSR_VECTOR, CSR_ROWS_LDS, CSR_PRODUCTS = 0, 1, 2, 3, 4
 CSR_KERNELS = {"auto": CSR_AUTO, "stream": CSR_STREAM, "vector": CSR_VECTOR,
-               "rows_lds": CSR_ROWS_LDS, "products": CSR_PRODUCTS}
+               "rows_lds": CSR_ROWS_LDS, "products": CSR_PRODUCTS, "merge": 5}
+CSR_MERGE = 5
 COO_AUTO, COO_LDS, COO_RUNS = 0, 1, 2
 COO_KERNELS = {"auto": COO_AUTO, "lds": COO_LDS, "runs": COO_RUNS}
 

@@ -214,7 +214,9 @@ CSR_VARIANTS = [dict(csr_kernel="stream", block_nnz=b, waves_per_group=w)
     dict(csr_kernel="rows_lds", block_nnz=b, lanes_per_row=g)
     for b in (512, 1024, 2048) for g in (1, 2, 4)] + [
     dict(csr_kernel="products", block_nnz=b, waves_per_group=w)
-    for b in (0, 512, 1024, 2048) for w in (0, 1, 2, 4)]
+    for b in (0, 512, 1024, 2048) for w in (0, 1, 2, 4)] + [
+    dict(csr_kernel="merge", block_nnz=b, waves_per_group=w)
+    for b in (0, 256, 512, 1024) for w in (1, 4)]
 
 
 @pytest.mark.parametrize("name", sorted(ZOO))
@@ -242,6 +244,10 @@ def test_spmv_csr_kernels(env, orc, name, dt):
     scale = 1.5 * orc.absrow(Aref, xr) + 0.5 * np.abs(y0r)
     tdt = torch.float64 if dt == "f64" else torch.float32
     for opts in CSR_VARIANTS:
+        if opts["csr_kernel"] == "merge" and dt == "f16":
+            with pytest.raises(mxs.MxsError):  # FP64 and FP32 values only
+                M.convert("csr", dt, **opts)
+            continue
         B = M.convert("csr", dt, **opts)
         d = B.info()
         assert (d["lanes_per_row"] > 0) == (opts["csr_kernel"] in ("vector", "rows_lds"))
@@ -249,7 +255,7 @@ def test_spmv_csr_kernels(env, orc, name, dt):
             g = d["lanes_per_row"]
             assert g == opts.get("lanes_per_row", g) and g in (1, 2, 4)
         assert d["csr_kernel"] == mxs.CSR_KERNELS[opts["csr_kernel"]]
-        if opts["csr_kernel"] in ("rows_lds", "products") and opts["block_nnz"]:
+        if opts["csr_kernel"] in ("rows_lds", "products", "merge") and opts["block_nnz"]:
             assert d["block_nnz"] == opts["block_nnz"]
         y = torch.from_numpy(y0r).to(tdt).cuda()
         mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
@@ -343,6 +349,30 @@ def test_spmv_f16_rowscaled(env, orc, name):
     _check(y.cpu().numpy().astype(np.float64), ref, orc.absrow(Ad, x.astype(np.float64)), 1e-5)
 
 
+def test_csr_merge_limits(env):
+    """The merge-path kernel refuses a chunk whose rows outgrow its LDS table
+    (a long run of empty rows) and complex values; an all-empty matrix of
+    many rows works (y = beta y)."""
+    mxs, ctx, torch = env
+    n = 2000
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = 1
+    rp[n] = 2
+    M = mxs.Matrix.from_csr(ctx, n, n, rp, np.array([0, n - 1], np.int32), np.array([2.0, 3.0]))
+    with pytest.raises(mxs.MxsError) as e:
+        M.convert("csr", "f64", csr_kernel="merge", block_nnz=256)
+    assert e.value.status == mxs.UNSUPPORTED
+    Z = mxs.Matrix.from_host_complex(ctx, 3, 3, np.array([0, 1, 2, 3], np.int32),
+                                     np.array([0, 1, 2], np.int32), np.array([1 + 1j, 2, 3j]))
+    with pytest.raises(mxs.MxsError):
+        Z.convert("csr", "c128", csr_kernel="merge")
+    E = mxs.Matrix.from_csr(ctx, 300, 300, np.zeros(301, np.int32), np.zeros(0, np.int32),
+                            np.zeros(0)).convert("csr", "f64", csr_kernel="merge")
+    y = torch.ones(300, dtype=torch.float64, device="cuda")
+    mxs.spmv(ctx, E, torch.ones(300, dtype=torch.float64, device="cuda"), y, 1.0, 2.0)
+    assert torch.all(y == 2.0)
+
+
 def test_spmv_empty_matrix(env):
     mxs, ctx, torch = env
     M = mxs.Matrix.from_csr(ctx, 0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32),
@@ -391,8 +421,8 @@ def test_spmv_full_size(env, orc, which):
     scale32 = orc.absrow(A32, x32.astype(np.float64))
     M = mxs.Matrix.from_host(ctx, A)
     # COO in both kernels (AUTO picks one of them)
-    cases = [("csr", {}), ("coo", {"coo_kernel": "lds"}), ("coo", {"coo_kernel": "runs"}),
-             ("ell", {}), ("hyb", {})]
+    cases = [("csr", {}), ("csr", {"csr_kernel": "merge"}), ("coo", {"coo_kernel": "lds"}),
+             ("coo", {"coo_kernel": "runs"}), ("ell", {}), ("hyb", {})]
     for fmt, opts in cases:
         if fmt == "ell" and which == "zipf_2p20_m16":
             continue  # the same 4096-wide padded layout as zipf_2p20 (51.5 GB in FP64)
