@@ -133,8 +133,8 @@ typedef struct {
   int32_t coo_kernel;     /* COO and the COO part of HYB: MXS_COO_AUTO, MXS_COO_LDS, MXS_COO_RUNS */
 } mxs_convert_opts;
 
-#define MXS_CSR_AUTO 0   /* MERGE if a row exceeds 64 entries (FP64/FP32 values whose chunks fit,
-                            else STREAM); else ROWS_LDS for F32/F16
+#define MXS_CSR_AUTO 0   /* MERGE if a row exceeds 64 entries (real values whose chunks fit, else
+                            STREAM); else ROWS_LDS for F32/F16
                             values and for F64 rows of at most 8 entries, PRODUCTS otherwise */
 #define MXS_CSR_STREAM 1
 #define MXS_CSR_VECTOR 2
@@ -142,9 +142,9 @@ typedef struct {
 #define MXS_CSR_PRODUCTS 4 /* blocks of <= 64 rows; products formed by all lanes, summed per row from LDS */
 #define MXS_CSR_MERGE 5    /* equal chunks of block_nnz entries whatever the rows (merge path): each
                               chunk's row pointers staged in LDS give the row of every entry; rows cut
-                              by chunk edges completed by a fix-up pass.  FP64/FP32 values only, and
-                              no chunk may span more than block_nnz + 1 rows (long runs of empty
-                              rows): otherwise MXS_UNSUPPORTED */
+                              by chunk edges completed by a fix-up pass.  FP64, FP32 and row-scaled
+                              FP16 values, and no chunk may span more than block_nnz + 1 rows (long
+                              runs of empty rows): otherwise MXS_UNSUPPORTED */
 
 #define MXS_COO_AUTO 0 /* RUNS for FP32/FP16 values when no row has more than 16 entries in
                           the part, else LDS */

@@ -303,8 +303,9 @@ bool merge_rows(const std::vector<int32_t>& rp, int64_t nnz, int C, std::vector<
 }
 
 mxs_status build_csr_merge(mxs_ctx* ctx, mxs_matrix* A, const mxs_convert_opts* opts) {
-  if (A->dt != MXS_F64 && A->dt != MXS_F32)
-    return fail(ctx, MXS_UNSUPPORTED, "the merge-path CSR kernel takes FP64 or FP32 values");
+  if (A->dt != MXS_F64 && A->dt != MXS_F32 && A->dt != MXS_F16_ROWSCALED)
+    return fail(ctx, MXS_UNSUPPORTED,
+                "the merge-path CSR kernel takes FP64, FP32 or row-scaled FP16 values");
   const std::vector<int32_t>& rp = A->h_rowptr;
   const int64_t n = A->n, nnz = A->nnz;
   const int C = merge_chunk(opts);
@@ -372,7 +373,7 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
     // s = 1.79 FP32 119.1 vs 134.5, FP64 198.3 vs 201.5)
     std::vector<int32_t> crow;
     int64_t bad = 0;
-    if (maxL > 64 && (A->dt == MXS_F64 || A->dt == MXS_F32) &&
+    if (maxL > 64 && (A->dt == MXS_F64 || A->dt == MXS_F32 || A->dt == MXS_F16_ROWSCALED) &&
         merge_rows(rp, A->nnz, merge_chunk(opts), crow, &bad))
       kind_eff = MXS_CSR_MERGE;
   }

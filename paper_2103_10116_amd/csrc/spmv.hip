@@ -805,12 +805,13 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
 // cut by chunk edges are completed by k_coo_fix.  Against COO it reads no
 // row index per entry; against the row-block stream kernel every wave gets
 // the same number of entries whatever the row lengths.
-template <typename V, typename T, int NPL, int WPB>
+template <typename V, typename T, int NPL, int WPB, bool SCALED>
 __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nchunks,
                                                        const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ crow,
                                                        const int32_t* __restrict__ col,
                                                        const V* __restrict__ val,
+                                                       const float* __restrict__ scale,
                                                        const T* __restrict__ x, T* __restrict__ y,
                                                        T alpha, T beta,
                                                        int32_t* __restrict__ cont_row,
@@ -833,19 +834,20 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nch
   for (int j = lane; j < span; j += 64) rl[j] = rowptr[r0 + j];
   {
     int32_t c[NPL];
-    V v[NPL];
+    typename Raw<V>::type v[NPL];  // 2-byte values staged one per register
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const int k = t * 64 + lane;
       const int64_t kk = s + (k < len ? k : len - 1);
       c[t] = col[kk];
-      v[t] = val[kk];
+      v[t] = Raw<V>::load(val, kk);
     }
     T g[NPL];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) g[t] = x[c[t]];
 #pragma unroll
-    for (int t = 0; t < NPL; ++t) prod[pad(t * 64 + lane)] = to_acc(v[t]) * g[t];
+    for (int t = 0; t < NPL; ++t)
+      prod[pad(t * 64 + lane)] = to_acc(Raw<V>::value(v[t])) * g[t];
   }
   wave_sync();
   const int k0 = lane * NPL;
@@ -877,7 +879,10 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nch
   const int32_t next_first = __shfl_down(r[0], 1, 64);
   const bool first_continues = rl[0] < s;  // row r0 began in an earlier chunk
 
+  // a row's partial sums are scaled (FP16 values with per-row scales) before
+  // they are stored or joined by the fix-up pass
   auto emit = [&](int32_t rr, T sum) {
+    if (SCALED) sum *= (T)scale[rr];
     if (first_continues && rr == first) {
       cont_row[ch] = rr;
       cont_val[ch] = sum;
@@ -1123,26 +1128,26 @@ void launch_csr_pr(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, 
     launch_csr_pr_w<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip);
 }
 
-template <typename V, typename T, int NPL, int WPB>
+template <typename V, typename T, int NPL, int WPB, bool SCALED>
 void launch_csr_merge_w(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
                         T beta, T* y, const int32_t* skip) {
   const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
-  k_csr_merge<V, T, NPL, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-      nnz, P.nchunks, P.rowptr, P.crow, P.col, (const V*)P.val, x, y, alpha, beta, P.cont_row,
-      (T*)P.cont_val, skip);
+  k_csr_merge<V, T, NPL, WPB, SCALED><<<grid, 64 * WPB, 0, ctx->stream>>>(
+      nnz, P.nchunks, P.rowptr, P.crow, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
+      P.cont_row, (T*)P.cont_val, skip);
 }
 
-template <typename V, typename T, int NPL>
+template <typename V, typename T, int NPL, bool SCALED>
 void launch_csr_merge_n(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
                         T beta, T* y, const int32_t* skip) {
   if (P.wpb == 1)
-    launch_csr_merge_w<V, T, NPL, 1>(ctx, P, nnz, alpha, x, beta, y, skip);
+    launch_csr_merge_w<V, T, NPL, 1, SCALED>(ctx, P, nnz, alpha, x, beta, y, skip);
   else
-    launch_csr_merge_w<V, T, NPL, 4>(ctx, P, nnz, alpha, x, beta, y, skip);
+    launch_csr_merge_w<V, T, NPL, 4, SCALED>(ctx, P, nnz, alpha, x, beta, y, skip);
 }
 
 // merge-path CSR: empty rows, the chunks, then the fix-up of cut rows
-template <typename V, typename T>
+template <typename V, typename T, bool SCALED>
 void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
                       const int32_t* skip) {
   const CsrPart& P = A->csr;
@@ -1151,9 +1156,9 @@ void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T 
         P.nempty, P.empty_rows, y, beta, skip);
   if (P.nchunks == 0) return;
   switch (P.block_nnz) {
-    case 256: launch_csr_merge_n<V, T, 4>(ctx, P, A->nnz, alpha, x, beta, y, skip); break;
-    case 512: launch_csr_merge_n<V, T, 8>(ctx, P, A->nnz, alpha, x, beta, y, skip); break;
-    default: launch_csr_merge_n<V, T, 16>(ctx, P, A->nnz, alpha, x, beta, y, skip);
+    case 256: launch_csr_merge_n<V, T, 4, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip); break;
+    case 512: launch_csr_merge_n<V, T, 8, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip); break;
+    default: launch_csr_merge_n<V, T, 16, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip);
   }
   if (P.nchunks > 1)
     k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
@@ -1165,10 +1170,10 @@ void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, 
                 const int32_t* skip) {
   const CsrPart& P = A->csr;
   if (P.merge) {
-    // set-up admits FP64 and FP32 values only
-    if constexpr (!SCALED && std::is_same_v<V, T> &&
-                  (std::is_same_v<T, double> || std::is_same_v<T, float>))
-      launch_csr_merge<V, T>(ctx, A, alpha, x, beta, y, skip);
+    // set-up admits FP64, FP32 and row-scaled FP16 values
+    if constexpr (std::is_same_v<V, double> || std::is_same_v<V, float> ||
+                  std::is_same_v<V, _Float16>)
+      launch_csr_merge<V, T, SCALED>(ctx, A, alpha, x, beta, y, skip);
     return;
   }
   if (P.products) {

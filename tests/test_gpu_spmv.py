@@ -244,10 +244,6 @@ def test_spmv_csr_kernels(env, orc, name, dt):
     scale = 1.5 * orc.absrow(Aref, xr) + 0.5 * np.abs(y0r)
     tdt = torch.float64 if dt == "f64" else torch.float32
     for opts in CSR_VARIANTS:
-        if opts["csr_kernel"] == "merge" and dt == "f16":
-            with pytest.raises(mxs.MxsError):  # FP64 and FP32 values only
-                M.convert("csr", dt, **opts)
-            continue
         B = M.convert("csr", dt, **opts)
         d = B.info()
         assert (d["lanes_per_row"] > 0) == (opts["csr_kernel"] in ("vector", "rows_lds"))
