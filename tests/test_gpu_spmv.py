@@ -345,7 +345,7 @@ def test_spmv_f16_rowscaled(env, orc, name):
     _check(y.cpu().numpy().astype(np.float64), ref, orc.absrow(Ad, x.astype(np.float64)), 1e-5)
 
 
-def test_csr_merge_limits(env):
+def test_csr_merge_limits(env, orc):
     """The merge-path kernel refuses a chunk whose rows outgrow its LDS table
     (a long run of empty rows) and complex values; an all-empty matrix of
     many rows works (y = beta y)."""
@@ -362,6 +362,22 @@ def test_csr_merge_limits(env):
                                      np.array([0, 1, 2], np.int32), np.array([1 + 1j, 2, 3j]))
     with pytest.raises(mxs.MxsError):
         Z.convert("csr", "c128", csr_kernel="merge")
+    # AUTO: a row over 64 entries asks for the merge path, but the one chunk
+    # would span 3000 rows: the row-block stream kernel is used instead
+    n2 = 3000
+    rp2 = np.full(n2 + 1, 100, np.int32)
+    rp2[0] = 0
+    rp2[n2] = 101
+    col2 = np.concatenate([np.arange(100) * 7, [5]]).astype(np.int32)
+    val2 = I.uniform_vector(101, 61)
+    A2 = I.CSRMatrix(n2, n2, rp2, col2, val2)
+    M2 = mxs.Matrix.from_csr(ctx, n2, n2, rp2, col2, val2)
+    assert M2.info()["csr_kernel"] == mxs.CSR_STREAM
+    x2 = I.uniform_vector(n2, 62)
+    y2 = torch.zeros(n2, dtype=torch.float64, device="cuda")
+    mxs.spmv(ctx, M2, _dev(torch, x2), y2)
+    ref2 = orc.spmv_csr(A2, x2)
+    _check(y2.cpu().numpy(), ref2, orc.absrow(A2, x2), 1e-13)
     E = mxs.Matrix.from_csr(ctx, 300, 300, np.zeros(301, np.int32), np.zeros(0, np.int32),
                             np.zeros(0)).convert("csr", "f64", csr_kernel="merge")
     y = torch.ones(300, dtype=torch.float64, device="cuda")
