@@ -3,15 +3,19 @@
 // Functionality"; the byte-per-entry model of its "SpMV Performance
 // Analysis" subsection makes every variant HBM-bound, so none uses MFMA).
 //
-// CSR  -- one wave per row block (<= 64*NPL entries, whole rows).  The wave
-//         streams the block's values and column indices with fully
-//         coalesced loads, gathers x, and stages the products and the
-//         block's row pointers in LDS.  Each lane then owns NPL consecutive
-//         products, sums the row segments it holds, and a segmented
-//         inclusive scan across the 64 lanes joins the segments of rows that
-//         straddle lanes.  Work per lane is NPL regardless of the row-length
-//         mix; a row longer than the block budget gets a wave of its own
-//         with four independent accumulators per lane.
+// CSR  -- five kernels.  Stream: one wave per row block (<= 64*NPL
+//         entries, whole rows); the wave streams the block's values and
+//         column indices with fully coalesced loads, gathers x, and stages
+//         the products and the block's row pointers in LDS.  Each lane then
+//         owns NPL consecutive products, sums the row segments it holds, and
+//         a segmented inclusive scan across the 64 lanes joins the segments
+//         of rows that straddle lanes; a row longer than the block budget
+//         gets a wave of its own with four independent accumulators per lane.
+//         Merge path: the same lane runs over equal chunks of entries
+//         whatever the rows, each entry's row found from the chunk's row
+//         pointers in LDS, cut rows fixed up as for COO.  Rows-from-LDS and
+//         products-through-LDS: blocks of at most 64 rows for short-row
+//         matrices.  Vector: G lanes per row, on request.
 // COO  -- same lane-run/segmented-scan scheme over fixed chunks of 64*NPL
 //         entries.  A row cut by a chunk boundary is written by the chunk
 //         where it starts; later chunks store their part as a continuation
