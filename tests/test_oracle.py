@@ -187,6 +187,52 @@ def test_spmv_vs_dense(orc, shape, density, empty, full):
     assert np.array_equal(orc.spmv_hyb(orc.csr_to_hyb(Ai, 8), xi), Mi @ xi)
 
 
+_DENSE_ZOO = [((1, 1), 1.0, (), None), ((7, 7), 0.0, (), None), ((33, 40), 0.2, (0, 5, 32), 7),
+              ((64, 64), 0.5, (3,), 63), ((50, 17), 0.3, (), 0)]
+
+
+@pytest.mark.parametrize("shape,density,empty,full", _DENSE_ZOO)
+def test_absrow_vs_dense(orc, shape, density, empty, full):
+    """The tolerance scale sum_j |a_ij| |x_j| of every parity check, against
+    numpy's dense |M| |x| (a different summation order: within (L+1)u).
+    The matrix is rectangular or nonsymmetric and x has no symmetry, so a
+    row/column swap, a dropped modulus or a wrong index fails."""
+    M = random_pattern(*shape, density, seed=sum(shape) + 1, empty_rows=empty, full_row=full)
+    A = I.dense_to_csr(M)
+    x = I.rng(19).uniform(-1, 1, shape[1])
+    ref = np.abs(M) @ np.abs(x)
+    got = orc.absrow(A, x)
+    assert np.all(np.abs(got - ref) <= (shape[1] + 1) * U * ref)
+    for r in empty:
+        assert got[r] == 0.0
+    # it bounds the product it scales: |y_i| <= sum_j |a_ij| |x_j|
+    assert np.all(np.abs(orc.spmv_csr(A, x)) <= got * (1 + 4 * U))
+    # x with one nonzero entry picks one column of |M|, exactly
+    if shape[1] > 1 and density > 0:
+        e = np.zeros(shape[1])
+        e[shape[1] // 2] = -2.0
+        assert np.array_equal(orc.absrow(A, e), 2.0 * np.abs(M[:, shape[1] // 2]))
+
+
+@pytest.mark.parametrize("shape,density,empty,full", _DENSE_ZOO)
+def test_absrow_z_vs_dense(orc, shape, density, empty, full):
+    """Complex moduli: numpy's dense |M| |x| with |.| the complex modulus."""
+    M = random_pattern(*shape, density, seed=sum(shape) + 2, empty_rows=empty, full_row=full)
+    g = I.rng(23)
+    Mz = M + 1j * np.where(M != 0, g.uniform(-1, 1, M.shape), 0.0)
+    A = I.dense_to_csr(M)                       # the pattern of Mz (same nonzeros)
+    zval = Mz[M != 0]                           # row-major, columns ascending
+    x = g.uniform(-1, 1, shape[1]) + 1j * g.uniform(-1, 1, shape[1])
+    ref = np.abs(Mz) @ np.abs(x)
+    got = orc.absrow_z(A.n, A.rowptr, A.col, zval, x)
+    assert np.all(np.abs(got - ref) <= (shape[1] + 2) * U * ref)
+    # a purely imaginary matrix has the same scale as its real magnitudes
+    zim = 1j * np.abs(A.val)
+    assert np.array_equal(orc.absrow_z(A.n, A.rowptr, A.col, zim, np.abs(x) + 0j),
+                          orc.absrow(I.CSRMatrix(A.n, A.ncols, A.rowptr, A.col, np.abs(A.val)),
+                                     np.abs(x)))
+
+
 def test_spmv_accurate_beats_naive(orc):
     # catastrophic cancellation: 1e16 + 1 - 1e16 is 1 exactly
     A = I.dense_to_csr(np.array([[1e16, 1.0, -1e16]]))
