@@ -81,6 +81,8 @@ _D = C.c_double
 def _declare(L):
     sig = {
         "orc_csr_validate": (C.c_int, [_I64, _I64, _I64, _P, _P]),
+        "orc_csr_sort_and_sum": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, C.c_int, _P, _P, _P,
+                                           C.POINTER(_I64)]),
         "orc_csr_to_coo": (None, [_I64, _P, _P]),
         "orc_coo_to_csr": (None, [_I64, _I64, _P, _P]),
         "orc_ell_width": (_I64, [_I64, _P]),
@@ -147,6 +149,29 @@ def validate(n, ncols, rowptr, col) -> int:
     rp = _c(rowptr, np.int32)
     ci = _c(col, np.int32)
     return lib().orc_csr_validate(n, ncols, int(rp[-1]) if len(rp) else 0, _p(rp), _p(ci))
+
+
+def csr_sort_and_sum(n, ncols, rowptr, col, val):
+    """(status, CSRMatrix-like tuple (rowptr, col, val)) of the row-grouped
+    list with each row ordered by column and repeated columns summed in input
+    order; val may be real (float64) or complex (complex128)."""
+    rp = _c(rowptr, np.int32)
+    ci = _c(col, np.int32)
+    cplx = np.iscomplexobj(val)
+    v = _c(np.asarray(val, np.complex128).view(np.float64) if cplx else val, np.float64)
+    nnz = int(rp[n]) if len(rp) > n else 0
+    vpe = 2 if cplx else 1
+    orp = np.zeros(n + 1, np.int32)
+    oc = np.zeros(max(nnz, 1), np.int32)
+    ov = np.zeros(max(nnz, 1) * vpe, np.float64)
+    nout = _I64(0)
+    st = lib().orc_csr_sort_and_sum(n, ncols, len(ci), _p(rp), _p(ci), _p(v), vpe, _p(orp),
+                                    _p(oc), _p(ov), C.byref(nout))
+    if st != OK:
+        return st, None
+    k = nout.value
+    ov = ov[:k * vpe]
+    return st, (orp, oc[:k].copy(), (ov.view(np.complex128) if cplx else ov).copy())
 
 
 def csr_to_coo(n, rowptr):

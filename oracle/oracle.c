@@ -91,6 +91,78 @@ int orc_csr_validate(int64_t n, int64_t ncols, int64_t nnz,
   return ORC_OK;
 }
 
+/* Ingest of a row-grouped coordinate list whose columns may be unordered or
+ * repeated within a row (paper, "Central Sparse Linear Algebra
+ * Functionality": CSR is the row-sorted coordinate list compressed by row
+ * pointers; an entry listed twice stands for the sum of its values).  Each
+ * row's entries are ordered by column with ties kept in input order (a
+ * sort whose key is the pair (column, position in the row), so it is
+ * stable by construction), and each run of equal columns becomes one entry
+ * whose value is the run's values added left to right, i.e. in input
+ * order: ((v0 + v1) + v2) + ...  A run that sums to zero stays as an
+ * explicit zero.  Row pointers and column range are checked as in
+ * orc_csr_validate (order and repeats are what this routine repairs).
+ * vpe = doubles per value (1 real, 2 complex as (re, im), parts summed
+ * separately).  Outputs: rowptr_out[n+1], col_out / val_out with room for
+ * nnz entries; *nnz_out = entries kept. */
+typedef struct {
+  int32_t col;
+  int64_t pos;
+} orc_key;
+
+static int orc_key_cmp(const void* a, const void* b) {
+  const orc_key* x = (const orc_key*)a;
+  const orc_key* y = (const orc_key*)b;
+  if (x->col != y->col) return x->col < y->col ? -1 : 1;
+  return x->pos < y->pos ? -1 : (x->pos > y->pos ? 1 : 0);
+}
+
+int orc_csr_sort_and_sum(int64_t n, int64_t ncols, int64_t nnz,
+                         const int32_t* rowptr, const int32_t* col,
+                         const double* val, int vpe, int32_t* rowptr_out,
+                         int32_t* col_out, double* val_out, int64_t* nnz_out) {
+  if (n < 0 || ncols < 0 || nnz < 0 || (vpe != 1 && vpe != 2)) return ORC_INVALID_ARG;
+  if (n > INT32_MAX || ncols > INT32_MAX || nnz > INT32_MAX) return ORC_UNSUPPORTED;
+  if (rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) return ORC_INVALID_MATRIX;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return ORC_INVALID_MATRIX;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+      if (col[k] < 0 || (int64_t)col[k] >= ncols) return ORC_INVALID_MATRIX;
+  }
+  int64_t maxlen = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] - rowptr[i] > maxlen) maxlen = rowptr[i + 1] - rowptr[i];
+  orc_key* keys = (orc_key*)malloc((size_t)(maxlen > 0 ? maxlen : 1) * sizeof(orc_key));
+  if (!keys) return ORC_INVALID_ARG;
+  int64_t out = 0;
+  rowptr_out[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t s = rowptr[i], L = rowptr[i + 1] - rowptr[i];
+    for (int64_t t = 0; t < L; ++t) {
+      keys[t].col = col[s + t];
+      keys[t].pos = t;
+    }
+    qsort(keys, (size_t)L, sizeof(orc_key), orc_key_cmp);
+    int64_t t = 0;
+    while (t < L) {
+      const int32_t c = keys[t].col;
+      for (int q = 0; q < vpe; ++q) {
+        double sum = val[(s + keys[t].pos) * vpe + q];
+        for (int64_t u = t + 1; u < L && keys[u].col == c; ++u)
+          sum = sum + val[(s + keys[u].pos) * vpe + q];
+        val_out[out * vpe + q] = sum;
+      }
+      col_out[out] = c;
+      ++out;
+      while (t < L && keys[t].col == c) ++t;
+    }
+    rowptr_out[i + 1] = (int32_t)out;
+  }
+  free(keys);
+  *nnz_out = out;
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* conversions                                                              */
 /* ------------------------------------------------------------------------ */

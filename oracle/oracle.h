@@ -35,6 +35,12 @@ enum {
 /* ---- CSR ingest ------------------------------------------------------- */
 int orc_csr_validate(int64_t n, int64_t ncols, int64_t nnz,
                      const int32_t* rowptr, const int32_t* col);
+/* Rows ordered by column (ties in input order), repeated columns summed in
+ * input order; vpe = doubles per value (1 real, 2 complex). */
+int orc_csr_sort_and_sum(int64_t n, int64_t ncols, int64_t nnz,
+                         const int32_t* rowptr, const int32_t* col,
+                         const double* val, int vpe, int32_t* rowptr_out,
+                         int32_t* col_out, double* val_out, int64_t* nnz_out);
 
 /* ---- format conversions ----------------------------------------------- */
 void orc_csr_to_coo(int64_t n, const int32_t* rowptr, int32_t* row_out);

@@ -50,6 +50,113 @@ def test_validate_accepts_and_rejects(orc):
 # ---------------------------------------------------------------------------
 # conversions: hand-computed layouts and round trips
 # ---------------------------------------------------------------------------
+def unsorted_rows(n, ncols, max_len, seed, integer=True, dup_rate=0.4, empty_every=5):
+    """A row-grouped coordinate list: each row's columns in random order with
+    repeats (about dup_rate of the entries repeat a column of the row)."""
+    g = I.rng(seed)
+    rows_c, rows_v, lens = [], [], []
+    for i in range(n):
+        L = 0 if (empty_every and i % empty_every == 0) else int(g.integers(1, max_len + 1))
+        base = g.choice(ncols, size=min(ncols, max(1, int(np.ceil(L * (1 - dup_rate))))),
+                        replace=False)
+        c = g.choice(base, size=L, replace=True) if L else np.zeros(0, np.int64)
+        v = (g.integers(-8, 9, L).astype(float) if integer else g.uniform(-1, 1, L))
+        rows_c.append(c)
+        rows_v.append(v)
+        lens.append(L)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    return (rp.astype(np.int32), np.concatenate(rows_c).astype(np.int32),
+            np.concatenate(rows_v))
+
+
+def test_sort_and_sum_golden(orc):
+    """Hand-worked example: order within a row, ties in input order (the
+    1e16 + 1 - 1e16 and 0.1 + 0.2 + 0.3 rows fix the summation order),
+    empty and already-sorted rows, explicit zeros kept."""
+    g = load_golden("sort_and_sum_small.txt")
+    st, (rp, c, v) = orc.csr_sort_and_sum(g["n"][0], g["ncols"][0], np.array(g["rowptr"]),
+                                          np.array(g["col"]), np.array(g["val"], float))
+    assert st == orc.OK
+    assert np.array_equal(rp, g["out_rowptr"]) and np.array_equal(c, g["out_col"])
+    assert np.array_equal(v.view(np.uint64), np.array(g["out_val"], float).view(np.uint64))
+
+
+@pytest.mark.parametrize("seed,max_len", [(1, 6), (2, 40), (3, 300)])
+def test_sort_and_sum_vs_dense_accumulation(orc, seed, max_len):
+    """Brute force: integer values make every sum exact whatever the order,
+    so the result must equal a dense accumulation at exactly the (row, col)
+    pairs the input lists, each row strictly ascending (a valid CSR)."""
+    n, ncols = 60, 97
+    rp, col, val = unsorted_rows(n, ncols, max_len, seed)
+    st, (orp, oc, ov) = orc.csr_sort_and_sum(n, ncols, rp, col, val)
+    assert st == orc.OK
+    assert orc.validate(n, ncols, orp, oc) == orc.OK
+    dense = np.zeros((n, ncols))
+    present = np.zeros((n, ncols), bool)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    np.add.at(dense, (rows, col), val)
+    present[rows, col] = True
+    orows = np.repeat(np.arange(n), np.diff(orp))
+    assert np.array_equal(present.nonzero()[0], orows)
+    assert np.array_equal(present.nonzero()[1], oc)
+    assert np.array_equal(dense[present], ov)
+    # complex values: each part summed on its own
+    cv = val + 1j * np.roll(val, 3)
+    st, (_, oc2, ov2) = orc.csr_sort_and_sum(n, ncols, rp, col, cv)
+    dz = np.zeros((n, ncols), complex)
+    np.add.at(dz, (rows, col), cv)
+    assert st == orc.OK and np.array_equal(oc2, oc) and np.array_equal(dz[present], ov2)
+
+
+def test_sort_and_sum_identity_and_rejects(orc):
+    """A valid CSR comes back unchanged, bit for bit; bad row pointers and
+    columns out of range are still rejected."""
+    A = I.zipf_random(800, 2.0, 120, seed=31)
+    st, (rp, c, v) = orc.csr_sort_and_sum(A.n, A.ncols, A.rowptr, A.col, A.val)
+    assert st == orc.OK and np.array_equal(rp, A.rowptr) and np.array_equal(c, A.col)
+    assert np.array_equal(v.view(np.uint64), A.val.view(np.uint64))
+    rp, col, val = unsorted_rows(10, 8, 5, 4)
+    bad = col.copy()
+    bad[3] = 8
+    assert orc.csr_sort_and_sum(10, 8, rp, bad, val)[0] == orc.INVALID_MATRIX
+    bad[3] = -1
+    assert orc.csr_sort_and_sum(10, 8, rp, bad, val)[0] == orc.INVALID_MATRIX
+    for k, d in ((0, 1), (10, -1), (5, 10 ** 6)):   # start, end, monotone
+        rpb = rp.astype(np.int64).copy()
+        rpb[k] += d
+        assert orc.csr_sort_and_sum(10, 8, rpb.astype(np.int32), col, val)[0] == \
+            orc.INVALID_MATRIX
+
+
+def test_sort_and_sum_ties_keep_input_order(orc):
+    """Three repeats whose sum depends on the order: only the input order
+    gives (1e16 + 1) - 1e16 = 0; placed at random positions of long rows with
+    random other columns, the sorted row still sums them in input order."""
+    g = I.rng(77)
+    n, ncols = 40, 500
+    cols, vals, lens = [], [], []
+    for i in range(n):
+        other = g.choice(np.arange(1, ncols), size=30, replace=False)
+        c = np.concatenate([other, [0, 0, 0]])
+        v = np.concatenate([g.uniform(-1, 1, 30), [1e16, 1.0, -1e16]])
+        perm = g.permutation(33)
+        # keep the three repeats in their original relative order
+        rep = np.sort(perm[30:])
+        order = np.empty(33, np.int64)
+        order[np.setdiff1d(np.arange(33), rep)] = g.permutation(30)
+        order[rep] = [30, 31, 32]
+        cols.append(c[order])
+        vals.append(v[order])
+        lens.append(33)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    st, (orp, oc, ov) = orc.csr_sort_and_sum(n, ncols, rp, np.concatenate(cols),
+                                            np.concatenate(vals))
+    assert st == orc.OK
+    first = orp[:-1]
+    assert np.array_equal(oc[first], np.zeros(n)) and np.array_equal(ov[first], np.zeros(n))
+
+
 def test_formats_match_hand_layout(orc):
     g, A = small_from_golden()
     assert np.array_equal(orc.csr_to_coo(A.n, A.rowptr), g["coo_row"])
