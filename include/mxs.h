@@ -18,9 +18,11 @@
  *  - All GPU work is enqueued on the ctx's HIP stream.  mxs_spmv returns
  *    without synchronising; calls that must report a result to the host
  *    (matrix creation/conversion, solvers, probes) synchronise that stream.
- *  - A ctx must not be used by two host threads at the same time.  Two
- *    SpMVs with the same COO or hybrid matrix must not run concurrently on
- *    different streams (the matrix owns a small scratch array per chunk).
+ *  - A ctx must not be used by two host threads at the same time.  A
+ *    matrix is read-only during a product or a solve: the chunked products
+ *    (merge-path CSR, COO, the COO part of hybrid) keep their per-chunk
+ *    continuation partials in scratch memory of the ctx, so one matrix may
+ *    be used by several ctxs on different streams at once.
  */
 #ifndef MXS_H
 #define MXS_H
@@ -96,6 +98,7 @@ mxs_status mxs_ctx_synchronize(mxs_ctx* ctx);
 /* ---------------------------------------------------------------------- */
 #define MXS_HOST_PTRS 0   /* rowptr/col/val are host memory (copied in)   */
 #define MXS_DEVICE_PTRS 1 /* rowptr/col/val are device memory (copied)    */
+#define MXS_SORT_AND_SUM 2 /* OR-ed with one of the above: see below        */
 
 /* Ingest a CSR matrix (paper, section "Central Sparse Linear Algebra
  * Functionality": row pointers to the first entry of each row of a
@@ -103,9 +106,17 @@ mxs_status mxs_ctx_synchronize(mxs_ctx* ctx);
  * col[nnz] int32, val[nnz] FP64.  The arrays are validated on the GPU:
  * rowptr[0] == 0, rowptr non-decreasing, rowptr[nrows] == nnz,
  * 0 <= col < ncols, columns strictly ascending within each row (sorted, no
- * duplicates); any violation returns MXS_INVALID_MATRIX.  The matrix owns
- * device copies of the arrays (format MXS_CSR, dtype MXS_F64) and the
- * row-block partition its SpMV kernel uses.  Synchronises the ctx stream. */
+ * duplicates); any violation returns MXS_INVALID_MATRIX.  With
+ * MXS_SORT_AND_SUM in flags, rows whose columns are unordered or repeated
+ * are repaired on the GPU instead of rejected: each such row is ordered by
+ * column (a stable sort: equal columns keep their input order) and every
+ * run of equal columns becomes one entry whose value is the run's values
+ * added left to right in input order (a run summing to zero stays as an
+ * explicit zero); the matrix then has nnz' <= nnz entries
+ * (mxs_matrix_info).  Row pointers and the column range are checked either
+ * way.  The matrix owns device copies of the arrays (format MXS_CSR, dtype
+ * MXS_F64) and the row-block partition its SpMV kernel uses.  Synchronises
+ * the ctx stream. */
 mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
                                  const int32_t* rowptr, const int32_t* col,
                                  const double* val, int flags, mxs_matrix** out);
@@ -116,7 +127,8 @@ mxs_status mxs_matrix_create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int
  * rounded to nearest even; MXS_UNSUPPORTED beyond the FP32 range).  Other
  * formats are not offered for complex values.  mxs_spmv takes alpha, beta
  * as host (re, im) pairs of the compute type (double or float) and x, y as
- * device arrays of pairs. */
+ * device arrays of pairs.  MXS_SORT_AND_SUM sums the real and imaginary
+ * parts of repeated columns separately, each in input order. */
 mxs_status mxs_matrix_create_csr_complex(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
                                          const int32_t* rowptr, const int32_t* col,
                                          const double* val, int flags, mxs_matrix** out);
@@ -331,7 +343,8 @@ typedef struct {
  * ||r||/||b|| <= outer->rel_tol, else solve A_low d = r/||r|| by CG in FP32
  * (FP32 vectors and accumulation) to inner_rel_tol and update
  * x += ||r|| d in FP64.  A64: F64 CSR; A_low: F32 or F16_ROWSCALED CSR with
- * the same pattern.  last_step_variant != 0 loosens the inner tolerance to
+ * the same pattern (any other value type of either, complex ones included,
+ * returns MXS_UNSUPPORTED before any work is enqueued).  last_step_variant != 0 loosens the inner tolerance to
  * max(inner_rel_tol, 0.1*tol/relres) once relres*inner_rel_tol <= tol.
  * inner_precond (nullable, built from A64) turns the inner solve into
  * preconditioned CG with the FP32 copy of M.  Synchronises the ctx stream. */
@@ -352,7 +365,8 @@ mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A
  * transition matrix T[j,i] = 1/d_i as an F64 CSR matrix
  * (mxs_graph_transition; it may be converted to any format and passed as
  * `op`) and the set D of nodes without out-links.  flags: MXS_HOST_PTRS or
- * MXS_DEVICE_PTRS. */
+ * MXS_DEVICE_PTRS (repeated edges are rejected: MXS_SORT_AND_SUM is not
+ * accepted here). */
 typedef struct mxs_graph mxs_graph;
 
 typedef struct {

@@ -52,6 +52,8 @@ struct mxs_ctx {
   int num_cus = 256;
   // grow-only scratch for solvers and format conversion
   mxs::Workspace ws;
+  // grow-only scratch of the chunked products (continuation partials)
+  mxs::Workspace spmv_ws;
   // pinned host mirror of small device state blocks
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -87,15 +89,16 @@ struct CsrPart {
   bool merge = false;
   int32_t* crow = nullptr;
   int64_t nchunks = 0;
-  int32_t* cont_row = nullptr;  // per-chunk continuation partials (fix-up pass)
-  void* cont_val = nullptr;
   int32_t* empty_rows = nullptr;
   int64_t nempty = 0;
 };
 
 // COO: equal chunks of block_nnz entries, one wave per chunk.  Rows cut by
 // a chunk boundary are completed by a fix-up pass from per-chunk
-// continuation partials; rows with no entry are listed in empty_rows.
+// continuation partials; rows with no entry are listed in empty_rows.  The
+// partials live in scratch memory of the product's context (or of the
+// caller), never in the matrix, so a matrix is read-only during a product
+// and two contexts may use it at once.
 struct CooPart {
   int32_t* row = nullptr;
   int32_t* col = nullptr;
@@ -103,8 +106,6 @@ struct CooPart {
   int64_t nnz = 0;
   int64_t nchunks = 0;
   int block_nnz = 512;
-  int32_t* cont_row = nullptr;
-  void* cont_val = nullptr;
   int32_t* empty_rows = nullptr;
   int64_t nempty = 0;
   int wpb = 4;  // independent waves per work-group (1 or 4)
@@ -180,6 +181,15 @@ inline size_t value_bytes(mxs_dtype dt) {
 // returns at once (solvers queue iterations past convergence this way)
 mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, const void* x,
                        const void* beta, void* y, const int32_t* skip);
+// Device scratch one product of A needs (continuation partials of the
+// merge-path CSR and COO chunks; 0 for the other kernels), and the same
+// product with that scratch supplied by the caller (at least
+// spmv_scratch_bytes(A) bytes, 256-byte aligned, not in use by any other
+// product until this one completes on ctx->stream).
+size_t spmv_scratch_bytes(const mxs_matrix* A);
+mxs_status launch_spmv_scratch(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha,
+                               const void* x, const void* beta, void* y, const int32_t* skip,
+                               void* scratch);
 int64_t csr_partition(const int32_t* rowptr, int64_t n, int block_nnz,
                       std::vector<int32_t>& blocks, int64_t max_rows = -1);
 // Small systems (n <= 8192, rows of <= 64 entries): CG by the batched

@@ -54,7 +54,7 @@ int64_t csr_partition(const int32_t* rp, int64_t n, int C, std::vector<int32_t>&
 
 namespace {
 
-constexpr int kErrRowptr = 1, kErrCol = 2, kErrRange = 4, kErrNonfinite = 8;
+constexpr int kErrRowptr = 1, kErrCol = 2, kErrRange = 4, kErrNonfinite = 8, kErrOrder = 16;
 
 int grid_for(mxs_ctx* ctx, int64_t work, int bs) {
   int64_t g = (work + bs - 1) / bs;
@@ -77,19 +77,162 @@ __global__ void k_check_rowptr(int64_t n, int64_t nnz, const int32_t* __restrict
   }
 }
 
-// one thread per row; only launched once the row pointers passed
+// one thread per row; only launched once the row pointers passed.  A column
+// outside [0, ncols) sets kErrCol; a row whose columns do not ascend
+// strictly sets kErrOrder and, when `disorder` is given, its flag there.
 __global__ void k_check_cols(int64_t n, int64_t ncols, const int32_t* __restrict__ rp,
-                             const int32_t* __restrict__ col, int* __restrict__ err) {
+                             const int32_t* __restrict__ col, int* __restrict__ err,
+                             uint8_t* __restrict__ disorder) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     int64_t prev = -1;
+    bool unordered = false;
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
       const int64_t c = col[k];
-      if (c < 0 || c >= ncols || c <= prev) {
+      if (c < 0 || c >= ncols) {
         atomicOr(err, kErrCol);
         break;
       }
+      unordered |= c <= prev;
       prev = c;
+    }
+    if (unordered) atomicOr(err, kErrOrder);
+    if (disorder) disorder[i] = unordered ? 1 : 0;
+  }
+}
+
+// ---- ingest of unordered rows: sort by column, sum repeats -----------------
+// A row's entries are ordered by the 64-bit key (column << 32 | position in
+// the row): a total order, so the sort is stable by construction and equal
+// columns keep their input order.  Bitonic sort over the next power of two
+// (padding keys ~0 sort last); `nt` threads of one work-group, a barrier
+// after every compare-exchange step.
+__device__ void bitonic_sort(uint64_t* s, int64_t P2, int tid, int nt) {
+  for (int64_t k = 2; k <= P2; k <<= 1) {
+    for (int64_t j = k >> 1; j > 0; j >>= 1) {
+      for (int64_t t = tid; t < P2 / 2; t += nt) {
+        const int64_t lo = 2 * j * (t / j) + (t % j), hi = lo + j;
+        const bool up = (lo & k) == 0;
+        const uint64_t a = s[lo], b = s[hi];
+        if ((a > b) == up) {
+          s[lo] = b;
+          s[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// distinct columns among a row's L sorted keys, summed over the work-group
+__device__ int32_t count_heads(const uint64_t* s, int64_t L, int tid, int nt, int32_t* red) {
+  int32_t h = 0;
+  for (int64_t t = tid; t < L; t += nt) h += (t == 0 || (s[t] >> 32) != (s[t - 1] >> 32));
+  h = wave_sum(h);
+  if ((tid & 63) == 0) red[tid >> 6] = h;
+  __syncthreads();
+  int32_t tot = 0;
+  for (int w = 0; w < nt / 64; ++w) tot += red[w];
+  return tot;
+}
+
+constexpr int kSortLds = 2048;  // rows up to this length are sorted in LDS
+
+// one work-group of 256 threads per listed row (2 <= length <= kSortLds):
+// sort in LDS, write the sorted keys over the row's slots, count its columns
+__global__ __launch_bounds__(256) void k_sort_rows_lds(const int32_t* __restrict__ rows,
+                                                       const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       uint64_t* __restrict__ keys,
+                                                       int32_t* __restrict__ cnt) {
+  __shared__ uint64_t s[kSortLds];
+  __shared__ int32_t red[4];
+  const int32_t i = rows[blockIdx.x];
+  const int32_t b = rp[i];
+  const int64_t L = rp[i + 1] - b;
+  int64_t P2 = 1;
+  while (P2 < L) P2 <<= 1;
+  for (int64_t t = threadIdx.x; t < P2; t += 256)
+    s[t] = t < L ? ((uint64_t)(uint32_t)col[b + t] << 32) | (uint64_t)t : ~0ull;
+  __syncthreads();
+  bitonic_sort(s, P2, threadIdx.x, 256);
+  for (int64_t t = threadIdx.x; t < L; t += 256) keys[b + t] = s[t];
+  const int32_t h = count_heads(s, L, threadIdx.x, 256, red);
+  if (threadIdx.x == 0) cnt[i] = h;
+}
+
+// one longer row by one work-group of 1024 threads in global memory
+// (tmp holds P2 keys; a work-group's barrier orders its global accesses)
+__global__ __launch_bounds__(1024) void k_sort_row_global(int32_t i, const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          uint64_t* __restrict__ tmp, int64_t P2,
+                                                          uint64_t* __restrict__ keys,
+                                                          int32_t* __restrict__ cnt) {
+  __shared__ int32_t red[16];
+  const int32_t b = rp[i];
+  const int64_t L = rp[i + 1] - b;
+  for (int64_t t = threadIdx.x; t < P2; t += 1024)
+    tmp[t] = t < L ? ((uint64_t)(uint32_t)col[b + t] << 32) | (uint64_t)t : ~0ull;
+  __syncthreads();
+  bitonic_sort(tmp, P2, threadIdx.x, 1024);
+  for (int64_t t = threadIdx.x; t < L; t += 1024) keys[b + t] = tmp[t];
+  const int32_t h = count_heads(tmp, L, threadIdx.x, 1024, red);
+  if (threadIdx.x == 0) cnt[i] = h;
+}
+
+// New CSR arrays: one wave per row.  Rows in order are copied; a sorted row
+// keeps one entry per distinct column, whose value is the sum of that
+// column's values in input order (sorted keys of equal column hold
+// ascending input positions), added left to right by the lane that holds
+// the column's first key.  vpe = doubles per value (2: complex, parts
+// summed separately).
+__global__ __launch_bounds__(256) void k_compact_rows(int64_t n, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ nrp,
+                                                      const uint8_t* __restrict__ disorder,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val, int vpe,
+                                                      const uint64_t* __restrict__ keys,
+                                                      int32_t* __restrict__ ocol,
+                                                      double* __restrict__ oval) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += nw) {
+    const int64_t b = rp[i], L = rp[i + 1] - b, ob = nrp[i];
+    if (!disorder[i]) {
+      for (int64_t t = lane; t < L; t += 64) {
+        ocol[ob + t] = col[b + t];
+        for (int q = 0; q < vpe; ++q) oval[(ob + t) * vpe + q] = val[(b + t) * vpe + q];
+      }
+      continue;
+    }
+    int64_t base = 0;
+    for (int64_t t0 = 0; t0 < L; t0 += 64) {
+      const int64_t t = t0 + lane;
+      bool head = false;
+      uint64_t k = 0;
+      if (t < L) {
+        k = keys[b + t];
+        head = t == 0 || (keys[b + t - 1] >> 32) != (k >> 32);
+      }
+      const uint64_t mask = __ballot(head);
+      const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+      if (head) {
+        const int64_t pos = ob + base + __popcll(mask & below);
+        const uint32_t c = (uint32_t)(k >> 32);
+        double s0 = val[(b + (int64_t)(uint32_t)k) * vpe];
+        double s1 = vpe == 2 ? val[(b + (int64_t)(uint32_t)k) * vpe + 1] : 0.0;
+        for (int64_t u = t + 1; u < L; ++u) {
+          const uint64_t k2 = keys[b + u];
+          if ((uint32_t)(k2 >> 32) != c) break;
+          const int64_t src = (b + (int64_t)(uint32_t)k2) * vpe;
+          s0 = s0 + val[src];
+          if (vpe == 2) s1 = s1 + val[src + 1];
+        }
+        ocol[pos] = (int32_t)c;
+        oval[pos * vpe] = s0;
+        if (vpe == 2) oval[pos * vpe + 1] = s1;
+      }
+      base += __popcll(mask);
     }
   }
 }
@@ -328,10 +471,7 @@ mxs_status build_csr_merge(mxs_ctx* ctx, mxs_matrix* A, const mxs_convert_opts* 
   P.nempty = (int64_t)empty.size();
   P.crow = upload(ctx, A, crow);
   P.empty_rows = upload(ctx, A, empty);
-  P.cont_row = (int32_t*)mat_alloc(A, (size_t)(P.nchunks + 1) * sizeof(int32_t));
-  P.cont_val = mat_alloc(A, (size_t)(P.nchunks + 1) * sizeof(double));
-  if (!P.crow || !P.empty_rows || !P.cont_row || !P.cont_val)
-    return fail(ctx, MXS_OOM, "merge-path CSR set-up");
+  if (!P.crow || !P.empty_rows) return fail(ctx, MXS_OOM, "merge-path CSR set-up");
   // the host vectors are freed on return: the copies must finish first
   MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return MXS_OK;
@@ -450,11 +590,9 @@ mxs_status setup_coo_part(mxs_ctx* ctx, mxs_matrix* A, mxs::CooPart& P, int64_t 
   P.nnz = nnz;
   P.block_nnz = block_nnz;
   P.nchunks = (nnz + block_nnz - 1) / block_nnz;
-  P.cont_row = (int32_t*)mat_alloc(A, (size_t)(P.nchunks + 1) * sizeof(int32_t));
-  P.cont_val = mat_alloc(A, (size_t)(P.nchunks + 1) * sizeof(double));
   P.nempty = (int64_t)empty.size();
   P.empty_rows = upload(ctx, A, empty);
-  if (!P.cont_row || !P.cont_val || !P.empty_rows) return fail(ctx, MXS_OOM, "coo setup");
+  if (!P.empty_rows) return fail(ctx, MXS_OOM, "coo setup");
   MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return MXS_OK;
 }
@@ -625,6 +763,124 @@ mxs_status mxs_matrix_create_csr_complex(mxs_ctx* ctx, int64_t nrows, int64_t nc
 
 }  // extern "C"
 
+namespace mxs {
+namespace {
+
+void mat_release(mxs_matrix* A, void* p, size_t bytes) {
+  auto it = std::find(A->owned.begin(), A->owned.end(), p);
+  if (it != A->owned.end()) {
+    A->owned.erase(it);
+    A->bytes -= (int64_t)bytes;
+  }
+  A->alloc.release(p);
+}
+
+// Rows flagged in `disorder` (device, one byte per row) are ordered by
+// column and their repeated columns summed in input order; the matrix's
+// rowptr/col/val are replaced by the result (A->nnz updated).
+mxs_status sort_and_sum(mxs_ctx* ctx, mxs_matrix* A, const uint8_t* disorder, int vpe) {
+  const int64_t n = A->n, nnz = A->nnz;
+  std::vector<int32_t> rp((size_t)n + 1);
+  std::vector<uint8_t> dis((size_t)n);
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(rp.data(), A->csr.rowptr, (n + 1) * 4, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+  MXS_HIP_TRY(ctx, hipMemcpyAsync(dis.data(), disorder, n, hipMemcpyDeviceToHost, ctx->stream));
+  MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  std::vector<int32_t> shortrows, longrows;
+  int64_t maxp2 = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!dis[i]) continue;
+    const int64_t L = (int64_t)rp[i + 1] - rp[i];
+    if (L <= kSortLds) {
+      shortrows.push_back((int32_t)i);
+    } else {
+      longrows.push_back((int32_t)i);
+      int64_t p2 = 1;
+      while (p2 < L) p2 <<= 1;
+      maxp2 = std::max(maxp2, p2);
+    }
+  }
+  const Allocator& al = ctx->alloc;
+  uint64_t* keys = (uint64_t*)al.alloc((size_t)nnz * 8 + 8);
+  int32_t* cnt = (int32_t*)al.alloc((size_t)n * 4 + 4);
+  int32_t* d_short = (int32_t*)al.alloc(shortrows.size() * 4 + 4);
+  int32_t* nrp_d = (int32_t*)al.alloc((size_t)(n + 1) * 4);
+  uint64_t* tmp = maxp2 ? (uint64_t*)al.alloc((size_t)maxp2 * 8) : nullptr;
+  int32_t *ocol = nullptr;
+  double* oval = nullptr;
+  mxs_status st = MXS_OK;
+  std::vector<int32_t> hcnt((size_t)n), nrp((size_t)n + 1);
+  do {
+    if (!keys || !cnt || !d_short || !nrp_d || (maxp2 && !tmp)) {
+      st = fail(ctx, MXS_OOM, "sorting the rows: scratch for %lld entries", (long long)nnz);
+      break;
+    }
+    if (!shortrows.empty()) {
+      if (hipMemcpyAsync(d_short, shortrows.data(), shortrows.size() * 4, hipMemcpyHostToDevice,
+                         ctx->stream) != hipSuccess) {
+        st = fail(ctx, MXS_HIP, "copy failed");
+        break;
+      }
+      k_sort_rows_lds<<<(unsigned)shortrows.size(), 256, 0, ctx->stream>>>(
+          d_short, A->csr.rowptr, A->csr.col, keys, cnt);
+    }
+    for (int32_t i : longrows) {
+      int64_t p2 = 1;
+      while (p2 < (int64_t)rp[i + 1] - rp[i]) p2 <<= 1;
+      k_sort_row_global<<<1, 1024, 0, ctx->stream>>>(i, A->csr.rowptr, A->csr.col, tmp, p2, keys,
+                                                   cnt);
+    }
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(hcnt.data(), cnt, n * 4, hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "sorting the rows failed");
+      break;
+    }
+    nrp[0] = 0;
+    for (int64_t i = 0; i < n; ++i)
+      nrp[i + 1] = nrp[i] + (dis[i] ? hcnt[i] : rp[i + 1] - rp[i]);
+    const int64_t nn = nrp[n];
+    ocol = (int32_t*)mat_alloc(A, (size_t)nn * 4 + 4);
+    oval = (double*)mat_alloc(A, (size_t)nn * 8 * vpe + 16);
+    if (!ocol || !oval) {
+      st = fail(ctx, MXS_OOM, "summed CSR arrays (%lld entries)", (long long)nn);
+      break;
+    }
+    if (hipMemcpyAsync(nrp_d, nrp.data(), (n + 1) * 4, hipMemcpyHostToDevice, ctx->stream) !=
+        hipSuccess) {
+      st = fail(ctx, MXS_HIP, "copy failed");
+      break;
+    }
+    if (n > 0)
+      k_compact_rows<<<grid_for(ctx, (n + 3) / 4, 1), 256, 0, ctx->stream>>>(
+          n, A->csr.rowptr, nrp_d, disorder, A->csr.col, (const double*)A->csr.val, vpe, keys,
+          ocol, oval);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(A->csr.rowptr, nrp_d, (n + 1) * 4, hipMemcpyDeviceToDevice,
+                       ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "compacting the rows failed");
+      break;
+    }
+    mat_release(A, A->csr.col, (size_t)nnz * 4 + 4);
+    mat_release(A, A->csr.val, (size_t)nnz * 8 * vpe + 16);
+    A->csr.col = ocol;
+    A->csr.val = oval;
+    A->nnz = nn;
+  } while (0);
+  (void)hipStreamSynchronize(ctx->stream);
+  al.release(keys);
+  al.release(cnt);
+  al.release(d_short);
+  al.release(nrp_d);
+  al.release(tmp);
+  return st;
+}
+
+}  // namespace
+}  // namespace mxs
+
 // validated CSR from host or device arrays; val == NULL gives zero values
 mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t nnz,
                            const int32_t* rowptr, const int32_t* col, const double* val,
@@ -637,7 +893,9 @@ mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t n
     return fail(ctx, MXS_UNSUPPORTED, "sizes beyond int32 indices");
   if (!rowptr || (nnz > 0 && !col))
     return fail(ctx, MXS_INVALID_ARG, "NULL array");
-  if (flags != MXS_HOST_PTRS && flags != MXS_DEVICE_PTRS)
+  const bool sort_sum = (flags & MXS_SORT_AND_SUM) != 0;
+  const int where = flags & ~MXS_SORT_AND_SUM;
+  if (where != MXS_HOST_PTRS && where != MXS_DEVICE_PTRS)
     return fail(ctx, MXS_INVALID_ARG, "unknown flags %d", flags);
   MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
   mxs_matrix* A = new_matrix(ctx);
@@ -657,7 +915,7 @@ mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t n
       break;
     }
     const hipMemcpyKind kind =
-        flags == MXS_HOST_PTRS ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        where == MXS_HOST_PTRS ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     if (hipMemcpyAsync(A->csr.rowptr, rowptr, (nrows + 1) * 4, kind, ctx->stream) ||
         (nnz && hipMemcpyAsync(A->csr.col, col, nnz * 4, kind, ctx->stream)) ||
         (nnz && val && hipMemcpyAsync(A->csr.val, val, nnz * vb, kind, ctx->stream)) ||
@@ -680,15 +938,28 @@ mxs_status mxs::create_csr(mxs_ctx* ctx, int64_t nrows, int64_t ncols, int64_t n
       break;
     }
     if (nrows > 0) {
-      k_check_cols<<<grid_for(ctx, nrows, 256), 256, 0, ctx->stream>>>(nrows, ncols,
-                                                                       A->csr.rowptr,
-                                                                       A->csr.col, d_err);
-      if ((st = read_err(ctx, d_err, &err))) break;
-      if (err) {
-        st = fail(ctx, MXS_INVALID_MATRIX,
-                  "column indices must lie in [0, ncols) and ascend strictly in each row");
+      uint8_t* disorder = sort_sum ? (uint8_t*)ctx->alloc.alloc((size_t)nrows) : nullptr;
+      if (sort_sum && !disorder) {
+        st = fail(ctx, MXS_OOM, "row flags");
         break;
       }
+      k_check_cols<<<grid_for(ctx, nrows, 256), 256, 0, ctx->stream>>>(
+          nrows, ncols, A->csr.rowptr, A->csr.col, d_err, disorder);
+      if ((st = read_err(ctx, d_err, &err))) {
+        ctx->alloc.release(disorder);
+        break;
+      }
+      if (err & kErrCol) {
+        st = fail(ctx, MXS_INVALID_MATRIX, "column indices must lie in [0, ncols)");
+      } else if ((err & kErrOrder) && !sort_sum) {
+        st = fail(ctx, MXS_INVALID_MATRIX,
+                  "column indices must ascend strictly in each row (or pass MXS_SORT_AND_SUM)");
+      } else if (err & kErrOrder) {
+        st = sort_and_sum(ctx, A, disorder, dt == MXS_C128 ? 2 : 1);
+      }
+      (void)hipStreamSynchronize(ctx->stream);
+      ctx->alloc.release(disorder);
+      if (st) break;
     }
     A->h_rowptr.resize((size_t)nrows + 1);
     if (hipMemcpyAsync(A->h_rowptr.data(), A->csr.rowptr, (nrows + 1) * 4,

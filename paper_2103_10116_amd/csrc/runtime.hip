@@ -285,6 +285,7 @@ mxs_status mxs_ctx_destroy(mxs_ctx* ctx) {
   if (!ctx) return MXS_OK;
   (void)hipStreamSynchronize(ctx->stream);
   ctx->alloc.release(ctx->ws.ptr);
+  ctx->alloc.release(ctx->spmv_ws.ptr);
   ctx->alloc.release(ctx->flush);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;

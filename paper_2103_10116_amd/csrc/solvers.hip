@@ -2158,8 +2158,8 @@ mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A
                         double inner_rel_tol, int64_t inner_max, int32_t last_step_variant,
                         const mxs_precond* inner_precond, mxs_ir_info* info) {
   if (!ctx || !A64 || !A_low) return MXS_INVALID_ARG;
-  if (A64->dt != MXS_F64 || A_low->dt == MXS_F64)
-    return fail(ctx, MXS_UNSUPPORTED, "need an F64 matrix and an F32/F16 copy");
+  if (A64->dt != MXS_F64 || (A_low->dt != MXS_F32 && A_low->dt != MXS_F16_ROWSCALED))
+    return fail(ctx, MXS_UNSUPPORTED, "need an F64 matrix and an F32 or F16_ROWSCALED copy");
   if (A64->n != A64->ncols || A_low->n != A64->n || A_low->ncols != A64->ncols)
     return fail(ctx, MXS_INVALID_ARG, "matrix shapes differ or are not square");
   if (A64->n > 0 && (!b || !x)) return fail(ctx, MXS_INVALID_ARG, "NULL vector");
@@ -2177,6 +2177,8 @@ mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A
 mxs_status mxs_graph_create(mxs_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr,
                             const int32_t* col, int32_t flags, mxs_graph** out) {
   if (!ctx || !out) return MXS_INVALID_ARG;
+  if (flags != MXS_HOST_PTRS && flags != MXS_DEVICE_PTRS)
+    return fail(ctx, MXS_INVALID_ARG, "unknown flags %d", flags);
   MXS_HIP_TRY(ctx, hipSetDevice(ctx->device));
   mxs_graph* G = new (std::nothrow) mxs_graph();
   if (!G) return MXS_OOM;

@@ -1132,52 +1132,65 @@ void launch_csr_pr(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, 
     launch_csr_pr_w<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip);
 }
 
+// continuation partials of a chunked product: the row each chunk's first
+// run ends in (or -1) and that run's partial sum, one per chunk
+struct Cont {
+  int32_t* row;
+  void* val;
+};
+
+Cont cont_of(void* scratch, int64_t nchunks) {
+  const size_t rb = ((size_t)(nchunks + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
+  return Cont{(int32_t*)scratch, (char*)scratch + rb};
+}
+
 template <typename V, typename T, int NPL, int WPB, bool SCALED>
 void launch_csr_merge_w(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
-                        T beta, T* y, const int32_t* skip) {
+                        T beta, T* y, const int32_t* skip, Cont c) {
   const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
   k_csr_merge<V, T, NPL, WPB, SCALED><<<grid, 64 * WPB, 0, ctx->stream>>>(
       nnz, P.nchunks, P.rowptr, P.crow, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
-      P.cont_row, (T*)P.cont_val, skip);
+      c.row, (T*)c.val, skip);
 }
 
 template <typename V, typename T, int NPL, bool SCALED>
 void launch_csr_merge_n(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
-                        T beta, T* y, const int32_t* skip) {
+                        T beta, T* y, const int32_t* skip, Cont c) {
   if (P.wpb == 1)
-    launch_csr_merge_w<V, T, NPL, 1, SCALED>(ctx, P, nnz, alpha, x, beta, y, skip);
+    launch_csr_merge_w<V, T, NPL, 1, SCALED>(ctx, P, nnz, alpha, x, beta, y, skip, c);
   else
-    launch_csr_merge_w<V, T, NPL, 4, SCALED>(ctx, P, nnz, alpha, x, beta, y, skip);
+    launch_csr_merge_w<V, T, NPL, 4, SCALED>(ctx, P, nnz, alpha, x, beta, y, skip, c);
 }
 
 // merge-path CSR: empty rows, the chunks, then the fix-up of cut rows
 template <typename V, typename T, bool SCALED>
 void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
-                      const int32_t* skip) {
+                      const int32_t* skip, void* scratch) {
   const CsrPart& P = A->csr;
   if (P.nempty > 0)
     k_empty_rows<T><<<(unsigned)((P.nempty + 255) / 256), 256, 0, ctx->stream>>>(
         P.nempty, P.empty_rows, y, beta, skip);
   if (P.nchunks == 0) return;
+  const Cont c = cont_of(scratch, P.nchunks);
   switch (P.block_nnz) {
-    case 256: launch_csr_merge_n<V, T, 4, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip); break;
-    case 512: launch_csr_merge_n<V, T, 8, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip); break;
-    default: launch_csr_merge_n<V, T, 16, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip);
+    case 256: launch_csr_merge_n<V, T, 4, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip, c); break;
+    case 512: launch_csr_merge_n<V, T, 8, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip, c); break;
+    default: launch_csr_merge_n<V, T, 16, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip, c);
   }
   if (P.nchunks > 1)
     k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
-        P.nchunks, P.cont_row, (T*)P.cont_val, y, alpha, skip);
+        P.nchunks, c.row, (T*)c.val, y, alpha, skip);
 }
 
 template <typename V, typename T, bool SCALED>
 void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
-                const int32_t* skip) {
+                const int32_t* skip, void* scratch) {
   const CsrPart& P = A->csr;
   if (P.merge) {
     // set-up admits FP64, FP32 and row-scaled FP16 values
     if constexpr (std::is_same_v<V, double> || std::is_same_v<V, float> ||
                   std::is_same_v<V, _Float16>)
-      launch_csr_merge<V, T, SCALED>(ctx, A, alpha, x, beta, y, skip);
+      launch_csr_merge<V, T, SCALED>(ctx, A, alpha, x, beta, y, skip, scratch);
     return;
   }
   if (P.products) {
@@ -1226,55 +1239,56 @@ void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, 
 
 template <typename V, typename T, bool ACCUM, int WPB>
 void launch_coo_chunks(mxs_ctx* ctx, const CooPart& P, T alpha, const T* x, T beta, T* y,
-                       const int32_t* skip) {
+                       const int32_t* skip, Cont c) {
   const V* val = (const V*)P.val;
   const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
-  T* cv = (T*)P.cont_val;
+  T* cv = (T*)c.val;
   if (P.kernel == MXS_COO_RUNS) {
     switch (P.block_nnz) {
       case 256:
         k_coo_runs<V, T, 4, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
         break;
       case 1024:
         k_coo_runs<V, T, 16, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
         break;
       default:
         k_coo_runs<V, T, 8, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+            P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
     }
     return;
   }
   switch (P.block_nnz) {
     case 256:
       k_coo<V, T, 4, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
       break;
     case 1024:
       k_coo<V, T, 16, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
       break;
     default:
       k_coo<V, T, 8, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
-          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, P.cont_row, cv, skip);
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
   }
 }
 
 template <typename V, typename T, bool ACCUM>
 void launch_coo(mxs_ctx* ctx, const CooPart& P, int64_t n, T alpha, const T* x, T beta, T* y,
-                const int32_t* skip) {
+                const int32_t* skip, void* scratch) {
   if (!ACCUM && P.nempty > 0)
     k_empty_rows<T><<<(unsigned)((P.nempty + 255) / 256), 256, 0, ctx->stream>>>(
         P.nempty, P.empty_rows, y, beta, skip);
   if (P.nchunks == 0) return;
+  const Cont c = cont_of(scratch, P.nchunks);
   if (P.wpb == 4)
-    launch_coo_chunks<V, T, ACCUM, 4>(ctx, P, alpha, x, beta, y, skip);
+    launch_coo_chunks<V, T, ACCUM, 4>(ctx, P, alpha, x, beta, y, skip, c);
   else
-    launch_coo_chunks<V, T, ACCUM, 1>(ctx, P, alpha, x, beta, y, skip);
+    launch_coo_chunks<V, T, ACCUM, 1>(ctx, P, alpha, x, beta, y, skip, c);
   if (P.nchunks > 1)
     k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
-        P.nchunks, P.cont_row, (T*)P.cont_val, y, alpha, skip);
+        P.nchunks, c.row, (T*)c.val, y, alpha, skip);
 }
 
 template <typename V, typename T>
@@ -1303,23 +1317,23 @@ void launch_ell(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, 
 
 template <typename V, typename T, bool SCALED>
 void launch_typed(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
-                  const int32_t* skip) {
+                  const int32_t* skip, void* scratch) {
   switch (A->fmt) {
     case MXS_CSR:
-      launch_csr<V, T, SCALED>(ctx, A, alpha, x, beta, y, skip);
+      launch_csr<V, T, SCALED>(ctx, A, alpha, x, beta, y, skip, scratch);
       break;
     case MXS_COO:
-      launch_coo<V, T, false>(ctx, A->coo, A->n, alpha, x, beta, y, skip);
+      launch_coo<V, T, false>(ctx, A->coo, A->n, alpha, x, beta, y, skip, scratch);
       break;
     case MXS_ELL:
       launch_ell<V, T>(ctx, A, alpha, x, beta, y, skip);
       break;
     case MXS_HYB:
       if (A->ell.K == 0) {
-        launch_coo<V, T, false>(ctx, A->coo, A->n, alpha, x, beta, y, skip);
+        launch_coo<V, T, false>(ctx, A->coo, A->n, alpha, x, beta, y, skip, scratch);
       } else {
         launch_ell<V, T>(ctx, A, alpha, x, beta, y, skip);
-        launch_coo<V, T, true>(ctx, A->coo, A->n, alpha, x, beta, y, skip);
+        launch_coo<V, T, true>(ctx, A->coo, A->n, alpha, x, beta, y, skip, scratch);
       }
       break;
   }
@@ -1327,29 +1341,60 @@ void launch_typed(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta
 
 }  // namespace
 
-mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, const void* x,
-                       const void* beta, void* y, const int32_t* skip) {
+size_t spmv_scratch_bytes(const mxs_matrix* A) {
+  int64_t chunks = 0;
+  if (A->fmt == MXS_CSR && A->csr.merge) chunks = A->csr.nchunks;
+  if (A->fmt == MXS_COO || A->fmt == MXS_HYB) chunks = A->coo.nchunks;
+  if (chunks == 0) return 0;
+  // row indices (rounded to 256 bytes), then one partial of up to 8 bytes
+  const size_t rb = ((size_t)(chunks + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
+  return rb + (size_t)(chunks + 1) * sizeof(double);
+}
+
+mxs_status launch_spmv_scratch(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha,
+                               const void* x, const void* beta, void* y, const int32_t* skip,
+                               void* scratch) {
   if (A->n == 0) return MXS_OK;
   if (A->dt == MXS_F64) {
     launch_typed<double, double, false>(ctx, A, *(const double*)alpha, (const double*)x,
-                                        *(const double*)beta, (double*)y, skip);
+                                        *(const double*)beta, (double*)y, skip, scratch);
   } else if (A->dt == MXS_F32) {
     launch_typed<float, float, false>(ctx, A, *(const float*)alpha, (const float*)x,
-                                      *(const float*)beta, (float*)y, skip);
+                                      *(const float*)beta, (float*)y, skip, scratch);
   } else if (A->dt == MXS_C128) {
     using Z = cplx<double>;
     if (A->fmt != MXS_CSR) return fail(ctx, MXS_UNSUPPORTED, "complex values are CSR only");
-    launch_csr<Z, Z, false>(ctx, A, *(const Z*)alpha, (const Z*)x, *(const Z*)beta, (Z*)y, skip);
+    launch_csr<Z, Z, false>(ctx, A, *(const Z*)alpha, (const Z*)x, *(const Z*)beta, (Z*)y, skip,
+                            scratch);
   } else if (A->dt == MXS_C64) {
     using Z = cplx<float>;
     if (A->fmt != MXS_CSR) return fail(ctx, MXS_UNSUPPORTED, "complex values are CSR only");
-    launch_csr<Z, Z, false>(ctx, A, *(const Z*)alpha, (const Z*)x, *(const Z*)beta, (Z*)y, skip);
+    launch_csr<Z, Z, false>(ctx, A, *(const Z*)alpha, (const Z*)x, *(const Z*)beta, (Z*)y, skip,
+                            scratch);
   } else {
     launch_typed<_Float16, float, true>(ctx, A, *(const float*)alpha, (const float*)x,
-                                        *(const float*)beta, (float*)y, skip);
+                                        *(const float*)beta, (float*)y, skip, scratch);
   }
   MXS_HIP_TRY(ctx, hipGetLastError());
   return MXS_OK;
+}
+
+// The context's own scratch, grown (after the stream has drained) when a
+// product needs more than it holds.
+mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, const void* x,
+                       const void* beta, void* y, const int32_t* skip) {
+  const size_t need = spmv_scratch_bytes(A);
+  if (need > ctx->spmv_ws.bytes) {
+    if (ctx->spmv_ws.ptr) {
+      MXS_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      ctx->alloc.release(ctx->spmv_ws.ptr);
+    }
+    const size_t want = need + need / 4;
+    ctx->spmv_ws.ptr = ctx->alloc.alloc(want);
+    ctx->spmv_ws.bytes = ctx->spmv_ws.ptr ? want : 0;
+    if (!ctx->spmv_ws.ptr) return fail(ctx, MXS_OOM, "product scratch (%zu bytes)", want);
+  }
+  return launch_spmv_scratch(ctx, A, alpha, x, beta, y, skip, ctx->spmv_ws.ptr);
 }
 
 }  // namespace mxs

@@ -337,3 +337,25 @@ def powerlaw_graph(n: int, s: float = 1.79, kmax: int = 4096, seed: int = MATRIX
     power-law pattern of zipf_random read as in-links."""
     Z = zipf_random(n, s, kmax, seed)
     return CSRMatrix(Z.n, Z.ncols, Z.rowptr, Z.col, np.ones(Z.nnz))
+
+
+def unsorted_rows(n, ncols, max_len, seed, integer=True, dup_rate=0.4, empty_every=5):
+    """A row-grouped coordinate list (rowptr, col, val): each row's columns in
+    random order with repeats (about dup_rate of the entries repeat a column
+    of the row); integer values in [-8, 8] or uniform in [-1, 1]; every
+    empty_every-th row empty."""
+    g = rng(seed)
+    rows_c, rows_v, lens = [], [], []
+    for i in range(n):
+        L = 0 if (empty_every and i % empty_every == 0) else int(g.integers(1, max_len + 1))
+        base = g.choice(ncols, size=min(ncols, max(1, int(np.ceil(L * (1 - dup_rate))))),
+                        replace=False)
+        c = g.choice(base, size=L, replace=True) if L else np.zeros(0, np.int64)
+        v = (g.integers(-8, 9, L).astype(float) if integer else g.uniform(-1, 1, L))
+        rows_c.append(c)
+        rows_v.append(v)
+        lens.append(L)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    return (rp.astype(np.int32), np.concatenate(rows_c).astype(np.int32),
+            np.concatenate(rows_v))

@@ -37,7 +37,7 @@ FORMATS = {"csr": CSR, "coo": COO, "ell": ELL, "hyb": HYB}
 DTYPES = {"f64": F64, "f32": F32, "f16": F16_ROWSCALED, "c128": C128, "c64": C64}
 CG, BICGSTAB, GMRES, CGS, PIPECG = 0, 1, 2, 3, 4
 SOLVERS = {"cg": CG, "bicgstab": BICGSTAB, "gmres": GMRES, "cgs": CGS, "pipecg": PIPECG}
-HOST_PTRS, DEVICE_PTRS = 0, 1
+HOST_PTRS, DEVICE_PTRS, SORT_AND_SUM = 0, 1, 2
 
 (ARR_ROWPTR, ARR_COL, ARR_VAL, ARR_ROW, ARR_ELL_COL, ARR_ELL_VAL,
  ARR_COO_ROW, ARR_COO_COL, ARR_COO_VAL, ARR_SCALE) = range(10)
@@ -287,8 +287,10 @@ class Matrix:
         self.desc = d
 
     @classmethod
-    def from_csr(cls, ctx: Context, n, ncols, rowptr, col, val) -> "Matrix":
-        """mxs_matrix_create_csr from host numpy arrays or device torch tensors."""
+    def from_csr(cls, ctx: Context, n, ncols, rowptr, col, val,
+                 sort_and_sum=False) -> "Matrix":
+        """mxs_matrix_create_csr from host numpy arrays or device torch tensors
+        (sort_and_sum: MXS_SORT_AND_SUM, unordered and repeated columns allowed)."""
         import torch
         if isinstance(rowptr, torch.Tensor):
             flags = DEVICE_PTRS
@@ -304,6 +306,8 @@ class Matrix:
                     np.ascontiguousarray(val, np.float64)]
             ptrs = [a.ctypes.data_as(C.c_void_p) for a in keep]
             nnz = len(keep[1])
+        if sort_and_sum:
+            flags |= SORT_AND_SUM
         h = C.c_void_p()
         _check(_lib.mxs_matrix_create_csr(ctx.handle, int(n), int(ncols), nnz, *ptrs, flags,
                                           C.byref(h)), ctx)
@@ -315,7 +319,8 @@ class Matrix:
         return cls.from_csr(ctx, A.n, A.ncols, A.rowptr, A.col, A.val)
 
     @classmethod
-    def from_host_complex(cls, ctx: Context, n, ncols, rowptr, col, val) -> "Matrix":
+    def from_host_complex(cls, ctx: Context, n, ncols, rowptr, col, val,
+                          sort_and_sum=False) -> "Matrix":
         """mxs_matrix_create_csr_complex from host numpy arrays (val complex)."""
         rp = np.ascontiguousarray(rowptr, np.int32)
         ci = np.ascontiguousarray(col, np.int32)
@@ -323,7 +328,9 @@ class Matrix:
         h = C.c_void_p()
         _check(_lib.mxs_matrix_create_csr_complex(ctx.handle, int(n), int(ncols), len(ci),
                                                   rp.ctypes.data_as(_P), ci.ctypes.data_as(_P),
-                                                  v.ctypes.data_as(_P), HOST_PTRS, C.byref(h)),
+                                                  v.ctypes.data_as(_P),
+                                                  HOST_PTRS | (SORT_AND_SUM if sort_and_sum else 0),
+                                                  C.byref(h)),
                ctx)
         return cls(ctx, h)
 

@@ -275,6 +275,28 @@ def test_ir_random_spd(env, orc):
         assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
 
 
+def test_ir_refuses_other_value_types(env):
+    """The low-precision copy must hold FP32 or row-scaled FP16 values: an
+    FP64 or complex copy is refused before anything runs, and x is untouched."""
+    mxs, ctx, torch = env
+    A = I.poisson2d(16)
+    M = mxs.Matrix.from_host(ctx, A)
+    Z = mxs.Matrix.from_host_complex(ctx, A.n, A.ncols, A.rowptr, A.col,
+                                     A.val.astype(np.complex128))
+    Z64 = Z.convert("csr", "c64")
+    b = _dev(torch, np.ones(A.n))
+    x0 = np.linspace(-1.0, 1.0, A.n)
+    for bad in (M, Z, Z64):
+        x = _dev(torch, x0)
+        with pytest.raises(mxs.MxsError) as e:
+            mxs.solve_ir(ctx, M, bad, b, x, tol=1e-10)
+        assert e.value.status == mxs.UNSUPPORTED
+        assert np.array_equal(x.cpu().numpy(), x0)
+    with pytest.raises(mxs.MxsError) as e:            # complex "FP64" matrix
+        mxs.solve_ir(ctx, Z, M.convert("csr", "f32"), b, _dev(torch, x0), tol=1e-10)
+    assert e.value.status == mxs.UNSUPPORTED
+
+
 @pytest.mark.slow
 def test_full_size_krylov(env, orc):
     """The 128^3 solver workloads: CG on the 7-point Poisson matrix,

@@ -101,6 +101,93 @@ def test_create_from_device_pointers(env, orc):
     assert np.array_equal(M.export(mxs.ARR_VAL), A.val)
 
 
+def _sort_sum_cases():
+    g = load_golden("sort_and_sum_small.txt")
+    cases = {"golden": (g["n"][0], g["ncols"][0], np.array(g["rowptr"], np.int32),
+                        np.array(g["col"], np.int32), np.array(g["val"], float))}
+    rp, col, val = I.unsorted_rows(3000, 4000, 60, 41, integer=False)
+    cases["random_3000"] = (3000, 4000, rp, col, val)
+    # rows at and around the in-LDS limit (2048 entries), and one of 5000
+    # entries (sorted in global memory), with repeats; ragged row count
+    gg = I.rng(42)
+    lens = [0, 2048, 7, 2049, 1, 5000, 3, 64]
+    cols = [gg.integers(0, 1800, L) for L in lens]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    cases["long_rows"] = (len(lens), 1800, rp, np.concatenate(cols).astype(np.int32),
+                          gg.uniform(-1, 1, int(rp[-1])))
+    # every entry of a row repeats one column; rows already in order
+    cases["all_repeats"] = (3, 5, np.array([0, 6, 6, 9], np.int32),
+                            np.array([4, 4, 4, 4, 4, 4, 0, 1, 2], np.int32),
+                            gg.uniform(-1, 1, 9))
+    return cases
+
+
+SORT_SUM = _sort_sum_cases()
+
+
+@pytest.mark.parametrize("name", sorted(SORT_SUM))
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_create_sort_and_sum(env, orc, name, where):
+    """MXS_SORT_AND_SUM: the GPU's ordered, summed CSR equals the oracle's
+    bit for bit (row pointers, columns, values), from host or device arrays;
+    the product of the result agrees with the oracle's."""
+    mxs, ctx, torch = env
+    n, ncols, rp, col, val = SORT_SUM[name]
+    st, (orp, oc, ov) = orc.csr_sort_and_sum(n, ncols, rp, col, val)
+    assert st == orc.OK
+    if where == "host":
+        M = mxs.Matrix.from_csr(ctx, n, ncols, rp, col, val, sort_and_sum=True)
+    else:
+        M = mxs.Matrix.from_csr(ctx, n, ncols, _dev(torch, rp), _dev(torch, col),
+                                _dev(torch, val), sort_and_sum=True)
+    assert M.info()["nnz"] == len(oc)
+    assert np.array_equal(M.export(mxs.ARR_ROWPTR), orp)
+    assert np.array_equal(M.export(mxs.ARR_COL), oc)
+    assert np.array_equal(M.export(mxs.ARR_VAL).view(np.uint64), ov.view(np.uint64))
+    if name == "golden":
+        g = load_golden("sort_and_sum_small.txt")
+        assert np.array_equal(M.export(mxs.ARR_VAL), np.array(g["out_val"], float))
+    A = I.CSRMatrix(n, ncols, orp, oc, ov)
+    x = I.uniform_vector(ncols, 43)
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for fmt in FORMATS:
+        B = M if fmt == "csr" else M.convert(fmt, "f64")
+        mxs.spmv(ctx, B, _dev(torch, x), y)
+        _check(y.cpu().numpy(), orc.spmv_csr(A, x), orc.absrow(A, x), 1e-13)
+
+
+def test_create_sort_and_sum_complex_and_rules(env, orc):
+    """Complex values: parts summed separately in input order.  A valid CSR
+    passes unchanged; without the flag unordered rows are rejected; with it
+    a column out of range or bad row pointers still are."""
+    mxs, ctx, torch = env
+    rp, col, val = I.unsorted_rows(500, 300, 40, 44, integer=False)
+    zv = val + 1j * I.uniform_vector(len(val), 45)
+    st, (orp, oc, ov) = orc.csr_sort_and_sum(500, 300, rp, col, zv)
+    Z = mxs.Matrix.from_host_complex(ctx, 500, 300, rp, col, zv, sort_and_sum=True)
+    assert np.array_equal(Z.export(mxs.ARR_ROWPTR), orp)
+    assert np.array_equal(Z.export(mxs.ARR_COL), oc)
+    assert np.array_equal(Z.export(mxs.ARR_VAL).view(np.uint64),
+                          ov.view(np.float64).view(np.uint64))
+    A = ZOO["zipf_3000"]
+    M = mxs.Matrix.from_csr(ctx, A.n, A.ncols, A.rowptr, A.col, A.val, sort_and_sum=True)
+    assert np.array_equal(M.export(mxs.ARR_COL), A.col)
+    assert np.array_equal(M.export(mxs.ARR_VAL).view(np.uint64), A.val.view(np.uint64))
+    with pytest.raises(mxs.MxsError) as e:
+        mxs.Matrix.from_csr(ctx, 500, 300, rp, col, val)
+    assert e.value.status == mxs.INVALID_MATRIX
+    bad = col.copy()
+    bad[7] = 300
+    with pytest.raises(mxs.MxsError) as e:
+        mxs.Matrix.from_csr(ctx, 500, 300, rp, bad, val, sort_and_sum=True)
+    assert e.value.status == mxs.INVALID_MATRIX
+    rpb = rp.copy()
+    rpb[250] = rp[-1] + 5        # past nnz, and the row pointers decrease after it
+    with pytest.raises(mxs.MxsError) as e:
+        mxs.Matrix.from_csr(ctx, 500, 300, rpb, col, val, sort_and_sum=True)
+    assert e.value.status == mxs.INVALID_MATRIX
+
+
 # ---------------------------------------------------------------------------
 # conversions: bit-exact against the oracle's own conversions
 # ---------------------------------------------------------------------------
@@ -409,6 +496,40 @@ def test_spmv_deterministic(env):
             mxs.spmv(ctx, B, x, y)
             ys.append(y.cpu().numpy())
         assert all(np.array_equal(ys[0].view(np.uint64), t.view(np.uint64)) for t in ys[1:])
+
+
+def test_spmv_two_contexts_share_a_matrix(env, orc):
+    """A matrix is read-only during a product: the chunked kernels (COO, the
+    COO part of hybrid, merge-path CSR) keep their continuation partials in
+    each context's own scratch, so two contexts on two streams may run
+    products of the same matrix at the same time."""
+    mxs, ctx, torch = env
+    A = ZOO["zipf_3000"]
+    M = mxs.Matrix.from_host(ctx, A)
+    mats = {"csr_merge": M.convert("csr", "f64", csr_kernel="merge", block_nnz=256),
+            "coo": M.convert("coo", "f64", block_nnz=256),
+            "hyb": M.convert("hyb", "f64", block_nnz=256)}
+    assert mats["hyb"].info()["coo_nnz"] > 0
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    c1, c2 = mxs.Context(0, stream=s1), mxs.Context(0, stream=s2)
+    xs = [I.uniform_vector(A.n, 40 + k) for k in range(2)]
+    xd = [_dev(torch, x) for x in xs]
+    scale = [orc.absrow(A, x) for x in xs]
+    refs = [orc.spmv_csr(A, x) for x in xs]
+    reps = 12
+    for name, B in mats.items():
+        ys = [[torch.zeros(A.n, dtype=torch.float64, device="cuda") for _ in range(reps)]
+              for _ in range(2)]
+        torch.cuda.synchronize()
+        for r in range(reps):   # interleaved launches on the two streams
+            mxs.spmv(c1, B, xd[0], ys[0][r])
+            mxs.spmv(c2, B, xd[1], ys[1][r])
+        torch.cuda.synchronize()
+        for k in range(2):
+            for r in range(reps):
+                _check(ys[k][r].cpu().numpy(), refs[k], scale[k], 1e-13)
+    c1.close()
+    c2.close()
 
 
 @pytest.mark.slow

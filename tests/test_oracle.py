@@ -50,26 +50,6 @@ def test_validate_accepts_and_rejects(orc):
 # ---------------------------------------------------------------------------
 # conversions: hand-computed layouts and round trips
 # ---------------------------------------------------------------------------
-def unsorted_rows(n, ncols, max_len, seed, integer=True, dup_rate=0.4, empty_every=5):
-    """A row-grouped coordinate list: each row's columns in random order with
-    repeats (about dup_rate of the entries repeat a column of the row)."""
-    g = I.rng(seed)
-    rows_c, rows_v, lens = [], [], []
-    for i in range(n):
-        L = 0 if (empty_every and i % empty_every == 0) else int(g.integers(1, max_len + 1))
-        base = g.choice(ncols, size=min(ncols, max(1, int(np.ceil(L * (1 - dup_rate))))),
-                        replace=False)
-        c = g.choice(base, size=L, replace=True) if L else np.zeros(0, np.int64)
-        v = (g.integers(-8, 9, L).astype(float) if integer else g.uniform(-1, 1, L))
-        rows_c.append(c)
-        rows_v.append(v)
-        lens.append(L)
-    rp = np.zeros(n + 1, np.int64)
-    np.cumsum(lens, out=rp[1:])
-    return (rp.astype(np.int32), np.concatenate(rows_c).astype(np.int32),
-            np.concatenate(rows_v))
-
-
 def test_sort_and_sum_golden(orc):
     """Hand-worked example: order within a row, ties in input order (the
     1e16 + 1 - 1e16 and 0.1 + 0.2 + 0.3 rows fix the summation order),
@@ -88,7 +68,7 @@ def test_sort_and_sum_vs_dense_accumulation(orc, seed, max_len):
     so the result must equal a dense accumulation at exactly the (row, col)
     pairs the input lists, each row strictly ascending (a valid CSR)."""
     n, ncols = 60, 97
-    rp, col, val = unsorted_rows(n, ncols, max_len, seed)
+    rp, col, val = I.unsorted_rows(n, ncols, max_len, seed)
     st, (orp, oc, ov) = orc.csr_sort_and_sum(n, ncols, rp, col, val)
     assert st == orc.OK
     assert orc.validate(n, ncols, orp, oc) == orc.OK
@@ -116,7 +96,7 @@ def test_sort_and_sum_identity_and_rejects(orc):
     st, (rp, c, v) = orc.csr_sort_and_sum(A.n, A.ncols, A.rowptr, A.col, A.val)
     assert st == orc.OK and np.array_equal(rp, A.rowptr) and np.array_equal(c, A.col)
     assert np.array_equal(v.view(np.uint64), A.val.view(np.uint64))
-    rp, col, val = unsorted_rows(10, 8, 5, 4)
+    rp, col, val = I.unsorted_rows(10, 8, 5, 4)
     bad = col.copy()
     bad[3] = 8
     assert orc.csr_sort_and_sum(10, 8, rp, bad, val)[0] == orc.INVALID_MATRIX
