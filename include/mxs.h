@@ -240,6 +240,25 @@ mxs_status mxs_matrix_destroy(mxs_matrix* A);
 mxs_status mxs_spmv(mxs_ctx* ctx, const void* alpha, const mxs_matrix* A, const void* x,
                     const void* beta, void* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as mxs_spmv, same arguments, same kernels and the same result bit
+ * for bit, but it never allocates or frees memory.  The scratch that the
+ * chunked kernels need (merge-path CSR, COO and the COO part of hybrid keep
+ * one row index and one partial sum per chunk) comes from a fixed device
+ * array of MXS_NOALLOC_SCRATCH_BYTES (64 MiB) in each GPU's copy of the
+ * library, set up by mxs_ctx_create and held until the process ends.  A
+ * product needing more scratch than that returns MXS_UNSUPPORTED before
+ * anything is enqueued.  Every call on one GPU shares that GPU's array:
+ * calls whose work overlaps on one GPU (two streams, two contexts, two host
+ * threads) race and must be ordered by the caller; calls on one stream are
+ * ordered by it.  The array keeps the last call's contents; nothing in it
+ * needs to start at zero (every chunk writes its slot before it is read).
+ * Asynchronous. */
+#define MXS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mxs_status mxs_spmv_noalloc(mxs_ctx* ctx, const void* alpha, const mxs_matrix* A, const void* x,
+                            const void* beta, void* y);
+
 /* ---------------------------------------------------------------------- */
 /* Krylov solvers                                                          */
 /* ---------------------------------------------------------------------- */

@@ -187,6 +187,12 @@ mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, con
 // spmv_scratch_bytes(A) bytes, 256-byte aligned, not in use by any other
 // product until this one completes on ctx->stream).
 size_t spmv_scratch_bytes(const mxs_matrix* A);
+// The allocation-free product's fixed device scratch (one copy per GPU, held
+// until the process ends): its size, its per-device address lookup (run once
+// per device by mxs_ctx_create with that device current) and that address.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+mxs_status noalloc_scratch_init(mxs_ctx* ctx);
+void* noalloc_scratch(int device);
 mxs_status launch_spmv_scratch(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha,
                                const void* x, const void* beta, void* y, const int32_t* skip,
                                void* scratch);

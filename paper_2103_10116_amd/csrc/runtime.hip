@@ -277,6 +277,12 @@ mxs_status mxs_ctx_create(int device, void* hip_stream, const mxs_allocator* all
     delete ctx;
     return MXS_OOM;
   }
+  const mxs_status st = noalloc_scratch_init(ctx);
+  if (st) {
+    (void)hipHostFree(ctx->pinned);
+    delete ctx;
+    return st;
+  }
   *out = ctx;
   return MXS_OK;
 }

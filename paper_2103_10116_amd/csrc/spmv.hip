@@ -33,6 +33,8 @@
 // rows and ELL; the FP64 error stays far below 1e-13 * sum|a_ij||x_j|.
 #include <type_traits>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace mxs {
@@ -1379,6 +1381,40 @@ mxs_status launch_spmv_scratch(mxs_ctx* ctx, const mxs_matrix* A, const void* al
   return MXS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free product: a fixed array in each GPU's copy of
+// the code object.  Host code never passes the array's name to a kernel: the
+// name is only a host-side stand-in, so the device address of each GPU's
+// copy is looked up once (with that GPU current) and kept per device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+mxs_status noalloc_scratch_init(mxs_ctx* ctx) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return fail(ctx, MXS_UNSUPPORTED, "device %d beyond the scratch table", ctx->device);
+  if (g_scratch_ptr[ctx->device]) return MXS_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(ctx, MXS_HIP, "looking up the product scratch on device %d: %s", ctx->device,
+                hipGetErrorString(e));
+  }
+  g_scratch_ptr[ctx->device] = p;
+  return MXS_OK;
+}
+
+void* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+
 // The context's own scratch, grown (after the stream has drained) when a
 // product needs more than it holds.
 mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, const void* x,
@@ -1405,4 +1441,23 @@ extern "C" mxs_status mxs_spmv(mxs_ctx* ctx, const void* alpha, const mxs_matrix
   if (A->n > 0 && !y) return mxs::fail(ctx, MXS_INVALID_ARG, "y is NULL");
   if (A->nnz > 0 && !x) return mxs::fail(ctx, MXS_INVALID_ARG, "x is NULL");
   return mxs::launch_spmv(ctx, A, alpha, x, beta, y, nullptr);
+}
+
+extern "C" mxs_status mxs_spmv_noalloc(mxs_ctx* ctx, const void* alpha, const mxs_matrix* A,
+                                       const void* x, const void* beta, void* y) {
+  if (!ctx || !A || !alpha || !beta) return MXS_INVALID_ARG;
+  if (A->n > 0 && !y) return mxs::fail(ctx, MXS_INVALID_ARG, "y is NULL");
+  if (A->nnz > 0 && !x) return mxs::fail(ctx, MXS_INVALID_ARG, "x is NULL");
+  if (A->device != ctx->device)
+    return mxs::fail(ctx, MXS_INVALID_ARG, "matrix on device %d, ctx on device %d", A->device,
+                     ctx->device);
+  const size_t need = mxs::spmv_scratch_bytes(A);
+  if (need > mxs::kNoAllocScratchBytes)
+    return mxs::fail(ctx, MXS_UNSUPPORTED,
+                     "this product needs %zu bytes of scratch; the allocation-free product "
+                     "holds %zu",
+                     need, mxs::kNoAllocScratchBytes);
+  void* p = mxs::noalloc_scratch(ctx->device);
+  if (!p) return mxs::fail(ctx, MXS_HIP, "product scratch of device %d not set up", ctx->device);
+  return mxs::launch_spmv_scratch(ctx, A, alpha, x, beta, y, nullptr, p);
 }

@@ -131,6 +131,7 @@ _SIGS = {
     "mxs_matrix_create_csr_complex": (_S, [_P, _I64, _I64, _I64, _P, _P, _P, C.c_int,
                                            C.POINTER(_P)]),
     "mxs_spmv": (_S, [_P, _P, _P, _P, _P, _P]),
+    "mxs_spmv_noalloc": (_S, [_P, _P, _P, _P, _P, _P]),
     "mxs_solve": (_S, [_P, C.c_int, _P, _P, _P, C.POINTER(Stop), C.POINTER(SolverOpts),
                        C.POINTER(SolveInfo)]),
     "mxs_solve_ir": (_S, [_P, _P, _P, _P, _P, C.POINTER(Stop), C.c_double, _I64, _S, _P,
@@ -495,8 +496,10 @@ def _compute_dtype(A: Matrix):
             C64: torch.complex64}.get(A.dtype, torch.float32)
 
 
-def spmv(ctx: Context, A: Matrix, x, y, alpha=1.0, beta=0.0):
-    """mxs_spmv: y = alpha*A*x + beta*y (asynchronous on the ctx stream)."""
+def spmv(ctx: Context, A: Matrix, x, y, alpha=1.0, beta=0.0, noalloc=False):
+    """mxs_spmv: y = alpha*A*x + beta*y (asynchronous on the ctx stream);
+    noalloc=True calls mxs_spmv_noalloc (scratch from the library's fixed
+    per-GPU array, no allocation)."""
     if A.dtype in (C128, C64):
         ct = C.c_double if A.dtype == C128 else C.c_float
         a = (ct * 2)(complex(alpha).real, complex(alpha).imag)
@@ -505,8 +508,9 @@ def spmv(ctx: Context, A: Matrix, x, y, alpha=1.0, beta=0.0):
         ct = C.c_double if A.dtype == F64 else C.c_float
         a, b = ct(alpha), ct(beta)
     dt = _compute_dtype(A)
-    _check(_lib.mxs_spmv(ctx.handle, C.byref(a), A.handle, _vec(x, A.desc.ncols, dt),
-                         C.byref(b), _vec(y, A.n, dt)), ctx)
+    fn = _lib.mxs_spmv_noalloc if noalloc else _lib.mxs_spmv
+    _check(fn(ctx.handle, C.byref(a), A.handle, _vec(x, A.desc.ncols, dt),
+              C.byref(b), _vec(y, A.n, dt)), ctx)
 
 
 @dataclass
