@@ -143,6 +143,7 @@ typedef struct {
   int32_t rows_per_group; /* CSR vector kernel: 2, 4 or 8 rows per lane group; 0 = default */
   int32_t waves_per_group;/* CSR stream / COO: independent waves per work-group, 1 or 4 (0 = 4) */
   int32_t coo_kernel;     /* COO and the COO part of HYB: MXS_COO_AUTO, MXS_COO_LDS, MXS_COO_RUNS */
+  int32_t col_panels;     /* merge-path CSR: column panels (0 = auto, 1 = none, 2, 4 or 8; see below) */
 } mxs_convert_opts;
 
 #define MXS_CSR_AUTO 0   /* MERGE if a row exceeds 64 entries (real values whose chunks fit, else
@@ -156,7 +157,16 @@ typedef struct {
                               chunk's row pointers staged in LDS give the row of every entry; rows cut
                               by chunk edges completed by a fix-up pass.  FP64, FP32 and row-scaled
                               FP16 values, and no chunk may span more than block_nnz + 1 rows (long
-                              runs of empty rows): otherwise MXS_UNSUPPORTED */
+                              runs of empty rows): otherwise MXS_UNSUPPORTED.
+                              Column panels (col_panels = P > 1): the columns are cut into P equal
+                              slices and the matrix keeps, besides its CSR arrays, a copy of its
+                              entries ordered panel by panel (each row's entries of one slice form a
+                              row of that panel; empty ones are left out), so that each XCD's share
+                              of the chunks gathers x from one slice only, which stays in the XCD's
+                              L2.  Each panel writes per-row partial sums into the ctx's scratch and
+                              a last pass adds a row's partials in panel order.  Auto (0): panels
+                              when x is larger than 4 MiB, P the smallest power of two that cuts it
+                              into slices of at most 2 MiB (at most 8), none otherwise */
 
 #define MXS_COO_AUTO 0 /* RUNS for FP32/FP16 values when no row has more than 16 entries in
                           the part, else LDS */
@@ -201,6 +211,7 @@ typedef struct {
   int32_t csr_kernel;            /* CSR: the kernel in use (MXS_CSR_STREAM ... MXS_CSR_PRODUCTS) */
   int32_t coo_kernel;            /* COO / COO part of HYB: the kernel in use (MXS_COO_LDS or
                                     MXS_COO_RUNS); other formats 0 */
+  int32_t col_panels;            /* merge-path CSR: column panels in use (1 = none); others 0 */
 } mxs_matrix_desc;
 
 mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out);

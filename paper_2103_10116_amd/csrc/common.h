@@ -91,6 +91,18 @@ struct CsrPart {
   int64_t nchunks = 0;
   int32_t* empty_rows = nullptr;
   int64_t nempty = 0;
+  // merge path over column panels (panels > 1): the entries again, panel by
+  // panel; stacked row r (a row's entries in one panel, empty ones left out)
+  // holds entries srowptr[r] .. srowptr[r+1]-1 of scol/sval and belongs to
+  // panel srid[r] / n, row srid[r] % n; pmask[i] has bit p set when row i
+  // has entries in panel p.  crow/nchunks then describe the stacked rows.
+  int panels = 1;
+  int32_t* srowptr = nullptr;
+  int32_t* srid = nullptr;
+  int32_t* scol = nullptr;
+  void* sval = nullptr;
+  uint8_t* pmask = nullptr;
+  int64_t nsrows = 0;
 };
 
 // COO: equal chunks of block_nnz entries, one wave per chunk.  Rows cut by

@@ -368,6 +368,55 @@ __global__ void k_fill_hyb_coo(int64_t n, int64_t K, const int32_t* __restrict__
   }
 }
 
+// ---- column panels of the merge path ---------------------------------------
+// Entries of row i per column slice [p*W, (p+1)*W): a row's columns ascend,
+// so each slice boundary is found by binary search.
+__global__ void k_panel_counts(int64_t n, int P, int64_t W, const int32_t* __restrict__ rp,
+                               const int32_t* __restrict__ col, int32_t* __restrict__ cnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int32_t e = rp[i + 1];
+    int32_t prev = rp[i];
+    for (int p = 0; p < P; ++p) {
+      int32_t lo = prev, hi = e;
+      if (p < P - 1) {
+        const int64_t lim = (int64_t)(p + 1) * W;
+        while (lo < hi) {
+          const int32_t mid = lo + (hi - lo) / 2;
+          if ((int64_t)col[mid] < lim) lo = mid + 1;
+          else hi = mid;
+        }
+      } else {
+        lo = e;
+      }
+      cnt[(int64_t)p * n + i] = lo - prev;
+      prev = lo;
+    }
+  }
+}
+
+// Copies each row's entries of slice p to its stacked row (dst[p*n + i]);
+// E is the raw value word (8, 4 or 2 bytes), copied bit for bit.
+template <typename E>
+__global__ void k_panel_scatter(int64_t n, int P, const int32_t* __restrict__ rp,
+                                const int32_t* __restrict__ cnt, const int32_t* __restrict__ dst,
+                                const int32_t* __restrict__ col, const E* __restrict__ val,
+                                int32_t* __restrict__ scol, E* __restrict__ sval) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int32_t k = rp[i];
+    for (int p = 0; p < P; ++p) {
+      const int32_t c = cnt[(int64_t)p * n + i];
+      const int32_t d = dst[(int64_t)p * n + i];
+      for (int32_t t = 0; t < c; ++t) {
+        scol[d + t] = col[k + t];
+        sval[d + t] = val[k + t];
+      }
+      k += c;
+    }
+  }
+}
+
 // ---- helpers ---------------------------------------------------------------
 mxs_status read_err(mxs_ctx* ctx, int* d_err, int* out) {
   MXS_HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, d_err, sizeof(int), hipMemcpyDeviceToHost,
@@ -445,6 +494,114 @@ bool merge_rows(const std::vector<int32_t>& rp, int64_t nnz, int C, std::vector<
   return true;
 }
 
+// Column panels for the merge path: the caller's choice, else (auto) panels
+// when x (ncols values of the compute type) exceeds 4 MiB, P the smallest
+// power of two that cuts it into slices of at most 2 MiB.  Random gathers
+// from x run near the L2's request rate only while each XCD's slice of x
+// stays in its 4 MB L2 (gathers from an 8 MiB x: 107e9/s; 4 MiB: 196e9/s;
+// 2 MiB: 226e9/s).  Measured on the 2^20 power-law matrices (cold / warm):
+// FP64 s = 1.79 197 / 197 us without panels, 145 / 136 with 4; random SPD
+// 133 / 133 vs 138 / 107; FP32 (x of 4 MiB) gains nothing (s = 2.0 57 / 53
+// vs 63 / 55 with 2).  Stacked rows are indexed by p*n + i in int32.
+int merge_panels(const mxs_matrix* A, const mxs_convert_opts* opts) {
+  const int req = opts ? opts->col_panels : 0;
+  if (req == 1) return 1;
+  const int64_t xb = A->ncols * (A->dt == MXS_F64 ? 8 : 4);
+  int P = 1;
+  if (req > 1) {
+    P = req <= 2 ? 2 : req <= 4 ? 4 : 8;
+  } else if (xb > (int64_t(4) << 20)) {
+    while (P < 8 && (xb + P - 1) / P > (int64_t(2) << 20)) P <<= 1;
+  }
+  if (P > 1 && ((int64_t)P * A->n > INT32_MAX || A->ncols < P)) P = 1;
+  return P;
+}
+
+// Stacked rows of the column panels (see CsrPart) and their chunk table.
+mxs_status build_panels(mxs_ctx* ctx, mxs_matrix* A, int P, int C) {
+  CsrPart& S = A->csr;
+  const int64_t n = A->n, nnz = A->nnz;
+  const int64_t W = (A->ncols + P - 1) / P;
+  const size_t vb = value_bytes(A->dt);
+  std::vector<int32_t> cnt((size_t)P * n), dst((size_t)P * n, -1), srp, srid, crow;
+  std::vector<uint8_t> mask((size_t)n, 0);
+  int32_t* d_cnt = (int32_t*)ctx->alloc.alloc((size_t)P * n * 4 + 4);
+  int32_t* d_dst = (int32_t*)ctx->alloc.alloc((size_t)P * n * 4 + 4);
+  mxs_status st = MXS_OK;
+  do {
+    if (!d_cnt || !d_dst) {
+      st = fail(ctx, MXS_OOM, "column panels: counts");
+      break;
+    }
+    k_panel_counts<<<grid_for(ctx, n, 256), 256, 0, ctx->stream>>>(n, P, W, S.rowptr, S.col,
+                                                                     d_cnt);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(cnt.data(), d_cnt, (size_t)P * n * 4, hipMemcpyDeviceToHost,
+                       ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "column panels: counting failed");
+      break;
+    }
+    int64_t pos = 0;
+    for (int p = 0; p < P; ++p)
+      for (int64_t i = 0; i < n; ++i) {
+        const int32_t c = cnt[(size_t)p * n + i];
+        if (c == 0) continue;
+        srid.push_back((int32_t)((int64_t)p * n + i));
+        srp.push_back((int32_t)pos);
+        dst[(size_t)p * n + i] = (int32_t)pos;
+        mask[(size_t)i] |= (uint8_t)(1u << p);
+        pos += c;
+      }
+    srp.push_back((int32_t)pos);
+    int64_t bad = 0;
+    if (pos != nnz || !merge_rows(srp, nnz, C, crow, &bad)) {
+      st = fail(ctx, MXS_HIP, "column panels: inconsistent counts");
+      break;
+    }
+    S.srowptr = upload(ctx, A, srp);
+    S.srid = upload(ctx, A, srid);
+    S.pmask = upload(ctx, A, mask);
+    S.crow = upload(ctx, A, crow);
+    S.scol = (int32_t*)mat_alloc(A, (size_t)nnz * 4 + 4);
+    S.sval = mat_alloc(A, (size_t)nnz * vb + 16);
+    if (!S.srowptr || !S.srid || !S.pmask || !S.crow || !S.scol || !S.sval) {
+      st = fail(ctx, MXS_OOM, "column panels");
+      break;
+    }
+    if (hipMemcpyAsync(d_dst, dst.data(), (size_t)P * n * 4, hipMemcpyHostToDevice,
+                       ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "copy failed");
+      break;
+    }
+    const int g = grid_for(ctx, n, 256);
+    if (vb == 8)
+      k_panel_scatter<uint64_t><<<g, 256, 0, ctx->stream>>>(
+          n, P, S.rowptr, d_cnt, d_dst, S.col, (const uint64_t*)S.val, S.scol, (uint64_t*)S.sval);
+    else if (vb == 4)
+      k_panel_scatter<uint32_t><<<g, 256, 0, ctx->stream>>>(
+          n, P, S.rowptr, d_cnt, d_dst, S.col, (const uint32_t*)S.val, S.scol, (uint32_t*)S.sval);
+    else
+      k_panel_scatter<uint16_t><<<g, 256, 0, ctx->stream>>>(
+          n, P, S.rowptr, d_cnt, d_dst, S.col, (const uint16_t*)S.val, S.scol, (uint16_t*)S.sval);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "column panels: scatter failed");
+      break;
+    }
+    S.panels = P;
+    S.nsrows = (int64_t)srid.size();
+    S.merge = true;
+    S.block_nnz = C;
+    S.nchunks = (nnz + C - 1) / C;
+    S.nblocks = S.nchunks;
+    S.nempty = 0;  // the pass that adds the panels' partials writes every row
+  } while (0);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->alloc.release(d_cnt);
+  ctx->alloc.release(d_dst);
+  return st;
+}
+
 mxs_status build_csr_merge(mxs_ctx* ctx, mxs_matrix* A, const mxs_convert_opts* opts) {
   if (A->dt != MXS_F64 && A->dt != MXS_F32 && A->dt != MXS_F16_ROWSCALED)
     return fail(ctx, MXS_UNSUPPORTED,
@@ -452,6 +609,11 @@ mxs_status build_csr_merge(mxs_ctx* ctx, mxs_matrix* A, const mxs_convert_opts* 
   const std::vector<int32_t>& rp = A->h_rowptr;
   const int64_t n = A->n, nnz = A->nnz;
   const int C = merge_chunk(opts);
+  // one wave per work-group unless asked (power law, cold: FP32 s = 2.0
+  // 56.5 vs 58.0 us, s = 1.79 119.1 vs 119.5 us)
+  A->csr.wpb = (opts && opts->waves_per_group > 1) ? 4 : 1;
+  const int panels = merge_panels(A, opts);
+  if (panels > 1 && nnz > 0) return build_panels(ctx, A, panels, C);
   std::vector<int32_t> crow, empty;
   int64_t bad = 0;
   if (!merge_rows(rp, nnz, C, crow, &bad))
@@ -461,9 +623,6 @@ mxs_status build_csr_merge(mxs_ctx* ctx, mxs_matrix* A, const mxs_convert_opts* 
   CsrPart& P = A->csr;
   P.merge = true;
   P.block_nnz = C;
-  // one wave per work-group unless asked (power law, cold: FP32 s = 2.0
-  // 56.5 vs 58.0 us, s = 1.79 119.1 vs 119.5 us)
-  P.wpb = (opts && opts->waves_per_group > 1) ? 4 : 1;
   P.nchunks = (nnz + C - 1) / C;
   P.nblocks = P.nchunks;
   for (int64_t i = 0; i < n; ++i)
@@ -511,10 +670,12 @@ mxs_status build_csr_partition(mxs_ctx* ctx, mxs_matrix* A, int block_nnz,
     // when every chunk's rows fit its table (cold, 2^20 rows: s = 2.0 FP32
     // 56.5 vs 65.6 us for the row-block stream kernel, FP64 84.8 vs 90.8;
     // s = 1.79 FP32 119.1 vs 134.5, FP64 198.3 vs 201.5)
+    // (with column panels the stacked rows are never empty, so every chunk
+    // fits its table)
     std::vector<int32_t> crow;
     int64_t bad = 0;
     if (maxL > 64 && (A->dt == MXS_F64 || A->dt == MXS_F32 || A->dt == MXS_F16_ROWSCALED) &&
-        merge_rows(rp, A->nnz, merge_chunk(opts), crow, &bad))
+        (merge_panels(A, opts) > 1 || merge_rows(rp, A->nnz, merge_chunk(opts), crow, &bad)))
       kind_eff = MXS_CSR_MERGE;
   }
   if (kind_eff == MXS_CSR_MERGE) return build_csr_merge(ctx, A, opts);
@@ -1150,6 +1311,7 @@ mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
                     : A->csr.lanes >= 1 ? MXS_CSR_VECTOR
                                        : MXS_CSR_STREAM;
   out->coo_kernel = A->fmt == MXS_COO || (A->fmt == MXS_HYB && A->coo.nnz > 0) ? A->coo.kernel : 0;
+  out->col_panels = A->fmt == MXS_CSR && A->csr.merge ? A->csr.panels : 0;
   out->bytes = A->bytes;
   return MXS_OK;
 }

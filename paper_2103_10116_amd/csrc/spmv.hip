@@ -33,6 +33,7 @@
 // rows and ELL; the FP64 error stays far below 1e-13 * sum|a_ij||x_j|.
 #include <type_traits>
 
+#include <algorithm>
 #include <mutex>
 
 #include "common.h"
@@ -811,13 +812,19 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
 // cut by chunk edges are completed by k_coo_fix.  Against COO it reads no
 // row index per entry; against the row-block stream kernel every wave gets
 // the same number of entries whatever the row lengths.
-template <typename V, typename T, int NPL, int WPB, bool SCALED>
+//
+// PANEL: the matrix is the stack of column panels (rows are a row's entries
+// of one column slice; rid gives each stacked row's slot p*n + i): a row's
+// sum is stored as is (no alpha, beta, scale) to y[rid[row]], the panel
+// partials that k_panel_add joins.
+template <typename V, typename T, int NPL, int WPB, bool SCALED, bool PANEL>
 __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nchunks,
                                                        const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ crow,
                                                        const int32_t* __restrict__ col,
                                                        const V* __restrict__ val,
                                                        const float* __restrict__ scale,
+                                                       const int32_t* __restrict__ rid,
                                                        const T* __restrict__ x, T* __restrict__ y,
                                                        T alpha, T beta,
                                                        int32_t* __restrict__ cont_row,
@@ -892,6 +899,8 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nch
     if (first_continues && rr == first) {
       cont_row[ch] = rr;
       cont_val[ch] = sum;
+    } else if (PANEL) {
+      y[rid[rr]] = sum;
     } else {
       y[rr] = combine(alpha, sum, beta, y, rr);
     }
@@ -953,18 +962,46 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nch
 }
 
 // Adds the continuation partials of rows that straddle chunks, in chunk
-// order, to the value their first chunk wrote.
+// order, to the value their first chunk wrote (at y[rid[r]] when rid is
+// given: the stacked rows of column panels).
 template <typename T>
 __global__ void k_coo_fix(int64_t nchunks, const int32_t* __restrict__ cont_row,
                           const T* __restrict__ cont_val, T* __restrict__ y, T alpha,
-                          const int32_t* __restrict__ skip) {
+                          const int32_t* __restrict__ skip, const int32_t* __restrict__ rid) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nchunks || (skip && *skip)) return;
   const int32_t r = cont_row[c];
   if (r < 0 || (c > 0 && cont_row[c - 1] == r)) return;
   T sum = cont_val[c];
   for (int64_t d = c + 1; d < nchunks && cont_row[d] == r; ++d) sum += cont_val[d];
-  y[r] = y[r] + alpha * sum;
+  const int64_t i = rid ? rid[r] : r;
+  y[i] = y[i] + alpha * sum;
+}
+
+// Column panels: y_i = alpha * s_i * (sum of row i's panel partials, in
+// panel order) + beta * y_i, over every row (a row with no entries gets 0).
+template <typename T, bool SCALED>
+__global__ __launch_bounds__(256) void k_panel_add(int64_t n, int P,
+                                                   const uint8_t* __restrict__ mask,
+                                                   const T* __restrict__ part,
+                                                   const float* __restrict__ scale,
+                                                   T* __restrict__ y, T alpha, T beta,
+                                                   const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const unsigned m = mask[i];
+    T v[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (p < P) v[p] = (m >> p) & 1u ? part[(int64_t)p * n + i] : T(0);
+    T s = 0;
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (p < P) s += v[p];
+    if (SCALED) s *= (T)scale[i];
+    y[i] = combine(alpha, s, beta, y, i);
+  }
 }
 
 template <typename T>
@@ -1146,42 +1183,75 @@ Cont cont_of(void* scratch, int64_t nchunks) {
   return Cont{(int32_t*)scratch, (char*)scratch + rb};
 }
 
-template <typename V, typename T, int NPL, int WPB, bool SCALED>
+template <typename V, typename T, int NPL, int WPB, bool SCALED, bool PANEL>
 void launch_csr_merge_w(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
                         T beta, T* y, const int32_t* skip, Cont c) {
   const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
-  k_csr_merge<V, T, NPL, WPB, SCALED><<<grid, 64 * WPB, 0, ctx->stream>>>(
-      nnz, P.nchunks, P.rowptr, P.crow, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
-      c.row, (T*)c.val, skip);
+  if constexpr (PANEL)
+    k_csr_merge<V, T, NPL, WPB, false, true><<<grid, 64 * WPB, 0, ctx->stream>>>(
+        nnz, P.nchunks, P.srowptr, P.crow, P.scol, (const V*)P.sval, nullptr, P.srid, x, y,
+        T(1), T(0), c.row, (T*)c.val, skip);
+  else
+    k_csr_merge<V, T, NPL, WPB, SCALED, false><<<grid, 64 * WPB, 0, ctx->stream>>>(
+        nnz, P.nchunks, P.rowptr, P.crow, P.col, (const V*)P.val, P.scale, nullptr, x, y,
+        alpha, beta, c.row, (T*)c.val, skip);
 }
 
-template <typename V, typename T, int NPL, bool SCALED>
+template <typename V, typename T, int NPL, bool SCALED, bool PANEL>
 void launch_csr_merge_n(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
                         T beta, T* y, const int32_t* skip, Cont c) {
   if (P.wpb == 1)
-    launch_csr_merge_w<V, T, NPL, 1, SCALED>(ctx, P, nnz, alpha, x, beta, y, skip, c);
+    launch_csr_merge_w<V, T, NPL, 1, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c);
   else
-    launch_csr_merge_w<V, T, NPL, 4, SCALED>(ctx, P, nnz, alpha, x, beta, y, skip, c);
+    launch_csr_merge_w<V, T, NPL, 4, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c);
 }
 
-// merge-path CSR: empty rows, the chunks, then the fix-up of cut rows
+template <typename V, typename T, bool SCALED, bool PANEL>
+void launch_csr_merge_c(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
+                        T beta, T* y, const int32_t* skip, Cont c) {
+  switch (P.block_nnz) {
+    case 256: launch_csr_merge_n<V, T, 4, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c); break;
+    case 512: launch_csr_merge_n<V, T, 8, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c); break;
+    default: launch_csr_merge_n<V, T, 16, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c);
+  }
+}
+
+// bytes of the continuation partials of `nchunks` chunks (row indices
+// rounded to 256 bytes, then one partial of up to 8 bytes each, rounded)
+size_t cont_bytes(int64_t nchunks) {
+  const size_t rb = ((size_t)(nchunks + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
+  return rb + (((size_t)(nchunks + 1) * sizeof(double) + 255) & ~(size_t)255);
+}
+
+// merge-path CSR: empty rows, the chunks, then the fix-up of cut rows; with
+// column panels: the stacked chunks into the panel partials (scratch after
+// the continuation partials), their fix-up, then the pass that adds them
 template <typename V, typename T, bool SCALED>
 void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
                       const int32_t* skip, void* scratch) {
   const CsrPart& P = A->csr;
+  if (P.panels > 1) {
+    if (P.nchunks == 0) return;
+    const Cont c = cont_of(scratch, P.nchunks);
+    T* part = (T*)((char*)scratch + cont_bytes(P.nchunks));
+    launch_csr_merge_c<V, T, false, true>(ctx, P, A->nnz, alpha, x, beta, part, skip, c);
+    if (P.nchunks > 1)
+      k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
+          P.nchunks, c.row, (T*)c.val, part, T(1), skip, P.srid);
+    const unsigned g = (unsigned)std::min<int64_t>((A->n + 255) / 256, (int64_t)ctx->num_cus * 16);
+    k_panel_add<T, SCALED><<<g, 256, 0, ctx->stream>>>(A->n, P.panels, P.pmask, part, P.scale, y,
+                                                       alpha, beta, skip);
+    return;
+  }
   if (P.nempty > 0)
     k_empty_rows<T><<<(unsigned)((P.nempty + 255) / 256), 256, 0, ctx->stream>>>(
         P.nempty, P.empty_rows, y, beta, skip);
   if (P.nchunks == 0) return;
   const Cont c = cont_of(scratch, P.nchunks);
-  switch (P.block_nnz) {
-    case 256: launch_csr_merge_n<V, T, 4, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip, c); break;
-    case 512: launch_csr_merge_n<V, T, 8, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip, c); break;
-    default: launch_csr_merge_n<V, T, 16, SCALED>(ctx, P, A->nnz, alpha, x, beta, y, skip, c);
-  }
+  launch_csr_merge_c<V, T, SCALED, false>(ctx, P, A->nnz, alpha, x, beta, y, skip, c);
   if (P.nchunks > 1)
     k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
-        P.nchunks, c.row, (T*)c.val, y, alpha, skip);
+        P.nchunks, c.row, (T*)c.val, y, alpha, skip, nullptr);
 }
 
 template <typename V, typename T, bool SCALED>
@@ -1290,7 +1360,7 @@ void launch_coo(mxs_ctx* ctx, const CooPart& P, int64_t n, T alpha, const T* x, 
     launch_coo_chunks<V, T, ACCUM, 1>(ctx, P, alpha, x, beta, y, skip, c);
   if (P.nchunks > 1)
     k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
-        P.nchunks, c.row, (T*)c.val, y, alpha, skip);
+        P.nchunks, c.row, (T*)c.val, y, alpha, skip, nullptr);
 }
 
 template <typename V, typename T>
@@ -1348,9 +1418,11 @@ size_t spmv_scratch_bytes(const mxs_matrix* A) {
   if (A->fmt == MXS_CSR && A->csr.merge) chunks = A->csr.nchunks;
   if (A->fmt == MXS_COO || A->fmt == MXS_HYB) chunks = A->coo.nchunks;
   if (chunks == 0) return 0;
-  // row indices (rounded to 256 bytes), then one partial of up to 8 bytes
-  const size_t rb = ((size_t)(chunks + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
-  return rb + (size_t)(chunks + 1) * sizeof(double);
+  size_t b = cont_bytes(chunks);
+  // column panels: one partial of up to 8 bytes per row and panel
+  if (A->fmt == MXS_CSR && A->csr.merge && A->csr.panels > 1)
+    b += (size_t)A->csr.panels * (size_t)A->n * sizeof(double);
+  return b;
 }
 
 mxs_status launch_spmv_scratch(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha,

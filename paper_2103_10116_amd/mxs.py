@@ -51,7 +51,8 @@ class ConvertOpts(C.Structure):
     _fields_ = [("ell_width", C.c_int64), ("max_ell_bytes", C.c_int64),
                 ("block_nnz", C.c_int32), ("csr_kernel", C.c_int32),
                 ("lanes_per_row", C.c_int32), ("rows_per_group", C.c_int32),
-                ("waves_per_group", C.c_int32), ("coo_kernel", C.c_int32)]
+                ("waves_per_group", C.c_int32), ("coo_kernel", C.c_int32),
+                ("col_panels", C.c_int32)]
 
 
 CSR_AUTO, CSR_STREAM, CSR_VECTOR, CSR_ROWS_LDS, CSR_PRODUCTS = 0, 1, 2, 3, 4
@@ -69,7 +70,7 @@ class MatrixDesc(C.Structure):
                 ("bytes", C.c_int64), ("block_nnz", C.c_int32),
                 ("lanes_per_row", C.c_int32), ("rows_per_group", C.c_int32),
                 ("waves_per_group", C.c_int32), ("csr_kernel", C.c_int32),
-                ("coo_kernel", C.c_int32)]
+                ("coo_kernel", C.c_int32), ("col_panels", C.c_int32)]
 
 
 class Stop(C.Structure):
@@ -337,11 +338,12 @@ class Matrix:
 
     def convert(self, fmt="csr", dtype="f64", ell_width=0, max_ell_bytes=0,
                 block_nnz=0, csr_kernel="auto", lanes_per_row=0,
-                rows_per_group=0, waves_per_group=0, coo_kernel="auto") -> "Matrix":
+                rows_per_group=0, waves_per_group=0, coo_kernel="auto",
+                col_panels=0) -> "Matrix":
         o = ConvertOpts(int(ell_width), int(max_ell_bytes), int(block_nnz),
                         CSR_KERNELS.get(csr_kernel, csr_kernel), int(lanes_per_row),
                         int(rows_per_group), int(waves_per_group),
-                        COO_KERNELS.get(coo_kernel, coo_kernel))
+                        COO_KERNELS.get(coo_kernel, coo_kernel), int(col_panels))
         h = C.c_void_p()
         _check(_lib.mxs_matrix_convert(self.ctx.handle, self.handle, FORMATS.get(fmt, fmt),
                                        DTYPES.get(dtype, dtype), C.byref(o), C.byref(h)),

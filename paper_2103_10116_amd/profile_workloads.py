@@ -14,6 +14,8 @@ cached beyond L2 residue):
              128^3 CSR FP64 (warm: the 27-point matrix is larger than the cache)
   cold7      the 7-point Poisson and convection-diffusion 128^3 CSR FP64,
              cold and then warm (the cache's share of in-solver products)
+  panels     the s = 1.79 power-law matrix, merge-path CSR FP64 and FP32 with
+             1, 2 and 4 column panels, cold
 
 Prints one line per product with the mean event-timed duration, so a counter
 run's per-dispatch figures can be matched to launches.
@@ -58,10 +60,10 @@ def main():
     ctx = mxs.Context(0)
     flush = lambda: mxs.flush_cache(ctx, 1 << 30)  # noqa: E731
 
-    def run(label, M, variants, cold):
+    def run(label, M, variants, cold, **opts):
         x64 = torch.from_numpy(I.uniform_vector(M.n, I.VECTOR_SEED)).to(dev)
         for fmt, dt in variants:
-            B = M if (fmt, dt) == ("csr", "f64") else M.convert(fmt, dt)
+            B = M if (fmt, dt) == ("csr", "f64") and not opts else M.convert(fmt, dt, **opts)
             x = x64 if dt == "f64" else x64.float()
             y = torch.zeros_like(x)
             fn = lambda B=B, x=x, y=y: mxs.spmv(ctx, B, x, y)  # noqa: E731
@@ -69,7 +71,8 @@ def main():
             torch.cuda.synchronize()
             us = _time(torch, fn, args.reps, flush if cold else None)
             print(f"{label} {fmt} {dt} {'cold' if cold else 'warm'}: {us:.1f} us "
-                  f"(csr_kernel {B.info()['csr_kernel']})", flush=True)
+                  f"(csr_kernel {B.info()['csr_kernel']}, panels {B.info()['col_panels']})",
+                  flush=True)
             if B is not M:
                 B.close()
 
@@ -97,6 +100,12 @@ def main():
                 run(label, P, [("csr", "f64")], True)
                 run(label, P, [("csr", "f64")], False)
                 P.close()
+        elif w == "panels":
+            Z = mxs.Matrix.from_host(ctx, I.zipf_random(2 ** 20, 1.79, 4096))
+            for p in (1, 2, 4):
+                run(f"powerlaw_s1.79_panels{p}", Z, [("csr", "f64"), ("csr", "f32")], True,
+                    csr_kernel="merge", col_panels=p)
+            Z.close()
         else:
             raise SystemExit(f"unknown workload {w!r}")
     ctx.close()

@@ -303,7 +303,9 @@ CSR_VARIANTS = [dict(csr_kernel="stream", block_nnz=b, waves_per_group=w)
     dict(csr_kernel="products", block_nnz=b, waves_per_group=w)
     for b in (0, 512, 1024, 2048) for w in (0, 1, 2, 4)] + [
     dict(csr_kernel="merge", block_nnz=b, waves_per_group=w)
-    for b in (0, 256, 512, 1024) for w in (1, 4)]
+    for b in (0, 256, 512, 1024) for w in (1, 4)] + [
+    dict(csr_kernel="merge", block_nnz=b, waves_per_group=w, col_panels=p)
+    for b in (256, 1024) for w in (1, 4) for p in (2, 4, 8)]
 
 
 @pytest.mark.parametrize("name", sorted(ZOO))
@@ -340,6 +342,8 @@ def test_spmv_csr_kernels(env, orc, name, dt):
         assert d["csr_kernel"] == mxs.CSR_KERNELS[opts["csr_kernel"]]
         if opts["csr_kernel"] in ("rows_lds", "products", "merge") and opts["block_nnz"]:
             assert d["block_nnz"] == opts["block_nnz"]
+        if "col_panels" in opts and A.nnz and A.ncols >= opts["col_panels"]:
+            assert d["col_panels"] == opts["col_panels"]
         y = torch.from_numpy(y0r).to(tdt).cuda()
         mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
         _check(y.cpu().numpy().astype(np.float64), ref, scale, tol)
@@ -554,12 +558,15 @@ def test_spmv_full_size(env, orc, which):
     scale32 = orc.absrow(A32, x32.astype(np.float64))
     M = mxs.Matrix.from_host(ctx, A)
     # COO in both kernels (AUTO picks one of them)
-    cases = [("csr", {}), ("csr", {"csr_kernel": "merge"}), ("coo", {"coo_kernel": "lds"}),
+    cases = [("csr", {}), ("csr", {"csr_kernel": "merge", "col_panels": 1}),
+             ("csr", {"csr_kernel": "merge", "col_panels": 8}), ("coo", {"coo_kernel": "lds"}),
              ("coo", {"coo_kernel": "runs"}), ("ell", {}), ("hyb", {})]
     for fmt, opts in cases:
         if fmt == "ell" and which == "zipf_2p20_m16":
             continue  # the same 4096-wide padded layout as zipf_2p20 (51.5 GB in FP64)
         B = M.convert(fmt, "f64", **opts)
+        if fmt == "csr" and not opts and which != "stencil27_128":
+            assert B.info()["col_panels"] == 4   # x of 8 MiB: slices of 2 MiB
         y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         mxs.spmv(ctx, B, _dev(torch, x), y)
         _check(y.cpu().numpy(), ref, scale, 1e-13)
