@@ -60,6 +60,9 @@ struct mxs_ctx {
   // cache-flush buffer
   void* flush = nullptr;
   size_t flush_bytes = 0;
+  // solver status polling: two copies of the device state in flight, each
+  // marked by an event (created with the ctx)
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
 };
 
 namespace mxs {
@@ -199,6 +202,13 @@ mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, con
 // spmv_scratch_bytes(A) bytes, 256-byte aligned, not in use by any other
 // product until this one completes on ctx->stream).
 size_t spmv_scratch_bytes(const mxs_matrix* A);
+// y = A x (square A) and, in the same launches, work-group partial sums of
+// x[i] * y[i] in dpart (CG's p.q with x = p): returns how many partials
+// (<= kDotPartials) were written, or 0 when A's kernel has no such form
+// (then nothing was enqueued and the caller forms p.q itself).
+constexpr int kDotPartials = 4096;
+int launch_spmv_dot(mxs_ctx* ctx, const mxs_matrix* A, const void* x, void* y,
+                    const int32_t* skip, double* dpart);
 // The allocation-free product's fixed device scratch (one copy per GPU, held
 // until the process ends): its size, its per-device address lookup (run once
 // per device by mxs_ctx_create with that device current) and that address.
@@ -208,6 +218,9 @@ void* noalloc_scratch(int device);
 mxs_status launch_spmv_scratch(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha,
                                const void* x, const void* beta, void* y, const int32_t* skip,
                                void* scratch);
+// After the values of a CSR matrix changed in place: copies them into the
+// column-panel copy of the merge path (no-op for other kernels).  Enqueued.
+mxs_status refresh_panel_values(mxs_ctx* ctx, mxs_matrix* A);
 int64_t csr_partition(const int32_t* rowptr, int64_t n, int block_nnz,
                       std::vector<int32_t>& blocks, int64_t max_rows = -1);
 // Small systems (n <= 8192, rows of <= 64 entries): CG by the batched

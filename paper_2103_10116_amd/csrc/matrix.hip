@@ -417,6 +417,29 @@ __global__ void k_panel_scatter(int64_t n, int P, const int32_t* __restrict__ rp
   }
 }
 
+// Copies the current values into the panel copy again, one thread per
+// stacked row r (row i = srid[r] % n of panel p = srid[r] / n): the slice's
+// first entry in row i is found by binary search, as at set-up.
+template <typename E>
+__global__ void k_panel_refresh(int64_t m, int64_t n, int64_t W,
+                                const int32_t* __restrict__ srowptr,
+                                const int32_t* __restrict__ srid, const int32_t* __restrict__ rp,
+                                const int32_t* __restrict__ col, const E* __restrict__ val,
+                                E* __restrict__ sval) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += stride) {
+    const int64_t f = srid[r], p = f / n, i = f - p * n;
+    int32_t lo = rp[i], hi = rp[i + 1];
+    const int64_t lim = p * W;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo) / 2;
+      if ((int64_t)col[mid] < lim) lo = mid + 1;
+      else hi = mid;
+    }
+    for (int32_t d = srowptr[r], e = srowptr[r + 1]; d < e; ++d, ++lo) sval[d] = val[lo];
+  }
+}
+
 // ---- helpers ---------------------------------------------------------------
 mxs_status read_err(mxs_ctx* ctx, int* d_err, int* out) {
   MXS_HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, d_err, sizeof(int), hipMemcpyDeviceToHost,
@@ -601,6 +624,35 @@ mxs_status build_panels(mxs_ctx* ctx, mxs_matrix* A, int P, int C) {
   ctx->alloc.release(d_dst);
   return st;
 }
+
+}  // namespace
+
+mxs_status refresh_panel_values(mxs_ctx* ctx, mxs_matrix* A) {
+  const CsrPart& S = A->csr;
+  if (A->fmt != MXS_CSR || !S.merge || S.panels <= 1 || S.nsrows == 0) return MXS_OK;
+  const int64_t W = (A->ncols + S.panels - 1) / S.panels;
+  const int g = grid_for(ctx, S.nsrows, 256);
+  const size_t vb = value_bytes(A->dt);
+  if (vb == 8)
+    k_panel_refresh<uint64_t><<<g, 256, 0, ctx->stream>>>(S.nsrows, A->n, W, S.srowptr, S.srid,
+                                                          S.rowptr, S.col,
+                                                          (const uint64_t*)S.val,
+                                                          (uint64_t*)S.sval);
+  else if (vb == 4)
+    k_panel_refresh<uint32_t><<<g, 256, 0, ctx->stream>>>(S.nsrows, A->n, W, S.srowptr, S.srid,
+                                                          S.rowptr, S.col,
+                                                          (const uint32_t*)S.val,
+                                                          (uint32_t*)S.sval);
+  else
+    k_panel_refresh<uint16_t><<<g, 256, 0, ctx->stream>>>(S.nsrows, A->n, W, S.srowptr, S.srid,
+                                                          S.rowptr, S.col,
+                                                          (const uint16_t*)S.val,
+                                                          (uint16_t*)S.sval);
+  MXS_HIP_TRY(ctx, hipGetLastError());
+  return MXS_OK;
+}
+
+namespace {
 
 mxs_status build_csr_merge(mxs_ctx* ctx, mxs_matrix* A, const mxs_convert_opts* opts) {
   if (A->dt != MXS_F64 && A->dt != MXS_F32 && A->dt != MXS_F16_ROWSCALED)

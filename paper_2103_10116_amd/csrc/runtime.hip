@@ -277,8 +277,13 @@ mxs_status mxs_ctx_create(int device, void* hip_stream, const mxs_allocator* all
     delete ctx;
     return MXS_OOM;
   }
-  const mxs_status st = noalloc_scratch_init(ctx);
+  mxs_status st = noalloc_scratch_init(ctx);
+  for (int i = 0; i < 2 && !st; ++i)
+    if (hipEventCreateWithFlags(&ctx->poll_ev[i], hipEventDisableTiming) != hipSuccess)
+      st = fail(ctx, MXS_HIP, "event creation failed");
   if (st) {
+    for (hipEvent_t e : ctx->poll_ev)
+      if (e) (void)hipEventDestroy(e);
     (void)hipHostFree(ctx->pinned);
     delete ctx;
     return st;
@@ -293,6 +298,8 @@ mxs_status mxs_ctx_destroy(mxs_ctx* ctx) {
   ctx->alloc.release(ctx->ws.ptr);
   ctx->alloc.release(ctx->spmv_ws.ptr);
   ctx->alloc.release(ctx->flush);
+  for (hipEvent_t e : ctx->poll_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return MXS_OK;

@@ -62,6 +62,11 @@ struct KState {
   // that starts a recurrence (beta = 0, gamma and delta from dot[])
   double pg[2], palpha[2];
   int64_t restart_at;
+  // CG: 0, or the iteration the x update stops at plus one (the update of
+  // iteration k runs while k < halt - 1); set with the terminal status by
+  // the kernel that decides it, so that the other blocks of that same
+  // launch, which may already see `done`, still finish their x update
+  int64_t halt;
 };
 
 int red_grid(int64_t n) {
@@ -112,6 +117,34 @@ __device__ __forceinline__ void finish(const double* __restrict__ part, int g, d
   const bool has = (int)threadIdx.x < g;
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = has ? part[(int64_t)threadIdx.x * NV + v] : 0.0;
+  const double s = block_sum_multi<NV>(acc, lds);
+  if ((int)threadIdx.x < NV) res[threadIdx.x] = s;
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = res[v];
+}
+
+// The same for up to 8 * RB partials (the product-with-dot kernels write one
+// per work-group): thread t adds partials t, t + RB, ... in that order.
+template <int NV>
+__device__ __forceinline__ void finish_wide(const double* __restrict__ part, int g,
+                                            double (&out)[NV]) {
+  __shared__ double lds[RB / 64][NV];
+  __shared__ double res[NV];
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double t[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int b = (int)threadIdx.x + j * RB;
+      t[j] = b < g ? part[(int64_t)b * NV + v] : 0.0;
+    }
+    double a = t[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) a += t[j];
+    acc[v] = a;
+  }
   const double s = block_sum_multi<NV>(acc, lds);
   if ((int)threadIdx.x < NV) res[threadIdx.x] = s;
   __syncthreads();
@@ -266,13 +299,9 @@ __global__ __launch_bounds__(RB) void k_dots_fin(const double* part, int g, KSta
 }
 
 // ---------------------------------------------------------------------------
-// CG (Hestenes-Stiefel).  Iteration k (parity par = k & 1):
-//   q = A p;  k_cg_pq: partials of p.q;
-//   k_cg_update: alpha = rho[par] / (p.q), x += alpha p, r -= alpha q,
-//                partials of r.r;
-//   k_cg_direction: rho' = r.r, stopping test, beta = rho'/rho[par],
-//                p = r + beta p, rho[1-par] = rho'.
+// CG (Hestenes-Stiefel)
 // ---------------------------------------------------------------------------
+// partials of p.q, for products that do not form them themselves
 template <typename T>
 __global__ __launch_bounds__(RB) void k_cg_pq(int64_t n, const T* __restrict__ p,
                                               const T* __restrict__ q, double* __restrict__ pa,
@@ -285,17 +314,31 @@ __global__ __launch_bounds__(RB) void k_cg_pq(int64_t n, const T* __restrict__ p
   block_partials<1>(acc, pa);
 }
 
+// CG in three launches, B_csr + 64n bytes per iteration in FP64.  Iteration k
+// (parity par):
+//   q = A p with the product's own partials of p.q (launch_spmv_dot), or the
+//   product and k_cg_pq when A's kernel has no such form;
+//   k_cg_r: alpha = rho[par] / (p.q), r -= alpha q, partials of r.r (reads
+//   r, q; writes r);
+//   k_cg_xp: rho' = r.r, stopping test, x += alpha p, beta = rho'/rho[par],
+//   p = r + beta p (reads x, r, p; writes x, p).
+// The x update rides with the direction update, so it must run in every
+// block even when the same launch decides that CG has converged: its blocks
+// skip by `halt`, not by `done` (see KState).
 template <typename T>
-__global__ __launch_bounds__(RB) void k_cg_update(int64_t n, T* __restrict__ x,
-                                                  const T* __restrict__ p, T* __restrict__ r,
-                                                  const T* __restrict__ q,
-                                                  const double* __restrict__ pa, int g,
-                                                  double* __restrict__ pb, KState* st, int par) {
+__global__ __launch_bounds__(RB) void k_cg_r(int64_t n, T* __restrict__ r,
+                                             const T* __restrict__ q,
+                                             const double* __restrict__ pa, int ga,
+                                             double* __restrict__ pb, KState* st, int par,
+                                             int64_t k) {
   if (st->done) return;
   double pq[1];
-  finish<1>(pa, g, pq);
+  finish_wide<1>(pa, ga, pq);
   if (!isfinite(pq[0]) || pq[0] <= 0.0) {
-    if (lead()) st->done = isfinite(pq[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+    if (lead()) {
+      st->done = isfinite(pq[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+      st->halt = k + 1;
+    }
     return;
   }
   const double alpha = st->rho[par] / pq[0];
@@ -303,10 +346,9 @@ __global__ __launch_bounds__(RB) void k_cg_update(int64_t n, T* __restrict__ x,
   const T a = (T)alpha;
   double acc[1] = {0.0};
   strided4(
-      n, [&](int64_t i) { return Pack<T, 4>{{x[i], p[i], r[i], q[i]}}; },
-      [&](int64_t i, const Pack<T, 4>& e) {
-        x[i] = e.v[0] + a * e.v[1];
-        const T ri = e.v[2] - a * e.v[3];
+      n, [&](int64_t i) { return Pack<T, 2>{{r[i], q[i]}}; },
+      [&](int64_t i, const Pack<T, 2>& e) {
+        const T ri = e.v[0] - a * e.v[1];
         r[i] = ri;
         acc[0] += (double)ri * (double)ri;
       });
@@ -314,17 +356,19 @@ __global__ __launch_bounds__(RB) void k_cg_update(int64_t n, T* __restrict__ x,
 }
 
 template <typename T>
-__global__ __launch_bounds__(RB) void k_cg_direction(int64_t n, const T* __restrict__ r,
-                                                     T* __restrict__ p,
-                                                     const double* __restrict__ pb, int g,
-                                                     KState* st, int par, int64_t k) {
-  if (st->done) return;
+__global__ __launch_bounds__(RB) void k_cg_xp(int64_t n, T* __restrict__ x,
+                                              const T* __restrict__ r, T* __restrict__ p,
+                                              const double* __restrict__ pb, int g, KState* st,
+                                              int par, int64_t k) {
+  const int64_t halt = st->halt;
+  if (halt != 0 && k >= halt - 1) return;
   double rr[1];
   finish<1>(pb, g, rr);
   const double rn = rr[0];
   const bool bad = !isfinite(rn);
   const bool conv = !bad && sqrt(rn) <= st->thr;
   const bool maxit = k + 1 >= st->max_iters;
+  const bool stop = bad || conv || maxit;
   if (lead()) {
     st->iters = k + 1;
     st->res2 = rn;
@@ -335,12 +379,22 @@ __global__ __launch_bounds__(RB) void k_cg_direction(int64_t n, const T* __restr
       st->done = ST_CONVERGED;
     else if (maxit)
       st->done = ST_MAXIT;
+    if (stop) st->halt = k + 2;
   }
-  if (bad || conv || maxit) return;
+  const T a = (T)st->alpha;
+  if (stop) {
+    strided4(
+        n, [&](int64_t i) { return Pack<T, 2>{{x[i], p[i]}}; },
+        [&](int64_t i, const Pack<T, 2>& e) { x[i] = e.v[0] + a * e.v[1]; });
+    return;
+  }
   const T beta = (T)(rn / st->rho[par]);
   strided4(
-      n, [&](int64_t i) { return Pack<T, 2>{{r[i], p[i]}}; },
-      [&](int64_t i, const Pack<T, 2>& e) { p[i] = e.v[0] + beta * e.v[1]; });
+      n, [&](int64_t i) { return Pack<T, 3>{{x[i], r[i], p[i]}}; },
+      [&](int64_t i, const Pack<T, 3>& e) {
+        x[i] = e.v[0] + a * e.v[2];
+        p[i] = e.v[1] + beta * e.v[2];
+      });
 }
 
 // ---------------------------------------------------------------------------
@@ -1184,6 +1238,7 @@ struct Work {
   double* pc;
   double* pd;
   double* pm;        // MAXG * MAXM doubles (GMRES multi-dots)
+  double* pw;        // kDotPartials doubles (partials of a product with its dot)
   char* vec;         // vectors
 };
 
@@ -1193,9 +1248,11 @@ mxs_status get_work(mxs_ctx* ctx, size_t vec_bytes, Work* w) {
   const size_t st_bytes = align_up(sizeof(KState), 256);
   const size_t p2 = (size_t)MAXG * 2 * sizeof(double);
   const size_t pm = (size_t)MAXG * MAXM * sizeof(double);
-  const size_t total = st_bytes + 4 * p2 + pm + vec_bytes + 256;
+  const size_t pw = (size_t)kDotPartials * sizeof(double);
+  const size_t total = st_bytes + 4 * p2 + pm + pw + vec_bytes + 256;
   if (!ws_reserve(ctx, total)) return fail(ctx, MXS_OOM, "solver workspace of %zu bytes", total);
-  if (!pinned_reserve(ctx, st_bytes)) return fail(ctx, MXS_OOM, "pinned state mirror");
+  // host mirror + the two polling copies
+  if (!pinned_reserve(ctx, 3 * st_bytes)) return fail(ctx, MXS_OOM, "pinned state mirror");
   char* base = (char*)ctx->ws.ptr;
   w->st = (KState*)base;
   w->pa = (double*)(base + st_bytes);
@@ -1203,7 +1260,8 @@ mxs_status get_work(mxs_ctx* ctx, size_t vec_bytes, Work* w) {
   w->pc = (double*)(base + st_bytes + 2 * p2);
   w->pd = (double*)(base + st_bytes + 3 * p2);
   w->pm = (double*)(base + st_bytes + 4 * p2);
-  w->vec = base + st_bytes + 4 * p2 + pm;
+  w->pw = (double*)(base + st_bytes + 4 * p2 + pm);
+  w->vec = base + st_bytes + 4 * p2 + pm + pw;
   w->hst = (KState*)ctx->pinned;
   MXS_HIP_TRY(ctx, hipMemsetAsync(w->st, 0, sizeof(KState), ctx->stream));
   return MXS_OK;
@@ -1287,31 +1345,79 @@ Stop read_stop(const mxs_stop* s, int64_t default_max) {
 
 // Runs CG iterations from the state already on the device until the
 // device status is set.  Vectors of type T; the operator is A.
+// The host polls the device status without leaving the GPU idle: after
+// each batch of `check_every` iterations it enqueues a copy of the state
+// into one of two pinned slots and an event, enqueues the next batch, and
+// only then waits for the previous batch's copy.  A batch enqueued after
+// the one that finished the solve returns at once in every kernel.
+struct StatusPoll {
+  mxs_ctx* ctx;
+  Work& w;
+  KState* slot[2];
+  StatusPoll(mxs_ctx* c, Work& wk) : ctx(c), w(wk) {
+    const size_t stb = align_up(sizeof(KState), 256);
+    slot[0] = (KState*)((char*)ctx->pinned + stb);
+    slot[1] = (KState*)((char*)ctx->pinned + 2 * stb);
+  }
+  mxs_status record(int s) {
+    MXS_HIP_TRY(ctx, hipMemcpyAsync(slot[s], w.st, sizeof(KState), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    MXS_HIP_TRY(ctx, hipEventRecord(ctx->poll_ev[s], ctx->stream));
+    return MXS_OK;
+  }
+  mxs_status wait(int s) {
+    MXS_HIP_TRY(ctx, hipEventSynchronize(ctx->poll_ev[s]));
+    return MXS_OK;
+  }
+};
+
+// Enqueues batch(k0) for k0 = k, k + C, k + 2C, ... until the device status
+// is set, polling it through StatusPoll; returns with the final state in
+// w.hst.
+template <typename Batch>
+mxs_status run_polled(mxs_ctx* ctx, Work& w, int64_t k, int C, const char* what, Batch batch) {
+  StatusPoll poll(ctx, w);
+  mxs_status s;
+  if ((s = batch(k)) || (s = poll.record(0))) return s;
+  int cur = 0;
+  int64_t seen = k;
+  for (int64_t kq = k + C;; kq += C) {
+    if ((s = batch(kq)) || (s = poll.record(1 - cur)) || (s = poll.wait(cur))) return s;
+    const KState& sn = *poll.slot[cur];
+    if (sn.done) return pull_state(ctx, w);
+    if (sn.iters <= seen)
+      return fail(ctx, MXS_HIP, "%s made no progress (device state not updated)", what);
+    seen = sn.iters;
+    cur = 1 - cur;
+  }
+}
+
 template <typename T>
 mxs_status cg_loop(mxs_ctx* ctx, const mxs_matrix* A, Work& w, T* x, T* r, T* p, T* q,
                    int check_every) {
   const int64_t n = A->n;
   const int g = red_grid(n);
   const T one = 1, zero = 0;
-  int64_t k = w.hst->iters;
-  for (;;) {
-    const int64_t before = k;
-    for (int it = 0; it < check_every; ++it, ++k) {
-      const int par = (int)(k & 1);
-      mxs_status s = launch_spmv(ctx, A, &one, p, &zero, q, &w.st->done);
-      if (s) return s;
-      k_cg_pq<T><<<g, RB, 0, ctx->stream>>>(n, p, q, w.pa, w.st);
-      k_cg_update<T><<<g, RB, 0, ctx->stream>>>(n, x, p, r, q, w.pa, g, w.pb, w.st, par);
-      k_cg_direction<T><<<g, RB, 0, ctx->stream>>>(n, r, p, w.pb, g, w.st, par, k);
+  return run_polled(ctx, w, w.hst->iters, check_every, "CG", [&](int64_t k0) -> mxs_status {
+    for (int64_t kk = k0; kk < k0 + check_every; ++kk) {
+      const int par = (int)(kk & 1);
+      // q = A p and p.q: in the product's own launches when its kernel
+      // offers that, else a separate reduction
+      const double* pq = w.pw;
+      int gq = launch_spmv_dot(ctx, A, p, q, &w.st->done, w.pw);
+      if (gq == 0) {
+        mxs_status s = launch_spmv(ctx, A, &one, p, &zero, q, &w.st->done);
+        if (s) return s;
+        k_cg_pq<T><<<g, RB, 0, ctx->stream>>>(n, p, q, w.pa, w.st);
+        pq = w.pa;
+        gq = g;
+      }
+      k_cg_r<T><<<g, RB, 0, ctx->stream>>>(n, r, q, pq, gq, w.pb, w.st, par, kk);
+      k_cg_xp<T><<<g, RB, 0, ctx->stream>>>(n, x, r, p, w.pb, g, w.st, par, kk);
     }
     MXS_HIP_TRY(ctx, hipGetLastError());
-    mxs_status s = pull_state(ctx, w);
-    if (s) return s;
-    if (w.hst->done) return MXS_OK;
-    if (w.hst->iters <= before)
-      return fail(ctx, MXS_HIP, "CG made no progress (device state not updated)");
-    k = w.hst->iters;
-  }
+    return MXS_OK;
+  });
 }
 
 void fill_info(mxs_solve_info* info, const KState& h, double base, double relres_true,
@@ -1449,6 +1555,7 @@ mxs_status solve_cg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double* 
     h.rho[h.iters & 1] = rt2;
     h.res2 = rt2;
     h.done = RUN;
+    h.halt = 0;
     if ((s = push_state(ctx, w))) return s;
     MXS_HIP_TRY(ctx, hipMemcpyAsync(p, r, n * sizeof(double), hipMemcpyDeviceToDevice,
                                     ctx->stream));
@@ -1474,10 +1581,8 @@ mxs_status pcg_loop(mxs_ctx* ctx, const mxs_matrix* A, const mxs_precond* M, con
   const int64_t n = A->n;
   const int g = red_grid(n);
   const T one = 1, zero = 0;
-  int64_t k = w.hst->iters;
-  for (;;) {
-    const int64_t before = k;
-    for (int it = 0; it < check_every; ++it, ++k) {
+  return run_polled(ctx, w, w.hst->iters, check_every, "PCG", [&](int64_t k0) -> mxs_status {
+    for (int64_t k = k0; k < k0 + check_every; ++k) {
       const int par = (int)(k & 1);
       mxs_status s = launch_spmv(ctx, A, &one, p, &zero, q, &w.st->done);
       if (s) return s;
@@ -1490,13 +1595,8 @@ mxs_status pcg_loop(mxs_ctx* ctx, const mxs_matrix* A, const mxs_precond* M, con
                                                         par, k);
     }
     MXS_HIP_TRY(ctx, hipGetLastError());
-    mxs_status s = pull_state(ctx, w);
-    if (s) return s;
-    if (w.hst->done) return MXS_OK;
-    if (w.hst->iters <= before)
-      return fail(ctx, MXS_HIP, "PCG made no progress (device state not updated)");
-    k = w.hst->iters;
-  }
+    return MXS_OK;
+  });
 }
 
 template <typename T>
@@ -1634,27 +1734,26 @@ mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, do
       if ((s = push_state(ctx, w))) return s;
     }
     bool first = true;
-    int64_t k = iters;
     while (done == RUN) {
-      for (int it = 0; it < stop.check_every; ++it, ++k) {
-        const int par = (int)(k & 1);
-        k_bi_p<<<g, RB, 0, ctx->stream>>>(n, r, p, v, w.pc, g, w.st, par, k, first ? 1 : 0);
-        first = false;
-        if ((s = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return s;
-        k_bi_rv<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
-        k_bi_s<<<g, RB, 0, ctx->stream>>>(n, r, v, sv, w.pa, g, w.pb, w.st, par);
-        if ((s = launch_spmv(ctx, A, &one, sv, &zero, t, &w.st->done))) return s;
-        k_bi_omega<<<g, RB, 0, ctx->stream>>>(n, t, sv, w.pb, g, w.pd, w.st, k);
-        k_bi_update<<<g, RB, 0, ctx->stream>>>(n, x, p, sv, t, r, rh, w.pd, g, w.pc, w.st, k);
-      }
-      MXS_HIP_TRY(ctx, hipGetLastError());
-      const int64_t before = iters;
-      if ((s = pull_state(ctx, w))) return s;
+      s = run_polled(ctx, w, iters, stop.check_every, "BiCGSTAB", [&](int64_t k0) -> mxs_status {
+        for (int64_t k = k0; k < k0 + stop.check_every; ++k) {
+          const int par = (int)(k & 1);
+          k_bi_p<<<g, RB, 0, ctx->stream>>>(n, r, p, v, w.pc, g, w.st, par, k, first ? 1 : 0);
+          first = false;
+          mxs_status e;
+          if ((e = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return e;
+          k_bi_rv<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
+          k_bi_s<<<g, RB, 0, ctx->stream>>>(n, r, v, sv, w.pa, g, w.pb, w.st, par);
+          if ((e = launch_spmv(ctx, A, &one, sv, &zero, t, &w.st->done))) return e;
+          k_bi_omega<<<g, RB, 0, ctx->stream>>>(n, t, sv, w.pb, g, w.pd, w.st, k);
+          k_bi_update<<<g, RB, 0, ctx->stream>>>(n, x, p, sv, t, r, rh, w.pd, g, w.pc, w.st, k);
+        }
+        MXS_HIP_TRY(ctx, hipGetLastError());
+        return MXS_OK;
+      });
+      if (s) return s;
       done = h.done;
       iters = h.iters;
-      if (done == RUN && iters <= before)
-        return fail(ctx, MXS_HIP, "BiCGSTAB made no progress (device state not updated)");
-      k = iters;
       if (done == ST_HALF) {
         k_bi_half<<<g, RB, 0, ctx->stream>>>(n, x, p, w.st);
         MXS_HIP_TRY(ctx, hipGetLastError());
@@ -1773,21 +1872,21 @@ mxs_status solve_pipecg(mxs_ctx* ctx, const mxs_matrix* A, const double* b, doub
     return s;
   }
   for (;;) {
-    int64_t k = h.iters;
-    while (h.done == RUN) {
-      const int64_t before = k;
-      for (int it = 0; it < stop.check_every; ++it, ++k) {
-        double* pin = (k & 1) ? w.pb : w.pa;
-        double* pout = (k & 1) ? w.pa : w.pb;
-        if ((s = launch_spmv(ctx, A, &one, wv, &zero, q, &w.st->done))) return s;
-        k_pipe_update<<<g, RB, 0, ctx->stream>>>(n, x, r, wv, q, z, sv, p, pin, g, pout, w.st,
-                                                 k);
-      }
-      MXS_HIP_TRY(ctx, hipGetLastError());
-      if ((s = pull_state(ctx, w))) return s;
-      if (h.done == RUN && h.iters <= before)
-        return fail(ctx, MXS_HIP, "pipelined CG made no progress (device state not updated)");
-      k = h.iters;
+    if (h.done == RUN) {
+      s = run_polled(ctx, w, h.iters, stop.check_every, "pipelined CG",
+                     [&](int64_t k0) -> mxs_status {
+                       for (int64_t k = k0; k < k0 + stop.check_every; ++k) {
+                         double* pin = (k & 1) ? w.pb : w.pa;
+                         double* pout = (k & 1) ? w.pa : w.pb;
+                         mxs_status e = launch_spmv(ctx, A, &one, wv, &zero, q, &w.st->done);
+                         if (e) return e;
+                         k_pipe_update<<<g, RB, 0, ctx->stream>>>(n, x, r, wv, q, z, sv, p, pin,
+                                                                  g, pout, w.st, k);
+                       }
+                       MXS_HIP_TRY(ctx, hipGetLastError());
+                       return MXS_OK;
+                     });
+      if (s) return s;
     }
     if (h.done == ST_BREAKDOWN || h.done == ST_NONFINITE) {
       s = map_done(h.done);
@@ -1864,25 +1963,24 @@ mxs_status solve_cgs(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double*
       h.max_iters = stop.max_iters;
       if ((s = push_state(ctx, w))) return s;
     }
-    int64_t k = iters;
-    while (done == RUN) {
-      for (int it = 0; it < stop.check_every; ++it, ++k) {
-        const int par = (int)(k & 1);
-        if ((s = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return s;
-        k_cgs_sigma<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
-        k_cgs_qw<<<g, RB, 0, ctx->stream>>>(n, u, v, q, wv, x, w.pa, g, w.st, par);
-        if ((s = launch_spmv(ctx, A, &one, wv, &zero, v, &w.st->done))) return s;
-        k_cgs_r<<<g, RB, 0, ctx->stream>>>(n, r, v, rh, w.pb, w.st);
-        k_cgs_dir<<<g, RB, 0, ctx->stream>>>(n, r, q, u, p, w.pb, g, w.st, par, k);
-      }
-      MXS_HIP_TRY(ctx, hipGetLastError());
-      const int64_t before = iters;
-      if ((s = pull_state(ctx, w))) return s;
+    if (done == RUN) {
+      s = run_polled(ctx, w, iters, stop.check_every, "CGS", [&](int64_t k0) -> mxs_status {
+        for (int64_t k = k0; k < k0 + stop.check_every; ++k) {
+          const int par = (int)(k & 1);
+          mxs_status e;
+          if ((e = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return e;
+          k_cgs_sigma<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
+          k_cgs_qw<<<g, RB, 0, ctx->stream>>>(n, u, v, q, wv, x, w.pa, g, w.st, par);
+          if ((e = launch_spmv(ctx, A, &one, wv, &zero, v, &w.st->done))) return e;
+          k_cgs_r<<<g, RB, 0, ctx->stream>>>(n, r, v, rh, w.pb, w.st);
+          k_cgs_dir<<<g, RB, 0, ctx->stream>>>(n, r, q, u, p, w.pb, g, w.st, par, k);
+        }
+        MXS_HIP_TRY(ctx, hipGetLastError());
+        return MXS_OK;
+      });
+      if (s) return s;
       done = h.done;
       iters = h.iters;
-      if (done == RUN && iters <= before)
-        return fail(ctx, MXS_HIP, "CGS made no progress (device state not updated)");
-      k = iters;
     }
     if (done == ST_BREAKDOWN || done == ST_NONFINITE) {
       s = map_done(done);
@@ -2209,6 +2307,7 @@ mxs_status mxs_graph_create(mxs_ctx* ctx, int64_t n, int64_t nnz, const int32_t*
     const unsigned ge = (unsigned)std::min<int64_t>((nnz + 255) / 256 + 1, 65536);
     k_outdeg<<<ge, 256, 0, ctx->stream>>>(nnz, G->T->csr.col, d);
     k_transition<<<ge, 256, 0, ctx->stream>>>(nnz, G->T->csr.col, d, (double*)G->T->csr.val);
+    if ((st = refresh_panel_values(ctx, G->T))) break;
     k_dangling<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(n, d, G->dangling);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(hd.data(), d, n * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream) !=

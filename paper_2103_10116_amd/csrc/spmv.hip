@@ -308,28 +308,21 @@ __global__ __launch_bounds__(256) void k_csr_vec(int64_t n, const int32_t* __res
 // (Staging the next block while walking the current one was measured
 // slower: the extra registers cost more occupancy than the overlap gains.)
 // ---------------------------------------------------------------------------
-template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G, int ST>
-__global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
-                                                     const int32_t* __restrict__ blocks,
-                                                     const int32_t* __restrict__ bnnz,
-                                                     const int32_t* __restrict__ rowptr,
-                                                     const int32_t* __restrict__ col,
-                                                     const V* __restrict__ val,
-                                                     const float* __restrict__ scale,
-                                                     const T* __restrict__ x, T* __restrict__ y,
-                                                     T alpha, T beta,
-                                                     const int32_t* __restrict__ skip) {
+// One row block (b) of the rows-from-LDS kernel, by one wave; vl/cl are the
+// wave's LDS tables.  With DOT the lanes that write a row i also return
+// x[i] * y[i] (the product's own inner product p.q when x = p and y = q = A p),
+// else 0.
+template <typename V, typename T, int CMAX, bool SCALED, int G, int ST, bool DOT>
+__device__ __forceinline__ double rl_block(int64_t b, const int32_t* __restrict__ blocks,
+                                           const int32_t* __restrict__ bnnz,
+                                           const int32_t* __restrict__ rowptr,
+                                           const int32_t* __restrict__ col,
+                                           const V* __restrict__ val,
+                                           const float* __restrict__ scale,
+                                           const T* __restrict__ x, T* __restrict__ y, T alpha,
+                                           T beta, V* vl, int32_t* cl) {
   constexpr int U = CMAX / 64;  // entries per lane of a full block
-  __shared__ V vl_all[WPB][CMAX];
-  __shared__ int32_t cl_all[WPB][CMAX];
-  if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
-  // wave-uniform (scalar block-bound loads)
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  V* vl = vl_all[wv];
-  int32_t* cl = cl_all[wv];
-  const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
-  if (b >= nblocks) return;
   const int32_t r0 = blocks[b], r1 = blocks[b + 1];
   const int32_t s = bnnz[b], e = bnnz[b + 1];
   const int nr = r1 - r0, len = e - s;
@@ -349,9 +342,11 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
     T acc = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) {
       if (SCALED) acc *= (T)scale[r0];
-      y[r0] = combine(alpha, acc, beta, y, r0);
+      const T out = combine(alpha, acc, beta, y, r0);
+      y[r0] = out;
+      if constexpr (DOT) return (double)x[r0] * (double)out;
     }
-    return;
+    return 0.0;
   }
   // bounds of the lane's row (an empty range at len for lanes past the
   // block): loaded unconditionally so that their wait can be deferred
@@ -402,10 +397,73 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
   T sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-  if (h != 0 || rl >= nr) return;
+  if (h != 0 || rl >= nr) return 0.0;
   const int64_t i = (int64_t)r0 + rl;
   if (SCALED) sum *= (T)scale[i];
-  y[i] = combine(alpha, sum, beta, y, i);
+  const T out = combine(alpha, sum, beta, y, i);
+  y[i] = out;
+  if constexpr (DOT) return (double)x[i] * (double)out;
+  return 0.0;
+}
+
+template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G, int ST>
+__global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
+                                                     const int32_t* __restrict__ blocks,
+                                                     const int32_t* __restrict__ bnnz,
+                                                     const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const V* __restrict__ val,
+                                                     const float* __restrict__ scale,
+                                                     const T* __restrict__ x, T* __restrict__ y,
+                                                     T alpha, T beta,
+                                                     const int32_t* __restrict__ skip) {
+  __shared__ V vl_all[WPB][CMAX];
+  __shared__ int32_t cl_all[WPB][CMAX];
+  if (skip && *skip) return;
+  // wave-uniform (scalar block-bound loads)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if (b >= nblocks) return;
+  rl_block<V, T, CMAX, SCALED, G, ST, false>(b, blocks, bnnz, rowptr, col, val, scale, x, y,
+                                             alpha, beta, vl_all[wv], cl_all[wv]);
+}
+
+// The same product, y = A x, where each work-group of WPB waves (one row
+// block each) also stores the sum of x[i] * y[i] over its rows to
+// part[blockIdx.x]: the p.q of a CG iteration comes with the product.  WPB
+// is chosen so that the partials stay few enough for every block of the
+// next kernel to add them.
+template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G, int ST>
+__global__ __launch_bounds__(64 * WPB) void k_csr_rl_dot(int64_t nblocks,
+                                                         const int32_t* __restrict__ blocks,
+                                                         const int32_t* __restrict__ bnnz,
+                                                         const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const V* __restrict__ val,
+                                                         const float* __restrict__ scale,
+                                                         const T* __restrict__ x,
+                                                         T* __restrict__ y,
+                                                         double* __restrict__ part,
+                                                         const int32_t* __restrict__ skip) {
+  __shared__ V vl_all[WPB][CMAX];
+  __shared__ int32_t cl_all[WPB][CMAX];
+  __shared__ double red[WPB];
+  if (skip && *skip) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  double acc = 0.0;
+  if (b < nblocks)
+    acc = rl_block<V, T, CMAX, SCALED, G, ST, true>(b, blocks, bnnz, rowptr, col, val, scale, x,
+                                                    y, T(1), T(0), vl_all[wv], cl_all[wv]);
+  acc = wave_total(acc);
+  if ((threadIdx.x & 63) == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+#pragma unroll
+    for (int w = 1; w < WPB; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -980,15 +1038,20 @@ __global__ void k_coo_fix(int64_t nchunks, const int32_t* __restrict__ cont_row,
 
 // Column panels: y_i = alpha * s_i * (sum of row i's panel partials, in
 // panel order) + beta * y_i, over every row (a row with no entries gets 0).
-template <typename T, bool SCALED>
+// With DOT (x = p, y = q = A p of a CG iteration) each work-group also
+// stores the sum of x[i] * y[i] over its rows to dpart[blockIdx.x].
+template <typename T, bool SCALED, bool DOT>
 __global__ __launch_bounds__(256) void k_panel_add(int64_t n, int P,
                                                    const uint8_t* __restrict__ mask,
                                                    const T* __restrict__ part,
                                                    const float* __restrict__ scale,
                                                    T* __restrict__ y, T alpha, T beta,
-                                                   const int32_t* __restrict__ skip) {
+                                                   const int32_t* __restrict__ skip,
+                                                   const T* __restrict__ x,
+                                                   double* __restrict__ dpart) {
   if (skip && *skip) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double dot = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const unsigned m = mask[i];
     T v[8];
@@ -1000,7 +1063,16 @@ __global__ __launch_bounds__(256) void k_panel_add(int64_t n, int P,
     for (int p = 0; p < 8; ++p)
       if (p < P) s += v[p];
     if (SCALED) s *= (T)scale[i];
-    y[i] = combine(alpha, s, beta, y, i);
+    const T out = combine(alpha, s, beta, y, i);
+    y[i] = out;
+    if constexpr (DOT) dot += (double)x[i] * (double)out;
+  }
+  if constexpr (DOT) {
+    __shared__ double red[4];
+    dot = wave_total(dot);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) dpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
   }
 }
 
@@ -1151,6 +1223,48 @@ void launch_csr_rl(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, 
     launch_csr_rl_g<V, T, SCALED, CMAX, 1>(ctx, P, alpha, x, beta, y, skip);
 }
 
+template <typename V, typename T, bool SCALED, int CMAX, int G, int ST, int WPB>
+int launch_csr_rl_dot_w(mxs_ctx* ctx, const CsrPart& P, const T* x, T* y, const int32_t* skip,
+                        double* dpart) {
+  const int g = (int)((P.nblocks + WPB - 1) / WPB);
+  k_csr_rl_dot<V, T, CMAX, SCALED, WPB, G, ST><<<g, 64 * WPB, 0, ctx->stream>>>(
+      P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, dpart, skip);
+  return g;
+}
+
+// the fewest waves per work-group (2, 4 or 8) that keep the partials within
+// kDotPartials; 0 (no launch) when even 8 do not
+template <typename V, typename T, bool SCALED, int CMAX, int G, int ST>
+int launch_csr_rl_dot_g(mxs_ctx* ctx, const CsrPart& P, const T* x, T* y, const int32_t* skip,
+                        double* dpart) {
+  // LDS of a work-group: WPB tables of CMAX values and column indices
+  constexpr size_t per_wave = (size_t)CMAX * (sizeof(V) + sizeof(int32_t));
+  if (P.nblocks <= 2 * (int64_t)kDotPartials)
+    return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 2>(ctx, P, x, y, skip, dpart);
+  if constexpr (4 * per_wave <= 98304) {
+    if (P.nblocks <= 4 * (int64_t)kDotPartials)
+      return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 4>(ctx, P, x, y, skip, dpart);
+  }
+  if constexpr (8 * per_wave <= 98304) {
+    if (P.nblocks <= 8 * (int64_t)kDotPartials)
+      return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 8>(ctx, P, x, y, skip, dpart);
+  }
+  return 0;
+}
+
+template <typename V, typename T, bool SCALED, int CMAX>
+int launch_csr_rl_dot(mxs_ctx* ctx, const CsrPart& P, const T* x, T* y, const int32_t* skip,
+                      double* dpart) {
+#define MXS_RL_DOT(GG)                                                               \
+  return P.rl_step == 16                                                             \
+             ? launch_csr_rl_dot_g<V, T, SCALED, CMAX, GG, 16>(ctx, P, x, y, skip, dpart) \
+             : launch_csr_rl_dot_g<V, T, SCALED, CMAX, GG, 8>(ctx, P, x, y, skip, dpart);
+  if (P.rl_lanes == 4) MXS_RL_DOT(4)
+  if (P.rl_lanes == 2) MXS_RL_DOT(2)
+  MXS_RL_DOT(1)
+#undef MXS_RL_DOT
+}
+
 template <typename V, typename T, bool SCALED, int CMAX, int WPB>
 void launch_csr_pr_w(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
                      const int32_t* skip) {
@@ -1228,7 +1342,8 @@ size_t cont_bytes(int64_t nchunks) {
 // the continuation partials), their fix-up, then the pass that adds them
 template <typename V, typename T, bool SCALED>
 void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
-                      const int32_t* skip, void* scratch) {
+                      const int32_t* skip, void* scratch, double* dpart = nullptr,
+                      int* ndpart = nullptr) {
   const CsrPart& P = A->csr;
   if (P.panels > 1) {
     if (P.nchunks == 0) return;
@@ -1239,8 +1354,15 @@ void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T 
       k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
           P.nchunks, c.row, (T*)c.val, part, T(1), skip, P.srid);
     const unsigned g = (unsigned)std::min<int64_t>((A->n + 255) / 256, (int64_t)ctx->num_cus * 16);
-    k_panel_add<T, SCALED><<<g, 256, 0, ctx->stream>>>(A->n, P.panels, P.pmask, part, P.scale, y,
-                                                       alpha, beta, skip);
+    if (dpart) {
+      const unsigned gd = std::min<unsigned>(g, kDotPartials);
+      k_panel_add<T, SCALED, true><<<gd, 256, 0, ctx->stream>>>(
+          A->n, P.panels, P.pmask, part, P.scale, y, alpha, beta, skip, x, dpart);
+      *ndpart = (int)gd;
+    } else {
+      k_panel_add<T, SCALED, false><<<g, 256, 0, ctx->stream>>>(
+          A->n, P.panels, P.pmask, part, P.scale, y, alpha, beta, skip, nullptr, nullptr);
+    }
     return;
   }
   if (P.nempty > 0)
@@ -1485,6 +1607,59 @@ mxs_status noalloc_scratch_init(mxs_ctx* ctx) {
 void* noalloc_scratch(int device) {
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+
+// y = A x together with work-group partial sums of x[i] * y[i] (CG's p.q),
+// for the kernels that write each row's result once from one lane: the
+// rows-from-LDS CSR kernel and the column-panel merge path (whose last pass
+// forms the rows).  Returns the number of partials written to dpart (at most
+// kDotPartials), or 0 when A's kernel has no such form (nothing enqueued).
+template <typename V, typename T, bool SCALED>
+int launch_dot_typed(mxs_ctx* ctx, const mxs_matrix* A, const T* x, T* y, const int32_t* skip,
+                     double* dpart, void* scratch) {
+  const CsrPart& P = A->csr;
+  if (P.rows_lds && P.nblocks > 0) {
+    if (P.block_nnz <= 512) return launch_csr_rl_dot<V, T, SCALED, 512>(ctx, P, x, y, skip, dpart);
+    if (P.block_nnz <= 1024)
+      return launch_csr_rl_dot<V, T, SCALED, 1024>(ctx, P, x, y, skip, dpart);
+    return launch_csr_rl_dot<V, T, SCALED, 2048>(ctx, P, x, y, skip, dpart);
+  }
+  if (P.merge && P.panels > 1 && P.nchunks > 0) {
+    if constexpr (std::is_same_v<V, double> || std::is_same_v<V, float> ||
+                  std::is_same_v<V, _Float16>) {
+      int nd = 0;
+      launch_csr_merge<V, T, SCALED>(ctx, A, T(1), x, T(0), y, skip, scratch, dpart, &nd);
+      return nd;
+    }
+  }
+  return 0;
+}
+
+int launch_spmv_dot(mxs_ctx* ctx, const mxs_matrix* A, const void* x, void* y,
+                    const int32_t* skip, double* dpart) {
+  if (A->fmt != MXS_CSR || A->n == 0 || A->n != A->ncols) return 0;
+  const CsrPart& P = A->csr;
+  if (!(P.rows_lds && P.nblocks > 0) && !(P.merge && P.panels > 1 && P.nchunks > 0)) return 0;
+  const size_t need = spmv_scratch_bytes(A);
+  if (need > ctx->spmv_ws.bytes) {
+    if (ctx->spmv_ws.ptr) {
+      if (hipStreamSynchronize(ctx->stream) != hipSuccess) return 0;
+      ctx->alloc.release(ctx->spmv_ws.ptr);
+    }
+    const size_t want = need + need / 4;
+    ctx->spmv_ws.ptr = ctx->alloc.alloc(want);
+    ctx->spmv_ws.bytes = ctx->spmv_ws.ptr ? want : 0;
+    if (!ctx->spmv_ws.ptr) return 0;
+  }
+  void* sc = ctx->spmv_ws.ptr;
+  int g = 0;
+  if (A->dt == MXS_F64)
+    g = launch_dot_typed<double, double, false>(ctx, A, (const double*)x, (double*)y, skip, dpart, sc);
+  else if (A->dt == MXS_F32)
+    g = launch_dot_typed<float, float, false>(ctx, A, (const float*)x, (float*)y, skip, dpart, sc);
+  else if (A->dt == MXS_F16_ROWSCALED)
+    g = launch_dot_typed<_Float16, float, true>(ctx, A, (const float*)x, (float*)y, skip, dpart, sc);
+  return g;
 }
 
 // The context's own scratch, grown (after the stream has drained) when a

@@ -150,6 +150,73 @@ def test_cg_paths_agree(env, orc):
         assert abs(rc.iters - ro.iters) <= 2, (kw, rc.iters, ro.iters)
 
 
+_DOT_CASES = {"rows_lds": ("poisson3d", "csr", {}),
+              "panels": ("spd", "csr", dict(csr_kernel="merge", col_panels=4)),
+              "separate_pq": ("poisson3d", "coo", {})}
+
+
+@pytest.mark.parametrize("case", sorted(_DOT_CASES))
+def test_cg_three_launch_iteration(env, orc, case):
+    """CG's iteration in three launches, on products that form p.q in their
+    own launches (rows-from-LDS CSR, merge path over column panels) and on
+    one that does not (COO, with a separate reduction): the oracle's
+    residual meets 1e-10 and the iterations stay within 3 (or 10%) of the
+    oracle's CG; after max_iters = 3 the iterate equals three steps of the oracle's
+    CG (every block applied the last x update), and a breakdown at the
+    first step leaves x untouched."""
+    mxs, ctx, torch = env
+    kind, fmt, opts = _DOT_CASES[case]
+    A = I.poisson3d(24) if kind == "poisson3d" else I.random_spd(20000, seed=26)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 61))
+    M = mxs.Matrix.from_host(ctx, A)
+    B = M.convert(fmt, "f64", **opts)
+    d = B.info()
+    if case == "rows_lds":
+        assert d["csr_kernel"] == mxs.CSR_ROWS_LDS
+    if case == "panels":
+        assert d["csr_kernel"] == mxs.CSR_MERGE and d["col_panels"] == 4
+    x = _dev(torch, np.zeros(A.n))
+    r = mxs.solve(ctx, "cg", B, _dev(torch, b), x, tol=1e-10)
+    _assert_converged(orc, A, b, x.cpu().numpy(), r, 1e-10)
+    ref = orc.cg(A, b, tol=1e-10)
+    # counts depend on rounding; the random SPD system needs ~850 steps
+    assert abs(r.iters - ref.iters) <= max(3, ref.iters // 10), (r.iters, ref.iters)
+    x = _dev(torch, np.zeros(A.n))
+    r = mxs.solve(ctx, "cg", B, _dev(torch, b), x, tol=1e-10, max_iters=3, raise_on_error=False)
+    assert r.status == mxs.NOT_CONVERGED and r.iters == 3
+    ref3 = orc.cg(A, b, tol=1e-10, maxit=3).x
+    assert np.linalg.norm(x.cpu().numpy() - ref3) <= 1e-12 * np.linalg.norm(ref3)
+    # indefinite diagonal of the same size: p.Ap < 0 at the first step
+    dv = np.where(np.arange(A.n) % 2 == 0, 1.0, -2.0)
+    D = I.CSRMatrix(A.n, A.n, np.arange(A.n + 1, dtype=np.int32),
+                    np.arange(A.n, dtype=np.int32), dv)
+    Dm = mxs.Matrix.from_host(ctx, D)
+    Db = Dm.convert(fmt, "f64", **opts) if fmt != "csr" or opts else Dm
+    x0 = I.uniform_vector(A.n, 62)
+    x = _dev(torch, x0)
+    r = mxs.solve(ctx, "cg", Db, _dev(torch, np.ones(A.n)), x, tol=1e-10,
+                  raise_on_error=False)
+    assert r.status == mxs.BREAKDOWN and r.iters == 0
+    assert np.array_equal(x.cpu().numpy(), x0)
+
+
+def test_ir_inner_product_with_dot(env, orc):
+    """Refinement whose FP32 inner CG runs on the merge path over column
+    panels (p.q formed by the product's last pass)."""
+    mxs, ctx, torch = env
+    A = I.random_spd(20000, seed=26)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 63))
+    M = mxs.Matrix.from_host(ctx, A)
+    for low in ("f32", "f16"):
+        L = M.convert("csr", low, csr_kernel="merge", col_panels=2)
+        assert L.info()["col_panels"] == 2
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        r = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-10, last_step_variant=True)
+        xh = x.cpu().numpy()
+        assert r.status == mxs.OK
+        assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
+
+
 def test_cg_eigenvector_one_step(env, orc):
     m = 12
     A = I.poisson2d(m)
