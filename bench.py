@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sections", default="probe,spmv,zipf,krylov,ir,pagerank,serve,cpu")
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--plain-requests", type=int, default=1000)
+    ap.add_argument("--plain-requests", type=int, default=10000)
     ap.add_argument("--grid", type=int, default=128, help="stencil grid side (128 = full size)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -154,11 +154,15 @@ def main():
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic"}
     extra = {}
+    # GPU solutions (host copies) of the solver rows, keyed by system: the
+    # CPU leg solves the same systems with the oracle and reports each row's
+    # distance to the oracle's solution
+    sols = {}
 
     # ---------------- HBM probe ----------------
     peak_meas = None
     if "probe" in sections:
-        bw = mxs.hbm_probe(ctx, 1 << 30, 5)
+        bw = mxs.hbm_probe(ctx, 4 << 30, 5)   # 4 GiB arrays, far beyond the 256 MB cache
         peak_meas = bw["best_gbs"]
         extra["hbm_probe_gbs"] = {k: round(v, 1) for k, v in bw.items()}
         log("hbm probe", extra["hbm_probe_gbs"])
@@ -271,6 +275,7 @@ def main():
             # columns uniform over all of x: every entry's x load is a cache
             # line of its own, so the random-gather rate bounds the product
             gp = {dt: mxs.gather_probe(ctx, Z.ncols, Z.nnz, vb, 5) for dt, vb in (("f64", 8), ("f32", 4))}
+            gp_slice = {}
             r["gather_probe_per_s"] = {dt: round(v / 1e9, 2) for dt, v in gp.items()}
             for fmt in ("csr", "coo", "hyb", "ell"):
                 for dt in ("f64", "f32"):
@@ -286,9 +291,20 @@ def main():
                          "warm_us": round(t_warm * 1e6, 2), "warm_GBs_cache_assisted": round(nbytes / t_warm / 1e9, 1),
                          "bytes": nbytes}
                     # bound: the x gathers at the probe's rate, or the rest of
-                    # the bytes at the measured HBM rate, whichever is longer
-                    t_g = Z.nnz / gp[dt]
+                    # the bytes at the measured HBM rate, whichever is longer;
+                    # with column panels each XCD gathers from one slice of x,
+                    # so the probe is taken on an x of the slice's size
                     t_b = (nbytes - Z.ncols * vb) / (peak_meas * 1e9) if peak_meas else 0.0
+                    t_g = Z.nnz / gp[dt]
+                    panels = info.get("col_panels", 0) if fmt == "csr" else 0
+                    e["gather_bound_full_x_us"] = round(max(t_g, t_b) * 1e6, 2)
+                    if panels > 1:
+                        key = (dt, panels)
+                        if key not in gp_slice:
+                            gp_slice[key] = mxs.gather_probe(ctx, -(-Z.ncols // panels), Z.nnz,
+                                                             vb, 5)
+                        t_g = Z.nnz / gp_slice[key]
+                        e["col_panels"] = panels
                     e["gather_bound_us"] = round(max(t_g, t_b) * 1e6, 2)
                     e["frac_of_gather_bound"] = round(max(t_g, t_b) / t_cold, 3)
                     if fmt == "ell":
@@ -316,45 +332,54 @@ def main():
         b = torch.zeros(P.n, dtype=torch.float64, device=dev)
         mxs.spmv(ctx, Pm, ones, b)
         xs = torch.zeros_like(b)
-        lat = []
-        for i in range(25):
-            xs.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = mxs.solve(ctx, "cg", Pm, b, xs, tol=1e-10)
-            lat.append(time.perf_counter() - t0)
-        lat = np.array(lat[3:])
-        kr["cg_poisson2d_64"] = {"iters": r.iters, "relres_true": r.relres_true,
-                                 "solves_per_s": round(1.0 / lat.mean(), 1),
-                                 "p50_ms": round(np.percentile(lat, 50) * 1e3, 3),
-                                 "p99_ms": round(np.percentile(lat, 99) * 1e3, 3)}
-        log("cg poisson2d 64", kr["cg_poisson2d_64"])
-        # 3D problems at 128^3
-        # the same with pipelined CG (two launches per iteration)
-        lat = []
-        for i in range(25):
-            xs.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = mxs.solve(ctx, "pipecg", Pm, b, xs, tol=1e-10)
-            lat.append(time.perf_counter() - t0)
-        lat = np.array(lat[3:])
-        kr["pipecg_poisson2d_64"] = {"iters": r.iters, "relres_true": r.relres_true,
-                                     "solves_per_s": round(1.0 / lat.mean(), 1),
-                                     "p50_ms": round(np.percentile(lat, 50) * 1e3, 3),
-                                     "p99_ms": round(np.percentile(lat, 99) * 1e3, 3)}
-        log("pipecg poisson2d 64", kr["pipecg_poisson2d_64"])
+        for solver in ("cg", "pipecg"):
+            lat = []
+            for i in range(25):
+                xs.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = mxs.solve(ctx, solver, Pm, b, xs, tol=1e-10)
+                lat.append(time.perf_counter() - t0)
+            lat = np.array(lat[3:])
+            row = f"{solver}_poisson2d_64"
+            kr[row] = {"iters": r.iters, "relres_true": r.relres_true,
+                       "solves_per_s": round(1.0 / lat.mean(), 1),
+                       "p50_ms": round(np.percentile(lat, 50) * 1e3, 3),
+                       "p99_ms": round(np.percentile(lat, 99) * 1e3, 3)}
+            sols.setdefault("poisson2d_64", {})[("krylov", row)] = xs.cpu().numpy()
+            log(row, kr[row])
+        # 3D problems at 128^3; the product of each matrix is also timed cold
+        # (256 MB cache flushed before each launch) and warm (back to back, as
+        # inside a solver, where the previous iteration leaves part of the
+        # matrix and vectors in the cache)
+        spmv_cw = {}
         for name, gen, solver in (("cg_poisson3d", I.poisson3d, "cg"),
                                   ("pipecg_poisson3d", I.poisson3d, "pipecg"),
                                   ("bicgstab_convdiff3d", I.convdiff3d, "bicgstab"),
                                   ("cgs_convdiff3d", I.convdiff3d, "cgs"),
                                   ("gmres30_convdiff3d", I.convdiff3d, "gmres")):
             Q = gen(N)
+            system = "poisson3d_%d" % N if gen is I.poisson3d else "convdiff3d_%d" % N
             Qm = mxs.Matrix.from_host(ctx, Q)
             xstar = torch.from_numpy(I.uniform_vector(Q.n, I.VECTOR_SEED)).to(dev)
             bq = torch.zeros(Q.n, dtype=torch.float64, device=dev)
             mxs.spmv(ctx, Qm, xstar, bq)
             xq = torch.zeros_like(bq)
+            csr_b = Q.nnz * 12 + 4 * (Q.n + 1) + 16 * Q.n
+            if system not in spmv_cw:
+                yq = torch.zeros_like(bq)
+                fn = lambda Qm=Qm, yq=yq: mxs.spmv(ctx, Qm, xstar, yq)
+                fn()
+                t_cold, _ = timer.time(fn, 10, flush=lambda: mxs.flush_cache(ctx, 1 << 30))
+                t_warm, _ = timer.time(fn, 20)
+                spmv_cw[system] = {
+                    "bytes": csr_b, "csr_kernel": Qm.info()["csr_kernel"],
+                    "cold_us": round(t_cold * 1e6, 2), "cold_GBs": round(csr_b / t_cold / 1e9, 1),
+                    "warm_us": round(t_warm * 1e6, 2),
+                    "warm_GBs_cache_assisted": round(csr_b / t_warm / 1e9, 1)}
+                if peak_meas:
+                    spmv_cw[system]["cold_frac_measured"] = round(csr_b / t_cold / 1e9 / peak_meas, 4)
+                log(system, "spmv cold/warm", spmv_cw[system])
             ts = []
             for rep in range(3):
                 xq.zero_()
@@ -365,7 +390,7 @@ def main():
                 ts.append(time.perf_counter() - t0)
             t = float(np.median(ts))
             err = float(torch.linalg.norm(xq - xstar) / torch.linalg.norm(xstar))
-            csr_b = Q.nnz * 12 + 4 * (Q.n + 1) + 16 * Q.n
+            sols.setdefault(system, {})[("krylov", name)] = xq.cpu().numpy()
             # fixed 1000 iterations (no convergence test can stop it), for
             # GFLOP/s and GB/s under the per-iteration models: CG 2nnz+10n
             # flops and B_csr+64n bytes; BiCGSTAB 4nnz+20n and 2B_csr+144n;
@@ -395,6 +420,10 @@ def main():
                      "frac_spec": round(by * itf / tf / 1e9 / PEAK_HBM_GBS, 4)}
             if peak_meas:
                 fixed["frac_measured"] = round(by * itf / tf / 1e9 / peak_meas, 4)
+                # an iteration re-reads the matrix (217 MB) and the vectors:
+                # part of it is served by the 256 MB cache, so this fraction
+                # is cache-assisted; the cold product gives the HBM figure
+                fixed["cache_assisted"] = True
             kr[name] = {"n": Q.n, "nnz": Q.nnz, "iters": r.iters, "restarts": r.restarts,
                         "relres_true": r.relres_true, "err_vs_xstar": err,
                         "time_s": round(t, 4), "solves_per_s": round(1 / t, 2),
@@ -402,12 +431,13 @@ def main():
                         "spmv_bytes": csr_b, "fixed_1000_iters": fixed}
             log(name, kr[name])
             Qm.close()
+        kr["spmv_cold_vs_warm"] = spmv_cw
         extra["krylov"] = kr
 
     # ---------------- iterative refinement vs plain FP64 CG ----------------
     if "ir" in sections:
         irr = {}
-        for name, gen in (("poisson3d_128", lambda: I.poisson3d(N)),
+        for name, gen in (("poisson3d_%d" % N, lambda: I.poisson3d(N)),
                           ("random_spd_2p20", lambda: I.random_spd(2 ** 20))):
             log("IR", name)
             Q = gen()
@@ -416,66 +446,59 @@ def main():
             bq = torch.zeros(Q.n, dtype=torch.float64, device=dev)
             mxs.spmv(ctx, Qm, xstar, bq)
             xq = torch.zeros_like(bq)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = mxs.solve(ctx, "cg", Qm, bq, xq, tol=1e-10, raise_on_error=False)
-            torch.cuda.synchronize()
-            t_plain = time.perf_counter() - t0
-            x_plain = xq.clone()
             nxs = float(torch.linalg.norm(xstar))
-            e = {"plain_f64_cg": {"iters": r.iters, "status": r.status, "time_s": round(t_plain, 4),
-                                  "relres_true": r.relres_true,
-                                  "err_vs_xstar": float(torch.linalg.norm(xq - xstar)) / nxs}}
+            store = sols.setdefault(name, {})
+
+            def run(label, fn):
+                xq.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = fn()
+                torch.cuda.synchronize()
+                t_ = time.perf_counter() - t0
+                store[("iterative_refinement", label)] = xq.cpu().numpy()
+                return res, t_, float(torch.linalg.norm(xq - xstar)) / nxs
+
+            r, t_plain, err = run("plain_f64_cg", lambda: mxs.solve(
+                ctx, "cg", Qm, bq, xq, tol=1e-10, raise_on_error=False))
+            e = {"plain_f64_cg": {"iters": r.iters, "status": r.status,
+                                  "time_s": round(t_plain, 4), "relres_true": r.relres_true,
+                                  "err_vs_xstar": err}}
             # preconditioned CG (Jacobi; block Jacobi with 8-row blocks)
             pcs = {"jacobi": mxs.Precond(ctx, Qm, "jacobi"),
                    "block8": mxs.Precond(ctx, Qm, "block_jacobi", 8)}
             for pname, P in pcs.items():
-                xq.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                rp_ = mxs.solve(ctx, "cg", Qm, bq, xq, tol=1e-10, raise_on_error=False,
-                                precond=P)
-                torch.cuda.synchronize()
-                t_p = time.perf_counter() - t0
+                rp_, t_p, err = run(f"pcg_{pname}_f64", lambda P=P: mxs.solve(
+                    ctx, "cg", Qm, bq, xq, tol=1e-10, raise_on_error=False, precond=P))
                 e[f"pcg_{pname}_f64"] = {
                     "iters": rp_.iters, "status": rp_.status, "time_s": round(t_p, 4),
                     "relres_true": rp_.relres_true, "speedup_vs_plain": round(t_plain / t_p, 3),
-                    "err_vs_xstar": float(torch.linalg.norm(xq - xstar)) / nxs}
+                    "err_vs_xstar": err}
             for low in ("f32", "f16"):
                 L = Qm.convert("csr", low)
-                xq.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                ri = mxs.solve_ir(ctx, Qm, L, bq, xq, tol=1e-10, raise_on_error=False,
-                                  precond=pcs["jacobi"])
-                torch.cuda.synchronize()
-                t_ir = time.perf_counter() - t0
+                ri, t_ir, err = run(f"ir_{low}_jacobi_inner", lambda L=L: mxs.solve_ir(
+                    ctx, Qm, L, bq, xq, tol=1e-10, raise_on_error=False, precond=pcs["jacobi"]))
                 e[f"ir_{low}_jacobi_inner"] = {
                     "outer": ri.outer_iters, "inner_total": ri.inner_iters_total,
                     "status": ri.status, "relres_true": ri.relres_true,
                     "time_s": round(t_ir, 4), "speedup_vs_plain": round(t_plain / t_ir, 3),
                     "speedup_vs_pcg_jacobi": round(e["pcg_jacobi_f64"]["time_s"] / t_ir, 3),
-                    "err_vs_xstar": float(torch.linalg.norm(xq - xstar)) / nxs}
+                    "err_vs_xstar": err}
                 L.close()
             for P in pcs.values():
                 P.close()
             for low in ("f32", "f16"):
                 for variant in (False, True):
                     L = Qm.convert("csr", low)
-                    xq.zero_()
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    ri = mxs.solve_ir(ctx, Qm, L, bq, xq, tol=1e-10, last_step_variant=variant,
-                                      raise_on_error=False)
-                    torch.cuda.synchronize()
-                    t_ir = time.perf_counter() - t0
-                    err = float(torch.linalg.norm(xq - x_plain) / torch.linalg.norm(x_plain))
-                    e[f"ir_{low}{'_laststep' if variant else ''}"] = {
+                    label = f"ir_{low}{'_laststep' if variant else ''}"
+                    ri, t_ir, err = run(label, lambda L=L, variant=variant: mxs.solve_ir(
+                        ctx, Qm, L, bq, xq, tol=1e-10, last_step_variant=variant,
+                        raise_on_error=False))
+                    e[label] = {
                         "outer": ri.outer_iters, "inner_total": ri.inner_iters_total,
                         "status": ri.status, "relres_true": ri.relres_true,
                         "time_s": round(t_ir, 4), "speedup_vs_plain": round(t_plain / t_ir, 3),
-                        "err_vs_fp64_cg": err,
-                        "err_vs_xstar": float(torch.linalg.norm(xq - xstar)) / nxs}
+                        "err_vs_xstar": err}
                     L.close()
             irr[name] = e
             log(name, json.dumps(e))
@@ -516,17 +539,19 @@ def main():
 
     # ---------------- batched CG serving vs plain CG ----------------
     if "serve" in sections:
-        from paper_2103_10116_amd import serve
-        classes = None
-        if "tune" in sections:
-            from paper_2103_10116_amd import autotune
-            classes = autotune.tune_batch_classes(ctx, log=log)
+        from paper_2103_10116_amd import autotune, serve
+        # threads per system of each size class, timed on this GPU (cached)
+        t0 = time.perf_counter()
+        classes = autotune.tune_batch_classes(ctx, log=log)
+        t_tune = time.perf_counter() - t0
         count = args.serve_requests
         closed = I.serving_stream(count, rate=0.0)
         log(f"generating {count} serving systems")
         systems = serve.build_systems(closed)
         sv = {"requests": count, "tol": 1e-10,
-              "system": "weighted 5-point Laplacian, m x m grid, m ~ U{8..96}, diagonal shift U[0,1]"}
+              "system": "weighted 5-point Laplacian, m x m grid, m ~ U{8..96}, diagonal shift U[0,1]",
+              "classes": [{"max_n": c[0], "threads": c[1]} for c in classes],
+              "tune_s": round(t_tune, 2)}
         bkw = dict(budget_bytes=4 << 30, max_slots=2048, iters_per_step=32, classes=classes,
                    staging_bytes=4 << 30)
         # untimed warm-up of both paths (first launches of their kernels)
@@ -541,6 +566,12 @@ def main():
         rbi = serve.run_batched(ctx, closed, systems, mode="ir32", **bkw)
         sv["batched_ir32_closed"] = rbi.summary()
         log("batched ir32 closed", sv["batched_ir32_closed"])
+        # admission by footprint: a budget far below what the slots could hold
+        # (the systems average ~0.37 MB), so requests wait for memory
+        small = dict(bkw, budget_bytes=256 << 20)
+        rs = serve.run_batched(ctx, closed, systems, **small)
+        sv["batched_closed_budget_256MiB"] = rs.summary()
+        log("batched closed, 256 MiB budget", sv["batched_closed_budget_256MiB"])
         nplain = min(count, args.plain_requests)
         rp = serve.run_plain(ctx, closed[:nplain], systems)
         sv["plain_closed"] = rp.summary()
@@ -553,7 +584,8 @@ def main():
                                         "batched": serve.run_batched(ctx, s_open, systems, **bkw).summary(),
                                         "plain": serve.run_plain(ctx, s_open, systems).summary()}
         log("open stream at 0.5 x plain capacity", sv["open_stream_plain_rate"])
-        # the batched path near its own saturation
+        # the batched path near its own saturation (the plain path cannot
+        # keep up with it: its queue would grow without bound)
         lam_b = 0.9 * mu_b
         s_hi = I.serving_stream(count, rate=lam_b)
         sv["open_stream_batched_rate"] = {"rate_per_s": round(lam_b, 2), "requests": count,
@@ -565,69 +597,158 @@ def main():
     # ---------------- CPU oracle baseline ----------------
     if "cpu" in sections:
         import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        hw = _cpu_info()
+        nt = hw["threads_used"]
         xs64 = I.uniform_vector(A.n, I.VECTOR_SEED)
-        oracle.lib()
-        t0 = time.perf_counter()
-        reps = 0
-        while True:
-            oracle.spmv_csr(A, xs64)
-            reps += 1
-            if time.perf_counter() - t0 > 10.0:
-                break
-        tcpu = (time.perf_counter() - t0) / reps
         b_csr = spmv_bytes("csr", {"nrows": A.n, "nnz": A.nnz}, 8, 8)
-        out["cpu_baseline"] = {"value": round(b_csr / tcpu / 1e9, 3), "unit": "GB/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"{reps} FP64 CSR products of the 27-point {N}^3 matrix "
-                                         f"(accurate row sums, 1 thread), {tcpu:.3f} s each",
-                               "cpu": _cpu_model()}
-        # the oracle's solvers on the same workloads (1 thread), beside the
-        # GPU's numbers: whole solves where they take well under a second,
-        # else a few iterations timed and reported per iteration
-        co = {"cores": 1, "kind": "oracle", "cpu": _cpu_model()}
+
+        def spmv_rate(threads, budget_s):
+            oracle.use_threads(threads)
+            t0 = time.perf_counter()
+            reps = 0
+            while True:
+                oracle.spmv_csr(A, xs64)
+                reps += 1
+                if time.perf_counter() - t0 > budget_s:
+                    break
+            return (time.perf_counter() - t0) / reps, reps
+
+        t1, reps1 = spmv_rate(1, 6.0)
+        tn, repsn = spmv_rate(nt, 3.0)
+        out["cpu_baseline"] = {
+            "value": round(b_csr / tn / 1e9, 3), "unit": "GB/s", "cores": nt, "kind": "oracle",
+            "sample": f"FP64 CSR products of the 27-point {N}^3 matrix (accurate row sums): "
+                      f"{repsn} on {nt} threads ({tn:.4f} s each; OpenMP build of the oracle "
+                      f"source, rows split statically) and {reps1} on 1 thread ({t1:.3f} s each)",
+            "single_thread_value": round(b_csr / t1 / 1e9, 3),
+            "cpu": hw["model"], "physical_cores": hw["physical_cores"],
+            "logical_cpus": hw["logical_cpus"]}
+        log("cpu baseline", out["cpu_baseline"])
+        # the oracle's solvers on the same workloads, 1 thread and all
+        # threads: whole solves where they take well under a second, else a
+        # few iterations timed and reported per iteration
+        co = {"cpu": hw["model"], "physical_cores": hw["physical_cores"], "threads": nt,
+              "kind": "oracle"}
         P2 = I.poisson2d(64)
         b2 = oracle.spmv_csr(P2, np.ones(P2.n))
-        t0 = time.perf_counter()
-        nrep = 0
-        while time.perf_counter() - t0 < 1.0:
-            rc = oracle.cg(P2, b2, tol=1e-10)
-            nrep += 1
-        t1 = (time.perf_counter() - t0) / nrep
-        co["cg_poisson2d_64"] = {"iters": rc.iters, "s_per_solve": round(t1, 5),
-                                 "solves_per_s": round(1.0 / t1, 1)}
-        CD = I.convdiff3d(N)
-        for label, Q, fn, its in (("cg_poisson3d_128", I.poisson3d(N), oracle.cg, 4),
-                                  ("bicgstab_convdiff3d_128", CD, oracle.bicgstab, 3),
-                                  ("gmres30_convdiff3d_128_first_steps", CD, oracle.gmres, 8)):
-            bq = oracle.spmv_csr(Q, I.uniform_vector(Q.n, I.VECTOR_SEED))
+        for th in (1, nt):
+            oracle.use_threads(th)
             t0 = time.perf_counter()
-            rq = fn(Q, bq, tol=1e-10, maxit=its)
-            tq = time.perf_counter() - t0
-            co[label] = {"iters_timed": rq.iters, "s_per_iter": round(tq / max(rq.iters, 1), 4)}
+            nrep = 0
+            while time.perf_counter() - t0 < 1.0:
+                rc = oracle.cg(P2, b2, tol=1e-10)
+                nrep += 1
+            t_ = (time.perf_counter() - t0) / nrep
+            co[f"cg_poisson2d_64_{th}t"] = {"iters": rc.iters, "s_per_solve": round(t_, 5),
+                                            "solves_per_s": round(1.0 / t_, 1)}
+        CD = I.convdiff3d(N)
+        P3 = I.poisson3d(N)
+        for th in (1, nt):
+            oracle.use_threads(th)
+            for label, Q, fn, its in (("cg_poisson3d", P3, oracle.cg, 4),
+                                      ("bicgstab_convdiff3d", CD, oracle.bicgstab, 3),
+                                      ("gmres30_convdiff3d_first_steps", CD, oracle.gmres, 8)):
+                bq = oracle.spmv_csr(Q, I.uniform_vector(Q.n, I.VECTOR_SEED))
+                t0 = time.perf_counter()
+                rq = fn(Q, bq, tol=1e-10, maxit=its)
+                tq = time.perf_counter() - t0
+                co[f"{label}_{N}_{th}t"] = {"iters_timed": rq.iters,
+                                            "s_per_iter": round(tq / max(rq.iters, 1), 4)}
+        # serving: the first 100 requests by the oracle's CG, one system per
+        # thread (the single-thread build; ctypes releases the interpreter
+        # lock during each solve)
+        oracle.use_threads(1)
         reqs = I.serving_stream(100, rate=0.0)
         sysm = [(I.serving_system(int(r.m), r.seed), I.serving_rhs(r.m * r.m, r.seed))
                 for r in reqs]
-        t0 = time.perf_counter()
-        for Aq, bq in sysm:
-            oracle.cg(Aq, bq, tol=1e-10)
-        ts = time.perf_counter() - t0
-        co["serving_cg_first_100"] = {"solves_per_s": round(len(sysm) / ts, 1)}
+        for th in (1, nt):
+            t0 = time.perf_counter()
+            with ThreadPoolExecutor(th) as ex:
+                list(ex.map(lambda ab: oracle.cg(ab[0], ab[1], tol=1e-10), sysm))
+            ts = time.perf_counter() - t0
+            co[f"serving_cg_first_100_{th}t"] = {"solves_per_s": round(len(sysm) / ts, 1)}
         extra["cpu_oracle"] = co
         log("cpu oracle", json.dumps(co))
+        # every solver row against the oracle's own solution of its system
+        oracle.use_threads(nt)
+        refs = attach_oracle_errors(sols, extra, N)
+        oracle.use_threads(1)
+        extra["oracle_reference_solutions"] = refs
+        log("oracle references", json.dumps(refs))
     out["extra"] = extra
     print(json.dumps(out), flush=True)
     M.close()
     ctx.close()
 
 
-def _cpu_model():
+def attach_oracle_errors(sols, extra, N):
+    """Adds err_vs_oracle = ||x - x_oracle|| / ||x_oracle|| to every solver
+    row whose solution is in `sols` ({system: {(section, row): x}}).  The
+    oracle forms b from the same x* itself and solves to 1e-12: CG for the
+    SPD Poisson matrices, BiCGSTAB for the convection-diffusion matrix,
+    Jacobi-preconditioned CG for the random SPD matrix.  Returns what each
+    reference solve took."""
+    import oracle
+    from paper_2103_10116_amd import inputs as I
+    refs = {}
+    for system, rows in sols.items():
+        if system == "poisson2d_64":
+            Q = I.poisson2d(64)
+            ref = oracle.cg(Q, oracle.spmv_csr(Q, np.ones(Q.n)), tol=1e-12)
+            kind = "cg"
+        else:
+            if system.startswith("poisson3d"):
+                Q, kind = I.poisson3d(N), "cg"
+            elif system.startswith("convdiff3d"):
+                Q, kind = I.convdiff3d(N), "bicgstab"
+            else:
+                Q, kind = I.random_spd(2 ** 20), "pcg_jacobi"
+            bq = oracle.spmv_csr(Q, I.uniform_vector(Q.n, I.VECTOR_SEED))
+            if kind == "cg":
+                ref = oracle.cg(Q, bq, tol=1e-12)
+            elif kind == "bicgstab":
+                ref = oracle.bicgstab(Q, bq, tol=1e-12)
+            else:
+                _, Mj = oracle.jacobi(Q)
+                ref = oracle.pcg(Q, bq, Mj, tol=1e-12)
+        nx = float(np.linalg.norm(ref.x))
+        refs[system] = {"solver": kind, "iters": ref.iters, "relres_true": ref.relres_true}
+        for (sec, row), xg in rows.items():
+            tgt = extra[sec][system] if sec == "iterative_refinement" else extra[sec]
+            tgt[row]["err_vs_oracle"] = float(np.linalg.norm(xg - ref.x)) / nx
+    return refs
+
+
+def _cpu_info():
+    """CPU model, physical cores and logical CPUs this process may run on,
+    and the threads the all-core baseline uses (OMP_NUM_THREADS if set,
+    else the physical cores available)."""
+    model, cores = "unknown", set()
+    allowed = os.sched_getaffinity(0)
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+        cpu = phys = core = None
+        for line in list(open("/proc/cpuinfo")) + [""]:
+            if ":" in line:
+                k, v = (t.strip() for t in line.split(":", 1))
+                if k == "processor":
+                    cpu = int(v)
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif k == "model name" and model == "unknown":
+                    model = v
+            elif cpu is not None:
+                if cpu in allowed:
+                    cores.add((phys, core))
+                cpu = phys = core = None
     except OSError:
         pass
-    return "unknown"
+    physical = len(cores) or len(allowed)
+    threads = int(os.environ.get("OMP_NUM_THREADS", physical))
+    return {"model": model, "physical_cores": physical, "logical_cpus": len(allowed),
+            "threads_used": max(1, min(threads, len(allowed)))}
 
 
 if __name__ == "__main__":

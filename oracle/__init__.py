@@ -26,33 +26,68 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with OpenMP: the host baseline's all-core timing only
+# (parity always uses the single-thread build)
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 OK, INVALID_ARG, INVALID_MATRIX, UNSUPPORTED = 0, 1, 2, 3
 NOT_CONVERGED, BREAKDOWN, NONFINITE = 6, 7, 8
 
 
+def _compile(out: str, openmp: bool) -> None:
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(
+        ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
+         *(["-fopenmp"] if openmp else []),
+         "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
+         _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (-O2, no FP contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
-             "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-             _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile liboracle.so with gcc (-O2, no FP contraction, no fast-math),
+    and liboracle_omp.so, the same source with OpenMP (timing only)."""
+    for out, omp in ((_LIB, False), (_LIB_OMP, True)):
+        if force or not os.path.exists(out):
+            _compile(out, omp)
     return _LIB
 
 
 _lib = None
+_libs = {}
+_threads = 1
+
+
+def _load(path, openmp):
+    if path not in _libs:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _compile(path, openmp)
+        L = C.CDLL(path)
+        _declare(L)
+        _libs[path] = L
+    return _libs[path]
+
+
+def use_threads(n: int) -> int:
+    """n == 1: the single-thread parity build (the default); n > 1: the
+    OpenMP build of the same source on n threads, for host-baseline timing
+    (its inner products are summed in another order).  Returns the previous
+    setting."""
+    global _lib, _threads
+    prev = _threads
+    _threads = max(1, int(n))
+    if _threads == 1:
+        _lib = _load(_LIB, False)
+    else:
+        _lib = _load(_LIB_OMP, True)
+        C.CDLL("libgomp.so.1").omp_set_num_threads(_threads)
+    return prev
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        _lib = C.CDLL(_LIB)
-        _declare(_lib)
+        _lib = _load(_LIB, False)
     return _lib
 
 

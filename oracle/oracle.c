@@ -35,6 +35,19 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Timing builds only (-fopenmp, the host baseline): row loops and vector
+ * updates split over threads give the same results as the single thread
+ * (each entry is computed alone); the solvers' inner products are summed in
+ * a different order there.  The parity build has no OpenMP and these are
+ * empty. */
+#ifdef _OPENMP
+#define ORC_PAR_FOR _Pragma("omp parallel for schedule(static)")
+#define ORC_PAR_SUM_S _Pragma("omp parallel for schedule(static) reduction(+:s)")
+#else
+#define ORC_PAR_FOR
+#define ORC_PAR_SUM_S
+#endif
+
 /* ------------------------------------------------------------------------ */
 /* compensated accumulation (Ogita-Rump-Oishi Dot2)                         */
 /* ------------------------------------------------------------------------ */
@@ -338,6 +351,7 @@ int orc_rowscale_f16(int64_t n, const int32_t* rowptr, const double* val,
 void orc_spmv_csr(int64_t n, const int32_t* rowptr, const int32_t* col,
                   const double* val, const double* x, double alpha,
                   double beta, double* y, int mode) {
+  ORC_PAR_FOR
   for (int64_t i = 0; i < n; ++i) {
     double s;
     if (mode == 1) {
@@ -537,6 +551,7 @@ static void matvec(const csr_t* A, const double* x, double* y) {
 /* r = b - A x, each entry accumulated accurately and rounded once */
 static void residual(const csr_t* A, const double* b, const double* x,
                      double* r) {
+  ORC_PAR_FOR
   for (int64_t i = 0; i < A->n; ++i) {
     acc_t a;
     acc_init(&a, b[i]);
@@ -548,6 +563,7 @@ static void residual(const csr_t* A, const double* b, const double* x,
 
 static double dot(int64_t n, const double* a, const double* b) {
   double s = 0.0;
+  ORC_PAR_SUM_S
   for (int64_t i = 0; i < n; ++i) s = s + a[i] * b[i];
   return s;
 }
@@ -581,6 +597,7 @@ int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
   double nb = nrm2(n, b);
   if (!isfinite(nb)) return ORC_NONFINITE;
   if (nb == 0.0) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     return ORC_OK;
   }
@@ -628,7 +645,9 @@ int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
       break;
     }
     double alpha = rho / pq;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
     double rho_new = dot(n, r, r);
     ++it;
@@ -642,6 +661,7 @@ int orc_cg(int64_t n, const int32_t* rowptr, const int32_t* col,
       check = 1;
       continue;
     }
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
     rho = rho_new;
   }
@@ -665,6 +685,7 @@ int orc_pagerank(int64_t n, const int32_t* rowptr, const int32_t* col,
   int64_t* d = (int64_t*)calloc((size_t)n, sizeof(int64_t));
   double* xn = vec(n);
   for (int64_t k = 0; k < rowptr[n]; ++k) d[col[k]]++;
+  ORC_PAR_FOR
   for (int64_t i = 0; i < n; ++i) x[i] = 1.0 / (double)n;
   int status = ORC_NOT_CONVERGED;
   for (int64_t it = 0; it < max_iters; ++it) {
@@ -750,6 +771,7 @@ int orc_block_jacobi(int64_t n, const int32_t* rowptr, const int32_t* col,
 void orc_prec_apply(int64_t n, int kind, int64_t bs, const double* minv,
                     const double* r, double* z) {
   if (kind == 1) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) z[i] = minv[i] * r[i];
     return;
   }
@@ -773,6 +795,7 @@ int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col,
   double nb = nrm2(n, b);
   if (!isfinite(nb)) return ORC_NONFINITE;
   if (nb == 0.0) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     return ORC_OK;
   }
@@ -824,7 +847,9 @@ int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col,
       break;
     }
     double alpha = rho / pq;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
     orc_prec_apply(n, kind, bs, minv, r, z);
     double rho_new = dot(n, r, z);
@@ -836,6 +861,7 @@ int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col,
       continue;
     }
     double beta = rho_new / rho;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
     rho = rho_new;
   }
@@ -860,6 +886,7 @@ int orc_pipecg(int64_t n, const int32_t* rowptr, const int32_t* col,
   double nb = nrm2(n, b);
   if (!isfinite(nb)) return ORC_NONFINITE;
   if (nb == 0.0) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     return ORC_OK;
   }
@@ -934,8 +961,11 @@ int orc_pipecg(int64_t n, const int32_t* rowptr, const int32_t* col,
         p[i] = r[i] + beta * p[i];
       }
     }
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * s[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) w[i] = w[i] - alpha * z[i];
     gamma_old = gamma;
     alpha_old = alpha;
@@ -964,6 +994,7 @@ int orc_cgs(int64_t n, const int32_t* rowptr, const int32_t* col,
   double nb = nrm2(n, b);
   if (!isfinite(nb)) return ORC_NONFINITE;
   if (nb == 0.0) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     return ORC_OK;
   }
@@ -1024,10 +1055,14 @@ int orc_cgs(int64_t n, const int32_t* rowptr, const int32_t* col,
       break;
     }
     double alpha = rho / sigma;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) q[i] = u[i] - alpha * v[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) w[i] = u[i] + q[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * w[i];
     matvec(&A, w, v); /* v = A (u + q) */
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * v[i];
     ++it;
     double nr = nrm2(n, r);
@@ -1042,7 +1077,9 @@ int orc_cgs(int64_t n, const int32_t* rowptr, const int32_t* col,
     }
     double rho_new = dot(n, rh, r);
     double beta = rho_new / rho;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) u[i] = r[i] + beta * q[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) p[i] = u[i] + beta * (q[i] + beta * p[i]);
     rho = rho_new;
   }
@@ -1069,6 +1106,7 @@ int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
   double nb = nrm2(n, b);
   if (!isfinite(nb)) return ORC_NONFINITE;
   if (nb == 0.0) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     return ORC_OK;
   }
@@ -1099,6 +1137,7 @@ int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
     }
     if (restart) {
       memcpy(rh, r, (size_t)n * sizeof(double));
+      ORC_PAR_FOR
       for (int64_t i = 0; i < n; ++i) p[i] = v[i] = 0.0;
       rho = alpha = omega = 1.0;
       restart = 0;
@@ -1119,6 +1158,7 @@ int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
       break;
     }
     double beta = (rho1 / rho) * (alpha / omega);
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
     matvec(&A, p, v);
     double rv = dot(n, rh, v);
@@ -1131,12 +1171,14 @@ int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
       break;
     }
     alpha = rho1 / rv;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
     ++it;
     double ns = nrm2(n, s);
     info->relres_recurrence = ns / base;
     if (ns <= thr) {
       /* half step: the first update already meets the tolerance */
+      ORC_PAR_FOR
       for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
       check = 1;
       continue;
@@ -1152,7 +1194,9 @@ int orc_bicgstab(int64_t n, const int32_t* rowptr, const int32_t* col,
       break;
     }
     omega = dot(n, t, s) / tt;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i] + omega * s[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
     double nr = nrm2(n, r);
     info->relres_recurrence = nr / base;
@@ -1184,6 +1228,7 @@ int orc_gmres(int64_t n, const int32_t* rowptr, const int32_t* col,
   double nb = nrm2(n, b);
   if (!isfinite(nb)) return ORC_NONFINITE;
   if (nb == 0.0) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     return ORC_OK;
   }
@@ -1293,6 +1338,7 @@ typedef struct {
 /* FP32 operator: y_i = sum_j a_ij x_j in float, ascending order; for the
  * FP16 storage y_i = s_i * sum_j float(h_ij) x_j.                         */
 static void low_matvec(const lowmat_t* L, const float* x, float* y) {
+  ORC_PAR_FOR
   for (int64_t i = 0; i < L->n; ++i) {
     float s = 0.0f;
     for (int64_t k = L->rowptr[i]; k < L->rowptr[i + 1]; ++k) {
@@ -1306,6 +1352,7 @@ static void low_matvec(const lowmat_t* L, const float* x, float* y) {
 /* reductions accumulate in double and round once to float */
 static float fdot(int64_t n, const float* a, const float* b) {
   double s = 0.0;
+  ORC_PAR_SUM_S
   for (int64_t i = 0; i < n; ++i) s = s + (double)a[i] * (double)b[i];
   return (float)s;
 }
@@ -1314,8 +1361,10 @@ static float fdot(int64_t n, const float* a, const float* b) {
 static void low_prec_apply(int64_t n, int kind, int64_t bs, const float* minv,
                            const float* r, float* z) {
   if (kind == 0) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) z[i] = r[i];
   } else if (kind == 1) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) z[i] = minv[i] * r[i];
   } else {
     for (int64_t r0 = 0; r0 < n; r0 += bs) {
@@ -1345,6 +1394,7 @@ static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
     r[i] = f[i];
   }
   low_prec_apply(n, pc_kind, bs, minv, r, z);
+  ORC_PAR_FOR
   for (int64_t i = 0; i < n; ++i) p[i] = z[i];
   float rho = fdot(n, r, z);
   float rr = fdot(n, r, r);
@@ -1355,7 +1405,9 @@ static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
     float pq = fdot(n, p, q);
     if (!(pq > 0.0f)) break;
     float alpha = rho / pq;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) d[i] = d[i] + alpha * p[i];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
     low_prec_apply(n, pc_kind, bs, minv, r, z);
     float rho_new = fdot(n, r, z);
@@ -1363,6 +1415,7 @@ static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
     ++it;
     if (sqrtf(rr) <= thr) break;
     float beta = rho_new / rho;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
     rho = rho_new;
   }
@@ -1396,6 +1449,7 @@ int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
   double nb = nrm2(n, b);
   if (!isfinite(nb)) return ORC_NONFINITE;
   if (nb == 0.0) {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     return ORC_OK;
   }
@@ -1418,6 +1472,7 @@ int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
       break;
     }
     double sigma = nr;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) f[i] = (float)(r[i] / sigma);
     double tol = inner_tol;
     if (last_step_variant && relres * inner_tol <= outer_tol) {
@@ -1426,6 +1481,7 @@ int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
     }
     info->inner_iters_total +=
         low_cg(&L, f, d, (float)tol, inner_max, pc_kind, bs, minv32);
+    ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + sigma * (double)d[i];
     info->outer_iters++;
   }

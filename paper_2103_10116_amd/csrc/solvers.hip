@@ -266,6 +266,36 @@ __device__ __forceinline__ void strided4(int64_t n, Load load, Use use) {
   for (; i < n; i += S) use(i, load(i));
 }
 
+// strided4 whose first round of loads is issued before `pre` runs (a
+// kernel's finishing of the previous kernel's partials, whose result the
+// uses need): the reduction's latency overlaps the first loads.
+template <typename Load, typename Pre, typename Use>
+__device__ __forceinline__ void strided4_pre(int64_t n, Load load, Pre pre, Use use) {
+  const int64_t S = (int64_t)gridDim.x * RB;
+  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+  using E = decltype(load(i));
+  E e[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (i + j * S < n) e[j] = load(i + j * S);
+  pre();
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (i + j * S < n) use(i + j * S, e[j]);
+  i += 4 * S;
+  for (; i + 3 * S < n; i += 4 * S) {
+    const auto e0 = load(i);
+    const auto e1 = load(i + S);
+    const auto e2 = load(i + 2 * S);
+    const auto e3 = load(i + 3 * S);
+    use(i, e0);
+    use(i + S, e1);
+    use(i + 2 * S, e2);
+    use(i + 3 * S, e3);
+  }
+  for (; i < n; i += S) use(i, load(i));
+}
+
 // ---------------------------------------------------------------------------
 // generic reductions
 // ---------------------------------------------------------------------------
@@ -333,25 +363,32 @@ __global__ __launch_bounds__(RB) void k_cg_r(int64_t n, T* __restrict__ r,
                                              int64_t k) {
   if (st->done) return;
   double pq[1];
-  finish_wide<1>(pa, ga, pq);
-  if (!isfinite(pq[0]) || pq[0] <= 0.0) {
-    if (lead()) {
-      st->done = isfinite(pq[0]) ? ST_BREAKDOWN : ST_NONFINITE;
-      st->halt = k + 1;
-    }
-    return;
-  }
-  const double alpha = st->rho[par] / pq[0];
-  if (lead()) st->alpha = alpha;
-  const T a = (T)alpha;
+  bool broke = false;
+  T a = 0;
   double acc[1] = {0.0};
-  strided4(
+  strided4_pre(
       n, [&](int64_t i) { return Pack<T, 2>{{r[i], q[i]}}; },
+      [&]() {
+        finish_wide<1>(pa, ga, pq);
+        broke = !isfinite(pq[0]) || pq[0] <= 0.0;
+        if (broke) {
+          if (lead()) {
+            st->done = isfinite(pq[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+            st->halt = k + 1;
+          }
+          return;
+        }
+        const double alpha = st->rho[par] / pq[0];
+        if (lead()) st->alpha = alpha;
+        a = (T)alpha;
+      },
       [&](int64_t i, const Pack<T, 2>& e) {
+        if (broke) return;
         const T ri = e.v[0] - a * e.v[1];
         r[i] = ri;
         acc[0] += (double)ri * (double)ri;
       });
+  if (broke) return;
   block_partials<1>(acc, pb);
 }
 

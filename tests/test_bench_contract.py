@@ -4,6 +4,8 @@ import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402  (importing it runs nothing: main() is guarded)
 
 
 def test_more_than_one_gpu_is_refused():
@@ -48,3 +50,37 @@ def test_traffic_lookup_finds_the_step_kernels():
     for dt in ("f64", "f32"):
         assert bench.measured_traffic("coo", dt, coo, 27), dt
         assert bench.measured_traffic("ell", dt, ell, 27), dt
+
+
+def test_oracle_errors_attach_to_every_solver_row():
+    """The CPU leg's err_vs_oracle: each stored GPU solution gets its
+    distance to the oracle's solution of the same system (here a small grid,
+    with the oracle's own 1e-10 solutions standing in for GPU results)."""
+    import numpy as np
+    import oracle
+    from paper_2103_10116_amd import inputs as I
+    N = 10
+    P = I.poisson3d(N)
+    b = oracle.spmv_csr(P, I.uniform_vector(P.n, I.VECTOR_SEED))
+    x_cg = oracle.cg(P, b, tol=1e-10).x
+    C = I.convdiff3d(N)
+    bc = oracle.spmv_csr(C, I.uniform_vector(C.n, I.VECTOR_SEED))
+    x_bi = oracle.bicgstab(C, bc, tol=1e-10).x
+    sols = {f"poisson3d_{N}": {("krylov", "cg_poisson3d"): x_cg,
+                               ("iterative_refinement", "plain_f64_cg"): x_cg + 1e-3},
+            f"convdiff3d_{N}": {("krylov", "bicgstab_convdiff3d"): x_bi}}
+    extra = {"krylov": {"cg_poisson3d": {}, "bicgstab_convdiff3d": {}},
+             "iterative_refinement": {f"poisson3d_{N}": {"plain_f64_cg": {}}}}
+    refs = bench.attach_oracle_errors(sols, extra, N)
+    assert refs[f"poisson3d_{N}"]["solver"] == "cg"
+    assert refs[f"convdiff3d_{N}"]["relres_true"] <= 1e-12 * (1 + 1e-6)
+    assert extra["krylov"]["cg_poisson3d"]["err_vs_oracle"] < 1e-7
+    assert extra["krylov"]["bicgstab_convdiff3d"]["err_vs_oracle"] < 1e-7
+    e = extra["iterative_refinement"][f"poisson3d_{N}"]["plain_f64_cg"]["err_vs_oracle"]
+    assert abs(e - 1e-3 * np.sqrt(P.n) / np.linalg.norm(x_cg)) < 1e-6
+
+
+def test_cpu_info():
+    info = bench._cpu_info()
+    assert info["physical_cores"] >= 1 and 1 <= info["threads_used"] <= info["logical_cpus"]
+    assert isinstance(info["model"], str)

@@ -365,6 +365,53 @@ def test_ir_refuses_other_value_types(env):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("system", ["poisson3d_128", "random_spd_2p20"])
+def test_full_size_ir(env, orc, system):
+    """Mixed-precision refinement at full size (FP32 and row-scaled FP16
+    storage, literal and last-step inner tolerance): the oracle's FP64
+    residual of every result meets 1e-10, and its distance to the oracle's
+    FP64 solution of the same system (single thread: CG on the Poisson
+    matrix, Jacobi-preconditioned CG on the random SPD one) stays within
+    what the two residuals allow, ||x - x_o|| <= (||r|| + ||r_o||) /
+    lambda_min, lambda_min from the closed form (Poisson) or Gershgorin
+    (diagonal 1.1 x the off-diagonal row sum: lambda_min >= 0.1 x the
+    smallest such sum)."""
+    mxs, ctx, torch = env
+    if system == "poisson3d_128":
+        A = I.poisson3d(128)
+        lam_min = 3 * (2 - 2 * np.cos(np.pi / 129))
+    else:
+        A = I.random_spd(2 ** 20)
+        rows = np.repeat(np.arange(A.n), A.row_lengths())
+        off = A.col != rows
+        rsum = np.bincount(rows[off], weights=np.abs(A.val[off]), minlength=A.n)
+        lam_min = float(np.min(np.where(rsum > 0, 0.1 * rsum, 1.0)))
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, I.VECTOR_SEED))
+    nb = np.linalg.norm(b)
+    if system == "poisson3d_128":
+        ref = orc.cg(A, b, tol=1e-10)
+    else:
+        ref = orc.pcg(A, b, orc.jacobi(A)[1], tol=1e-10)
+    assert ref.status == orc.OK
+    nxo = np.linalg.norm(ref.x)
+    M = mxs.Matrix.from_host(ctx, A)
+    bd = _dev(torch, b)
+    for low in ("f32", "f16"):
+        L = M.convert("csr", low)
+        for variant in (False, True):
+            x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            r = mxs.solve_ir(ctx, M, L, bd, x, tol=1e-10, last_step_variant=variant)
+            xh = x.cpu().numpy()
+            assert r.status == mxs.OK, (low, variant, r)
+            rel = orc.true_relres(A, b, xh)
+            assert rel <= 1e-10 + _eval_slack(orc, A, b, xh), (low, variant, rel)
+            err = np.linalg.norm(xh - ref.x) / nxo
+            bound = (rel + ref.relres_true) * nb / lam_min / nxo
+            assert err <= 1.01 * bound, (low, variant, err, bound)
+        L.close()
+
+
+@pytest.mark.slow
 def test_full_size_krylov(env, orc):
     """The 128^3 solver workloads: CG on the 7-point Poisson matrix,
     BiCGSTAB and GMRES(30) on the upwind convection-diffusion matrix."""

@@ -420,3 +420,24 @@ def test_lu_vs_numpy(orc):
         assert np.linalg.norm(x - xr) <= 1e-12 * np.linalg.cond(M) * np.linalg.norm(xr)
     st, _ = orc.lu_solve(np.zeros((3, 3)), np.ones(3))
     assert st == orc.BREAKDOWN
+
+
+def test_openmp_timing_build_matches(orc):
+    """The OpenMP build of the same source (host-baseline timing only) gives
+    the single-thread build's products bit for bit (rows are independent),
+    and its CG, whose inner products are summed in another order, converges
+    on the same system to the same tolerance."""
+    A = I.stencil27(12)
+    x = I.uniform_vector(A.n, 5)
+    y1 = orc.spmv_csr(A, x)
+    b = orc.spmv_csr(A, np.ones(A.n))
+    r1 = orc.cg(A, b, tol=1e-10)
+    prev = orc.use_threads(4)
+    try:
+        assert np.array_equal(orc.spmv_csr(A, x).view(np.uint64), y1.view(np.uint64))
+        r4 = orc.cg(A, b, tol=1e-10)
+        assert r4.status == orc.OK and r4.relres_true <= 1e-10 * (1 + 1e-6)
+        assert abs(r4.iters - r1.iters) <= 2
+    finally:
+        orc.use_threads(prev)
+    assert orc.lib() is orc._libs[orc._LIB]
