@@ -67,8 +67,10 @@ def tune_batch_classes(ctx, bounds=CLASS_BOUNDS, per_class=128, tol=1e-10, cache
         for blk in BLOCKS:
             if (mx + blk - 1) // blk > 16:
                 continue
-            classes = [(b_, blk if b_ == mx else 256, per_class if b_ == mx else 1)
-                       for b_ in bounds]
+            # the other classes get one slot each, on the fewest threads
+            # that keep their rows per thread within the engine's 16
+            classes = [(b_, blk if b_ == mx else next(k for k in BLOCKS if -(-b_ // k) <= 16),
+                        per_class if b_ == mx else 1) for b_ in bounds]
             B = mxs.Batch(ctx, 1 << 30, sum(c[2] for c in classes), 32, classes,
                           staging_bytes=64 << 20)
             for A, b in zip(systems, rhs):

@@ -71,3 +71,16 @@ def test_tune_batch_classes(tmp_path):
     assert B.poll(t, A.n)[0] == mxs.OK
     B.close()
     ctx.close()
+
+
+def test_tune_batch_classes_default_bounds(tmp_path):
+    """The serving bench's call: every default size class (up to 10240 rows,
+    whose other classes need 512 or 1024 threads to stay within 16 rows a
+    thread) is timed and a valid shape is returned for each."""
+    from paper_2103_10116_amd import autotune, mxs
+    ctx = mxs.Context(0)
+    classes = autotune.tune_batch_classes(ctx, per_class=4, cache=str(tmp_path / "t.json"))
+    assert [c[0] for c in classes] == list(autotune.CLASS_BOUNDS)
+    assert all(c[1] in autotune.BLOCKS and -(-c[0] // c[1]) <= 16 for c in classes)
+    mxs.Batch(ctx, 64 << 20, 8, classes=classes).close()
+    ctx.close()
