@@ -2,14 +2,23 @@
 
   python -m paper_2103_10116_amd.profile_summary stats <kernel_trace.csv> <out.md> "<command>"
   python -m paper_2103_10116_amd.profile_summary traffic <fetch_counter.csv> \
-      <write_counter.csv> <out.txt> "<command>"
+      <write_counter.csv> <out.txt> "<command>" [probe_bytes]
+  python -m paper_2103_10116_amd.profile_summary counters <out.txt> "<command>" \
+      <pass1.csv> [<pass2.csv> ...]
 
 `stats` lists every kernel (grouped by name and grid size) with its call
 count and mean / median duration.  `traffic` records FETCH_SIZE and
 WRITE_SIZE per dispatch (KiB) for the SpMV kernels, the scale factors
-measured on the HBM probe's copy kernel (1 GiB read + 1 GiB written), and
-the SHA-256 of spmv.hip at measurement time, so that a later reader can tell
-whether the counters still describe the current kernels.
+measured on the HBM probe's copy kernel (it reads and writes probe_bytes,
+the probe's array size), and the SHA-256 of spmv.hip at measurement time, so that a later reader can tell
+whether the counters still describe the current kernels.  `counters` merges
+the passes of one workload (one counter set per run) into one table per
+kernel and grid, with the ratios derived from them: L2 hit rate, mean
+latency of the vector cache's L2 reads and of the L2's reads beyond it (by
+Little's law from the accumulated in-flight level), the share of those that
+went to DRAM, resident waves per CU, and the shares of time the address unit
+was stalled by the vector cache and the vector cache waited on pending
+misses.
 """
 from __future__ import annotations
 
@@ -67,17 +76,21 @@ def _counters(path):
     return {k: sorted(v)[len(v) // 2] for k, v in agg.items()}
 
 
-def traffic(fetch_csv: str, write_csv: str, out: str, command: str) -> None:
+def traffic(fetch_csv: str, write_csv: str, out: str, command: str,
+            probe_bytes: int = 1 << 30) -> None:
+    """probe_bytes: the array size of the probe run in the same command (its
+    copy kernel reads and writes that many bytes)."""
     fe = _counters(fetch_csv)
     wr = _counters(write_csv)
     copy = [k for k in fe if k[0] == "k_probe_copy1"]
-    gib_kib = float(1 << 20)
-    fscale = gib_kib / fe[copy[0]] if copy else 1.0
-    wscale = gib_kib / wr[copy[0]] if copy else 1.0
+    probe_kib = float(probe_bytes) / 1024.0
+    fscale = probe_kib / fe[copy[0]] if copy else 1.0
+    wscale = probe_kib / wr[copy[0]] if copy else 1.0
     lines = ["# HBM traffic per dispatch from rocprofv3 --pmc (median over dispatches)",
              f"# command (FETCH_SIZE run; the WRITE_SIZE run is the same with --pmc WRITE_SIZE):",
              f"#   {command}",
-             "# scale factors from the probe's copy kernel (1 GiB read, 1 GiB written):",
+             f"# scale factors from the probe's copy kernel ({probe_bytes / 2**30:g} GiB read, "
+             f"{probe_bytes / 2**30:g} GiB written):",
              f"fetch_scale {fscale:.4f}", f"write_scale {wscale:.4f}",
              f"spmv_source_sha256 {spmv_source_sha()}",
              "# kernel grid fetch_kib write_kib scaled_bytes"]
@@ -90,6 +103,66 @@ def traffic(fetch_csv: str, write_csv: str, out: str, command: str) -> None:
         w_ = wr.get(k, 0.0)
         total = (f_ * fscale + w_ * wscale) * 1024.0
         lines.append(f"{name.replace(' ', '')} {grid} {f_:.1f} {w_:.1f} {total:.0f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _counters_all(paths):
+    """{(kernel, grid): {counter: median over dispatches}} over several runs."""
+    out = collections.defaultdict(dict)
+    for path in paths:
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            agg[(_short(r["Kernel_Name"]), int(r["Grid_Size"]), r["Counter_Name"])].append(
+                float(r["Counter_Value"]))
+        for (k, g, c), v in agg.items():
+            out[(k, g)][c] = sorted(v)[len(v) // 2]
+    return out
+
+
+def _derived(c: dict, num_cu: int = 256) -> dict:
+    d = {}
+    if "TCC_HIT_sum" in c and "TCC_MISS_sum" in c:
+        t = c["TCC_HIT_sum"] + c["TCC_MISS_sum"]
+        d["l2_hit_rate"] = c["TCC_HIT_sum"] / t if t else 0.0
+    if c.get("TCP_TCC_READ_REQ_sum"):
+        if "TCP_TCC_READ_REQ_LATENCY_sum" in c:
+            d["l2_read_latency_cycles"] = c["TCP_TCC_READ_REQ_LATENCY_sum"] / c["TCP_TCC_READ_REQ_sum"]
+    if c.get("TCC_EA0_RDREQ_sum"):
+        if "TCC_EA0_RDREQ_LEVEL_sum" in c:
+            d["beyond_l2_read_latency_cycles"] = c["TCC_EA0_RDREQ_LEVEL_sum"] / c["TCC_EA0_RDREQ_sum"]
+        if "TCC_EA0_RDREQ_DRAM_sum" in c:
+            d["beyond_l2_reads_to_dram"] = c["TCC_EA0_RDREQ_DRAM_sum"] / c["TCC_EA0_RDREQ_sum"]
+    busy = c.get("GRBM_GUI_ACTIVE")
+    if busy:
+        xcd = busy / 8.0  # the GUI-active count is summed over the 8 XCDs
+        if "SQ_WAVE_CYCLES" in c:
+            # wave-cycles are counted in units of 4 cycles
+            d["resident_waves_per_cu"] = 4.0 * c["SQ_WAVE_CYCLES"] / (xcd * num_cu)
+        if "SQ_WAIT_INST_ANY" in c and c.get("SQ_WAVE_CYCLES"):
+            d["wave_time_waiting"] = c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"]
+        if "TA_ADDR_STALLED_BY_TC_CYCLES_sum" in c:
+            d["ta_stalled_by_vector_cache"] = c["TA_ADDR_STALLED_BY_TC_CYCLES_sum"] / num_cu / xcd
+        if "TCP_PENDING_STALL_CYCLES_sum" in c:
+            d["vector_cache_pending_stall"] = c["TCP_PENDING_STALL_CYCLES_sum"] / num_cu / xcd
+        if "TA_BUSY_avr" in c:
+            d["ta_busy"] = c["TA_BUSY_avr"] / xcd
+    return d
+
+
+def counters(out: str, command: str, paths, prefixes=("k_",)) -> None:
+    table = _counters_all(paths)
+    lines = ["# rocprofv3 --pmc counters per dispatch (median over dispatches), one pass per run",
+             f"# command (each pass: --pmc <its counters>): {command}",
+             f"# spmv_source_sha256 {spmv_source_sha()}", ""]
+    for (name, grid), c in sorted(table.items()):
+        if not name.startswith(tuple(prefixes)):
+            continue
+        lines.append(f"## {name.replace(' ', '')} grid {grid}")
+        for k in sorted(c):
+            lines.append(f"  {k} {c[k]:.6g}")
+        for k, v in _derived(c).items():
+            lines.append(f"  = {k} {v:.4g}")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -116,6 +189,9 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5],
+                int(sys.argv[6]) if len(sys.argv) > 6 else 1 << 30)
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], sys.argv[4:])
     else:
         raise SystemExit(__doc__)

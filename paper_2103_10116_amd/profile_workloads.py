@@ -16,6 +16,8 @@ cached beyond L2 residue):
              cold and then warm (the cache's share of in-solver products)
   panels     the s = 1.79 power-law matrix, merge-path CSR FP64 and FP32 with
              1, 2 and 4 column panels, cold
+  probe      the HBM probe (read, copy, triad on 1 GiB arrays): the streaming
+             kernels' counters beside the products'
 
 Prints one line per product with the mean event-timed duration, so a counter
 run's per-dispatch figures can be matched to launches.
@@ -100,6 +102,9 @@ def main():
                 run(label, P, [("csr", "f64")], True)
                 run(label, P, [("csr", "f64")], False)
                 P.close()
+        elif w == "probe":
+            bw = mxs.hbm_probe(ctx, 1 << 30, 2)
+            print("probe", {k: round(v, 1) for k, v in bw.items()}, flush=True)
         elif w == "panels":
             Z = mxs.Matrix.from_host(ctx, I.zipf_random(2 ** 20, 1.79, 4096))
             for p in (1, 2, 4):

@@ -18,7 +18,8 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_summary_parses():
     """The committed PMC summary parses into (kernel, grid) -> bytes and holds
-    the probe's copy kernel, whose scaled traffic is its 2 GiB."""
+    the probe's copy kernel, whose scaled traffic is the 4 GiB it reads plus
+    the 4 GiB it writes."""
     sys.path.insert(0, ROOT)
     from paper_2103_10116_amd import profile_summary
     path = os.path.join(ROOT, "profiles", "spmv_stencil27_128_traffic.txt")
@@ -29,7 +30,7 @@ def test_traffic_summary_parses():
             rows[(p[0], int(p[1]))] = float(p[4])
     assert rows
     copy = [v for (k, _), v in rows.items() if k == "k_probe_copy1"]
-    assert copy and abs(copy[0] - 2.0 * (1 << 30)) / (1 << 30) < 1e-3
+    assert copy and abs(copy[0] - 8.0 * (1 << 30)) / (1 << 30) < 1e-3
     assert callable(profile_summary.load_traffic)
 
 
