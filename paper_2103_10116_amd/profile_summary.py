@@ -8,7 +8,7 @@
 
 `stats` lists every kernel (grouped by name and grid size) with its call
 count and mean / median duration.  `traffic` records FETCH_SIZE and
-WRITE_SIZE per dispatch (KiB) for the SpMV kernels, the scale factors
+WRITE_SIZE per dispatch (KiB) for the SpMV and CG kernels, the scale factors
 measured on the HBM probe's copy kernel (it reads and writes probe_bytes,
 the probe's array size), and the SHA-256 of spmv.hip at measurement time, so that a later reader can tell
 whether the counters still describe the current kernels.  `counters` merges
@@ -43,9 +43,10 @@ def _short(name: str) -> str:
 
 
 def stats(trace_csv: str, out: str, command: str, top: int = 30,
-          always=("k_csr", "k_coo", "k_ell")) -> None:
+          always=("k_csr", "k_coo", "k_ell", "k_cg")) -> None:
     """Per-kernel summary: the `top` kernel/grid pairs by total time, then
-    every SpMV kernel (names starting with one of `always`) not among them."""
+    every SpMV or CG kernel (names starting with one of `always`) not among
+    them."""
     rows = list(csv.DictReader(open(trace_csv)))
     agg = collections.defaultdict(list)
     for r in rows:
@@ -96,8 +97,7 @@ def traffic(fetch_csv: str, write_csv: str, out: str, command: str,
              "# kernel grid fetch_kib write_kib scaled_bytes"]
     for k in sorted(fe):
         name, grid = k
-        if not (name.startswith("k_csr") or name.startswith("k_coo") or name.startswith("k_ell")
-                or name.startswith("k_probe")):
+        if not name.startswith(("k_csr", "k_coo", "k_ell", "k_panel", "k_cg", "k_probe")):
             continue
         f_ = fe[k]
         w_ = wr.get(k, 0.0)

@@ -18,9 +18,13 @@ cached beyond L2 residue):
              1, 2 and 4 column panels, cold
   probe      the HBM probe (read, copy, triad on 1 GiB arrays): the streaming
              kernels' counters beside the products'
+  cg7        CG iterations without a stopping test (tolerance 0, 200 steps)
+             on the 7-point Poisson 128^3 in FP64, then the same count as the
+             FP32 inner solve of one refinement step
+  cgspd      the same FP64 CG iterations on the n = 2^20 random SPD matrix
 
-Prints one line per product with the mean event-timed duration, so a counter
-run's per-dispatch figures can be matched to launches.
+Prints one line per product (per solve for `cg`) with the mean event-timed
+duration, so a counter run's per-dispatch figures can be matched to launches.
 """
 from __future__ import annotations
 
@@ -102,6 +106,33 @@ def main():
                 run(label, P, [("csr", "f64")], True)
                 run(label, P, [("csr", "f64")], False)
                 P.close()
+        elif w in ("cg7", "cgspd"):
+            steps = 200
+            label = "poisson3d_128" if w == "cg7" else "random_spd"
+            P = mxs.Matrix.from_host(ctx, I.poisson3d(128) if w == "cg7"
+                                     else I.random_spd(2 ** 20))
+            b = torch.from_numpy(I.uniform_vector(P.n, I.VECTOR_SEED)).to(dev)
+            x = torch.zeros_like(b)
+            solve = lambda: mxs.solve(ctx, "cg", P, b, x.zero_(), tol=0.0,  # noqa: E731
+                                      max_iters=steps, raise_on_error=False)
+            solve()
+            torch.cuda.synchronize()
+            us = _time(torch, solve, args.reps)
+            print(f"{label} cg f64: {us / steps:.2f} us per iteration", flush=True)
+            if w == "cg7":
+                L = P.convert("csr", "f32")
+                # one outer step whose inner FP32 CG runs all its steps (an
+                # inner tolerance it cannot reach)
+                ir = lambda: mxs.solve_ir(ctx, P, L, b, x.zero_(), tol=1e-30,  # noqa: E731
+                                          outer_max=1, inner_tol=1e-30, inner_max=steps,
+                                          raise_on_error=False)
+                ir()
+                torch.cuda.synchronize()
+                us = _time(torch, ir, args.reps)
+                print(f"{label} refinement f32 inner: {us / steps:.2f} us per inner "
+                      f"iteration (with one outer step)", flush=True)
+                L.close()
+            P.close()
         elif w == "probe":
             bw = mxs.hbm_probe(ctx, 1 << 30, 2)
             print("probe", {k: round(v, 1) for k, v in bw.items()}, flush=True)

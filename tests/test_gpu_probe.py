@@ -15,10 +15,13 @@ def env():
 
 
 def test_hbm_probe(env):
+    """4 GiB arrays, 16 times the 256 MB Infinity Cache: every figure is an
+    HBM rate, so none can pass the 8 TB/s peak, and a working probe reaches
+    at least a third of it."""
     mxs, ctx = env
-    r = mxs.hbm_probe(ctx, 256 << 20, 2)
+    r = mxs.hbm_probe(ctx, 4 << 30, 2)
     for k in ("read_gbs", "copy_gbs", "triad_gbs"):
-        assert math.isfinite(r[k]) and 100.0 < r[k] < 20000.0, r
+        assert math.isfinite(r[k]) and 8000.0 / 3 < r[k] <= 8000.0, r
     assert r["best_gbs"] == max(r["read_gbs"], r["copy_gbs"], r["triad_gbs"])
 
 
