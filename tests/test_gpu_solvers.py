@@ -161,9 +161,11 @@ def test_cg_three_launch_iteration(env, orc, case):
     own launches (rows-from-LDS CSR, merge path over column panels) and on
     one that does not (COO, with a separate reduction): the oracle's
     residual meets 1e-10 and the iterations stay within 3 (or 10%) of the
-    oracle's CG; after max_iters = 3 the iterate equals three steps of the oracle's
-    CG (every block applied the last x update), and a breakdown at the
-    first step leaves x untouched."""
+    oracle's CG; after max_iters = 3 the iterate equals three steps of the
+    oracle's CG (every block applied the last x update); a tolerance below
+    the attainable accuracy restarts CG from the true residual the allowed
+    three times and then stops with the iterate at that accuracy; and a
+    breakdown at the first step leaves x untouched."""
     mxs, ctx, torch = env
     kind, fmt, opts = _DOT_CASES[case]
     A = I.poisson3d(24) if kind == "poisson3d" else I.random_spd(20000, seed=26)
@@ -186,6 +188,12 @@ def test_cg_three_launch_iteration(env, orc, case):
     assert r.status == mxs.NOT_CONVERGED and r.iters == 3
     ref3 = orc.cg(A, b, tol=1e-10, maxit=3).x
     assert np.linalg.norm(x.cpu().numpy() - ref3) <= 1e-12 * np.linalg.norm(ref3)
+    # residual replacements: each restart begins a new recurrence (beta = 0)
+    x = _dev(torch, np.zeros(A.n))
+    r = mxs.solve(ctx, "cg", B, _dev(torch, b), x, tol=1e-17, max_iters=20000,
+                  raise_on_error=False)
+    assert r.status == mxs.NOT_CONVERGED and r.replacements == 3, r
+    assert orc.true_relres(A, b, x.cpu().numpy()) <= 1e-12
     # indefinite diagonal of the same size: p.Ap < 0 at the first step
     dv = np.where(np.arange(A.n) % 2 == 0, 1.0, -2.0)
     D = I.CSRMatrix(A.n, A.n, np.arange(A.n + 1, dtype=np.int32),
