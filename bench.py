@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sections", default="probe,spmv,zipf,krylov,ir,pagerank,serve,cpu")
+    ap.add_argument("--sections", default="probe,spmv,tune,zipf,krylov,ir,pagerank,serve,cpu")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--plain-requests", type=int, default=10000)
     ap.add_argument("--grid", type=int, default=128, help="stencil grid side (128 = full size)")
@@ -255,10 +255,56 @@ def main():
             Bz.close()
     Mz.close()
     extra["stencil27_complex"] = cx
+    # the byte rule makes the hybrid all ELL on this matrix (K_h = 27); a
+    # forced width of 20 measures its COO part at full size (7 entries of
+    # every interior row)
+    hs = {}
+    for dt in ("f64", "f32"):
+        vb = 8 if dt == "f64" else 4
+        Bh = M.convert("hyb", dt, ell_width=20)
+        inf = Bh.info()
+        nbh = spmv_bytes("hyb", inf, vb, vb)
+        fn = lambda Bh=Bh, dt=dt: mxs.spmv(ctx, Bh, xd[dt], yd[dt])
+        for _ in range(args.warmup):
+            fn()
+        t, _ = timer.time(fn, max(args.steps, 10))
+        hs[f"hyb_w20_{dt}"] = {"us": round(t * 1e6, 2), "GBs": round(nbh / t / 1e9, 1),
+                               "bytes": nbh, "ell_width": inf["ell_width"],
+                               "coo_nnz": inf["coo_nnz"]}
+        if peak_meas:
+            hs[f"hyb_w20_{dt}"]["frac_measured"] = round(nbh / t / 1e9 / peak_meas, 4)
+        log(f"stencil27 hyb (width 20) {dt}: {t*1e6:.1f} us  {nbh/t/1e9:.0f} GB/s")
+        Bh.close()
+    extra["stencil27_hyb_forced_width"] = hs
     for k in list(mats):
         if k != ("csr", "f64"):
             mats[k].close()
     del mats
+
+    # ---------------- the SpMV autotuner against AUTO on the same matrix ------
+    if "tune" in sections:
+        from paper_2103_10116_amd import autotune
+        tuned = {}
+        for fmt in ("csr", "coo"):
+            for dt in ("f64", "f32"):
+                opts = autotune.tune_spmv(ctx, M, dt, fmt=fmt, refresh=True)
+                row = {"tuned_opts": opts}
+                for label, o in (("auto", {}), ("tuned", opts)):
+                    B = M.convert(fmt, dt, **o)
+                    fn = lambda B=B, dt=dt: mxs.spmv(ctx, B, xd[dt], yd[dt])
+                    for _ in range(args.warmup):
+                        fn()
+                    t, _ = timer.time(fn, max(args.steps, 10))
+                    row[f"{label}_us"] = round(t * 1e6, 2)
+                    row[f"{label}_kernel"] = {k: B.info()[k] for k in
+                                              ("csr_kernel", "coo_kernel", "block_nnz",
+                                               "lanes_per_row", "waves_per_group")}
+                    B.close()
+                row["tuned_over_auto"] = round(row["auto_us"] / row["tuned_us"], 3)
+                tuned[f"{fmt}_{dt}"] = row
+                log(f"autotune stencil27 {fmt} {dt}: auto {row['auto_us']} us, tuned "
+                    f"{row['tuned_us']} us {opts}")
+        extra["stencil27_spmv_autotune"] = tuned
 
     # ---------------- power-law matrices, cold (MALL flushed) ----------------
     if "zipf" in sections:

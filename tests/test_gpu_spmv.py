@@ -561,12 +561,18 @@ def test_spmv_full_size(env, orc, which):
     cases = [("csr", {}), ("csr", {"csr_kernel": "merge", "col_panels": 1}),
              ("csr", {"csr_kernel": "merge", "col_panels": 8}), ("coo", {"coo_kernel": "lds"}),
              ("coo", {"coo_kernel": "runs"}), ("ell", {}), ("hyb", {})]
+    if which == "stencil27_128":
+        # the byte rule makes the hybrid all ELL here (K_h = 27): a forced
+        # width of 20 sends 7 entries of every interior row to its COO part
+        cases.append(("hyb", {"ell_width": 20}))
     for fmt, opts in cases:
         if fmt == "ell" and which == "zipf_2p20_m16":
             continue  # the same 4096-wide padded layout as zipf_2p20 (51.5 GB in FP64)
         B = M.convert(fmt, "f64", **opts)
         if fmt == "csr" and not opts and which != "stencil27_128":
             assert B.info()["col_panels"] == 4   # x of 8 MiB: slices of 2 MiB
+        if "ell_width" in opts:
+            assert B.info()["ell_width"] == 20 and B.info()["coo_nnz"] > 7 * 120 ** 3
         y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         mxs.spmv(ctx, B, _dev(torch, x), y)
         _check(y.cpu().numpy(), ref, scale, 1e-13)
