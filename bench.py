@@ -24,6 +24,9 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the all-core host baseline keeps its OpenMP threads next to each other;
+# set before any OpenMP runtime reads the environment
+os.environ.setdefault("OMP_PROC_BIND", "close")
 
 METRIC = "SpMV GB/s & % HBM roofline; CG solves/s + p99 latency, batched vs plain"
 PEAK_HBM_GBS = 8000.0
@@ -669,6 +672,7 @@ def main():
                       f"source, rows split statically) and {reps1} on 1 thread ({t1:.3f} s each)",
             "single_thread_value": round(b_csr / t1 / 1e9, 3),
             "cpu": hw["model"], "physical_cores": hw["physical_cores"],
+            "omp_proc_bind": os.environ.get("OMP_PROC_BIND"),
             "logical_cpus": hw["logical_cpus"]}
         log("cpu baseline", out["cpu_baseline"])
         # the oracle's solvers on the same workloads, 1 thread and all
