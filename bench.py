@@ -367,6 +367,19 @@ def main():
                         f"warm {t_warm*1e6:.1f} us, gather bound {e['gather_bound_us']:.1f} us")
                     if B is not Zm:
                         B.close()
+            # y = A x + y (beta = 1: y is read as well), cold, FP64
+            for fmt in ("csr", "coo"):
+                B = Zm if fmt == "csr" else Zm.convert(fmt, "f64")
+                nbytes = spmv_bytes(fmt, B.info(), 8, 8, beta_nonzero=True)
+                fn = lambda B=B: mxs.spmv(ctx, B, zx["f64"], zy["f64"], 1.0, 1.0)
+                fn()
+                t_cold, _ = timer.time(fn, 10, flush=lambda: mxs.flush_cache(ctx, 1 << 30))
+                r[f"{fmt}_f64_beta1"] = {"cold_us": round(t_cold * 1e6, 2),
+                                         "cold_GBs": round(nbytes / t_cold / 1e9, 1),
+                                         "bytes": nbytes}
+                log(f"{label} {fmt} f64 beta=1: cold {t_cold*1e6:.1f} us")
+                if B is not Zm:
+                    B.close()
             Zm.close()
             zres[label] = r
         extra["powerlaw_2p20"] = zres
