@@ -70,7 +70,10 @@ def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1
     """Continuous batching.  A submitter thread hands arrived requests to the
     engine (at most `chunk` per call) while the main thread steps: the host's
     validation and packing of new requests overlaps the device's steps, and
-    requests join the batch at the next step after they are queued."""
+    requests join the batch at the next step after they are queued.  The
+    main thread launches a step, then collects the results that earlier
+    steps retired while it runs, then waits for it: the copying out of
+    results overlaps the device too."""
     from . import mxs
     B = mxs.Batch(ctx, budget_bytes, max_slots, iters_per_step, classes, staging_bytes)
     order = sorted(reqs, key=lambda r: r.arrival)
@@ -109,21 +112,17 @@ def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1
     th.start()
     steps = 0
     max_active = 0
-    early = []   # retired before the submitter recorded their tickets
+    early = []   # retired, not yet collected (or not yet recorded by the submitter)
     while len(done) < len(order):
         if failure:
             th.join()
             B.close()
             raise failure[0]
         with lock:
-            work = queued[0] > len(done)
-        if not work:
-            time.sleep(50e-6)
-            continue
-        st = B.step()
-        steps += 1
-        max_active = max(max_active, st["active"])
-        early.extend(B.completed())
+            work = queued[0] > len(done) + len(early)
+        if work:
+            B.step_launch()
+            steps += 1
         with lock:
             ready = [t for t in early if t in rid_of]
             early = [t for t in early if t not in rid_of]
@@ -135,6 +134,12 @@ def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1
             statuses[r.rid] = s
             if keep_x:
                 xs[r.rid] = x
+        if work:
+            st = B.step_finish()
+            max_active = max(max_active, st["active"])
+            early.extend(B.completed())
+        elif not ready:
+            time.sleep(50e-6)
     th.join()
     B.close()
     return _report("batched" if mode == "f64" else f"batched_{mode}", order, arrival, done,
