@@ -864,6 +864,8 @@ struct mxs_batch {
   int nclasses = 0;
   mxs::ClassCfg cls[mxs::kMaxClasses];
   std::vector<mxs::Slot> slots;
+  // free slots of each class, the lowest index on top
+  std::vector<int> free_slots[mxs::kMaxClasses];
   std::deque<mxs::Request> pending;
   std::unordered_map<uint64_t, mxs::Result> results;
   uint64_t next_ticket = 1;
@@ -954,6 +956,12 @@ mxs_status build_graph(mxs_batch* B, int mask) {
   if (e != hipSuccess) return fail(ctx, MXS_HIP, "graph capture failed: %s", hipGetErrorString(e));
   MXS_HIP_TRY(ctx, hipGraphInstantiate(&B->exec[mask], B->graph[mask], nullptr, nullptr, 0));
   return MXS_OK;
+}
+
+int class_of_slot(const mxs_batch* B, int slot) {
+  int c = 0;
+  while (c + 1 < B->nclasses && slot >= B->cls[c + 1].base) ++c;
+  return c;
 }
 
 int class_of(const mxs_batch* B, int64_t n) {
@@ -1557,6 +1565,9 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
   B->nclasses = nc;
   B->nslots = base;
   B->slots.resize(B->nslots);
+  for (int c = 0; c < nc; ++c)
+    for (int i = B->cls[c].base + B->cls[c].slots - 1; i >= B->cls[c].base; --i)
+      B->free_slots[c].push_back(i);
   mxs_status st = MXS_OK;
   do {
     bool ok = hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) == hipSuccess &&
@@ -1800,46 +1811,50 @@ mxs_status mxs_batch_step_launch(mxs_batch* B) {
   // 1. admit in FIFO order, first fit: a request that does not fit (no free
   // slot in its class, or no arena gap) is passed over by later ones,
   // unless it has been the oldest waiting request for more than 64 steps;
-  // then nothing behind it is admitted until it fits (starvation guard)
-  auto find_free = [&](int c) {
-    const ClassCfg& C = B->cls[c];
-    for (int i = C.base; i < C.base + C.slots; ++i)
-      if (!B->slots[i].busy) return i;
-    return -1;
-  };
-  size_t idx = 0;
-  while (idx < B->pending.size()) {
+  // then nothing behind it is admitted until it fits (starvation guard).
+  // One pass over the queue: admitted requests leave it, the others are
+  // moved down in order; a request whose class has no free slot costs one
+  // test.
+  size_t keep = 0;
+  bool blocked = false;
+  for (size_t idx = 0; idx < B->pending.size(); ++idx) {
     Request& R = B->pending[idx];
-    const int si = find_free(R.cls);
+    bool fits = false;
     size_t off = 0;
-    bool fits = si >= 0 && B->arena.alloc(R.bytes, &off);
-    if (fits && !R.packed) {
-      if (B->inpool.alloc(R.in_bytes, &R.in_off)) {
-        pack(B->in_mem + R.in_off, R.n, R.nnz, R.rowptr.data(), R.col.data(), R.val.data(),
-             R.b.data());
-        R.packed = true;
-        std::vector<int32_t>().swap(R.rowptr);
-        std::vector<int32_t>().swap(R.col);
-        std::vector<double>().swap(R.val);
-        std::vector<double>().swap(R.b);
-      } else {
-        B->arena.release(off, R.bytes);
-        fits = false;
+    std::vector<int>& fs = B->free_slots[R.cls];
+    if (!blocked && !fs.empty() && B->arena.alloc(R.bytes, &off)) {
+      fits = true;
+      if (!R.packed) {
+        if (B->inpool.alloc(R.in_bytes, &R.in_off)) {
+          pack(B->in_mem + R.in_off, R.n, R.nnz, R.rowptr.data(), R.col.data(), R.val.data(),
+               R.b.data());
+          R.packed = true;
+          std::vector<int32_t>().swap(R.rowptr);
+          std::vector<int32_t>().swap(R.col);
+          std::vector<double>().swap(R.val);
+          std::vector<double>().swap(R.b);
+        } else {
+          B->arena.release(off, R.bytes);
+          fits = false;
+        }
       }
     }
     if (!fits) {
-      if (idx == 0) {
+      if (keep == 0 && !blocked) {  // the oldest request still waiting
         if (R.ticket == B->starve_ticket) {
           B->starve_steps++;
         } else {
           B->starve_ticket = R.ticket;
           B->starve_steps = 1;
         }
-        if (B->starve_steps > 64) break;
+        if (B->starve_steps > 64) blocked = true;
       }
-      ++idx;
+      if (keep != idx) B->pending[keep] = std::move(R);
+      ++keep;
       continue;
     }
+    const int si = fs.back();
+    fs.pop_back();
     char* p = (char*)B->arena_mem + off;
     const Layout L = layout(R.n, R.nnz, R.mode);
     SlotDesc& d = B->h_desc[si];
@@ -1874,8 +1889,8 @@ mxs_status mxs_batch_step_launch(mxs_batch* B) {
     s.in_off = R.in_off;
     s.in_bytes = R.in_bytes;
     s.n = R.n;
-    B->pending.erase(B->pending.begin() + idx);
   }
+  B->pending.resize(keep);
   // 2. run K iterations of every resident system, read the states back
   int active = 0, mask = 0;
   for (int i = 0; i < B->nslots; ++i) {
@@ -1937,6 +1952,7 @@ mxs_status mxs_batch_step_finish(mxs_batch* B, mxs_batch_stats* stats) {
     B->newly_done.push_back(s.ticket);
     B->arena.release(s.off, s.bytes);
     s.busy = false;
+    B->free_slots[class_of_slot(B, i)].push_back(i);
     B->h_desc[i].active = 0;
     B->desc_dirty = true;
     B->completed++;
