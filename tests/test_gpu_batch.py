@@ -334,3 +334,48 @@ def test_serving_concurrent_submission_bitwise(env):
         assert s == mxs.OK
         assert np.array_equal(x.view(np.uint64), rb.x[r.rid].view(np.uint64)), r.rid
     B.close()
+
+
+def test_starvation_guard(env, orc):
+    """A request too large to fit beside the residents is passed over by the
+    small ones behind it, but once it has been the oldest waiting request
+    for 64 steps nothing behind it is admitted: the residents drain, it is
+    admitted and finishes, although small requests keep arriving."""
+    mxs, ctx, torch = env
+    big = _systems([96], 700)[0]
+    smalls = _systems([30] * 400, 800)
+    # the footprints as the engine counts them
+    B0 = mxs.Batch(ctx, 64 << 20, 8, iters_per_step=1)
+    B0.submit(*big, 1e-10)
+    fp_big = B0.step()["arena_used"]
+    B0.close()
+    B0 = mxs.Batch(ctx, 64 << 20, 8, iters_per_step=1)
+    B0.submit(*smalls[0], 1e-10)
+    fp_small = B0.step()["arena_used"]
+    B0.close()
+    assert fp_big > 8 * fp_small
+    # room for the big one alone, or for several small ones, never for both
+    B = mxs.Batch(ctx, fp_big + fp_small // 2, 32, iters_per_step=8)
+    it = iter(smalls)
+    tickets = [B.submit(*next(it), 1e-10) for _ in range(4)]
+    B.step()
+    tb = B.submit(*big, 1e-10)
+    done_at = None
+    for step in range(300):
+        for _ in range(2):      # two new small requests every step
+            nxt = next(it, None)
+            if nxt is not None:
+                tickets.append(B.submit(*nxt, 1e-10))
+        B.step()
+        s, x, _ = B.poll(tb, big[0].n)
+        if s != mxs.PENDING:
+            done_at = step
+            break
+    assert done_at is not None and done_at >= 64, done_at
+    assert s == mxs.OK
+    assert orc.true_relres(big[0], big[1], x) <= 1e-10 + _slack(orc, big[0], big[1], x)
+    _drain(B)
+    for t, (A, b) in zip(tickets, smalls):
+        s, x, _ = B.poll(t, A.n)
+        assert s == mxs.OK
+    B.close()
