@@ -539,6 +539,18 @@ mxs_status mxs_batch_step_finish(mxs_batch* batch, mxs_batch_stats* stats);
 mxs_status mxs_batch_poll(mxs_batch* batch, uint64_t ticket, double* x_host,
                           mxs_solve_info* info);
 
+/* mxs_batch_poll for `count` tickets in one call (one lock, one crossing of
+ * the boundary): request i's x (n_i doubles) goes to x_host + x_off[i]
+ * (offsets in doubles, the caller's layout; x_host nullable), its info to
+ * infos[i] (infos nullable) and the status mxs_batch_poll would return to
+ * statuses[i]; a PENDING request's x and info are left untouched and its
+ * ticket is kept.  Returns MXS_INVALID_ARG for bad arguments of the call
+ * itself (count < 0, NULL tickets or statuses, NULL x_off with x_host),
+ * else MXS_OK; an unknown ticket gets MXS_INVALID_ARG in statuses[i]. */
+mxs_status mxs_batch_poll_many(mxs_batch* batch, int64_t count, const uint64_t* tickets,
+                               double* x_host, const int64_t* x_off, mxs_solve_info* infos,
+                               mxs_status* statuses);
+
 /* Moves up to `cap` tickets retired since the previous call into
  * tickets[] (oldest first); *count receives how many were written. */
 mxs_status mxs_batch_completed(mxs_batch* batch, uint64_t* tickets, int64_t cap, int64_t* count);

@@ -1992,6 +1992,28 @@ mxs_status mxs_batch_poll(mxs_batch* B, uint64_t ticket, double* x_host, mxs_sol
   return st;
 }
 
+mxs_status mxs_batch_poll_many(mxs_batch* B, int64_t count, const uint64_t* tickets,
+                               double* x_host, const int64_t* x_off, mxs_solve_info* infos,
+                               mxs_status* statuses) {
+  if (!B || count < 0 || (count && (!tickets || !statuses)) || (x_host && !x_off))
+    return MXS_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(B->mu);
+  for (int64_t i = 0; i < count; ++i) {
+    const uint64_t t = tickets[i];
+    auto it = B->results.find(t);
+    if (it == B->results.end() || !it->second.done) {
+      statuses[i] = (t == 0 || t >= B->next_ticket) ? MXS_INVALID_ARG : MXS_PENDING;
+      continue;
+    }
+    if (x_host)
+      std::memcpy(x_host + x_off[i], it->second.x.data(), it->second.x.size() * sizeof(double));
+    if (infos) infos[i] = it->second.info;
+    statuses[i] = it->second.info.status;
+    B->results.erase(it);
+  }
+  return MXS_OK;
+}
+
 mxs_status mxs_batch_completed(mxs_batch* B, uint64_t* tickets, int64_t cap, int64_t* count) {
   if (!B || !count || (cap > 0 && !tickets)) return MXS_INVALID_ARG;
   std::lock_guard<std::mutex> lock(B->mu);

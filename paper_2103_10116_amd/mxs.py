@@ -154,6 +154,7 @@ _SIGS = {
     "mxs_batch_step_launch": (_S, [_P]),
     "mxs_batch_step_finish": (_S, [_P, C.POINTER(BatchStats)]),
     "mxs_batch_poll": (_S, [_P, C.c_uint64, _P, C.POINTER(SolveInfo)]),
+    "mxs_batch_poll_many": (_S, [_P, _I64, _P, _P, _P, _P, _P]),
     "mxs_batch_completed": (_S, [_P, C.POINTER(C.c_uint64), _I64, C.POINTER(_I64)]),
     "mxs_batch_config": (_S, [_P, _S, C.POINTER(_S), C.POINTER(_S), C.POINTER(_S),
                               C.POINTER(_S), C.POINTER(_S)]),
@@ -713,6 +714,37 @@ class Batch:
             _check(s, self.ctx)
         return s, x, Result(s, info.iters, info.relres_recurrence, info.relres_true,
                             info.replacements, info.restarts)
+
+    def poll_many(self, tickets, ns):
+        """mxs_batch_poll_many: (statuses, xs, results) for the tickets, with
+        ns their system sizes; xs[i] is a view of one shared buffer (None
+        while request i is pending), results[i] its Result (None likewise)."""
+        t = np.ascontiguousarray(np.asarray(tickets, dtype=np.uint64))
+        ns = np.asarray(ns, dtype=np.int64)
+        k = int(t.size)
+        off = np.zeros(k, np.int64)
+        if k > 1:
+            np.cumsum(ns[:-1], out=off[1:])
+        buf = np.empty(int(ns.sum()), np.float64)
+        infos = (SolveInfo * max(k, 1))()
+        sts = np.zeros(k, np.int32)
+        _check(_lib.mxs_batch_poll_many(self.handle, k, t.ctypes.data, buf.ctypes.data,
+                                        off.ctypes.data, C.addressof(infos), sts.ctypes.data),
+               self.ctx)
+        xs, res = [], []
+        for i in range(k):
+            s = int(sts[i])
+            if s == INVALID_ARG:
+                _check(s, self.ctx)
+            if s == PENDING:
+                xs.append(None)
+                res.append(None)
+                continue
+            xs.append(buf[off[i]:off[i] + ns[i]])
+            f = infos[i]
+            res.append(Result(s, f.iters, f.relres_recurrence, f.relres_true, f.replacements,
+                              f.restarts))
+        return sts, xs, res
 
     def config(self, cls: int) -> dict:
         vals = [C.c_int32() for _ in range(5)]

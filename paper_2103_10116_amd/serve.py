@@ -127,13 +127,15 @@ def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1
             ready = [t for t in early if t in rid_of]
             early = [t for t in early if t not in rid_of]
             rs = [rid_of[t] for t in ready]
-        for t, r in zip(ready, rs):
-            s, x, res = B.poll(t, systems[r.rid][0].n)
-            done[r.rid] = time.perf_counter() - t0
-            iters[r.rid] = res.iters
-            statuses[r.rid] = s
-            if keep_x:
-                xs[r.rid] = x
+        if ready:
+            sts, xv, res = B.poll_many(ready, [systems[r.rid][0].n for r in rs])
+            now = time.perf_counter() - t0
+            for r, s, x, rr in zip(rs, sts.tolist(), xv, res):
+                done[r.rid] = now
+                iters[r.rid] = rr.iters
+                statuses[r.rid] = s
+                if keep_x:
+                    xs[r.rid] = x
         if work:
             st = B.step_finish()
             max_active = max(max_active, st["active"])

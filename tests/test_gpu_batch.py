@@ -379,3 +379,33 @@ def test_starvation_guard(env, orc):
         s, x, _ = B.poll(t, A.n)
         assert s == mxs.OK
     B.close()
+
+
+def test_poll_many_equals_poll(env):
+    """mxs_batch_poll_many hands back what mxs_batch_poll would, bit for bit,
+    for several finished requests in one call; a request still waiting is
+    reported PENDING and kept; an unknown ticket is refused."""
+    mxs, ctx, torch = env
+    sys_ = _systems([9, 40, 17, 64, 25, 33], 900)
+    runs = []
+    for use_many in (False, True):
+        B = mxs.Batch(ctx, 64 << 20, 16, iters_per_step=8)
+        tickets = [B.submit(A, b, 1e-10) for A, b in sys_]
+        _drain(B)
+        late = B.submit(*_systems([90], 901)[0], 1e-10)   # queued, not stepped
+        if use_many:
+            sts, xs, res = B.poll_many(tickets + [late], [A.n for A, _ in sys_] + [8100])
+            assert sts[-1] == mxs.PENDING and xs[-1] is None and res[-1] is None
+            s, _, _ = B.poll(late, 8100)
+            assert s == mxs.PENDING   # still known: poll_many kept it
+            out = [(int(s), x.copy(), r) for s, x, r in zip(sts[:-1], xs[:-1], res[:-1])]
+            with pytest.raises(mxs.MxsError):
+                B.poll_many([10 ** 9], [1])   # never issued
+        else:
+            out = [B.poll(t, A.n) for t, (A, _) in zip(tickets, sys_)]
+        runs.append(out)
+        B.close()
+    for (s1, x1, r1), (s2, x2, r2) in zip(*runs):
+        assert s1 == s2 == mxs.OK
+        assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64))
+        assert (r1.iters, r1.relres_true) == (r2.iters, r2.relres_true)
