@@ -31,6 +31,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -814,7 +815,8 @@ struct Request {
 };
 
 struct Result {
-  std::vector<double> x;
+  std::unique_ptr<double[]> x;  // n doubles, filled at retirement
+  int64_t n = 0;
   mxs_solve_info info;
   bool done = false;
 };
@@ -1043,6 +1045,35 @@ void pack(char* dst, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     std::memcpy(dst + L.val, val, nnz * 8);
   }
   std::memcpy(dst + L.b, b, n * 8);
+}
+
+// Runs the retirement copies (pinned output -> result buffers), split by
+// bytes over up to 8 threads when they add up to more than 4 MiB.
+template <typename Copy>
+void copy_out(const std::vector<Copy>& c) {
+  size_t total = 0;
+  for (const Copy& k : c) total += (size_t)k.n * sizeof(double);
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nt = std::min<size_t>({(size_t)std::min(hw, 8u), c.size(), total >> 22});
+  if (nt <= 1) {
+    for (const Copy& k : c) std::memcpy(k.dst, k.src, (size_t)k.n * sizeof(double));
+    return;
+  }
+  // contiguous runs of copies of about total / nt bytes each
+  std::vector<size_t> cut{0};
+  size_t acc = 0;
+  for (size_t j = 0; j < c.size(); ++j) {
+    acc += (size_t)c[j].n * sizeof(double);
+    if (acc * nt >= total * cut.size() && cut.size() < nt) cut.push_back(j + 1);
+  }
+  cut.push_back(c.size());
+  std::vector<std::thread> pool;
+  for (size_t t = 0; t + 1 < cut.size(); ++t)
+    pool.emplace_back([&, t] {
+      for (size_t j = cut[t]; j < cut[t + 1]; ++j)
+        std::memcpy(c[j].dst, c[j].src, (size_t)c[j].n * sizeof(double));
+    });
+  for (auto& th : pool) th.join();
 }
 
 mxs_status upload_desc(mxs_batch* B) {
@@ -1921,7 +1952,14 @@ mxs_status mxs_batch_step_finish(mxs_batch* B, mxs_batch_stats* stats) {
   lock.lock();
   B->in_flight = false;
   // 3. every resident slot has copied its inputs by now; retire the
-  // finished ones (their x is already in the pinned output)
+  // finished ones (their x is already in the pinned output, and is copied
+  // out below, on several threads when there is much of it)
+  struct Copy {
+    double* dst;
+    const double* src;
+    int64_t n;
+  };
+  std::vector<Copy> copies;
   for (int i = 0; i < B->nslots && active > 0; ++i) {
     Slot& s = B->slots[i];
     if (!s.busy) continue;
@@ -1932,8 +1970,9 @@ mxs_status mxs_batch_step_finish(mxs_batch* B, mxs_batch_stats* stats) {
     const SlotState& d = B->h_state[i];
     if (d.gen != B->h_desc[i].gen || d.status < SLOT_CONVERGED) continue;
     Result& R = B->results[s.ticket];
-    const double* xs = B->xout_mem + B->xout_off[i];
-    R.x.assign(xs, xs + s.n);
+    R.x.reset(new double[(size_t)s.n]);
+    R.n = s.n;
+    copies.push_back({R.x.get(), B->xout_mem + B->xout_off[i], s.n});
     std::memset(&R.info, 0, sizeof(R.info));
     R.info.iters = d.iters;  // refinement mode: inner iterations in total
     R.info.replacements = d.repl;
@@ -1958,6 +1997,7 @@ mxs_status mxs_batch_step_finish(mxs_batch* B, mxs_batch_stats* stats) {
     B->completed++;
     active--;
   }
+  copy_out(copies);
   if (stats) {
     int resident = 0;
     for (const Slot& s : B->slots) resident += s.busy ? 1 : 0;
@@ -1985,7 +2025,7 @@ mxs_status mxs_batch_poll(mxs_batch* B, uint64_t ticket, double* x_host, mxs_sol
     if (ticket == 0 || ticket >= B->next_ticket) return MXS_INVALID_ARG;
     return MXS_PENDING;
   }
-  if (x_host) std::memcpy(x_host, it->second.x.data(), it->second.x.size() * sizeof(double));
+  if (x_host) std::memcpy(x_host, it->second.x.get(), (size_t)it->second.n * sizeof(double));
   if (info) *info = it->second.info;
   const mxs_status st = it->second.info.status;
   B->results.erase(it);
@@ -2006,7 +2046,7 @@ mxs_status mxs_batch_poll_many(mxs_batch* B, int64_t count, const uint64_t* tick
       continue;
     }
     if (x_host)
-      std::memcpy(x_host + x_off[i], it->second.x.data(), it->second.x.size() * sizeof(double));
+      std::memcpy(x_host + x_off[i], it->second.x.get(), (size_t)it->second.n * sizeof(double));
     if (infos) infos[i] = it->second.info;
     statuses[i] = it->second.info.status;
     B->results.erase(it);
