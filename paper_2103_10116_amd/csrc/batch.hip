@@ -2038,6 +2038,13 @@ mxs_status mxs_batch_poll_many(mxs_batch* B, int64_t count, const uint64_t* tick
   if (!B || count < 0 || (count && (!tickets || !statuses)) || (x_host && !x_off))
     return MXS_INVALID_ARG;
   std::lock_guard<std::mutex> lock(B->mu);
+  struct Copy {
+    double* dst;
+    const double* src;
+    int64_t n;
+  };
+  std::vector<Copy> copies;
+  std::vector<std::unique_ptr<double[]>> hold;  // freed once the copies are done
   for (int64_t i = 0; i < count; ++i) {
     const uint64_t t = tickets[i];
     auto it = B->results.find(t);
@@ -2045,12 +2052,13 @@ mxs_status mxs_batch_poll_many(mxs_batch* B, int64_t count, const uint64_t* tick
       statuses[i] = (t == 0 || t >= B->next_ticket) ? MXS_INVALID_ARG : MXS_PENDING;
       continue;
     }
-    if (x_host)
-      std::memcpy(x_host + x_off[i], it->second.x.get(), (size_t)it->second.n * sizeof(double));
+    if (x_host) copies.push_back({x_host + x_off[i], it->second.x.get(), it->second.n});
     if (infos) infos[i] = it->second.info;
     statuses[i] = it->second.info.status;
+    hold.push_back(std::move(it->second.x));
     B->results.erase(it);
   }
+  copy_out(copies);
   return MXS_OK;
 }
 

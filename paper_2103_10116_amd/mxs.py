@@ -93,6 +93,14 @@ class SolveInfo(C.Structure):
                 ("restarts", C.c_int64), ("status", C.c_int32)]
 
 
+# the same record as a numpy dtype (for arrays of results)
+_SOLVE_INFO_DTYPE = np.dtype({"names": [f for f, _ in SolveInfo._fields_],
+                              "formats": [np.dtype(t) for _, t in SolveInfo._fields_],
+                              "offsets": [getattr(SolveInfo, f).offset
+                                          for f, _ in SolveInfo._fields_],
+                              "itemsize": C.sizeof(SolveInfo)})
+
+
 class IRInfo(C.Structure):
     _fields_ = [("outer_iters", C.c_int64), ("inner_iters_total", C.c_int64),
                 ("relres_true", C.c_double), ("status", C.c_int32)]
@@ -716,35 +724,27 @@ class Batch:
                             info.replacements, info.restarts)
 
     def poll_many(self, tickets, ns):
-        """mxs_batch_poll_many: (statuses, xs, results) for the tickets, with
-        ns their system sizes; xs[i] is a view of one shared buffer (None
-        while request i is pending), results[i] its Result (None likewise)."""
+        """mxs_batch_poll_many: (statuses, x, off, info) for the tickets, with
+        ns their system sizes.  Request i's x is x[off[i]:off[i] + ns[i]] (one
+        shared buffer); info is a structured array of SolveInfo records
+        (fields iters, relres_recurrence, relres_true, replacements,
+        restarts, status).  A pending request keeps status PENDING and its
+        slice of x is left unwritten."""
         t = np.ascontiguousarray(np.asarray(tickets, dtype=np.uint64))
         ns = np.asarray(ns, dtype=np.int64)
         k = int(t.size)
         off = np.zeros(k, np.int64)
         if k > 1:
             np.cumsum(ns[:-1], out=off[1:])
-        buf = np.empty(int(ns.sum()), np.float64)
-        infos = (SolveInfo * max(k, 1))()
+        x = np.empty(int(ns.sum()), np.float64)
+        info = np.zeros(k, _SOLVE_INFO_DTYPE)
         sts = np.zeros(k, np.int32)
-        _check(_lib.mxs_batch_poll_many(self.handle, k, t.ctypes.data, buf.ctypes.data,
-                                        off.ctypes.data, C.addressof(infos), sts.ctypes.data),
+        _check(_lib.mxs_batch_poll_many(self.handle, k, t.ctypes.data, x.ctypes.data,
+                                        off.ctypes.data, info.ctypes.data, sts.ctypes.data),
                self.ctx)
-        xs, res = [], []
-        for i in range(k):
-            s = int(sts[i])
-            if s == INVALID_ARG:
-                _check(s, self.ctx)
-            if s == PENDING:
-                xs.append(None)
-                res.append(None)
-                continue
-            xs.append(buf[off[i]:off[i] + ns[i]])
-            f = infos[i]
-            res.append(Result(s, f.iters, f.relres_recurrence, f.relres_true, f.replacements,
-                              f.restarts))
-        return sts, xs, res
+        if (sts == INVALID_ARG).any():
+            _check(INVALID_ARG, self.ctx)
+        return sts, x, off, info
 
     def config(self, cls: int) -> dict:
         vals = [C.c_int32() for _ in range(5)]

@@ -128,14 +128,15 @@ def run_batched(ctx, reqs, systems, tol=1e-10, budget_bytes=2 << 30, max_slots=1
             early = [t for t in early if t not in rid_of]
             rs = [rid_of[t] for t in ready]
         if ready:
-            sts, xv, res = B.poll_many(ready, [systems[r.rid][0].n for r in rs])
+            ns = [systems[r.rid][0].n for r in rs]
+            sts, xbuf, off, info = B.poll_many(ready, ns)
             now = time.perf_counter() - t0
-            for r, s, x, rr in zip(rs, sts.tolist(), xv, res):
+            for r, s, it, o, n in zip(rs, sts.tolist(), info["iters"].tolist(), off.tolist(), ns):
                 done[r.rid] = now
-                iters[r.rid] = rr.iters
+                iters[r.rid] = it
                 statuses[r.rid] = s
                 if keep_x:
-                    xs[r.rid] = x
+                    xs[r.rid] = xbuf[o:o + n]
         if work:
             st = B.step_finish()
             max_active = max(max_active, st["active"])
