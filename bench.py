@@ -345,7 +345,7 @@ def main():
                     # so the probe is taken on an x of the slice's size
                     t_b = (nbytes - Z.ncols * vb) / (peak_meas * 1e9) if peak_meas else 0.0
                     t_g = Z.nnz / gp[dt]
-                    panels = info.get("col_panels", 0) if fmt == "csr" else 0
+                    panels = info.get("col_panels", 0) if fmt in ("csr", "coo") else 0
                     e["gather_bound_full_x_us"] = round(max(t_g, t_b) * 1e6, 2)
                     if panels > 1:
                         key = (dt, panels)

@@ -125,6 +125,13 @@ struct CooPart {
   int64_t nempty = 0;
   int wpb = 4;  // independent waves per work-group (1 or 4)
   int kernel = MXS_COO_LDS;  // MXS_COO_LDS or MXS_COO_RUNS
+  // column panels (COO format only, panels > 1): the entries ordered by
+  // panel, then row, then column, with row[k] = p * n + i for an entry of
+  // row i in panel p; the chunks write the P * n panel partials (product
+  // scratch) and a last pass adds each row's partials in panel order,
+  // reading those whose bit is set in pmask[i]
+  int panels = 1;
+  uint8_t* pmask = nullptr;
 };
 
 // ELL: column-major padded slots; `waves` waves per 64 rows split the

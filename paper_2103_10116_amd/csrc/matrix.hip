@@ -417,6 +417,18 @@ __global__ void k_panel_scatter(int64_t n, int P, const int32_t* __restrict__ rp
   }
 }
 
+// Row index of every entry of the panel-ordered COO arrays: entries
+// srowptr[r] .. srowptr[r+1]-1 belong to stacked row r, output index srid[r].
+__global__ void k_coo_stacked_rows(int64_t m, const int32_t* __restrict__ srowptr,
+                                   const int32_t* __restrict__ srid,
+                                   int32_t* __restrict__ row) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += stride) {
+    const int32_t v = srid[r];
+    for (int32_t k = srowptr[r]; k < srowptr[r + 1]; ++k) row[k] = v;
+  }
+}
+
 // Copies the current values into the panel copy again, one thread per
 // stacked row r (row i = srid[r] % n of panel p = srid[r] / n): the slice's
 // first entry in row i is found by binary search, as at set-up.
@@ -842,6 +854,98 @@ mxs_status alloc_coo_arrays(mxs_ctx* ctx, mxs_matrix* A, mxs::CooPart& P, int64_
   return MXS_OK;
 }
 
+// COO arrays in panel order (see CooPart) from the FP64 CSR source S: the
+// entries counted per row and panel, placed by the merge path's scatter
+// (FP64 values, cast afterwards), and each given its stacked output index.
+template <typename V>
+mxs_status build_coo_panels(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, int P,
+                            int* d_err) {
+  CooPart& C = A->coo;
+  const int64_t n = S->n, nnz = S->nnz;
+  const int64_t W = (S->ncols + P - 1) / P;
+  std::vector<int32_t> cnt((size_t)P * n), dst((size_t)P * n, -1), srp, srid;
+  std::vector<uint8_t> mask((size_t)n, 0);
+  int32_t* d_cnt = (int32_t*)ctx->alloc.alloc((size_t)P * n * 4 + 4);
+  int32_t* d_dst = (int32_t*)ctx->alloc.alloc((size_t)P * n * 4 + 4);
+  int32_t* d_srp = nullptr;
+  int32_t* d_srid = nullptr;
+  double* v64 = sizeof(V) == 8 ? (double*)C.val : (double*)ctx->alloc.alloc((size_t)nnz * 8 + 8);
+  mxs_status st = MXS_OK;
+  do {
+    if (!d_cnt || !d_dst || !v64) {
+      st = fail(ctx, MXS_OOM, "COO column panels: counts");
+      break;
+    }
+    k_panel_counts<<<grid_for(ctx, n, 256), 256, 0, ctx->stream>>>(n, P, W, S->csr.rowptr,
+                                                                     S->csr.col, d_cnt);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(cnt.data(), d_cnt, (size_t)P * n * 4, hipMemcpyDeviceToHost,
+                       ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "COO column panels: counting failed");
+      break;
+    }
+    int64_t pos = 0;
+    for (int p = 0; p < P; ++p)
+      for (int64_t i = 0; i < n; ++i) {
+        const int32_t c = cnt[(size_t)p * n + i];
+        if (c == 0) continue;
+        srid.push_back((int32_t)((int64_t)p * n + i));
+        srp.push_back((int32_t)pos);
+        dst[(size_t)p * n + i] = (int32_t)pos;
+        mask[(size_t)i] |= (uint8_t)(1u << p);
+        pos += c;
+      }
+    srp.push_back((int32_t)pos);
+    if (pos != nnz) {
+      st = fail(ctx, MXS_HIP, "COO column panels: inconsistent counts");
+      break;
+    }
+    C.pmask = upload(ctx, A, mask);
+    d_srp = (int32_t*)ctx->alloc.alloc(srp.size() * 4 + 4);
+    d_srid = (int32_t*)ctx->alloc.alloc(srid.size() * 4 + 4);
+    if (!C.pmask || !d_srp || !d_srid) {
+      st = fail(ctx, MXS_OOM, "COO column panels");
+      break;
+    }
+    if (hipMemcpyAsync(d_dst, dst.data(), (size_t)P * n * 4, hipMemcpyHostToDevice,
+                       ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(d_srp, srp.data(), srp.size() * 4, hipMemcpyHostToDevice, ctx->stream) !=
+            hipSuccess ||
+        (!srid.empty() && hipMemcpyAsync(d_srid, srid.data(), srid.size() * 4,
+                                         hipMemcpyHostToDevice, ctx->stream) != hipSuccess)) {
+      st = fail(ctx, MXS_HIP, "copy failed");
+      break;
+    }
+    const int g = grid_for(ctx, n, 256);
+    k_panel_scatter<uint64_t><<<g, 256, 0, ctx->stream>>>(
+        n, P, S->csr.rowptr, d_cnt, d_dst, S->csr.col, (const uint64_t*)S->csr.val, C.col,
+        (uint64_t*)v64);
+    k_coo_stacked_rows<<<grid_for(ctx, (int64_t)srid.size(), 256), 256, 0, ctx->stream>>>(
+        (int64_t)srid.size(), d_srp, d_srid, C.row);
+    if (hipGetLastError() != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "COO column panels: scatter failed");
+      break;
+    }
+    if (sizeof(V) != 8) {
+      st = cast_into<V>(ctx, nnz, v64, C.val, d_err);
+      if (st) break;
+    }
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "COO column panels: set-up failed");
+      break;
+    }
+    C.panels = P;
+  } while (0);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->alloc.release(d_cnt);
+  ctx->alloc.release(d_dst);
+  ctx->alloc.release(d_srp);
+  ctx->alloc.release(d_srid);
+  if (sizeof(V) != 8) ctx->alloc.release(v64);
+  return st;
+}
+
 template <typename V>
 mxs_status convert_typed(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, mxs_format fmt,
                          const mxs_convert_opts* opts, int* d_err) {
@@ -872,6 +976,16 @@ mxs_status convert_typed(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, mxs_f
 
   if (fmt == MXS_COO) {
     if (mxs_status st = alloc_coo_arrays(ctx, A, A->coo, nnz, vb)) return st;
+    // column panels: asked for, or (auto) for rows longer than 64 entries
+    // (power-law patterns, whose gathers range over all of x) when x is
+    // large enough for the merge path's rule
+    const int req = opts ? opts->col_panels : 0;
+    const int P = (req > 1 || (req == 0 && Kmax > 64)) ? merge_panels(A, opts) : 1;
+    if (P > 1 && nnz > 0) {
+      mxs_status st = build_coo_panels<V>(ctx, S, A, P, d_err);
+      if (st) return st;
+      return setup_coo_part(ctx, A, A->coo, nnz, Kmax, vb, bnnz, std::vector<int32_t>(), opts);
+    }
     k_coo_rows<<<grid_for(ctx, n, 256), 256, 0, ctx->stream>>>(n, rp, A->coo.row);
     MXS_HIP_TRY(ctx, hipGetLastError());
     if (nnz)
@@ -1363,7 +1477,9 @@ mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
                     : A->csr.lanes >= 1 ? MXS_CSR_VECTOR
                                        : MXS_CSR_STREAM;
   out->coo_kernel = A->fmt == MXS_COO || (A->fmt == MXS_HYB && A->coo.nnz > 0) ? A->coo.kernel : 0;
-  out->col_panels = A->fmt == MXS_CSR && A->csr.merge ? A->csr.panels : 0;
+  out->col_panels = A->fmt == MXS_CSR && A->csr.merge ? A->csr.panels
+                    : A->fmt == MXS_COO                 ? A->coo.panels
+                                                        : 0;
   out->bytes = A->bytes;
   return MXS_OK;
 }

@@ -1471,6 +1471,26 @@ void launch_coo_chunks(mxs_ctx* ctx, const CooPart& P, T alpha, const T* x, T be
 template <typename V, typename T, bool ACCUM>
 void launch_coo(mxs_ctx* ctx, const CooPart& P, int64_t n, T alpha, const T* x, T beta, T* y,
                 const int32_t* skip, void* scratch) {
+  if (P.panels > 1) {
+    // column panels: the chunks write the panel partials (scratch after the
+    // continuation partials) with alpha = 1, beta = 0, the cut rows are
+    // completed there, and the last pass forms y = alpha sum + beta y
+    if (P.nchunks == 0) return;
+    const Cont c = cont_of(scratch, P.nchunks);
+    T* part = (T*)((char*)scratch + cont_bytes(P.nchunks));
+    if (P.wpb == 4)
+      launch_coo_chunks<V, T, false, 4>(ctx, P, T(1), x, T(0), part, skip, c);
+    else
+      launch_coo_chunks<V, T, false, 1>(ctx, P, T(1), x, T(0), part, skip, c);
+    if (P.nchunks > 1)
+      k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
+          P.nchunks, c.row, (T*)c.val, part, T(1), skip, nullptr);
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)ctx->num_cus * 16);
+    k_panel_add<T, false, false><<<g, 256, 0, ctx->stream>>>(
+        n, P.panels, P.pmask, part, nullptr, y, alpha, ACCUM ? T(1) : beta, skip, nullptr,
+        nullptr);
+    return;
+  }
   if (!ACCUM && P.nempty > 0)
     k_empty_rows<T><<<(unsigned)((P.nempty + 255) / 256), 256, 0, ctx->stream>>>(
         P.nempty, P.empty_rows, y, beta, skip);
@@ -1544,6 +1564,8 @@ size_t spmv_scratch_bytes(const mxs_matrix* A) {
   // column panels: one partial of up to 8 bytes per row and panel
   if (A->fmt == MXS_CSR && A->csr.merge && A->csr.panels > 1)
     b += (size_t)A->csr.panels * (size_t)A->n * sizeof(double);
+  if (A->fmt == MXS_COO && A->coo.panels > 1)
+    b += (size_t)A->coo.panels * (size_t)A->n * sizeof(double);
   return b;
 }
 

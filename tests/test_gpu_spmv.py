@@ -354,7 +354,8 @@ def test_spmv_csr_kernels(env, orc, name, dt):
 def test_spmv_coo_kernels(env, orc, name, kernel):
     """Both COO kernels (and the COO part of HYB, which the power-law matrices
     have at a forced width) at every chunk size and work-group shape, FP64
-    and FP32; chunks of 256 entries leave ragged last chunks on every matrix."""
+    and FP32, and COO with its entries in 2 or 8 column panels; chunks of
+    256 entries leave ragged last chunks on every matrix."""
     mxs, ctx, torch = env
     A = ZOO[name]
     M = mxs.Matrix.from_host(ctx, A)
@@ -370,18 +371,23 @@ def test_spmv_coo_kernels(env, orc, name, kernel):
             yr = y0.astype(np.float32).astype(np.float64) if dt == "f32" else y0
             ref = orc.spmv_csr(Ar, xr, 1.5, -0.5, yr)
             scale = 1.5 * orc.absrow(Ar, xr) + 0.5 * np.abs(yr)
-            for bn in (256, 512, 1024):
-                for wpg in (1, 4):
-                    B = M.convert(fmt, dt, block_nnz=bn, waves_per_group=wpg,
-                                  coo_kernel=kernel, ell_width=width)
-                    d = B.info()
-                    assert d["block_nnz"] == bn and d["waves_per_group"] == wpg
-                    if d["coo_nnz"]:
-                        assert d["coo_kernel"] == mxs.COO_KERNELS[kernel]
-                    y = torch.from_numpy(yr).to(tdt).cuda()
-                    mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
-                    _check(y.cpu().numpy().astype(np.float64), ref, scale, tol)
-                    B.close()
+            shapes = [(bn, wpg, 0) for bn in (256, 512, 1024) for wpg in (1, 4)]
+            if fmt == "coo":   # entries in column-panel order
+                shapes += [(bn, wpg, p) for bn in (256, 1024) for wpg in (1, 4) for p in (2, 8)]
+            for bn, wpg, panels in shapes:
+                extra = {"col_panels": panels} if panels else {}
+                B = M.convert(fmt, dt, block_nnz=bn, waves_per_group=wpg,
+                              coo_kernel=kernel, ell_width=width, **extra)
+                d = B.info()
+                assert d["block_nnz"] == bn and d["waves_per_group"] == wpg
+                if d["coo_nnz"]:
+                    assert d["coo_kernel"] == mxs.COO_KERNELS[kernel]
+                if panels and A.nnz and A.ncols >= panels:
+                    assert d["col_panels"] == panels
+                y = torch.from_numpy(yr).to(tdt).cuda()
+                mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
+                _check(y.cpu().numpy().astype(np.float64), ref, scale, tol)
+                B.close()
 
 
 def test_coo_kernel_auto_choice(env):
@@ -560,7 +566,8 @@ def test_spmv_full_size(env, orc, which):
     # COO in both kernels (AUTO picks one of them)
     cases = [("csr", {}), ("csr", {"csr_kernel": "merge", "col_panels": 1}),
              ("csr", {"csr_kernel": "merge", "col_panels": 8}), ("coo", {"coo_kernel": "lds"}),
-             ("coo", {"coo_kernel": "runs"}), ("ell", {}), ("hyb", {})]
+             ("coo", {"coo_kernel": "runs"}), ("coo", {"col_panels": 1}), ("ell", {}),
+             ("hyb", {})]
     if which == "stencil27_128":
         # the byte rule makes the hybrid all ELL here (K_h = 27): a forced
         # width of 20 sends 7 entries of every interior row to its COO part
@@ -571,6 +578,9 @@ def test_spmv_full_size(env, orc, which):
         B = M.convert(fmt, "f64", **opts)
         if fmt == "csr" and not opts and which != "stencil27_128":
             assert B.info()["col_panels"] == 4   # x of 8 MiB: slices of 2 MiB
+        if fmt == "coo" and "col_panels" not in opts:
+            # rows over 64 entries and an x of 8 MiB: panels; stencils: none
+            assert B.info()["col_panels"] == (4 if which != "stencil27_128" else 1)
         if "ell_width" in opts:
             assert B.info()["ell_width"] == 20 and B.info()["coo_nnz"] > 7 * 120 ** 3
         y = torch.zeros(A.n, dtype=torch.float64, device="cuda")

@@ -20,6 +20,7 @@ def _mats(mxs, ctx, A):
             "csr_panels": M.convert("csr", "f64", csr_kernel="merge", col_panels=4),
             "csr_stream": M.convert("csr", "f64", csr_kernel="stream"),
             "coo": M.convert("coo", "f64", block_nnz=256),
+            "coo_panels": M.convert("coo", "f64", block_nnz=256, col_panels=4),
             "coo_f32": M.convert("coo", "f32"),
             "hyb": M.convert("hyb", "f64"),
             "merge_f16": M.convert("csr", "f16", csr_kernel="merge"),
