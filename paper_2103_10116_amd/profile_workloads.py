@@ -16,6 +16,8 @@ cached beyond L2 residue):
              cold and then warm (the cache's share of in-solver products)
   panels     the s = 1.79 power-law matrix, merge-path CSR FP64 and FP32 with
              1, 2 and 4 column panels, cold
+  coopanels  both power-law matrices, COO FP64 and FP32 with 1, 2, 4 and 8
+             column panels, cold
   probe      the HBM probe (read, copy, triad on 1 GiB arrays): the streaming
              kernels' counters beside the products'
   cg7        CG iterations without a stopping test (tolerance 0, 200 steps)
@@ -136,6 +138,13 @@ def main():
         elif w == "probe":
             bw = mxs.hbm_probe(ctx, 1 << 30, 2)
             print("probe", {k: round(v, 1) for k, v in bw.items()}, flush=True)
+        elif w == "coopanels":
+            for sv in (1.79, 2.0):
+                Z = mxs.Matrix.from_host(ctx, I.zipf_random(2 ** 20, sv, 4096))
+                for p in (1, 2, 4, 8):
+                    run(f"powerlaw_s{sv}_coo_panels{p}", Z, [("coo", "f64"), ("coo", "f32")], True,
+                        col_panels=p)
+                Z.close()
         elif w == "panels":
             Z = mxs.Matrix.from_host(ctx, I.zipf_random(2 ** 20, 1.79, 4096))
             for p in (1, 2, 4):
