@@ -563,10 +563,13 @@ class IRResult:
 
 def ir(A, b, low="f32", x0=None, tol=1e-10, outer_max=50, inner_tol=1e-4,
        inner_max=20000, last_step_variant=False, val32=None, h16=None, scale=None,
-       precond: Precond | None = None):
+       precond: Precond | None = None, carry_direction=False):
     """Iterative refinement; the low-precision copy is built by the oracle's
     own conversions unless passed in.  `precond` (from jacobi/block_jacobi)
-    preconditions the inner CG with its values rounded to FP32."""
+    preconditions the inner CG with its values rounded to FP32.
+    `carry_direction` keeps the inner CG's last direction across refinement
+    steps (ORC_IR_CARRY) instead of restarting it."""
+    flags = (1 if last_step_variant else 0) | (2 if carry_direction else 0)
     n, rp, ci, v = _csr(A)
     bb = _c(b, np.float64)
     x = np.zeros(n) if x0 is None else np.array(x0, np.float64, copy=True)
@@ -589,14 +592,14 @@ def ir(A, b, low="f32", x0=None, tol=1e-10, outer_max=50, inner_tol=1e-4,
     if precond is None:
         st = lib().orc_ir(n, _p(rp), _p(ci), _p(v), kind, _p(v32), _p(hh), _p(ss), _p(bb),
                           _p(x), tol, outer_max, inner_tol, inner_max,
-                          1 if last_step_variant else 0, C.byref(info))
+                          flags, C.byref(info))
     else:
         st_c, m32 = cast_f32(precond.minv)
         assert st_c == OK
         m32 = _c(m32, np.float32)
         st = lib().orc_ir_pc(n, _p(rp), _p(ci), _p(v), kind, _p(v32), _p(hh), _p(ss), _p(bb),
                              _p(x), tol, outer_max, inner_tol, inner_max,
-                             1 if last_step_variant else 0, precond.kind, precond.bs,
+                             flags, precond.kind, precond.bs,
                              _p(m32), C.byref(info))
     return IRResult(st, x, info.outer_iters, info.inner_iters_total, info.relres_true)
 

@@ -26,7 +26,13 @@
  *    per-entry tolerance of a GPU comparison measures the GPU alone.
  *  - Mixed-precision iterative refinement is not in the paper; it is the
  *    classical scheme (residual and update in FP64, correction solved in
- *    FP32) with the inner solver being the CG below run in float.
+ *    FP32) with the inner solver being the CG below run in float.  Its
+ *    carried-direction form keeps the inner CG's search direction from one
+ *    refinement step to the next: the FP64 residual then replaces the FP32
+ *    recurrence residual inside one continuing CG, the residual replacement
+ *    of van der Vorst & Ye (SIAM J. Sci. Comput. 22, 2000) used with a
+ *    low-precision iteration as in the "reliable updates" of Clark et al.
+ *    (Comput. Phys. Commun. 181, 2010).
  */
 #include "oracle.h"
 
@@ -1381,29 +1387,50 @@ static void low_prec_apply(int64_t n, int kind, int64_t bs, const float* minv,
 
 /* inner FP32 (preconditioned) CG from d = 0 on A_low d = f, to
  * ||r|| <= tol * ||f||; without a preconditioner z = r and this is plain CG */
+/* Inner CG in float on L d = f from d = 0 (Hestenes-Stiefel, as cg()
+ * above, with z = M^{-1} r).  p is the caller's direction vector.  When
+ * carry > 0 the first direction is not z but z + (rho / (carry * *rho_io)) p:
+ * p and *rho_io hold the last direction p_k and rho_k = r_k.z_k of the
+ * previous inner solve, and carry is the factor s by which that solve's
+ * normalised quantities grow when they are expressed relative to the new
+ * right-hand side (p_k becomes s p_k, rho_k becomes s^2 rho_k), so the
+ * first direction is the CG direction z + beta (s p_k) with
+ * beta = rho / (s^2 rho_k).  On return p and *rho_io hold this solve's
+ * last direction and its rho, and *usable says whether they may be carried
+ * (at least one step, and no breakdown).                                   */
 static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
                       int64_t maxit, int pc_kind, int64_t bs,
-                      const float* minv) {
+                      const float* minv, float* p, double carry, double* rho_io,
+                      int* usable) {
   int64_t n = L->n;
   float* r = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   float* z = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
-  float* p = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   float* q = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   for (int64_t i = 0; i < n; ++i) {
     d[i] = 0.0f;
     r[i] = f[i];
   }
   low_prec_apply(n, pc_kind, bs, minv, r, z);
-  ORC_PAR_FOR
-  for (int64_t i = 0; i < n; ++i) p[i] = z[i];
   float rho = fdot(n, r, z);
   float rr = fdot(n, r, r);
+  if (carry > 0.0) {
+    float c = (float)((double)rho / (carry * *rho_io));
+    ORC_PAR_FOR
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + c * p[i];
+  } else {
+    ORC_PAR_FOR
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+  }
   float thr = tol * sqrtf(rr);
   int64_t it = 0;
+  int broke = 0;
   while (sqrtf(rr) > thr && it < maxit) {
     low_matvec(L, p, q);
     float pq = fdot(n, p, q);
-    if (!(pq > 0.0f)) break;
+    if (!(pq > 0.0f)) {
+      broke = 1;
+      break;
+    }
     float alpha = rho / pq;
     ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) d[i] = d[i] + alpha * p[i];
@@ -1413,15 +1440,18 @@ static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
     float rho_new = fdot(n, r, z);
     rr = fdot(n, r, r);
     ++it;
-    if (sqrtf(rr) <= thr) break;
+    /* the last direction stays p_k with rho_k whether the tolerance or the
+     * step cap ends the solve */
+    if (sqrtf(rr) <= thr || it >= maxit) break;
     float beta = rho_new / rho;
     ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
     rho = rho_new;
   }
+  *rho_io = rho;
+  *usable = it > 0 && !broke && rho > 0.0f;
   free(r);
   free(z);
-  free(p);
   free(q);
   return it;
 }
@@ -1456,7 +1486,12 @@ int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
   double* r = vec(n);
   float* f = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   float* d = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+  float* p = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   int status = ORC_OK;
+  /* the previous step's residual norm, its inner rho and whether its last
+   * direction may be carried (ORC_IR_CARRY) */
+  double sigma_prev = 0.0, rho_prev = 0.0;
+  int usable = 0;
   for (;;) {
     residual(&A, b, x, r); /* FP64 residual with the FP64 matrix */
     double nr = nrm2(n, r);
@@ -1475,12 +1510,16 @@ int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
     ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) f[i] = (float)(r[i] / sigma);
     double tol = inner_tol;
-    if (last_step_variant && relres * inner_tol <= outer_tol) {
+    if ((last_step_variant & ORC_IR_LAST_STEP) && relres * inner_tol <= outer_tol) {
       double t2 = 0.1 * outer_tol / relres;
       if (t2 > tol) tol = t2;
     }
-    info->inner_iters_total +=
-        low_cg(&L, f, d, (float)tol, inner_max, pc_kind, bs, minv32);
+    /* carried direction: the previous normalised quantities grow by
+     * sigma_prev / sigma relative to the new right-hand side r / sigma */
+    double carry = ((last_step_variant & ORC_IR_CARRY) && usable) ? sigma_prev / sigma : 0.0;
+    info->inner_iters_total += low_cg(&L, f, d, (float)tol, inner_max, pc_kind, bs,
+                                      minv32, p, carry, &rho_prev, &usable);
+    sigma_prev = sigma;
     ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + sigma * (double)d[i];
     info->outer_iters++;
@@ -1488,5 +1527,6 @@ int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
   free(r);
   free(f);
   free(d);
+  free(p);
   return status;
 }

@@ -188,7 +188,16 @@ int orc_pagerank(int64_t n, const int32_t* rowptr, const int32_t* col,
 
 /* Mixed-precision iterative refinement: FP64 residual and update, inner CG
  * in FP32 on a low-precision copy of A.  low_kind 0: FP32 values (val32);
- * low_kind 1: FP16 values with a per-row power-of-two scale (h16, scale). */
+ * low_kind 1: FP16 values with a per-row power-of-two scale (h16, scale).
+ * last_step_variant holds flags: ORC_IR_LAST_STEP loosens the inner
+ * tolerance of the last step to max(inner_tol, 0.1*tol/relres) once
+ * relres*inner_tol <= tol; ORC_IR_CARRY starts each inner CG after the
+ * first from the previous one's last direction, rescaled to the new
+ * right-hand side (z + rho/(s rho_k) p_k with s = the previous residual
+ * norm over the new one), instead of from z, whenever the previous inner
+ * solve took a step and did not break down. */
+#define ORC_IR_LAST_STEP 1
+#define ORC_IR_CARRY 2
 typedef struct {
   int64_t outer_iters;
   int64_t inner_iters_total;

@@ -214,6 +214,47 @@ def test_ir_random_spd_small(orc):
         assert r.status == orc.OK and r.relres_true <= 1e-10
 
 
+@pytest.mark.parametrize("seed,cond,n", [(3, 30.0, 300), (5, 100.0, 400), (7, 10.0, 200)])
+def test_ir_carried_direction_follows_cg(orc, seed, cond, n):
+    """With the direction carried, refinement is one CG whose residual is
+    replaced by the FP64 one at each step: in exact arithmetic it makes
+    the iterates of plain CG.  After two steps x matches FP64 CG run for the
+    same total number of iterations to FP32 rounding, while the restarted
+    scheme stays about 3e-5 away (a wrong rescaling of the carried direction
+    sends it thousands of steps off, or back to the restarted iterates)."""
+    A = I.dense_to_csr(I.random_spd_small(n, cond, seed))
+    b = I.uniform_vector(n, seed + 1)
+    for carry in (False, True):
+        r = orc.ir(A, b, tol=1e-14, outer_max=2, inner_tol=1e-2, carry_direction=carry)
+        assert r.outer_iters == 2
+        ref = orc.cg(A, b, tol=0.0, maxit=r.inner_iters_total)
+        d = _relerr(r.x, ref.x)
+        if carry:
+            assert d <= 2e-6, d
+        else:
+            assert d >= 1e-5, d
+
+
+@pytest.mark.parametrize("low", ["f32", "f16"])
+def test_ir_carried_direction_poisson(orc, low):
+    A = I.poisson3d(24)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 7))
+    restart = orc.ir(A, b, low=low, tol=1e-10)
+    carry = orc.ir(A, b, low=low, tol=1e-10, carry_direction=True)
+    assert carry.status == orc.OK and orc.true_relres(A, b, carry.x) <= 1e-10
+    assert carry.outer_iters == restart.outer_iters
+    # carrying the direction removes most of the restarts' extra steps:
+    # within 20% of FP64 CG run to the same final residual (restarted: 139
+    # against 118 here, carried 134)
+    plain = orc.cg(A, b, tol=carry.relres_true)
+    assert carry.inner_iters_total < restart.inner_iters_total
+    assert carry.inner_iters_total <= 1.2 * plain.iters
+    # with a Jacobi inner solve too
+    st, M = orc.jacobi(A)
+    pc = orc.ir(A, b, low=low, tol=1e-10, carry_direction=True, precond=M)
+    assert pc.status == orc.OK and pc.relres_true <= 1e-10
+
+
 # ---------------------------------------------------------------------------
 # Jacobi / block-Jacobi preconditioned CG (Saad 2003, ch. 9-10)
 # ---------------------------------------------------------------------------
