@@ -1396,12 +1396,13 @@ static void low_prec_apply(int64_t n, int kind, int64_t bs, const float* minv,
  * right-hand side (p_k becomes s p_k, rho_k becomes s^2 rho_k), so the
  * first direction is the CG direction z + beta (s p_k) with
  * beta = rho / (s^2 rho_k).  On return p and *rho_io hold this solve's
- * last direction and its rho, and *usable says whether they may be carried
- * (at least one step, and no breakdown).                                   */
+ * last direction and its rho, *usable says whether they may be carried
+ * (at least one step, and no breakdown), and *reduction is the recurrence
+ * residual's final norm over its initial one.                             */
 static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
                       int64_t maxit, int pc_kind, int64_t bs,
                       const float* minv, float* p, double carry, double* rho_io,
-                      int* usable) {
+                      int* usable, double* reduction) {
   int64_t n = L->n;
   float* r = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   float* z = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
@@ -1422,6 +1423,7 @@ static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
     for (int64_t i = 0; i < n; ++i) p[i] = z[i];
   }
   float thr = tol * sqrtf(rr);
+  const float rr0 = rr;
   int64_t it = 0;
   int broke = 0;
   while (sqrtf(rr) > thr && it < maxit) {
@@ -1450,6 +1452,7 @@ static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
   }
   *rho_io = rho;
   *usable = it > 0 && !broke && rho > 0.0f;
+  *reduction = sqrt((double)rr / (double)rr0);
   free(r);
   free(z);
   free(q);
@@ -1488,9 +1491,10 @@ int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
   float* d = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   float* p = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   int status = ORC_OK;
-  /* the previous step's residual norm, its inner rho and whether its last
-   * direction may be carried (ORC_IR_CARRY) */
-  double sigma_prev = 0.0, rho_prev = 0.0;
+  /* the previous step's residual norm, its inner rho, the reduction its
+   * recurrence residual claimed and whether its last direction may be
+   * carried (ORC_IR_CARRY) */
+  double sigma_prev = 0.0, rho_prev = 0.0, claimed = 0.0;
   int usable = 0;
   for (;;) {
     residual(&A, b, x, r); /* FP64 residual with the FP64 matrix */
@@ -1515,10 +1519,15 @@ int orc_ir_pc(int64_t n, const int32_t* rowptr, const int32_t* col,
       if (t2 > tol) tol = t2;
     }
     /* carried direction: the previous normalised quantities grow by
-     * sigma_prev / sigma relative to the new right-hand side r / sigma */
-    double carry = ((last_step_variant & ORC_IR_CARRY) && usable) ? sigma_prev / sigma : 0.0;
+     * sigma_prev / sigma relative to the new right-hand side r / sigma.  It
+     * is carried only while the FP64 residual followed the recurrence the
+     * direction was built for: a true reduction sigma / sigma_prev more
+     * than twice the recurrence's own means the low-precision operator is
+     * too far from A for its directions to serve the next step. */
+    double carry = ((last_step_variant & ORC_IR_CARRY) && usable &&
+                    sigma <= 2.0 * claimed * sigma_prev) ? sigma_prev / sigma : 0.0;
     info->inner_iters_total += low_cg(&L, f, d, (float)tol, inner_max, pc_kind, bs,
-                                      minv32, p, carry, &rho_prev, &usable);
+                                      minv32, p, carry, &rho_prev, &usable, &claimed);
     sigma_prev = sigma;
     ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) x[i] = x[i] + sigma * (double)d[i];

@@ -195,7 +195,8 @@ int orc_pagerank(int64_t n, const int32_t* rowptr, const int32_t* col,
  * first from the previous one's last direction, rescaled to the new
  * right-hand side (z + rho/(s rho_k) p_k with s = the previous residual
  * norm over the new one), instead of from z, whenever the previous inner
- * solve took a step and did not break down. */
+ * solve took a step, did not break down, and the FP64 residual fell to at
+ * most twice the fraction its recurrence residual claimed. */
 #define ORC_IR_LAST_STEP 1
 #define ORC_IR_CARRY 2
 typedef struct {

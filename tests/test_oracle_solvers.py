@@ -235,6 +235,21 @@ def test_ir_carried_direction_follows_cg(orc, seed, cond, n):
             assert d >= 1e-5, d
 
 
+def test_ir_carried_direction_guard(orc):
+    """Row-scaled FP16 values of the random SPD matrix are too far from A
+    for the inner directions to serve the next step: the FP64 residual
+    falls by about three times what the FP16 recurrence claimed, so the
+    direction is never carried and the run is the restarted one exactly
+    (carried regardless, this system takes 11 times the inner steps)."""
+    A = I.random_spd(4000, seed=8)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 9))
+    restart = orc.ir(A, b, low="f16", tol=1e-10)
+    carry = orc.ir(A, b, low="f16", tol=1e-10, carry_direction=True)
+    assert carry.status == orc.OK and carry.relres_true <= 1e-10
+    assert carry.inner_iters_total == restart.inner_iters_total
+    assert np.array_equal(carry.x, restart.x)
+
+
 @pytest.mark.parametrize("low", ["f32", "f16"])
 def test_ir_carried_direction_poisson(orc, low):
     A = I.poisson3d(24)
