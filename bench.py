@@ -511,15 +511,18 @@ def main():
             nxs = float(torch.linalg.norm(xstar))
             store = sols.setdefault(name, {})
 
-            def run(label, fn):
-                xq.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                res = fn()
-                torch.cuda.synchronize()
-                t_ = time.perf_counter() - t0
+            def run(label, fn, reps=3):
+                # full solves from x = 0, median wall time of `reps`
+                ts = []
+                for _ in range(reps):
+                    xq.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    res = fn()
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
                 store[("iterative_refinement", label)] = xq.cpu().numpy()
-                return res, t_, float(torch.linalg.norm(xq - xstar)) / nxs
+                return res, float(np.median(ts)), float(torch.linalg.norm(xq - xstar)) / nxs
 
             r, t_plain, err = run("plain_f64_cg", lambda: mxs.solve(
                 ctx, "cg", Qm, bq, xq, tol=1e-10, raise_on_error=False))
@@ -550,12 +553,16 @@ def main():
             for P in pcs.values():
                 P.close()
             for low in ("f32", "f16"):
-                for variant in (False, True):
+                for carry, variant in ((False, False), (False, True), (True, False),
+                                       (True, True)):
                     L = Qm.convert("csr", low)
-                    label = f"ir_{low}{'_laststep' if variant else ''}"
-                    ri, t_ir, err = run(label, lambda L=L, variant=variant: mxs.solve_ir(
-                        ctx, Qm, L, bq, xq, tol=1e-10, last_step_variant=variant,
-                        raise_on_error=False))
+                    label = (f"ir_{low}{'_carry' if carry else ''}"
+                             f"{'_laststep' if variant else ''}")
+                    ri, t_ir, err = run(label, lambda L=L, variant=variant, carry=carry:
+                                        mxs.solve_ir(ctx, Qm, L, bq, xq, tol=1e-10,
+                                                     last_step_variant=variant,
+                                                     carry_direction=carry,
+                                                     raise_on_error=False))
                     e[label] = {
                         "outer": ri.outer_iters, "inner_total": ri.inner_iters_total,
                         "status": ri.status, "relres_true": ri.relres_true,

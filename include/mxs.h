@@ -374,13 +374,30 @@ typedef struct {
  * (FP32 vectors and accumulation) to inner_rel_tol and update
  * x += ||r|| d in FP64.  A64: F64 CSR; A_low: F32 or F16_ROWSCALED CSR with
  * the same pattern (any other value type of either, complex ones included,
- * returns MXS_UNSUPPORTED before any work is enqueued).  last_step_variant != 0 loosens the inner tolerance to
- * max(inner_rel_tol, 0.1*tol/relres) once relres*inner_rel_tol <= tol.
+ * returns MXS_UNSUPPORTED before any work is enqueued).  `variant` holds
+ * flags:
+ *   MXS_IR_LAST_STEP loosens the inner tolerance to
+ *     max(inner_rel_tol, 0.1*tol/relres) once relres*inner_rel_tol <= tol;
+ *   MXS_IR_CARRY_DIRECTION starts every inner CG after the first from the
+ *     previous one's last direction p_k, rescaled to the new right-hand side,
+ *     instead of from z = M^{-1} f: with s = (previous ||r||) / (new ||r||),
+ *     p = z + (f.z / (s rho_k)) p_k, rho_k = r_k.z_k of that last step.  The
+ *     FP64 residual then replaces the FP32 recurrence residual inside one
+ *     continuing CG (residual replacement, van der Vorst & Ye, SIAM J. Sci.
+ *     Comput. 22, 2000; with a low-precision iteration as in the "reliable
+ *     updates" of Clark et al., Comput. Phys. Commun. 181, 2010), so the
+ *     inner steps do not start over at every refinement step.  A previous
+ *     solve that took no step or broke down is not carried, nor one after
+ *     which the FP64 residual fell by more than twice the fraction its FP32
+ *     recurrence residual claimed (A_low too far from A64 for its
+ *     directions to serve the next step: the step restarts instead).
  * inner_precond (nullable, built from A64) turns the inner solve into
  * preconditioned CG with the FP32 copy of M.  Synchronises the ctx stream. */
+#define MXS_IR_LAST_STEP 1
+#define MXS_IR_CARRY_DIRECTION 2
 mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A_low,
                         const double* b, double* x, const mxs_stop* outer,
-                        double inner_rel_tol, int64_t inner_max, int32_t last_step_variant,
+                        double inner_rel_tol, int64_t inner_max, int32_t variant,
                         const mxs_precond* inner_precond, mxs_ir_info* info);
 
 /* ---------------------------------------------------------------------- */

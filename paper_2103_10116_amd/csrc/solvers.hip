@@ -837,6 +837,16 @@ __global__ __launch_bounds__(RB) void k_add(int64_t n, double* __restrict__ x,
       [&](int64_t i, const Pack<double, 2>& e) { x[i] = e.v[0] + e.v[1]; });
 }
 
+// p = z + c p in float: the first direction of an inner solve that carries
+// the previous solve's last direction (c rescales it to the new right-hand
+// side and is the CG coefficient beta)
+__global__ __launch_bounds__(RB) void k_ir_carry(int64_t n, const float* __restrict__ z,
+                                                 float* __restrict__ p, float c) {
+  strided4(
+      n, [&](int64_t i) { return Pack<float, 2>{{z[i], p[i]}}; },
+      [&](int64_t i, const Pack<float, 2>& e) { p[i] = e.v[0] + c * e.v[1]; });
+}
+
 // x += sigma * double(d)
 __global__ __launch_bounds__(RB) void k_ir_update(int64_t n, double* __restrict__ x,
                                                   const float* __restrict__ d, double sigma) {
@@ -2173,7 +2183,7 @@ mxs_status solve_dispatch(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, co
 
 mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* Al,
                          const double* b, double* x, const mxs_stop* outer, double inner_tol,
-                         int64_t inner_max, int last_step_variant, const mxs_precond* M,
+                         int64_t inner_max, int variant, const mxs_precond* M,
                          mxs_ir_info* info) {
   const int64_t n = A64->n;
   const size_t ld = align_up((size_t)n, 64);
@@ -2204,6 +2214,14 @@ mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* 
   const int g = red_grid(n);
   KState& h = *w.hst;
   mxs_status result = MXS_OK;
+  const bool last_step = (variant & MXS_IR_LAST_STEP) != 0;
+  const bool carry = (variant & MXS_IR_CARRY_DIRECTION) != 0;
+  // what the carried direction needs from the previous inner solve: its
+  // residual norm sigma, its last rho = r_k.z_k, the reduction its
+  // recurrence residual claimed, and whether it took a step without
+  // breaking down (pf then still holds its last direction p_k)
+  double nr_prev = 0.0, rho_prev = 0.0, claimed = 0.0;
+  bool usable = false;
   for (;;) {
     double nr2;
     if ((s = residual(ctx, A64, b, x, r))) return s;
@@ -2221,22 +2239,34 @@ mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* 
       break;
     }
     double itol = inner_tol;
-    if (last_step_variant && relres * inner_tol <= tol) itol = std::max(itol, 0.1 * tol / relres);
+    if (last_step && relres * inner_tol <= tol) itol = std::max(itol, 0.1 * tol / relres);
     // inner FP32 CG from d = 0 on A_low d = f, f = r / ||r||
     k_ir_scale<<<g, RB, 0, ctx->stream>>>(n, r, nr, rf);
     MXS_HIP_TRY(ctx, hipMemsetAsync(d, 0, n * sizeof(float), ctx->stream));
     double f2, rz;
+    // z = M^{-1} f (z = f without a preconditioner), rho = f.z
+    const float* z0 = rf;
     if (M) {
-      // preconditioned inner solve: z = M^{-1} f, rho = f.z, p = z
       apply_precond<float>(ctx, M, M->m32, n, rf, zf);
       if ((s = dots<float>(ctx, w, n, rf, rf, rf, zf, &f2, &rz))) return s;
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(pf, zf, n * sizeof(float), hipMemcpyDeviceToDevice,
-                                      ctx->stream));
+      z0 = zf;
     } else {
-      MXS_HIP_TRY(ctx, hipMemcpyAsync(pf, rf, n * sizeof(float), hipMemcpyDeviceToDevice,
-                                      ctx->stream));
       if ((s = dots<float>(ctx, w, n, rf, rf, nullptr, nullptr, &f2, nullptr))) return s;
       rz = f2;
+    }
+    // carried only while the FP64 residual followed the recurrence the
+    // direction was built for: a true reduction nr / nr_prev more than twice
+    // the recurrence's own means A_low is too far from A64 for its
+    // directions to serve the next step
+    if (carry && usable && nr <= 2.0 * claimed * nr_prev) {
+      // the previous solve's quantities, normalised by nr_prev, grow by
+      // sc = nr_prev / nr against f: p_k -> sc p_k, rho_k -> sc^2 rho_k, so
+      // the CG direction is z + beta sc p_k with beta = rz / (sc^2 rho_k)
+      const double sc = nr_prev / nr;
+      k_ir_carry<<<g, RB, 0, ctx->stream>>>(n, z0, pf, (float)(rz / (sc * rho_prev)));
+    } else {
+      MXS_HIP_TRY(ctx, hipMemcpyAsync(pf, z0, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                      ctx->stream));
     }
     std::memset(&h, 0, sizeof(KState));
     h.rho[0] = rz;
@@ -2253,6 +2283,13 @@ mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* 
       if (s) return s;
     }
     out.inner_iters_total += h.iters;
+    // the inner kernels leave p_k in pf and rho_k in rho[k & 1] when the
+    // tolerance or the step cap stops iteration k
+    usable = h.iters > 0 && (h.done == ST_CONVERGED || h.done == ST_MAXIT) &&
+             h.rho[(h.iters - 1) & 1] > 0.0;
+    rho_prev = usable ? h.rho[(h.iters - 1) & 1] : 0.0;
+    claimed = sqrt(h.res2 / f2);
+    nr_prev = nr;
     if (h.done == ST_NONFINITE) {
       result = fail(ctx, MXS_NONFINITE, "non-finite value in the inner solve");
       break;
@@ -2290,7 +2327,7 @@ mxs_status mxs_solve(mxs_ctx* ctx, mxs_solver kind, const mxs_matrix* A, const d
 
 mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A_low,
                         const double* b, double* x, const mxs_stop* outer,
-                        double inner_rel_tol, int64_t inner_max, int32_t last_step_variant,
+                        double inner_rel_tol, int64_t inner_max, int32_t variant,
                         const mxs_precond* inner_precond, mxs_ir_info* info) {
   if (!ctx || !A64 || !A_low) return MXS_INVALID_ARG;
   if (A64->dt != MXS_F64 || (A_low->dt != MXS_F32 && A_low->dt != MXS_F16_ROWSCALED))
@@ -2306,7 +2343,7 @@ mxs_status mxs_solve_ir(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* A
   if (inner_precond && inner_precond->n != A64->n)
     return fail(ctx, MXS_INVALID_ARG, "preconditioner size differs");
   return solve_ir_impl(ctx, A64, A_low, b, x, outer, inner_rel_tol, inner_max,
-                       last_step_variant, inner_precond, info);
+                       variant, inner_precond, info);
 }
 
 mxs_status mxs_graph_create(mxs_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr,

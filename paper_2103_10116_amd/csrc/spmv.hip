@@ -875,6 +875,11 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
 // of one column slice; rid gives each stacked row's slot p*n + i): a row's
 // sum is stored as is (no alpha, beta, scale) to y[rid[row]], the panel
 // partials that k_panel_add joins.
+//
+// dchunk (not with PANEL; alpha = 1, beta = 0): each chunk also stores the
+// sum of x[row] * s over the partial sums s it emits, cut rows' pieces
+// included, so the chunks' values add up to x.y (CG's p.q) once k_coo_fix
+// has completed the cut rows: x_r (s_1 + s_2) = x_r s_1 + x_r s_2.
 template <typename V, typename T, int NPL, int WPB, bool SCALED, bool PANEL>
 __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nchunks,
                                                        const int32_t* __restrict__ rowptr,
@@ -887,7 +892,8 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nch
                                                        T alpha, T beta,
                                                        int32_t* __restrict__ cont_row,
                                                        T* __restrict__ cont_val,
-                                                       const int32_t* __restrict__ skip) {
+                                                       const int32_t* __restrict__ skip,
+                                                       double* __restrict__ dchunk) {
   constexpr int C = 64 * NPL;
   if (skip && *skip) return;
   __shared__ T prod_all[WPB][C + C / 32];
@@ -952,8 +958,10 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nch
 
   // a row's partial sums are scaled (FP16 values with per-row scales) before
   // they are stored or joined by the fix-up pass
+  double dacc = 0.0;
   auto emit = [&](int32_t rr, T sum) {
     if (SCALED) sum *= (T)scale[rr];
+    if (!PANEL && dchunk) dacc += (double)x[rr] * (double)sum;
     if (first_continues && rr == first) {
       cont_row[ch] = rr;
       cont_val[ch] = sum;
@@ -1017,23 +1025,44 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_merge(int64_t nnz, int64_t nch
       emit(hrow, vs);
     }
   }
+  if (!PANEL && dchunk) {
+    const double t = wave_total(dacc);
+    if (lane == 0) dchunk[ch] = t;
+  }
 }
 
 // Adds the continuation partials of rows that straddle chunks, in chunk
 // order, to the value their first chunk wrote (at y[rid[r]] when rid is
-// given: the stacked rows of column panels).
+// given: the stacked rows of column panels).  With dpart (256 threads a
+// work-group) each work-group also stores the sum of its chunks' dchunk
+// values, in chunk order, to dpart[blockIdx.x].
 template <typename T>
-__global__ void k_coo_fix(int64_t nchunks, const int32_t* __restrict__ cont_row,
-                          const T* __restrict__ cont_val, T* __restrict__ y, T alpha,
-                          const int32_t* __restrict__ skip, const int32_t* __restrict__ rid) {
+__global__ __launch_bounds__(256) void k_coo_fix(int64_t nchunks,
+                                                 const int32_t* __restrict__ cont_row,
+                                                 const T* __restrict__ cont_val,
+                                                 T* __restrict__ y, T alpha,
+                                                 const int32_t* __restrict__ skip,
+                                                 const int32_t* __restrict__ rid,
+                                                 const double* __restrict__ dchunk = nullptr,
+                                                 double* __restrict__ dpart = nullptr) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nchunks || (skip && *skip)) return;
-  const int32_t r = cont_row[c];
-  if (r < 0 || (c > 0 && cont_row[c - 1] == r)) return;
-  T sum = cont_val[c];
-  for (int64_t d = c + 1; d < nchunks && cont_row[d] == r; ++d) sum += cont_val[d];
-  const int64_t i = rid ? rid[r] : r;
-  y[i] = y[i] + alpha * sum;
+  const bool on = c < nchunks && !(skip && *skip);
+  if (on) {
+    const int32_t r = cont_row[c];
+    if (r >= 0 && !(c > 0 && cont_row[c - 1] == r)) {
+      T sum = cont_val[c];
+      for (int64_t d = c + 1; d < nchunks && cont_row[d] == r; ++d) sum += cont_val[d];
+      const int64_t i = rid ? rid[r] : r;
+      y[i] = y[i] + alpha * sum;
+    }
+  }
+  if (dpart) {
+    __shared__ double red[4];
+    const double t = wave_total(on ? dchunk[c] : 0.0);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) dpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
 }
 
 // Column panels: y_i = alpha * s_i * (sum of row i's panel partials, in
@@ -1299,34 +1328,36 @@ Cont cont_of(void* scratch, int64_t nchunks) {
 
 template <typename V, typename T, int NPL, int WPB, bool SCALED, bool PANEL>
 void launch_csr_merge_w(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
-                        T beta, T* y, const int32_t* skip, Cont c) {
+                        T beta, T* y, const int32_t* skip, Cont c, double* dchunk) {
   const dim3 grid((unsigned)((P.nchunks + WPB - 1) / WPB));
   if constexpr (PANEL)
     k_csr_merge<V, T, NPL, WPB, false, true><<<grid, 64 * WPB, 0, ctx->stream>>>(
         nnz, P.nchunks, P.srowptr, P.crow, P.scol, (const V*)P.sval, nullptr, P.srid, x, y,
-        T(1), T(0), c.row, (T*)c.val, skip);
+        T(1), T(0), c.row, (T*)c.val, skip, nullptr);
   else
     k_csr_merge<V, T, NPL, WPB, SCALED, false><<<grid, 64 * WPB, 0, ctx->stream>>>(
         nnz, P.nchunks, P.rowptr, P.crow, P.col, (const V*)P.val, P.scale, nullptr, x, y,
-        alpha, beta, c.row, (T*)c.val, skip);
+        alpha, beta, c.row, (T*)c.val, skip, dchunk);
 }
 
 template <typename V, typename T, int NPL, bool SCALED, bool PANEL>
 void launch_csr_merge_n(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
-                        T beta, T* y, const int32_t* skip, Cont c) {
+                        T beta, T* y, const int32_t* skip, Cont c, double* dchunk) {
   if (P.wpb == 1)
-    launch_csr_merge_w<V, T, NPL, 1, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c);
+    launch_csr_merge_w<V, T, NPL, 1, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c,
+                                                     dchunk);
   else
-    launch_csr_merge_w<V, T, NPL, 4, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c);
+    launch_csr_merge_w<V, T, NPL, 4, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c,
+                                                     dchunk);
 }
 
 template <typename V, typename T, bool SCALED, bool PANEL>
 void launch_csr_merge_c(mxs_ctx* ctx, const CsrPart& P, int64_t nnz, T alpha, const T* x,
-                        T beta, T* y, const int32_t* skip, Cont c) {
+                        T beta, T* y, const int32_t* skip, Cont c, double* dchunk = nullptr) {
   switch (P.block_nnz) {
-    case 256: launch_csr_merge_n<V, T, 4, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c); break;
-    case 512: launch_csr_merge_n<V, T, 8, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c); break;
-    default: launch_csr_merge_n<V, T, 16, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c);
+    case 256: launch_csr_merge_n<V, T, 4, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c, dchunk); break;
+    case 512: launch_csr_merge_n<V, T, 8, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c, dchunk); break;
+    default: launch_csr_merge_n<V, T, 16, SCALED, PANEL>(ctx, P, nnz, alpha, x, beta, y, skip, c, dchunk);
   }
 }
 
@@ -1339,7 +1370,11 @@ size_t cont_bytes(int64_t nchunks) {
 
 // merge-path CSR: empty rows, the chunks, then the fix-up of cut rows; with
 // column panels: the stacked chunks into the panel partials (scratch after
-// the continuation partials), their fix-up, then the pass that adds them
+// the continuation partials), their fix-up, then the pass that adds them.
+// With dpart (CG's q = A p, alpha = 1, beta = 0) the partials of p.q go to
+// dpart and their count to *ndpart: from the panel-adding pass, or without
+// panels from the fix-up pass over the chunks' own sums (scratch after the
+// continuation partials), one per 256 chunks.
 template <typename V, typename T, bool SCALED>
 void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, T* y,
                       const int32_t* skip, void* scratch, double* dpart = nullptr,
@@ -1370,10 +1405,20 @@ void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T 
         P.nempty, P.empty_rows, y, beta, skip);
   if (P.nchunks == 0) return;
   const Cont c = cont_of(scratch, P.nchunks);
+  const unsigned gf = (unsigned)((P.nchunks + 255) / 256);
+  if (dpart) {
+    double* dchunk = (double*)((char*)scratch + cont_bytes(P.nchunks));
+    launch_csr_merge_c<V, T, SCALED, false>(ctx, P, A->nnz, alpha, x, beta, y, skip, c,
+                                            dchunk);
+    k_coo_fix<T><<<gf, 256, 0, ctx->stream>>>(P.nchunks, c.row, (T*)c.val, y, alpha, skip,
+                                              nullptr, dchunk, dpart);
+    *ndpart = (int)gf;
+    return;
+  }
   launch_csr_merge_c<V, T, SCALED, false>(ctx, P, A->nnz, alpha, x, beta, y, skip, c);
   if (P.nchunks > 1)
-    k_coo_fix<T><<<(unsigned)((P.nchunks + 255) / 256), 256, 0, ctx->stream>>>(
-        P.nchunks, c.row, (T*)c.val, y, alpha, skip, nullptr);
+    k_coo_fix<T><<<gf, 256, 0, ctx->stream>>>(P.nchunks, c.row, (T*)c.val, y, alpha, skip,
+                                              nullptr);
 }
 
 template <typename V, typename T, bool SCALED>
@@ -1646,7 +1691,7 @@ int launch_dot_typed(mxs_ctx* ctx, const mxs_matrix* A, const T* x, T* y, const 
       return launch_csr_rl_dot<V, T, SCALED, 1024>(ctx, P, x, y, skip, dpart);
     return launch_csr_rl_dot<V, T, SCALED, 2048>(ctx, P, x, y, skip, dpart);
   }
-  if (P.merge && P.panels > 1 && P.nchunks > 0) {
+  if (P.merge && P.nchunks > 0 && (P.panels > 1 || (P.nchunks + 255) / 256 <= kDotPartials)) {
     if constexpr (std::is_same_v<V, double> || std::is_same_v<V, float> ||
                   std::is_same_v<V, _Float16>) {
       int nd = 0;
@@ -1661,8 +1706,10 @@ int launch_spmv_dot(mxs_ctx* ctx, const mxs_matrix* A, const void* x, void* y,
                     const int32_t* skip, double* dpart) {
   if (A->fmt != MXS_CSR || A->n == 0 || A->n != A->ncols) return 0;
   const CsrPart& P = A->csr;
-  if (!(P.rows_lds && P.nblocks > 0) && !(P.merge && P.panels > 1 && P.nchunks > 0)) return 0;
-  const size_t need = spmv_scratch_bytes(A);
+  if (!(P.rows_lds && P.nblocks > 0) && !(P.merge && P.nchunks > 0)) return 0;
+  // the merge path without panels also keeps one dot partial per chunk
+  const size_t need = spmv_scratch_bytes(A) +
+                      (P.merge && P.panels <= 1 ? (size_t)P.nchunks * sizeof(double) : 0);
   if (need > ctx->spmv_ws.bytes) {
     if (ctx->spmv_ws.ptr) {
       if (hipStreamSynchronize(ctx->stream) != hipSuccess) return 0;

@@ -38,6 +38,7 @@ DTYPES = {"f64": F64, "f32": F32, "f16": F16_ROWSCALED, "c128": C128, "c64": C64
 CG, BICGSTAB, GMRES, CGS, PIPECG = 0, 1, 2, 3, 4
 SOLVERS = {"cg": CG, "bicgstab": BICGSTAB, "gmres": GMRES, "cgs": CGS, "pipecg": PIPECG}
 HOST_PTRS, DEVICE_PTRS, SORT_AND_SUM = 0, 1, 2
+IR_LAST_STEP, IR_CARRY_DIRECTION = 1, 2
 
 (ARR_ROWPTR, ARR_COL, ARR_VAL, ARR_ROW, ARR_ELL_COL, ARR_ELL_VAL,
  ARR_COO_ROW, ARR_COO_COL, ARR_COO_VAL, ARR_SCALE) = range(10)
@@ -563,15 +564,19 @@ class IRResult:
 
 def solve_ir(ctx: Context, A64: Matrix, Alow: Matrix, b, x, tol=1e-10, outer_max=50,
              inner_tol=1e-4, inner_max=20000, last_step_variant=False, check_every=0,
-             raise_on_error=True, precond: Precond | None = None):
+             raise_on_error=True, precond: Precond | None = None, carry_direction=False):
     """mxs_solve_ir: FP64 refinement around an FP32 CG on the low-precision
-    copy (preconditioned with the FP32 copy of `precond` when given)."""
+    copy (preconditioned with the FP32 copy of `precond` when given);
+    `carry_direction` keeps the inner CG's direction across refinement steps
+    (MXS_IR_CARRY_DIRECTION)."""
+    flags = (IR_LAST_STEP if last_step_variant else 0) | \
+        (IR_CARRY_DIRECTION if carry_direction else 0)
     import torch
     st = Stop(int(outer_max), float(tol), 0.0, 0, int(check_every), -1)
     info = IRInfo()
     s = _lib.mxs_solve_ir(ctx.handle, A64.handle, Alow.handle, _vec(b, A64.n, torch.float64),
                           _vec(x, A64.n, torch.float64), C.byref(st), float(inner_tol),
-                          int(inner_max), 1 if last_step_variant else 0,
+                          int(inner_max), flags,
                           precond.handle if precond is not None else None, C.byref(info))
     if raise_on_error and s != OK:
         _check(s, ctx)

@@ -63,6 +63,8 @@ def test_binding_structs_match_header(tmp_path):
     lines.append('  printf("mxs_batch_request size %zu\\n", sizeof(mxs_batch_request));')
     for f in req.names:
         lines.append(f'  printf("mxs_batch_request {f} %zu\\n", offsetof(mxs_batch_request, {f}));')
+    for macro in ("MXS_IR_LAST_STEP", "MXS_IR_CARRY_DIRECTION"):
+        lines.append(f'  printf("define {macro} %d\\n", {macro});')
     lines.append("  return 0;\n}")
     src = tmp_path / "sizes.c"
     src.write_text("\n".join(lines))
@@ -75,6 +77,8 @@ def test_binding_structs_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+    assert got[("define", "MXS_IR_LAST_STEP")] == mxs.IR_LAST_STEP
+    assert got[("define", "MXS_IR_CARRY_DIRECTION")] == mxs.IR_CARRY_DIRECTION
     assert got[("mxs_batch_request", "size")] == req.itemsize
     for f in req.names:
         assert got[("mxs_batch_request", f)] == req.fields[f][1], f

@@ -152,14 +152,16 @@ def test_cg_paths_agree(env, orc):
 
 _DOT_CASES = {"rows_lds": ("poisson3d", "csr", {}),
               "panels": ("spd", "csr", dict(csr_kernel="merge", col_panels=4)),
+              "merge": ("spd", "csr", dict(csr_kernel="merge", col_panels=1)),
               "separate_pq": ("poisson3d", "coo", {})}
 
 
 @pytest.mark.parametrize("case", sorted(_DOT_CASES))
 def test_cg_three_launch_iteration(env, orc, case):
     """CG's iteration in three launches, on products that form p.q in their
-    own launches (rows-from-LDS CSR, merge path over column panels) and on
-    one that does not (COO, with a separate reduction): the oracle's
+    own launches (rows-from-LDS CSR, merge path over column panels, merge
+    path whose chunks sum their own pieces of p.q) and on one that does not
+    (COO, with a separate reduction): the oracle's
     residual meets 1e-10 and the iterations stay within 3 (or 10%) of the
     oracle's CG; after max_iters = 3 the iterate equals three steps of the
     oracle's CG (every block applied the last x update); a tolerance below
@@ -177,6 +179,8 @@ def test_cg_three_launch_iteration(env, orc, case):
         assert d["csr_kernel"] == mxs.CSR_ROWS_LDS
     if case == "panels":
         assert d["csr_kernel"] == mxs.CSR_MERGE and d["col_panels"] == 4
+    if case == "merge":
+        assert d["csr_kernel"] == mxs.CSR_MERGE and d["col_panels"] <= 1
     x = _dev(torch, np.zeros(A.n))
     r = mxs.solve(ctx, "cg", B, _dev(torch, b), x, tol=1e-10)
     _assert_converged(orc, A, b, x.cpu().numpy(), r, 1e-10)
@@ -336,6 +340,100 @@ def test_ir_poisson3d(env, orc, low, variant):
     assert np.linalg.norm(xh - cg.x) <= 1e-8 * np.linalg.norm(cg.x)
 
 
+@pytest.mark.parametrize("low", ["f32", "f16"])
+@pytest.mark.parametrize("last_step", [False, True])
+def test_ir_carried_direction_poisson3d(env, orc, low, last_step):
+    """Refinement whose inner CG carries its direction across steps: meets
+    the FP64 tolerance by the oracle's residual, takes the oracle's outer
+    steps and about its inner steps, and fewer inner steps than restarting."""
+    mxs, ctx, torch = env
+    A = I.poisson3d(24)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 25))
+    M = mxs.Matrix.from_host(ctx, A)
+    L = M.convert("csr", low)
+    bd = _dev(torch, b)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r = mxs.solve_ir(ctx, M, L, bd, x, tol=1e-10, last_step_variant=last_step,
+                     carry_direction=True)
+    xh = x.cpu().numpy()
+    assert r.status == mxs.OK
+    assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
+    ref = orc.ir(A, b, low=low, tol=1e-10, last_step_variant=last_step, carry_direction=True)
+    assert abs(r.outer_iters - ref.outer_iters) <= 1
+    # the oracle rounds CG's scalars to float, the GPU keeps them in FP64:
+    # inner step counts differ by a few per cent (most at the loose last step)
+    assert abs(r.inner_iters_total - ref.inner_iters_total) <= 0.1 * ref.inner_iters_total + 2
+    x2 = torch.zeros_like(x)
+    restart = mxs.solve_ir(ctx, M, L, bd, x2, tol=1e-10, last_step_variant=last_step)
+    assert r.inner_iters_total < restart.inner_iters_total
+    cg = orc.cg(A, b, tol=1e-12)
+    assert np.linalg.norm(xh - cg.x) <= 1e-8 * np.linalg.norm(cg.x)
+
+
+@pytest.mark.parametrize("seed,cond,n", [(3, 30.0, 300), (7, 10.0, 200)])
+def test_ir_carried_direction_follows_cg(env, orc, seed, cond, n):
+    """Two refinement steps with the direction carried give the iterate of
+    FP64 CG run for the same total number of steps, to FP32 rounding; the
+    restarted scheme does not (the oracle pins the same property)."""
+    mxs, ctx, torch = env
+    A = I.dense_to_csr(I.random_spd_small(n, cond, seed))
+    b = I.uniform_vector(n, seed + 1)
+    M = mxs.Matrix.from_host(ctx, A)
+    L = M.convert("csr", "f32")
+    for carry in (False, True):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        r = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-14, outer_max=2, inner_tol=1e-2,
+                         carry_direction=carry, raise_on_error=False)
+        assert r.status == mxs.NOT_CONVERGED and r.outer_iters == 2
+        ref = orc.cg(A, b, tol=0.0, maxit=r.inner_iters_total)
+        d = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+        if carry:
+            assert d <= 2e-6, d
+        else:
+            assert d >= 1e-5, d
+
+
+def test_ir_carried_direction_guard(env, orc):
+    """Row-scaled FP16 values of the random SPD matrix: the FP64 residual
+    does not follow the FP16 recurrence, so no direction is carried and the
+    result is the restarted refinement's bit for bit (the oracle pins the
+    same guard on this system)."""
+    mxs, ctx, torch = env
+    A = I.random_spd(4000, seed=8)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 9))
+    M = mxs.Matrix.from_host(ctx, A)
+    L = M.convert("csr", "f16")
+    out = []
+    for carry in (False, True):
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        r = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-10, carry_direction=carry)
+        assert r.status == mxs.OK
+        out.append((r.inner_iters_total, x.cpu().numpy()))
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_ir_carried_direction_jacobi_inner(env, orc):
+    mxs, ctx, torch = env
+    A = I.random_spd(20000, seed=26)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 27))
+    M = mxs.Matrix.from_host(ctx, A)
+    P = mxs.Precond(ctx, M, "jacobi")
+    for low in ("f32", "f16"):
+        L = M.convert("csr", low)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        r = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-10, precond=P,
+                         carry_direction=True)
+        xh = x.cpu().numpy()
+        assert r.status == mxs.OK
+        assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
+        ref = orc.ir(A, b, low=low, tol=1e-10, precond=orc.jacobi(A)[1], carry_direction=True)
+        assert abs(r.outer_iters - ref.outer_iters) <= 1
+        assert abs(r.inner_iters_total - ref.inner_iters_total) <= 0.1 * ref.inner_iters_total + 2
+        L.close()
+    P.close()
+
+
 def test_ir_random_spd(env, orc):
     mxs, ctx, torch = env
     A = I.random_spd(20000, seed=26)
@@ -376,7 +474,8 @@ def test_ir_refuses_other_value_types(env):
 @pytest.mark.parametrize("system", ["poisson3d_128", "random_spd_2p20"])
 def test_full_size_ir(env, orc, system):
     """Mixed-precision refinement at full size (FP32 and row-scaled FP16
-    storage, literal and last-step inner tolerance): the oracle's FP64
+    storage, literal and last-step inner tolerance, restarted and carried
+    inner directions): the oracle's FP64
     residual of every result meets 1e-10, and its distance to the oracle's
     FP64 solution of the same system (single thread: CG on the Poisson
     matrix, Jacobi-preconditioned CG on the random SPD one) stays within
@@ -406,11 +505,12 @@ def test_full_size_ir(env, orc, system):
     bd = _dev(torch, b)
     for low in ("f32", "f16"):
         L = M.convert("csr", low)
-        for variant in (False, True):
+        for variant, carry in ((False, False), (True, False), (False, True), (True, True)):
             x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-            r = mxs.solve_ir(ctx, M, L, bd, x, tol=1e-10, last_step_variant=variant)
+            r = mxs.solve_ir(ctx, M, L, bd, x, tol=1e-10, last_step_variant=variant,
+                             carry_direction=carry)
             xh = x.cpu().numpy()
-            assert r.status == mxs.OK, (low, variant, r)
+            assert r.status == mxs.OK, (low, variant, carry, r)
             rel = orc.true_relres(A, b, xh)
             assert rel <= 1e-10 + _eval_slack(orc, A, b, xh), (low, variant, rel)
             err = np.linalg.norm(xh - ref.x) / nxo
