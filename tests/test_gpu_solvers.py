@@ -393,6 +393,32 @@ def test_ir_carried_direction_follows_cg(env, orc, seed, cond, n):
             assert d >= 1e-5, d
 
 
+@pytest.mark.parametrize("cap", [5, 10])
+def test_ir_carried_direction_capped_inner(env, orc, cap):
+    """Inner solves cut off after `cap` steps (each ends at its step cap,
+    and the direction is still carried): the refinement takes about CG's
+    own step count, as the oracle's does, where restarting takes several
+    times as many."""
+    mxs, ctx, torch = env
+    A = I.poisson3d(24)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 25))
+    M = mxs.Matrix.from_host(ctx, A)
+    L = M.convert("csr", "f32")
+    ref = orc.ir(A, b, tol=1e-10, inner_max=cap, outer_max=200, carry_direction=True)
+    cg = orc.cg(A, b, tol=1e-10)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-10, inner_max=cap, outer_max=200,
+                     carry_direction=True)
+    xh = x.cpu().numpy()
+    assert r.status == mxs.OK
+    assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
+    assert abs(r.outer_iters - ref.outer_iters) <= 2
+    assert r.inner_iters_total <= 1.05 * cg.iters + 2
+    x2 = torch.zeros_like(x)
+    rr = mxs.solve_ir(ctx, M, L, _dev(torch, b), x2, tol=1e-10, inner_max=cap, outer_max=200)
+    assert rr.status == mxs.OK and rr.inner_iters_total >= 2 * cg.iters
+
+
 def test_ir_carried_direction_guard(env, orc):
     """Row-scaled FP16 values of the random SPD matrix: the FP64 residual
     does not follow the FP16 recurrence, so no direction is carried and the

@@ -235,6 +235,23 @@ def test_ir_carried_direction_follows_cg(orc, seed, cond, n):
             assert d >= 1e-5, d
 
 
+@pytest.mark.parametrize("cap", [5, 10])
+def test_ir_carried_direction_capped_inner(orc, cap):
+    """Inner solves cut off after `cap` steps: carried, the refinement is CG
+    with its residual replaced every `cap` steps and takes CG's own step
+    count (98 here); restarted, it is CG restarted every `cap` steps and
+    takes 2.4-4 times as many."""
+    A = I.poisson3d(24)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 25))
+    cg = orc.cg(A, b, tol=1e-10)
+    carry = orc.ir(A, b, tol=1e-10, inner_max=cap, outer_max=200, carry_direction=True)
+    restart = orc.ir(A, b, tol=1e-10, inner_max=cap, outer_max=200)
+    assert carry.status == restart.status == orc.OK
+    assert carry.relres_true <= 1e-10 and restart.relres_true <= 1e-10
+    assert carry.inner_iters_total <= 1.05 * cg.iters + 2
+    assert restart.inner_iters_total >= 2 * cg.iters
+
+
 def test_ir_carried_direction_guard(orc):
     """Row-scaled FP16 values of the random SPD matrix are too far from A
     for the inner directions to serve the next step: the FP64 residual
