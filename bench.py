@@ -60,6 +60,20 @@ def ell_streamed_bytes(desc, vb, xb):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_stencil27_128_traffic.txt")
 
 
+# The paper's own measurements on Intel GPUs, quoted as context only (other
+# hardware, SuiteSparse matrices): sections "Bandwidth Tests and Roofline
+# Performance Model", "SpMV Performance Analysis", "Krylov Solver
+# Performance Analysis" and "Platform Portability".
+PAPER_CONTEXT = {
+    "hardware": {"gen9": "Intel Gen9 UHD P630, 41.6 GB/s theoretical, ~37 GB/s BabelStream",
+                 "gen12": "Intel Gen12 Iris Xe Max (DG1), 68 GB/s theoretical, ~58 GB/s BabelStream"},
+    "spmv_gen9_fp64_gflops": {"csr": 5.1, "coo": 3.8, "csr_roofline": 6.0, "coo_roofline": 4.6},
+    "spmv_gen12_fp32": "CSR and COO close to their roofline bounds (14.5 / 9.7 GFLOP/s)",
+    "krylov_1000_iters_gflops": {"gen9_fp64": [1.5, 2.5], "gen12_fp32": [5.0, 9.0]},
+    "spmv_fraction_of_peak_bw": {"nvidia_and_gen12": 0.9, "radeon_vii_and_gen9": [0.6, 0.7]},
+}
+
+
 def measured_traffic(fmt, dt, info, max_row):
     """HBM bytes per launch of this SpMV from the committed rocprofv3 --pmc
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors), or
@@ -156,7 +170,7 @@ def main():
     out = {"metric": METRIC, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic"}
-    extra = {}
+    extra = {"paper_context": PAPER_CONTEXT}
     # GPU solutions (host copies) of the solver rows, keyed by system: the
     # CPU leg solves the same systems with the oracle and reports each row's
     # distance to the oracle's solution
