@@ -25,6 +25,8 @@
 // Each mxs_batch_step admits waiting requests whose footprint fits the
 // arena and whose class has a free slot, launches the graph, waits for it,
 // and retires the slots that finished.
+#include <sched.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -1047,13 +1049,25 @@ void pack(char* dst, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   std::memcpy(dst + L.b, b, n * 8);
 }
 
+// Host CPUs this process may run on (its affinity mask; a container or job
+// slot may allow fewer than the machine has), at least 1.
+unsigned usable_cpus() {
+  cpu_set_t set;
+  CPU_ZERO(&set);
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) {
+    const int c = CPU_COUNT(&set);
+    if (c > 0) return (unsigned)c;
+  }
+  return std::max(1u, std::thread::hardware_concurrency());
+}
+
 // Runs the retirement copies (pinned output -> result buffers), split by
 // bytes over up to 8 threads when they add up to more than 4 MiB.
 template <typename Copy>
 void copy_out(const std::vector<Copy>& c) {
   size_t total = 0;
   for (const Copy& k : c) total += (size_t)k.n * sizeof(double);
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned hw = usable_cpus();
   const size_t nt = std::min<size_t>({(size_t)std::min(hw, 8u), c.size(), total >> 22});
   if (nt <= 1) {
     for (const Copy& k : c) std::memcpy(k.dst, k.src, (size_t)k.n * sizeof(double));
@@ -1633,7 +1647,7 @@ mxs_status mxs_batch_create(mxs_ctx* ctx, const mxs_batch_opts* opts, mxs_batch*
     // write to a page of pinned memory costs several times a later one, and
     // would otherwise land on the submissions of a running service
     {
-      const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+      const unsigned hw = usable_cpus();
       const size_t nt = std::max<size_t>(1, std::min<size_t>({(size_t)std::min(hw, 16u),
                                                               in_size >> 24}));
       const size_t per = (in_size / nt + 4095) / 4096 * 4096;
@@ -1791,7 +1805,7 @@ mxs_status mxs_batch_submit_many(mxs_batch* B, int64_t count, const mxs_batch_re
   int64_t bytes_total = 0;
   for (int64_t i = 0; i < count; ++i)
     if (statuses[i] == MXS_OK) bytes_total += (int64_t)R[i].in_bytes;
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned hw = usable_cpus();
   const int64_t nthreads =
       std::min<int64_t>({(int64_t)std::min(hw, 16u), count, bytes_total >> 20});
   if (nthreads <= 1) {

@@ -2288,7 +2288,7 @@ mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* 
     usable = h.iters > 0 && (h.done == ST_CONVERGED || h.done == ST_MAXIT) &&
              h.rho[(h.iters - 1) & 1] > 0.0;
     rho_prev = usable ? h.rho[(h.iters - 1) & 1] : 0.0;
-    claimed = sqrt(h.res2 / f2);
+    claimed = f2 > 0.0 ? sqrt(h.res2 / f2) : 0.0;
     nr_prev = nr;
     if (h.done == ST_NONFINITE) {
       result = fail(ctx, MXS_NONFINITE, "non-finite value in the inner solve");

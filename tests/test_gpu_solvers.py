@@ -212,6 +212,59 @@ def test_cg_three_launch_iteration(env, orc, case):
     assert np.array_equal(x.cpu().numpy(), x0)
 
 
+@pytest.mark.parametrize("n,seed", [(20, 70), (300, 71)])
+def test_cg_merge_path_dot_chunk_counts(env, orc, n, seed):
+    """CG on the merge path without panels (p.q from the chunks' own sums,
+    reduced by the cut-row pass): one chunk (n = 20: 400 entries, so the
+    cut-row pass runs only to reduce the dot) and many chunks with rows cut
+    at every chunk edge (n = 300: 90,000 entries, rows of 300); FP64 and
+    FP32 values, iterations within 10% of the oracle's CG."""
+    mxs, ctx, torch = env
+    A = I.dense_to_csr(I.random_spd_small(n, 30.0, seed))
+    b = I.uniform_vector(n, seed + 1)
+    M = mxs.Matrix.from_host(ctx, A)
+    B = M.convert("csr", "f64", csr_kernel="merge", col_panels=1)
+    d = B.info()
+    assert d["csr_kernel"] == mxs.CSR_MERGE and d["col_panels"] <= 1
+    x = _dev(torch, np.zeros(n))
+    r = mxs.solve(ctx, "cg", B, _dev(torch, b), x, tol=1e-10)
+    _assert_converged(orc, A, b, x.cpu().numpy(), r, 1e-10)
+    ref = orc.cg(A, b, tol=1e-10)
+    assert abs(r.iters - ref.iters) <= max(3, ref.iters // 10), (r.iters, ref.iters)
+    # the FP32 inner solve of refinement on the same kernel
+    L = M.convert("csr", "f32", csr_kernel="merge", col_panels=1)
+    assert L.info()["csr_kernel"] == mxs.CSR_MERGE
+    x = _dev(torch, np.zeros(n))
+    ri = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-10)
+    assert ri.status == mxs.OK
+    xh = x.cpu().numpy()
+    assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
+
+
+def test_ir_carried_direction_block_jacobi_inner(env, orc):
+    """Carried directions with a block-Jacobi inner solve (its own apply
+    kernel and p.z partials): converges and follows the oracle's carried
+    refinement."""
+    mxs, ctx, torch = env
+    A = I.poisson3d(24)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 72))
+    M = mxs.Matrix.from_host(ctx, A)
+    P = mxs.Precond(ctx, M, "block_jacobi", 8)
+    L = M.convert("csr", "f32")
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r = mxs.solve_ir(ctx, M, L, _dev(torch, b), x, tol=1e-10, precond=P, carry_direction=True)
+    xh = x.cpu().numpy()
+    assert r.status == mxs.OK
+    assert orc.true_relres(A, b, xh) <= 1e-10 + _eval_slack(orc, A, b, xh)
+    ref = orc.ir(A, b, low="f32", tol=1e-10, precond=orc.block_jacobi(A, 8)[1],
+                 carry_direction=True)
+    assert abs(r.outer_iters - ref.outer_iters) <= 1
+    assert abs(r.inner_iters_total - ref.inner_iters_total) <= 0.1 * ref.inner_iters_total + 2
+    restart = orc.ir(A, b, low="f32", tol=1e-10, precond=orc.block_jacobi(A, 8)[1])
+    assert ref.inner_iters_total < restart.inner_iters_total
+    P.close()
+
+
 def test_ir_inner_product_with_dot(env, orc):
     """Refinement whose FP32 inner CG runs on the merge path over column
     panels (p.q formed by the product's last pass)."""
