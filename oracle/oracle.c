@@ -1414,8 +1414,8 @@ static int64_t low_cg(const lowmat_t* L, const float* f, float* d, float tol,
   low_prec_apply(n, pc_kind, bs, minv, r, z);
   float rho = fdot(n, r, z);
   float rr = fdot(n, r, r);
-  if (carry > 0.0) {
-    float c = (float)((double)rho / (carry * *rho_io));
+  float c = carry > 0.0 ? (float)((double)rho / (carry * *rho_io)) : 0.0f;
+  if (carry > 0.0 && isfinite(c)) {
     ORC_PAR_FOR
     for (int64_t i = 0; i < n; ++i) p[i] = z[i] + c * p[i];
   } else {
