@@ -386,11 +386,12 @@ typedef struct {
  *     continuing CG (residual replacement, van der Vorst & Ye, SIAM J. Sci.
  *     Comput. 22, 2000; with a low-precision iteration as in the "reliable
  *     updates" of Clark et al., Comput. Phys. Commun. 181, 2010), so the
- *     inner steps do not start over at every refinement step.  A previous
- *     solve that took no step or broke down is not carried, nor one after
- *     which the FP64 residual fell by more than twice the fraction its FP32
- *     recurrence residual claimed (A_low too far from A64 for its
- *     directions to serve the next step: the step restarts instead).
+ *     inner steps do not start over at every refinement step.  The step
+ *     restarts instead (p = z) when the previous solve took no step or broke
+ *     down, when the new ||r|| exceeds twice the previous ||r|| times the
+ *     reduction the previous FP32 recurrence residual claimed (A_low too far
+ *     from A64 for its directions to serve the next step), or when the
+ *     coefficient is not finite in FP32.
  * inner_precond (nullable, built from A64) turns the inner solve into
  * preconditioned CG with the FP32 copy of M.  Synchronises the ctx stream. */
 #define MXS_IR_LAST_STEP 1
