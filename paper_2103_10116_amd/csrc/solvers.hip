@@ -2254,13 +2254,13 @@ mxs_status solve_ir_impl(mxs_ctx* ctx, const mxs_matrix* A64, const mxs_matrix* 
       if ((s = dots<float>(ctx, w, n, rf, rf, nullptr, nullptr, &f2, nullptr))) return s;
       rz = f2;
     }
-    // carried only while the FP64 residual followed the recurrence the
-    // direction was built for: a true reduction nr / nr_prev more than twice
-    // the recurrence's own means A_low is too far from A64 for its
-    // directions to serve the next step
-    // the previous solve's quantities, normalised by nr_prev, grow by
-    // sc = nr_prev / nr against f: p_k -> sc p_k, rho_k -> sc^2 rho_k, so
-    // the CG direction is z + beta sc p_k with beta = rz / (sc^2 rho_k)
+    // Carried direction: the previous solve's quantities, normalised by
+    // nr_prev, grow by sc = nr_prev / nr against f (p_k -> sc p_k,
+    // rho_k -> sc^2 rho_k), so the CG direction is z + beta sc p_k with
+    // beta = rz / (sc^2 rho_k), i.e. z + cc p_k.  It is carried only while
+    // the FP64 residual followed the recurrence the direction was built for:
+    // a true reduction nr / nr_prev more than twice the recurrence's own
+    // means A_low is too far from A64 for its directions to serve this step.
     const float cc = carry && usable ? (float)(rz / ((nr_prev / nr) * rho_prev)) : 0.0f;
     if (carry && usable && nr <= 2.0 * claimed * nr_prev && std::isfinite(cc)) {
       k_ir_carry<<<g, RB, 0, ctx->stream>>>(n, z0, pf, cc);
