@@ -106,6 +106,11 @@ struct CsrPart {
   void* sval = nullptr;
   uint8_t* pmask = nullptr;
   int64_t nsrows = 0;
+  // FP64 / FP32 values: the output slot srid[r] of every entry's stacked
+  // row (srow, like COO's row array), with srow, scol and sval padded with
+  // zeros to whole 1024-entry chunks, so the product runs the COO chunks
+  // over the panel copy (row-scaled FP16 keeps the merge kernel)
+  int32_t* srow = nullptr;
 };
 
 // COO: equal chunks of block_nnz entries, one wave per chunk.  Rows cut by

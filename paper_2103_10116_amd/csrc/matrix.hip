@@ -598,10 +598,20 @@ mxs_status build_panels(mxs_ctx* ctx, mxs_matrix* A, int P, int C) {
     S.srid = upload(ctx, A, srid);
     S.pmask = upload(ctx, A, mask);
     S.crow = upload(ctx, A, crow);
-    S.scol = (int32_t*)mat_alloc(A, (size_t)nnz * 4 + 4);
-    S.sval = mat_alloc(A, (size_t)nnz * vb + 16);
-    if (!S.srowptr || !S.srid || !S.pmask || !S.crow || !S.scol || !S.sval) {
+    // padded to whole 1024-entry chunks (zeros) for the COO chunks
+    const size_t npad = (size_t)((nnz + 1023) / 1024 * 1024);
+    S.scol = (int32_t*)mat_alloc(A, npad * 4 + 4);
+    S.sval = mat_alloc(A, npad * vb + 16);
+    if (vb != 2) S.srow = (int32_t*)mat_alloc(A, npad * 4 + 4);
+    if (!S.srowptr || !S.srid || !S.pmask || !S.crow || !S.scol || !S.sval ||
+        (vb != 2 && !S.srow)) {
       st = fail(ctx, MXS_OOM, "column panels");
+      break;
+    }
+    if (hipMemsetAsync(S.scol, 0, npad * 4 + 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(S.sval, 0, npad * vb + 16, ctx->stream) != hipSuccess ||
+        (S.srow && hipMemsetAsync(S.srow, 0, npad * 4 + 4, ctx->stream) != hipSuccess)) {
+      st = fail(ctx, MXS_HIP, "column panels: clearing failed");
       break;
     }
     if (hipMemcpyAsync(d_dst, dst.data(), (size_t)P * n * 4, hipMemcpyHostToDevice,
@@ -619,6 +629,9 @@ mxs_status build_panels(mxs_ctx* ctx, mxs_matrix* A, int P, int C) {
     else
       k_panel_scatter<uint16_t><<<g, 256, 0, ctx->stream>>>(
           n, P, S.rowptr, d_cnt, d_dst, S.col, (const uint16_t*)S.val, S.scol, (uint16_t*)S.sval);
+    if (S.srow && !srid.empty())
+      k_coo_stacked_rows<<<grid_for(ctx, (int64_t)srid.size(), 256), 256, 0, ctx->stream>>>(
+          (int64_t)srid.size(), S.srowptr, S.srid, S.srow);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
       st = fail(ctx, MXS_HIP, "column panels: scatter failed");
       break;
