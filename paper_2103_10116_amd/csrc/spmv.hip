@@ -1376,10 +1376,10 @@ void launch_coo_chunks(mxs_ctx* ctx, const CooPart& P, T alpha, const T* x, T be
 // column panels: the stacked chunks into the panel partials (scratch after
 // the continuation partials), their fix-up, then the pass that adds them.
 // With FP64 or FP32 values the panel copy also holds each entry's output
-// slot (srow), and its chunks run as COO chunks: on the power-law and random
-// SPD matrices 76 vs 85 us (s = 2.0), 140 vs 144 (s = 1.79) and 120 vs 135
-// (random SPD), cold, FP64: no row-pointer table, search or slot lookup per
-// chunk.
+// slot (srow), and a plain product runs its chunks as COO chunks: on the
+// power-law and random SPD matrices 76 vs 89 us (s = 2.0), 142 vs 145
+// (s = 1.79) and 122 vs 137 (random SPD), cold, FP64: no row-pointer table,
+// search or slot lookup per chunk.
 // With dpart (CG's q = A p, alpha = 1, beta = 0) the partials of p.q go to
 // dpart and their count to *ndpart: from the panel-adding pass, or without
 // panels from the fix-up pass over the chunks' own sums (scratch after the
@@ -1393,8 +1393,12 @@ void launch_csr_merge(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T 
     if (P.nchunks == 0) return;
     const Cont c = cont_of(scratch, P.nchunks);
     T* part = (T*)((char*)scratch + cont_bytes(P.nchunks));
+    // plain products take the COO chunks; CG's product with its p.q keeps
+    // the merge kernel, whose smaller footprint (no row index per entry)
+    // shares the Infinity Cache better with the solver's vectors: random
+    // SPD 121.8 vs 128.0 us per CG iteration, same box
     bool as_coo = false;
-    if constexpr (!SCALED) as_coo = P.srow != nullptr;
+    if constexpr (!SCALED) as_coo = P.srow != nullptr && dpart == nullptr;
     if (as_coo) {
       CooPart Q;
       Q.row = P.srow;
