@@ -74,6 +74,20 @@ PAPER_CONTEXT = {
 }
 
 
+def fastest_refinement(rows):
+    """The unpreconditioned refinement variant with the shortest solve (the
+    comparison with plain FP64 CG is between unpreconditioned solvers), and
+    the literal scheme's own figure beside it."""
+    cand = {k: v for k, v in rows.items()
+            if k.startswith("ir_") and "jacobi" not in k and v.get("status") == 0}
+    if not cand:
+        return None
+    best = min(cand, key=lambda k: cand[k]["time_s"])
+    lit = rows.get("ir_f32", {})
+    return {"variant": best, "speedup_vs_plain": cand[best]["speedup_vs_plain"],
+            "literal_ir_f32_speedup_vs_plain": lit.get("speedup_vs_plain")}
+
+
 def measured_traffic(fmt, dt, info, max_row):
     """HBM bytes per launch of this SpMV from the committed rocprofv3 --pmc
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors), or
@@ -583,6 +597,7 @@ def main():
                         "time_s": round(t_ir, 4), "speedup_vs_plain": round(t_plain / t_ir, 3),
                         "err_vs_xstar": err}
                     L.close()
+            e["fastest_refinement"] = fastest_refinement(e)
             irr[name] = e
             log(name, json.dumps(e))
             Qm.close()

@@ -85,3 +85,15 @@ def test_cpu_info():
     info = bench._cpu_info()
     assert info["physical_cores"] >= 1 and 1 <= info["threads_used"] <= info["logical_cpus"]
     assert isinstance(info["model"], str)
+
+
+def test_fastest_refinement_ignores_preconditioned_and_failed_rows():
+    rows = {"plain_f64_cg": {"time_s": 1.0, "status": 0},
+            "ir_f32_jacobi_inner": {"time_s": 0.01, "speedup_vs_plain": 100.0, "status": 0},
+            "ir_f32": {"time_s": 1.1, "speedup_vs_plain": 0.91, "status": 0},
+            "ir_f32_carry": {"time_s": 0.9, "speedup_vs_plain": 1.11, "status": 0},
+            "ir_f16_carry": {"time_s": 0.5, "speedup_vs_plain": 2.0, "status": 6}}
+    best = bench.fastest_refinement(rows)
+    assert best == {"variant": "ir_f32_carry", "speedup_vs_plain": 1.11,
+                    "literal_ir_f32_speedup_vs_plain": 0.91}
+    assert bench.fastest_refinement({"plain_f64_cg": {"time_s": 1.0}}) is None
