@@ -373,14 +373,17 @@ def main():
                     # so the probe is taken on an x of the slice's size
                     t_b = (nbytes - Z.ncols * vb) / (peak_meas * 1e9) if peak_meas else 0.0
                     t_g = Z.nnz / gp[dt]
-                    panels = info.get("col_panels", 0) if fmt in ("csr", "coo") else 0
+                    panels = info.get("col_panels", 0) if fmt in ("csr", "coo", "hyb") else 0
                     e["gather_bound_full_x_us"] = round(max(t_g, t_b) * 1e6, 2)
                     if panels > 1:
                         key = (dt, panels)
                         if key not in gp_slice:
                             gp_slice[key] = mxs.gather_probe(ctx, -(-Z.ncols // panels), Z.nnz,
                                                              vb, 5)
-                        t_g = Z.nnz / gp_slice[key]
+                        # the hybrid's ELL part gathers over the whole x, its
+                        # COO part from the slices
+                        sliced = info["coo_nnz"] if fmt == "hyb" else Z.nnz
+                        t_g = (Z.nnz - sliced) / gp[dt] + sliced / gp_slice[key]
                         e["col_panels"] = panels
                     e["gather_bound_us"] = round(max(t_g, t_b) * 1e6, 2)
                     e["frac_of_gather_bound"] = round(max(t_g, t_b) / t_cold, 3)

@@ -143,7 +143,8 @@ typedef struct {
   int32_t rows_per_group; /* CSR vector kernel: 2, 4 or 8 rows per lane group; 0 = default */
   int32_t waves_per_group;/* CSR stream / COO: independent waves per work-group, 1 or 4 (0 = 4) */
   int32_t coo_kernel;     /* COO and the COO part of HYB: MXS_COO_AUTO, MXS_COO_LDS, MXS_COO_RUNS */
-  int32_t col_panels;     /* merge-path CSR: column panels (0 = auto, 1 = none, 2, 4 or 8; see below) */
+  int32_t col_panels;     /* merge-path CSR, COO and the COO part of HYB: column panels (0 = auto,
+                             1 = none, 2, 4 or 8; see below) */
 } mxs_convert_opts;
 
 #define MXS_CSR_AUTO 0   /* MERGE if a row exceeds 64 entries (real values whose chunks fit, else
@@ -166,7 +167,12 @@ typedef struct {
                               L2.  Each panel writes per-row partial sums into the ctx's scratch and
                               a last pass adds a row's partials in panel order.  Auto (0): panels
                               when x is larger than 4 MiB, P the smallest power of two that cuts it
-                              into slices of at most 2 MiB (at most 8), none otherwise */
+                              into slices of at most 2 MiB (at most 8), none otherwise.
+                              COO and the COO part of HYB take the same panels (auto: when a row has
+                              more than 64 entries and x is larger than 4 MiB): their arrays then
+                              hold the entries ordered by (panel, row, column), the row index of an
+                              entry of row i in panel p being p * nrows + i (so exports show that
+                              order), and a last pass adds each row's panel partials. */
 
 #define MXS_COO_AUTO 0 /* RUNS for FP32/FP16 values when no row has more than 16 entries in
                           the part, else LDS */
@@ -211,7 +217,8 @@ typedef struct {
   int32_t csr_kernel;            /* CSR: the kernel in use (MXS_CSR_STREAM ... MXS_CSR_PRODUCTS) */
   int32_t coo_kernel;            /* COO / COO part of HYB: the kernel in use (MXS_COO_LDS or
                                     MXS_COO_RUNS); other formats 0 */
-  int32_t col_panels;            /* merge-path CSR: column panels in use (1 = none); others 0 */
+  int32_t col_panels;            /* merge-path CSR, COO, HYB's COO part: column panels in use
+                                    (1 = none); other formats and kernels 0 */
 } mxs_matrix_desc;
 
 mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out);

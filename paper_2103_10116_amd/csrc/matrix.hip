@@ -959,6 +959,104 @@ mxs_status build_coo_panels(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, in
   return st;
 }
 
+// The hybrid format's COO part in panel order (see CooPart): its entries,
+// already in A->coo in row order with their values cast, are counted per row
+// and panel over the part's own row pointers `off`, moved bit for bit into
+// panel order, and each given its stacked output index.
+template <typename V>
+mxs_status hyb_coo_panels(mxs_ctx* ctx, mxs_matrix* A, int P, const std::vector<int64_t>& off) {
+  using E = std::conditional_t<sizeof(V) == 8, uint64_t, uint32_t>;
+  static_assert(sizeof(V) == sizeof(E), "FP64 or FP32 values");
+  CooPart& C = A->coo;
+  const int64_t n = A->n, cnnz = off[(size_t)n];
+  const int64_t W = (A->ncols + P - 1) / P;
+  std::vector<int32_t> rp32((size_t)n + 1), cnt((size_t)P * n), dst((size_t)P * n, -1), srp, srid;
+  for (int64_t i = 0; i <= n; ++i) rp32[(size_t)i] = (int32_t)off[(size_t)i];
+  std::vector<uint8_t> mask((size_t)n, 0);
+  int32_t* d_rp = (int32_t*)ctx->alloc.alloc(((size_t)n + 1) * 4);
+  int32_t* d_cnt = (int32_t*)ctx->alloc.alloc((size_t)P * n * 4 + 4);
+  int32_t* d_dst = (int32_t*)ctx->alloc.alloc((size_t)P * n * 4 + 4);
+  int32_t* d_col = (int32_t*)ctx->alloc.alloc((size_t)cnnz * 4 + 4);
+  E* d_val = (E*)ctx->alloc.alloc((size_t)cnnz * sizeof(E) + 8);
+  int32_t* d_srp = nullptr;
+  int32_t* d_srid = nullptr;
+  mxs_status st = MXS_OK;
+  do {
+    if (!d_rp || !d_cnt || !d_dst || !d_col || !d_val) {
+      st = fail(ctx, MXS_OOM, "hybrid column panels: work arrays");
+      break;
+    }
+    if (hipMemcpyAsync(d_rp, rp32.data(), ((size_t)n + 1) * 4, hipMemcpyHostToDevice,
+                       ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(d_col, C.col, (size_t)cnnz * 4, hipMemcpyDeviceToDevice, ctx->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_val, C.val, (size_t)cnnz * sizeof(E), hipMemcpyDeviceToDevice,
+                       ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "copy failed");
+      break;
+    }
+    k_panel_counts<<<grid_for(ctx, n, 256), 256, 0, ctx->stream>>>(n, P, W, d_rp, d_col, d_cnt);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(cnt.data(), d_cnt, (size_t)P * n * 4, hipMemcpyDeviceToHost,
+                       ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "hybrid column panels: counting failed");
+      break;
+    }
+    int64_t pos = 0;
+    for (int p = 0; p < P; ++p)
+      for (int64_t i = 0; i < n; ++i) {
+        const int32_t c = cnt[(size_t)p * n + i];
+        if (c == 0) continue;
+        srid.push_back((int32_t)((int64_t)p * n + i));
+        srp.push_back((int32_t)pos);
+        dst[(size_t)p * n + i] = (int32_t)pos;
+        mask[(size_t)i] |= (uint8_t)(1u << p);
+        pos += c;
+      }
+    srp.push_back((int32_t)pos);
+    if (pos != cnnz) {
+      st = fail(ctx, MXS_HIP, "hybrid column panels: inconsistent counts");
+      break;
+    }
+    C.pmask = upload(ctx, A, mask);
+    d_srp = (int32_t*)ctx->alloc.alloc(srp.size() * 4 + 4);
+    d_srid = (int32_t*)ctx->alloc.alloc(srid.size() * 4 + 4);
+    if (!C.pmask || !d_srp || !d_srid) {
+      st = fail(ctx, MXS_OOM, "hybrid column panels");
+      break;
+    }
+    if (hipMemcpyAsync(d_dst, dst.data(), (size_t)P * n * 4, hipMemcpyHostToDevice,
+                       ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(d_srp, srp.data(), srp.size() * 4, hipMemcpyHostToDevice, ctx->stream) !=
+            hipSuccess ||
+        (!srid.empty() && hipMemcpyAsync(d_srid, srid.data(), srid.size() * 4,
+                                         hipMemcpyHostToDevice, ctx->stream) != hipSuccess)) {
+      st = fail(ctx, MXS_HIP, "copy failed");
+      break;
+    }
+    k_panel_scatter<E><<<grid_for(ctx, n, 256), 256, 0, ctx->stream>>>(
+        n, P, d_rp, d_cnt, d_dst, d_col, d_val, C.col, (E*)C.val);
+    if (!srid.empty())
+      k_coo_stacked_rows<<<grid_for(ctx, (int64_t)srid.size(), 256), 256, 0, ctx->stream>>>(
+          (int64_t)srid.size(), d_srp, d_srid, C.row);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = fail(ctx, MXS_HIP, "hybrid column panels: scatter failed");
+      break;
+    }
+    C.panels = P;
+  } while (0);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->alloc.release(d_rp);
+  ctx->alloc.release(d_cnt);
+  ctx->alloc.release(d_dst);
+  ctx->alloc.release(d_col);
+  ctx->alloc.release(d_val);
+  ctx->alloc.release(d_srp);
+  ctx->alloc.release(d_srid);
+  return st;
+}
+
 template <typename V>
 mxs_status convert_typed(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, mxs_format fmt,
                          const mxs_convert_opts* opts, int* d_err) {
@@ -1073,6 +1171,16 @@ mxs_status convert_typed(mxs_ctx* ctx, const mxs_matrix* S, mxs_matrix* A, mxs_f
         n, K, rp, S->csr.col, (const double*)S->csr.val, d_off, A->coo.row, A->coo.col,
         (V*)A->coo.val, d_err);
     MXS_HIP_TRY(ctx, hipGetLastError());
+  }
+  // column panels for the COO part, by the COO format's rule (rows longer
+  // than 64 entries and an x above 4 MiB, or asked for); the pass that adds
+  // the panel partials writes every row
+  const int req = opts ? opts->col_panels : 0;
+  const int P = (cnnz > 0 && (req > 1 || (req == 0 && Kmax > 64))) ? merge_panels(A, opts) : 1;
+  if (P > 1) {
+    if (mxs_status st = hyb_coo_panels<V>(ctx, A, P, off)) return st;
+    return setup_coo_part(ctx, A, A->coo, cnnz, std::max<int64_t>(Kmax - K, 0), vb, bnnz,
+                          std::vector<int32_t>(), opts);
   }
   return setup_coo_part(ctx, A, A->coo, cnnz, std::max<int64_t>(Kmax - K, 0), vb, bnnz,
                         empty, opts);
@@ -1490,9 +1598,9 @@ mxs_status mxs_matrix_info(const mxs_matrix* A, mxs_matrix_desc* out) {
                     : A->csr.lanes >= 1 ? MXS_CSR_VECTOR
                                        : MXS_CSR_STREAM;
   out->coo_kernel = A->fmt == MXS_COO || (A->fmt == MXS_HYB && A->coo.nnz > 0) ? A->coo.kernel : 0;
-  out->col_panels = A->fmt == MXS_CSR && A->csr.merge ? A->csr.panels
-                    : A->fmt == MXS_COO                 ? A->coo.panels
-                                                        : 0;
+  out->col_panels = A->fmt == MXS_CSR && A->csr.merge           ? A->csr.panels
+                    : A->fmt == MXS_COO || A->fmt == MXS_HYB     ? A->coo.panels
+                                                                 : 0;
   out->bytes = A->bytes;
   return MXS_OK;
 }

@@ -1645,7 +1645,7 @@ size_t spmv_scratch_bytes(const mxs_matrix* A) {
   // column panels: one partial of up to 8 bytes per row and panel
   if (A->fmt == MXS_CSR && A->csr.merge && A->csr.panels > 1)
     b += (size_t)A->csr.panels * (size_t)A->n * sizeof(double);
-  if (A->fmt == MXS_COO && A->coo.panels > 1)
+  if ((A->fmt == MXS_COO || A->fmt == MXS_HYB) && A->coo.panels > 1)
     b += (size_t)A->coo.panels * (size_t)A->n * sizeof(double);
   return b;
 }

@@ -354,8 +354,8 @@ def test_spmv_csr_kernels(env, orc, name, dt):
 def test_spmv_coo_kernels(env, orc, name, kernel):
     """Both COO kernels (and the COO part of HYB, which the power-law matrices
     have at a forced width) at every chunk size and work-group shape, FP64
-    and FP32, and COO with its entries in 2 or 8 column panels; chunks of
-    256 entries leave ragged last chunks on every matrix."""
+    and FP32, and both formats with their COO entries in 2 or 8 column
+    panels; chunks of 256 entries leave ragged last chunks on every matrix."""
     mxs, ctx, torch = env
     A = ZOO[name]
     M = mxs.Matrix.from_host(ctx, A)
@@ -372,8 +372,8 @@ def test_spmv_coo_kernels(env, orc, name, kernel):
             ref = orc.spmv_csr(Ar, xr, 1.5, -0.5, yr)
             scale = 1.5 * orc.absrow(Ar, xr) + 0.5 * np.abs(yr)
             shapes = [(bn, wpg, 0) for bn in (256, 512, 1024) for wpg in (1, 4)]
-            if fmt == "coo":   # entries in column-panel order
-                shapes += [(bn, wpg, p) for bn in (256, 1024) for wpg in (1, 4) for p in (2, 8)]
+            # entries (of COO, of the hybrid's COO part) in column-panel order
+            shapes += [(bn, wpg, p) for bn in (256, 1024) for wpg in (1, 4) for p in (2, 8)]
             for bn, wpg, panels in shapes:
                 extra = {"col_panels": panels} if panels else {}
                 B = M.convert(fmt, dt, block_nnz=bn, waves_per_group=wpg,
@@ -382,7 +382,7 @@ def test_spmv_coo_kernels(env, orc, name, kernel):
                 assert d["block_nnz"] == bn and d["waves_per_group"] == wpg
                 if d["coo_nnz"]:
                     assert d["coo_kernel"] == mxs.COO_KERNELS[kernel]
-                if panels and A.nnz and A.ncols >= panels:
+                if panels and d["coo_nnz"] and A.ncols >= panels:
                     assert d["col_panels"] == panels
                 y = torch.from_numpy(yr).to(tdt).cuda()
                 mxs.spmv(ctx, B, torch.from_numpy(xr).to(tdt).cuda(), y, 1.5, -0.5)
@@ -578,7 +578,7 @@ def test_spmv_full_size(env, orc, which):
         B = M.convert(fmt, "f64", **opts)
         if fmt == "csr" and not opts and which != "stencil27_128":
             assert B.info()["col_panels"] == 4   # x of 8 MiB: slices of 2 MiB
-        if fmt == "coo" and "col_panels" not in opts:
+        if fmt in ("coo", "hyb") and "col_panels" not in opts and B.info()["coo_nnz"]:
             # rows over 64 entries and an x of 8 MiB: panels; stencils: none
             assert B.info()["col_panels"] == (4 if which != "stencil27_128" else 1)
         if "ell_width" in opts:
