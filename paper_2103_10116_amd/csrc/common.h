@@ -215,12 +215,15 @@ mxs_status launch_spmv(mxs_ctx* ctx, const mxs_matrix* A, const void* alpha, con
 // product until this one completes on ctx->stream).
 size_t spmv_scratch_bytes(const mxs_matrix* A);
 // y = A x (square A) and, in the same launches, work-group partial sums of
-// x[i] * y[i] in dpart (CG's p.q with x = p): returns how many partials
-// (<= kDotPartials) were written, or 0 when A's kernel has no such form
-// (then nothing was enqueued and the caller forms p.q itself).
+// w[i] * y[i] in dpart (w = x when NULL: CG's p.q with x = p), and with
+// nv = 2 also of y[i]^2, interleaved (dpart[b * nv + v]): returns how many
+// work-group partials (<= kDotPartials) were written, or 0 when A's kernel
+// has no such form (then nothing was enqueued and the caller forms the dots
+// itself).  The merge path forms x.y only; w != x or nv = 2 need the
+// rows-from-LDS kernel.
 constexpr int kDotPartials = 4096;
 int launch_spmv_dot(mxs_ctx* ctx, const mxs_matrix* A, const void* x, void* y,
-                    const int32_t* skip, double* dpart);
+                    const int32_t* skip, double* dpart, const void* w = nullptr, int nv = 1);
 // The allocation-free product's fixed device scratch (one copy per GPU, held
 // until the process ends): its size, its per-device address lookup (run once
 // per device by mxs_ctx_create with that device current) and that address.

@@ -499,7 +499,7 @@ __global__ __launch_bounds__(RB) void k_bi_s(int64_t n, const double* __restrict
                                              double* __restrict__ pb, KState* st, int par) {
   if (st->done) return;
   double rv[1];
-  finish<1>(pa, g, rv);
+  finish_wide<1>(pa, g, rv);  // the product's partials when it formed r_hat.v
   if (!isfinite(rv[0]) || rv[0] == 0.0) {
     if (lead()) st->done = isfinite(rv[0]) ? ST_BREAKDOWN : ST_NONFINITE;
     return;
@@ -546,6 +546,9 @@ __global__ __launch_bounds__(RB) void k_bi_omega(int64_t n, const double* __rest
   block_partials<2>(acc, pd);
 }
 
+// pd holds the partials of (t.s, t.t): k_bi_omega's, or (half != 0) those
+// the product t = A s formed itself, when this kernel first takes the
+// half-step test on s.s (pb, gb partials) that k_bi_omega would have taken.
 __global__ __launch_bounds__(RB) void k_bi_update(int64_t n, double* __restrict__ x,
                                                   const double* __restrict__ p,
                                                   const double* __restrict__ s,
@@ -554,10 +557,27 @@ __global__ __launch_bounds__(RB) void k_bi_update(int64_t n, double* __restrict_
                                                   const double* __restrict__ rh,
                                                   const double* __restrict__ pd, int g,
                                                   double* __restrict__ pc, KState* st,
-                                                  int64_t k) {
+                                                  int64_t k, int half,
+                                                  const double* __restrict__ pb, int gb) {
   if (st->done) return;
+  if (half) {
+    double ss[1];
+    finish<1>(pb, gb, ss);
+    if (!isfinite(ss[0])) {
+      if (lead()) st->done = ST_NONFINITE;
+      return;
+    }
+    if (sqrt(ss[0]) <= st->thr) {
+      if (lead()) {
+        st->res2 = ss[0];
+        st->iters = k + 1;
+        st->done = ST_HALF;
+      }
+      return;
+    }
+  }
   double tstt[2];
-  finish<2>(pd, g, tstt);
+  finish_wide<2>(pd, g, tstt);
   if (!isfinite(tstt[0]) || !isfinite(tstt[1]) || tstt[1] == 0.0) {
     if (lead()) st->done = tstt[1] == 0.0 ? ST_BREAKDOWN : ST_NONFINITE;
     return;
@@ -1788,12 +1808,29 @@ mxs_status solve_bicgstab(mxs_ctx* ctx, const mxs_matrix* A, const double* b, do
           k_bi_p<<<g, RB, 0, ctx->stream>>>(n, r, p, v, w.pc, g, w.st, par, k, first ? 1 : 0);
           first = false;
           mxs_status e;
-          if ((e = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return e;
-          k_bi_rv<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
-          k_bi_s<<<g, RB, 0, ctx->stream>>>(n, r, v, sv, w.pa, g, w.pb, w.st, par);
-          if ((e = launch_spmv(ctx, A, &one, sv, &zero, t, &w.st->done))) return e;
-          k_bi_omega<<<g, RB, 0, ctx->stream>>>(n, t, sv, w.pb, g, w.pd, w.st, k);
-          k_bi_update<<<g, RB, 0, ctx->stream>>>(n, x, p, sv, t, r, rh, w.pd, g, w.pc, w.st, k);
+          // v = A p with r_hat.v formed by the product when its kernel can
+          // (rows from LDS), else a separate reduction
+          const double* pv = w.pw;
+          int gv = launch_spmv_dot(ctx, A, p, v, &w.st->done, w.pw, rh, 1);
+          if (gv == 0) {
+            if ((e = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return e;
+            k_bi_rv<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
+            pv = w.pa;
+            gv = g;
+          }
+          k_bi_s<<<g, RB, 0, ctx->stream>>>(n, r, v, sv, pv, gv, w.pb, w.st, par);
+          // t = A s with t.s and t.t formed by the product (the half-step
+          // test then moves into k_bi_update), else k_bi_omega forms them
+          int gt = launch_spmv_dot(ctx, A, sv, t, &w.st->done, w.pm, nullptr, 2);
+          if (gt == 0) {
+            if ((e = launch_spmv(ctx, A, &one, sv, &zero, t, &w.st->done))) return e;
+            k_bi_omega<<<g, RB, 0, ctx->stream>>>(n, t, sv, w.pb, g, w.pd, w.st, k);
+            k_bi_update<<<g, RB, 0, ctx->stream>>>(n, x, p, sv, t, r, rh, w.pd, g, w.pc, w.st,
+                                                   k, 0, w.pb, g);
+          } else {
+            k_bi_update<<<g, RB, 0, ctx->stream>>>(n, x, p, sv, t, r, rh, w.pm, gt, w.pc, w.st,
+                                                   k, 1, w.pb, g);
+          }
         }
         MXS_HIP_TRY(ctx, hipGetLastError());
         return MXS_OK;

@@ -320,7 +320,9 @@ __device__ __forceinline__ double rl_block(int64_t b, const int32_t* __restrict_
                                            const V* __restrict__ val,
                                            const float* __restrict__ scale,
                                            const T* __restrict__ x, T* __restrict__ y, T alpha,
-                                           T beta, V* vl, int32_t* cl) {
+                                           T beta, V* vl, int32_t* cl,
+                                           const T* __restrict__ wdot = nullptr,
+                                           double* d1 = nullptr) {
   constexpr int U = CMAX / 64;  // entries per lane of a full block
   const int lane = threadIdx.x & 63;
   const int32_t r0 = blocks[b], r1 = blocks[b + 1];
@@ -402,7 +404,10 @@ __device__ __forceinline__ double rl_block(int64_t b, const int32_t* __restrict_
   if (SCALED) sum *= (T)scale[i];
   const T out = combine(alpha, sum, beta, y, i);
   y[i] = out;
-  if constexpr (DOT) return (double)x[i] * (double)out;
+  if constexpr (DOT) {
+    if (d1) *d1 = (double)out * (double)out;
+    return (double)wdot[i] * (double)out;
+  }
   return 0.0;
 }
 
@@ -429,11 +434,12 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
 }
 
 // The same product, y = A x, where each work-group of WPB waves (one row
-// block each) also stores the sum of x[i] * y[i] over its rows to
-// part[blockIdx.x]: the p.q of a CG iteration comes with the product.  WPB
-// is chosen so that the partials stay few enough for every block of the
-// next kernel to add them.
-template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G, int ST>
+// block each) also stores the sum of w[i] * y[i] over its rows (w = x for
+// the p.q of a CG iteration, another vector for BiCGSTAB's r_hat.v) to
+// part[blockIdx.x * NV] and, with NV = 2, the sum of y[i]^2 to
+// part[blockIdx.x * NV + 1].  WPB is chosen so that the partials stay few
+// enough for every block of the next kernel to add them.
+template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G, int ST, int NV>
 __global__ __launch_bounds__(64 * WPB) void k_csr_rl_dot(int64_t nblocks,
                                                          const int32_t* __restrict__ blocks,
                                                          const int32_t* __restrict__ bnnz,
@@ -443,26 +449,32 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl_dot(int64_t nblocks,
                                                          const float* __restrict__ scale,
                                                          const T* __restrict__ x,
                                                          T* __restrict__ y,
+                                                         const T* __restrict__ w,
                                                          double* __restrict__ part,
                                                          const int32_t* __restrict__ skip) {
   __shared__ V vl_all[WPB][CMAX];
   __shared__ int32_t cl_all[WPB][CMAX];
-  __shared__ double red[WPB];
+  __shared__ double red[NV][WPB];
   if (skip && *skip) return;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
-  double acc = 0.0;
+  double acc = 0.0, acc1 = 0.0;
   if (b < nblocks)
     acc = rl_block<V, T, CMAX, SCALED, G, ST, true>(b, blocks, bnnz, rowptr, col, val, scale, x,
-                                                    y, T(1), T(0), vl_all[wv], cl_all[wv]);
+                                                    y, T(1), T(0), vl_all[wv], cl_all[wv], w,
+                                                    NV == 2 ? &acc1 : nullptr);
   acc = wave_total(acc);
-  if ((threadIdx.x & 63) == 0) red[wv] = acc;
+  if constexpr (NV == 2) acc1 = wave_total(acc1);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wv] = acc;
+    if constexpr (NV == 2) red[1][wv] = acc1;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = red[0];
+  if (threadIdx.x < NV) {
+    double t = red[threadIdx.x][0];
 #pragma unroll
-    for (int w = 1; w < WPB; ++w) t += red[w];
-    part[blockIdx.x] = t;
+    for (int q = 1; q < WPB; ++q) t += red[threadIdx.x][q];
+    part[(int64_t)blockIdx.x * NV + threadIdx.x] = t;
   }
 }
 
@@ -1254,10 +1266,16 @@ void launch_csr_rl(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, 
 
 template <typename V, typename T, bool SCALED, int CMAX, int G, int ST, int WPB>
 int launch_csr_rl_dot_w(mxs_ctx* ctx, const CsrPart& P, const T* x, T* y, const int32_t* skip,
-                        double* dpart) {
+                        double* dpart, const T* w, int nv) {
   const int g = (int)((P.nblocks + WPB - 1) / WPB);
-  k_csr_rl_dot<V, T, CMAX, SCALED, WPB, G, ST><<<g, 64 * WPB, 0, ctx->stream>>>(
-      P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, dpart, skip);
+  if (nv == 2)
+    k_csr_rl_dot<V, T, CMAX, SCALED, WPB, G, ST, 2><<<g, 64 * WPB, 0, ctx->stream>>>(
+        P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, w, dpart,
+        skip);
+  else
+    k_csr_rl_dot<V, T, CMAX, SCALED, WPB, G, ST, 1><<<g, 64 * WPB, 0, ctx->stream>>>(
+        P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, w, dpart,
+        skip);
   return g;
 }
 
@@ -1265,29 +1283,29 @@ int launch_csr_rl_dot_w(mxs_ctx* ctx, const CsrPart& P, const T* x, T* y, const 
 // kDotPartials; 0 (no launch) when even 8 do not
 template <typename V, typename T, bool SCALED, int CMAX, int G, int ST>
 int launch_csr_rl_dot_g(mxs_ctx* ctx, const CsrPart& P, const T* x, T* y, const int32_t* skip,
-                        double* dpart) {
+                        double* dpart, const T* w, int nv) {
   // LDS of a work-group: WPB tables of CMAX values and column indices
   constexpr size_t per_wave = (size_t)CMAX * (sizeof(V) + sizeof(int32_t));
   if (P.nblocks <= 2 * (int64_t)kDotPartials)
-    return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 2>(ctx, P, x, y, skip, dpart);
+    return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 2>(ctx, P, x, y, skip, dpart, w, nv);
   if constexpr (4 * per_wave <= 98304) {
     if (P.nblocks <= 4 * (int64_t)kDotPartials)
-      return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 4>(ctx, P, x, y, skip, dpart);
+      return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 4>(ctx, P, x, y, skip, dpart, w, nv);
   }
   if constexpr (8 * per_wave <= 98304) {
     if (P.nblocks <= 8 * (int64_t)kDotPartials)
-      return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 8>(ctx, P, x, y, skip, dpart);
+      return launch_csr_rl_dot_w<V, T, SCALED, CMAX, G, ST, 8>(ctx, P, x, y, skip, dpart, w, nv);
   }
   return 0;
 }
 
 template <typename V, typename T, bool SCALED, int CMAX>
 int launch_csr_rl_dot(mxs_ctx* ctx, const CsrPart& P, const T* x, T* y, const int32_t* skip,
-                      double* dpart) {
+                      double* dpart, const T* w, int nv) {
 #define MXS_RL_DOT(GG)                                                               \
   return P.rl_step == 16                                                             \
-             ? launch_csr_rl_dot_g<V, T, SCALED, CMAX, GG, 16>(ctx, P, x, y, skip, dpart) \
-             : launch_csr_rl_dot_g<V, T, SCALED, CMAX, GG, 8>(ctx, P, x, y, skip, dpart);
+             ? launch_csr_rl_dot_g<V, T, SCALED, CMAX, GG, 16>(ctx, P, x, y, skip, dpart, w, nv) \
+             : launch_csr_rl_dot_g<V, T, SCALED, CMAX, GG, 8>(ctx, P, x, y, skip, dpart, w, nv);
   if (P.rl_lanes == 4) MXS_RL_DOT(4)
   if (P.rl_lanes == 2) MXS_RL_DOT(2)
   MXS_RL_DOT(1)
@@ -1719,14 +1737,18 @@ void* noalloc_scratch(int device) {
 // kDotPartials), or 0 when A's kernel has no such form (nothing enqueued).
 template <typename V, typename T, bool SCALED>
 int launch_dot_typed(mxs_ctx* ctx, const mxs_matrix* A, const T* x, T* y, const int32_t* skip,
-                     double* dpart, void* scratch) {
+                     double* dpart, void* scratch, const T* w, int nv) {
   const CsrPart& P = A->csr;
   if (P.rows_lds && P.nblocks > 0) {
-    if (P.block_nnz <= 512) return launch_csr_rl_dot<V, T, SCALED, 512>(ctx, P, x, y, skip, dpart);
+    const T* wd = w ? w : x;
+    if (P.block_nnz <= 512)
+      return launch_csr_rl_dot<V, T, SCALED, 512>(ctx, P, x, y, skip, dpart, wd, nv);
     if (P.block_nnz <= 1024)
-      return launch_csr_rl_dot<V, T, SCALED, 1024>(ctx, P, x, y, skip, dpart);
-    return launch_csr_rl_dot<V, T, SCALED, 2048>(ctx, P, x, y, skip, dpart);
+      return launch_csr_rl_dot<V, T, SCALED, 1024>(ctx, P, x, y, skip, dpart, wd, nv);
+    return launch_csr_rl_dot<V, T, SCALED, 2048>(ctx, P, x, y, skip, dpart, wd, nv);
   }
+  // the merge path forms x.y only
+  if ((w && w != x) || nv != 1) return 0;
   if (P.merge && P.nchunks > 0 && (P.panels > 1 || (P.nchunks + 255) / 256 <= kDotPartials)) {
     if constexpr (std::is_same_v<V, double> || std::is_same_v<V, float> ||
                   std::is_same_v<V, _Float16>) {
@@ -1739,10 +1761,11 @@ int launch_dot_typed(mxs_ctx* ctx, const mxs_matrix* A, const T* x, T* y, const 
 }
 
 int launch_spmv_dot(mxs_ctx* ctx, const mxs_matrix* A, const void* x, void* y,
-                    const int32_t* skip, double* dpart) {
-  if (A->fmt != MXS_CSR || A->n == 0 || A->n != A->ncols) return 0;
+                    const int32_t* skip, double* dpart, const void* w, int nv) {
+  if (A->fmt != MXS_CSR || A->n == 0 || A->n != A->ncols || nv < 1 || nv > 2) return 0;
   const CsrPart& P = A->csr;
   if (!(P.rows_lds && P.nblocks > 0) && !(P.merge && P.nchunks > 0)) return 0;
+  if (!(P.rows_lds && P.nblocks > 0) && ((w && w != x) || nv != 1)) return 0;
   // the merge path without panels also keeps one dot partial per chunk
   const size_t need = spmv_scratch_bytes(A) +
                       (P.merge && P.panels <= 1 ? (size_t)P.nchunks * sizeof(double) : 0);
@@ -1759,11 +1782,14 @@ int launch_spmv_dot(mxs_ctx* ctx, const mxs_matrix* A, const void* x, void* y,
   void* sc = ctx->spmv_ws.ptr;
   int g = 0;
   if (A->dt == MXS_F64)
-    g = launch_dot_typed<double, double, false>(ctx, A, (const double*)x, (double*)y, skip, dpart, sc);
+    g = launch_dot_typed<double, double, false>(ctx, A, (const double*)x, (double*)y, skip, dpart,
+                                                sc, (const double*)w, nv);
   else if (A->dt == MXS_F32)
-    g = launch_dot_typed<float, float, false>(ctx, A, (const float*)x, (float*)y, skip, dpart, sc);
+    g = launch_dot_typed<float, float, false>(ctx, A, (const float*)x, (float*)y, skip, dpart, sc,
+                                              (const float*)w, nv);
   else if (A->dt == MXS_F16_ROWSCALED)
-    g = launch_dot_typed<_Float16, float, true>(ctx, A, (const float*)x, (float*)y, skip, dpart, sc);
+    g = launch_dot_typed<_Float16, float, true>(ctx, A, (const float*)x, (float*)y, skip, dpart,
+                                                sc, (const float*)w, nv);
   return g;
 }
 

@@ -317,6 +317,62 @@ def test_bicgstab_identity_and_breakdown(env, orc):
     assert r.status == mxs.BREAKDOWN
 
 
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_bicgstab_products_with_dots(env, orc, fmt):
+    """BiCGSTAB where the rows-from-LDS CSR products form r_hat.v and
+    (t.s, t.t) in their own launches (the half-step test then moves to the
+    update kernel), beside COO whose products leave the dots to separate
+    reductions: the residual meets 1e-10 within 3 (or 10%) iterations of the
+    oracle's; after max_iters = 3 the iterate equals three oracle steps; on
+    3I the first half step converges (x = b / 3 exactly); and a block-diagonal
+    skew matrix (r_hat.A r_hat = 0) breaks down at the first step with x
+    untouched."""
+    mxs, ctx, torch = env
+    A = I.convdiff3d(24)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 63))
+    M = mxs.Matrix.from_host(ctx, A)
+    B = M if fmt == "csr" else M.convert(fmt, "f64")
+    if fmt == "csr":
+        assert B.info()["csr_kernel"] == mxs.CSR_ROWS_LDS
+    x = _dev(torch, np.zeros(A.n))
+    r = mxs.solve(ctx, "bicgstab", B, _dev(torch, b), x, tol=1e-10)
+    _assert_converged(orc, A, b, x.cpu().numpy(), r, 1e-10)
+    ref = orc.bicgstab(A, b, tol=1e-10)
+    assert abs(r.iters - ref.iters) <= max(3, ref.iters // 10), (r.iters, ref.iters)
+    x = _dev(torch, np.zeros(A.n))
+    r = mxs.solve(ctx, "bicgstab", B, _dev(torch, b), x, tol=1e-10, max_iters=3,
+                  raise_on_error=False)
+    assert r.status == mxs.NOT_CONVERGED and r.iters == 3
+    ref3 = orc.bicgstab(A, b, tol=1e-10, maxit=3).x
+    assert np.linalg.norm(x.cpu().numpy() - ref3) <= 1e-12 * np.linalg.norm(ref3)
+    n = A.n
+    eye = I.CSRMatrix(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+                      np.full(n, 3.0))
+    Em = mxs.Matrix.from_host(ctx, eye)
+    Eb = Em if fmt == "csr" else Em.convert(fmt, "f64")
+    if fmt == "csr":
+        assert Eb.info()["csr_kernel"] == mxs.CSR_ROWS_LDS
+    # integer entries: every dot is exact, so alpha rounds only once
+    bi = (np.arange(n) % 7 + 1).astype(np.float64)
+    x = _dev(torch, np.zeros(n))
+    r = mxs.solve(ctx, "bicgstab", Eb, _dev(torch, bi), x, tol=1e-14)
+    assert r.status == mxs.OK and r.iters == 1
+    assert np.allclose(x.cpu().numpy(), bi / 3.0, rtol=1e-15, atol=0)
+    # 2x2 blocks [[0, 1], [-1, 0]]: v = A r_hat is orthogonal to r_hat
+    rows = np.arange(n)
+    cols = np.where(rows % 2 == 0, rows + 1, rows - 1).astype(np.int32)
+    sk = I.CSRMatrix(n, n, np.arange(n + 1, dtype=np.int32), cols,
+                     np.where(rows % 2 == 0, 1.0, -1.0))
+    Sm = mxs.Matrix.from_host(ctx, sk)
+    Sb = Sm if fmt == "csr" else Sm.convert(fmt, "f64")
+    # integer x0 and b: r_hat.v is an exact zero in any summation order
+    x0 = (rows % 5).astype(np.float64) - 2.0
+    x = _dev(torch, x0)
+    r = mxs.solve(ctx, "bicgstab", Sb, _dev(torch, np.ones(n)), x, raise_on_error=False)
+    assert r.status == mxs.BREAKDOWN and r.iters == 0, r
+    assert np.array_equal(x.cpu().numpy(), x0)
+
+
 def test_bicgstab_nonsymmetric_vs_lu(env, orc):
     g = I.rng(23)
     n = 25
