@@ -966,7 +966,7 @@ __global__ __launch_bounds__(RB) void k_pipe_update(int64_t n, double* __restric
 // ---------------------------------------------------------------------------
 // CGS (Sonneveld 1989; Saad 2003, Algorithm 7.6), r_hat = r0.  Iteration k
 // (par = k & 1), rho[par] = (r_hat, r):
-//   v = A p;   k_cgs_sigma: partials of r_hat.v
+//   v = A p;   k_cgs_sigma: partials of r_hat.v (or the product forms them)
 //   k_cgs_qw:  alpha = rho[par] / (r_hat.v), q = u - alpha v, w = u + q,
 //              x += alpha w
 //   v = A w;   k_cgs_r: r -= alpha v, partials of (r.r, r_hat.r)
@@ -993,7 +993,7 @@ __global__ __launch_bounds__(RB) void k_cgs_qw(int64_t n, const double* __restri
                                                int par) {
   if (st->done) return;
   double sg[1];
-  finish<1>(pa, g, sg);
+  finish_wide<1>(pa, g, sg);  // the product's partials when it formed r_hat.v
   if (!isfinite(sg[0]) || sg[0] == 0.0) {
     if (lead()) st->done = isfinite(sg[0]) ? ST_BREAKDOWN : ST_NONFINITE;
     return;
@@ -2052,9 +2052,16 @@ mxs_status solve_cgs(mxs_ctx* ctx, const mxs_matrix* A, const double* b, double*
         for (int64_t k = k0; k < k0 + stop.check_every; ++k) {
           const int par = (int)(k & 1);
           mxs_status e;
-          if ((e = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return e;
-          k_cgs_sigma<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
-          k_cgs_qw<<<g, RB, 0, ctx->stream>>>(n, u, v, q, wv, x, w.pa, g, w.st, par);
+          // v = A p with r_hat.v formed by the product when its kernel can
+          const double* ps = w.pw;
+          int gs = launch_spmv_dot(ctx, A, p, v, &w.st->done, w.pw, rh, 1);
+          if (gs == 0) {
+            if ((e = launch_spmv(ctx, A, &one, p, &zero, v, &w.st->done))) return e;
+            k_cgs_sigma<<<g, RB, 0, ctx->stream>>>(n, rh, v, w.pa, w.st);
+            ps = w.pa;
+            gs = g;
+          }
+          k_cgs_qw<<<g, RB, 0, ctx->stream>>>(n, u, v, q, wv, x, ps, gs, w.st, par);
           if ((e = launch_spmv(ctx, A, &one, wv, &zero, v, &w.st->done))) return e;
           k_cgs_r<<<g, RB, 0, ctx->stream>>>(n, r, v, rh, w.pb, w.st);
           k_cgs_dir<<<g, RB, 0, ctx->stream>>>(n, r, q, u, p, w.pb, g, w.st, par, k);

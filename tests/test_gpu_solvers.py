@@ -837,6 +837,38 @@ def test_cgs_convdiff(env, orc, fmt):
     assert abs(r.iters - ref.iters) <= 2 + ref.iters // 10, (r.iters, ref.iters)
 
 
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_cgs_product_with_dot(env, orc, fmt):
+    """CGS where the rows-from-LDS CSR product v = A p forms r_hat.v in its
+    own launch, beside COO with a separate reduction: after max_iters = 3
+    the iterate equals three oracle steps, and a block-diagonal skew matrix
+    (r_hat.A r_hat = 0, exact in integers) breaks down at the first step."""
+    mxs, ctx, torch = env
+    A = I.convdiff3d(24)
+    b = orc.spmv_csr(A, I.uniform_vector(A.n, 53))
+    M = mxs.Matrix.from_host(ctx, A)
+    B = M if fmt == "csr" else M.convert(fmt, "f64")
+    if fmt == "csr":
+        assert B.info()["csr_kernel"] == mxs.CSR_ROWS_LDS
+    x = _dev(torch, np.zeros(A.n))
+    r = mxs.solve(ctx, "cgs", B, _dev(torch, b), x, tol=1e-10, max_iters=3,
+                  raise_on_error=False)
+    assert r.status == mxs.NOT_CONVERGED and r.iters == 3
+    ref3 = orc.cgs(A, b, tol=1e-10, maxit=3).x
+    assert np.linalg.norm(x.cpu().numpy() - ref3) <= 1e-12 * np.linalg.norm(ref3)
+    n = A.n
+    rows = np.arange(n)
+    cols = np.where(rows % 2 == 0, rows + 1, rows - 1).astype(np.int32)
+    sk = I.CSRMatrix(n, n, np.arange(n + 1, dtype=np.int32), cols,
+                     np.where(rows % 2 == 0, 1.0, -1.0))
+    Sm = mxs.Matrix.from_host(ctx, sk)
+    Sb = Sm if fmt == "csr" else Sm.convert(fmt, "f64")
+    x = _dev(torch, np.zeros(n))
+    r = mxs.solve(ctx, "cgs", Sb, _dev(torch, np.ones(n)), x, raise_on_error=False)
+    assert r.status == mxs.BREAKDOWN and r.iters == 0, r
+    assert not x.cpu().numpy().any()
+
+
 @pytest.mark.parametrize("n,seed", [(6, 1), (20, 2)])
 def test_cgs_nonsymmetric_vs_lu(env, orc, n, seed):
     g = I.rng(seed + 60)
