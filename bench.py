@@ -486,16 +486,21 @@ def main():
             sols.setdefault(system, {})[("krylov", name)] = xq.cpu().numpy()
             # fixed 1000 iterations (no convergence test can stop it), for
             # GFLOP/s and GB/s under the per-iteration models: CG 2nnz+10n
-            # flops and B_csr+64n bytes; BiCGSTAB 4nnz+20n and 2B_csr+144n;
+            # flops and B_csr+64n bytes; BiCGSTAB 4nnz+20n and 2B_csr+120n
+            # when the products form r_hat.v and (t.s, t.t) (rows-from-LDS
+            # CSR: r_hat read by the first product), else 2B_csr+144n;
             # pipelined CG 2nnz+16n and B_csr+104n (q, z, w, s, r, p, x read,
-            # z, s, p, x, r, w written); CGS 4nnz+19n and 2B_csr+136n;
+            # z, s, p, x, r, w written); CGS 4nnz+19n and 2B_csr+128n (the
+            # product forms r_hat.v), else 2B_csr+136n;
             # GMRES(30) step j 2nnz+8(j+1)n+3n
             # and B_csr+(4(j+1)+9)8n, averaged over j = 0..29
             n_, z_ = Q.n, Q.nnz
+            own_dots = Qm.info()["csr_kernel"] == mxs.CSR_ROWS_LDS
             fl, by = {"cg": (2 * z_ + 10 * n_, csr_b + 64 * n_),
                       "pipecg": (2 * z_ + 16 * n_, csr_b + 104 * n_),
-                      "bicgstab": (4 * z_ + 20 * n_, 2 * csr_b + 144 * n_),
-                      "cgs": (4 * z_ + 19 * n_, 2 * csr_b + 136 * n_),
+                      "bicgstab": (4 * z_ + 20 * n_,
+                                   2 * csr_b + (120 if own_dots else 144) * n_),
+                      "cgs": (4 * z_ + 19 * n_, 2 * csr_b + (128 if own_dots else 136) * n_),
                       "gmres": (2 * z_ + 8 * 15.5 * n_ + 3 * n_,
                                 csr_b + (4 * 15.5 + 9) * 8 * n_)}[solver]
             xq.zero_()
