@@ -97,32 +97,46 @@ def measured_traffic(fmt, dt, info, max_row):
     if not table:
         return None
     t = "double,double" if dt == "f64" else "float,float"
+    vb = 8 if dt == "f64" else 4
     npl = {256: 4, 512: 8, 1024: 16}.get(info["block_nnz"], 8)
+    # the library streams the arrays of a matrix above 256 MiB non-temporally
+    # (a template flag of the kernel: part of its name)
+    big = lambda nbytes: "true" if nbytes > 256 * (1 << 20) else "false"
+    nt_csr = big(info["nnz"] * (4 + vb))
+    nt_coo = big(info["coo_nnz"] * (8 + vb))
+    nt_ell = big(info["ell_width"] * info["ell_stride"] * (4 + vb))
     wpg = info["waves_per_group"]
     chunked = -(-info["blocks"] // wpg) * 64 * wpg  # threads of the stream/COO grid
     keys = []
     ck = info["csr_kernel"]
     if fmt == "csr" and ck == 4:  # products through LDS
-        keys.append((f"k_csr_pr<{t},{info['block_nnz']},false,{wpg}>", chunked))
+        nt = nt_csr if info["block_nnz"] == 512 else "false"
+        keys.append((f"k_csr_pr<{t},{info['block_nnz']},false,{wpg},{nt}>", chunked))
     if fmt == "csr" and ck == 3:  # rows from LDS, two waves per group, G lanes per row
         g = info["lanes_per_row"]
         st = 16 if -(-max_row // g) > 8 else 8  # a lane's entries per step
-        keys.append((f"k_csr_rl<{t},{info['block_nnz']},false,2,{g},{st}>",
+        nt = nt_csr if info["block_nnz"] == 1024 else "false"
+        keys.append((f"k_csr_rl<{t},{info['block_nnz']},false,2,{g},{st},{nt}>",
                      -(-info["blocks"] // 2) * 128))
     if fmt == "csr" and ck == 1:
         keys.append((f"k_csr<{t},{npl},false,{wpg}>", chunked))
     if fmt == "csr" and info["lanes_per_row"] == 1:
         keys.append((f"k_csr_row<{t},false>", -(-info["nrows"] // 256) * 256))
     coo = "k_coo_runs" if info["coo_kernel"] == 2 else "k_coo"
+    if coo == "k_coo":
+        nt = nt_coo if npl <= 8 else "false"
+        coo_args = lambda accum: f"{t},{npl},{accum},{wpg},{nt}"
+    else:
+        coo_args = lambda accum: f"{t},{npl},{accum},{wpg}"
     if fmt == "coo":
-        keys.append((f"{coo}<{t},{npl},false,{wpg}>", chunked))
+        keys.append((f"{coo}<{coo_args('false')}>", chunked))
     if fmt in ("ell", "hyb"):
         w = 1
         while w < 16 and (info["ell_width"] + w - 1) // w > 256:
             w *= 2
-        keys.append((f"k_ell<{t},{w}>", info["ell_stride"] * w))
+        keys.append((f"k_ell<{t},{w},{nt_ell if w == 1 else 'false'}>", info["ell_stride"] * w))
     if fmt == "hyb" and info["coo_nnz"]:
-        keys.append((f"{coo}<{t},{npl},true,{wpg}>", chunked))
+        keys.append((f"{coo}<{coo_args('true')}>", chunked))
     if not keys or any(k not in table for k in keys):
         return None
     return int(sum(table[k] for k in keys))

@@ -136,7 +136,8 @@ mxs_status mxs_matrix_create_csr_complex(mxs_ctx* ctx, int64_t nrows, int64_t nc
 typedef struct {
   int64_t ell_width;      /* ELL: 0 = max row length; HYB: 0 = byte-model width, else forced K */
   int64_t max_ell_bytes;  /* 0 = no limit; ELL/HYB larger than this -> MXS_UNSUPPORTED */
-  int32_t block_nnz;      /* CSR/COO: entries per work unit (256, 512 or 1024; others are rounded up); 0 = 512 */
+  int32_t block_nnz;      /* CSR/COO: entries per work unit (256, 512 or 1024; others are rounded up); 0 = 512
+                             (COO without column panels whose arrays exceed 256 MiB: 256) */
   int32_t csr_kernel;     /* CSR: MXS_CSR_AUTO, MXS_CSR_STREAM (row blocks), MXS_CSR_VECTOR (lanes per row), MXS_CSR_ROWS_LDS, MXS_CSR_PRODUCTS */
   int32_t lanes_per_row;  /* CSR vector kernel: 1 (thread per row), 4, 8, 16, 32 or 64; 0 = from the mean row length.
                              CSR rows-from-LDS kernel: 1, 2 or 4 lanes per row; 0 = the fewest that fill a wave */
@@ -254,7 +255,12 @@ mxs_status mxs_matrix_destroy(mxs_matrix* A);
  * scalars of the compute type: double for F64 matrices, float for F32 and
  * F16_ROWSCALED.  x (ncols entries) and y (nrows entries) are device
  * vectors of the compute type; they must not overlap.  beta == 0 never
- * reads y (NaN/Inf in the old y do not propagate).  Asynchronous. */
+ * reads y (NaN/Inf in the old y do not propagate).  Asynchronous.
+ * The products of a matrix whose streamed arrays exceed 256 MiB (larger
+ * than the Infinity Cache) read those arrays with non-temporal loads, so
+ * they do not displace x, y and the dirty lines of y from the caches;
+ * smaller matrices keep ordinary loads, which leave them cached for the
+ * next product. */
 mxs_status mxs_spmv(mxs_ctx* ctx, const void* alpha, const mxs_matrix* A, const void* x,
                     const void* beta, void* y);
 

@@ -75,6 +75,29 @@ struct Raw<_Float16> {
   }
 };
 
+// One element of a streamed matrix array.  NT: a non-temporal load, for
+// matrices whose streamed arrays exceed the 256 MB Infinity Cache: on the
+// 27-point 128^3 matrix (906 MB of COO arrays) the bare stream of row, col
+// and val with its x gathers runs at 7.1 instead of 6.4 TB/s, and the cost
+// of the y stores written among the reads drops from 28 to 22 us.  Matrices
+// that fit the cache keep ordinary loads, which leave their lines there for
+// the next product (a solver's).
+template <bool NT, typename E>
+__device__ __forceinline__ E ld_stream(const E* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+// Streamed bytes above which a product reads its matrix non-temporally.
+constexpr double kStreamNtBytes = 256.0 * (1 << 20);
+
+// Value types whose streamed loads may be non-temporal (the others, complex
+// pairs and FP16 bit patterns, keep ordinary loads).
+template <typename V>
+constexpr bool kNtValue = std::is_same_v<V, double> || std::is_same_v<V, float>;
+
 // ---------------------------------------------------------------------------
 // CSR
 // ---------------------------------------------------------------------------
@@ -312,7 +335,8 @@ __global__ __launch_bounds__(256) void k_csr_vec(int64_t n, const int32_t* __res
 // wave's LDS tables.  With DOT the lanes that write a row i also return
 // x[i] * y[i] (the product's own inner product p.q when x = p and y = q = A p),
 // else 0.
-template <typename V, typename T, int CMAX, bool SCALED, int G, int ST, bool DOT>
+template <typename V, typename T, int CMAX, bool SCALED, int G, int ST, bool DOT,
+          bool NT = false>
 __device__ __forceinline__ double rl_block(int64_t b, const int32_t* __restrict__ blocks,
                                            const int32_t* __restrict__ bnnz,
                                            const int32_t* __restrict__ rowptr,
@@ -362,8 +386,13 @@ __device__ __forceinline__ double rl_block(int64_t b, const int32_t* __restrict_
     for (int t = 0; t < U; ++t) {
       const int k = t * 64 + lane;
       if (k < len) {
-        c[t] = col[s + k];
-        v[t] = Raw<V>::load(val, s + k);
+        if constexpr (NT) {
+          c[t] = ld_stream<true>(col + s + k);
+          v[t] = ld_stream<true>(val + s + k);
+        } else {
+          c[t] = col[s + k];
+          v[t] = Raw<V>::load(val, s + k);
+        }
       }
     }
 #pragma unroll
@@ -411,7 +440,7 @@ __device__ __forceinline__ double rl_block(int64_t b, const int32_t* __restrict_
   return 0.0;
 }
 
-template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G, int ST>
+template <typename V, typename T, int CMAX, bool SCALED, int WPB, int G, int ST, bool NT = false>
 __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
                                                      const int32_t* __restrict__ blocks,
                                                      const int32_t* __restrict__ bnnz,
@@ -429,8 +458,8 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl(int64_t nblocks,
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t b = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
   if (b >= nblocks) return;
-  rl_block<V, T, CMAX, SCALED, G, ST, false>(b, blocks, bnnz, rowptr, col, val, scale, x, y,
-                                             alpha, beta, vl_all[wv], cl_all[wv]);
+  rl_block<V, T, CMAX, SCALED, G, ST, false, NT>(b, blocks, bnnz, rowptr, col, val, scale, x, y,
+                                                 alpha, beta, vl_all[wv], cl_all[wv]);
 }
 
 // The same product, y = A x, where each work-group of WPB waves (one row
@@ -487,7 +516,7 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_rl_dot(int64_t nblocks,
 // interleaved accumulators.  LDS holds one value per entry (8 bytes in
 // FP64) instead of a value and an index.
 // ---------------------------------------------------------------------------
-template <typename V, typename T, int CMAX, bool SCALED, int WPB>
+template <typename V, typename T, int CMAX, bool SCALED, int WPB, bool NT = false>
 __global__ __launch_bounds__(64 * WPB) void k_csr_pr(int64_t nblocks,
                                                      const int32_t* __restrict__ blocks,
                                                      const int32_t* __restrict__ bnnz,
@@ -544,8 +573,13 @@ __global__ __launch_bounds__(64 * WPB) void k_csr_pr(int64_t nblocks,
       const int k = base + t * 64 + lane;
       c[t] = 0;  // (v[t] of an unused slot is never read)
       if (k < len) {
-        c[t] = col[s + k];
-        v[t] = Raw<V>::load(val, s + k);
+        if constexpr (NT) {
+          c[t] = ld_stream<true>(col + s + k);
+          v[t] = ld_stream<true>(val + s + k);
+        } else {
+          c[t] = col[s + k];
+          v[t] = Raw<V>::load(val, s + k);
+        }
       }
     }
     // every gather in flight together (column 0 for unused slots, whose
@@ -618,19 +652,27 @@ __global__ __launch_bounds__(256) void k_csr_row(int64_t n, const int32_t* __res
 // the run is a whole number of them (p is then 16-byte aligned: every device
 // allocation is, and runs start at multiples of NPL elements), else one load
 // each.
-template <int NPL, typename E>
+// NT: non-temporal loads (see ld_stream).
+template <int NPL, bool NT = false, typename E>
 __device__ __forceinline__ void load_run(const E* __restrict__ p, E (&out)[NPL]) {
   if constexpr ((NPL * sizeof(E)) % 16 == 0) {
     constexpr int NW = (int)(NPL * sizeof(E) / 16);
-    uint4 w[NW];
+    typedef uint32_t w4 __attribute__((ext_vector_type(4)));
+    w4 w[NW];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) w[j] = reinterpret_cast<const uint4*>(p)[j];
+    for (int j = 0; j < NW; ++j) {
+      if constexpr (NT)
+        w[j] = __builtin_nontemporal_load(reinterpret_cast<const w4*>(p) + j);
+      else
+        w[j] = reinterpret_cast<const w4*>(p)[j];
+    }
     __builtin_memcpy(out, w, sizeof(out));
   } else {
 #pragma unroll
     for (int t = 0; t < NPL; ++t) out[t] = p[t];
   }
 }
+
 
 // COO, one wave per chunk of 64*NPL entries, each lane's run held in
 // registers: lane l loads entries l*NPL .. l*NPL+NPL-1 of the chunk itself
@@ -753,7 +795,7 @@ __global__ __launch_bounds__(64 * WPB) void k_coo_runs(int64_t nnz, int64_t nchu
 // neighbouring entries' x; the products go to LDS and lane l reads back the
 // run l*NPL .. l*NPL+NPL-1, whose row indices it loads itself.  The run is
 // summed and rows are joined across lanes as in k_coo_runs.
-template <typename V, typename T, int NPL, bool ACCUM, int WPB>
+template <typename V, typename T, int NPL, bool ACCUM, int WPB, bool NT = false>
 __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
                                                       const int32_t* __restrict__ row,
                                                       const int32_t* __restrict__ col,
@@ -784,10 +826,10 @@ __global__ __launch_bounds__(64 * WPB) void k_coo(int64_t nnz, int64_t nchunks,
     V v[NPL];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
-      c[t] = col[s + t * 64 + lane];
-      v[t] = val[s + t * 64 + lane];
+      c[t] = ld_stream<NT>(col + s + t * 64 + lane);
+      v[t] = ld_stream<NT>(val + s + t * 64 + lane);
     }
-    load_run<NPL>(row + s + k0, r);
+    load_run<NPL, NT>(row + s + k0, r);
     T g[NPL];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) g[t] = x[c[t]];
@@ -1129,7 +1171,7 @@ __global__ void k_empty_rows(int64_t count, const int32_t* __restrict__ rows,
 // ---------------------------------------------------------------------------
 // ELL
 // ---------------------------------------------------------------------------
-template <typename V, typename T, int W>
+template <typename V, typename T, int W, bool NT = false>
 __global__ __launch_bounds__(64 * W) void k_ell(int64_t n, int64_t K, int64_t ld,
                                                 const int32_t* __restrict__ ecol,
                                                 const V* __restrict__ eval,
@@ -1152,14 +1194,14 @@ __global__ __launch_bounds__(64 * W) void k_ell(int64_t n, int64_t K, int64_t ld
   for (int64_t j = w; j < K; j += 4 * W) {
     if constexpr (sizeof(V) == 8) {
       const int64_t o0 = j * ld + i;
-      const int32_t c0 = ecol[o0];
-      const int32_t c1 = (j + W < K) ? ecol[o0 + W * ld] : -1;
-      const int32_t c2 = (j + 2 * W < K) ? ecol[o0 + 2 * W * ld] : -1;
-      const int32_t c3 = (j + 3 * W < K) ? ecol[o0 + 3 * W * ld] : -1;
-      if (c0 >= 0) a0 += to_acc(eval[o0]) * x[c0];
-      if (c1 >= 0) a1 += to_acc(eval[o0 + W * ld]) * x[c1];
-      if (c2 >= 0) a2 += to_acc(eval[o0 + 2 * W * ld]) * x[c2];
-      if (c3 >= 0) a3 += to_acc(eval[o0 + 3 * W * ld]) * x[c3];
+      const int32_t c0 = ld_stream<NT>(ecol + o0);
+      const int32_t c1 = (j + W < K) ? ld_stream<NT>(ecol + o0 + W * ld) : -1;
+      const int32_t c2 = (j + 2 * W < K) ? ld_stream<NT>(ecol + o0 + 2 * W * ld) : -1;
+      const int32_t c3 = (j + 3 * W < K) ? ld_stream<NT>(ecol + o0 + 3 * W * ld) : -1;
+      if (c0 >= 0) a0 += to_acc(ld_stream<NT>(eval + o0)) * x[c0];
+      if (c1 >= 0) a1 += to_acc(ld_stream<NT>(eval + o0 + W * ld)) * x[c1];
+      if (c2 >= 0) a2 += to_acc(ld_stream<NT>(eval + o0 + 2 * W * ld)) * x[c2];
+      if (c3 >= 0) a3 += to_acc(ld_stream<NT>(eval + o0 + 3 * W * ld)) * x[c3];
       if (!__any(c3 >= 0)) break;  // every later slot of these rows is padding
     } else {
       int32_t c[4];
@@ -1168,8 +1210,8 @@ __global__ __launch_bounds__(64 * W) void k_ell(int64_t n, int64_t K, int64_t ld
       for (int u = 0; u < 4; ++u) {
         const int64_t jj = j + u * W;
         const int64_t o = (jj < K ? jj : j) * ld + i;
-        c[u] = ecol[o];
-        v[u] = eval[o];
+        c[u] = ld_stream<NT>(ecol + o);
+        v[u] = ld_stream<NT>(eval + o);
       }
 #pragma unroll
       for (int u = 1; u < 4; ++u)
@@ -1240,9 +1282,22 @@ void launch_csr_stream(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T be
 
 template <typename V, typename T, bool SCALED, int CMAX, int G>
 void launch_csr_rl_g(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
-                     const int32_t* skip) {
+                     const int32_t* skip, bool nt) {
   constexpr int WPB = 2;
   const dim3 grid((unsigned)((P.nblocks + WPB - 1) / WPB));
+  if constexpr (CMAX == 1024 && kNtValue<V>) {
+    if (nt) {
+      if (P.rl_step == 16)
+        k_csr_rl<V, T, CMAX, SCALED, WPB, G, 16, true><<<grid, 64 * WPB, 0, ctx->stream>>>(
+            P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha,
+            beta, skip);
+      else
+        k_csr_rl<V, T, CMAX, SCALED, WPB, G, 8, true><<<grid, 64 * WPB, 0, ctx->stream>>>(
+            P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha,
+            beta, skip);
+      return;
+    }
+  }
   if (P.rl_step == 16)
     k_csr_rl<V, T, CMAX, SCALED, WPB, G, 16><<<grid, 64 * WPB, 0, ctx->stream>>>(
         P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha,
@@ -1255,13 +1310,13 @@ void launch_csr_rl_g(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta
 
 template <typename V, typename T, bool SCALED, int CMAX>
 void launch_csr_rl(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
-                   const int32_t* skip) {
+                   const int32_t* skip, bool nt) {
   if (P.rl_lanes == 4)
-    launch_csr_rl_g<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip);
+    launch_csr_rl_g<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip, nt);
   else if (P.rl_lanes == 2)
-    launch_csr_rl_g<V, T, SCALED, CMAX, 2>(ctx, P, alpha, x, beta, y, skip);
+    launch_csr_rl_g<V, T, SCALED, CMAX, 2>(ctx, P, alpha, x, beta, y, skip, nt);
   else
-    launch_csr_rl_g<V, T, SCALED, CMAX, 1>(ctx, P, alpha, x, beta, y, skip);
+    launch_csr_rl_g<V, T, SCALED, CMAX, 1>(ctx, P, alpha, x, beta, y, skip, nt);
 }
 
 template <typename V, typename T, bool SCALED, int CMAX, int G, int ST, int WPB>
@@ -1314,8 +1369,16 @@ int launch_csr_rl_dot(mxs_ctx* ctx, const CsrPart& P, const T* x, T* y, const in
 
 template <typename V, typename T, bool SCALED, int CMAX, int WPB>
 void launch_csr_pr_w(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
-                     const int32_t* skip) {
+                     const int32_t* skip, bool nt) {
   const dim3 grid((unsigned)((P.nblocks + WPB - 1) / WPB));
+  if constexpr (CMAX == 512 && kNtValue<V>) {
+    if (nt) {
+      k_csr_pr<V, T, CMAX, SCALED, WPB, true><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha,
+          beta, skip);
+      return;
+    }
+  }
   k_csr_pr<V, T, CMAX, SCALED, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
       P.nblocks, P.blocks, P.bnnz, P.rowptr, P.col, (const V*)P.val, P.scale, x, y, alpha, beta,
       skip);
@@ -1323,13 +1386,13 @@ void launch_csr_pr_w(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta
 
 template <typename V, typename T, bool SCALED, int CMAX>
 void launch_csr_pr(mxs_ctx* ctx, const CsrPart& P, T alpha, const T* x, T beta, T* y,
-                   const int32_t* skip) {
+                   const int32_t* skip, bool nt) {
   if (P.wpb == 1)
-    launch_csr_pr_w<V, T, SCALED, CMAX, 1>(ctx, P, alpha, x, beta, y, skip);
+    launch_csr_pr_w<V, T, SCALED, CMAX, 1>(ctx, P, alpha, x, beta, y, skip, nt);
   else if (P.wpb == 2)
-    launch_csr_pr_w<V, T, SCALED, CMAX, 2>(ctx, P, alpha, x, beta, y, skip);
+    launch_csr_pr_w<V, T, SCALED, CMAX, 2>(ctx, P, alpha, x, beta, y, skip, nt);
   else
-    launch_csr_pr_w<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip);
+    launch_csr_pr_w<V, T, SCALED, CMAX, 4>(ctx, P, alpha, x, beta, y, skip, nt);
 }
 
 // continuation partials of a chunked product: the row each chunk's first
@@ -1486,24 +1549,27 @@ void launch_csr(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, 
       launch_csr_merge<V, T, SCALED>(ctx, A, alpha, x, beta, y, skip, scratch);
     return;
   }
+  // col and val of a matrix larger than the Infinity Cache are streamed
+  // non-temporally
+  const bool nt = (double)A->nnz * (4 + sizeof(V)) > kStreamNtBytes;
   if (P.products) {
     if (P.nblocks == 0) return;
     if (P.block_nnz <= 512)
-      launch_csr_pr<V, T, SCALED, 512>(ctx, P, alpha, x, beta, y, skip);
+      launch_csr_pr<V, T, SCALED, 512>(ctx, P, alpha, x, beta, y, skip, nt);
     else if (P.block_nnz <= 1024)
-      launch_csr_pr<V, T, SCALED, 1024>(ctx, P, alpha, x, beta, y, skip);
+      launch_csr_pr<V, T, SCALED, 1024>(ctx, P, alpha, x, beta, y, skip, nt);
     else
-      launch_csr_pr<V, T, SCALED, 2048>(ctx, P, alpha, x, beta, y, skip);
+      launch_csr_pr<V, T, SCALED, 2048>(ctx, P, alpha, x, beta, y, skip, nt);
     return;
   }
   if (P.rows_lds) {
     if (P.nblocks == 0) return;
     if (P.block_nnz <= 512)
-      launch_csr_rl<V, T, SCALED, 512>(ctx, P, alpha, x, beta, y, skip);
+      launch_csr_rl<V, T, SCALED, 512>(ctx, P, alpha, x, beta, y, skip, nt);
     else if (P.block_nnz <= 1024)
-      launch_csr_rl<V, T, SCALED, 1024>(ctx, P, alpha, x, beta, y, skip);
+      launch_csr_rl<V, T, SCALED, 1024>(ctx, P, alpha, x, beta, y, skip, nt);
     else
-      launch_csr_rl<V, T, SCALED, 2048>(ctx, P, alpha, x, beta, y, skip);
+      launch_csr_rl<V, T, SCALED, 2048>(ctx, P, alpha, x, beta, y, skip, nt);
     return;
   }
   if (P.lanes == 1) {
@@ -1550,6 +1616,15 @@ void launch_coo_chunks(mxs_ctx* ctx, const CooPart& P, T alpha, const T* x, T be
         k_coo_runs<V, T, 8, ACCUM, WPB><<<grid, 64 * WPB, 0, ctx->stream>>>(
             P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
     }
+    return;
+  }
+  if (P.block_nnz <= 512 && (double)P.nnz * (8 + sizeof(V)) > kStreamNtBytes) {
+    if (P.block_nnz == 256)
+      k_coo<V, T, 4, ACCUM, WPB, true><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
+    else
+      k_coo<V, T, 8, ACCUM, WPB, true><<<grid, 64 * WPB, 0, ctx->stream>>>(
+          P.nnz, P.nchunks, P.row, P.col, val, x, y, alpha, beta, c.row, cv, skip);
     return;
   }
   switch (P.block_nnz) {
@@ -1623,8 +1698,12 @@ void launch_ell(mxs_ctx* ctx, const mxs_matrix* A, T alpha, const T* x, T beta, 
     MXS_ELL_CASE(16)
 #undef MXS_ELL_CASE
     default:
-      k_ell<V, T, 1><<<grid, 64, 0, ctx->stream>>>(A->n, P.K, P.stride, P.col, val, x, y, alpha,
-                                                   beta, skip);
+      if ((double)P.K * P.stride * (4 + sizeof(V)) > kStreamNtBytes)
+        k_ell<V, T, 1, true><<<grid, 64, 0, ctx->stream>>>(A->n, P.K, P.stride, P.col, val, x, y,
+                                                           alpha, beta, skip);
+      else
+        k_ell<V, T, 1><<<grid, 64, 0, ctx->stream>>>(A->n, P.K, P.stride, P.col, val, x, y,
+                                                     alpha, beta, skip);
   }
 }
 

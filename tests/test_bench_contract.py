@@ -44,9 +44,9 @@ def test_traffic_lookup_finds_the_step_kernels():
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
     n, nnz = 128 ** 3, 55742968
-    coo = {"block_nnz": 512, "waves_per_group": 4, "blocks": -(-nnz // 512), "coo_kernel": 1,
-           "csr_kernel": 0, "lanes_per_row": 0, "nrows": n, "ell_width": 0, "ell_stride": n,
-           "coo_nnz": nnz}
+    coo = {"block_nnz": 256, "waves_per_group": 4, "blocks": -(-nnz // 256), "coo_kernel": 1,
+           "csr_kernel": 0, "lanes_per_row": 0, "nrows": n, "nnz": nnz, "ell_width": 0,
+           "ell_stride": n, "coo_nnz": nnz}
     ell = dict(coo, ell_width=27, coo_nnz=0, coo_kernel=0)
     for dt in ("f64", "f32"):
         assert bench.measured_traffic("coo", dt, coo, 27), dt
