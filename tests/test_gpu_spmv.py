@@ -572,6 +572,10 @@ def test_spmv_full_size(env, orc, which):
         # the byte rule makes the hybrid all ELL here (K_h = 27): a forced
         # width of 20 sends 7 entries of every interior row to its COO part
         cases.append(("hyb", {"ell_width": 20}))
+        # arrays above 256 MiB are streamed non-temporally: COO at the
+        # 512-entry chunk (AUTO takes 256 there) and a hybrid whose COO part
+        # (19 entries of every interior row, about 600 MB) is that large
+        cases += [("coo", {"block_nnz": 512}), ("hyb", {"ell_width": 8})]
     for fmt, opts in cases:
         if fmt == "ell" and which == "zipf_2p20_m16":
             continue  # the same 4096-wide padded layout as zipf_2p20 (51.5 GB in FP64)
@@ -582,7 +586,10 @@ def test_spmv_full_size(env, orc, which):
             # rows over 64 entries and an x of 8 MiB: panels; stencils: none
             assert B.info()["col_panels"] == (4 if which != "stencil27_128" else 1)
         if "ell_width" in opts:
-            assert B.info()["ell_width"] == 20 and B.info()["coo_nnz"] > 7 * 120 ** 3
+            w = opts["ell_width"]
+            assert B.info()["ell_width"] == w and B.info()["coo_nnz"] > (27 - w) * 120 ** 3
+        if fmt == "coo" and which == "stencil27_128":
+            assert B.info()["block_nnz"] == opts.get("block_nnz", 256)
         y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         mxs.spmv(ctx, B, _dev(torch, x), y)
         _check(y.cpu().numpy(), ref, scale, 1e-13)
