@@ -594,7 +594,8 @@ mxs_status mxs_batch_config(const mxs_batch* batch, int32_t cls, int32_t* max_n,
 /* measurement                                                             */
 /* ---------------------------------------------------------------------- */
 typedef struct {
-  double read_gbs;   /* sum-reduction over one array          */
+  double read_gbs;   /* sum-reduction over one array (the faster of ordinary
+                        and non-temporal loads, as the products use both) */
   double copy_gbs;   /* b = a                                  */
   double triad_gbs;  /* a = b + s*c                            */
   double best_gbs;   /* max of the three                       */
