@@ -77,11 +77,12 @@ struct Raw<_Float16> {
 
 // One element of a streamed matrix array.  NT: a non-temporal load, for
 // matrices whose streamed arrays exceed the 256 MB Infinity Cache: on the
-// 27-point 128^3 matrix (906 MB of COO arrays) the bare stream of row, col
-// and val with its x gathers runs at 7.1 instead of 6.4 TB/s, and the cost
-// of the y stores written among the reads drops from 28 to 22 us.  Matrices
-// that fit the cache keep ordinary loads, which leave their lines there for
-// the next product (a solver's).
+// 27-point 128^3 matrix (906 MB of COO arrays) a bare stream of row, col and
+// val with its x gathers takes 10% less time than with ordinary loads, and
+// the y stores written among the reads cost 22 instead of 28 us; the
+// products themselves run 3-11% faster.  Matrices that fit the cache keep
+// ordinary loads, which leave their lines there for the next product (a
+// solver's).
 template <bool NT, typename E>
 __device__ __forceinline__ E ld_stream(const E* p) {
   if constexpr (NT)
