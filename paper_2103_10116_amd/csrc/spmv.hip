@@ -85,19 +85,28 @@ struct Raw<_Float16> {
 // solver's).
 template <bool NT, typename E>
 __device__ __forceinline__ E ld_stream(const E* p) {
-  if constexpr (NT)
-    return __builtin_nontemporal_load(p);
-  else
+  if constexpr (!NT) {
     return *p;
+  } else if constexpr (std::is_same_v<E, cplx<double>> || std::is_same_v<E, cplx<float>>) {
+    // both parts in one load (entries are 2 x 8 or 2 x 4 bytes and every
+    // device allocation is 16-byte aligned, so each entry is aligned to its size)
+    using R = decltype(p->re);
+    typedef R r2 __attribute__((ext_vector_type(2)));
+    const r2 v = __builtin_nontemporal_load(reinterpret_cast<const r2*>(p));
+    return E(v.x, v.y);
+  } else {
+    return __builtin_nontemporal_load(p);
+  }
 }
 
 // Streamed bytes above which a product reads its matrix non-temporally.
 constexpr double kStreamNtBytes = 256.0 * (1 << 20);
 
-// Value types whose streamed loads may be non-temporal (the others, complex
-// pairs and FP16 bit patterns, keep ordinary loads).
+// Value types whose streamed loads may be non-temporal (FP16 bit patterns
+// keep ordinary loads).
 template <typename V>
-constexpr bool kNtValue = std::is_same_v<V, double> || std::is_same_v<V, float>;
+constexpr bool kNtValue = std::is_same_v<V, double> || std::is_same_v<V, float> ||
+                          std::is_same_v<V, cplx<double>> || std::is_same_v<V, cplx<float>>;
 
 // ---------------------------------------------------------------------------
 // CSR

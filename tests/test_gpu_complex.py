@@ -71,6 +71,36 @@ def test_complex_spmv(env, orc, name, dt):
             B.close()
 
 
+@pytest.mark.slow
+def test_complex_spmv_full_size(env, orc):
+    """The 27-point 128^3 pattern with complex values (1.1 GB as C128, 0.67 GB
+    as C64: both streamed with non-temporal loads) in AUTO's kernel and in
+    rows-from-LDS at 1024-entry blocks, against the oracle's complex product
+    per entry."""
+    mxs, ctx, torch = env
+    A = I.stencil27(128)
+    g = I.rng(95)
+    z = A.val + 1j * g.uniform(-1, 1, A.nnz)
+    x = g.uniform(-1, 1, A.ncols) + 1j * g.uniform(-1, 1, A.ncols)
+    M = mxs.Matrix.from_host_complex(ctx, A.n, A.ncols, A.rowptr, A.col, z)
+    for dt, tol in (("c128", 1e-13), ("c64", 1e-5)):
+        if dt == "c64":
+            zr, xr = (np.asarray(v, np.complex64).astype(np.complex128) for v in (z, x))
+        else:
+            zr, xr = z, x
+        ref = orc.spmv_csr_z(A.n, A.rowptr, A.col, zr, xr, 1.0, 0.0, np.zeros(A.n, complex))
+        scale = orc.absrow_z(A.n, A.rowptr, A.col, zr, xr)
+        tdt = torch.complex128 if dt == "c128" else torch.complex64
+        for opts in (dict(), dict(csr_kernel="rows_lds", block_nnz=1024)):
+            B = M.convert("csr", dt, **opts)
+            y = torch.zeros(A.n, dtype=tdt, device="cuda")
+            mxs.spmv(ctx, B, torch.from_numpy(x).to(tdt).cuda(), y)
+            got = y.cpu().numpy().astype(np.complex128)
+            assert np.all(np.abs(got - ref) <= tol * scale + 1e-300), (dt, opts)
+            B.close()
+    M.close()
+
+
 def test_complex_export_and_limits(env, orc):
     mxs, ctx, torch = env
     A, z = ZOO["powerlaw"]
